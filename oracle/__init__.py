@@ -1,0 +1,34 @@
+"""FP64 CPU oracle for the dry/wet generalized-Poisson path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing on the product path may import, call or
+execute this package: only the tests, the smoke check and the CPU-baseline leg
+of the benchmark do.  It shares no code with the HIP library or its binding;
+both sides take their inputs from the seeded generators, which hold none of the
+method's arithmetic.
+
+What it computes (paper, Sec. II.B-II.F and Appendix B):
+  * the 7-point conservative discretisation of div(eps grad phi) (Eq. 3);
+  * the periodic vacuum Poisson solve by FFT with the discrete 7-point symbol
+    (the discrete counterpart of Eq. 15);
+  * the unique zero-mean solution of A phi = -4 pi (rho - mean rho) on the full
+    periodic box, by conjugate gradients preconditioned with that FFT solve
+    (a different algorithm from the GPU's dry/wet coupling, on purpose);
+  * the Hartree energy 1/2 int phi rho and its permittivity form (Eq. 4);
+  * dE/d eps at every node and dE/dR for every atom (Eq. 11, App. B) through
+    the product-of-erf switches and the Gaussian charges;
+  * the paper's one-pass split (vacuum FFT, then a Dirichlet solve in the wet
+    slab with the vacuum potential as boundary data, Sec. II.F) as a
+    diagnostic.
+
+Every pin of these functions lives in the CPU test-suite.  Parity unpinned:
+none of the functions above (the one-pass split is pinned only by its epsilon
+= 1 special case, where it reduces to the vacuum solve).
+"""
+from .poisson import (apply_A, vacuum_symbol, vacuum_solve, solve, energy,
+                      energy_eps_form, eps_gradient, residual_norm)
+from .atoms import eps_erf, rho_gauss, forces, deps_dR_dense, drho_dR_dense
+from .split import one_pass_split
+
+__all__ = ["apply_A", "vacuum_symbol", "vacuum_solve", "solve", "energy",
+           "energy_eps_form", "eps_gradient", "residual_norm", "eps_erf",
+           "rho_gauss", "forces", "deps_dR_dense", "drho_dR_dense", "one_pass_split"]

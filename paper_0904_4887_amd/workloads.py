@@ -1,0 +1,198 @@
+"""Seeded synthetic workloads for the dry/wet generalized-Poisson path.
+
+This module only draws inputs: grids, atom positions, charges, radii, the
+planar tanh permittivity that the smallest workload hands over directly, and
+the solver options each workload is run with.  It holds none of the method's
+arithmetic (no permittivity switch, no Gaussian density, no operator), so the
+FP64 oracle and the HIP path can both be fed from it without sharing code.
+
+The paper's own systems are DFT slabs (an anatase (101) slab in a continuum
+solvent, Sec. II.A); they are replaced here by synthetic stand-ins of the same
+kind: a rutile-like TiO2 slab of Gaussian point charges with solvent above it.
+
+Conventions (Sec. II.B-II.F of the paper, made concrete):
+  * lengths in Angstrom, charges in e, energies in e^2/Angstrom;
+  * node n = (i*hx, j*hy, k*hz) for 0 <= i < nx etc., arrays are [nz][ny][nx];
+  * the wet region W is the periodic z-interval [z_wet_lo, z_wet_hi) (hi may
+    exceed Lz, in which case W wraps through z = 0).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+EPS_INF = 78.36          # solvent permittivity used by every workload
+DELTA = 0.3              # width of the erf switch, Angstrom
+R_TI, R_O = 2.0, 1.6     # switch radii, Angstrom
+Q_TI, Q_O = 4.0, -2.0    # Gaussian valence charges, e
+SIGMA_SLAB = 0.6         # Gaussian width (standard deviation) for slab charges
+RUTILE_U = 0.305         # rutile internal parameter
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    n: tuple              # (nx, ny, nz)
+    L: tuple              # (Lx, Ly, Lz), Angstrom
+    xyz: np.ndarray       # (natoms, 3) float64, wrapped into [0, L)
+    q: np.ndarray         # (natoms,) charges
+    sigma: np.ndarray     # (natoms,) Gaussian standard deviations
+    radius: np.ndarray    # (natoms,) switch radii (unused when eps is given)
+    eps_kind: str         # "tanh_z" (eps handed over as a grid) or "erf"
+    eps_params: dict      # eps_inf, delta, exclusion (0/1), z_lim, delta_z
+    z_wet: tuple          # (z_wet_lo, z_wet_hi) Angstrom
+    tol: float            # relative residual tolerance of the solve
+    precision: int = 0    # 0 = FP64, 1 = mixed FP32-in-FP64
+    buried: np.ndarray = None  # (natoms,) bool, atoms under the exclusion rule
+
+    @property
+    def N(self):
+        return self.n[0] * self.n[1] * self.n[2]
+
+    @property
+    def h(self):
+        return tuple(self.L[d] / self.n[d] for d in range(3))
+
+    def eps_grid(self):
+        """Node permittivity for the 'tanh_z' workload (an input, not a builder)."""
+        assert self.eps_kind == "tanh_z"
+        p = self.eps_params
+        nz = self.n[2]
+        z = np.arange(nz, dtype=np.float64) * self.h[2]
+        prof = 1.0 + (p["eps_inf"] - 1.0) * 0.5 * (1.0 + np.tanh((z - p["z0"]) / p["width"]))
+        return np.ascontiguousarray(
+            np.broadcast_to(prof[:, None, None], (nz, self.n[1], self.n[0])))
+
+
+def _rutile_slab(cells_xy, cell_xy, n_layers, z0, layer_dz):
+    """Rutile-like TiO2 slab, c axis along z.
+
+    Conventional cell basis (fractional x, y; layer index): Ti at (0,0) and
+    (1/2,1/2); O at (u,u), (-u,-u) in the same layer as Ti(0,0) and at
+    (1/2+u, 1/2-u), (1/2-u, 1/2+u) in the layer of Ti(1/2,1/2).
+    Returns xyz (unwrapped), species code (0 = Ti, 1 = O) and layer index.
+    """
+    u = RUTILE_U
+    basis_even = [(0, 0.0, 0.0), (1, u, u), (1, -u, -u)]
+    basis_odd = [(0, 0.5, 0.5), (1, 0.5 + u, 0.5 - u), (1, 0.5 - u, 0.5 + u)]
+    xyz, spec, layer = [], [], []
+    for lz in range(n_layers):
+        basis = basis_even if lz % 2 == 0 else basis_odd
+        for cx in range(cells_xy):
+            for cy in range(cells_xy):
+                for s, fx, fy in basis:
+                    xyz.append(((cx + fx) * cell_xy, (cy + fy) * cell_xy, z0 + lz * layer_dz))
+                    spec.append(s)
+                    layer.append(lz)
+    return np.array(xyz, dtype=np.float64), np.array(spec), np.array(layer)
+
+
+def _slab_workload(name, n, L, cells_xy, layer_dz, seed, z_cut, tol, precision, exclusion):
+    cell_xy = L[0] / cells_xy
+    xyz, spec, layer = _rutile_slab(cells_xy, cell_xy, 6, 5.0, layer_dz)
+    rng = np.random.default_rng(seed)
+    xyz = xyz + rng.normal(0.0, 0.05, size=xyz.shape)
+    xyz = np.mod(xyz, np.array(L, dtype=np.float64))
+    q = np.where(spec == 0, Q_TI, Q_O).astype(np.float64)
+    radius = np.where(spec == 0, R_TI, R_O).astype(np.float64)
+    sigma = np.full(len(q), SIGMA_SLAB)
+    # Exclusion (the smooth analogue of the paper's Eq. 19): atoms of every
+    # layer up to the second one from the top are "buried"; z_lim sits half
+    # way between the two top layers so that jitter cannot flip the choice.
+    z_top2 = 5.0 + 4 * layer_dz
+    z_lim = z_top2 + 0.5 * layer_dz
+    buried = layer <= 4
+    params = dict(eps_inf=EPS_INF, delta=DELTA, exclusion=int(exclusion),
+                  z_lim=z_lim, delta_z=DELTA)
+    if exclusion:
+        # Below the highest buried atom minus 6 switch widths the permittivity
+        # is exactly 1; W starts there and wraps two planes past z = 0 so that
+        # every dry row of the operator is a vacuum row.
+        zmax = float(xyz[buried, 2].max())
+        z_wet = (zmax - 6.0 * DELTA, L[2] + 2.0 * L[2] / n[2])
+    else:
+        z_wet = (z_cut, L[2])
+    return Workload(name=name, n=n, L=L, xyz=xyz, q=q, sigma=sigma, radius=radius,
+                    eps_kind="erf", eps_params=params, z_wet=z_wet, tol=tol,
+                    precision=precision, buried=buried)
+
+
+def tanh_box(n=(32, 32, 64), seed=0):
+    """10x10x20 A box, planar tanh permittivity, 8 Gaussians of charge +-1.
+
+    Centres are uniform in [0,10) x [0,10) x [0,8) from the seed; charges
+    alternate +1, -1; sigma = 0.5 A; dry z < 8 A.
+    """
+    L = (10.0, 10.0, 20.0)
+    rng = np.random.default_rng(seed)
+    xyz = rng.uniform(0.0, 1.0, size=(8, 3)) * np.array([10.0, 10.0, 8.0])
+    q = np.array([1.0, -1.0] * 4)
+    return Workload(name=f"tanh_box_{n[0]}x{n[1]}x{n[2]}", n=tuple(n), L=L, xyz=xyz, q=q,
+                    sigma=np.full(8, 0.5), radius=np.zeros(8), eps_kind="tanh_z",
+                    eps_params=dict(eps_inf=EPS_INF, z0=10.0, width=1.0),
+                    z_wet=(8.0, 20.0), tol=1e-10, precision=0,
+                    buried=np.zeros(8, dtype=bool))
+
+
+def slab(n=(96, 96, 192), exclusion=False, tol=1e-10, precision=0, seed=1, name=None):
+    """11.8 x 11.8 x 40 A cell, 72-atom rutile-like slab in z in [5, 12] A.
+
+    Six Ti/O layers 1.4 A apart (2x2x3 conventional cells, in-plane edge
+    5.9 A), N(0, 0.05 A) jitter, Ti +4 / O -2 Gaussians of sigma 0.6 A,
+    switch radii 2.0 / 1.6 A, dry z < 14 A.
+    """
+    nm = name or f"slab_{n[0]}x{n[1]}x{n[2]}" + ("_excl" if exclusion else "")
+    return _slab_workload(nm, tuple(n), (11.8, 11.8, 40.0), 2, 1.4, seed, 14.0, tol,
+                          precision, exclusion)
+
+
+def big_slab(n=(256, 256, 512), exclusion=False, tol=1e-8, precision=1, seed=5):
+    """23.6 x 23.6 x 60 A cell, 288 atoms (2x2 lateral replica of the slab),
+    six layers stretched to 2.8 A spacing so that they span z in [5, 19] A;
+    dry z < 21 A."""
+    nm = f"big_slab_{n[0]}x{n[1]}x{n[2]}" + ("_excl" if exclusion else "")
+    return _slab_workload(nm, tuple(n), (23.6, 23.6, 60.0), 4, 2.8, seed, 21.0, tol,
+                          precision, exclusion)
+
+
+def md_displacements(natoms, steps, seed=6, scale=0.02):
+    """Per-step Gaussian displacements N(0, 0.02 A), applied cumulatively."""
+    rng = np.random.default_rng(seed)
+    return rng.normal(0.0, scale, size=(steps, natoms, 3))
+
+
+def fd_atoms(natoms, seed=2, count=6):
+    """Atoms whose forces are checked by central finite differences."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(natoms, size=count, replace=False))
+
+
+def random_fields(n, seed, eps_lo=1.0, eps_hi=EPS_INF):
+    """Random permittivity in [eps_lo, eps_hi] and a random neutral density."""
+    rng = np.random.default_rng(seed)
+    shape = (n[2], n[1], n[0])
+    eps = rng.uniform(eps_lo, eps_hi, size=shape)
+    rho = rng.normal(size=shape)
+    rho -= rho.mean()
+    return eps, rho
+
+
+# The five workloads the solver is specified on.
+def configs():
+    return {
+        "C1": tanh_box(),
+        "C2": slab((96, 96, 192), tol=1e-10),
+        "C3": slab((128, 128, 256), tol=1e-12),
+        "C4": slab((192, 192, 384), tol=1e-8, precision=1),
+        "C5": big_slab(),
+    }
+
+
+def wet_planes(n_z, L_z, z_wet):
+    """First wet plane ceil(z_lo/hz) and one-past-last plane ceil(z_hi/hz)."""
+    hz = L_z / n_z
+    k0 = int(math.ceil(z_wet[0] / hz - 1e-9))
+    k1 = int(math.ceil(z_wet[1] / hz - 1e-9))
+    return k0, k1
