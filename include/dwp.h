@@ -1,0 +1,206 @@
+/*
+ * dwp.h -- C ABI of the MI355X dry/wet generalized-Poisson library (libdwp.so).
+ *
+ * The library solves the generalized Poisson problem of the paper's continuum
+ * solvent model, div(eps grad phi) = -4 pi rho (Eq. 3), on a periodic 3-D grid,
+ * with the paper's split of the cell into a solvent-free ("dry") part handled
+ * by a periodic FFT Poisson solve (Eq. 15) and a solvated ("wet") slab handled
+ * by multigrid with boundary data from the dry solution (Sec. II.F); the two
+ * are iterated to self-consistency on the full box.  It also returns the
+ * Hartree energy E = 1/2 int phi rho (Sec. II.C, equal to Eq. 4 at the
+ * solution), its derivative with respect to the permittivity (first term of
+ * Eq. 11) and the atomic forces dE/dR (Eq. 11, derived in Appendix B).
+ *
+ * Conventions shared by every entry point:
+ *   - lengths in Angstrom, charges in e, energies in e^2/Angstrom
+ *     (multiply by 14.399645 for eV);
+ *   - grids are float64 arrays laid out [nz][ny][nx] with x fastest; node
+ *     (i, j, k) sits at (i hx, j hy, k hz), h_d = L_d / n_d, all directions
+ *     periodic;
+ *   - "_dev" pointers are device (HBM) pointers on the context's device,
+ *     owned by the caller, 8-byte aligned, dense; "_host" pointers are host
+ *     memory, owned by the caller and only read or written during the call;
+ *   - all device work is enqueued on the context's stream; entry points that
+ *     return host values (energy, forces, info) synchronise that stream;
+ *   - every function returns a dwp_status; nothing throws across the ABI.  On
+ *     error the context stays usable and dwp_last_error() describes the
+ *     failure.  Arguments are validated before any device work is issued.
+ *   - a context is not thread-safe; use one context per stream.
+ *
+ * Discretisation (the paper's Eq. 3 written in conservative form):
+ *   (A phi)_n = sum_d [eps_{n+e_d/2} (phi_{n+e_d} - phi_n)
+ *                      - eps_{n-e_d/2} (phi_n - phi_{n-e_d})] / h_d^2,
+ *   eps_{n+e_d/2} = (eps_n + eps_{n+e_d}) / 2.
+ * The solution is the unique zero-mean phi with A phi = -4 pi (rho - mean rho):
+ * a uniform neutralising background, the G = 0 convention of Eq. 15.
+ */
+#ifndef DWP_H
+#define DWP_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dwp_ctx dwp_ctx; /* opaque, library-owned */
+
+typedef enum {
+    DWP_OK = 0,
+    DWP_EINVAL = -1,     /* an argument is out of range or inconsistent        */
+    DWP_ESTATE = -2,     /* called before set_grid / set_epsilon / solve       */
+    DWP_ENOCONV = -3,    /* tolerance not reached; best iterate returned       */
+    DWP_EHIP = -4,       /* the HIP runtime reported an error                  */
+    DWP_ENOMEM = -5,     /* device allocation failed                          */
+    DWP_ENONFINITE = -6  /* NaN or Inf found in an input or a residual        */
+} dwp_status;
+
+typedef enum { DWP_FP64 = 0, DWP_MIXED = 1 } dwp_precision;
+
+/* Solver options.  dwp_default_opts() fills every field. */
+typedef struct {
+    int precision;         /* DWP_FP64, or DWP_MIXED: the multigrid hierarchy
+                              (smoothing, inner residuals, transfers, coarse
+                              solve) in float32 inside the float64 Krylov
+                              coupling; the full-box residual, the wet-slab
+                              residual, the FFT dry update, the coupling update
+                              and the energy stay float64                      */
+    double z_wet_lo;       /* wet slab W = [z_wet_lo, z_wet_hi) (Angstrom);    */
+    double z_wet_hi;       /* z_wet_hi may exceed Lz: W then wraps through 0.  */
+                           /* The first wet plane is ceil(z_wet_lo / hz), the  */
+                           /* plane past the last one ceil(z_wet_hi / hz); the */
+                           /* library may move the first plane down by a few   */
+                           /* planes so that W coarsens well (info reports it) */
+    int pre, post;         /* red-black Gauss-Seidel sweeps per V-cycle level  */
+    int coarse_sweeps;     /* sweeps on the coarsest level                     */
+    int max_levels;        /* upper bound on multigrid levels (>= 1)           */
+    int cycles;            /* V-cycles per application of the split            */
+    int scaled_dry;        /* 1: dry update s * L^-1 (s * r), s = eps^-1/2     */
+    double tol;            /* stop at ||b - A phi||_2 <= tol ||b||_2           */
+    int max_outer;         /* cap on preconditioned Krylov iterations          */
+    int restart;           /* FGMRES restart length m (1..64)                  */
+    int warm_start;        /* 1: phi_dev holds the initial guess on entry      */
+} dwp_opts;
+
+/* Per-solve report. */
+typedef struct {
+    int outer_iters;         /* Krylov iterations = applications of the split  */
+    int vcycles;             /* V-cycles run                                   */
+    int restarts;            /* FGMRES cycles                                  */
+    int k_w0, k_w1;          /* wet planes actually used: [k_w0, k_w1) mod nz  */
+    int n_levels;            /* multigrid levels on W                          */
+    double rel_res;          /* final ||b - A phi||_2 / ||b||_2 (true residual)*/
+    double energy;           /* E = 1/2 h^3 sum rho phi                        */
+    double energy_eps_form;  /* (h^3 / 8 pi) sum_faces eps_f (D_f phi)^2       */
+    double mean_rho_removed; /* mean of rho that was projected out            */
+    double t_total_ms;       /* wall time of the solve                         */
+} dwp_info;
+
+/* Permittivity built from the atoms (dwp_build_epsilon):
+ *   eps_n = 1 + (eps_inf - 1) * prod_i s_i(d_in) * H(z_n),
+ *   s_i(d) = 1/2 [1 + erf((d - r_i) / delta)], d_in the minimum-image distance,
+ * a product of smooth switches that plays the role of the paper's
+ * atom-defined dielectric (Eqs. 9-10).  s_i is taken as exactly 0 below
+ * r_i - 6 delta and exactly 1 beyond r_i + 6 delta.  With exclusion = 1 every
+ * atom with z_i <= z_lim ("buried") adds the height factor
+ *   h_i(z) = 1/2 [1 + erf((z - z_i) / delta_z)],  H(z) = prod_buried h_i(z),
+ * with z the node height in [0, Lz): the smooth counterpart of Eq. 19, which
+ * drives eps to 1 underneath the buried atoms so that the region below the
+ * exposed face is really dry (Sec. II.F).  exclusion = 0 gives H = 1. */
+typedef struct {
+    double eps_inf;  /* bulk solvent permittivity (> 1)            */
+    double delta;    /* switch width (Angstrom, > 0)               */
+    int exclusion;   /* 0 or 1                                     */
+    double z_lim;    /* buried atoms: z_i <= z_lim                 */
+    double delta_z;  /* width of the height factor (Angstrom, > 0) */
+} dwp_eps_params;
+
+/* Defaults: FP64, W = [0.35 Lz, Lz), V(2,2), 64 coarse sweeps, 1 cycle,
+ * tol 1e-10, 600 iterations, restart 30, cold start. */
+void dwp_default_opts(dwp_opts *opts);
+
+/* Create a context on HIP device `device`; `hip_stream` is a hipStream_t (or
+ * NULL for the null stream), typically torch's current stream. */
+int dwp_create(dwp_ctx **ctx, int device, void *hip_stream);
+int dwp_destroy(dwp_ctx *ctx);
+/* Change the stream later calls enqueue on. */
+int dwp_set_stream(dwp_ctx *ctx, void *hip_stream);
+
+/* Fix the grid and plan the solver (Sec. II.F: FFT plan for the whole cell,
+ * multigrid hierarchy for the wet slab).  Each n_d must be even, at least 8,
+ * with no prime factor other than 2 and 3 and at most 4096; L_d > 0; W must
+ * leave at least one dry plane and hold at least 3 planes.  Allocates all
+ * device memory the solver needs (about (2 restart + 14) N doubles).
+ * Invalidates epsilon and the last solution. */
+int dwp_set_grid(dwp_ctx *ctx, int nx, int ny, int nz, double Lx, double Ly, double Lz,
+                 const dwp_opts *opts);
+/* Replace the options of the current grid (the wet slab may change). */
+int dwp_set_opts(dwp_ctx *ctx, const dwp_opts *opts);
+
+/* Use a caller-supplied node permittivity grid (copied; >= 1 and finite,
+ * else DWP_EINVAL / DWP_ENONFINITE). */
+int dwp_set_epsilon(dwp_ctx *ctx, const double *eps_dev);
+
+/* Build eps from n atoms (xyz_host: n x 3, radius_host: n), see
+ * dwp_eps_params.  The result stays in the context; dwp_get_epsilon copies it
+ * out. */
+int dwp_build_epsilon(dwp_ctx *ctx, int n, const double *xyz_host, const double *radius_host,
+                      const dwp_eps_params *params);
+int dwp_get_epsilon(dwp_ctx *ctx, double *eps_dev);
+
+/* Gaussian charges (the smeared ionic densities of Sec. II.C, here with
+ * sigma_i a standard deviation): rho_n = sum_i q_i (2 pi sigma_i^2)^(-3/2)
+ * exp(-d_in^2 / (2 sigma_i^2)), minimum image, cut off at 9 sigma_i
+ * (sigma_i must be below min(L)/18).  Writes N doubles to rho_dev. */
+int dwp_build_rho(dwp_ctx *ctx, int n, const double *xyz_host, const double *q_host,
+                  const double *sigma_host, double *rho_dev);
+
+/* Solve A phi = -4 pi (rho - mean rho) to the tolerance of the options.
+ * phi_dev (N doubles) receives the zero-mean solution; with warm_start it
+ * also supplies the initial guess.  *energy_host (nullable) receives
+ * E = 1/2 h^3 sum rho phi, *info (nullable) the report.  Returns DWP_ENOCONV
+ * with the best iterate in phi_dev if max_outer is reached. */
+int dwp_solve(dwp_ctx *ctx, const double *rho_dev, double *phi_dev, double *energy_host,
+              dwp_info *info);
+
+/* dE/d eps_n = -(h^3 / 8 pi) sum_d 1/2 [(D+_d phi)_n^2 + (D-_d phi)_n^2] for
+ * the last solution (the discrete first term of Eq. 11).  N doubles. */
+int dwp_eps_gradient(dwp_ctx *ctx, double *dEdeps_dev);
+
+/* dE/dR (n x 3, host) for the last solution: sum_n (dE/d eps_n) d eps_n/dR_I
+ * + h^3 sum_n phi_n d rho_n / dR_I (Eq. 11).  The atoms and parameters must
+ * be those eps and rho were built from.  params == NULL means eps does not
+ * depend on the atoms (caller-supplied eps): only the charge term is
+ * returned.  Forces are F = -dE/dR. */
+int dwp_forces(dwp_ctx *ctx, int n, const double *xyz_host, const double *radius_host,
+               const double *q_host, const double *sigma_host, const dwp_eps_params *params,
+               double *dEdR_host);
+
+/* Building blocks, exposed for checking and for callers that compose them. */
+/* out = A phi on the full periodic box with the current eps. */
+int dwp_apply_operator(dwp_ctx *ctx, const double *phi_dev, double *out_dev);
+/* out = zero-mean psi with L psi = r - mean r, L the 7-point vacuum Laplacian,
+ * by the library's 3-D FFT and discrete Green's function (Eq. 15 on the
+ * grid). */
+int dwp_vacuum_solve(dwp_ctx *ctx, const double *r_dev, double *out_dev);
+/* out = one application of the dry/wet split to r (the preconditioner of the
+ * coupled iteration). */
+int dwp_apply_split(dwp_ctx *ctx, const double *r_dev, double *out_dev);
+/* E = 1/2 h^3 sum rho phi (compensated, deterministic). */
+int dwp_energy(dwp_ctx *ctx, const double *rho_dev, const double *phi_dev, double *energy_host);
+
+/* Validate a grid and options on the host and report the solver plan without
+ * touching a device: out[0] = first wet plane k_w0 (in [0, nz)), out[1] =
+ * k_w1 (W = planes [k_w0, k_w1) mod nz), out[2] = number of multigrid levels
+ * nl, then (nx, ny, nw) of each level.  out_len must be >= 3 + 3 nl (100 is
+ * always enough).  Errors are described by dwp_last_error(NULL). */
+int dwp_plan(int nx, int ny, int nz, double Lx, double Ly, double Lz, const dwp_opts *opts, int *out,
+             int out_len);
+
+/* Message of the last failure on this context (ctx-owned, valid until the
+ * next call).  Also accepts NULL (then describes the last dwp_create error). */
+const char *dwp_last_error(const dwp_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DWP_H */

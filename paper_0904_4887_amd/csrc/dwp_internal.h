@@ -1,0 +1,201 @@
+// Internal declarations of libdwp: device buffers, multigrid levels, the
+// context, and the host-side launchers of every kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dwp.h"
+
+namespace dwp {
+
+// ----------------------------------------------------------------------------
+// Error handling: every HIP call is checked; a failure becomes a C++ exception
+// inside the library and a dwp_status at the ABI boundary.
+struct Error {
+    int status;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int status, const std::string &msg);
+
+#define DWP_HIP(call)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            ::dwp::fail(DWP_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define DWP_LAUNCH_CHECK() DWP_HIP(hipGetLastError())
+
+// Device buffer owned by the context (RAII).
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void alloc(size_t n_bytes);
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// ----------------------------------------------------------------------------
+// One level of the wet-slab hierarchy.  Arrays of the unknowns and of eps hold
+// nw + 2 planes: plane 0 and plane nw + 1 are the Dirichlet planes next to the
+// slab (zero for the correction, the neighbouring node eps for eps); plane
+// p = k + 1 holds slab plane k.  x and y are periodic.
+struct Level {
+    int nx = 0, ny = 0, nw = 0;   // slab dimensions of this level
+    double h[3] = {0, 0, 0};
+    bool zc = false;              // coarsened in z from the previous level
+    size_t plane = 0;             // nx * ny
+    DevBuf eps;                   // (nw + 2) planes, T
+    DevBuf u;                     // (nw + 2) planes, T, ghost planes zero
+    DevBuf f;                     // nw planes, T
+    DevBuf r;                     // nw planes, T (residual scratch)
+    size_t n_interior() const { return plane * (size_t)nw; }
+    size_t n_ghosted() const { return plane * (size_t)(nw + 2); }
+};
+
+struct Plan {
+    int nx = 0, ny = 0, nz = 0;
+    double L[3] = {0, 0, 0};
+    double h[3] = {0, 0, 0};
+    size_t N = 0;
+    int nkx = 0;                  // nx / 2 + 1
+    int k_w0 = 0, k_w1 = 0;       // wet planes [k_w0, k_w1) mod nz
+    int nw = 0;                   // k_w1 - k_w0
+    std::vector<Level *> levels;  // levels[0] is the fine slab
+};
+
+// Radix plan of one FFT axis.
+struct FFTAxis {
+    int n = 0;
+    std::vector<int> radices;     // product = n
+    DevBuf tw;                    // n complex twiddles exp(-2 pi i t / n), double2
+    DevBuf lam;                   // n (or nkx for x) discrete symbol values
+};
+
+struct Timers {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
+}  // namespace dwp
+
+struct dwp_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    dwp_opts opts{};
+    dwp::Plan plan;
+    bool have_grid = false, have_eps = false, have_solution = false;
+    int precision_built = -1;     // precision of the current level buffers
+
+    // full-box float64 arrays
+    dwp::DevBuf eps, sinv, S, b, r, w, phi_last, gbuf;
+    dwp::DevBuf V, Z;             // Krylov bases, (restart + 1) N and restart N
+    dwp::DevBuf cbuf;             // FFT workspace, nkx * ny * nz double2
+    dwp::DevBuf Hz;               // per-plane height factor (exclusion)
+    dwp::DevBuf partial;          // reduction partials
+    dwp::DevBuf coef;             // small device vectors (Krylov coefficients)
+    dwp::DevBuf atoms;            // packed atom data
+    dwp::DevBuf fpart;            // force partials
+    dwp::FFTAxis fx, fy, fz;
+    double *host = nullptr;       // pinned host staging (small)
+    size_t host_len = 0;
+    dwp::Timers t;
+    double mean_rho = 0.0;
+    // atom bookkeeping of the last build_epsilon
+    int eps_natoms = -1;
+    bool eps_exclusion = false;
+};
+
+namespace dwp {
+
+constexpr int RED_BLOCKS = 1024;      // blocks of every partial-sum kernel
+constexpr int RED_THREADS = 256;
+
+// ----------------------------------------------------------------------------
+// Launchers (defined in the kernel translation units).
+
+// kern_grid.hip: full-box stencils
+void launch_apply_full(hipStream_t s, const Plan &p, const double *phi, const double *eps,
+                       const double *b, double *out, bool residual);
+void launch_eps_gradient(hipStream_t s, const Plan &p, const double *phi, double *g);
+void launch_fill(hipStream_t s, double *x, double v, size_t n);
+void launch_axpby(hipStream_t s, double *y, double a, const double *x, double b, size_t n);
+void launch_scale_dev(hipStream_t s, double *x, const double *num, const double *den_sq,
+                      size_t n, int mode);
+void launch_rhs(hipStream_t s, const double *rho, const double *sum, double inv_n, double *b, size_t n);
+void launch_sub_mean(hipStream_t s, double *x, const double *sum, double inv_n, size_t n);
+void launch_mul(hipStream_t s, double *y, const double *a, const double *x, size_t n);
+void launch_rsqrt(hipStream_t s, const double *eps, double *sinv, size_t n);
+void launch_check_eps(hipStream_t s, const double *eps, size_t n, int *flags);
+void launch_check_finite(hipStream_t s, const double *x, size_t n, int *flags);
+
+// wet slab <-> full box
+template <class T>
+void launch_wet_residual(hipStream_t s, const Plan &p, const double *v, const double *dD,
+                         const double *eps, T *fW);
+template <class T>
+void launch_wet_add(hipStream_t s, const Plan &p, const T *uW, double *z);
+template <class T>
+void launch_wet_eps(hipStream_t s, const Plan &p, const double *eps, T *epsW);
+
+// level operations
+template <class T>
+void launch_level_residual(hipStream_t s, const Level &L, T *r);  // r = f - A u
+template <class T>
+void launch_level_smooth(hipStream_t s, const Level &L, int color);
+template <class T>
+void launch_level_coarse_solve(hipStream_t s, const Level &L, int sweeps);
+template <class T>
+void launch_restrict(hipStream_t s, const Level &F, const Level &C, const T *rf, T *fc);
+template <class T>
+void launch_prolong_add(hipStream_t s, const Level &F, const Level &C);
+template <class T>
+void launch_coarsen_eps(hipStream_t s, const Level &F, const Level &C);
+template <class T>
+void launch_zero(hipStream_t s, T *x, size_t n);
+
+// kern_fft.hip
+void fft_plan_axis(FFTAxis &ax, int n, double h, bool half);
+// out = s .* L^{-1} (s .* r) (s == nullptr: unscaled), zero mean
+void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay,
+                         const FFTAxis &az, const double *r, const double *sinv, double2 *cbuf,
+                         double *out);
+
+// kern_blas.hip: deterministic reductions
+void launch_dot(hipStream_t s, const double *x, const double *y, size_t n, double *partial,
+                double *out);
+void launch_sum(hipStream_t s, const double *x, size_t n, double *partial, double *out);
+void launch_multidot(hipStream_t s, const double *V, size_t ldv, int nv, const double *w,
+                     size_t n, double *partial, double *out);
+// w -= sum_i c[i] V_i ; if norm_out: *norm_out = ||w||^2
+void launch_axpy_multi(hipStream_t s, double *w, const double *V, size_t ldv, int nv,
+                       const double *c, size_t n, double sign, double *partial, double *norm_out);
+// energy sums: out[0] = sum rho phi (compensated), out[1] = sum_faces eps_f (D_f phi)^2
+void launch_energy(hipStream_t s, const Plan &p, const double *rho, const double *phi,
+                   const double *eps, double *partial, double *out);
+
+// kern_atoms.hip
+struct AtomParams {
+    double eps_inf, delta, delta_z, z_lim;
+    int exclusion;
+};
+void launch_build_eps(hipStream_t s, const Plan &p, int n, const double *atoms_dev,
+                      const AtomParams &ap, double *Hz, double *eps, double *S);
+void launch_build_rho(hipStream_t s, const Plan &p, int n, const double *atoms_dev,
+                      double *rho);
+void launch_forces(hipStream_t s, const Plan &p, int n, const double *atoms_dev,
+                   const AtomParams *ap, const double *phi, const double *g, const double *S,
+                   const double *Hz, double *fpart, double *out);
+size_t forces_partial_len(const Plan &p, int n);
+
+}  // namespace dwp

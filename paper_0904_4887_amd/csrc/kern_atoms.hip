@@ -1,0 +1,387 @@
+// Atom-dependent kernels: the permittivity built from the atoms, the Gaussian
+// charge density, and the atomic forces dE/dR (paper Eq. 11, App. B).
+//
+// Permittivity: eps_n = 1 + (eps_inf - 1) prod_i s_i(d_in) H(z_n) with
+// s_i(d) = 1/2 [1 + erf((d - r_i)/delta)] (exactly 0 below r_i - 6 delta and 1
+// beyond r_i + 6 delta) and, when the exclusion rule is on, the height factor
+// H(z) = prod_{z_i <= z_lim} 1/2 [1 + erf((z - z_i)/delta_z)] of the buried
+// atoms (the smooth counterpart of the paper's Eq. 19).
+//
+// Forces: dE/dR_I = sum_n g_n d eps_n/dR_I + h^3 sum_n phi_n d rho_n/dR_I with
+// g = dE/d eps.  The switch part uses the product of the OTHER switches at
+// each node, evaluated directly (never as S / s_I, since s_I may vanish).  The
+// height-factor part of buried atoms depends on z only and is reduced per
+// plane first.  All sums are per block, then per atom in a fixed order.
+//
+// Packed atom record (8 doubles): x, y, z, radius, q, sigma, buried, 0.
+#include "dwp_internal.h"
+
+namespace dwp {
+
+namespace {
+
+constexpr int AT_THREADS = 256;
+constexpr int AREC = 8;
+constexpr double PI = 3.14159265358979323846;
+constexpr double SQRT_PI = 1.77245385090551602730;
+
+__device__ __forceinline__ double min_image(double d, double L, double invL) { return d - L * rint(d * invL); }
+
+struct Box {
+    int nx, ny, nz;
+    double hx, hy, hz, Lx, Ly, Lz, iLx, iLy, iLz;
+};
+
+Box make_box(const Plan &p) {
+    Box b;
+    b.nx = p.nx; b.ny = p.ny; b.nz = p.nz;
+    b.hx = p.h[0]; b.hy = p.h[1]; b.hz = p.h[2];
+    b.Lx = p.L[0]; b.Ly = p.L[1]; b.Lz = p.L[2];
+    b.iLx = 1.0 / p.L[0]; b.iLy = 1.0 / p.L[1]; b.iLz = 1.0 / p.L[2];
+    return b;
+}
+
+// Block-wide exclusive scan of 0/1 flags (AT_THREADS entries); returns this
+// thread's slot and writes the total to *total.  Deterministic order.
+__device__ int block_compact(int flag, int *scan, int *total) {
+    scan[threadIdx.x] = flag;
+    __syncthreads();
+    for (int off = 1; off < AT_THREADS; off <<= 1) {
+        const int v = (int)threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
+        __syncthreads();
+        scan[threadIdx.x] += v;
+        __syncthreads();
+    }
+    const int incl = scan[threadIdx.x];
+    *total = scan[AT_THREADS - 1];
+    __syncthreads();
+    return incl - flag;
+}
+
+// Tile of the grid handled by one block of the builders: 32 x 4 x 2 nodes.
+constexpr int TX = 32, TY = 4, TZ = 2;
+
+// Minimum-image distance (squared) from point a to the axis-aligned tile
+// [lo, hi] (lengths well below L / 2).
+__device__ __forceinline__ double dist2_to_tile(const Box &b, double ax, double ay, double az, double x0, double x1,
+                                                double y0, double y1, double z0, double z1) {
+    const double cx = 0.5 * (x0 + x1), cy = 0.5 * (y0 + y1), cz = 0.5 * (z0 + z1);
+    const double dx = fmax(0.0, fabs(min_image(ax - cx, b.Lx, b.iLx)) - 0.5 * (x1 - x0));
+    const double dy = fmax(0.0, fabs(min_image(ay - cy, b.Ly, b.iLy)) - 0.5 * (y1 - y0));
+    const double dz = fmax(0.0, fabs(min_image(az - cz, b.Lz, b.iLz)) - 0.5 * (z1 - z0));
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// mode 0: permittivity switches (cutoff r + 6 delta); mode 1: Gaussians (9 sigma)
+template <int MODE>
+__global__ void __launch_bounds__(AT_THREADS)
+k_build(const double *__restrict__ atoms, int natoms, Box b, double eps_inf, double delta,
+        const double *__restrict__ Hz, double *__restrict__ out, double *__restrict__ S) {
+    __shared__ double ax[AT_THREADS], ay[AT_THREADS], az[AT_THREADS], ar[AT_THREADS], aq[AT_THREADS];
+    __shared__ int scan[AT_THREADS];
+    __shared__ int cnt;
+    const int tx = threadIdx.x % TX, ty = (threadIdx.x / TX) % TY, tz = threadIdx.x / (TX * TY);
+    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY, k0 = blockIdx.z * TZ;
+    const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
+    const bool live = i < b.nx && j < b.ny && k < b.nz;
+    const double x = i * b.hx, y = j * b.hy, z = k * b.hz;
+    const double x0 = i0 * b.hx, x1 = min(i0 + TX - 1, b.nx - 1) * b.hx;
+    const double y0 = j0 * b.hy, y1 = min(j0 + TY - 1, b.ny - 1) * b.hy;
+    const double z0 = k0 * b.hz, z1 = min(k0 + TZ - 1, b.nz - 1) * b.hz;
+    double acc = MODE == 0 ? 1.0 : 0.0;
+    bool zero = false;
+    for (int base = 0; base < natoms; base += AT_THREADS) {
+        const int a = base + threadIdx.x;
+        int keep = 0;
+        double px = 0, py = 0, pz = 0, pr = 0, pq = 0;
+        if (a < natoms) {
+            const double *r = atoms + (size_t)a * AREC;
+            px = r[0]; py = r[1]; pz = r[2];
+            const double cut = MODE == 0 ? r[3] + 6.0 * delta : 9.0 * r[5];
+            pr = MODE == 0 ? r[3] : r[5];
+            pq = r[4];
+            keep = dist2_to_tile(b, px, py, pz, x0, x1, y0, y1, z0, z1) < cut * cut;
+        }
+        int total;
+        const int slot = block_compact(keep, scan, &total);
+        if (keep) { ax[slot] = px; ay[slot] = py; az[slot] = pz; ar[slot] = pr; aq[slot] = pq; }
+        if (threadIdx.x == 0) cnt = total;
+        __syncthreads();
+        const int m = cnt;
+        if (live && !zero) {
+            for (int q = 0; q < m; ++q) {
+                const double dx = min_image(x - ax[q], b.Lx, b.iLx);
+                const double dy = min_image(y - ay[q], b.Ly, b.iLy);
+                const double dz = min_image(z - az[q], b.Lz, b.iLz);
+                const double d2 = dx * dx + dy * dy + dz * dz;
+                if (MODE == 0) {
+                    const double d = sqrt(d2);
+                    const double t = (d - ar[q]) / delta;
+                    if (t <= -6.0) { zero = true; break; }
+                    if (t < 6.0) acc *= 0.5 * (1.0 + erf(t));
+                } else {
+                    const double s2 = ar[q] * ar[q];
+                    if (d2 < 81.0 * s2) acc += aq[q] * pow(2.0 * PI * s2, -1.5) * exp(-d2 / (2.0 * s2));
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (!live) return;
+    const size_t c = ((size_t)k * b.ny + j) * b.nx + i;
+    if (MODE == 0) {
+        const double Sv = zero ? 0.0 : acc;
+        const double H = Hz ? Hz[k] : 1.0;
+        out[c] = 1.0 + (eps_inf - 1.0) * Sv * H;
+        if (S) S[c] = Sv;
+    } else {
+        out[c] = acc;
+    }
+}
+
+// H(z_k) = prod over buried atoms of 1/2 [1 + erf((z_k - z_i)/delta_z)]
+__global__ void k_height(const double *__restrict__ atoms, int natoms, int nz, double hz, double delta_z,
+                         double *__restrict__ Hz) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nz) return;
+    const double z = k * hz;
+    double H = 1.0;
+    for (int a = 0; a < natoms; ++a) {
+        const double *r = atoms + (size_t)a * AREC;
+        if (r[6] == 0.0) continue;
+        const double t = (z - r[2]) / delta_z;
+        if (t <= -6.0) { H = 0.0; break; }
+        if (t < 6.0) H *= 0.5 * (1.0 + erf(t));
+    }
+    Hz[k] = H;
+}
+
+// ---------------------------------------------------------------- forces
+// Block = (atom a, chunk c) over the cube of nodes around atom a.
+__global__ void __launch_bounds__(AT_THREADS)
+k_forces(const double *__restrict__ atoms, int natoms, Box b, int eps_mode, double eps_inf, double delta,
+         const double *__restrict__ phi, const double *__restrict__ g, const double *__restrict__ Hz,
+         int nchunk, double *__restrict__ fpart) {
+    __shared__ double ax[AT_THREADS], ay[AT_THREADS], az[AT_THREADS], ar[AT_THREADS];
+    __shared__ int scan[AT_THREADS];
+    __shared__ int cnt;
+    __shared__ double red[3][AT_THREADS / 64];
+    const int a = blockIdx.x / nchunk, chunk = blockIdx.x % nchunk;
+    const double *ra = atoms + (size_t)a * AREC;
+    const double X = ra[0], Y = ra[1], Z = ra[2], Ra = ra[3], Q = ra[4], Sg = ra[5];
+    const double ceps = eps_mode ? Ra + 6.0 * delta : 0.0;
+    const double crho = 9.0 * Sg;
+    const double Rc = fmax(ceps, crho);
+    const double h3 = b.hx * b.hy * b.hz;
+    const double gnorm = Q * pow(2.0 * PI * Sg * Sg, -1.5);
+    // node ranges (unwrapped indices)
+    const int ilo = (int)ceil((X - Rc) / b.hx), ihi = (int)floor((X + Rc) / b.hx);
+    const int jlo = (int)ceil((Y - Rc) / b.hy), jhi = (int)floor((Y + Rc) / b.hy);
+    const int klo = (int)ceil((Z - Rc) / b.hz), khi = (int)floor((Z + Rc) / b.hz);
+    const int cx = ihi - ilo + 1, cy = jhi - jlo + 1, cz = khi - klo + 1;
+    const long total = (long)cx * cy * cz;
+    // neighbours whose switch can be != 1 where atom a's switch varies
+    int m = 0;
+    if (eps_mode) {
+        for (int base = 0; base < natoms; base += AT_THREADS) {
+            const int j = base + threadIdx.x;
+            int keep = 0;
+            double px = 0, py = 0, pz = 0, pr = 0;
+            if (j < natoms && j != a) {
+                const double *r = atoms + (size_t)j * AREC;
+                px = r[0]; py = r[1]; pz = r[2]; pr = r[3];
+                const double dx = min_image(px - X, b.Lx, b.iLx), dy = min_image(py - Y, b.Ly, b.iLy),
+                             dz = min_image(pz - Z, b.Lz, b.iLz);
+                const double lim = ceps + pr + 6.0 * delta;
+                keep = dx * dx + dy * dy + dz * dz < lim * lim;
+            }
+            int tot;
+            const int slot = block_compact(keep, scan, &tot);
+            if (keep && m + slot < AT_THREADS) { ax[m + slot] = px; ay[m + slot] = py; az[m + slot] = pz; ar[m + slot] = pr; }
+            if (threadIdx.x == 0) cnt = m + tot;
+            __syncthreads();
+            m = cnt;
+            __syncthreads();
+        }
+        if (m > AT_THREADS) m = AT_THREADS;  // guarded by the host (see launch_forces)
+    }
+    const long per = (total + nchunk - 1) / nchunk;
+    const long q0 = (long)chunk * per, q1 = min(total, q0 + per);
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    for (long q = q0 + threadIdx.x; q < q1; q += AT_THREADS) {
+        const int ii = (int)(q % cx), jj = (int)((q / cx) % cy), kk = (int)(q / ((long)cx * cy));
+        const int iu = ilo + ii, ju = jlo + jj, ku = klo + kk;
+        const int i = ((iu % b.nx) + b.nx) % b.nx, j = ((ju % b.ny) + b.ny) % b.ny, k = ((ku % b.nz) + b.nz) % b.nz;
+        const double x = i * b.hx, y = j * b.hy, z = k * b.hz;
+        const double dx = min_image(x - X, b.Lx, b.iLx), dy = min_image(y - Y, b.Ly, b.iLy), dz = min_image(z - Z, b.Lz, b.iLz);
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        const size_t c = ((size_t)k * b.ny + j) * b.nx + i;
+        // charge term: d rho_n / dR_a = q G(d) (r_n - R_a) / sigma^2
+        if (d2 < crho * crho) {
+            const double w = h3 * phi[c] * gnorm * exp(-d2 / (2.0 * Sg * Sg)) / (Sg * Sg);
+            fx += w * dx; fy += w * dy; fz += w * dz;
+        }
+        if (eps_mode) {
+            const double d = sqrt(d2);
+            const double t = (d - Ra) / delta;
+            if (t > -6.0 && t < 6.0 && d > 0.0) {
+                double P = 1.0;
+                for (int s = 0; s < m; ++s) {
+                    const double ex = min_image(x - ax[s], b.Lx, b.iLx), ey = min_image(y - ay[s], b.Ly, b.iLy),
+                                 ez = min_image(z - az[s], b.Lz, b.iLz);
+                    const double ts = (sqrt(ex * ex + ey * ey + ez * ez) - ar[s]) / delta;
+                    if (ts <= -6.0) { P = 0.0; break; }
+                    if (ts < 6.0) P *= 0.5 * (1.0 + erf(ts));
+                }
+                if (P != 0.0) {
+                    const double H = Hz ? Hz[k] : 1.0;
+                    const double ds = exp(-t * t) / (delta * SQRT_PI);
+                    // d d / dR_a = -(r - R_a) / d
+                    const double w = -g[c] * (eps_inf - 1.0) * H * P * ds / d;
+                    fx += w * dx; fy += w * dy; fz += w * dz;
+                }
+            }
+        }
+    }
+    // block reduction of (fx, fy, fz)
+    double v[3] = {fx, fy, fz};
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int c = 0; c < 3; ++c) {
+        double s = v[c];
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+        if (lane == 0) red[c][wid] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double s = 0.0;
+        for (int w = 0; w < AT_THREADS / 64; ++w) s += red[threadIdx.x][w];
+        fpart[(size_t)blockIdx.x * 3 + threadIdx.x] = s;
+    }
+}
+
+// Plane sums Q_k = sum_{i,j} g_ijk S_ijk (one block per plane).
+__global__ void __launch_bounds__(AT_THREADS)
+k_plane_gs(const double *__restrict__ g, const double *__restrict__ S, int nx, int ny, double *__restrict__ Q) {
+    __shared__ double red[AT_THREADS / 64];
+    const size_t plane = (size_t)nx * ny;
+    const size_t base = (size_t)blockIdx.x * plane;
+    double s = 0.0;
+    for (size_t t = threadIdx.x; t < plane; t += AT_THREADS) s += g[base + t] * S[base + t];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = 0.0;
+        for (int w = 0; w < AT_THREADS / 64; ++w) r += red[w];
+        Q[blockIdx.x] = r;
+    }
+}
+
+// Height-factor force on buried atom a (one block per atom):
+// dE/dz_a += (eps_inf - 1) sum_k Q_k prod_{K buried != a} h_K(z_k) (-h_a'(z_k)).
+__global__ void __launch_bounds__(AT_THREADS)
+k_height_forces(const double *__restrict__ atoms, int natoms, int nz, double hz, double delta_z, double eps_inf,
+                const double *__restrict__ Q, double *__restrict__ out) {
+    __shared__ double red[AT_THREADS / 64];
+    const int a = blockIdx.x;
+    const double *ra = atoms + (size_t)a * AREC;
+    if (ra[6] == 0.0) {
+        if (threadIdx.x == 0) out[a] = 0.0;
+        return;
+    }
+    const double za = ra[2];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nz; k += AT_THREADS) {
+        const double z = k * hz;
+        const double ta = (z - za) / delta_z;
+        if (ta <= -6.0 || ta >= 6.0) continue;
+        double P = 1.0;
+        for (int K = 0; K < natoms; ++K) {
+            if (K == a) continue;
+            const double *r = atoms + (size_t)K * AREC;
+            if (r[6] == 0.0) continue;
+            const double t = (z - r[2]) / delta_z;
+            if (t <= -6.0) { P = 0.0; break; }
+            if (t < 6.0) P *= 0.5 * (1.0 + erf(t));
+        }
+        const double dh = exp(-ta * ta) / (delta_z * SQRT_PI);  // d h_a / dz; d h_a / dz_a = -dh
+        s += Q[k] * P * (-dh);
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = 0.0;
+        for (int w = 0; w < AT_THREADS / 64; ++w) r += red[w];
+        out[a] = (eps_inf - 1.0) * r;
+    }
+}
+
+// out[a][c] = sum over chunks (fixed order) [+ height term on z]
+__global__ void k_forces_final(const double *__restrict__ fpart, int natoms, int nchunk,
+                               const double *__restrict__ hforce, double *__restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= natoms * 3) return;
+    const int a = t / 3, c = t % 3;
+    double s = 0.0;
+    for (int q = 0; q < nchunk; ++q) s += fpart[((size_t)a * nchunk + q) * 3 + c];
+    if (hforce && c == 2) s += hforce[a];
+    out[t] = s;
+}
+
+int chunks_for(int natoms) {
+    int nch = 8192 / (natoms > 0 ? natoms : 1);
+    if (nch < 1) nch = 1;
+    if (nch > 512) nch = 512;
+    return nch;
+}
+
+}  // namespace
+
+void launch_build_eps(hipStream_t s, const Plan &p, int n, const double *atoms_dev, const AtomParams &ap,
+                      double *Hz, double *eps, double *S) {
+    Box b = make_box(p);
+    if (ap.exclusion) {
+        k_height<<<(p.nz + 127) / 128, 128, 0, s>>>(atoms_dev, n, p.nz, p.h[2], ap.delta_z, Hz);
+        DWP_LAUNCH_CHECK();
+    }
+    dim3 g((p.nx + TX - 1) / TX, (p.ny + TY - 1) / TY, (p.nz + TZ - 1) / TZ);
+    k_build<0><<<g, AT_THREADS, 0, s>>>(atoms_dev, n, b, ap.eps_inf, ap.delta, ap.exclusion ? Hz : nullptr, eps,
+                                        ap.exclusion ? S : nullptr);
+    DWP_LAUNCH_CHECK();
+}
+
+void launch_build_rho(hipStream_t s, const Plan &p, int n, const double *atoms_dev, double *rho) {
+    Box b = make_box(p);
+    dim3 g((p.nx + TX - 1) / TX, (p.ny + TY - 1) / TY, (p.nz + TZ - 1) / TZ);
+    k_build<1><<<g, AT_THREADS, 0, s>>>(atoms_dev, n, b, 0.0, 0.0, nullptr, rho, nullptr);
+    DWP_LAUNCH_CHECK();
+}
+
+size_t forces_partial_len(const Plan &p, int n) {
+    return (size_t)n * chunks_for(n) * 3 + (size_t)p.nz + (size_t)n + 64;
+}
+
+// fpart: forces_partial_len doubles; out: 3n doubles (device)
+void launch_forces(hipStream_t s, const Plan &p, int n, const double *atoms_dev, const AtomParams *ap,
+                   const double *phi, const double *g, const double *S, const double *Hz, double *fpart,
+                   double *out) {
+    Box b = make_box(p);
+    const int nch = chunks_for(n);
+    const bool excl = ap && ap->exclusion;
+    k_forces<<<n * nch, AT_THREADS, 0, s>>>(atoms_dev, n, b, ap ? 1 : 0, ap ? ap->eps_inf : 1.0,
+                                            ap ? ap->delta : 1.0, phi, g, excl ? Hz : nullptr, nch, fpart);
+    DWP_LAUNCH_CHECK();
+    double *Q = fpart + (size_t)n * nch * 3;
+    double *hf = Q + p.nz;
+    if (excl) {
+        k_plane_gs<<<p.nz, AT_THREADS, 0, s>>>(g, S, p.nx, p.ny, Q);
+        DWP_LAUNCH_CHECK();
+        k_height_forces<<<n, AT_THREADS, 0, s>>>(atoms_dev, n, p.nz, p.h[2], ap->delta_z, ap->eps_inf, Q, hf);
+        DWP_LAUNCH_CHECK();
+    }
+    k_forces_final<<<(3 * n + 127) / 128, 128, 0, s>>>(fpart, n, nch, excl ? hf : nullptr, out);
+    DWP_LAUNCH_CHECK();
+}
+
+}  // namespace dwp

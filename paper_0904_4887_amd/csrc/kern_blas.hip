@@ -1,0 +1,230 @@
+// Deterministic reductions and the Krylov vector kernels.
+//
+// Every reduction runs on a fixed grid of RED_BLOCKS blocks: each block
+// reduces its grid-stride share with wave64 shuffles and LDS and writes one
+// partial per output; a second kernel adds the partials of each output in a
+// fixed tree order.  Results are therefore bitwise reproducible.  The energy
+// sums use compensated (two-sum) accumulation throughout.
+#include "dwp_internal.h"
+
+namespace dwp {
+
+namespace {
+
+constexpr int MD_GROUP = 8;  // dot products per pass of multidot
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// Sum of v over the block; valid in thread 0.  `sh` holds one double per wave.
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int q = 0; q < nw; ++q) r += sh[q];
+    }
+    return r;
+}
+
+// two-sum accumulator
+struct DD {
+    double s, c;
+};
+__device__ __forceinline__ DD dd_add(DD a, double b) {
+    const double s = a.s + b;
+    const double bp = s - a.s;
+    const double e = (a.s - (s - bp)) + (b - bp);
+    return DD{s, a.c + e};
+}
+__device__ __forceinline__ DD dd_merge(DD a, DD b) {
+    const double s = a.s + b.s;
+    const double bp = s - a.s;
+    const double e = (a.s - (s - bp)) + (b.s - bp);
+    return DD{s, a.c + b.c + e};
+}
+__device__ __forceinline__ DD wave_dd(DD v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        DD w{__shfl_down(v.s, o, 64), __shfl_down(v.c, o, 64)};
+        v = dd_merge(v, w);
+    }
+    return v;
+}
+
+__global__ void __launch_bounds__(RED_THREADS)
+k_multidot(const double *__restrict__ V, size_t ldv, int v0, int nv, const double *__restrict__ w, size_t n,
+           double *__restrict__ partial, int stride) {
+    __shared__ double sh[RED_THREADS / 64];
+    double acc[MD_GROUP];
+#pragma unroll
+    for (int q = 0; q < MD_GROUP; ++q) acc[q] = 0.0;
+    for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n; t += (size_t)gridDim.x * RED_THREADS) {
+        const double wt = w[t];
+#pragma unroll
+        for (int q = 0; q < MD_GROUP; ++q)
+            if (q < nv) acc[q] += V[(size_t)(v0 + q) * ldv + t] * wt;
+    }
+#pragma unroll
+    for (int q = 0; q < MD_GROUP; ++q) {
+        if (q < nv) {
+            const double r = block_sum(acc[q], sh);
+            if (threadIdx.x == 0) partial[(size_t)blockIdx.x * stride + v0 + q] = r;
+        }
+    }
+}
+
+// out[idx] = sum_b partial[b * stride + idx], one block per idx, fixed order
+__global__ void __launch_bounds__(RED_THREADS)
+k_reduce_partials(const double *__restrict__ partial, int nblocks, int stride, double *__restrict__ out) {
+    __shared__ double sh[RED_THREADS / 64];
+    const int idx = blockIdx.x;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += RED_THREADS) v += partial[(size_t)b * stride + idx];
+    const double r = block_sum(v, sh);
+    if (threadIdx.x == 0) out[idx] = r;
+}
+
+__global__ void __launch_bounds__(RED_THREADS)
+k_sum(const double *__restrict__ x, size_t n, double *__restrict__ partial) {
+    __shared__ double sh[RED_THREADS / 64];
+    double acc = 0.0;
+    for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n; t += (size_t)gridDim.x * RED_THREADS)
+        acc += x[t];
+    const double r = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+// w += sign * sum_q c[q] V_q ; optionally partial[blockIdx] = sum w_new^2
+__global__ void __launch_bounds__(RED_THREADS)
+k_axpy_multi(double *__restrict__ w, const double *__restrict__ V, size_t ldv, int nv,
+             const double *__restrict__ c, size_t n, double sign, double *__restrict__ partial) {
+    __shared__ double sh[RED_THREADS / 64];
+    __shared__ double cs[64];
+    for (int q = threadIdx.x; q < nv && q < 64; q += RED_THREADS) cs[q] = sign * c[q];
+    __syncthreads();
+    double nrm = 0.0;
+    for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n; t += (size_t)gridDim.x * RED_THREADS) {
+        double acc = w[t];
+        for (int q = 0; q < nv; ++q) acc += cs[q] * V[(size_t)q * ldv + t];
+        w[t] = acc;
+        nrm += acc * acc;
+    }
+    if (partial) {
+        const double r = block_sum(nrm, sh);
+        if (threadIdx.x == 0) partial[blockIdx.x] = r;
+    }
+}
+
+// Energy sums with two-sum accumulation: [0] sum rho phi, [1] sum over the
+// three forward faces of every node of eps_f (D_f phi)^2.
+__global__ void __launch_bounds__(RED_THREADS)
+k_energy(const double *__restrict__ rho, const double *__restrict__ phi, const double *__restrict__ eps,
+         int nx, int ny, int nz, double cx, double cy, double cz, double *__restrict__ partial) {
+    __shared__ double shs[2][RED_THREADS / 64], shc[2][RED_THREADS / 64];
+    DD a{0.0, 0.0}, f{0.0, 0.0};
+    const size_t plane = (size_t)nx * ny, n = plane * nz;
+    for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n; t += (size_t)gridDim.x * RED_THREADS) {
+        const int i = (int)(t % nx);
+        const int j = (int)((t / nx) % ny);
+        const int k = (int)(t / plane);
+        const double p0 = phi[t], e0 = eps[t];
+        a = dd_add(a, rho[t] * p0);
+        const size_t xp = t - i + (i + 1 == nx ? 0 : i + 1);
+        const size_t yp = t + (size_t)((j + 1 == ny ? 0 : j + 1) - j) * nx;
+        const size_t zp = t + (size_t)((k + 1 == nz ? 0 : k + 1) - k) * plane;
+        const double dx = phi[xp] - p0, dy = phi[yp] - p0, dz = phi[zp] - p0;
+        const double fx = 0.5 * (e0 + eps[xp]) * dx * dx * cx;
+        const double fy = 0.5 * (e0 + eps[yp]) * dy * dy * cy;
+        const double fz = 0.5 * (e0 + eps[zp]) * dz * dz * cz;
+        f = dd_add(dd_add(dd_add(f, fx), fy), fz);
+    }
+    a = wave_dd(a);
+    f = wave_dd(f);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        shs[0][wid] = a.s; shc[0][wid] = a.c;
+        shs[1][wid] = f.s; shc[1][wid] = f.c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        DD ra{0.0, 0.0}, rf{0.0, 0.0};
+        for (int q = 0; q < RED_THREADS / 64; ++q) {
+            ra = dd_merge(ra, DD{shs[0][q], shc[0][q]});
+            rf = dd_merge(rf, DD{shs[1][q], shc[1][q]});
+        }
+        partial[(size_t)blockIdx.x * 4 + 0] = ra.s;
+        partial[(size_t)blockIdx.x * 4 + 1] = ra.c;
+        partial[(size_t)blockIdx.x * 4 + 2] = rf.s;
+        partial[(size_t)blockIdx.x * 4 + 3] = rf.c;
+    }
+}
+
+__global__ void __launch_bounds__(64)
+k_energy_final(const double *__restrict__ partial, int nblocks, double *__restrict__ out) {
+    // one wave; lane q merges blocks q, q + 64, ... then a fixed shuffle tree
+    DD a{0.0, 0.0}, f{0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += 64) {
+        a = dd_merge(a, DD{partial[(size_t)b * 4 + 0], partial[(size_t)b * 4 + 1]});
+        f = dd_merge(f, DD{partial[(size_t)b * 4 + 2], partial[(size_t)b * 4 + 3]});
+    }
+    a = wave_dd(a);
+    f = wave_dd(f);
+    if (threadIdx.x == 0) {
+        out[0] = a.s + a.c;
+        out[1] = f.s + f.c;
+    }
+}
+
+}  // namespace
+
+void launch_multidot(hipStream_t s, const double *V, size_t ldv, int nv, const double *w, size_t n,
+                     double *partial, double *out) {
+    for (int v0 = 0; v0 < nv; v0 += MD_GROUP) {
+        const int g = nv - v0 < MD_GROUP ? nv - v0 : MD_GROUP;
+        k_multidot<<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, v0, g, w, n, partial, 64);
+        DWP_LAUNCH_CHECK();
+    }
+    k_reduce_partials<<<nv, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, 64, out);
+    DWP_LAUNCH_CHECK();
+}
+
+void launch_dot(hipStream_t s, const double *x, const double *y, size_t n, double *partial, double *out) {
+    launch_multidot(s, x, n, 1, y, n, partial, out);
+}
+
+void launch_sum(hipStream_t s, const double *x, size_t n, double *partial, double *out) {
+    k_sum<<<RED_BLOCKS, RED_THREADS, 0, s>>>(x, n, partial);
+    DWP_LAUNCH_CHECK();
+    k_reduce_partials<<<1, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, 1, out);
+    DWP_LAUNCH_CHECK();
+}
+
+void launch_axpy_multi(hipStream_t s, double *w, const double *V, size_t ldv, int nv, const double *c, size_t n,
+                       double sign, double *partial, double *norm_out) {
+    if (nv > 64) fail(DWP_EINVAL, "axpy_multi: at most 64 vectors");
+    k_axpy_multi<<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, V, ldv, nv, c, n, sign, norm_out ? partial : nullptr);
+    DWP_LAUNCH_CHECK();
+    if (norm_out) {
+        k_reduce_partials<<<1, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, 1, norm_out);
+        DWP_LAUNCH_CHECK();
+    }
+}
+
+void launch_energy(hipStream_t s, const Plan &p, const double *rho, const double *phi, const double *eps,
+                   double *partial, double *out) {
+    k_energy<<<RED_BLOCKS, RED_THREADS, 0, s>>>(rho, phi, eps, p.nx, p.ny, p.nz, 1.0 / (p.h[0] * p.h[0]),
+                                                1.0 / (p.h[1] * p.h[1]), 1.0 / (p.h[2] * p.h[2]), partial);
+    DWP_LAUNCH_CHECK();
+    k_energy_final<<<1, 64, 0, s>>>(partial, RED_BLOCKS, out);
+    DWP_LAUNCH_CHECK();
+}
+
+}  // namespace dwp

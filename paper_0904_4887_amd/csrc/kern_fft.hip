@@ -1,0 +1,337 @@
+// Periodic vacuum Poisson solve by a hand-written mixed-radix 3-D FFT.
+//
+// psi = L^{-1} r with L the 7-point vacuum Laplacian: in Fourier space
+// psi~(m) = -r~(m) / lambda(m), lambda(m) = sum_d 4 sin^2(pi m_d / n_d) / h_d^2,
+// psi~(0) = 0 -- the grid counterpart of the paper's Eq. 15, with the discrete
+// symbol in place of G^2 so that the dry update inverts exactly the operator
+// the wet multigrid discretises.
+//
+// Five passes over HBM, each a batch of 1-D transforms staged in LDS:
+//   x  : two real rows packed as one complex row, forward, split (R2C)
+//   y  : forward along y on tiles of consecutive kx
+//   z  : forward along z, multiply by -1/(N lambda), inverse along z
+//   y  : inverse
+//   x  : inverse of two rows at once (C2R)
+// Each 1-D transform is a Stockham autosort FFT with radix-4, -3 and -2
+// stages; a stage reads its inputs into registers, synchronises, and writes
+// its outputs back in place.
+#include "dwp_internal.h"
+
+#include <cmath>
+
+namespace dwp {
+
+namespace {
+
+constexpr int FFT_THREADS = 256;
+constexpr int MAX_STAGES = 12;
+
+struct Radices {
+    int n;
+    int nst;
+    int r[MAX_STAGES];
+};
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+// multiply by -i (forward) or +i (inverse)
+__device__ __forceinline__ double2 rot(double2 a, bool inv) {
+    return inv ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+
+template <int R> __device__ __forceinline__ void dft(double2 *x, bool inv);
+
+template <> __device__ __forceinline__ void dft<2>(double2 *x, bool) {
+    const double2 a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+}
+template <> __device__ __forceinline__ void dft<4>(double2 *x, bool inv) {
+    const double2 a = cadd(x[0], x[2]), b = csub(x[0], x[2]);
+    const double2 c = cadd(x[1], x[3]), d = csub(x[1], x[3]);
+    x[0] = cadd(a, c);
+    x[2] = csub(a, c);
+    const double2 rd = rot(d, inv);  // -i d (forward)
+    x[1] = cadd(b, rd);
+    x[3] = csub(b, rd);
+}
+template <> __device__ __forceinline__ void dft<3>(double2 *x, bool inv) {
+    // w = exp(-2 pi i / 3) = -1/2 - i sqrt(3)/2
+    const double s3 = 0.86602540378443864676;
+    const double2 t1 = cadd(x[1], x[2]);
+    const double2 t2 = make_double2(x[0].x - 0.5 * t1.x, x[0].y - 0.5 * t1.y);
+    const double2 d = csub(x[1], x[2]);
+    const double2 rd = rot(make_double2(s3 * d.x, s3 * d.y), inv);  // -i s3 d (forward)
+    x[0] = cadd(x[0], t1);
+    x[1] = cadd(t2, rd);
+    x[2] = csub(t2, rd);
+}
+
+// One Stockham stage of radix R on B lines of length n held in LDS; element
+// t of line l sits at buf[l * ls + t * es].  p = product of the radices of
+// the earlier stages.  Butterfly i of a line reads x_q = buf[i + q n/R],
+// twiddles x_q by exp(-+2 pi i q (i mod p) / (p R)), and writes output r to
+// (i - i mod p) R + i mod p + r p.
+template <int R>
+__device__ void stage(double2 *buf, int n, int p, int B, int es, int ls, const double2 *__restrict__ tw,
+                      bool inv) {
+    constexpr int K = (4096 / R + FFT_THREADS - 1) / FFT_THREADS;
+    const int T = n / R;
+    const int items = B * T;
+    const int tstride = n / (p * R);
+    double2 x[K][R];
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+        const int w = threadIdx.x + m * FFT_THREADS;
+        if (w < items) {
+            const int l = w % B, i = w / B;
+#pragma unroll
+            for (int q = 0; q < R; ++q) x[m][q] = buf[l * ls + (i + q * T) * es];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+        const int w = threadIdx.x + m * FFT_THREADS;
+        if (w < items) {
+            const int l = w % B, i = w / B;
+            const int k = i % p;
+            if (p > 1) {
+#pragma unroll
+                for (int q = 1; q < R; ++q) {
+                    double2 t = tw[q * k * tstride];
+                    if (inv) t.y = -t.y;
+                    x[m][q] = cmul(x[m][q], t);
+                }
+            }
+            dft<R>(x[m], inv);
+            const int j = (i - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[l * ls + (j + r * p) * es] = x[m][r];
+        }
+    }
+    __syncthreads();
+}
+
+__device__ void fft_lines(double2 *buf, const Radices &rd, int B, int es, int ls,
+                          const double2 *__restrict__ tw, bool inv) {
+    int p = 1;
+    for (int s = 0; s < rd.nst; ++s) {
+        const int R = rd.r[s];
+        if (R == 4) stage<4>(buf, rd.n, p, B, es, ls, tw, inv);
+        else if (R == 3) stage<3>(buf, rd.n, p, B, es, ls, tw, inv);
+        else stage<2>(buf, rd.n, p, B, es, ls, tw, inv);
+        p *= R;
+    }
+}
+
+// ---------------------------------------------------------------- x passes
+// Rows are the nx-long x lines of the [nz][ny][nx] grid; B complex lines per
+// block carry 2B real rows.  LDS lines are padded to n + 1 elements.
+__global__ void __launch_bounds__(FFT_THREADS)
+k_fft_x_fwd(const double *__restrict__ in, const double *__restrict__ sinv, double2 *__restrict__ out,
+            Radices rd, const double2 *__restrict__ tw, int B, int nrows, int nkx) {
+    extern __shared__ double2 lds[];
+    const int n = rd.n, ls = n + 1;
+    const int r0 = blockIdx.x * 2 * B;
+    for (int e = threadIdx.x; e < B * n; e += FFT_THREADS) {
+        const int l = e / n, t = e % n;
+        const int ra = r0 + 2 * l, rb = ra + 1;
+        double a = 0.0, b = 0.0;
+        if (rb < nrows) {
+            const size_t ia = (size_t)ra * n + t, ib = (size_t)rb * n + t;
+            a = in[ia];
+            b = in[ib];
+            if (sinv) { a *= sinv[ia]; b *= sinv[ib]; }
+        }
+        lds[l * ls + t] = make_double2(a, b);
+    }
+    __syncthreads();
+    fft_lines(lds, rd, B, 1, ls, tw, false);
+    for (int e = threadIdx.x; e < B * nkx; e += FFT_THREADS) {
+        const int l = e / nkx, k = e % nkx;
+        const int ra = r0 + 2 * l, rb = ra + 1;
+        if (rb >= nrows) continue;
+        const double2 z = lds[l * ls + k];
+        const double2 zc = lds[l * ls + (k == 0 ? 0 : n - k)];  // Z[-k]
+        // A = (Z + conj Z[-k]) / 2, B = (Z - conj Z[-k]) / (2 i)
+        const double2 A = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
+        const double2 Bv = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
+        out[(size_t)ra * nkx + k] = A;
+        out[(size_t)rb * nkx + k] = Bv;
+    }
+}
+
+__global__ void __launch_bounds__(FFT_THREADS)
+k_fft_x_inv(const double2 *__restrict__ in, const double *__restrict__ sinv, double *__restrict__ out,
+            Radices rd, const double2 *__restrict__ tw, int B, int nrows, int nkx) {
+    extern __shared__ double2 lds[];
+    const int n = rd.n, ls = n + 1;
+    const int r0 = blockIdx.x * 2 * B;
+    for (int e = threadIdx.x; e < B * n; e += FFT_THREADS) {
+        const int l = e / n, k = e % n;
+        const int ra = r0 + 2 * l, rb = ra + 1;
+        double2 z = make_double2(0.0, 0.0);
+        if (rb < nrows) {
+            const int kk = (k < nkx) ? k : n - k;
+            double2 A = in[(size_t)ra * nkx + kk], Bv = in[(size_t)rb * nkx + kk];
+            if (kk == 0 || 2 * kk == n) { A.y = 0.0; Bv.y = 0.0; }
+            if (k >= nkx) { A.y = -A.y; Bv.y = -Bv.y; }  // Hermitian extension
+            z = make_double2(A.x - Bv.y, A.y + Bv.x);     // A + i B
+        }
+        lds[l * ls + k] = z;
+    }
+    __syncthreads();
+    fft_lines(lds, rd, B, 1, ls, tw, true);
+    for (int e = threadIdx.x; e < B * n; e += FFT_THREADS) {
+        const int l = e / n, t = e % n;
+        const int ra = r0 + 2 * l, rb = ra + 1;
+        if (rb >= nrows) continue;
+        const double2 z = lds[l * ls + t];
+        const size_t ia = (size_t)ra * n + t, ib = (size_t)rb * n + t;
+        if (sinv) {
+            out[ia] = z.x * sinv[ia];
+            out[ib] = z.y * sinv[ib];
+        } else {
+            out[ia] = z.x;
+            out[ib] = z.y;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- y pass
+// Block (tile of B consecutive kx, plane z): lines along y, LDS element
+// (y, l) at y * B + l.
+__global__ void __launch_bounds__(FFT_THREADS)
+k_fft_y(double2 *__restrict__ c, Radices rd, const double2 *__restrict__ tw, int B, int nkx, int inv) {
+    extern __shared__ double2 lds[];
+    const int ny = rd.n;
+    const int kx0 = blockIdx.x * B;
+    const int z = blockIdx.y;
+    const int bw = min(B, nkx - kx0);
+    const size_t base = (size_t)z * ny * nkx + kx0;
+    for (int e = threadIdx.x; e < B * ny; e += FFT_THREADS) {
+        const int y = e / B, l = e % B;
+        lds[y * B + l] = (l < bw) ? c[base + (size_t)y * nkx + l] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    fft_lines(lds, rd, B, B, 1, tw, inv != 0);
+    for (int e = threadIdx.x; e < B * ny; e += FFT_THREADS) {
+        const int y = e / B, l = e % B;
+        if (l < bw) c[base + (size_t)y * nkx + l] = lds[y * B + l];
+    }
+}
+
+// ---------------------------------------------------------------- z pass + Green
+__global__ void __launch_bounds__(FFT_THREADS)
+k_fft_z_green(double2 *__restrict__ c, Radices rd, const double2 *__restrict__ tw, int B, int nkx, int ny,
+              const double *__restrict__ lamx, const double *__restrict__ lamy,
+              const double *__restrict__ lamz, double inv_n) {
+    extern __shared__ double2 lds[];
+    const int nz = rd.n;
+    const int kx0 = blockIdx.x * B;
+    const int y = blockIdx.y;
+    const int bw = min(B, nkx - kx0);
+    const size_t zstride = (size_t)ny * nkx;
+    const size_t base = (size_t)y * nkx + kx0;
+    for (int e = threadIdx.x; e < B * nz; e += FFT_THREADS) {
+        const int z = e / B, l = e % B;
+        lds[z * B + l] = (l < bw) ? c[base + (size_t)z * zstride + l] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    fft_lines(lds, rd, B, B, 1, tw, false);
+    const double ly = lamy[y];
+    for (int e = threadIdx.x; e < B * nz; e += FFT_THREADS) {
+        const int z = e / B, l = e % B;
+        const int kx = kx0 + l;
+        double g = 0.0;
+        if (l < bw) {
+            const double lam = lamx[kx] + ly + lamz[z];
+            g = (kx == 0 && y == 0 && z == 0) ? 0.0 : -inv_n / lam;
+        }
+        double2 v = lds[z * B + l];
+        lds[z * B + l] = make_double2(v.x * g, v.y * g);
+    }
+    __syncthreads();
+    fft_lines(lds, rd, B, B, 1, tw, true);
+    for (int e = threadIdx.x; e < B * nz; e += FFT_THREADS) {
+        const int z = e / B, l = e % B;
+        if (l < bw) c[base + (size_t)z * zstride + l] = lds[z * B + l];
+    }
+}
+
+Radices radices_of(const FFTAxis &ax) {
+    Radices r{};
+    r.n = ax.n;
+    r.nst = (int)ax.radices.size();
+    for (int s = 0; s < r.nst; ++s) r.r[s] = ax.radices[s];
+    return r;
+}
+
+int tile_lines(int n, int budget) {
+    int B = budget / n;
+    if (B > 16) B = 16;
+    if (B < 1) B = 1;
+    return B;
+}
+
+}  // namespace
+
+// Radix plan, twiddles and the discrete symbol 4 sin^2(pi m / n) / h^2 of one
+// axis (m < n / 2 + 1 when `half`).  Twiddles and symbol are evaluated in long
+// double on the host.
+void fft_plan_axis(FFTAxis &ax, int n, double h, bool half) {
+    ax.n = n;
+    ax.radices.clear();
+    int m = n;
+    while (m % 3 == 0) { ax.radices.push_back(3); m /= 3; }
+    while (m % 4 == 0) { ax.radices.push_back(4); m /= 4; }
+    while (m % 2 == 0) { ax.radices.push_back(2); m /= 2; }
+    if (m != 1 || (int)ax.radices.size() > MAX_STAGES) fail(DWP_EINVAL, "grid size must be 2^a 3^b");
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<double2> tw(n);
+    for (int t = 0; t < n; ++t) {
+        const long double a = -2.0L * pi * (long double)t / (long double)n;
+        tw[t] = make_double2((double)cosl(a), (double)sinl(a));
+    }
+    const int nl = half ? n / 2 + 1 : n;
+    std::vector<double> lam(nl);
+    for (int k = 0; k < nl; ++k) {
+        const long double s = sinl(pi * (long double)k / (long double)n);
+        lam[k] = (double)(4.0L * s * s / ((long double)h * (long double)h));
+    }
+    ax.tw.alloc(sizeof(double2) * n);
+    ax.lam.alloc(sizeof(double) * nl);
+    DWP_HIP(hipMemcpy(ax.tw.p, tw.data(), sizeof(double2) * n, hipMemcpyHostToDevice));
+    DWP_HIP(hipMemcpy(ax.lam.p, lam.data(), sizeof(double) * nl, hipMemcpyHostToDevice));
+}
+
+void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay,
+                         const FFTAxis &az, const double *r, const double *sinv, double2 *cbuf,
+                         double *out) {
+    const int nrows = p.ny * p.nz;
+    const int Bx = tile_lines(p.nx, 2048);
+    const int gx = (nrows + 2 * Bx - 1) / (2 * Bx);
+    const size_t ldsx = sizeof(double2) * Bx * (p.nx + 1);
+    k_fft_x_fwd<<<gx, FFT_THREADS, ldsx, st>>>(r, sinv, cbuf, radices_of(ax), ax.tw.as<double2>(), Bx, nrows, p.nkx);
+    DWP_LAUNCH_CHECK();
+    const int By = tile_lines(p.ny, 4096);
+    dim3 gy((p.nkx + By - 1) / By, p.nz);
+    k_fft_y<<<gy, FFT_THREADS, sizeof(double2) * By * p.ny, st>>>(cbuf, radices_of(ay), ay.tw.as<double2>(), By, p.nkx, 0);
+    DWP_LAUNCH_CHECK();
+    const int Bz = tile_lines(p.nz, 4096);
+    dim3 gz((p.nkx + Bz - 1) / Bz, p.ny);
+    k_fft_z_green<<<gz, FFT_THREADS, sizeof(double2) * Bz * p.nz, st>>>(
+        cbuf, radices_of(az), az.tw.as<double2>(), Bz, p.nkx, p.ny, ax.lam.as<double>(), ay.lam.as<double>(),
+        az.lam.as<double>(), 1.0 / (double)p.N);
+    DWP_LAUNCH_CHECK();
+    k_fft_y<<<gy, FFT_THREADS, sizeof(double2) * By * p.ny, st>>>(cbuf, radices_of(ay), ay.tw.as<double2>(), By, p.nkx, 1);
+    DWP_LAUNCH_CHECK();
+    k_fft_x_inv<<<gx, FFT_THREADS, ldsx, st>>>(cbuf, sinv, out, radices_of(ax), ax.tw.as<double2>(), Bx, nrows, p.nkx);
+    DWP_LAUNCH_CHECK();
+}
+
+}  // namespace dwp

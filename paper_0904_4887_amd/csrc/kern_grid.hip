@@ -1,0 +1,527 @@
+// Grid kernels: the 7-point conservative operator on the periodic box, the
+// permittivity adjoint, the wet-slab extraction and combination, and the
+// multigrid level kernels (red-black Gauss-Seidel, residual, full-weighting
+// restriction, trilinear prolongation, coefficient coarsening).
+//
+// Operator (paper Eq. 3 in conservative form, face eps = mean of its nodes):
+//   (A u)_n = sum over the 6 neighbours m of n of
+//             1/2 (eps_n + eps_m) (u_m - u_n) / h_d^2.
+#include "dwp_internal.h"
+
+namespace dwp {
+
+namespace {
+
+constexpr int BX = 64, BY = 4;
+
+__device__ __forceinline__ int wrap_p(int i, int n) { return (i + 1 == n) ? 0 : i + 1; }
+__device__ __forceinline__ int wrap_m(int i, int n) { return (i == 0) ? n - 1 : i - 1; }
+
+// ---------------------------------------------------------------- full box
+__global__ void __launch_bounds__(BX *BY)
+k_apply_full(const double *__restrict__ phi, const double *__restrict__ eps,
+             const double *__restrict__ b, double *__restrict__ out, int nx, int ny, int nz,
+             double cx, double cy, double cz, int residual) {
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= nx || j >= ny) return;
+    const size_t plane = (size_t)nx * ny;
+    const size_t row = (size_t)k * plane + (size_t)j * nx;
+    const size_t c = row + i;
+    const size_t xp = row + wrap_p(i, nx), xm = row + wrap_m(i, nx);
+    const size_t yp = (size_t)k * plane + (size_t)wrap_p(j, ny) * nx + i;
+    const size_t ym = (size_t)k * plane + (size_t)wrap_m(j, ny) * nx + i;
+    const size_t zp = (size_t)wrap_p(k, nz) * plane + (size_t)j * nx + i;
+    const size_t zm = (size_t)wrap_m(k, nz) * plane + (size_t)j * nx + i;
+    const double e0 = eps[c], p0 = phi[c];
+    double acc = cx * ((e0 + eps[xp]) * (phi[xp] - p0) + (e0 + eps[xm]) * (phi[xm] - p0)) +
+                 cy * ((e0 + eps[yp]) * (phi[yp] - p0) + (e0 + eps[ym]) * (phi[ym] - p0)) +
+                 cz * ((e0 + eps[zp]) * (phi[zp] - p0) + (e0 + eps[zm]) * (phi[zm] - p0));
+    acc *= 0.5;
+    out[c] = residual ? b[c] - acc : acc;
+}
+
+// dE/d eps_n = -(h^3 / 8 pi) sum_d 1/2 [(D+ phi)^2 + (D- phi)^2]
+__global__ void __launch_bounds__(BX *BY)
+k_eps_gradient(const double *__restrict__ phi, double *__restrict__ g, int nx, int ny, int nz,
+               double ihx, double ihy, double ihz, double scale) {
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= nx || j >= ny) return;
+    const size_t plane = (size_t)nx * ny;
+    const size_t row = (size_t)k * plane + (size_t)j * nx;
+    const size_t c = row + i;
+    const double p0 = phi[c];
+    double dxp = (phi[row + wrap_p(i, nx)] - p0) * ihx, dxm = (p0 - phi[row + wrap_m(i, nx)]) * ihx;
+    double dyp = (phi[(size_t)k * plane + (size_t)wrap_p(j, ny) * nx + i] - p0) * ihy;
+    double dym = (p0 - phi[(size_t)k * plane + (size_t)wrap_m(j, ny) * nx + i]) * ihy;
+    double dzp = (phi[(size_t)wrap_p(k, nz) * plane + (size_t)j * nx + i] - p0) * ihz;
+    double dzm = (p0 - phi[(size_t)wrap_m(k, nz) * plane + (size_t)j * nx + i]) * ihz;
+    g[c] = scale * 0.5 * (dxp * dxp + dxm * dxm + dyp * dyp + dym * dym + dzp * dzp + dzm * dzm);
+}
+
+// ---------------------------------------------------------------- vectors
+__global__ void k_fill(double *x, double v, size_t n) {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        x[t] = v;
+}
+template <class T>
+__global__ void k_zero(T *x, size_t n) {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        x[t] = T(0);
+}
+__global__ void k_axpby(double *y, double a, const double *x, double b, size_t n) {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        y[t] = a * x[t] + b * y[t];
+}
+// mode 0: x *= 1/sqrt(*den_sq) ; mode 1: x *= *num
+__global__ void k_scale_dev(double *x, const double *num, const double *den_sq, size_t n, int mode) {
+    const double s = mode == 0 ? 1.0 / sqrt(*den_sq) : *num;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        x[t] *= s;
+}
+// b = -4 pi (rho - mean), mean = (*sum) * inv_n
+__global__ void k_rhs(const double *rho, const double *sum, double inv_n, double *b, size_t n) {
+    const double m = *sum * inv_n;
+    const double fpi = -4.0 * 3.14159265358979323846;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        b[t] = fpi * (rho[t] - m);
+}
+__global__ void k_sub_mean(double *x, const double *sum, double inv_n, size_t n) {
+    const double m = *sum * inv_n;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        x[t] -= m;
+}
+__global__ void k_mul(double *y, const double *a, const double *x, size_t n) {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        y[t] = a[t] * x[t];
+}
+__global__ void k_rsqrt(const double *eps, double *s, size_t n) {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        s[t] = 1.0 / sqrt(eps[t]);
+}
+// flags[blockIdx.x]: bit 0 non-finite, bit 1 below one (each block writes its own word)
+__global__ void k_check(const double *x, size_t n, int *flags, int check_ge1) {
+    __shared__ int sflag[256];
+    int f = 0;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        const double v = x[t];
+        if (!isfinite(v)) f |= 1;
+        else if (check_ge1 && v < 1.0) f |= 2;
+    }
+    sflag[threadIdx.x] = f;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sflag[threadIdx.x] |= sflag[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) flags[blockIdx.x] = sflag[0];
+}
+
+// ---------------------------------------------------------------- wet slab <-> box
+// fW[kk] = (v - A dD) at box plane (k_w0 + kk) mod nz
+template <class T>
+__global__ void __launch_bounds__(BX *BY)
+k_wet_residual(const double *__restrict__ v, const double *__restrict__ dD,
+               const double *__restrict__ eps, T *__restrict__ fW, int nx, int ny, int nz,
+               int k_w0, double cx, double cy, double cz) {
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int kk = blockIdx.z;
+    if (i >= nx || j >= ny) return;
+    const int k = (k_w0 + kk) % nz;
+    const size_t plane = (size_t)nx * ny;
+    const size_t row = (size_t)k * plane + (size_t)j * nx;
+    const size_t c = row + i;
+    const size_t xp = row + wrap_p(i, nx), xm = row + wrap_m(i, nx);
+    const size_t yp = (size_t)k * plane + (size_t)wrap_p(j, ny) * nx + i;
+    const size_t ym = (size_t)k * plane + (size_t)wrap_m(j, ny) * nx + i;
+    const size_t zp = (size_t)wrap_p(k, nz) * plane + (size_t)j * nx + i;
+    const size_t zm = (size_t)wrap_m(k, nz) * plane + (size_t)j * nx + i;
+    const double e0 = eps[c], p0 = dD[c];
+    double acc = cx * ((e0 + eps[xp]) * (dD[xp] - p0) + (e0 + eps[xm]) * (dD[xm] - p0)) +
+                 cy * ((e0 + eps[yp]) * (dD[yp] - p0) + (e0 + eps[ym]) * (dD[ym] - p0)) +
+                 cz * ((e0 + eps[zp]) * (dD[zp] - p0) + (e0 + eps[zm]) * (dD[zm] - p0));
+    fW[(size_t)kk * plane + (size_t)j * nx + i] = (T)(v[c] - 0.5 * acc);
+}
+
+// z at box plane (k_w0 + kk) mod nz += uW (ghosted plane kk + 1)
+template <class T>
+__global__ void k_wet_add(const T *__restrict__ uW, double *__restrict__ z, int nx, int ny, int nz,
+                          int k_w0, int nw) {
+    const size_t plane = (size_t)nx * ny;
+    const size_t total = plane * nw;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        const int kk = (int)(t / plane);
+        const size_t rem = t - (size_t)kk * plane;
+        const int k = (k_w0 + kk) % nz;
+        z[(size_t)k * plane + rem] += (double)uW[(size_t)(kk + 1) * plane + rem];
+    }
+}
+
+// epsW ghosted plane p <- eps at box plane (k_w0 - 1 + p) mod nz, p in [0, nw + 2)
+template <class T>
+__global__ void k_wet_eps(const double *__restrict__ eps, T *__restrict__ epsW, int nx, int ny, int nz,
+                          int k_w0, int nw) {
+    const size_t plane = (size_t)nx * ny;
+    const size_t total = plane * (nw + 2);
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        const int p = (int)(t / plane);
+        const size_t rem = t - (size_t)p * plane;
+        const int k = ((k_w0 - 1 + p) % nz + nz) % nz;
+        epsW[t] = (T)eps[(size_t)k * plane + rem];
+    }
+}
+
+// ---------------------------------------------------------------- levels
+struct LevelArgs {
+    int nx, ny, nw;
+    float cxf, cyf, czf;
+    double cx, cy, cz;
+};
+
+template <class T> __device__ __forceinline__ T cxv(const LevelArgs &a, int d);
+template <> __device__ __forceinline__ float cxv<float>(const LevelArgs &a, int d) {
+    return d == 0 ? a.cxf : (d == 1 ? a.cyf : a.czf);
+}
+template <> __device__ __forceinline__ double cxv<double>(const LevelArgs &a, int d) {
+    return d == 0 ? a.cx : (d == 1 ? a.cy : a.cz);
+}
+
+// Neighbour sums at ghosted index g of slab point (i, j): returns the
+// off-diagonal sum  sum_m w_m u_m  and the diagonal  sum_m w_m,
+// w_m = 1/2 (eps_n + eps_m) / h_d^2.
+template <class T>
+__device__ __forceinline__ void level_sums(const T *__restrict__ u, const T *__restrict__ e,
+                                           const LevelArgs &a, int i, int j, size_t g, T &off,
+                                           T &diag) {
+    const size_t plane = (size_t)a.nx * a.ny;
+    const size_t rowbase = g - (size_t)i;
+    const size_t xp = rowbase + wrap_p(i, a.nx), xm = rowbase + wrap_m(i, a.nx);
+    const size_t pbase = g - (size_t)j * a.nx;  // start of (plane, row 0) + i
+    const size_t yp = pbase + (size_t)wrap_p(j, a.ny) * a.nx;
+    const size_t ym = pbase + (size_t)wrap_m(j, a.ny) * a.nx;
+    const size_t zp = g + plane, zm = g - plane;
+    const T e0 = e[g];
+    const T cx = cxv<T>(a, 0), cy = cxv<T>(a, 1), cz = cxv<T>(a, 2);
+    const T wxp = cx * (e0 + e[xp]), wxm = cx * (e0 + e[xm]);
+    const T wyp = cy * (e0 + e[yp]), wym = cy * (e0 + e[ym]);
+    const T wzp = cz * (e0 + e[zp]), wzm = cz * (e0 + e[zm]);
+    off = T(0.5) * (wxp * u[xp] + wxm * u[xm] + wyp * u[yp] + wym * u[ym] + wzp * u[zp] + wzm * u[zm]);
+    diag = T(0.5) * (wxp + wxm + wyp + wym + wzp + wzm);
+}
+
+// r = f - A u at every slab point (r, f not ghosted)
+template <class T>
+__global__ void __launch_bounds__(BX *BY)
+k_level_residual(const T *__restrict__ u, const T *__restrict__ e, const T *__restrict__ f,
+                 T *__restrict__ r, LevelArgs a) {
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int kk = blockIdx.z;
+    if (i >= a.nx || j >= a.ny) return;
+    const size_t plane = (size_t)a.nx * a.ny;
+    const size_t li = (size_t)kk * plane + (size_t)j * a.nx + i;
+    const size_t g = li + plane;
+    T off, diag;
+    level_sums(u, e, a, i, j, g, off, diag);
+    r[li] = f[li] - (off - diag * u[g]);
+}
+
+// One colour of red-black Gauss-Seidel: points with (i + j + kk) % 2 == color
+// take u = (off - f) / diag.  nx is even, so the colouring is consistent
+// across the periodic wrap and no two points of one colour are neighbours.
+template <class T>
+__global__ void __launch_bounds__(BX *BY)
+k_level_smooth(T *__restrict__ u, const T *__restrict__ e, const T *__restrict__ f, LevelArgs a,
+               int color) {
+    const int t = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int kk = blockIdx.z;
+    const int i = 2 * t + ((j + kk + color) & 1);
+    if (i >= a.nx || j >= a.ny) return;
+    const size_t plane = (size_t)a.nx * a.ny;
+    const size_t li = (size_t)kk * plane + (size_t)j * a.nx + i;
+    const size_t g = li + plane;
+    T off, diag;
+    level_sums(u, e, a, i, j, g, off, diag);
+    u[g] = (off - f[li]) / diag;
+}
+
+// Coarsest level: `sweeps` red-black sweeps by one workgroup.
+template <class T>
+__global__ void __launch_bounds__(1024)
+k_level_coarse(T *__restrict__ u, const T *__restrict__ e, const T *__restrict__ f, LevelArgs a,
+               int sweeps) {
+    const int half = a.nx / 2;
+    const int per_color = half * a.ny * a.nw;
+    const size_t plane = (size_t)a.nx * a.ny;
+    for (int s = 0; s < sweeps; ++s) {
+        for (int color = 0; color < 2; ++color) {
+            for (int q = threadIdx.x; q < per_color; q += blockDim.x) {
+                const int t = q % half;
+                const int j = (q / half) % a.ny;
+                const int kk = q / (half * a.ny);
+                const int i = 2 * t + ((j + kk + color) & 1);
+                const size_t li = (size_t)kk * plane + (size_t)j * a.nx + i;
+                const size_t g = li + plane;
+                T off, diag;
+                level_sums(u, e, a, i, j, g, off, diag);
+                u[g] = (off - f[li]) / diag;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Full weighting: 1/4, 1/2, 1/4 along every coarsened direction (periodic in
+// x, y; in z the three fine planes 2kc, 2kc+1, 2kc+2 all lie inside the slab).
+template <class T>
+__global__ void k_restrict(const T *__restrict__ rf, T *__restrict__ fc, int nxf, int nyf,
+                           int nxc, int nyc, int nwc, int zc) {
+    const size_t planec = (size_t)nxc * nyc, planef = (size_t)nxf * nyf;
+    const size_t total = planec * nwc;
+    const T w3[3] = {T(0.25), T(0.5), T(0.25)};
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < total; q += (size_t)gridDim.x * blockDim.x) {
+        const int ic = (int)(q % nxc);
+        const int jc = (int)((q / nxc) % nyc);
+        const int kc = (int)(q / planec);
+        T acc = T(0);
+        const int nzt = zc ? 3 : 1;
+        for (int dz = 0; dz < nzt; ++dz) {
+            const int kf = zc ? 2 * kc + dz : kc;
+            const T wz = zc ? w3[dz] : T(1);
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int jf = (2 * jc + dy + nyf) % nyf;
+                const T wy = w3[dy + 1];
+                const size_t rb = (size_t)kf * planef + (size_t)jf * nxf;
+                const int i0 = 2 * ic;
+                const T sx = T(0.25) * rf[rb + (i0 == 0 ? nxf - 1 : i0 - 1)] + T(0.5) * rf[rb + i0] +
+                             T(0.25) * rf[rb + (i0 + 1 == nxf ? 0 : i0 + 1)];
+                acc += wz * wy * sx;
+            }
+        }
+        fc[q] = acc;
+    }
+}
+
+// Trilinear interpolation of the coarse correction, added to the fine unknowns.
+template <class T>
+__global__ void k_prolong_add(T *__restrict__ uf, const T *__restrict__ uc, int nxf, int nyf,
+                              int nwf, int nxc, int nyc, int zc) {
+    const size_t planef = (size_t)nxf * nyf, planec = (size_t)nxc * nyc;
+    const size_t total = planef * nwf;
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < total; q += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(q % nxf);
+        const int j = (int)((q / nxf) % nyf);
+        const int kf = (int)(q / planef);
+        int ix[2], jy[2], pz[2];
+        T wx[2], wyv[2], wz[2];
+        int nxs, nys, nzs;
+        if (i & 1) { ix[0] = i >> 1; ix[1] = (ix[0] + 1 == nxc) ? 0 : ix[0] + 1; wx[0] = wx[1] = T(0.5); nxs = 2; }
+        else { ix[0] = i >> 1; wx[0] = T(1); nxs = 1; }
+        if (j & 1) { jy[0] = j >> 1; jy[1] = (jy[0] + 1 == nyc) ? 0 : jy[0] + 1; wyv[0] = wyv[1] = T(0.5); nys = 2; }
+        else { jy[0] = j >> 1; wyv[0] = T(1); nys = 1; }
+        if (zc) {
+            if (kf & 1) { pz[0] = (kf - 1) / 2 + 1; wz[0] = T(1); nzs = 1; }
+            else { pz[0] = kf / 2; pz[1] = kf / 2 + 1; wz[0] = wz[1] = T(0.5); nzs = 2; }
+        } else { pz[0] = kf + 1; wz[0] = T(1); nzs = 1; }
+        T acc = T(0);
+        for (int a = 0; a < nzs; ++a)
+            for (int b = 0; b < nys; ++b)
+                for (int c = 0; c < nxs; ++c)
+                    acc += wz[a] * wyv[b] * wx[c] * uc[(size_t)pz[a] * planec + (size_t)jy[b] * nxc + ix[c]];
+        uf[q + planef] += acc;
+    }
+}
+
+// Coarse node eps by full weighting of the fine node eps (ghost planes map to
+// ghost planes).
+template <class T>
+__global__ void k_coarsen_eps(const T *__restrict__ ef, T *__restrict__ ec, int nxf, int nyf,
+                              int nxc, int nyc, int nwc, int zc) {
+    const size_t planec = (size_t)nxc * nyc, planef = (size_t)nxf * nyf;
+    const size_t total = planec * (nwc + 2);
+    const T w3[3] = {T(0.25), T(0.5), T(0.25)};
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < total; q += (size_t)gridDim.x * blockDim.x) {
+        const int ic = (int)(q % nxc);
+        const int jc = (int)((q / nxc) % nyc);
+        const int pc = (int)(q / planec);
+        int pf[3];
+        T wz[3];
+        int nzt;
+        if (!zc) { pf[0] = pc; wz[0] = T(1); nzt = 1; }
+        else if (pc == 0) { pf[0] = 0; wz[0] = T(1); nzt = 1; }
+        else if (pc == nwc + 1) { pf[0] = 2 * nwc + 2; wz[0] = T(1); nzt = 1; }
+        else { pf[0] = 2 * pc - 1; pf[1] = 2 * pc; pf[2] = 2 * pc + 1; wz[0] = w3[0]; wz[1] = w3[1]; wz[2] = w3[2]; nzt = 3; }
+        T acc = T(0);
+        for (int a = 0; a < nzt; ++a)
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int jf = (2 * jc + dy + nyf) % nyf;
+                const size_t rb = (size_t)pf[a] * planef + (size_t)jf * nxf;
+                const int i0 = 2 * ic;
+                const T sx = T(0.25) * ef[rb + (i0 == 0 ? nxf - 1 : i0 - 1)] + T(0.5) * ef[rb + i0] +
+                             T(0.25) * ef[rb + (i0 + 1 == nxf ? 0 : i0 + 1)];
+                acc += wz[a] * w3[dy + 1] * sx;
+            }
+        ec[q] = acc;
+    }
+}
+
+inline int grid1d(size_t n, int threads = 256) {
+    size_t b = (n + threads - 1) / threads;
+    if (b > 16384) b = 16384;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+LevelArgs level_args(const Level &L) {
+    LevelArgs a;
+    a.nx = L.nx; a.ny = L.ny; a.nw = L.nw;
+    a.cx = 1.0 / (L.h[0] * L.h[0]);
+    a.cy = 1.0 / (L.h[1] * L.h[1]);
+    a.cz = 1.0 / (L.h[2] * L.h[2]);
+    a.cxf = (float)a.cx; a.cyf = (float)a.cy; a.czf = (float)a.cz;
+    return a;
+}
+
+}  // namespace
+
+// ============================================================== launchers
+void launch_apply_full(hipStream_t s, const Plan &p, const double *phi, const double *eps,
+                       const double *b, double *out, bool residual) {
+    dim3 g((p.nx + BX - 1) / BX, (p.ny + BY - 1) / BY, p.nz), blk(BX, BY);
+    k_apply_full<<<g, blk, 0, s>>>(phi, eps, b, out, p.nx, p.ny, p.nz, 1.0 / (p.h[0] * p.h[0]),
+                                   1.0 / (p.h[1] * p.h[1]), 1.0 / (p.h[2] * p.h[2]), residual ? 1 : 0);
+    DWP_LAUNCH_CHECK();
+}
+
+void launch_eps_gradient(hipStream_t s, const Plan &p, const double *phi, double *g) {
+    const double h3 = p.h[0] * p.h[1] * p.h[2];
+    const double scale = -h3 / (8.0 * 3.14159265358979323846);
+    dim3 gr((p.nx + BX - 1) / BX, (p.ny + BY - 1) / BY, p.nz), blk(BX, BY);
+    k_eps_gradient<<<gr, blk, 0, s>>>(phi, g, p.nx, p.ny, p.nz, 1.0 / p.h[0], 1.0 / p.h[1], 1.0 / p.h[2], scale);
+    DWP_LAUNCH_CHECK();
+}
+
+void launch_fill(hipStream_t s, double *x, double v, size_t n) {
+    k_fill<<<grid1d(n), 256, 0, s>>>(x, v, n);
+    DWP_LAUNCH_CHECK();
+}
+void launch_axpby(hipStream_t s, double *y, double a, const double *x, double b, size_t n) {
+    k_axpby<<<grid1d(n), 256, 0, s>>>(y, a, x, b, n);
+    DWP_LAUNCH_CHECK();
+}
+void launch_scale_dev(hipStream_t s, double *x, const double *num, const double *den_sq, size_t n, int mode) {
+    k_scale_dev<<<grid1d(n), 256, 0, s>>>(x, num, den_sq, n, mode);
+    DWP_LAUNCH_CHECK();
+}
+void launch_rhs(hipStream_t s, const double *rho, const double *sum, double inv_n, double *b, size_t n) {
+    k_rhs<<<grid1d(n), 256, 0, s>>>(rho, sum, inv_n, b, n);
+    DWP_LAUNCH_CHECK();
+}
+void launch_sub_mean(hipStream_t s, double *x, const double *sum, double inv_n, size_t n) {
+    k_sub_mean<<<grid1d(n), 256, 0, s>>>(x, sum, inv_n, n);
+    DWP_LAUNCH_CHECK();
+}
+void launch_mul(hipStream_t s, double *y, const double *a, const double *x, size_t n) {
+    k_mul<<<grid1d(n), 256, 0, s>>>(y, a, x, n);
+    DWP_LAUNCH_CHECK();
+}
+void launch_rsqrt(hipStream_t s, const double *eps, double *sinv, size_t n) {
+    k_rsqrt<<<grid1d(n), 256, 0, s>>>(eps, sinv, n);
+    DWP_LAUNCH_CHECK();
+}
+void launch_check_eps(hipStream_t s, const double *eps, size_t n, int *flags) {
+    k_check<<<RED_BLOCKS, 256, 0, s>>>(eps, n, flags, 1);
+    DWP_LAUNCH_CHECK();
+}
+void launch_check_finite(hipStream_t s, const double *x, size_t n, int *flags) {
+    k_check<<<RED_BLOCKS, 256, 0, s>>>(x, n, flags, 0);
+    DWP_LAUNCH_CHECK();
+}
+
+template <class T>
+void launch_wet_residual(hipStream_t s, const Plan &p, const double *v, const double *dD,
+                         const double *eps, T *fW) {
+    dim3 g((p.nx + BX - 1) / BX, (p.ny + BY - 1) / BY, p.nw), blk(BX, BY);
+    k_wet_residual<T><<<g, blk, 0, s>>>(v, dD, eps, fW, p.nx, p.ny, p.nz, p.k_w0, 1.0 / (p.h[0] * p.h[0]),
+                                        1.0 / (p.h[1] * p.h[1]), 1.0 / (p.h[2] * p.h[2]));
+    DWP_LAUNCH_CHECK();
+}
+template <class T>
+void launch_wet_add(hipStream_t s, const Plan &p, const T *uW, double *z) {
+    const size_t n = (size_t)p.nx * p.ny * p.nw;
+    k_wet_add<T><<<grid1d(n), 256, 0, s>>>(uW, z, p.nx, p.ny, p.nz, p.k_w0, p.nw);
+    DWP_LAUNCH_CHECK();
+}
+template <class T>
+void launch_wet_eps(hipStream_t s, const Plan &p, const double *eps, T *epsW) {
+    const size_t n = (size_t)p.nx * p.ny * (p.nw + 2);
+    k_wet_eps<T><<<grid1d(n), 256, 0, s>>>(eps, epsW, p.nx, p.ny, p.nz, p.k_w0, p.nw);
+    DWP_LAUNCH_CHECK();
+}
+
+template <class T>
+void launch_level_residual(hipStream_t s, const Level &L, T *r) {
+    LevelArgs a = level_args(L);
+    dim3 g((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, L.nw), blk(BX, BY);
+    k_level_residual<T><<<g, blk, 0, s>>>(L.u.as<T>(), L.eps.as<T>(), L.f.as<T>(), r, a);
+    DWP_LAUNCH_CHECK();
+}
+template <class T>
+void launch_level_smooth(hipStream_t s, const Level &L, int color) {
+    LevelArgs a = level_args(L);
+    const int half = L.nx / 2;
+    dim3 g((half + BX - 1) / BX, (L.ny + BY - 1) / BY, L.nw), blk(BX, BY);
+    k_level_smooth<T><<<g, blk, 0, s>>>(L.u.as<T>(), L.eps.as<T>(), L.f.as<T>(), a, color);
+    DWP_LAUNCH_CHECK();
+}
+template <class T>
+void launch_level_coarse_solve(hipStream_t s, const Level &L, int sweeps) {
+    LevelArgs a = level_args(L);
+    k_level_coarse<T><<<1, 1024, 0, s>>>(L.u.as<T>(), L.eps.as<T>(), L.f.as<T>(), a, sweeps);
+    DWP_LAUNCH_CHECK();
+}
+template <class T>
+void launch_restrict(hipStream_t s, const Level &F, const Level &C, const T *rf, T *fc) {
+    const size_t n = C.n_interior();
+    k_restrict<T><<<grid1d(n), 256, 0, s>>>(rf, fc, F.nx, F.ny, C.nx, C.ny, C.nw, C.zc ? 1 : 0);
+    DWP_LAUNCH_CHECK();
+}
+template <class T>
+void launch_prolong_add(hipStream_t s, const Level &F, const Level &C) {
+    const size_t n = F.n_interior();
+    k_prolong_add<T><<<grid1d(n), 256, 0, s>>>(F.u.as<T>(), C.u.as<T>(), F.nx, F.ny, F.nw, C.nx, C.ny, C.zc ? 1 : 0);
+    DWP_LAUNCH_CHECK();
+}
+template <class T>
+void launch_coarsen_eps(hipStream_t s, const Level &F, const Level &C) {
+    const size_t n = C.n_ghosted();
+    k_coarsen_eps<T><<<grid1d(n), 256, 0, s>>>(F.eps.as<T>(), C.eps.as<T>(), F.nx, F.ny, C.nx, C.ny, C.nw, C.zc ? 1 : 0);
+    DWP_LAUNCH_CHECK();
+}
+template <class T>
+void launch_zero(hipStream_t s, T *x, size_t n) {
+    k_zero<T><<<grid1d(n), 256, 0, s>>>(x, n);
+    DWP_LAUNCH_CHECK();
+}
+
+#define DWP_INST(T)                                                                                  \
+    template void launch_wet_residual<T>(hipStream_t, const Plan &, const double *, const double *,  \
+                                         const double *, T *);                                      \
+    template void launch_wet_add<T>(hipStream_t, const Plan &, const T *, double *);                  \
+    template void launch_wet_eps<T>(hipStream_t, const Plan &, const double *, T *);                  \
+    template void launch_level_residual<T>(hipStream_t, const Level &, T *);                          \
+    template void launch_level_smooth<T>(hipStream_t, const Level &, int);                            \
+    template void launch_level_coarse_solve<T>(hipStream_t, const Level &, int);                      \
+    template void launch_restrict<T>(hipStream_t, const Level &, const Level &, const T *, T *);      \
+    template void launch_prolong_add<T>(hipStream_t, const Level &, const Level &);                   \
+    template void launch_coarsen_eps<T>(hipStream_t, const Level &, const Level &);                   \
+    template void launch_zero<T>(hipStream_t, T *, size_t);
+DWP_INST(float)
+DWP_INST(double)
+
+}  // namespace dwp

@@ -1,0 +1,833 @@
+// Host orchestration of the dry/wet solver and the C ABI.
+//
+// The solve (paper Sec. II.F, made self-consistent): flexible GMRES(m) on the
+// full periodic box for A phi = -4 pi (rho - mean rho), right-preconditioned by
+// one application of the dry/wet split:
+//   1. dry update   dD = L^{-1} v        (3-D FFT vacuum solve, Eq. 15 on the
+//                                          grid; optionally s L^{-1} s v with
+//                                          s = eps^-1/2)
+//   2. wet residual rW = (v - A dD) on W  (float64)
+//   3. wet solve    dW ~ A_WW^{-1} rW     (V-cycles on W, zero Dirichlet data
+//                                          on the dry planes next to W)
+//   4. combine      z = dD + extend(dW)
+// The dry update gives the wet solve its boundary data, as in the paper's
+// two-step scheme; the Krylov iteration makes the combination converge to the
+// exact full-box solution.
+#include "dwp_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+namespace dwp {
+
+void fail(int status, const std::string &msg) { throw Error{status, msg}; }
+
+void DevBuf::alloc(size_t n_bytes) {
+    if (p && bytes >= n_bytes) return;
+    release();
+    if (n_bytes == 0) return;
+    if (hipMalloc(&p, n_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+        fail(DWP_ENOMEM, "device allocation of " + std::to_string(n_bytes) + " bytes failed");
+    }
+    bytes = n_bytes;
+}
+
+void DevBuf::release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+namespace {
+
+constexpr int COARSE_TARGET = 1024;  // coarsest level: at most this many points
+
+struct LevelDims {
+    int nx, ny, nw;
+    double h[3];
+    bool zc;
+};
+
+// Coarsening rule: x, y periodic, halved only while the child stays even (so
+// red-black colouring survives the wrap); z (Dirichlet) halved when the
+// interval count nw + 1 is even.  While hz > sqrt(2) max(hx, hy) only x, y are
+// coarsened (semi-coarsening for the anisotropic spacing).
+std::vector<LevelDims> plan_levels(int nx, int ny, int nw, const double h[3], int max_levels) {
+    std::vector<LevelDims> v;
+    LevelDims L{nx, ny, nw, {h[0], h[1], h[2]}, false};
+    v.push_back(L);
+    while ((int)v.size() < max_levels && (long)L.nx * L.ny * L.nw > COARSE_TARGET) {
+        const double hxy = std::max(L.h[0], L.h[1]);
+        const bool semi = L.h[2] > std::sqrt(2.0) * hxy;
+        const bool can_xy = L.nx % 4 == 0 && L.ny % 4 == 0;
+        const bool can_z = (L.nw + 1) % 2 == 0 && (L.nw + 1) / 2 - 1 >= 1;
+        if (!can_xy) break;
+        LevelDims C = L;
+        C.nx = L.nx / 2;
+        C.ny = L.ny / 2;
+        C.h[0] = 2 * L.h[0];
+        C.h[1] = 2 * L.h[1];
+        if (semi) {
+            C.zc = false;
+        } else {
+            if (!can_z) break;
+            C.nw = (L.nw + 1) / 2 - 1;
+            C.h[2] = 2 * L.h[2];
+            C.zc = true;
+        }
+        v.push_back(C);
+        L = C;
+    }
+    return v;
+}
+
+long coarsest_size(const std::vector<LevelDims> &v) {
+    const LevelDims &c = v.back();
+    return (long)c.nx * c.ny * c.nw;
+}
+
+bool good_size(int n) {
+    if (n < 8 || n > 4096 || n % 2) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+template <class T> size_t tsize() { return sizeof(T); }
+
+void free_levels(dwp_ctx *c) {
+    for (Level *L : c->plan.levels) delete L;
+    c->plan.levels.clear();
+    c->precision_built = -1;
+}
+
+// Choose the wet planes [k_w0, k_w1) (k_w0 in [0, nz)) for the options: the
+// requested first plane may move down by up to nz / 8 planes until the slab
+// coarsens to a level of at most COARSE_TARGET points.
+void choose_wet(int nx, int ny, int nz, const double h[3], const double L[3], const dwp_opts &o, int *kw0,
+                int *kw1, int *nw_out) {
+    double zlo = o.z_wet_lo, zhi = o.z_wet_hi;
+    if (std::isnan(zlo)) zlo = 0.35 * L[2];
+    if (std::isnan(zhi)) zhi = L[2];
+    if (!std::isfinite(zlo) || !std::isfinite(zhi)) fail(DWP_EINVAL, "wet bounds must be finite");
+    const int k0 = (int)std::ceil(zlo / h[2] - 1e-9);
+    const int k1 = (int)std::ceil(zhi / h[2] - 1e-9);
+    const int nw0 = k1 - k0;
+    if (nw0 < 3) fail(DWP_EINVAL, "wet region must hold at least 3 planes");
+    if (nw0 > nz - 1) fail(DWP_EINVAL, "wet region must leave at least one dry plane");
+    int best_nw = nw0;
+    long best = coarsest_size(plan_levels(nx, ny, nw0, h, o.max_levels));
+    const int limit = std::min(nz - 1, nw0 + std::max(1, nz / 8));
+    for (int nw = nw0; nw <= limit; ++nw) {
+        const long cs = coarsest_size(plan_levels(nx, ny, nw, h, o.max_levels));
+        if (cs < best) { best = cs; best_nw = nw; }
+        if (cs <= COARSE_TARGET) { best_nw = nw; break; }
+    }
+    int a = k1 - best_nw, b = k1;
+    const int shift = ((a % nz) + nz) % nz - a;
+    *kw0 = a + shift;
+    *kw1 = b + shift;
+    *nw_out = best_nw;
+}
+
+// Plan the wet slab and its hierarchy for the current options.
+void plan_wet(dwp_ctx *c) {
+    Plan &p = c->plan;
+    choose_wet(p.nx, p.ny, p.nz, p.h, p.L, c->opts, &p.k_w0, &p.k_w1, &p.nw);
+    free_levels(c);
+    for (const LevelDims &d : plan_levels(p.nx, p.ny, p.nw, p.h, c->opts.max_levels)) {
+        Level *L = new Level();
+        L->nx = d.nx; L->ny = d.ny; L->nw = d.nw;
+        L->h[0] = d.h[0]; L->h[1] = d.h[1]; L->h[2] = d.h[2];
+        L->zc = d.zc;
+        L->plane = (size_t)d.nx * d.ny;
+        p.levels.push_back(L);
+    }
+}
+
+template <class T>
+void alloc_levels(dwp_ctx *c) {
+    for (Level *L : c->plan.levels) {
+        L->eps.release(); L->u.release(); L->f.release(); L->r.release();
+        L->eps.alloc(tsize<T>() * L->n_ghosted());
+        L->u.alloc(tsize<T>() * L->n_ghosted());
+        L->f.alloc(tsize<T>() * L->n_interior());
+        L->r.alloc(tsize<T>() * L->n_interior());
+        launch_zero<T>(c->stream, L->u.as<T>(), L->n_ghosted());
+    }
+}
+
+void ensure_levels(dwp_ctx *c) {
+    if (c->precision_built == c->opts.precision) return;
+    if (c->opts.precision == DWP_MIXED) alloc_levels<float>(c);
+    else alloc_levels<double>(c);
+    c->precision_built = c->opts.precision;
+}
+
+// Level permittivities from the full-box eps.
+template <class T>
+void prepare_level_eps(dwp_ctx *c) {
+    Plan &p = c->plan;
+    launch_wet_eps<T>(c->stream, p, c->eps.as<double>(), p.levels[0]->eps.as<T>());
+    for (size_t l = 1; l < p.levels.size(); ++l)
+        launch_coarsen_eps<T>(c->stream, *p.levels[l - 1], *p.levels[l]);
+}
+
+void prepare_eps(dwp_ctx *c) {
+    ensure_levels(c);
+    launch_rsqrt(c->stream, c->eps.as<double>(), c->sinv.as<double>(), c->plan.N);
+    if (c->opts.precision == DWP_MIXED) prepare_level_eps<float>(c);
+    else prepare_level_eps<double>(c);
+}
+
+void sync(dwp_ctx *c) { DWP_HIP(hipStreamSynchronize(c->stream)); }
+
+void to_host(dwp_ctx *c, const double *dev, size_t n) {
+    if (n > c->host_len) fail(DWP_EINVAL, "internal: host staging too small");
+    DWP_HIP(hipMemcpyAsync(c->host, dev, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+}
+
+template <class T>
+void vcycle(dwp_ctx *c, size_t l) {
+    Plan &p = c->plan;
+    Level &L = *p.levels[l];
+    hipStream_t s = c->stream;
+    if (l + 1 == p.levels.size()) {
+        launch_level_coarse_solve<T>(s, L, c->opts.coarse_sweeps);
+        return;
+    }
+    for (int k = 0; k < c->opts.pre; ++k) {
+        launch_level_smooth<T>(s, L, 0);
+        launch_level_smooth<T>(s, L, 1);
+    }
+    Level &C = *p.levels[l + 1];
+    launch_level_residual<T>(s, L, L.r.as<T>());
+    launch_restrict<T>(s, L, C, L.r.as<T>(), C.f.as<T>());
+    launch_zero<T>(s, C.u.as<T>(), C.n_ghosted());
+    vcycle<T>(c, l + 1);
+    launch_prolong_add<T>(s, L, C);
+    for (int k = 0; k < c->opts.post; ++k) {
+        launch_level_smooth<T>(s, L, 1);
+        launch_level_smooth<T>(s, L, 0);
+    }
+}
+
+template <class T>
+void split_impl(dwp_ctx *c, const double *v, double *z) {
+    Plan &p = c->plan;
+    hipStream_t s = c->stream;
+    launch_vacuum_solve(s, p, c->fx, c->fy, c->fz, v, c->opts.scaled_dry ? c->sinv.as<double>() : nullptr,
+                        c->cbuf.as<double2>(), z);
+    Level &F = *p.levels[0];
+    launch_wet_residual<T>(s, p, v, z, c->eps.as<double>(), F.f.as<T>());
+    launch_zero<T>(s, F.u.as<T>(), F.n_ghosted());
+    for (int k = 0; k < c->opts.cycles; ++k) vcycle<T>(c, 0);
+    launch_wet_add<T>(s, p, F.u.as<T>(), z);
+}
+
+void apply_split(dwp_ctx *c, const double *v, double *z) {
+    if (c->opts.precision == DWP_MIXED) split_impl<float>(c, v, z);
+    else split_impl<double>(c, v, z);
+}
+
+void check_finite_dev(dwp_ctx *c, const double *x, const char *what) {
+    int *flags = reinterpret_cast<int *>(c->partial.as<double>());
+    launch_check_finite(c->stream, x, c->plan.N, flags);
+    DWP_HIP(hipMemcpyAsync(c->host, flags, sizeof(int) * RED_BLOCKS, hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    const int *hf = reinterpret_cast<const int *>(c->host);
+    int f = 0;
+    for (int b = 0; b < RED_BLOCKS; ++b) f |= hf[b];
+    if (f & 1) fail(DWP_ENONFINITE, std::string(what) + " holds NaN or Inf");
+}
+
+// FGMRES(m) with the split as right preconditioner; x is updated in place.
+// Returns the number of iterations; *rel receives the final true relative
+// residual.
+int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, double *rel) {
+    Plan &p = c->plan;
+    const dwp_opts &o = c->opts;
+    hipStream_t s = c->stream;
+    const size_t N = p.N;
+    const int m = o.restart;
+    double *V = c->V.as<double>(), *Z = c->Z.as<double>();
+    double *coef = c->coef.as<double>();
+    double *part = c->partial.as<double>();
+    std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), y(m);
+    auto Hij = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
+    int iters = 0;
+    *restarts = 0;
+    for (;;) {
+        // r = b - A x into V_0
+        launch_apply_full(s, p, x, c->eps.as<double>(), b, V, true);
+        launch_dot(s, V, V, N, part, coef);
+        to_host(c, coef, 1);
+        const double beta = std::sqrt(c->host[0]);
+        if (!std::isfinite(beta)) fail(DWP_ENONFINITE, "residual is not finite");
+        *rel = beta / bnorm;
+        if (*rel <= o.tol || iters >= o.max_outer) return iters;
+        ++*restarts;
+        launch_axpby(s, V, 1.0 / beta, V, 0.0, N);
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        for (int j = 0; j < m && iters < o.max_outer; ++j) {
+            double *Vj = V + (size_t)j * N, *Vn = V + (size_t)(j + 1) * N, *Zj = Z + (size_t)j * N;
+            apply_split(c, Vj, Zj);
+            launch_apply_full(s, p, Zj, c->eps.as<double>(), nullptr, Vn, false);
+            // classical Gram-Schmidt, twice
+            launch_multidot(s, V, N, j + 1, Vn, N, part, coef);
+            launch_axpy_multi(s, Vn, V, N, j + 1, coef, N, -1.0, part, nullptr);
+            launch_multidot(s, V, N, j + 1, Vn, N, part, coef + 64);
+            launch_axpy_multi(s, Vn, V, N, j + 1, coef + 64, N, -1.0, part, coef + 128);
+            DWP_HIP(hipMemcpyAsync(c->host, coef, sizeof(double) * 129, hipMemcpyDeviceToHost, s));
+            sync(c);
+            for (int i = 0; i <= j; ++i) Hij(i, j) = c->host[i] + c->host[64 + i];
+            const double hn = std::sqrt(c->host[128]);
+            Hij(j + 1, j) = hn;
+            ++iters;
+            if (!std::isfinite(hn)) fail(DWP_ENONFINITE, "Krylov basis is not finite");
+            if (hn > 0.0) launch_axpby(s, Vn, 1.0 / hn, Vn, 0.0, N);
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
+                Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
+                Hij(i, j) = t;
+            }
+            const double den = std::hypot(Hij(j, j), Hij(j + 1, j));
+            cs[j] = den > 0 ? Hij(j, j) / den : 1.0;
+            sn[j] = den > 0 ? Hij(j + 1, j) / den : 0.0;
+            Hij(j, j) = den;
+            Hij(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            k = j + 1;
+            if (std::fabs(g[j + 1]) <= o.tol * bnorm || hn == 0.0) break;
+        }
+        // y = H^{-1} g (upper triangular), x += Z y
+        for (int i = k - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int l = i + 1; l < k; ++l) t -= Hij(i, l) * y[l];
+            y[i] = Hij(i, i) != 0.0 ? t / Hij(i, i) : 0.0;
+        }
+        for (int i = 0; i < k; ++i) c->host[i] = y[i];
+        DWP_HIP(hipMemcpyAsync(coef + 192, c->host, sizeof(double) * k, hipMemcpyHostToDevice, s));
+        launch_axpy_multi(s, x, Z, N, k, coef + 192, N, 1.0, part, nullptr);
+        sync(c);  // the staging buffer is reused next
+    }
+}
+
+void need_grid(dwp_ctx *c) {
+    if (!c->have_grid) fail(DWP_ESTATE, "dwp_set_grid has not been called");
+}
+void need_eps(dwp_ctx *c) {
+    need_grid(c);
+    if (!c->have_eps) fail(DWP_ESTATE, "no permittivity: call dwp_set_epsilon or dwp_build_epsilon");
+}
+
+void validate_opts(const dwp_opts &o) {
+    if (o.precision != DWP_FP64 && o.precision != DWP_MIXED) fail(DWP_EINVAL, "precision must be 0 or 1");
+    if (o.pre < 0 || o.post < 0 || o.pre + o.post < 1 || o.pre > 16 || o.post > 16)
+        fail(DWP_EINVAL, "pre/post sweeps out of range");
+    if (o.coarse_sweeps < 1 || o.coarse_sweeps > 100000) fail(DWP_EINVAL, "coarse_sweeps out of range");
+    if (o.max_levels < 1 || o.max_levels > 32) fail(DWP_EINVAL, "max_levels out of range");
+    if (o.cycles < 1 || o.cycles > 16) fail(DWP_EINVAL, "cycles out of range");
+    if (!(o.tol > 0.0) || !(o.tol < 1.0)) fail(DWP_EINVAL, "tol must lie in (0, 1)");
+    if (o.max_outer < 1) fail(DWP_EINVAL, "max_outer must be >= 1");
+    if (o.restart < 1 || o.restart > 63) fail(DWP_EINVAL, "restart must lie in [1, 63]");
+    if (o.scaled_dry != 0 && o.scaled_dry != 1) fail(DWP_EINVAL, "scaled_dry must be 0 or 1");
+    if (o.warm_start != 0 && o.warm_start != 1) fail(DWP_EINVAL, "warm_start must be 0 or 1");
+}
+
+AtomParams atom_params(const dwp_eps_params *ep) {
+    AtomParams a;
+    a.eps_inf = ep->eps_inf;
+    a.delta = ep->delta;
+    a.delta_z = ep->delta_z;
+    a.z_lim = ep->z_lim;
+    a.exclusion = ep->exclusion;
+    return a;
+}
+
+void validate_eps_params(const dwp_eps_params *ep) {
+    if (!ep) fail(DWP_EINVAL, "params is NULL");
+    if (!(ep->eps_inf > 1.0) || !std::isfinite(ep->eps_inf)) fail(DWP_EINVAL, "eps_inf must be > 1");
+    if (!(ep->delta > 0.0) || !std::isfinite(ep->delta)) fail(DWP_EINVAL, "delta must be > 0");
+    if (ep->exclusion != 0 && ep->exclusion != 1) fail(DWP_EINVAL, "exclusion must be 0 or 1");
+    if (ep->exclusion && (!(ep->delta_z > 0.0) || !std::isfinite(ep->z_lim)))
+        fail(DWP_EINVAL, "exclusion needs delta_z > 0 and a finite z_lim");
+}
+
+// Packs atoms (x, y, z wrapped into the cell) into the device buffer.
+void upload_atoms(dwp_ctx *c, int n, const double *xyz, const double *radius, const double *q,
+                  const double *sigma, const dwp_eps_params *ep) {
+    const Plan &p = c->plan;
+    if (n < 1 || n > 1000000) fail(DWP_EINVAL, "atom count out of range");
+    if (!xyz) fail(DWP_EINVAL, "xyz is NULL");
+    std::vector<double> rec((size_t)n * 8, 0.0);
+    const double Lmin = std::min(p.L[0], std::min(p.L[1], p.L[2]));
+    for (int a = 0; a < n; ++a) {
+        for (int d = 0; d < 3; ++d) {
+            const double v = xyz[3 * a + d];
+            if (!std::isfinite(v)) fail(DWP_ENONFINITE, "atom coordinate is not finite");
+            double w = std::fmod(v, p.L[d]);
+            if (w < 0) w += p.L[d];
+            rec[8 * a + d] = w;
+        }
+        if (radius) {
+            if (!(radius[a] > 0.0) || !std::isfinite(radius[a])) fail(DWP_EINVAL, "radius must be > 0");
+            if (ep && 2.0 * (radius[a] + 6.0 * ep->delta) >= Lmin)
+                fail(DWP_EINVAL, "switch cutoff r + 6 delta must be below half the cell");
+            rec[8 * a + 3] = radius[a];
+        }
+        if (q) {
+            if (!std::isfinite(q[a])) fail(DWP_ENONFINITE, "charge is not finite");
+            rec[8 * a + 4] = q[a];
+        }
+        if (sigma) {
+            if (!(sigma[a] > 0.0) || !std::isfinite(sigma[a])) fail(DWP_EINVAL, "sigma must be > 0");
+            if (18.0 * sigma[a] >= Lmin) fail(DWP_EINVAL, "Gaussian cutoff 9 sigma must be below half the cell");
+            rec[8 * a + 5] = sigma[a];
+        }
+        rec[8 * a + 6] = (ep && ep->exclusion && xyz[3 * a + 2] <= ep->z_lim) ? 1.0 : 0.0;
+    }
+    if (ep && radius) {
+        // the force kernel keeps at most 256 switch neighbours per atom
+        for (int a = 0; a < n; ++a) {
+            int cnt = 0;
+            for (int b2 = 0; b2 < n; ++b2) {
+                if (b2 == a) continue;
+                double d2 = 0;
+                for (int d = 0; d < 3; ++d) {
+                    double dd = rec[8 * a + d] - rec[8 * b2 + d];
+                    dd -= p.L[d] * std::nearbyint(dd / p.L[d]);
+                    d2 += dd * dd;
+                }
+                const double lim = radius[a] + radius[b2] + 12.0 * ep->delta;
+                if (d2 < lim * lim) ++cnt;
+            }
+            if (cnt > 255) fail(DWP_EINVAL, "more than 255 overlapping switches around one atom");
+        }
+    }
+    c->atoms.alloc(sizeof(double) * rec.size());
+    DWP_HIP(hipMemcpyAsync(c->atoms.p, rec.data(), sizeof(double) * rec.size(), hipMemcpyHostToDevice, c->stream));
+    sync(c);  // rec goes out of scope
+}
+
+void validate_grid(int nx, int ny, int nz, double Lx, double Ly, double Lz) {
+    if (!good_size(nx) || !good_size(ny) || !good_size(nz))
+        fail(DWP_EINVAL, "each grid size must be even, in [8, 4096], with prime factors 2 and 3 only");
+    if (!(Lx > 0) || !(Ly > 0) || !(Lz > 0) || !std::isfinite(Lx) || !std::isfinite(Ly) || !std::isfinite(Lz))
+        fail(DWP_EINVAL, "cell lengths must be positive and finite");
+}
+
+void set_grid_impl(dwp_ctx *c, int nx, int ny, int nz, double Lx, double Ly, double Lz, const dwp_opts *o) {
+    validate_grid(nx, ny, nz, Lx, Ly, Lz);
+    dwp_opts opts;
+    if (o) opts = *o;
+    else dwp_default_opts(&opts);
+    validate_opts(opts);
+    c->have_grid = c->have_eps = c->have_solution = false;
+    free_levels(c);
+    Plan &p = c->plan;
+    p.nx = nx; p.ny = ny; p.nz = nz;
+    p.L[0] = Lx; p.L[1] = Ly; p.L[2] = Lz;
+    p.h[0] = Lx / nx; p.h[1] = Ly / ny; p.h[2] = Lz / nz;
+    p.N = (size_t)nx * ny * nz;
+    p.nkx = nx / 2 + 1;
+    c->opts = opts;
+    plan_wet(c);
+    const size_t N = p.N;
+    const size_t d = sizeof(double);
+    c->eps.alloc(d * N); c->sinv.alloc(d * N); c->b.alloc(d * N); c->r.alloc(d * N);
+    c->w.alloc(d * N); c->phi_last.alloc(d * N); c->gbuf.alloc(d * N);
+    c->V.alloc(d * N * (opts.restart + 1));
+    c->Z.alloc(d * N * opts.restart);
+    c->cbuf.alloc(sizeof(double2) * (size_t)p.nkx * ny * nz);
+    c->Hz.alloc(d * nz);
+    c->partial.alloc(d * (size_t)RED_BLOCKS * 64);
+    c->coef.alloc(d * 512);
+    fft_plan_axis(c->fx, nx, p.h[0], true);
+    fft_plan_axis(c->fy, ny, p.h[1], false);
+    fft_plan_axis(c->fz, nz, p.h[2], false);
+    ensure_levels(c);
+    c->have_grid = true;
+}
+
+void set_opts_impl(dwp_ctx *c, const dwp_opts *o) {
+    need_grid(c);
+    if (!o) fail(DWP_EINVAL, "opts is NULL");
+    validate_opts(*o);
+    const dwp_opts old = c->opts;
+    c->opts = *o;
+    try {
+        if (o->restart > old.restart) {
+            c->V.alloc(sizeof(double) * c->plan.N * (o->restart + 1));
+            c->Z.alloc(sizeof(double) * c->plan.N * o->restart);
+        }
+        const bool replan = o->z_wet_lo != old.z_wet_lo || o->z_wet_hi != old.z_wet_hi ||
+                            o->max_levels != old.max_levels ||
+                            (std::isnan(o->z_wet_lo) != std::isnan(old.z_wet_lo)) ||
+                            (std::isnan(o->z_wet_hi) != std::isnan(old.z_wet_hi));
+        if (replan) plan_wet(c);
+        ensure_levels(c);
+        if (c->have_eps) prepare_eps(c);
+    } catch (...) {
+        c->opts = old;
+        throw;
+    }
+}
+
+void set_epsilon_impl(dwp_ctx *c, const double *eps_dev) {
+    need_grid(c);
+    if (!eps_dev) fail(DWP_EINVAL, "eps_dev is NULL");
+    int *flags = reinterpret_cast<int *>(c->partial.as<double>());
+    launch_check_eps(c->stream, eps_dev, c->plan.N, flags);
+    DWP_HIP(hipMemcpyAsync(c->host, flags, sizeof(int) * RED_BLOCKS, hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    const int *hf = reinterpret_cast<const int *>(c->host);
+    int f = 0;
+    for (int b = 0; b < RED_BLOCKS; ++b) f |= hf[b];
+    if (f & 1) fail(DWP_ENONFINITE, "eps holds NaN or Inf");
+    if (f & 2) fail(DWP_EINVAL, "eps must be >= 1 everywhere");
+    DWP_HIP(hipMemcpyAsync(c->eps.p, eps_dev, sizeof(double) * c->plan.N, hipMemcpyDeviceToDevice, c->stream));
+    prepare_eps(c);
+    c->have_eps = true;
+    c->have_solution = false;
+    c->eps_natoms = -1;
+    c->eps_exclusion = false;
+}
+
+void build_epsilon_impl(dwp_ctx *c, int n, const double *xyz, const double *radius, const dwp_eps_params *ep) {
+    need_grid(c);
+    validate_eps_params(ep);
+    if (!radius) fail(DWP_EINVAL, "radius is NULL");
+    upload_atoms(c, n, xyz, radius, nullptr, nullptr, ep);
+    AtomParams ap = atom_params(ep);
+    if (ep->exclusion) c->S.alloc(sizeof(double) * c->plan.N);
+    launch_build_eps(c->stream, c->plan, n, c->atoms.as<double>(), ap, c->Hz.as<double>(), c->eps.as<double>(),
+                     ep->exclusion ? c->S.as<double>() : nullptr);
+    prepare_eps(c);
+    c->have_eps = true;
+    c->have_solution = false;
+    c->eps_natoms = n;
+    c->eps_exclusion = ep->exclusion != 0;
+}
+
+void solve_impl(dwp_ctx *c, const double *rho, double *phi, double *energy, dwp_info *info) {
+    need_eps(c);
+    if (!rho || !phi) fail(DWP_EINVAL, "rho_dev and phi_dev must not be NULL");
+    Plan &p = c->plan;
+    hipStream_t s = c->stream;
+    const size_t N = p.N;
+    double *coef = c->coef.as<double>();
+    double *part = c->partial.as<double>();
+    const auto t0 = std::chrono::steady_clock::now();
+    check_finite_dev(c, rho, "rho");
+    if (c->opts.warm_start) check_finite_dev(c, phi, "the initial phi");
+    launch_sum(s, rho, N, part, coef + 400);
+    launch_rhs(s, rho, coef + 400, 1.0 / (double)N, c->b.as<double>(), N);
+    launch_dot(s, c->b.as<double>(), c->b.as<double>(), N, part, coef + 401);
+    DWP_HIP(hipMemcpyAsync(c->host, coef + 400, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    sync(c);
+    c->mean_rho = c->host[0] / (double)N;
+    const double bnorm = std::sqrt(c->host[1]);
+    if (!c->opts.warm_start) launch_fill(s, phi, 0.0, N);
+    int iters = 0, restarts = 0;
+    double rel = 0.0;
+    int status = DWP_OK;
+    if (bnorm > 0.0) {
+        iters = fgmres(c, c->b.as<double>(), bnorm, phi, &restarts, &rel);
+        if (rel > c->opts.tol) status = DWP_ENOCONV;
+    } else {
+        launch_fill(s, phi, 0.0, N);
+    }
+    // gauge: zero mean
+    launch_sum(s, phi, N, part, coef + 402);
+    launch_sub_mean(s, phi, coef + 402, 1.0 / (double)N, N);
+    launch_energy(s, p, rho, phi, c->eps.as<double>(), part, coef + 403);
+    DWP_HIP(hipMemcpyAsync(c->phi_last.p, phi, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    to_host(c, coef + 403, 2);
+    const double h3 = p.h[0] * p.h[1] * p.h[2];
+    const double E = 0.5 * h3 * c->host[0];
+    const double Eeps = h3 / (8.0 * 3.14159265358979323846) * c->host[1];
+    c->have_solution = true;
+    if (energy) *energy = E;
+    if (info) {
+        info->outer_iters = iters;
+        info->vcycles = iters * c->opts.cycles;
+        info->restarts = restarts;
+        info->k_w0 = p.k_w0;
+        info->k_w1 = p.k_w1;
+        info->n_levels = (int)p.levels.size();
+        info->rel_res = rel;
+        info->energy = E;
+        info->energy_eps_form = Eeps;
+        info->mean_rho_removed = c->mean_rho;
+        info->t_total_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (status != DWP_OK) fail(status, "tolerance not reached within max_outer iterations");
+}
+
+void forces_impl(dwp_ctx *c, int n, const double *xyz, const double *radius, const double *q,
+                 const double *sigma, const dwp_eps_params *ep, double *out) {
+    need_eps(c);
+    if (!c->have_solution) fail(DWP_ESTATE, "no solution: call dwp_solve first");
+    if (!q || !sigma || !out) fail(DWP_EINVAL, "q, sigma and dEdR must not be NULL");
+    if (ep) {
+        validate_eps_params(ep);
+        if (!radius) fail(DWP_EINVAL, "radius is NULL");
+        if (c->eps_natoms != n) fail(DWP_ESTATE, "eps was not built from these atoms");
+        if ((ep->exclusion != 0) != c->eps_exclusion) fail(DWP_ESTATE, "exclusion differs from the eps build");
+    }
+    upload_atoms(c, n, xyz, ep ? radius : nullptr, q, sigma, ep);
+    Plan &p = c->plan;
+    AtomParams ap{};
+    if (ep) ap = atom_params(ep);
+    launch_eps_gradient(c->stream, p, c->phi_last.as<double>(), c->gbuf.as<double>());
+    c->fpart.alloc(sizeof(double) * (forces_partial_len(p, n) + 3 * (size_t)n));
+    double *outd = c->fpart.as<double>() + forces_partial_len(p, n);
+    launch_forces(c->stream, p, n, c->atoms.as<double>(), ep ? &ap : nullptr, c->phi_last.as<double>(),
+                  c->gbuf.as<double>(), c->S.as<double>(), c->Hz.as<double>(), c->fpart.as<double>(), outd);
+    DWP_HIP(hipMemcpyAsync(out, outd, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+}
+
+thread_local std::string g_create_err;
+
+}  // namespace
+}  // namespace dwp
+
+// ============================================================== C ABI
+using dwp::Error;
+
+#define ABI_BEGIN(c)                                   \
+    if (!(c)) return DWP_EINVAL;                       \
+    (c)->err.clear();                                  \
+    try {
+#define ABI_END(c)                                     \
+    }                                                  \
+    catch (const Error &e) {                           \
+        (c)->err = e.msg;                              \
+        return e.status;                               \
+    }                                                  \
+    catch (const std::exception &e) {                  \
+        (c)->err = e.what();                           \
+        return DWP_EHIP;                               \
+    }                                                  \
+    return DWP_OK;
+
+extern "C" {
+
+void dwp_default_opts(dwp_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = DWP_FP64;
+    o->z_wet_lo = std::numeric_limits<double>::quiet_NaN();
+    o->z_wet_hi = std::numeric_limits<double>::quiet_NaN();
+    o->pre = 2;
+    o->post = 2;
+    o->coarse_sweeps = 64;
+    o->max_levels = 16;
+    o->cycles = 1;
+    o->scaled_dry = 0;
+    o->tol = 1e-10;
+    o->max_outer = 600;
+    o->restart = 30;
+    o->warm_start = 0;
+}
+
+int dwp_create(dwp_ctx **out, int device, void *stream) {
+    if (!out) return DWP_EINVAL;
+    *out = nullptr;
+    dwp_ctx *c = new dwp_ctx();
+    try {
+        int count = 0;
+        DWP_HIP(hipGetDeviceCount(&count));
+        if (device < 0 || device >= count) dwp::fail(DWP_EINVAL, "no such HIP device");
+        DWP_HIP(hipSetDevice(device));
+        c->device = device;
+        c->stream = static_cast<hipStream_t>(stream);
+        c->host_len = 4096;
+        DWP_HIP(hipHostMalloc(reinterpret_cast<void **>(&c->host), sizeof(double) * c->host_len, hipHostMallocDefault));
+        dwp_default_opts(&c->opts);
+    } catch (const Error &e) {
+        dwp::g_create_err = e.msg;
+        if (c->host) (void)hipHostFree(c->host);
+        delete c;
+        return e.status;
+    }
+    *out = c;
+    return DWP_OK;
+}
+
+int dwp_destroy(dwp_ctx *c) {
+    if (!c) return DWP_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    dwp::free_levels(c);
+    if (c->host) (void)hipHostFree(c->host);
+    delete c;
+    return DWP_OK;
+}
+
+int dwp_set_stream(dwp_ctx *c, void *stream) {
+    ABI_BEGIN(c)
+    c->stream = static_cast<hipStream_t>(stream);
+    ABI_END(c)
+}
+
+int dwp_set_grid(dwp_ctx *c, int nx, int ny, int nz, double Lx, double Ly, double Lz, const dwp_opts *o) {
+    ABI_BEGIN(c)
+    DWP_HIP(hipSetDevice(c->device));
+    dwp::set_grid_impl(c, nx, ny, nz, Lx, Ly, Lz, o);
+    ABI_END(c)
+}
+
+int dwp_set_opts(dwp_ctx *c, const dwp_opts *o) {
+    ABI_BEGIN(c)
+    DWP_HIP(hipSetDevice(c->device));
+    dwp::set_opts_impl(c, o);
+    ABI_END(c)
+}
+
+int dwp_set_epsilon(dwp_ctx *c, const double *eps_dev) {
+    ABI_BEGIN(c)
+    DWP_HIP(hipSetDevice(c->device));
+    dwp::set_epsilon_impl(c, eps_dev);
+    ABI_END(c)
+}
+
+int dwp_build_epsilon(dwp_ctx *c, int n, const double *xyz, const double *radius, const dwp_eps_params *ep) {
+    ABI_BEGIN(c)
+    DWP_HIP(hipSetDevice(c->device));
+    dwp::build_epsilon_impl(c, n, xyz, radius, ep);
+    ABI_END(c)
+}
+
+int dwp_get_epsilon(dwp_ctx *c, double *eps_dev) {
+    ABI_BEGIN(c)
+    dwp::need_eps(c);
+    if (!eps_dev) dwp::fail(DWP_EINVAL, "eps_dev is NULL");
+    DWP_HIP(hipSetDevice(c->device));
+    DWP_HIP(hipMemcpyAsync(eps_dev, c->eps.p, sizeof(double) * c->plan.N, hipMemcpyDeviceToDevice, c->stream));
+    ABI_END(c)
+}
+
+int dwp_build_rho(dwp_ctx *c, int n, const double *xyz, const double *q, const double *sigma, double *rho_dev) {
+    ABI_BEGIN(c)
+    dwp::need_grid(c);
+    if (!q || !sigma || !rho_dev) dwp::fail(DWP_EINVAL, "q, sigma and rho_dev must not be NULL");
+    DWP_HIP(hipSetDevice(c->device));
+    dwp::upload_atoms(c, n, xyz, nullptr, q, sigma, nullptr);
+    dwp::launch_build_rho(c->stream, c->plan, n, c->atoms.as<double>(), rho_dev);
+    ABI_END(c)
+}
+
+int dwp_solve(dwp_ctx *c, const double *rho, double *phi, double *energy, dwp_info *info) {
+    ABI_BEGIN(c)
+    DWP_HIP(hipSetDevice(c->device));
+    dwp::solve_impl(c, rho, phi, energy, info);
+    ABI_END(c)
+}
+
+int dwp_eps_gradient(dwp_ctx *c, double *g) {
+    ABI_BEGIN(c)
+    dwp::need_eps(c);
+    if (!c->have_solution) dwp::fail(DWP_ESTATE, "no solution: call dwp_solve first");
+    if (!g) dwp::fail(DWP_EINVAL, "dEdeps_dev is NULL");
+    DWP_HIP(hipSetDevice(c->device));
+    dwp::launch_eps_gradient(c->stream, c->plan, c->phi_last.as<double>(), g);
+    ABI_END(c)
+}
+
+int dwp_forces(dwp_ctx *c, int n, const double *xyz, const double *radius, const double *q, const double *sigma,
+               const dwp_eps_params *ep, double *out) {
+    ABI_BEGIN(c)
+    DWP_HIP(hipSetDevice(c->device));
+    dwp::forces_impl(c, n, xyz, radius, q, sigma, ep, out);
+    ABI_END(c)
+}
+
+int dwp_apply_operator(dwp_ctx *c, const double *phi, double *out) {
+    ABI_BEGIN(c)
+    dwp::need_eps(c);
+    if (!phi || !out) dwp::fail(DWP_EINVAL, "NULL pointer");
+    DWP_HIP(hipSetDevice(c->device));
+    dwp::launch_apply_full(c->stream, c->plan, phi, c->eps.as<double>(), nullptr, out, false);
+    ABI_END(c)
+}
+
+int dwp_vacuum_solve(dwp_ctx *c, const double *r, double *out) {
+    ABI_BEGIN(c)
+    dwp::need_grid(c);
+    if (!r || !out) dwp::fail(DWP_EINVAL, "NULL pointer");
+    DWP_HIP(hipSetDevice(c->device));
+    dwp::launch_vacuum_solve(c->stream, c->plan, c->fx, c->fy, c->fz, r, nullptr, c->cbuf.as<double2>(), out);
+    ABI_END(c)
+}
+
+int dwp_apply_split(dwp_ctx *c, const double *r, double *out) {
+    ABI_BEGIN(c)
+    dwp::need_eps(c);
+    if (!r || !out) dwp::fail(DWP_EINVAL, "NULL pointer");
+    DWP_HIP(hipSetDevice(c->device));
+    dwp::apply_split(c, r, out);
+    ABI_END(c)
+}
+
+int dwp_energy(dwp_ctx *c, const double *rho, const double *phi, double *e) {
+    ABI_BEGIN(c)
+    dwp::need_eps(c);
+    if (!rho || !phi || !e) dwp::fail(DWP_EINVAL, "NULL pointer");
+    DWP_HIP(hipSetDevice(c->device));
+    double *coef = c->coef.as<double>();
+    dwp::launch_energy(c->stream, c->plan, rho, phi, c->eps.as<double>(), c->partial.as<double>(), coef + 403);
+    dwp::to_host(c, coef + 403, 1);
+    const dwp::Plan &p = c->plan;
+    *e = 0.5 * p.h[0] * p.h[1] * p.h[2] * c->host[0];
+    ABI_END(c)
+}
+
+int dwp_plan(int nx, int ny, int nz, double Lx, double Ly, double Lz, const dwp_opts *o, int *out, int out_len) {
+    try {
+        dwp::g_create_err.clear();
+        dwp::validate_grid(nx, ny, nz, Lx, Ly, Lz);
+        dwp_opts opts;
+        if (o) opts = *o;
+        else dwp_default_opts(&opts);
+        dwp::validate_opts(opts);
+        const double L[3] = {Lx, Ly, Lz};
+        const double h[3] = {Lx / nx, Ly / ny, Lz / nz};
+        int k0, k1, nw;
+        dwp::choose_wet(nx, ny, nz, h, L, opts, &k0, &k1, &nw);
+        const auto lv = dwp::plan_levels(nx, ny, nw, h, opts.max_levels);
+        if (!out || out_len < 3 + 3 * (int)lv.size()) dwp::fail(DWP_EINVAL, "output array too short");
+        out[0] = k0;
+        out[1] = k1;
+        out[2] = (int)lv.size();
+        for (size_t l = 0; l < lv.size(); ++l) {
+            out[3 + 3 * l] = lv[l].nx;
+            out[4 + 3 * l] = lv[l].ny;
+            out[5 + 3 * l] = lv[l].nw;
+        }
+    } catch (const Error &e) {
+        dwp::g_create_err = e.msg;
+        return e.status;
+    }
+    return DWP_OK;
+}
+
+const char *dwp_last_error(const dwp_ctx *c) {
+    if (!c) return dwp::g_create_err.c_str();
+    return c->err.c_str();
+}
+
+}  // extern "C"
