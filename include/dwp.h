@@ -78,6 +78,8 @@ typedef struct {
     int max_outer;         /* cap on preconditioned Krylov iterations          */
     int restart;           /* FGMRES restart length m (1..64)                  */
     int warm_start;        /* 1: phi_dev holds the initial guess on entry      */
+    int profile;           /* 1: time kernel groups with HIP events on the     */
+                           /* context stream (see dwp_profile)                 */
 } dwp_opts;
 
 /* Per-solve report. */
@@ -186,6 +188,16 @@ int dwp_vacuum_solve(dwp_ctx *ctx, const double *r_dev, double *out_dev);
 int dwp_apply_split(dwp_ctx *ctx, const double *r_dev, double *out_dev);
 /* E = 1/2 h^3 sum rho phi (compensated, deterministic). */
 int dwp_energy(dwp_ctx *ctx, const double *rho_dev, const double *phi_dev, double *energy_host);
+
+/* Kernel-group timings gathered while opts.profile = 1 (HIP events recorded
+ * around each launch on the context stream).  Group g in [0, dwp_profile_count()):
+ * *name receives a static string, *ms the summed launch durations, *launches
+ * the number of launches, *bytes the algorithmic HBM bytes those launches
+ * must move (the minimum traffic of the operation, not a counter reading).
+ * dwp_profile_reset() clears the sums. */
+int dwp_profile_count(void);
+int dwp_profile_get(dwp_ctx *ctx, int group, const char **name, double *ms, long *launches, double *bytes);
+int dwp_profile_reset(dwp_ctx *ctx);
 
 /* Validate a grid and options on the host and report the solver plan without
  * touching a device: out[0] = first wet plane k_w0 (in [0, nz)), out[1] =

@@ -79,6 +79,7 @@ def solve(rho, eps, h, tol=1e-12, max_iter=2000, return_info=False):
     rz = np.vdot(r, z)
     it = 0
     rel = 1.0
+    history = []
     while it < max_iter:
         Ap = apply_A(p, eps, h)
         alpha = rz / np.vdot(p, Ap)
@@ -88,6 +89,7 @@ def solve(rho, eps, h, tol=1e-12, max_iter=2000, return_info=False):
         if it % 25 == 0:  # refresh the recursive residual with the true one
             r = b - apply_A(phi, eps, h)
         rel = np.linalg.norm(r) / bnorm
+        history.append(float(rel))
         if rel <= tol:
             rel = np.linalg.norm(b - apply_A(phi, eps, h)) / bnorm
             if rel <= tol:
@@ -99,7 +101,7 @@ def solve(rho, eps, h, tol=1e-12, max_iter=2000, return_info=False):
         rz = rz_new
     phi -= phi.mean()
     if return_info:
-        return phi, dict(iters=it, rel_res=float(rel))
+        return phi, dict(iters=it, rel_res=float(rel), history=history)
     return phi
 
 

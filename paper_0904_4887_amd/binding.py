@@ -33,7 +33,7 @@ class Opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("z_wet_lo", C.c_double), ("z_wet_hi", C.c_double),
                 ("pre", C.c_int), ("post", C.c_int), ("coarse_sweeps", C.c_int), ("max_levels", C.c_int),
                 ("cycles", C.c_int), ("scaled_dry", C.c_int), ("tol", C.c_double), ("max_outer", C.c_int),
-                ("restart", C.c_int), ("warm_start", C.c_int)]
+                ("restart", C.c_int), ("warm_start", C.c_int), ("profile", C.c_int)]
 
 
 class Info(C.Structure):
@@ -74,6 +74,9 @@ _SIGNATURES = {
     "dwp_plan": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.POINTER(Opts),
                            C.POINTER(C.c_int), C.c_int]),
     "dwp_last_error": (C.c_char_p, [_P]),
+    "dwp_profile_count": (C.c_int, []),
+    "dwp_profile_get": (C.c_int, [_P, C.c_int, C.POINTER(C.c_char_p), _D, C.POINTER(C.c_long), _D]),
+    "dwp_profile_reset": (C.c_int, [_P]),
 }
 
 _lib_handle = None
@@ -266,6 +269,20 @@ class Solver:
     def apply_split(self, r, out=None):
         out = self.empty() if out is None else out
         self._check(lib().dwp_apply_split(self._h, self._dev(r, "r"), self._dev(out, "out")))
+        return out
+
+    def profile_reset(self):
+        self._check(lib().dwp_profile_reset(self._h))
+
+    def profile(self):
+        """{group: dict(name, ms, launches, bytes)} for groups with launches."""
+        out = {}
+        for g in range(lib().dwp_profile_count()):
+            name, ms, n, by = C.c_char_p(), C.c_double(), C.c_long(), C.c_double()
+            self._check(lib().dwp_profile_get(self._h, g, C.byref(name), C.byref(ms), C.byref(n), C.byref(by)))
+            if n.value:
+                nm = name.value.decode()
+                out[nm] = dict(name=nm, ms=ms.value, launches=n.value, bytes=by.value)
         return out
 
     def energy(self, rho, phi):

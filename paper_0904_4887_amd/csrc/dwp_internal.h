@@ -82,9 +82,40 @@ struct FFTAxis {
     DevBuf lam;                   // n (or nkx for x) discrete symbol values
 };
 
-struct Timers {
-    hipEvent_t a = nullptr, b = nullptr;
+// Kernel groups timed when profiling is on.
+enum ProfGroup {
+    PG_FFT = 0,        // one dry update: the five FFT passes
+    PG_RBGS_FINE,      // one colour pass of red-black Gauss-Seidel on the fine slab
+    PG_RBGS_COARSE,    // colour passes on the coarser levels
+    PG_MG_OTHER,       // residuals, transfers, coarsest solve
+    PG_APPLY,          // full-box operator / residual
+    PG_WET,            // wet-slab residual extraction and combination
+    PG_KRYLOV,         // Gram-Schmidt dots and updates, norms
+    PG_BUILD,          // eps and rho builders
+    PG_FORCES,         // adjoint and forces
+    PG_COUNT
 };
+
+struct Profiler {
+    bool on = false;
+    double ms[PG_COUNT] = {0};
+    double bytes[PG_COUNT] = {0};
+    long launches[PG_COUNT] = {0};
+    std::vector<hipEvent_t> pool;
+    struct Pending {
+        int group, ev;
+        double bytes;
+    };
+    std::vector<Pending> pending;
+    size_t next = 0;
+    int begin(hipStream_t s);                                 // -1 when off
+    void end(hipStream_t s, int ev, int group, double bytes);
+    void collect();                                           // after a stream sync
+    void reset();
+    ~Profiler();
+};
+
+const char *prof_group_name(int g);
 
 }  // namespace dwp
 
@@ -109,7 +140,7 @@ struct dwp_ctx {
     dwp::FFTAxis fx, fy, fz;
     double *host = nullptr;       // pinned host staging (small)
     size_t host_len = 0;
-    dwp::Timers t;
+    dwp::Profiler prof;
     double mean_rho = 0.0;
     // atom bookkeeping of the last build_epsilon
     int eps_natoms = -1;

@@ -43,6 +43,58 @@ void DevBuf::release() {
     bytes = 0;
 }
 
+static const char *const kGroupNames[PG_COUNT] = {"fft_dry_update", "rbgs_fine", "rbgs_coarse", "mg_other",
+                                                  "apply_full",     "wet_slab",  "krylov",      "builders",
+                                                  "forces"};
+
+const char *prof_group_name(int g) { return (g >= 0 && g < PG_COUNT) ? kGroupNames[g] : ""; }
+
+int Profiler::begin(hipStream_t s) {
+    if (!on) return -1;
+    while (next + 2 > pool.size()) {
+        hipEvent_t e;
+        DWP_HIP(hipEventCreate(&e));
+        pool.push_back(e);
+    }
+    const int ev = (int)next;
+    next += 2;
+    DWP_HIP(hipEventRecord(pool[ev], s));
+    return ev;
+}
+
+void Profiler::end(hipStream_t s, int ev, int group, double b) {
+    if (ev < 0) return;
+    DWP_HIP(hipEventRecord(pool[ev + 1], s));
+    pending.push_back(Pending{group, ev, b});
+}
+
+void Profiler::collect() {
+    for (const Pending &q : pending) {
+        float t = 0.f;
+        DWP_HIP(hipEventElapsedTime(&t, pool[q.ev], pool[q.ev + 1]));
+        ms[q.group] += t;
+        bytes[q.group] += q.bytes;
+        launches[q.group] += 1;
+    }
+    pending.clear();
+    next = 0;
+}
+
+void Profiler::reset() {
+    for (int g = 0; g < PG_COUNT; ++g) { ms[g] = 0; bytes[g] = 0; launches[g] = 0; }
+}
+
+Profiler::~Profiler() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
+#define PROF(c, group, nbytes, stmt)                                \
+    do {                                                           \
+        const int ev_ = (c)->prof.begin((c)->stream);               \
+        stmt;                                                      \
+        (c)->prof.end((c)->stream, ev_, (group), (double)(nbytes)); \
+    } while (0)
+
 namespace {
 
 constexpr int COARSE_TARGET = 1024;  // coarsest level: at most this many points
@@ -185,7 +237,10 @@ void prepare_eps(dwp_ctx *c) {
     else prepare_level_eps<double>(c);
 }
 
-void sync(dwp_ctx *c) { DWP_HIP(hipStreamSynchronize(c->stream)); }
+void sync(dwp_ctx *c) {
+    DWP_HIP(hipStreamSynchronize(c->stream));
+    c->prof.collect();
+}
 
 void to_host(dwp_ctx *c, const double *dev, size_t n) {
     if (n > c->host_len) fail(DWP_EINVAL, "internal: host staging too small");
@@ -198,37 +253,49 @@ void vcycle(dwp_ctx *c, size_t l) {
     Plan &p = c->plan;
     Level &L = *p.levels[l];
     hipStream_t s = c->stream;
+    const double ts = (double)sizeof(T);
+    const int sg = l == 0 ? PG_RBGS_FINE : PG_RBGS_COARSE;
+    const double pass_bytes = 2.0 * ts * (double)L.n_interior();  // half of read u, eps, f + write u
     if (l + 1 == p.levels.size()) {
-        launch_level_coarse_solve<T>(s, L, c->opts.coarse_sweeps);
+        PROF(c, PG_MG_OTHER, 4.0 * ts * L.n_interior(), launch_level_coarse_solve<T>(s, L, c->opts.coarse_sweeps));
         return;
     }
     for (int k = 0; k < c->opts.pre; ++k) {
-        launch_level_smooth<T>(s, L, 0);
-        launch_level_smooth<T>(s, L, 1);
+        PROF(c, sg, pass_bytes, launch_level_smooth<T>(s, L, 0));
+        PROF(c, sg, pass_bytes, launch_level_smooth<T>(s, L, 1));
     }
     Level &C = *p.levels[l + 1];
-    launch_level_residual<T>(s, L, L.r.as<T>());
-    launch_restrict<T>(s, L, C, L.r.as<T>(), C.f.as<T>());
-    launch_zero<T>(s, C.u.as<T>(), C.n_ghosted());
+    PROF(c, PG_MG_OTHER, 4.0 * ts * L.n_interior(), launch_level_residual<T>(s, L, L.r.as<T>()));
+    PROF(c, PG_MG_OTHER, ts * (L.n_interior() + C.n_interior()),
+         launch_restrict<T>(s, L, C, L.r.as<T>(), C.f.as<T>()));
+    PROF(c, PG_MG_OTHER, ts * C.n_ghosted(), launch_zero<T>(s, C.u.as<T>(), C.n_ghosted()));
     vcycle<T>(c, l + 1);
-    launch_prolong_add<T>(s, L, C);
+    PROF(c, PG_MG_OTHER, ts * (C.n_interior() + 2.0 * L.n_interior()), launch_prolong_add<T>(s, L, C));
     for (int k = 0; k < c->opts.post; ++k) {
-        launch_level_smooth<T>(s, L, 1);
-        launch_level_smooth<T>(s, L, 0);
+        PROF(c, sg, pass_bytes, launch_level_smooth<T>(s, L, 1));
+        PROF(c, sg, pass_bytes, launch_level_smooth<T>(s, L, 0));
     }
+}
+
+double fft_bytes(const Plan &p, bool scaled) {
+    const double C = (double)p.nkx * p.ny * p.nz;
+    return 16.0 * p.N + 128.0 * C + (scaled ? 16.0 * p.N : 0.0);
 }
 
 template <class T>
 void split_impl(dwp_ctx *c, const double *v, double *z) {
     Plan &p = c->plan;
     hipStream_t s = c->stream;
-    launch_vacuum_solve(s, p, c->fx, c->fy, c->fz, v, c->opts.scaled_dry ? c->sinv.as<double>() : nullptr,
-                        c->cbuf.as<double2>(), z);
+    const bool scaled = c->opts.scaled_dry != 0;
+    PROF(c, PG_FFT, fft_bytes(p, scaled),
+         launch_vacuum_solve(s, p, c->fx, c->fy, c->fz, v, scaled ? c->sinv.as<double>() : nullptr,
+                             c->cbuf.as<double2>(), z));
     Level &F = *p.levels[0];
-    launch_wet_residual<T>(s, p, v, z, c->eps.as<double>(), F.f.as<T>());
-    launch_zero<T>(s, F.u.as<T>(), F.n_ghosted());
+    const double nW = (double)F.n_interior();
+    PROF(c, PG_WET, (24.0 + sizeof(T)) * nW, launch_wet_residual<T>(s, p, v, z, c->eps.as<double>(), F.f.as<T>()));
+    PROF(c, PG_WET, sizeof(T) * (double)F.n_ghosted(), launch_zero<T>(s, F.u.as<T>(), F.n_ghosted()));
     for (int k = 0; k < c->opts.cycles; ++k) vcycle<T>(c, 0);
-    launch_wet_add<T>(s, p, F.u.as<T>(), z);
+    PROF(c, PG_WET, (16.0 + sizeof(T)) * nW, launch_wet_add<T>(s, p, F.u.as<T>(), z));
 }
 
 void apply_split(dwp_ctx *c, const double *v, double *z) {
@@ -265,15 +332,15 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
     *restarts = 0;
     for (;;) {
         // r = b - A x into V_0
-        launch_apply_full(s, p, x, c->eps.as<double>(), b, V, true);
-        launch_dot(s, V, V, N, part, coef);
+        PROF(c, PG_APPLY, 32.0 * N, launch_apply_full(s, p, x, c->eps.as<double>(), b, V, true));
+        PROF(c, PG_KRYLOV, 8.0 * N, launch_dot(s, V, V, N, part, coef));
         to_host(c, coef, 1);
         const double beta = std::sqrt(c->host[0]);
         if (!std::isfinite(beta)) fail(DWP_ENONFINITE, "residual is not finite");
         *rel = beta / bnorm;
         if (*rel <= o.tol || iters >= o.max_outer) return iters;
         ++*restarts;
-        launch_axpby(s, V, 1.0 / beta, V, 0.0, N);
+        PROF(c, PG_KRYLOV, 16.0 * N, launch_axpby(s, V, 1.0 / beta, V, 0.0, N));
         std::fill(H.begin(), H.end(), 0.0);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
@@ -281,12 +348,13 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
         for (int j = 0; j < m && iters < o.max_outer; ++j) {
             double *Vj = V + (size_t)j * N, *Vn = V + (size_t)(j + 1) * N, *Zj = Z + (size_t)j * N;
             apply_split(c, Vj, Zj);
-            launch_apply_full(s, p, Zj, c->eps.as<double>(), nullptr, Vn, false);
+            PROF(c, PG_APPLY, 24.0 * N, launch_apply_full(s, p, Zj, c->eps.as<double>(), nullptr, Vn, false));
             // classical Gram-Schmidt, twice
-            launch_multidot(s, V, N, j + 1, Vn, N, part, coef);
-            launch_axpy_multi(s, Vn, V, N, j + 1, coef, N, -1.0, part, nullptr);
-            launch_multidot(s, V, N, j + 1, Vn, N, part, coef + 64);
-            launch_axpy_multi(s, Vn, V, N, j + 1, coef + 64, N, -1.0, part, coef + 128);
+            const double md = 8.0 * N * (j + 2), ax = 8.0 * N * (j + 3);
+            PROF(c, PG_KRYLOV, md, launch_multidot(s, V, N, j + 1, Vn, N, part, coef));
+            PROF(c, PG_KRYLOV, ax, launch_axpy_multi(s, Vn, V, N, j + 1, coef, N, -1.0, part, nullptr));
+            PROF(c, PG_KRYLOV, md, launch_multidot(s, V, N, j + 1, Vn, N, part, coef + 64));
+            PROF(c, PG_KRYLOV, ax, launch_axpy_multi(s, Vn, V, N, j + 1, coef + 64, N, -1.0, part, coef + 128));
             DWP_HIP(hipMemcpyAsync(c->host, coef, sizeof(double) * 129, hipMemcpyDeviceToHost, s));
             sync(c);
             for (int i = 0; i <= j; ++i) Hij(i, j) = c->host[i] + c->host[64 + i];
@@ -294,7 +362,7 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
             Hij(j + 1, j) = hn;
             ++iters;
             if (!std::isfinite(hn)) fail(DWP_ENONFINITE, "Krylov basis is not finite");
-            if (hn > 0.0) launch_axpby(s, Vn, 1.0 / hn, Vn, 0.0, N);
+            if (hn > 0.0) PROF(c, PG_KRYLOV, 16.0 * N, launch_axpby(s, Vn, 1.0 / hn, Vn, 0.0, N));
             for (int i = 0; i < j; ++i) {
                 const double t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
                 Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
@@ -318,7 +386,7 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
         }
         for (int i = 0; i < k; ++i) c->host[i] = y[i];
         DWP_HIP(hipMemcpyAsync(coef + 192, c->host, sizeof(double) * k, hipMemcpyHostToDevice, s));
-        launch_axpy_multi(s, x, Z, N, k, coef + 192, N, 1.0, part, nullptr);
+        PROF(c, PG_KRYLOV, 8.0 * N * (k + 2), launch_axpy_multi(s, x, Z, N, k, coef + 192, N, 1.0, part, nullptr));
         sync(c);  // the staging buffer is reused next
     }
 }
@@ -343,6 +411,7 @@ void validate_opts(const dwp_opts &o) {
     if (o.restart < 1 || o.restart > 63) fail(DWP_EINVAL, "restart must lie in [1, 63]");
     if (o.scaled_dry != 0 && o.scaled_dry != 1) fail(DWP_EINVAL, "scaled_dry must be 0 or 1");
     if (o.warm_start != 0 && o.warm_start != 1) fail(DWP_EINVAL, "warm_start must be 0 or 1");
+    if (o.profile != 0 && o.profile != 1) fail(DWP_EINVAL, "profile must be 0 or 1");
 }
 
 AtomParams atom_params(const dwp_eps_params *ep) {
@@ -442,6 +511,7 @@ void set_grid_impl(dwp_ctx *c, int nx, int ny, int nz, double Lx, double Ly, dou
     p.N = (size_t)nx * ny * nz;
     p.nkx = nx / 2 + 1;
     c->opts = opts;
+    c->prof.on = opts.profile != 0;
     plan_wet(c);
     const size_t N = p.N;
     const size_t d = sizeof(double);
@@ -466,6 +536,7 @@ void set_opts_impl(dwp_ctx *c, const dwp_opts *o) {
     validate_opts(*o);
     const dwp_opts old = c->opts;
     c->opts = *o;
+    c->prof.on = o->profile != 0;
     try {
         if (o->restart > old.restart) {
             c->V.alloc(sizeof(double) * c->plan.N * (o->restart + 1));
@@ -480,6 +551,7 @@ void set_opts_impl(dwp_ctx *c, const dwp_opts *o) {
         if (c->have_eps) prepare_eps(c);
     } catch (...) {
         c->opts = old;
+        c->prof.on = old.profile != 0;
         throw;
     }
 }
@@ -511,8 +583,9 @@ void build_epsilon_impl(dwp_ctx *c, int n, const double *xyz, const double *radi
     upload_atoms(c, n, xyz, radius, nullptr, nullptr, ep);
     AtomParams ap = atom_params(ep);
     if (ep->exclusion) c->S.alloc(sizeof(double) * c->plan.N);
-    launch_build_eps(c->stream, c->plan, n, c->atoms.as<double>(), ap, c->Hz.as<double>(), c->eps.as<double>(),
-                     ep->exclusion ? c->S.as<double>() : nullptr);
+    PROF(c, PG_BUILD, (ep->exclusion ? 16.0 : 8.0) * c->plan.N,
+         launch_build_eps(c->stream, c->plan, n, c->atoms.as<double>(), ap, c->Hz.as<double>(), c->eps.as<double>(),
+                          ep->exclusion ? c->S.as<double>() : nullptr));
     prepare_eps(c);
     c->have_eps = true;
     c->have_solution = false;
@@ -591,11 +664,12 @@ void forces_impl(dwp_ctx *c, int n, const double *xyz, const double *radius, con
     Plan &p = c->plan;
     AtomParams ap{};
     if (ep) ap = atom_params(ep);
-    launch_eps_gradient(c->stream, p, c->phi_last.as<double>(), c->gbuf.as<double>());
+    PROF(c, PG_FORCES, 16.0 * p.N, launch_eps_gradient(c->stream, p, c->phi_last.as<double>(), c->gbuf.as<double>()));
     c->fpart.alloc(sizeof(double) * (forces_partial_len(p, n) + 3 * (size_t)n));
     double *outd = c->fpart.as<double>() + forces_partial_len(p, n);
-    launch_forces(c->stream, p, n, c->atoms.as<double>(), ep ? &ap : nullptr, c->phi_last.as<double>(),
-                  c->gbuf.as<double>(), c->S.as<double>(), c->Hz.as<double>(), c->fpart.as<double>(), outd);
+    PROF(c, PG_FORCES, 16.0 * p.N,
+         launch_forces(c->stream, p, n, c->atoms.as<double>(), ep ? &ap : nullptr, c->phi_last.as<double>(),
+                       c->gbuf.as<double>(), c->S.as<double>(), c->Hz.as<double>(), c->fpart.as<double>(), outd));
     DWP_HIP(hipMemcpyAsync(out, outd, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c->stream));
     sync(c);
 }
@@ -727,7 +801,7 @@ int dwp_build_rho(dwp_ctx *c, int n, const double *xyz, const double *q, const d
     if (!q || !sigma || !rho_dev) dwp::fail(DWP_EINVAL, "q, sigma and rho_dev must not be NULL");
     DWP_HIP(hipSetDevice(c->device));
     dwp::upload_atoms(c, n, xyz, nullptr, q, sigma, nullptr);
-    dwp::launch_build_rho(c->stream, c->plan, n, c->atoms.as<double>(), rho_dev);
+    PROF(c, dwp::PG_BUILD, 8.0 * c->plan.N, dwp::launch_build_rho(c->stream, c->plan, n, c->atoms.as<double>(), rho_dev));
     ABI_END(c)
 }
 
@@ -793,6 +867,28 @@ int dwp_energy(dwp_ctx *c, const double *rho, const double *phi, double *e) {
     dwp::to_host(c, coef + 403, 1);
     const dwp::Plan &p = c->plan;
     *e = 0.5 * p.h[0] * p.h[1] * p.h[2] * c->host[0];
+    ABI_END(c)
+}
+
+int dwp_profile_count(void) { return dwp::PG_COUNT; }
+
+int dwp_profile_get(dwp_ctx *c, int g, const char **name, double *ms, long *launches, double *bytes) {
+    ABI_BEGIN(c)
+    if (g < 0 || g >= dwp::PG_COUNT) dwp::fail(DWP_EINVAL, "no such profile group");
+    DWP_HIP(hipSetDevice(c->device));
+    dwp::sync(c);
+    if (name) *name = dwp::prof_group_name(g);
+    if (ms) *ms = c->prof.ms[g];
+    if (launches) *launches = c->prof.launches[g];
+    if (bytes) *bytes = c->prof.bytes[g];
+    ABI_END(c)
+}
+
+int dwp_profile_reset(dwp_ctx *c) {
+    ABI_BEGIN(c)
+    DWP_HIP(hipSetDevice(c->device));
+    dwp::sync(c);
+    c->prof.reset();
     ABI_END(c)
 }
 

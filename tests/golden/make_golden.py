@@ -1,0 +1,80 @@
+"""Write the oracle's reference results for the full-size workloads.
+
+Calls only the FP64 oracle (and the seeded input generators).  Output: one
+JSON file per workload in this directory, holding the energy in both forms,
+the oracle's PCG iteration counts, phi and dE/d eps at 64 seeded nodes, the
+mean of phi^2, and dE/dR of every atom (atom-built permittivities only).
+
+Usage: python tests/golden/make_golden.py [name ...]
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle as O  # noqa: E402
+from paper_0904_4887_amd import workloads as W  # noqa: E402
+
+
+def workloads():
+    return {
+        "tanh_box_32x32x64": W.tanh_box(),
+        "slab_96x96x192": W.slab((96, 96, 192)),
+        "slab_96x96x192_excl": W.slab((96, 96, 192), exclusion=True),
+        "slab_128x128x256": W.slab((128, 128, 256), tol=1e-12),
+        "slab_192x192x384": W.slab((192, 192, 384), tol=1e-8, precision=1),
+        "slab_192x192x384_excl": W.slab((192, 192, 384), exclusion=True, tol=1e-8, precision=1),
+        "big_slab_256x256x512": W.big_slab(),
+    }
+
+
+def first_below(history, tol):
+    for i, r in enumerate(history):
+        if r <= tol:
+            return i + 1
+    return None
+
+
+def make(name, w):
+    t0 = time.time()
+    if w.eps_kind == "tanh_z":
+        eps = w.eps_grid()
+        params = None
+    else:
+        eps = O.eps_erf(w.n, w.L, w.xyz, w.radius, w.eps_params)
+        params = w.eps_params
+    rho = O.rho_gauss(w.n, w.L, w.xyz, w.q, w.sigma)
+    t1 = time.time()
+    phi, info = O.solve(rho, eps, w.h, tol=1e-13, max_iter=3000, return_info=True)
+    t2 = time.time()
+    E = O.energy(rho, phi, w.h)
+    Ee = O.energy_eps_form(phi, eps, w.h)
+    g = O.eps_gradient(phi, w.h)
+    rng = np.random.default_rng(12345)
+    nodes = np.sort(rng.choice(w.N, size=64, replace=False))
+    out = dict(name=name, n=list(w.n), L=list(w.L), energy=E, energy_eps_form=Ee,
+               oracle_iters=info["iters"], oracle_rel_res=info["rel_res"],
+               oracle_iters_to=dict((f"{t:.0e}", first_below(info["history"], t)) for t in (1e-8, 1e-10, 1e-12)),
+               nodes=nodes.tolist(), phi=phi.ravel()[nodes].tolist(), g=g.ravel()[nodes].tolist(),
+               phi2_mean=float(np.mean(phi * phi)), t_build_s=t1 - t0, t_solve_s=t2 - t1)
+    del g
+    if params is not None:
+        t3 = time.time()
+        F = O.forces(w.n, w.L, w.xyz, w.radius, w.q, w.sigma, params, phi, O.eps_gradient(phi, w.h))
+        out["forces"] = F.tolist()
+        out["t_forces_s"] = time.time() - t3
+    with open(os.path.join(HERE, f"oracle_{name}.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print(name, "E", E, "iters", info["iters"], "solve s", round(t2 - t1, 1), flush=True)
+
+
+if __name__ == "__main__":
+    ws = workloads()
+    names = sys.argv[1:] or list(ws)
+    for nm in names:
+        make(nm, ws[nm])
