@@ -80,6 +80,10 @@ typedef struct {
     int warm_start;        /* 1: phi_dev holds the initial guess on entry      */
     int profile;           /* 1: time kernel groups with HIP events on the     */
                            /* context stream (see dwp_profile)                 */
+    int smoother;          /* red-black Gauss-Seidel on the large levels:      */
+                           /* 1 = one fused pass per sweep (out of place),     */
+                           /* 0 = one launch per colour (in place); the two    */
+                           /* give the same sweep up to rounding               */
 } dwp_opts;
 
 /* Per-solve report. */
@@ -87,6 +91,7 @@ typedef struct {
     int outer_iters;         /* Krylov iterations = applications of the split  */
     int vcycles;             /* V-cycles run                                   */
     int restarts;            /* FGMRES cycles                                  */
+    int reorth;              /* second Gram-Schmidt rounds that were needed    */
     int k_w0, k_w1;          /* wet planes actually used: [k_w0, k_w1) mod nz  */
     int n_levels;            /* multigrid levels on W                          */
     double rel_res;          /* final ||b - A phi||_2 / ||b||_2 (true residual)*/
@@ -116,7 +121,8 @@ typedef struct {
 } dwp_eps_params;
 
 /* Defaults: FP64, W = [0.35 Lz, Lz), V(2,2), 64 coarse sweeps, 1 cycle,
- * tol 1e-10, 600 iterations, restart 30, cold start. */
+ * unscaled dry update, tol 1e-10, 600 iterations, restart 10, cold start,
+ * profiling off, fused sweeps. */
 void dwp_default_opts(dwp_opts *opts);
 
 /* Create a context on HIP device `device`; `hip_stream` is a hipStream_t (or

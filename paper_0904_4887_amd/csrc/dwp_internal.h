@@ -57,6 +57,7 @@ struct Level {
     size_t plane = 0;             // nx * ny
     DevBuf eps;                   // (nw + 2) planes, T
     DevBuf u;                     // (nw + 2) planes, T, ghost planes zero
+    DevBuf u2;                    // second copy for out-of-place sweeps
     DevBuf f;                     // nw planes, T
     DevBuf r;                     // nw planes, T (residual scratch)
     size_t n_interior() const { return plane * (size_t)nw; }
@@ -72,6 +73,7 @@ struct Plan {
     int k_w0 = 0, k_w1 = 0;       // wet planes [k_w0, k_w1) mod nz
     int nw = 0;                   // k_w1 - k_w0
     std::vector<Level *> levels;  // levels[0] is the fine slab
+    size_t bottom = 0;            // first level handled by the single-workgroup kernel
 };
 
 // Radix plan of one FFT axis.
@@ -84,13 +86,18 @@ struct FFTAxis {
 
 // Kernel groups timed when profiling is on.
 enum ProfGroup {
-    PG_FFT = 0,        // one dry update: the five FFT passes
+    PG_FFT_X = 0,      // x passes of the dry update (R2C / C2R of two rows at once)
+    PG_FFT_Y,          // y passes
+    PG_FFT_Z,          // z pass with the Green's-function multiply
     PG_RBGS_FINE,      // one colour pass of red-black Gauss-Seidel on the fine slab
     PG_RBGS_COARSE,    // colour passes on the coarser levels
-    PG_MG_OTHER,       // residuals, transfers, coarsest solve
+    PG_MG_OTHER,       // residuals and transfers of the large levels
+    PG_MG_BOTTOM,      // the single-workgroup bottom of the V-cycle
     PG_APPLY,          // full-box operator / residual
     PG_WET,            // wet-slab residual extraction and combination
-    PG_KRYLOV,         // Gram-Schmidt dots and updates, norms
+    PG_MULTIDOT,       // Gram-Schmidt projections (V^T w, with ||w||^2)
+    PG_AXPY,           // Gram-Schmidt updates w -= V h and x += Z y
+    PG_VEC,            // other vector kernels (scaling, norms)
     PG_BUILD,          // eps and rho builders
     PG_FORCES,         // adjoint and forces
     PG_COUNT
@@ -142,6 +149,7 @@ struct dwp_ctx {
     size_t host_len = 0;
     dwp::Profiler prof;
     double mean_rho = 0.0;
+    int reorth = 0;               // second Gram-Schmidt rounds in the last solve
     // atom bookkeeping of the last build_epsilon
     int eps_natoms = -1;
     bool eps_exclusion = false;
@@ -194,20 +202,31 @@ template <class T>
 void launch_coarsen_eps(hipStream_t s, const Level &F, const Level &C);
 template <class T>
 void launch_zero(hipStream_t s, T *x, size_t n);
+// One red-black sweep (first_color, then the other) from uin to uout in a
+// single pass; uin, uout: ghosted arrays of level L (ghost planes zero).
+template <class T>
+void launch_sweep_fused(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color);
+// The rest of a V-cycle from level l0 down, in one single-workgroup kernel.
+template <class T>
+void launch_vcycle_bottom(hipStream_t s, const std::vector<Level *> &levels, size_t l0, int pre, int post,
+                          int coarse_sweeps);
+constexpr size_t BOTTOM_MAX_POINTS = 8192;     // levels this small (and below) go to the bottom kernel
+constexpr size_t FUSED_MIN_POINTS = 1u << 20;  // levels this large use the fused sweep
 
 // kern_fft.hip
 void fft_plan_axis(FFTAxis &ax, int n, double h, bool half);
 // out = s .* L^{-1} (s .* r) (s == nullptr: unscaled), zero mean
 void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay,
                          const FFTAxis &az, const double *r, const double *sinv, double2 *cbuf,
-                         double *out);
+                         double *out, Profiler *prof);
 
 // kern_blas.hip: deterministic reductions
 void launch_dot(hipStream_t s, const double *x, const double *y, size_t n, double *partial,
                 double *out);
 void launch_sum(hipStream_t s, const double *x, size_t n, double *partial, double *out);
+// out[i] = V_i . w (i < nv); if norm_out: *norm_out = w . w (same pass)
 void launch_multidot(hipStream_t s, const double *V, size_t ldv, int nv, const double *w,
-                     size_t n, double *partial, double *out);
+                     size_t n, double *partial, double *out, double *norm_out);
 // w -= sum_i c[i] V_i ; if norm_out: *norm_out = ||w||^2
 void launch_axpy_multi(hipStream_t s, double *w, const double *V, size_t ldv, int nv,
                        const double *c, size_t n, double sign, double *partial, double *norm_out);

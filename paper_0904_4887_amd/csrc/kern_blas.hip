@@ -11,7 +11,9 @@ namespace dwp {
 
 namespace {
 
-constexpr int MD_GROUP = 8;  // dot products per pass of multidot
+constexpr int MD_GROUP = 8;   // dot products per pass of multidot
+constexpr int MD_STRIDE = 72; // partial slots per block: 64 dots + the norm
+constexpr int NORM_SLOT = 64;
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -59,15 +61,19 @@ __device__ __forceinline__ DD wave_dd(DD v) {
     return v;
 }
 
+// partial[b * stride + v0 + q] = sum over block b of V_{v0+q} . w  (q < nv);
+// with_norm: partial[b * stride + NORM_SLOT] = sum over block b of w . w
 __global__ void __launch_bounds__(RED_THREADS)
 k_multidot(const double *__restrict__ V, size_t ldv, int v0, int nv, const double *__restrict__ w, size_t n,
-           double *__restrict__ partial, int stride) {
+           double *__restrict__ partial, int stride, int with_norm) {
     __shared__ double sh[RED_THREADS / 64];
     double acc[MD_GROUP];
+    double accn = 0.0;
 #pragma unroll
     for (int q = 0; q < MD_GROUP; ++q) acc[q] = 0.0;
     for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n; t += (size_t)gridDim.x * RED_THREADS) {
         const double wt = w[t];
+        accn += wt * wt;
 #pragma unroll
         for (int q = 0; q < MD_GROUP; ++q)
             if (q < nv) acc[q] += V[(size_t)(v0 + q) * ldv + t] * wt;
@@ -78,6 +84,10 @@ k_multidot(const double *__restrict__ V, size_t ldv, int v0, int nv, const doubl
             const double r = block_sum(acc[q], sh);
             if (threadIdx.x == 0) partial[(size_t)blockIdx.x * stride + v0 + q] = r;
         }
+    }
+    if (with_norm) {
+        const double r = block_sum(accn, sh);
+        if (threadIdx.x == 0) partial[(size_t)blockIdx.x * stride + NORM_SLOT] = r;
     }
 }
 
@@ -186,18 +196,24 @@ k_energy_final(const double *__restrict__ partial, int nblocks, double *__restri
 }  // namespace
 
 void launch_multidot(hipStream_t s, const double *V, size_t ldv, int nv, const double *w, size_t n,
-                     double *partial, double *out) {
+                     double *partial, double *out, double *norm_out) {
+    if (nv > 64) fail(DWP_EINVAL, "multidot: at most 64 vectors");
     for (int v0 = 0; v0 < nv; v0 += MD_GROUP) {
         const int g = nv - v0 < MD_GROUP ? nv - v0 : MD_GROUP;
-        k_multidot<<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, v0, g, w, n, partial, 64);
+        k_multidot<<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, v0, g, w, n, partial, MD_STRIDE,
+                                                      (v0 == 0 && norm_out) ? 1 : 0);
         DWP_LAUNCH_CHECK();
     }
-    k_reduce_partials<<<nv, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, 64, out);
+    k_reduce_partials<<<nv, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, MD_STRIDE, out);
     DWP_LAUNCH_CHECK();
+    if (norm_out) {
+        k_reduce_partials<<<1, RED_THREADS, 0, s>>>(partial + NORM_SLOT, RED_BLOCKS, MD_STRIDE, norm_out);
+        DWP_LAUNCH_CHECK();
+    }
 }
 
 void launch_dot(hipStream_t s, const double *x, const double *y, size_t n, double *partial, double *out) {
-    launch_multidot(s, x, n, 1, y, n, partial, out);
+    launch_multidot(s, x, n, 1, y, n, partial, out, nullptr);
 }
 
 void launch_sum(hipStream_t s, const double *x, size_t n, double *partial, double *out) {

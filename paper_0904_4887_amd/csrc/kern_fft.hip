@@ -12,7 +12,7 @@
 //   z  : forward along z, multiply by -1/(N lambda), inverse along z
 //   y  : inverse
 //   x  : inverse of two rows at once (C2R)
-// Each 1-D transform is a Stockham autosort FFT with radix-4, -3 and -2
+// Each 1-D transform is a Stockham autosort FFT with radix-8, -4, -3 and -2
 // stages; a stage reads its inputs into registers, synchronises, and writes
 // its outputs back in place.
 #include "dwp_internal.h"
@@ -70,6 +70,28 @@ template <> __device__ __forceinline__ void dft<3>(double2 *x, bool inv) {
     x[2] = csub(t2, rd);
 }
 
+template <> __device__ __forceinline__ void dft<8>(double2 *x, bool inv) {
+    // two radix-4 transforms of the even and odd inputs, then one radix-2 layer
+    // with the eighth roots of unity w8^k = exp(-+i pi k / 4)
+    double2 ev[4] = {x[0], x[2], x[4], x[6]}, od[4] = {x[1], x[3], x[5], x[7]};
+    dft<4>(ev, inv);
+    dft<4>(od, inv);
+    const double c = 0.70710678118654752440;
+    const double2 t1 = inv ? make_double2(c * (od[1].x - od[1].y), c * (od[1].x + od[1].y))
+                           : make_double2(c * (od[1].x + od[1].y), c * (od[1].y - od[1].x));
+    const double2 t2 = rot(od[2], inv);
+    const double2 t3 = inv ? make_double2(-c * (od[3].x + od[3].y), c * (od[3].x - od[3].y))
+                           : make_double2(c * (od[3].y - od[3].x), -c * (od[3].x + od[3].y));
+    x[0] = cadd(ev[0], od[0]);
+    x[4] = csub(ev[0], od[0]);
+    x[1] = cadd(ev[1], t1);
+    x[5] = csub(ev[1], t1);
+    x[2] = cadd(ev[2], t2);
+    x[6] = csub(ev[2], t2);
+    x[3] = cadd(ev[3], t3);
+    x[7] = csub(ev[3], t3);
+}
+
 // One Stockham stage of radix R on B lines of length n held in LDS; element
 // t of line l sits at buf[l * ls + t * es].  p = product of the radices of
 // the earlier stages.  Butterfly i of a line reads x_q = buf[i + q n/R],
@@ -121,7 +143,8 @@ __device__ void fft_lines(double2 *buf, const Radices &rd, int B, int es, int ls
     int p = 1;
     for (int s = 0; s < rd.nst; ++s) {
         const int R = rd.r[s];
-        if (R == 4) stage<4>(buf, rd.n, p, B, es, ls, tw, inv);
+        if (R == 8) stage<8>(buf, rd.n, p, B, es, ls, tw, inv);
+        else if (R == 4) stage<4>(buf, rd.n, p, B, es, ls, tw, inv);
         else if (R == 3) stage<3>(buf, rd.n, p, B, es, ls, tw, inv);
         else stage<2>(buf, rd.n, p, B, es, ls, tw, inv);
         p *= R;
@@ -288,6 +311,7 @@ void fft_plan_axis(FFTAxis &ax, int n, double h, bool half) {
     ax.radices.clear();
     int m = n;
     while (m % 3 == 0) { ax.radices.push_back(3); m /= 3; }
+    while (m % 8 == 0) { ax.radices.push_back(8); m /= 8; }
     while (m % 4 == 0) { ax.radices.push_back(4); m /= 4; }
     while (m % 2 == 0) { ax.radices.push_back(2); m /= 2; }
     if (m != 1 || (int)ax.radices.size() > MAX_STAGES) fail(DWP_EINVAL, "grid size must be 2^a 3^b");
@@ -311,27 +335,44 @@ void fft_plan_axis(FFTAxis &ax, int n, double h, bool half) {
 
 void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay,
                          const FFTAxis &az, const double *r, const double *sinv, double2 *cbuf,
-                         double *out) {
+                         double *out, Profiler *prof) {
+    // algorithmic bytes of each pass: the real grid (8 B / point, twice when
+    // scaled) and the half-spectrum (16 B / complex value) read and written once
+    const double C = (double)p.nkx * p.ny * p.nz;
+    const double bx = (sinv ? 16.0 : 8.0) * p.N + 16.0 * C;
+    auto pb = [&]() { return prof ? prof->begin(st) : -1; };
+    auto pe = [&](int ev, int g, double b) { if (prof) prof->end(st, ev, g, b); };
+    int ev;
     const int nrows = p.ny * p.nz;
     const int Bx = tile_lines(p.nx, 2048);
     const int gx = (nrows + 2 * Bx - 1) / (2 * Bx);
     const size_t ldsx = sizeof(double2) * Bx * (p.nx + 1);
+    ev = pb();
     k_fft_x_fwd<<<gx, FFT_THREADS, ldsx, st>>>(r, sinv, cbuf, radices_of(ax), ax.tw.as<double2>(), Bx, nrows, p.nkx);
     DWP_LAUNCH_CHECK();
+    pe(ev, PG_FFT_X, bx);
     const int By = tile_lines(p.ny, 4096);
     dim3 gy((p.nkx + By - 1) / By, p.nz);
+    ev = pb();
     k_fft_y<<<gy, FFT_THREADS, sizeof(double2) * By * p.ny, st>>>(cbuf, radices_of(ay), ay.tw.as<double2>(), By, p.nkx, 0);
     DWP_LAUNCH_CHECK();
+    pe(ev, PG_FFT_Y, 32.0 * C);
     const int Bz = tile_lines(p.nz, 4096);
     dim3 gz((p.nkx + Bz - 1) / Bz, p.ny);
+    ev = pb();
     k_fft_z_green<<<gz, FFT_THREADS, sizeof(double2) * Bz * p.nz, st>>>(
         cbuf, radices_of(az), az.tw.as<double2>(), Bz, p.nkx, p.ny, ax.lam.as<double>(), ay.lam.as<double>(),
         az.lam.as<double>(), 1.0 / (double)p.N);
     DWP_LAUNCH_CHECK();
+    pe(ev, PG_FFT_Z, 32.0 * C);
+    ev = pb();
     k_fft_y<<<gy, FFT_THREADS, sizeof(double2) * By * p.ny, st>>>(cbuf, radices_of(ay), ay.tw.as<double2>(), By, p.nkx, 1);
     DWP_LAUNCH_CHECK();
+    pe(ev, PG_FFT_Y, 32.0 * C);
+    ev = pb();
     k_fft_x_inv<<<gx, FFT_THREADS, ldsx, st>>>(cbuf, sinv, out, radices_of(ax), ax.tw.as<double2>(), Bx, nrows, p.nkx);
     DWP_LAUNCH_CHECK();
+    pe(ev, PG_FFT_X, bx);
 }
 
 }  // namespace dwp

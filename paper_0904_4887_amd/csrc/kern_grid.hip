@@ -42,6 +42,74 @@ k_apply_full(const double *__restrict__ phi, const double *__restrict__ eps,
     out[c] = residual ? b[c] - acc : acc;
 }
 
+// z-marching form of the same operator: a thread owns one (i, j) column for
+// ZM consecutive planes and keeps phi and eps of planes k-1, k, k+1 in
+// registers, so each point loads its centre values once and its four in-plane
+// neighbours through the cache.  Blocks are renumbered so that each of the 8
+// XCDs (the hardware deals blocks round-robin over them) works on a
+// contiguous range of tiles, i.e. of planes, keeping neighbour planes in its
+// own L2.  mode 0: out = A phi; 1: out = b - A phi; 2: outW[kk] = b - A phi at
+// box plane (k_w0 + kk) mod nz for kk < nplanes (b = v, output of type T).
+constexpr int ZM = 8;
+
+__device__ __forceinline__ int xcd_tile(int nb_real) {
+    const int per = gridDim.x / 8;  // the grid is padded to a multiple of 8
+    return (blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+
+template <class T, int MODE>
+__global__ void __launch_bounds__(BX *BY)
+k_apply_zmarch(const double *__restrict__ phi, const double *__restrict__ eps, const double *__restrict__ b,
+               T *__restrict__ out, int nx, int ny, int nz, double cx, double cy, double cz, int k_w0,
+               int nplanes, int tiles_x, int tiles_y, int nb_real) {
+    const int t = xcd_tile(nb_real);
+    if (t >= nb_real) return;
+    const int tx = t % tiles_x, ty = (t / tiles_x) % tiles_y, tz = t / (tiles_x * tiles_y);
+    const int i = tx * BX + threadIdx.x, j = ty * BY + threadIdx.y;
+    if (i >= nx || j >= ny) return;
+    const size_t plane = (size_t)nx * ny;
+    const size_t col = (size_t)j * nx + i;
+    const int ixp = wrap_p(i, nx) - i, ixm = wrap_m(i, nx) - i;
+    const long jyp = (long)(wrap_p(j, ny) - j) * nx, jym = (long)(wrap_m(j, ny) - j) * nx;
+    const int kk0 = tz * ZM, kk1 = min(nplanes, kk0 + ZM);
+    auto boxk = [&](int kk) { return MODE == 2 ? (k_w0 + kk) % nz : kk; };
+    // Software pipeline: the centre values of plane k+1 and the in-plane
+    // neighbours of plane k are loaded one plane ahead of their use.
+    int k = boxk(kk0);
+    size_t c = (size_t)k * plane + col;
+    const size_t cm0 = (size_t)wrap_m(k, nz) * plane + col;
+    double pm = phi[cm0], em = eps[cm0], p0 = phi[c], e0 = eps[c];
+    double nb[8];
+    auto load_nb = [&](size_t cc, double *o) {
+        o[0] = phi[cc + ixp]; o[1] = eps[cc + ixp]; o[2] = phi[cc + ixm]; o[3] = eps[cc + ixm];
+        o[4] = phi[cc + jyp]; o[5] = eps[cc + jyp]; o[6] = phi[cc + jym]; o[7] = eps[cc + jym];
+    };
+    load_nb(c, nb);
+    int kp = wrap_p(k, nz);
+    size_t cp = (size_t)kp * plane + col;
+    double pp = phi[cp], ep = eps[cp];
+    for (int kk = kk0; kk < kk1; ++kk) {
+        // prefetch for plane kk + 1 (clamped inside the chunk: always a valid address)
+        const bool more = kk + 1 < kk1;
+        const int kn = wrap_p(kp, nz);
+        const size_t cn = (size_t)(more ? kn : kp) * plane + col;
+        double nb2[8];
+        load_nb(cp, nb2);
+        const double pq = phi[cn], eq = eps[cn];
+        double acc = cx * ((e0 + nb[1]) * (nb[0] - p0) + (e0 + nb[3]) * (nb[2] - p0)) +
+                     cy * ((e0 + nb[5]) * (nb[4] - p0) + (e0 + nb[7]) * (nb[6] - p0)) +
+                     cz * ((e0 + ep) * (pp - p0) + (e0 + em) * (pm - p0));
+        acc *= 0.5;
+        if (MODE == 0) out[c] = (T)acc;
+        else if (MODE == 1) out[c] = (T)(b[c] - acc);
+        else out[(size_t)kk * plane + col] = (T)(b[c] - acc);
+        pm = p0; em = e0; p0 = pp; e0 = ep; pp = pq; ep = eq;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) nb[q] = nb2[q];
+        k = kp; c = cp; kp = kn; cp = cn;
+    }
+}
+
 // dE/d eps_n = -(h^3 / 8 pi) sum_d 1/2 [(D+ phi)^2 + (D- phi)^2]
 __global__ void __launch_bounds__(BX *BY)
 k_eps_gradient(const double *__restrict__ phi, double *__restrict__ g, int nx, int ny, int nz,
@@ -370,6 +438,306 @@ __global__ void k_coarsen_eps(const T *__restrict__ ef, T *__restrict__ ec, int 
     }
 }
 
+// ---------------------------------------------------------------- fused sweep
+// One full red-black sweep in a single pass over HBM, out of place:
+// u_out = sweep(u_in).  The first colour c0 is updated from u_in (its
+// neighbours all have the other colour), the second colour from the new
+// first-colour values.  A block owns a TX x TY tile of (x, y) for a chunk of
+// KC planes and marches up in z with LDS rings: at step m it loads plane m+1
+// of u_in and eps (tile plus a 2-cell halo), computes first-colour values at
+// plane m on the tile plus a 1-cell halo, then second-colour values at plane
+// m-1 on the tile, and writes plane m-1 of u_out.  Halo values are recomputed
+// by each block that needs them (from u_in, which nobody writes), so the
+// result does not depend on block order.  Equals two colour passes in place.
+constexpr int FTX = 32, FTY = 8, FKC = 16;
+constexpr int FHX = FTX + 4, FHY = FTY + 4;  // 2-cell halo
+constexpr int FRX = FTX + 2, FRY = FTY + 2;  // 1-cell halo
+constexpr int FNT = FTX * FTY;               // threads
+constexpr int FNH = (FHX * FHY + FNT - 1) / FNT;  // halo-2 elements per thread
+constexpr int FNR = (FRX * FRY + FNT - 1) / FNT;  // halo-1 elements per thread
+
+template <class T>
+__global__ void __launch_bounds__(FNT)
+k_sweep_fused(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ e, const T *__restrict__ f,
+              LevelArgs a, int c0, int tiles_x, int tiles_y, int nb_real) {
+    // plane buffers padded to a whole number of per-thread elements, so that
+    // every thread stores unconditionally (the padding is never read)
+    __shared__ T su[3][FNH * FNT];
+    __shared__ T se[4][FNH * FNT];
+    __shared__ T sr[3][FRY * FRX];
+    __shared__ T sf[3][FNR * FNT];
+    // XCD-aware order: each XCD gets a contiguous run of tiles (x fastest,
+    // then y, then z chunk), so neighbouring tiles share its L2.
+    const int tile = xcd_tile(nb_real);
+    if (tile >= nb_real) return;
+    const int nx = a.nx, ny = a.ny, nw = a.nw;
+    const size_t plane = (size_t)nx * ny;
+    const int i0 = (tile % tiles_x) * FTX, j0 = ((tile / tiles_x) % tiles_y) * FTY;
+    const int k0 = (tile / (tiles_x * tiles_y)) * FKC, k1 = min(nw, k0 + FKC);
+    const T cx = cxv<T>(a, 0), cy = cxv<T>(a, 1), cz = cxv<T>(a, 2);
+    const int tid = threadIdx.x;
+    const int base_par = (i0 + j0) & 1;  // colour of local (x, y, m) = (base_par + x + y + m) & 1
+    int oh[FNH], orr[FNR];
+    bool vh[FNH], vr[FNR];
+#pragma unroll
+    for (int t = 0; t < FNH; ++t) {
+        const int q = tid + t * FNT;
+        const int x = q % FHX - 2, y = q / FHX - 2;
+        const int i = ((i0 + x) % nx + nx) % nx, j = ((j0 + y) % ny + ny) % ny;
+        oh[t] = j * nx + i;
+        vh[t] = q < FHX * FHY;
+    }
+#pragma unroll
+    for (int t = 0; t < FNR; ++t) {
+        const int q = tid + t * FNT;
+        const int x = q % FRX - 1, y = q / FRX - 1;
+        const int i = ((i0 + x) % nx + nx) % nx, j = ((j0 + y) % ny + ny) % ny;
+        orr[t] = j * nx + i;
+        vr[t] = q < FRX * FRY;
+    }
+    // first-colour work: thread tid < FRX*FRY/2 takes the tid-th first-colour
+    // point of the tile + 1-cell halo (rows of FRX = 34 hold 17 of each colour)
+    const bool red_on = tid < FRX * FRY / 2;
+    const int ry = tid / (FRX / 2) - 1, rt = tid % (FRX / 2);
+    // second-colour work: threads < FTX*FTY/2 compute, the others copy the
+    // first-colour values of the tile to the output
+    const bool blk_on = tid < FTX * FTY / 2;
+    const int q2 = blk_on ? tid : tid - FTX * FTY / 2;
+    const int by = q2 / (FTX / 2), bt = q2 % (FTX / 2);
+
+    T pu[2][FNH], pe[2][FNH], pf[2][FNR];
+    // Loads are unconditional: plane indices are clamped into the ghosted
+    // range, which is harmless because values of planes outside [-1, nw] (f:
+    // outside [0, nw)) are never used.  Keeping the loads free of branches and
+    // selects lets them stay in flight for two steps.
+    auto fetch = [&](int k, T *du, T *de, T *df) {
+        const int kc = min(max(k, -1), nw), kfc = min(max(k, 0), nw - 1);
+        const size_t g = (size_t)(kc + 1) * plane, gf = (size_t)kfc * plane;
+#pragma unroll
+        for (int t = 0; t < FNH; ++t) {
+            du[t] = uin[g + oh[t]];
+            de[t] = e[g + oh[t]];
+        }
+#pragma unroll
+        for (int t = 0; t < FNR; ++t) df[t] = f[gf + orr[t]];
+    };
+    auto stash = [&](int k, const T *du, const T *de, const T *df) {
+        T *lu = su[(k + 3) % 3], *le = se[(k + 4) % 4], *lf = sf[(k + 3) % 3];
+#pragma unroll
+        for (int t = 0; t < FNH; ++t) { lu[tid + t * FNT] = du[t]; le[tid + t * FNT] = de[t]; }
+#pragma unroll
+        for (int t = 0; t < FNR; ++t) lf[tid + t * FNT] = df[t];
+    };
+    auto update = [&](const T *em, const T *ep, const T *en, int h, T uxp, T uxm, T uyp, T uym, T uzp, T uzm,
+                      T fv) {
+        const T e0 = em[h];
+        const T wxp = cx * (e0 + em[h + 1]), wxm = cx * (e0 + em[h - 1]);
+        const T wyp = cy * (e0 + em[h + FHX]), wym = cy * (e0 + em[h - FHX]);
+        const T wzp = cz * (e0 + ep[h]), wzm = cz * (e0 + en[h]);
+        const T off = wxp * uxp + wxm * uxm + wyp * uyp + wym * uym + wzp * uzp + wzm * uzm;
+        const T dg = wxp + wxm + wyp + wym + wzp + wzm;
+        return (T(0.5) * off - fv) / (T(0.5) * dg);
+    };
+    auto step = [&](int m, T *du, T *de, T *df) {
+        __syncthreads();
+        stash(m + 1, du, de, df);  // plane m + 1, fetched two steps ago
+        fetch(m + 3, du, de, df);  // in flight for the next two steps
+        __syncthreads();
+        if (red_on) {  // first colour at plane m on the tile + 1-cell halo
+            const int off = (c0 - base_par - ry - m + 1) & 1;
+            const int x = -1 + 2 * rt + off;
+            const int q = (ry + 1) * FRX + (x + 1), h = (ry + 2) * FHX + (x + 2);
+            T v = T(0);
+            if (m >= 0 && m < nw) {
+                const T *um = su[(m + 3) % 3];
+                v = update(se[(m + 4) % 4], se[(m + 5) % 4], se[(m + 3) % 4], h, um[h + 1], um[h - 1],
+                           um[h + FHX], um[h - FHX], su[(m + 4) % 3][h], su[(m + 2) % 3][h], sf[(m + 3) % 3][q]);
+            }
+            sr[(m + 3) % 3][q] = v;
+            // the other-colour slot of this position pair keeps a defined value
+            sr[(m + 3) % 3][q + (off ? -1 : 1)] = T(0);
+        }
+        __syncthreads();
+        const int k = m - 1;  // second colour at plane k on the tile, write plane k
+        if (k >= k0 && k < k1) {
+            const int c1 = blk_on ? 1 - c0 : c0;
+            const int off = (c1 - base_par - by - k) & 1;
+            const int x = 2 * bt + off;
+            const int i = i0 + x, j = j0 + by;
+            if (i < nx && j < ny) {
+                const int r = (by + 1) * FRX + (x + 1);
+                const T *rm = sr[(k + 3) % 3];
+                T v;
+                if (!blk_on) {
+                    v = rm[r];
+                } else {
+                    const int h = (by + 2) * FHX + (x + 2);
+                    v = update(se[(k + 4) % 4], se[(k + 5) % 4], se[(k + 3) % 4], h, rm[r + 1], rm[r - 1],
+                               rm[r + FRX], rm[r - FRX], sr[(k + 4) % 3][r], sr[(k + 2) % 3][r], sf[(k + 3) % 3][r]);
+                }
+                uout[(size_t)(k + 1) * plane + (size_t)j * nx + i] = v;
+            }
+        }
+    };
+    // k0 is a multiple of the (even) chunk length: step m uses register set (m + 1) & 1
+    fetch(k0 - 2, pu[0], pe[0], pf[0]);
+    stash(k0 - 2, pu[0], pe[0], pf[0]);
+    fetch(k0 - 1, pu[1], pe[1], pf[1]);
+    stash(k0 - 1, pu[1], pe[1], pf[1]);
+    fetch(k0, pu[0], pe[0], pf[0]);
+    fetch(k0 + 1, pu[1], pe[1], pf[1]);
+    // steps m = k0-1 .. k1, padded to an even count (an extra step past k1
+    // only recomputes ring values and writes nothing)
+    const int pairs = (k1 - k0 + 3) / 2;
+    for (int it = 0; it < pairs; ++it) {
+        const int m = k0 - 1 + 2 * it;
+        step(m, pu[0], pe[0], pf[0]);
+        step(m + 1, pu[1], pe[1], pf[1]);
+    }
+}
+
+// ---------------------------------------------------------------- V-cycle bottom
+// Levels small enough for one workgroup run the rest of the V-cycle inside a
+// single kernel (one CU), phases separated by barriers: this replaces a few
+// dozen tiny launches per cycle.
+template <class T>
+struct LevelDesc {
+    T *u, *f, *r;
+    const T *e;
+    LevelArgs a;
+    int zc;
+};
+constexpr int MAX_BOTTOM = 10;
+template <class T>
+struct Bottom {
+    LevelDesc<T> L[MAX_BOTTOM];
+    int nl, pre, post, coarse;
+};
+
+template <class T>
+__device__ void bt_smooth(const LevelDesc<T> &d, int color) {
+    const int half = d.a.nx / 2;
+    const int per = half * d.a.ny * d.a.nw;
+    const size_t plane = (size_t)d.a.nx * d.a.ny;
+    for (int q = threadIdx.x; q < per; q += blockDim.x) {
+        const int t = q % half, j = (q / half) % d.a.ny, kk = q / (half * d.a.ny);
+        const int i = 2 * t + ((j + kk + color) & 1);
+        const size_t li = (size_t)kk * plane + (size_t)j * d.a.nx + i;
+        T off, diag;
+        level_sums(d.u, d.e, d.a, i, j, li + plane, off, diag);
+        d.u[li + plane] = (off - d.f[li]) / diag;
+    }
+    __syncthreads();
+}
+
+template <class T>
+__device__ void bt_residual(const LevelDesc<T> &d) {
+    const size_t plane = (size_t)d.a.nx * d.a.ny;
+    const int n = (int)(plane * d.a.nw);
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        const int i = q % d.a.nx, j = (q / d.a.nx) % d.a.ny;
+        T off, diag;
+        level_sums(d.u, d.e, d.a, i, j, (size_t)q + plane, off, diag);
+        d.r[q] = d.f[q] - (off - diag * d.u[q + plane]);
+    }
+    __syncthreads();
+}
+
+template <class T>
+__device__ void bt_restrict_zero(const LevelDesc<T> &F, const LevelDesc<T> &C) {
+    const T w3[3] = {T(0.25), T(0.5), T(0.25)};
+    const int nxf = F.a.nx, nyf = F.a.ny, nxc = C.a.nx, nyc = C.a.ny;
+    const size_t planef = (size_t)nxf * nyf, planec = (size_t)nxc * nyc;
+    const int n = (int)(planec * C.a.nw);
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        const int ic = q % nxc, jc = (q / nxc) % nyc, kc = q / (int)planec;
+        T acc = T(0);
+        const int nzt = C.zc ? 3 : 1;
+        for (int dz = 0; dz < nzt; ++dz) {
+            const int kf = C.zc ? 2 * kc + dz : kc;
+            const T wz = C.zc ? w3[dz] : T(1);
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int jf = (2 * jc + dy + nyf) % nyf;
+                const size_t rb = (size_t)kf * planef + (size_t)jf * nxf;
+                const int i0 = 2 * ic;
+                const T sx = T(0.25) * F.r[rb + (i0 == 0 ? nxf - 1 : i0 - 1)] + T(0.5) * F.r[rb + i0] +
+                             T(0.25) * F.r[rb + (i0 + 1 == nxf ? 0 : i0 + 1)];
+                acc += wz * w3[dy + 1] * sx;
+            }
+        }
+        C.f[q] = acc;
+    }
+    const int ng = (int)(planec * (C.a.nw + 2));
+    for (int q = threadIdx.x; q < ng; q += blockDim.x) C.u[q] = T(0);
+    __syncthreads();
+}
+
+template <class T>
+__device__ void bt_prolong(const LevelDesc<T> &F, const LevelDesc<T> &C) {
+    const int nxf = F.a.nx, nyf = F.a.ny, nxc = C.a.nx, nyc = C.a.ny;
+    const size_t planef = (size_t)nxf * nyf, planec = (size_t)nxc * nyc;
+    const int n = (int)(planef * F.a.nw);
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        const int i = q % nxf, j = (q / nxf) % nyf, kf = q / (int)planef;
+        int ix[2], jy[2], pz[2];
+        T wx[2], wyv[2], wz[2];
+        int nxs, nys, nzs;
+        if (i & 1) { ix[0] = i >> 1; ix[1] = (ix[0] + 1 == nxc) ? 0 : ix[0] + 1; wx[0] = wx[1] = T(0.5); nxs = 2; }
+        else { ix[0] = i >> 1; wx[0] = T(1); nxs = 1; }
+        if (j & 1) { jy[0] = j >> 1; jy[1] = (jy[0] + 1 == nyc) ? 0 : jy[0] + 1; wyv[0] = wyv[1] = T(0.5); nys = 2; }
+        else { jy[0] = j >> 1; wyv[0] = T(1); nys = 1; }
+        if (C.zc) {
+            if (kf & 1) { pz[0] = (kf - 1) / 2 + 1; wz[0] = T(1); nzs = 1; }
+            else { pz[0] = kf / 2; pz[1] = kf / 2 + 1; wz[0] = wz[1] = T(0.5); nzs = 2; }
+        } else { pz[0] = kf + 1; wz[0] = T(1); nzs = 1; }
+        T acc = T(0);
+        for (int a = 0; a < nzs; ++a)
+            for (int b = 0; b < nys; ++b)
+                for (int c = 0; c < nxs; ++c)
+                    acc += wz[a] * wyv[b] * wx[c] * C.u[(size_t)pz[a] * planec + (size_t)jy[b] * nxc + ix[c]];
+        F.u[q + planef] += acc;
+    }
+    __syncthreads();
+}
+
+constexpr int BOTTOM_LDS = 2048;  // coarsest level staged in LDS when its ghosted size fits
+
+// V-cycle over levels L[0..nl-1] of the bottom set; L[0].f is given and
+// L[0].u holds the initial guess.  The coarsest level's sweeps run out of LDS
+// when it is small enough.
+template <class T>
+__global__ void __launch_bounds__(1024) k_vcycle_bottom(Bottom<T> B) {
+    __shared__ T lu[BOTTOM_LDS], lf[BOTTOM_LDS], le[BOTTOM_LDS];
+    for (int l = 0; l + 1 < B.nl; ++l) {
+        for (int k = 0; k < B.pre; ++k) { bt_smooth(B.L[l], 0); bt_smooth(B.L[l], 1); }
+        bt_residual(B.L[l]);
+        bt_restrict_zero(B.L[l], B.L[l + 1]);
+    }
+    {
+        const LevelDesc<T> &c = B.L[B.nl - 1];
+        const int plane = c.a.nx * c.a.ny;
+        const int ng = plane * (c.a.nw + 2), ni = plane * c.a.nw;
+        if (ng <= BOTTOM_LDS) {
+            for (int q = threadIdx.x; q < ng; q += blockDim.x) { lu[q] = c.u[q]; le[q] = c.e[q]; }
+            for (int q = threadIdx.x; q < ni; q += blockDim.x) lf[q] = c.f[q];
+            __syncthreads();
+            LevelDesc<T> d = c;
+            d.u = lu;
+            d.f = lf;
+            d.e = le;
+            for (int k = 0; k < B.coarse; ++k) { bt_smooth(d, 0); bt_smooth(d, 1); }
+            for (int q = threadIdx.x; q < ng; q += blockDim.x) c.u[q] = lu[q];
+            __syncthreads();
+        } else {
+            for (int k = 0; k < B.coarse; ++k) { bt_smooth(c, 0); bt_smooth(c, 1); }
+        }
+    }
+    for (int l = B.nl - 2; l >= 0; --l) {
+        bt_prolong(B.L[l], B.L[l + 1]);
+        for (int k = 0; k < B.post; ++k) { bt_smooth(B.L[l], 1); bt_smooth(B.L[l], 0); }
+    }
+}
+
 inline int grid1d(size_t n, int threads = 256) {
     size_t b = (n + threads - 1) / threads;
     if (b > 16384) b = 16384;
@@ -390,12 +758,22 @@ LevelArgs level_args(const Level &L) {
 }  // namespace
 
 // ============================================================== launchers
+template <class T, int MODE>
+void launch_zmarch(hipStream_t s, const Plan &p, const double *phi, const double *eps, const double *b, T *out,
+                   int nplanes) {
+    const int tx = (p.nx + BX - 1) / BX, ty = (p.ny + BY - 1) / BY, tz = (nplanes + ZM - 1) / ZM;
+    const int nb = tx * ty * tz;
+    const int padded = (nb + 7) / 8 * 8;
+    k_apply_zmarch<T, MODE><<<padded, dim3(BX, BY), 0, s>>>(phi, eps, b, out, p.nx, p.ny, p.nz, 1.0 / (p.h[0] * p.h[0]),
+                                                            1.0 / (p.h[1] * p.h[1]), 1.0 / (p.h[2] * p.h[2]), p.k_w0,
+                                                            nplanes, tx, ty, nb);
+    DWP_LAUNCH_CHECK();
+}
+
 void launch_apply_full(hipStream_t s, const Plan &p, const double *phi, const double *eps,
                        const double *b, double *out, bool residual) {
-    dim3 g((p.nx + BX - 1) / BX, (p.ny + BY - 1) / BY, p.nz), blk(BX, BY);
-    k_apply_full<<<g, blk, 0, s>>>(phi, eps, b, out, p.nx, p.ny, p.nz, 1.0 / (p.h[0] * p.h[0]),
-                                   1.0 / (p.h[1] * p.h[1]), 1.0 / (p.h[2] * p.h[2]), residual ? 1 : 0);
-    DWP_LAUNCH_CHECK();
+    if (residual) launch_zmarch<double, 1>(s, p, phi, eps, b, out, p.nz);
+    else launch_zmarch<double, 0>(s, p, phi, eps, b, out, p.nz);
 }
 
 void launch_eps_gradient(hipStream_t s, const Plan &p, const double *phi, double *g) {
@@ -446,10 +824,7 @@ void launch_check_finite(hipStream_t s, const double *x, size_t n, int *flags) {
 template <class T>
 void launch_wet_residual(hipStream_t s, const Plan &p, const double *v, const double *dD,
                          const double *eps, T *fW) {
-    dim3 g((p.nx + BX - 1) / BX, (p.ny + BY - 1) / BY, p.nw), blk(BX, BY);
-    k_wet_residual<T><<<g, blk, 0, s>>>(v, dD, eps, fW, p.nx, p.ny, p.nz, p.k_w0, 1.0 / (p.h[0] * p.h[0]),
-                                        1.0 / (p.h[1] * p.h[1]), 1.0 / (p.h[2] * p.h[2]));
-    DWP_LAUNCH_CHECK();
+    launch_zmarch<T, 2>(s, p, dD, eps, v, fW, p.nw);
 }
 template <class T>
 void launch_wet_add(hipStream_t s, const Plan &p, const T *uW, double *z) {
@@ -504,6 +879,37 @@ void launch_coarsen_eps(hipStream_t s, const Level &F, const Level &C) {
     DWP_LAUNCH_CHECK();
 }
 template <class T>
+void launch_sweep_fused(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color) {
+    LevelArgs a = level_args(L);
+    const int tx = (L.nx + FTX - 1) / FTX, ty = (L.ny + FTY - 1) / FTY, tz = (L.nw + FKC - 1) / FKC;
+    const int nb = tx * ty * tz, padded = (nb + 7) / 8 * 8;
+    k_sweep_fused<T><<<padded, FNT, 0, s>>>(uin, uout, L.eps.as<T>(), L.f.as<T>(), a, first_color, tx, ty, nb);
+    DWP_LAUNCH_CHECK();
+}
+
+template <class T>
+void launch_vcycle_bottom(hipStream_t s, const std::vector<Level *> &levels, size_t l0, int pre, int post,
+                          int coarse_sweeps) {
+    Bottom<T> B{};
+    B.nl = (int)(levels.size() - l0);
+    if (B.nl < 1 || B.nl > MAX_BOTTOM) fail(DWP_EINVAL, "internal: bad bottom level count");
+    for (int l = 0; l < B.nl; ++l) {
+        const Level &L = *levels[l0 + l];
+        B.L[l].u = L.u.as<T>();
+        B.L[l].f = L.f.as<T>();
+        B.L[l].r = L.r.as<T>();
+        B.L[l].e = L.eps.as<T>();
+        B.L[l].a = level_args(L);
+        B.L[l].zc = L.zc ? 1 : 0;
+    }
+    B.pre = pre;
+    B.post = post;
+    B.coarse = coarse_sweeps;
+    k_vcycle_bottom<T><<<1, 1024, 0, s>>>(B);
+    DWP_LAUNCH_CHECK();
+}
+
+template <class T>
 void launch_zero(hipStream_t s, T *x, size_t n) {
     k_zero<T><<<grid1d(n), 256, 0, s>>>(x, n);
     DWP_LAUNCH_CHECK();
@@ -520,7 +926,9 @@ void launch_zero(hipStream_t s, T *x, size_t n) {
     template void launch_restrict<T>(hipStream_t, const Level &, const Level &, const T *, T *);      \
     template void launch_prolong_add<T>(hipStream_t, const Level &, const Level &);                   \
     template void launch_coarsen_eps<T>(hipStream_t, const Level &, const Level &);                   \
-    template void launch_zero<T>(hipStream_t, T *, size_t);
+    template void launch_zero<T>(hipStream_t, T *, size_t);                                          \
+    template void launch_vcycle_bottom<T>(hipStream_t, const std::vector<Level *> &, size_t, int, int, int); \
+    template void launch_sweep_fused<T>(hipStream_t, const Level &, const T *, T *, int);
 DWP_INST(float)
 DWP_INST(double)
 

@@ -43,9 +43,9 @@ void DevBuf::release() {
     bytes = 0;
 }
 
-static const char *const kGroupNames[PG_COUNT] = {"fft_dry_update", "rbgs_fine", "rbgs_coarse", "mg_other",
-                                                  "apply_full",     "wet_slab",  "krylov",      "builders",
-                                                  "forces"};
+static const char *const kGroupNames[PG_COUNT] = {
+    "fft_x", "fft_y", "fft_z", "rbgs_fine", "rbgs_coarse", "mg_other", "mg_bottom", "apply_full",
+    "wet_slab", "multidot", "axpy_multi", "vector", "builders", "forces"};
 
 const char *prof_group_name(int g) { return (g >= 0 && g < PG_COUNT) ? kGroupNames[g] : ""; }
 
@@ -200,14 +200,20 @@ void plan_wet(dwp_ctx *c) {
         L->plane = (size_t)d.nx * d.ny;
         p.levels.push_back(L);
     }
+    // the bottom kernel takes every level from the first one that fits
+    p.bottom = p.levels.size() - 1;
+    while (p.bottom > 0 && p.levels[p.bottom - 1]->n_interior() <= BOTTOM_MAX_POINTS) --p.bottom;
+    if (p.levels.size() - p.bottom > 10) p.bottom = p.levels.size() - 10;
 }
 
 template <class T>
 void alloc_levels(dwp_ctx *c) {
     for (Level *L : c->plan.levels) {
-        L->eps.release(); L->u.release(); L->f.release(); L->r.release();
+        L->eps.release(); L->u.release(); L->u2.release(); L->f.release(); L->r.release();
         L->eps.alloc(tsize<T>() * L->n_ghosted());
         L->u.alloc(tsize<T>() * L->n_ghosted());
+        L->u2.alloc(tsize<T>() * L->n_ghosted());
+        launch_zero<T>(c->stream, L->u2.as<T>(), L->n_ghosted());
         L->f.alloc(tsize<T>() * L->n_interior());
         L->r.alloc(tsize<T>() * L->n_interior());
         launch_zero<T>(c->stream, L->u.as<T>(), L->n_ghosted());
@@ -256,14 +262,23 @@ void vcycle(dwp_ctx *c, size_t l) {
     const double ts = (double)sizeof(T);
     const int sg = l == 0 ? PG_RBGS_FINE : PG_RBGS_COARSE;
     const double pass_bytes = 2.0 * ts * (double)L.n_interior();  // half of read u, eps, f + write u
-    if (l + 1 == p.levels.size()) {
-        PROF(c, PG_MG_OTHER, 4.0 * ts * L.n_interior(), launch_level_coarse_solve<T>(s, L, c->opts.coarse_sweeps));
+    if (l >= p.bottom) {
+        double nb = 0.0;
+        for (size_t q = l; q < p.levels.size(); ++q) nb += (double)p.levels[q]->n_interior();
+        PROF(c, PG_MG_BOTTOM, 4.0 * ts * nb,
+             launch_vcycle_bottom<T>(s, p.levels, l, c->opts.pre, c->opts.post, c->opts.coarse_sweeps));
         return;
     }
-    for (int k = 0; k < c->opts.pre; ++k) {
-        PROF(c, sg, pass_bytes, launch_level_smooth<T>(s, L, 0));
-        PROF(c, sg, pass_bytes, launch_level_smooth<T>(s, L, 1));
-    }
+    auto smooth = [&](int first) {
+        if (c->opts.smoother == 1 && L.n_interior() >= FUSED_MIN_POINTS) {
+            PROF(c, sg, 2.0 * pass_bytes, launch_sweep_fused<T>(s, L, L.u.as<T>(), L.u2.as<T>(), first));
+            std::swap(L.u.p, L.u2.p);
+        } else {
+            PROF(c, sg, pass_bytes, launch_level_smooth<T>(s, L, first));
+            PROF(c, sg, pass_bytes, launch_level_smooth<T>(s, L, 1 - first));
+        }
+    };
+    for (int k = 0; k < c->opts.pre; ++k) smooth(0);
     Level &C = *p.levels[l + 1];
     PROF(c, PG_MG_OTHER, 4.0 * ts * L.n_interior(), launch_level_residual<T>(s, L, L.r.as<T>()));
     PROF(c, PG_MG_OTHER, ts * (L.n_interior() + C.n_interior()),
@@ -271,15 +286,7 @@ void vcycle(dwp_ctx *c, size_t l) {
     PROF(c, PG_MG_OTHER, ts * C.n_ghosted(), launch_zero<T>(s, C.u.as<T>(), C.n_ghosted()));
     vcycle<T>(c, l + 1);
     PROF(c, PG_MG_OTHER, ts * (C.n_interior() + 2.0 * L.n_interior()), launch_prolong_add<T>(s, L, C));
-    for (int k = 0; k < c->opts.post; ++k) {
-        PROF(c, sg, pass_bytes, launch_level_smooth<T>(s, L, 1));
-        PROF(c, sg, pass_bytes, launch_level_smooth<T>(s, L, 0));
-    }
-}
-
-double fft_bytes(const Plan &p, bool scaled) {
-    const double C = (double)p.nkx * p.ny * p.nz;
-    return 16.0 * p.N + 128.0 * C + (scaled ? 16.0 * p.N : 0.0);
+    for (int k = 0; k < c->opts.post; ++k) smooth(1);
 }
 
 template <class T>
@@ -287,9 +294,8 @@ void split_impl(dwp_ctx *c, const double *v, double *z) {
     Plan &p = c->plan;
     hipStream_t s = c->stream;
     const bool scaled = c->opts.scaled_dry != 0;
-    PROF(c, PG_FFT, fft_bytes(p, scaled),
-         launch_vacuum_solve(s, p, c->fx, c->fy, c->fz, v, scaled ? c->sinv.as<double>() : nullptr,
-                             c->cbuf.as<double2>(), z));
+    launch_vacuum_solve(s, p, c->fx, c->fy, c->fz, v, scaled ? c->sinv.as<double>() : nullptr,
+                        c->cbuf.as<double2>(), z, &c->prof);
     Level &F = *p.levels[0];
     const double nW = (double)F.n_interior();
     PROF(c, PG_WET, (24.0 + sizeof(T)) * nW, launch_wet_residual<T>(s, p, v, z, c->eps.as<double>(), F.f.as<T>()));
@@ -314,6 +320,10 @@ void check_finite_dev(dwp_ctx *c, const double *x, const char *what) {
     if (f & 1) fail(DWP_ENONFINITE, std::string(what) + " holds NaN or Inf");
 }
 
+// A second Gram-Schmidt round runs when the projection removed all but this
+// fraction of ||w||^2 (||w'|| < 1e-2 ||w||).
+constexpr double REORTH_ETA2 = 1e-4;
+
 // FGMRES(m) with the split as right preconditioner; x is updated in place.
 // Returns the number of iterations; *rel receives the final true relative
 // residual.
@@ -333,14 +343,14 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
     for (;;) {
         // r = b - A x into V_0
         PROF(c, PG_APPLY, 32.0 * N, launch_apply_full(s, p, x, c->eps.as<double>(), b, V, true));
-        PROF(c, PG_KRYLOV, 8.0 * N, launch_dot(s, V, V, N, part, coef));
+        PROF(c, PG_VEC, 8.0 * N, launch_dot(s, V, V, N, part, coef));
         to_host(c, coef, 1);
         const double beta = std::sqrt(c->host[0]);
         if (!std::isfinite(beta)) fail(DWP_ENONFINITE, "residual is not finite");
         *rel = beta / bnorm;
         if (*rel <= o.tol || iters >= o.max_outer) return iters;
         ++*restarts;
-        PROF(c, PG_KRYLOV, 16.0 * N, launch_axpby(s, V, 1.0 / beta, V, 0.0, N));
+        PROF(c, PG_VEC, 16.0 * N, launch_axpby(s, V, 1.0 / beta, V, 0.0, N));
         std::fill(H.begin(), H.end(), 0.0);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
@@ -349,20 +359,32 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
             double *Vj = V + (size_t)j * N, *Vn = V + (size_t)(j + 1) * N, *Zj = Z + (size_t)j * N;
             apply_split(c, Vj, Zj);
             PROF(c, PG_APPLY, 24.0 * N, launch_apply_full(s, p, Zj, c->eps.as<double>(), nullptr, Vn, false));
-            // classical Gram-Schmidt, twice
+            // classical Gram-Schmidt in one projection pass (which also gives
+            // ||w||^2) and one update pass (which gives ||w'||^2); a second
+            // round runs only on severe cancellation.  The true residual is
+            // recomputed at every restart, so a slightly non-orthogonal basis
+            // can cost iterations but never the accuracy of the result
             const double md = 8.0 * N * (j + 2), ax = 8.0 * N * (j + 3);
-            PROF(c, PG_KRYLOV, md, launch_multidot(s, V, N, j + 1, Vn, N, part, coef));
-            PROF(c, PG_KRYLOV, ax, launch_axpy_multi(s, Vn, V, N, j + 1, coef, N, -1.0, part, nullptr));
-            PROF(c, PG_KRYLOV, md, launch_multidot(s, V, N, j + 1, Vn, N, part, coef + 64));
-            PROF(c, PG_KRYLOV, ax, launch_axpy_multi(s, Vn, V, N, j + 1, coef + 64, N, -1.0, part, coef + 128));
-            DWP_HIP(hipMemcpyAsync(c->host, coef, sizeof(double) * 129, hipMemcpyDeviceToHost, s));
+            PROF(c, PG_MULTIDOT, md, launch_multidot(s, V, N, j + 1, Vn, N, part, coef, coef + 128));
+            PROF(c, PG_AXPY, ax, launch_axpy_multi(s, Vn, V, N, j + 1, coef, N, -1.0, part, coef + 129));
+            DWP_HIP(hipMemcpyAsync(c->host, coef, sizeof(double) * 130, hipMemcpyDeviceToHost, s));
             sync(c);
-            for (int i = 0; i <= j; ++i) Hij(i, j) = c->host[i] + c->host[64 + i];
-            const double hn = std::sqrt(c->host[128]);
+            for (int i = 0; i <= j; ++i) Hij(i, j) = c->host[i];
+            double hn2 = c->host[129];
+            if (!(hn2 > REORTH_ETA2 * c->host[128])) {
+                ++c->reorth;
+                PROF(c, PG_MULTIDOT, md, launch_multidot(s, V, N, j + 1, Vn, N, part, coef + 64, nullptr));
+                PROF(c, PG_AXPY, ax, launch_axpy_multi(s, Vn, V, N, j + 1, coef + 64, N, -1.0, part, coef + 130));
+                DWP_HIP(hipMemcpyAsync(c->host + 64, coef + 64, sizeof(double) * 67, hipMemcpyDeviceToHost, s));
+                sync(c);
+                for (int i = 0; i <= j; ++i) Hij(i, j) += c->host[64 + i];
+                hn2 = c->host[130];
+            }
+            const double hn = std::sqrt(hn2);
             Hij(j + 1, j) = hn;
             ++iters;
             if (!std::isfinite(hn)) fail(DWP_ENONFINITE, "Krylov basis is not finite");
-            if (hn > 0.0) PROF(c, PG_KRYLOV, 16.0 * N, launch_axpby(s, Vn, 1.0 / hn, Vn, 0.0, N));
+            if (hn > 0.0) PROF(c, PG_VEC, 16.0 * N, launch_axpby(s, Vn, 1.0 / hn, Vn, 0.0, N));
             for (int i = 0; i < j; ++i) {
                 const double t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
                 Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
@@ -386,7 +408,7 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
         }
         for (int i = 0; i < k; ++i) c->host[i] = y[i];
         DWP_HIP(hipMemcpyAsync(coef + 192, c->host, sizeof(double) * k, hipMemcpyHostToDevice, s));
-        PROF(c, PG_KRYLOV, 8.0 * N * (k + 2), launch_axpy_multi(s, x, Z, N, k, coef + 192, N, 1.0, part, nullptr));
+        PROF(c, PG_AXPY, 8.0 * N * (k + 2), launch_axpy_multi(s, x, Z, N, k, coef + 192, N, 1.0, part, nullptr));
         sync(c);  // the staging buffer is reused next
     }
 }
@@ -412,6 +434,7 @@ void validate_opts(const dwp_opts &o) {
     if (o.scaled_dry != 0 && o.scaled_dry != 1) fail(DWP_EINVAL, "scaled_dry must be 0 or 1");
     if (o.warm_start != 0 && o.warm_start != 1) fail(DWP_EINVAL, "warm_start must be 0 or 1");
     if (o.profile != 0 && o.profile != 1) fail(DWP_EINVAL, "profile must be 0 or 1");
+    if (o.smoother != 0 && o.smoother != 1) fail(DWP_EINVAL, "smoother must be 0 or 1");
 }
 
 AtomParams atom_params(const dwp_eps_params *ep) {
@@ -521,7 +544,7 @@ void set_grid_impl(dwp_ctx *c, int nx, int ny, int nz, double Lx, double Ly, dou
     c->Z.alloc(d * N * opts.restart);
     c->cbuf.alloc(sizeof(double2) * (size_t)p.nkx * ny * nz);
     c->Hz.alloc(d * nz);
-    c->partial.alloc(d * (size_t)RED_BLOCKS * 64);
+    c->partial.alloc(d * (size_t)RED_BLOCKS * 80);
     c->coef.alloc(d * 512);
     fft_plan_axis(c->fx, nx, p.h[0], true);
     fft_plan_axis(c->fy, ny, p.h[1], false);
@@ -614,6 +637,7 @@ void solve_impl(dwp_ctx *c, const double *rho, double *phi, double *energy, dwp_
     if (!c->opts.warm_start) launch_fill(s, phi, 0.0, N);
     int iters = 0, restarts = 0;
     double rel = 0.0;
+    c->reorth = 0;
     int status = DWP_OK;
     if (bnorm > 0.0) {
         iters = fgmres(c, c->b.as<double>(), bnorm, phi, &restarts, &rel);
@@ -636,6 +660,7 @@ void solve_impl(dwp_ctx *c, const double *rho, double *phi, double *energy, dwp_
         info->outer_iters = iters;
         info->vcycles = iters * c->opts.cycles;
         info->restarts = restarts;
+        info->reorth = c->reorth;
         info->k_w0 = p.k_w0;
         info->k_w1 = p.k_w1;
         info->n_levels = (int)p.levels.size();
@@ -714,8 +739,10 @@ void dwp_default_opts(dwp_opts *o) {
     o->scaled_dry = 0;
     o->tol = 1e-10;
     o->max_outer = 600;
-    o->restart = 30;
+    o->restart = 10;
     o->warm_start = 0;
+    o->profile = 0;
+    o->smoother = 1;
 }
 
 int dwp_create(dwp_ctx **out, int device, void *stream) {
@@ -844,7 +871,8 @@ int dwp_vacuum_solve(dwp_ctx *c, const double *r, double *out) {
     dwp::need_grid(c);
     if (!r || !out) dwp::fail(DWP_EINVAL, "NULL pointer");
     DWP_HIP(hipSetDevice(c->device));
-    dwp::launch_vacuum_solve(c->stream, c->plan, c->fx, c->fy, c->fz, r, nullptr, c->cbuf.as<double2>(), out);
+    dwp::launch_vacuum_solve(c->stream, c->plan, c->fx, c->fy, c->fz, r, nullptr, c->cbuf.as<double2>(), out,
+                             nullptr);
     ABI_END(c)
 }
 

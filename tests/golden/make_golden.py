@@ -50,7 +50,7 @@ def make(name, w):
         params = w.eps_params
     rho = O.rho_gauss(w.n, w.L, w.xyz, w.q, w.sigma)
     t1 = time.time()
-    phi, info = O.solve(rho, eps, w.h, tol=1e-13, max_iter=3000, return_info=True)
+    phi, info = O.solve(rho, eps, w.h, tol=1e-12, max_iter=1000, return_info=True)
     t2 = time.time()
     E = O.energy(rho, phi, w.h)
     Ee = O.energy_eps_form(phi, eps, w.h)

@@ -172,3 +172,18 @@ def test_error_paths(torch):
     s.set_opts(max_outer=600)
     phi, E, info = s.solve(_dev(torch, rho))
     assert info["rel_res"] <= 1e-10
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fused_sweep_equals_colour_passes(torch, precision):
+    """The fused out-of-place sweep and the two in-place colour passes are the
+    same Gauss-Seidel sweep: one application of the split agrees to rounding."""
+    w = W.slab(n=(48, 48, 96), exclusion=True)
+    s = _solver(torch, w.n, w.L, z_wet_lo=w.z_wet[0], z_wet_hi=w.z_wet[1], precision=precision, smoother=1)
+    s.build_epsilon(w.xyz, w.radius, w.eps_params)
+    rng = np.random.default_rng(3)
+    r = _dev(torch, rng.normal(size=s.shape))
+    z1 = _host(s.apply_split(r))
+    s.set_opts(smoother=0)
+    z0 = _host(s.apply_split(r))
+    assert _rel(z1, z0) <= (1e-12 if precision == 0 else 2e-5)
