@@ -74,8 +74,7 @@ def run_steps(s, w, steps, warmup, torch):
 def solver_for(w, precision, torch):
     from paper_0904_4887_amd.binding import Solver
     s = Solver(0)
-    s.set_grid(w.n, w.L, z_wet_lo=w.z_wet[0], z_wet_hi=w.z_wet[1], tol=1e-8,
-               precision=1 if precision == "mixed" else 0, profile=1)
+    s.set_grid(w.n, w.L, **w.solver_opts(tol=1e-8, precision=1 if precision == "mixed" else 0, profile=1))
     return s
 
 
@@ -103,6 +102,33 @@ def cpu_baseline(w, golden_iters):
                       f"workload; eps/rho builds and forces not included (NumPy, one thread)"}
 
 
+def md_loop(w, steps, torch, precision="mixed"):
+    """MD-like steps: R += N(0, 0.02 A) per step (cumulative), eps and rho
+    rebuilt, phi warm-started from the previous step, forces every step."""
+    from paper_0904_4887_amd.binding import Solver
+    s = Solver(0)
+    s.set_grid(w.n, w.L, **w.solver_opts(tol=1e-8, precision=1 if precision == "mixed" else 0))
+    disp = W.md_displacements(len(w.q), steps)
+    rho, phi = s.empty(), s.empty()
+    xyz = w.xyz.copy()
+    per = []
+    for t in range(steps):
+        if t > 0:
+            xyz = np.mod(xyz + disp[t], np.array(w.L))
+        s.set_opts(warm_start=1 if t > 0 else 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.build_epsilon(xyz, w.radius, w.eps_params)
+        s.build_rho(xyz, w.q, w.sigma, out=rho)
+        _, E, info = s.solve(rho, phi)
+        F = s.forces(xyz, w.q, w.sigma, w.radius, w.eps_params)
+        torch.cuda.synchronize()
+        per.append(dict(ms=round(1e3 * (time.perf_counter() - t0), 2), iters=info["outer_iters"], energy=E,
+                        max_force=float(np.abs(F).max())))
+    s.close()
+    return per
+
+
 def golden_iters(name):
     p = os.path.join(ROOT, "tests", "golden", f"oracle_{name}.json")
     if os.path.exists(p):
@@ -124,6 +150,8 @@ def main():
     ap.add_argument("--exclusion", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--md-steps", type=int, default=10,
+                    help="MD-like warm-started steps on the 256x256x512 slab (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling hardware traffic counters)")
     args = ap.parse_args()
@@ -190,6 +218,14 @@ def main():
             "iters": inf3[-1]["outer_iters"], "energy": E3, "z_wet": list(we.z_wet)}
         s3.close()
         print(f"# other mode: {1e3 * sec3:.2f} ms/step", file=sys.stderr, flush=True)
+
+    if not args.no_compare and args.md_steps > 0:
+        wb = W.big_slab(exclusion=args.exclusion, tol=1e-8)
+        per = md_loop(wb, args.md_steps, torch, args.precision)
+        extra["md_256x256x512"] = {"steps": per, "ms_per_step_warm": round(float(np.mean([p["ms"] for p in per[1:]])), 2),
+                                   "iters_cold": per[0]["iters"],
+                                   "iters_warm_mean": round(float(np.mean([p["iters"] for p in per[1:]])), 2)}
+        print(f"# md: {[p['ms'] for p in per]} ms, iters {[p['iters'] for p in per]}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu:

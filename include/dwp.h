@@ -173,6 +173,14 @@ int dwp_solve(dwp_ctx *ctx, const double *rho_dev, double *phi_dev, double *ener
  * the last solution (the discrete first term of Eq. 11).  N doubles. */
 int dwp_eps_gradient(dwp_ctx *ctx, double *dEdeps_dev);
 
+/* out_n = scale * sum_d 1/2 [(D+_d a)_n (D+_d b)_n + (D-_d a)_n (D-_d b)_n]:
+ * -d(a.A b)/d eps_n times scale (no h^3 factor), for two grids a, b (N
+ * doubles each).  With a = b = phi and scale = -h^3/(8 pi) it is
+ * dwp_eps_gradient; with a = lambda (an adjoint solution) it gives the
+ * permittivity gradient of a loss that depends on phi itself. */
+int dwp_eps_pair_gradient(dwp_ctx *ctx, const double *a_dev, const double *b_dev, double scale,
+                          double *out_dev);
+
 /* dE/dR (n x 3, host) for the last solution: sum_n (dE/d eps_n) d eps_n/dR_I
  * + h^3 sum_n phi_n d rho_n / dR_I (Eq. 11).  The atoms and parameters must
  * be those eps and rho were built from.  params == NULL means eps does not

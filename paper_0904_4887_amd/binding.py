@@ -68,6 +68,7 @@ _SIGNATURES = {
     "dwp_build_rho": (C.c_int, [_P, C.c_int, _D, _D, _D, _P]),
     "dwp_solve": (C.c_int, [_P, _P, _P, _D, C.POINTER(Info)]),
     "dwp_eps_gradient": (C.c_int, [_P, _P]),
+    "dwp_eps_pair_gradient": (C.c_int, [_P, _P, _P, C.c_double, _P]),
     "dwp_forces": (C.c_int, [_P, C.c_int, _D, _D, _D, _D, C.POINTER(EpsParams), _D]),
     "dwp_apply_operator": (C.c_int, [_P, _P, _P]),
     "dwp_vacuum_solve": (C.c_int, [_P, _P, _P]),
@@ -240,6 +241,12 @@ class Solver:
     def eps_gradient(self, out=None):
         out = self.empty() if out is None else out
         self._check(lib().dwp_eps_gradient(self._h, self._dev(out, "dEdeps")))
+        return out
+
+    def eps_pair_gradient(self, a, b, scale, out=None):
+        out = self.empty() if out is None else out
+        self._check(lib().dwp_eps_pair_gradient(self._h, self._dev(a, "a"), self._dev(b, "b"), float(scale),
+                                                self._dev(out, "out")))
         return out
 
     def forces(self, xyz, q, sigma, radius=None, params=None):

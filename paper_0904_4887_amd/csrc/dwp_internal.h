@@ -167,6 +167,7 @@ constexpr int RED_THREADS = 256;
 void launch_apply_full(hipStream_t s, const Plan &p, const double *phi, const double *eps,
                        const double *b, double *out, bool residual);
 void launch_eps_gradient(hipStream_t s, const Plan &p, const double *phi, double *g);
+void launch_eps_pair(hipStream_t s, const Plan &p, const double *a, const double *b, double scale, double *g);
 void launch_fill(hipStream_t s, double *x, double v, size_t n);
 void launch_axpby(hipStream_t s, double *y, double a, const double *x, double b, size_t n);
 void launch_scale_dev(hipStream_t s, double *x, const double *num, const double *den_sq,

@@ -130,6 +130,33 @@ k_eps_gradient(const double *__restrict__ phi, double *__restrict__ g, int nx, i
     g[c] = scale * 0.5 * (dxp * dxp + dxm * dxm + dyp * dyp + dym * dym + dzp * dzp + dzm * dzm);
 }
 
+// out_n = scale * sum_d 1/2 [(D+_d a)(D+_d b) + (D-_d a)(D-_d b)]: the derivative
+// of the bilinear form a.A b with respect to the node permittivity eps_n
+// (times -scale), used for gradients through phi.
+__global__ void __launch_bounds__(BX *BY)
+k_eps_pair(const double *__restrict__ pa, const double *__restrict__ pb, double *__restrict__ g, int nx, int ny,
+           int nz, double ihx, double ihy, double ihz, double scale) {
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= nx || j >= ny) return;
+    const size_t plane = (size_t)nx * ny;
+    const size_t row = (size_t)k * plane + (size_t)j * nx;
+    const size_t c = row + i;
+    const size_t nbr[6] = {row + wrap_p(i, nx), row + wrap_m(i, nx),
+                           (size_t)k * plane + (size_t)wrap_p(j, ny) * nx + i,
+                           (size_t)k * plane + (size_t)wrap_m(j, ny) * nx + i,
+                           (size_t)wrap_p(k, nz) * plane + (size_t)j * nx + i,
+                           (size_t)wrap_m(k, nz) * plane + (size_t)j * nx + i};
+    const double ih[3] = {ihx, ihy, ihz};
+    double acc = 0.0;
+    for (int q = 0; q < 6; ++q) {
+        const double da = (pa[nbr[q]] - pa[c]) * ih[q / 2], db = (pb[nbr[q]] - pb[c]) * ih[q / 2];
+        acc += da * db;
+    }
+    g[c] = scale * 0.5 * acc;
+}
+
 // ---------------------------------------------------------------- vectors
 __global__ void k_fill(double *x, double v, size_t n) {
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
@@ -781,6 +808,12 @@ void launch_eps_gradient(hipStream_t s, const Plan &p, const double *phi, double
     const double scale = -h3 / (8.0 * 3.14159265358979323846);
     dim3 gr((p.nx + BX - 1) / BX, (p.ny + BY - 1) / BY, p.nz), blk(BX, BY);
     k_eps_gradient<<<gr, blk, 0, s>>>(phi, g, p.nx, p.ny, p.nz, 1.0 / p.h[0], 1.0 / p.h[1], 1.0 / p.h[2], scale);
+    DWP_LAUNCH_CHECK();
+}
+
+void launch_eps_pair(hipStream_t s, const Plan &p, const double *a, const double *b, double scale, double *g) {
+    dim3 gr((p.nx + BX - 1) / BX, (p.ny + BY - 1) / BY, p.nz), blk(BX, BY);
+    k_eps_pair<<<gr, blk, 0, s>>>(a, b, g, p.nx, p.ny, p.nz, 1.0 / p.h[0], 1.0 / p.h[1], 1.0 / p.h[2], scale);
     DWP_LAUNCH_CHECK();
 }
 

@@ -849,6 +849,16 @@ int dwp_eps_gradient(dwp_ctx *c, double *g) {
     ABI_END(c)
 }
 
+int dwp_eps_pair_gradient(dwp_ctx *c, const double *a, const double *b, double scale, double *out) {
+    ABI_BEGIN(c)
+    dwp::need_grid(c);
+    if (!a || !b || !out) dwp::fail(DWP_EINVAL, "NULL pointer");
+    if (!std::isfinite(scale)) dwp::fail(DWP_EINVAL, "scale must be finite");
+    DWP_HIP(hipSetDevice(c->device));
+    PROF(c, dwp::PG_FORCES, 24.0 * c->plan.N, dwp::launch_eps_pair(c->stream, c->plan, a, b, scale, out));
+    ABI_END(c)
+}
+
 int dwp_forces(dwp_ctx *c, int n, const double *xyz, const double *radius, const double *q, const double *sigma,
                const dwp_eps_params *ep, double *out) {
     ABI_BEGIN(c)

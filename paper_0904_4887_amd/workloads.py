@@ -46,6 +46,14 @@ class Workload:
     tol: float            # relative residual tolerance of the solve
     precision: int = 0    # 0 = FP64, 1 = mixed FP32-in-FP64
     buried: np.ndarray = None  # (natoms,) bool, atoms under the exclusion rule
+    opts: dict = dataclasses.field(default_factory=dict)  # solver options tuned for this input
+
+    def solver_opts(self, **extra):
+        """Options for Solver.set_grid: wet slab, tolerance, precision, tuning."""
+        o = dict(z_wet_lo=self.z_wet[0], z_wet_hi=self.z_wet[1], tol=self.tol, precision=self.precision)
+        o.update(self.opts)
+        o.update(extra)
+        return o
 
     @property
     def N(self):
@@ -114,9 +122,12 @@ def _slab_workload(name, n, L, cells_xy, layer_dz, seed, z_cut, tol, precision, 
         z_wet = (zmax - 6.0 * DELTA, L[2] + 2.0 * L[2] / n[2])
     else:
         z_wet = (z_cut, L[2])
+    # With a really dry region the eps^-1/2-scaled dry update needs fewer
+    # coupling iterations; with solvent inside the "dry" region it needs more.
+    opts = dict(scaled_dry=1) if exclusion else {}
     return Workload(name=name, n=n, L=L, xyz=xyz, q=q, sigma=sigma, radius=radius,
                     eps_kind="erf", eps_params=params, z_wet=z_wet, tol=tol,
-                    precision=precision, buried=buried)
+                    precision=precision, buried=buried, opts=opts)
 
 
 def tanh_box(n=(32, 32, 64), seed=0):

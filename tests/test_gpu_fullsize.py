@@ -1,0 +1,64 @@
+"""Parity at the full workload sizes, in the configuration the benchmark runs.
+
+The oracle's results for these sizes take minutes to hours of CPU time, so
+they are stored under tests/golden/ (written by tests/golden/make_golden.py,
+which calls only the oracle): the energy in both forms, phi and dE/d eps at 64
+seeded nodes, and dE/dR of every atom.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_0904_4887_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+# name -> (workload, E tol, phi tol (x max|phi| at the samples), force tol (x max|F|))
+CASES = {
+    "tanh_box_32x32x64": (lambda: W.tanh_box(), 1e-10, 1e-8, None),
+    "slab_96x96x192": (lambda: W.slab((96, 96, 192)), 1e-10, 1e-8, 1e-7),
+    "slab_96x96x192_excl": (lambda: W.slab((96, 96, 192), exclusion=True), 1e-10, 1e-8, 1e-7),
+    "slab_128x128x256": (lambda: W.slab((128, 128, 256), tol=1e-12), 1e-10, 1e-9, 1e-8),
+    "slab_192x192x384": (lambda: W.slab((192, 192, 384), tol=1e-8, precision=1), 1e-8, 1e-6, 1e-5),
+    "slab_192x192x384_excl": (lambda: W.slab((192, 192, 384), exclusion=True, tol=1e-8, precision=1),
+                              1e-8, 1e-6, 1e-5),
+    "big_slab_256x256x512": (lambda: W.big_slab(), 1e-8, 1e-6, 1e-5),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_full_size_matches_stored_oracle(name):
+    path = os.path.join(GOLDEN, f"oracle_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"no stored oracle result for {name}")
+    import torch
+    from paper_0904_4887_amd.binding import Solver
+    make, tol_E, tol_phi, tol_F = CASES[name]
+    w = make()
+    with open(path) as f:
+        ref = json.load(f)
+    s = Solver(0)
+    s.set_grid(w.n, w.L, **w.solver_opts())
+    if w.eps_kind == "tanh_z":
+        s.set_epsilon(torch.from_numpy(w.eps_grid()).cuda())
+    else:
+        s.build_epsilon(w.xyz, w.radius, w.eps_params)
+    rho = s.build_rho(w.xyz, w.q, w.sigma)
+    phi, E, info = s.solve(rho)
+    assert info["rel_res"] <= w.tol
+    assert abs(E - ref["energy"]) <= tol_E * abs(ref["energy"]), (E, ref["energy"])
+    nodes = np.array(ref["nodes"])
+    ph = phi.reshape(-1)[torch.from_numpy(nodes).cuda()].cpu().numpy()
+    ref_phi = np.array(ref["phi"])
+    assert np.abs(ph - ref_phi).max() <= tol_phi * np.abs(ref_phi).max()
+    g = s.eps_gradient().reshape(-1)[torch.from_numpy(nodes).cuda()].cpu().numpy()
+    ref_g = np.array(ref["g"])
+    assert np.abs(g - ref_g).max() <= 10 * tol_phi * np.abs(ref_g).max()
+    if tol_F is not None and "forces" in ref:
+        F = s.forces(w.xyz, w.q, w.sigma, w.radius, w.eps_params)
+        F_ref = np.array(ref["forces"])
+        assert np.abs(F - F_ref).max() <= tol_F * np.abs(F_ref).max()
+    s.close()

@@ -1,0 +1,41 @@
+"""Warm-started MD-like steps: after displacing the atoms, rebuilding eps and
+rho and solving from the previous phi, energy and forces still match the
+oracle at the new positions."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_0904_4887_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_md_steps_warm_start(precision):
+    import torch
+    from paper_0904_4887_amd.binding import Solver
+    w = W.slab(n=(48, 48, 96), exclusion=True)
+    s = Solver(0)
+    s.set_grid(w.n, w.L, z_wet_lo=w.z_wet[0], z_wet_hi=w.z_wet[1], tol=1e-10, precision=precision)
+    disp = W.md_displacements(len(w.q), 3, scale=0.02)
+    xyz = w.xyz.copy()
+    rho, phi = s.empty(), s.empty()
+    iters = []
+    for t in range(3):
+        if t:
+            xyz = np.mod(xyz + disp[t], np.array(w.L))
+        s.set_opts(warm_start=1 if t else 0)
+        s.build_epsilon(xyz, w.radius, w.eps_params)
+        s.build_rho(xyz, w.q, w.sigma, out=rho)
+        _, E, info = s.solve(rho, phi)
+        iters.append(info["outer_iters"])
+    F = s.forces(xyz, w.q, w.sigma, w.radius, w.eps_params)
+    torch.cuda.synchronize()
+    eps = O.eps_erf(w.n, w.L, xyz, w.radius, w.eps_params)
+    rho_o = O.rho_gauss(w.n, w.L, xyz, w.q, w.sigma)
+    phi_o = O.solve(rho_o, eps, s.h, tol=1e-13)
+    E_o = O.energy(rho_o, phi_o, s.h)
+    F_o = O.forces(w.n, w.L, xyz, w.radius, w.q, w.sigma, w.eps_params, phi_o, O.eps_gradient(phi_o, s.h))
+    assert abs(E - E_o) <= 1e-10 * abs(E_o)
+    assert np.abs(F - F_o).max() <= 1e-7 * np.abs(F_o).max()
+    assert iters[1] < iters[0] and iters[2] < iters[0]  # the warm start pays off
