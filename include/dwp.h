@@ -78,8 +78,9 @@ typedef struct {
     int max_outer;         /* cap on preconditioned Krylov iterations          */
     int restart;           /* FGMRES restart length m (1..64)                  */
     int warm_start;        /* 1: phi_dev holds the initial guess on entry      */
-    int profile;           /* 1: time kernel groups with HIP events on the     */
-                           /* context stream (see dwp_profile)                 */
+    int profile;           /* 1: time every kernel group with HIP events on    */
+                           /* the context stream (see dwp_profile); 2: only    */
+                           /* the fine-level smoother (least overhead); 0 off  */
     int smoother;          /* red-black Gauss-Seidel on the large levels:      */
                            /* 1 = one fused pass per sweep (out of place),     */
                            /* 0 = one launch per colour (in place); the two    */
@@ -89,9 +90,10 @@ typedef struct {
 /* Per-solve report. */
 typedef struct {
     int outer_iters;         /* Krylov iterations = applications of the split  */
+                             /* (whole restart cycles: a cycle runs all its    */
+                             /* steps before the residual is checked)          */
     int vcycles;             /* V-cycles run                                   */
     int restarts;            /* FGMRES cycles                                  */
-    int reorth;              /* second Gram-Schmidt rounds that were needed    */
     int k_w0, k_w1;          /* wet planes actually used: [k_w0, k_w1) mod nz  */
     int n_levels;            /* multigrid levels on W                          */
     double rel_res;          /* final ||b - A phi||_2 / ||b||_2 (true residual)*/

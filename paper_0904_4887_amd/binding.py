@@ -38,8 +38,7 @@ class Opts(C.Structure):
 
 
 class Info(C.Structure):
-    _fields_ = [("outer_iters", C.c_int), ("vcycles", C.c_int), ("restarts", C.c_int), ("reorth", C.c_int),
-                ("k_w0", C.c_int),
+    _fields_ = [("outer_iters", C.c_int), ("vcycles", C.c_int), ("restarts", C.c_int), ("k_w0", C.c_int),
                 ("k_w1", C.c_int), ("n_levels", C.c_int), ("rel_res", C.c_double), ("energy", C.c_double),
                 ("energy_eps_form", C.c_double), ("mean_rho_removed", C.c_double), ("t_total_ms", C.c_double)]
 

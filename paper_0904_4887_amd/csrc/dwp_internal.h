@@ -70,6 +70,7 @@ struct Plan {
     double h[3] = {0, 0, 0};
     size_t N = 0;
     int nkx = 0;                  // nx / 2 + 1
+    int ldc = 0;                  // row stride of the half spectrum: nkx rounded up to 8
     int k_w0 = 0, k_w1 = 0;       // wet planes [k_w0, k_w1) mod nz
     int nw = 0;                   // k_w1 - k_w0
     std::vector<Level *> levels;  // levels[0] is the fine slab
@@ -105,6 +106,7 @@ enum ProfGroup {
 
 struct Profiler {
     bool on = false;
+    int only = -1;                // >= 0: time only this group
     double ms[PG_COUNT] = {0};
     double bytes[PG_COUNT] = {0};
     long launches[PG_COUNT] = {0};
@@ -115,7 +117,7 @@ struct Profiler {
     };
     std::vector<Pending> pending;
     size_t next = 0;
-    int begin(hipStream_t s);                                 // -1 when off
+    int begin(hipStream_t s, int group = -1);                 // -1 when off
     void end(hipStream_t s, int ev, int group, double bytes);
     void collect();                                           // after a stream sync
     void reset();
@@ -149,7 +151,6 @@ struct dwp_ctx {
     size_t host_len = 0;
     dwp::Profiler prof;
     double mean_rho = 0.0;
-    int reorth = 0;               // second Gram-Schmidt rounds in the last solve
     // atom bookkeeping of the last build_epsilon
     int eps_natoms = -1;
     bool eps_exclusion = false;
@@ -195,10 +196,12 @@ template <class T>
 void launch_level_smooth(hipStream_t s, const Level &L, int color);
 template <class T>
 void launch_level_coarse_solve(hipStream_t s, const Level &L, int sweeps);
+// fc = full weighting of the fine residual rf; also zeroes C.u
 template <class T>
 void launch_restrict(hipStream_t s, const Level &F, const Level &C, const T *rf, T *fc);
 template <class T>
 void launch_prolong_add(hipStream_t s, const Level &F, const Level &C);
+
 template <class T>
 void launch_coarsen_eps(hipStream_t s, const Level &F, const Level &C);
 template <class T>

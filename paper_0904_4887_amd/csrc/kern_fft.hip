@@ -23,7 +23,7 @@ namespace dwp {
 
 namespace {
 
-constexpr int FFT_THREADS = 256;
+constexpr int FFT_THREADS = 512;
 constexpr int MAX_STAGES = 12;
 
 struct Radices {
@@ -156,7 +156,7 @@ __device__ void fft_lines(double2 *buf, const Radices &rd, int B, int es, int ls
 // block carry 2B real rows.  LDS lines are padded to n + 1 elements.
 __global__ void __launch_bounds__(FFT_THREADS)
 k_fft_x_fwd(const double *__restrict__ in, const double *__restrict__ sinv, double2 *__restrict__ out,
-            Radices rd, const double2 *__restrict__ tw, int B, int nrows, int nkx) {
+            Radices rd, const double2 *__restrict__ tw, int B, int nrows, int nkx, int ldc) {
     extern __shared__ double2 lds[];
     const int n = rd.n, ls = n + 1;
     const int r0 = blockIdx.x * 2 * B;
@@ -183,14 +183,14 @@ k_fft_x_fwd(const double *__restrict__ in, const double *__restrict__ sinv, doub
         // A = (Z + conj Z[-k]) / 2, B = (Z - conj Z[-k]) / (2 i)
         const double2 A = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
         const double2 Bv = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
-        out[(size_t)ra * nkx + k] = A;
-        out[(size_t)rb * nkx + k] = Bv;
+        out[(size_t)ra * ldc + k] = A;
+        out[(size_t)rb * ldc + k] = Bv;
     }
 }
 
 __global__ void __launch_bounds__(FFT_THREADS)
 k_fft_x_inv(const double2 *__restrict__ in, const double *__restrict__ sinv, double *__restrict__ out,
-            Radices rd, const double2 *__restrict__ tw, int B, int nrows, int nkx) {
+            Radices rd, const double2 *__restrict__ tw, int B, int nrows, int nkx, int ldc) {
     extern __shared__ double2 lds[];
     const int n = rd.n, ls = n + 1;
     const int r0 = blockIdx.x * 2 * B;
@@ -200,7 +200,7 @@ k_fft_x_inv(const double2 *__restrict__ in, const double *__restrict__ sinv, dou
         double2 z = make_double2(0.0, 0.0);
         if (rb < nrows) {
             const int kk = (k < nkx) ? k : n - k;
-            double2 A = in[(size_t)ra * nkx + kk], Bv = in[(size_t)rb * nkx + kk];
+            double2 A = in[(size_t)ra * ldc + kk], Bv = in[(size_t)rb * ldc + kk];
             if (kk == 0 || 2 * kk == n) { A.y = 0.0; Bv.y = 0.0; }
             if (k >= nkx) { A.y = -A.y; Bv.y = -Bv.y; }  // Hermitian extension
             z = make_double2(A.x - Bv.y, A.y + Bv.x);     // A + i B
@@ -229,28 +229,28 @@ k_fft_x_inv(const double2 *__restrict__ in, const double *__restrict__ sinv, dou
 // Block (tile of B consecutive kx, plane z): lines along y, LDS element
 // (y, l) at y * B + l.
 __global__ void __launch_bounds__(FFT_THREADS)
-k_fft_y(double2 *__restrict__ c, Radices rd, const double2 *__restrict__ tw, int B, int nkx, int inv) {
+k_fft_y(double2 *__restrict__ c, Radices rd, const double2 *__restrict__ tw, int B, int nkx, int ldc, int inv) {
     extern __shared__ double2 lds[];
     const int ny = rd.n;
     const int kx0 = blockIdx.x * B;
     const int z = blockIdx.y;
     const int bw = min(B, nkx - kx0);
-    const size_t base = (size_t)z * ny * nkx + kx0;
+    const size_t base = (size_t)z * ny * ldc + kx0;
     for (int e = threadIdx.x; e < B * ny; e += FFT_THREADS) {
         const int y = e / B, l = e % B;
-        lds[y * B + l] = (l < bw) ? c[base + (size_t)y * nkx + l] : make_double2(0.0, 0.0);
+        lds[y * B + l] = (l < bw) ? c[base + (size_t)y * ldc + l] : make_double2(0.0, 0.0);
     }
     __syncthreads();
     fft_lines(lds, rd, B, B, 1, tw, inv != 0);
     for (int e = threadIdx.x; e < B * ny; e += FFT_THREADS) {
         const int y = e / B, l = e % B;
-        if (l < bw) c[base + (size_t)y * nkx + l] = lds[y * B + l];
+        if (l < bw) c[base + (size_t)y * ldc + l] = lds[y * B + l];
     }
 }
 
 // ---------------------------------------------------------------- z pass + Green
 __global__ void __launch_bounds__(FFT_THREADS)
-k_fft_z_green(double2 *__restrict__ c, Radices rd, const double2 *__restrict__ tw, int B, int nkx, int ny,
+k_fft_z_green(double2 *__restrict__ c, Radices rd, const double2 *__restrict__ tw, int B, int nkx, int ldc, int ny,
               const double *__restrict__ lamx, const double *__restrict__ lamy,
               const double *__restrict__ lamz, double inv_n) {
     extern __shared__ double2 lds[];
@@ -258,8 +258,8 @@ k_fft_z_green(double2 *__restrict__ c, Radices rd, const double2 *__restrict__ t
     const int kx0 = blockIdx.x * B;
     const int y = blockIdx.y;
     const int bw = min(B, nkx - kx0);
-    const size_t zstride = (size_t)ny * nkx;
-    const size_t base = (size_t)y * nkx + kx0;
+    const size_t zstride = (size_t)ny * ldc;
+    const size_t base = (size_t)y * ldc + kx0;
     for (int e = threadIdx.x; e < B * nz; e += FFT_THREADS) {
         const int z = e / B, l = e % B;
         lds[z * B + l] = (l < bw) ? c[base + (size_t)z * zstride + l] : make_double2(0.0, 0.0);
@@ -294,9 +294,12 @@ Radices radices_of(const FFTAxis &ax) {
     return r;
 }
 
+// Lines per block: at most budget / n, capped at 16, rounded down to a
+// multiple of 8 (whole 128-byte segments of the padded spectrum) when >= 8.
 int tile_lines(int n, int budget) {
     int B = budget / n;
     if (B > 16) B = 16;
+    if (B >= 8) B -= B % 8;
     if (B < 1) B = 1;
     return B;
 }
@@ -340,37 +343,41 @@ void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const
     // scaled) and the half-spectrum (16 B / complex value) read and written once
     const double C = (double)p.nkx * p.ny * p.nz;
     const double bx = (sinv ? 16.0 : 8.0) * p.N + 16.0 * C;
-    auto pb = [&]() { return prof ? prof->begin(st) : -1; };
+    auto pb = [&](int g) { return prof ? prof->begin(st, g) : -1; };
     auto pe = [&](int ev, int g, double b) { if (prof) prof->end(st, ev, g, b); };
     int ev;
     const int nrows = p.ny * p.nz;
     const int Bx = tile_lines(p.nx, 2048);
     const int gx = (nrows + 2 * Bx - 1) / (2 * Bx);
     const size_t ldsx = sizeof(double2) * Bx * (p.nx + 1);
-    ev = pb();
-    k_fft_x_fwd<<<gx, FFT_THREADS, ldsx, st>>>(r, sinv, cbuf, radices_of(ax), ax.tw.as<double2>(), Bx, nrows, p.nkx);
+    ev = pb(PG_FFT_X);
+    k_fft_x_fwd<<<gx, FFT_THREADS, ldsx, st>>>(r, sinv, cbuf, radices_of(ax), ax.tw.as<double2>(), Bx, nrows, p.nkx,
+                                               p.ldc);
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_X, bx);
     const int By = tile_lines(p.ny, 4096);
     dim3 gy((p.nkx + By - 1) / By, p.nz);
-    ev = pb();
-    k_fft_y<<<gy, FFT_THREADS, sizeof(double2) * By * p.ny, st>>>(cbuf, radices_of(ay), ay.tw.as<double2>(), By, p.nkx, 0);
+    ev = pb(PG_FFT_Y);
+    k_fft_y<<<gy, FFT_THREADS, sizeof(double2) * By * p.ny, st>>>(cbuf, radices_of(ay), ay.tw.as<double2>(), By, p.nkx,
+                                                                  p.ldc, 0);
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_Y, 32.0 * C);
     const int Bz = tile_lines(p.nz, 4096);
     dim3 gz((p.nkx + Bz - 1) / Bz, p.ny);
-    ev = pb();
+    ev = pb(PG_FFT_Z);
     k_fft_z_green<<<gz, FFT_THREADS, sizeof(double2) * Bz * p.nz, st>>>(
-        cbuf, radices_of(az), az.tw.as<double2>(), Bz, p.nkx, p.ny, ax.lam.as<double>(), ay.lam.as<double>(),
+        cbuf, radices_of(az), az.tw.as<double2>(), Bz, p.nkx, p.ldc, p.ny, ax.lam.as<double>(), ay.lam.as<double>(),
         az.lam.as<double>(), 1.0 / (double)p.N);
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_Z, 32.0 * C);
-    ev = pb();
-    k_fft_y<<<gy, FFT_THREADS, sizeof(double2) * By * p.ny, st>>>(cbuf, radices_of(ay), ay.tw.as<double2>(), By, p.nkx, 1);
+    ev = pb(PG_FFT_Y);
+    k_fft_y<<<gy, FFT_THREADS, sizeof(double2) * By * p.ny, st>>>(cbuf, radices_of(ay), ay.tw.as<double2>(), By, p.nkx,
+                                                                  p.ldc, 1);
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_Y, 32.0 * C);
-    ev = pb();
-    k_fft_x_inv<<<gx, FFT_THREADS, ldsx, st>>>(cbuf, sinv, out, radices_of(ax), ax.tw.as<double2>(), Bx, nrows, p.nkx);
+    ev = pb(PG_FFT_X);
+    k_fft_x_inv<<<gx, FFT_THREADS, ldsx, st>>>(cbuf, sinv, out, radices_of(ax), ax.tw.as<double2>(), Bx, nrows, p.nkx,
+                                               p.ldc);
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_X, bx);
 }

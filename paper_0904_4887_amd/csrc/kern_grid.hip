@@ -171,9 +171,10 @@ __global__ void k_axpby(double *y, double a, const double *x, double b, size_t n
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
         y[t] = a * x[t] + b * y[t];
 }
-// mode 0: x *= 1/sqrt(*den_sq) ; mode 1: x *= *num
+// mode 0: x *= 1/sqrt(*den_sq) (0 when *den_sq is 0: a breakdown leaves a zero
+// vector); mode 1: x *= *num
 __global__ void k_scale_dev(double *x, const double *num, const double *den_sq, size_t n, int mode) {
-    const double s = mode == 0 ? 1.0 / sqrt(*den_sq) : *num;
+    const double s = mode == 0 ? (*den_sq > 0.0 ? 1.0 / sqrt(*den_sq) : 0.0) : *num;
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
         x[t] *= s;
 }
@@ -373,9 +374,13 @@ k_level_coarse(T *__restrict__ u, const T *__restrict__ e, const T *__restrict__
 
 // Full weighting: 1/4, 1/2, 1/4 along every coarsened direction (periodic in
 // x, y; in z the three fine planes 2kc, 2kc+1, 2kc+2 all lie inside the slab).
+// The coarse unknowns (ghosted array uc) are zeroed in the same launch.
 template <class T>
-__global__ void k_restrict(const T *__restrict__ rf, T *__restrict__ fc, int nxf, int nyf,
+__global__ void k_restrict(const T *__restrict__ rf, T *__restrict__ fc, T *__restrict__ uc, int nxf, int nyf,
                            int nxc, int nyc, int nwc, int zc) {
+    const size_t ng = (size_t)nxc * nyc * (nwc + 2);
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < ng; q += (size_t)gridDim.x * blockDim.x)
+        uc[q] = T(0);
     const size_t planec = (size_t)nxc * nyc, planef = (size_t)nxf * nyf;
     const size_t total = planec * nwc;
     const T w3[3] = {T(0.25), T(0.5), T(0.25)};
@@ -586,24 +591,28 @@ k_sweep_fused(const T *__restrict__ uin, T *__restrict__ uout, const T *__restri
         }
         __syncthreads();
         const int k = m - 1;  // second colour at plane k on the tile, write plane k
-        if (k >= k0 && k < k1) {
+        {
             const int c1 = blk_on ? 1 - c0 : c0;
             const int off = (c1 - base_par - by - k) & 1;
             const int x = 2 * bt + off;
             const int i = i0 + x, j = j0 + by;
-            if (i < nx && j < ny) {
-                const int r = (by + 1) * FRX + (x + 1);
-                const T *rm = sr[(k + 3) % 3];
-                T v;
-                if (!blk_on) {
-                    v = rm[r];
-                } else {
-                    const int h = (by + 2) * FHX + (x + 2);
-                    v = update(se[(k + 4) % 4], se[(k + 5) % 4], se[(k + 3) % 4], h, rm[r + 1], rm[r - 1],
-                               rm[r + FRX], rm[r - FRX], sr[(k + 4) % 3][r], sr[(k + 2) % 3][r], sf[(k + 3) % 3][r]);
-                }
-                uout[(size_t)(k + 1) * plane + (size_t)j * nx + i] = v;
+            const bool valid = k >= k0 && k < k1 && i < nx && j < ny;
+            const int r = (by + 1) * FRX + (x + 1);
+            const T *rm = sr[(k + 3) % 3];
+            T v = rm[r];
+            if (blk_on) {
+                const int h = (by + 2) * FHX + (x + 2);
+                v = update(se[(k + 4) % 4], se[(k + 5) % 4], se[(k + 3) % 4], h, rm[r + 1], rm[r - 1],
+                           rm[r + FRX], rm[r - FRX], sr[(k + 4) % 3][r], sr[(k + 2) % 3][r], sf[(k + 3) % 3][r]);
             }
+            // Every thread stores once per step, so the compiler can count the
+            // outstanding memory operations exactly (a conditional store would
+            // make it wait for all prefetched loads).  Steps or positions that
+            // own no point store a zero into the ghost plane 0 of uout, which
+            // already holds zeros and is never written otherwise.
+            const size_t dst = valid ? (size_t)(k + 1) * plane + (size_t)j * nx + i
+                                     : (size_t)((i < nx && j < ny) ? j * nx + i : 0);
+            uout[dst] = valid ? v : T(0);
         }
     };
     // k0 is a multiple of the (even) chunk length: step m uses register set (m + 1) & 1
@@ -896,7 +905,7 @@ void launch_level_coarse_solve(hipStream_t s, const Level &L, int sweeps) {
 template <class T>
 void launch_restrict(hipStream_t s, const Level &F, const Level &C, const T *rf, T *fc) {
     const size_t n = C.n_interior();
-    k_restrict<T><<<grid1d(n), 256, 0, s>>>(rf, fc, F.nx, F.ny, C.nx, C.ny, C.nw, C.zc ? 1 : 0);
+    k_restrict<T><<<grid1d(n), 256, 0, s>>>(rf, fc, C.u.as<T>(), F.nx, F.ny, C.nx, C.ny, C.nw, C.zc ? 1 : 0);
     DWP_LAUNCH_CHECK();
 }
 template <class T>

@@ -49,8 +49,8 @@ static const char *const kGroupNames[PG_COUNT] = {
 
 const char *prof_group_name(int g) { return (g >= 0 && g < PG_COUNT) ? kGroupNames[g] : ""; }
 
-int Profiler::begin(hipStream_t s) {
-    if (!on) return -1;
+int Profiler::begin(hipStream_t s, int group) {
+    if (!on || (only >= 0 && group != only)) return -1;
     while (next + 2 > pool.size()) {
         hipEvent_t e;
         DWP_HIP(hipEventCreate(&e));
@@ -90,7 +90,7 @@ Profiler::~Profiler() {
 
 #define PROF(c, group, nbytes, stmt)                                \
     do {                                                           \
-        const int ev_ = (c)->prof.begin((c)->stream);               \
+        const int ev_ = (c)->prof.begin((c)->stream, (group));      \
         stmt;                                                      \
         (c)->prof.end((c)->stream, ev_, (group), (double)(nbytes)); \
     } while (0)
@@ -98,6 +98,8 @@ Profiler::~Profiler() {
 namespace {
 
 constexpr int COARSE_TARGET = 1024;  // coarsest level: at most this many points
+constexpr size_t HESS_OFFSET = 512;   // device Hessenberg columns inside coef
+constexpr size_t HESS_STRIDE = 72;
 
 struct LevelDims {
     int nx, ny, nw;
@@ -281,9 +283,8 @@ void vcycle(dwp_ctx *c, size_t l) {
     for (int k = 0; k < c->opts.pre; ++k) smooth(0);
     Level &C = *p.levels[l + 1];
     PROF(c, PG_MG_OTHER, 4.0 * ts * L.n_interior(), launch_level_residual<T>(s, L, L.r.as<T>()));
-    PROF(c, PG_MG_OTHER, ts * (L.n_interior() + C.n_interior()),
+    PROF(c, PG_MG_OTHER, ts * (L.n_interior() + C.n_interior() + C.n_ghosted()),
          launch_restrict<T>(s, L, C, L.r.as<T>(), C.f.as<T>()));
-    PROF(c, PG_MG_OTHER, ts * C.n_ghosted(), launch_zero<T>(s, C.u.as<T>(), C.n_ghosted()));
     vcycle<T>(c, l + 1);
     PROF(c, PG_MG_OTHER, ts * (C.n_interior() + 2.0 * L.n_interior()), launch_prolong_add<T>(s, L, C));
     for (int k = 0; k < c->opts.post; ++k) smooth(1);
@@ -320,13 +321,16 @@ void check_finite_dev(dwp_ctx *c, const double *x, const char *what) {
     if (f & 1) fail(DWP_ENONFINITE, std::string(what) + " holds NaN or Inf");
 }
 
-// A second Gram-Schmidt round runs when the projection removed all but this
-// fraction of ||w||^2 (||w'|| < 1e-2 ||w||).
-constexpr double REORTH_ETA2 = 1e-4;
-
 // FGMRES(m) with the split as right preconditioner; x is updated in place.
-// Returns the number of iterations; *rel receives the final true relative
-// residual.
+// Each restart cycle is enqueued without host round trips: the Gram-Schmidt
+// coefficients, the norm of the new basis vector and its normalisation stay on
+// the device (one projection pass and one update pass of classical
+// Gram-Schmidt per step), and the host reads the whole Hessenberg matrix once
+// per cycle to solve the small least-squares problem.  A cycle always runs its
+// m steps (capped by max_outer); the true residual is recomputed at the start
+// of every cycle, so the result meets the tolerance whatever the loss of
+// orthogonality.  Returns the number of steps; *rel receives the final true
+// relative residual.
 int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, double *rel) {
     Plan &p = c->plan;
     const dwp_opts &o = c->opts;
@@ -335,56 +339,49 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
     const int m = o.restart;
     double *V = c->V.as<double>(), *Z = c->Z.as<double>();
     double *coef = c->coef.as<double>();
+    double *Hd = coef + HESS_OFFSET;   // column j at Hd + j * 72: [0..j] dots, 64 ||w||^2, 65 ||w'||^2
+    double *beta2 = coef + 8;
     double *part = c->partial.as<double>();
     std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), y(m);
     auto Hij = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
     int iters = 0;
     *restarts = 0;
     for (;;) {
-        // r = b - A x into V_0
+        // r = b - A x into V_0, ||r||^2 on the device
         PROF(c, PG_APPLY, 32.0 * N, launch_apply_full(s, p, x, c->eps.as<double>(), b, V, true));
-        PROF(c, PG_VEC, 8.0 * N, launch_dot(s, V, V, N, part, coef));
-        to_host(c, coef, 1);
+        PROF(c, PG_VEC, 8.0 * N, launch_dot(s, V, V, N, part, beta2));
+        to_host(c, beta2, 1);
         const double beta = std::sqrt(c->host[0]);
         if (!std::isfinite(beta)) fail(DWP_ENONFINITE, "residual is not finite");
         *rel = beta / bnorm;
         if (*rel <= o.tol || iters >= o.max_outer) return iters;
         ++*restarts;
-        PROF(c, PG_VEC, 16.0 * N, launch_axpby(s, V, 1.0 / beta, V, 0.0, N));
+        PROF(c, PG_VEC, 16.0 * N, launch_scale_dev(s, V, nullptr, beta2, N, 0));
+        const int mm = std::min(m, o.max_outer - iters);
+        for (int j = 0; j < mm; ++j) {
+            double *Vj = V + (size_t)j * N, *Vn = V + (size_t)(j + 1) * N, *Zj = Z + (size_t)j * N;
+            double *hc = Hd + (size_t)j * HESS_STRIDE;
+            apply_split(c, Vj, Zj);
+            PROF(c, PG_APPLY, 24.0 * N, launch_apply_full(s, p, Zj, c->eps.as<double>(), nullptr, Vn, false));
+            const double md = 8.0 * N * (j + 2), ax = 8.0 * N * (j + 3);
+            PROF(c, PG_MULTIDOT, md, launch_multidot(s, V, N, j + 1, Vn, N, part, hc, hc + 64));
+            PROF(c, PG_AXPY, ax, launch_axpy_multi(s, Vn, V, N, j + 1, hc, N, -1.0, part, hc + 65));
+            PROF(c, PG_VEC, 16.0 * N, launch_scale_dev(s, Vn, nullptr, hc + 65, N, 0));
+        }
+        iters += mm;
+        DWP_HIP(hipMemcpyAsync(c->host, Hd, sizeof(double) * HESS_STRIDE * mm, hipMemcpyDeviceToHost, s));
+        sync(c);
+        // Hessenberg matrix, Givens rotations, least squares (host, (m+1) x m)
         std::fill(H.begin(), H.end(), 0.0);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         int k = 0;
-        for (int j = 0; j < m && iters < o.max_outer; ++j) {
-            double *Vj = V + (size_t)j * N, *Vn = V + (size_t)(j + 1) * N, *Zj = Z + (size_t)j * N;
-            apply_split(c, Vj, Zj);
-            PROF(c, PG_APPLY, 24.0 * N, launch_apply_full(s, p, Zj, c->eps.as<double>(), nullptr, Vn, false));
-            // classical Gram-Schmidt in one projection pass (which also gives
-            // ||w||^2) and one update pass (which gives ||w'||^2); a second
-            // round runs only on severe cancellation.  The true residual is
-            // recomputed at every restart, so a slightly non-orthogonal basis
-            // can cost iterations but never the accuracy of the result
-            const double md = 8.0 * N * (j + 2), ax = 8.0 * N * (j + 3);
-            PROF(c, PG_MULTIDOT, md, launch_multidot(s, V, N, j + 1, Vn, N, part, coef, coef + 128));
-            PROF(c, PG_AXPY, ax, launch_axpy_multi(s, Vn, V, N, j + 1, coef, N, -1.0, part, coef + 129));
-            DWP_HIP(hipMemcpyAsync(c->host, coef, sizeof(double) * 130, hipMemcpyDeviceToHost, s));
-            sync(c);
-            for (int i = 0; i <= j; ++i) Hij(i, j) = c->host[i];
-            double hn2 = c->host[129];
-            if (!(hn2 > REORTH_ETA2 * c->host[128])) {
-                ++c->reorth;
-                PROF(c, PG_MULTIDOT, md, launch_multidot(s, V, N, j + 1, Vn, N, part, coef + 64, nullptr));
-                PROF(c, PG_AXPY, ax, launch_axpy_multi(s, Vn, V, N, j + 1, coef + 64, N, -1.0, part, coef + 130));
-                DWP_HIP(hipMemcpyAsync(c->host + 64, coef + 64, sizeof(double) * 67, hipMemcpyDeviceToHost, s));
-                sync(c);
-                for (int i = 0; i <= j; ++i) Hij(i, j) += c->host[64 + i];
-                hn2 = c->host[130];
-            }
-            const double hn = std::sqrt(hn2);
-            Hij(j + 1, j) = hn;
-            ++iters;
+        for (int j = 0; j < mm; ++j) {
+            const double *hc = c->host + (size_t)j * HESS_STRIDE;
+            for (int i = 0; i <= j; ++i) Hij(i, j) = hc[i];
+            const double hn = std::sqrt(std::max(hc[65], 0.0));
             if (!std::isfinite(hn)) fail(DWP_ENONFINITE, "Krylov basis is not finite");
-            if (hn > 0.0) PROF(c, PG_VEC, 16.0 * N, launch_axpby(s, Vn, 1.0 / hn, Vn, 0.0, N));
+            Hij(j + 1, j) = hn;
             for (int i = 0; i < j; ++i) {
                 const double t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
                 Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
@@ -398,7 +395,7 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
             g[j + 1] = -sn[j] * g[j];
             g[j] = cs[j] * g[j];
             k = j + 1;
-            if (std::fabs(g[j + 1]) <= o.tol * bnorm || hn == 0.0) break;
+            if (hn == 0.0) break;  // exact solution in the current space
         }
         // y = H^{-1} g (upper triangular), x += Z y
         for (int i = k - 1; i >= 0; --i) {
@@ -433,7 +430,7 @@ void validate_opts(const dwp_opts &o) {
     if (o.restart < 1 || o.restart > 63) fail(DWP_EINVAL, "restart must lie in [1, 63]");
     if (o.scaled_dry != 0 && o.scaled_dry != 1) fail(DWP_EINVAL, "scaled_dry must be 0 or 1");
     if (o.warm_start != 0 && o.warm_start != 1) fail(DWP_EINVAL, "warm_start must be 0 or 1");
-    if (o.profile != 0 && o.profile != 1) fail(DWP_EINVAL, "profile must be 0 or 1");
+    if (o.profile < 0 || o.profile > 2) fail(DWP_EINVAL, "profile must be 0, 1 or 2");
     if (o.smoother != 0 && o.smoother != 1) fail(DWP_EINVAL, "smoother must be 0 or 1");
 }
 
@@ -533,8 +530,10 @@ void set_grid_impl(dwp_ctx *c, int nx, int ny, int nz, double Lx, double Ly, dou
     p.h[0] = Lx / nx; p.h[1] = Ly / ny; p.h[2] = Lz / nz;
     p.N = (size_t)nx * ny * nz;
     p.nkx = nx / 2 + 1;
+    p.ldc = (p.nkx + 7) / 8 * 8;
     c->opts = opts;
     c->prof.on = opts.profile != 0;
+    c->prof.only = opts.profile == 2 ? PG_RBGS_FINE : -1;
     plan_wet(c);
     const size_t N = p.N;
     const size_t d = sizeof(double);
@@ -542,10 +541,10 @@ void set_grid_impl(dwp_ctx *c, int nx, int ny, int nz, double Lx, double Ly, dou
     c->w.alloc(d * N); c->phi_last.alloc(d * N); c->gbuf.alloc(d * N);
     c->V.alloc(d * N * (opts.restart + 1));
     c->Z.alloc(d * N * opts.restart);
-    c->cbuf.alloc(sizeof(double2) * (size_t)p.nkx * ny * nz);
+    c->cbuf.alloc(sizeof(double2) * (size_t)p.ldc * ny * nz);
     c->Hz.alloc(d * nz);
     c->partial.alloc(d * (size_t)RED_BLOCKS * 80);
-    c->coef.alloc(d * 512);
+    c->coef.alloc(d * (HESS_OFFSET + HESS_STRIDE * 64));
     fft_plan_axis(c->fx, nx, p.h[0], true);
     fft_plan_axis(c->fy, ny, p.h[1], false);
     fft_plan_axis(c->fz, nz, p.h[2], false);
@@ -560,6 +559,7 @@ void set_opts_impl(dwp_ctx *c, const dwp_opts *o) {
     const dwp_opts old = c->opts;
     c->opts = *o;
     c->prof.on = o->profile != 0;
+    c->prof.only = o->profile == 2 ? PG_RBGS_FINE : -1;
     try {
         if (o->restart > old.restart) {
             c->V.alloc(sizeof(double) * c->plan.N * (o->restart + 1));
@@ -575,6 +575,7 @@ void set_opts_impl(dwp_ctx *c, const dwp_opts *o) {
     } catch (...) {
         c->opts = old;
         c->prof.on = old.profile != 0;
+        c->prof.only = old.profile == 2 ? PG_RBGS_FINE : -1;
         throw;
     }
 }
@@ -637,7 +638,6 @@ void solve_impl(dwp_ctx *c, const double *rho, double *phi, double *energy, dwp_
     if (!c->opts.warm_start) launch_fill(s, phi, 0.0, N);
     int iters = 0, restarts = 0;
     double rel = 0.0;
-    c->reorth = 0;
     int status = DWP_OK;
     if (bnorm > 0.0) {
         iters = fgmres(c, c->b.as<double>(), bnorm, phi, &restarts, &rel);
@@ -660,7 +660,6 @@ void solve_impl(dwp_ctx *c, const double *rho, double *phi, double *energy, dwp_
         info->outer_iters = iters;
         info->vcycles = iters * c->opts.cycles;
         info->restarts = restarts;
-        info->reorth = c->reorth;
         info->k_w0 = p.k_w0;
         info->k_w1 = p.k_w1;
         info->n_levels = (int)p.levels.size();
@@ -756,7 +755,7 @@ int dwp_create(dwp_ctx **out, int device, void *stream) {
         DWP_HIP(hipSetDevice(device));
         c->device = device;
         c->stream = static_cast<hipStream_t>(stream);
-        c->host_len = 4096;
+        c->host_len = 8192;
         DWP_HIP(hipHostMalloc(reinterpret_cast<void **>(&c->host), sizeof(double) * c->host_len, hipHostMallocDefault));
         dwp_default_opts(&c->opts);
     } catch (const Error &e) {
