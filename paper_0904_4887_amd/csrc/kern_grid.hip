@@ -6,6 +6,8 @@
 // Operator (paper Eq. 3 in conservative form, face eps = mean of its nodes):
 //   (A u)_n = sum over the 6 neighbours m of n of
 //             1/2 (eps_n + eps_m) (u_m - u_n) / h_d^2.
+#include <algorithm>
+
 #include "dwp_internal.h"
 
 namespace dwp {
@@ -475,29 +477,62 @@ __global__ void k_coarsen_eps(const T *__restrict__ ef, T *__restrict__ ec, int 
 // u_out = sweep(u_in).  The first colour c0 is updated from u_in (its
 // neighbours all have the other colour), the second colour from the new
 // first-colour values.  A block owns a TX x TY tile of (x, y) for a chunk of
-// KC planes and marches up in z with LDS rings: at step m it loads plane m+1
-// of u_in and eps (tile plus a 2-cell halo), computes first-colour values at
-// plane m on the tile plus a 1-cell halo, then second-colour values at plane
-// m-1 on the tile, and writes plane m-1 of u_out.  Halo values are recomputed
-// by each block that needs them (from u_in, which nobody writes), so the
-// result does not depend on block order.  Equals two colour passes in place.
-constexpr int FTX = 32, FTY = 8, FKC = 16;
+// kc planes and marches up in z with LDS rings: at step m it stashes plane
+// m+1 of u_in, eps and f (tile plus a 2-cell halo, loaded FPD steps
+// earlier) and starts loading plane m+1+FPD, computes first-colour values at plane m on
+// the tile plus a 1-cell halo, then second-colour values at plane m-1 on the
+// tile, and writes plane m-1 of u_out.  Halo values are recomputed by each
+// block that needs them (from u_in, which nobody writes), so the result does
+// not depend on block order.  Equals two colour passes in place.
+//
+// Two barriers per step: one after the stash (first colour may read plane
+// m+1), one after the first colour (second colour reads it).  A ring slot is
+// rewritten only when every thread is known to be past its last read: a
+// thread that stashes at step m has only passed the second barrier of step
+// m-1, so a slot read by the second colour of step m-1 must not be reused at
+// step m.  That needs 4 planes of u, f and first-colour values and 5 of eps
+// (read by the second colour one step later than by the first; 8 are kept).
+// The step loop is unrolled by 8 so that every ring slot is a constant.
+constexpr int FTX = 32, FTY = 8;
 constexpr int FHX = FTX + 4, FHY = FTY + 4;  // 2-cell halo
 constexpr int FRX = FTX + 2, FRY = FTY + 2;  // 1-cell halo
 constexpr int FNT = FTX * FTY;               // threads
 constexpr int FNH = (FHX * FHY + FNT - 1) / FNT;  // halo-2 elements per thread
 constexpr int FNR = (FRX * FRY + FNT - 1) / FNT;  // halo-1 elements per thread
+constexpr int FUNROLL = 8;
+constexpr int FPD = 2;  // prefetch distance in plane steps (divides FUNROLL)
+
+// Gauss-Seidel value (off - f) / diag through the hardware reciprocal.  The
+// smoother only shapes the preconditioner, so the last bit of the quotient
+// does not matter; in FP64 two Newton steps bring the estimate to full
+// precision.
+__device__ __forceinline__ float gs_value(float off, float f, float diag) {
+    return (off - f) * __builtin_amdgcn_rcpf(diag);
+}
+__device__ __forceinline__ double gs_value(double off, double f, double diag) {
+    double r = __builtin_amdgcn_rcp(diag);
+    double e = __builtin_fma(-diag, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-diag, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    return (off - f) * r;
+}
+
+template <class T>
+__device__ __forceinline__ T ld_off(const T *base, unsigned byte_off) {
+    return *(const T *)((const char *)base + byte_off);
+}
 
 template <class T>
 __global__ void __launch_bounds__(FNT)
 k_sweep_fused(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ e, const T *__restrict__ f,
-              LevelArgs a, int c0, int tiles_x, int tiles_y, int nb_real) {
+              LevelArgs a, int c0, int tiles_x, int tiles_y, int kc, int nb_real) {
     // plane buffers padded to a whole number of per-thread elements, so that
     // every thread stores unconditionally (the padding is never read)
-    __shared__ T su[3][FNH * FNT];
-    __shared__ T se[4][FNH * FNT];
-    __shared__ T sr[3][FRY * FRX];
-    __shared__ T sf[3][FNR * FNT];
+    __shared__ T su[4][FNH * FNT];
+    __shared__ T se[8][FNH * FNT];
+    __shared__ T sf[4][FNR * FNT];
+    __shared__ T sr[4][FRY * FRX];
     // XCD-aware order: each XCD gets a contiguous run of tiles (x fastest,
     // then y, then z chunk), so neighbouring tiles share its L2.
     const int tile = xcd_tile(nb_real);
@@ -505,27 +540,26 @@ k_sweep_fused(const T *__restrict__ uin, T *__restrict__ uout, const T *__restri
     const int nx = a.nx, ny = a.ny, nw = a.nw;
     const size_t plane = (size_t)nx * ny;
     const int i0 = (tile % tiles_x) * FTX, j0 = ((tile / tiles_x) % tiles_y) * FTY;
-    const int k0 = (tile / (tiles_x * tiles_y)) * FKC, k1 = min(nw, k0 + FKC);
+    const int k0 = (tile / (tiles_x * tiles_y)) * kc, k1 = min(nw, k0 + kc);
     const T cx = cxv<T>(a, 0), cy = cxv<T>(a, 1), cz = cxv<T>(a, 2);
     const int tid = threadIdx.x;
     const int base_par = (i0 + j0) & 1;  // colour of local (x, y, m) = (base_par + x + y + m) & 1
-    int oh[FNH], orr[FNR];
-    bool vh[FNH], vr[FNR];
+    // byte offsets inside a plane of the halo-2 and halo-1 positions this
+    // thread loads (periodic wrap in x and y)
+    unsigned oh[FNH], orr[FNR];
 #pragma unroll
     for (int t = 0; t < FNH; ++t) {
         const int q = tid + t * FNT;
         const int x = q % FHX - 2, y = q / FHX - 2;
         const int i = ((i0 + x) % nx + nx) % nx, j = ((j0 + y) % ny + ny) % ny;
-        oh[t] = j * nx + i;
-        vh[t] = q < FHX * FHY;
+        oh[t] = (unsigned)((j * nx + i) * sizeof(T));
     }
 #pragma unroll
     for (int t = 0; t < FNR; ++t) {
         const int q = tid + t * FNT;
         const int x = q % FRX - 1, y = q / FRX - 1;
         const int i = ((i0 + x) % nx + nx) % nx, j = ((j0 + y) % ny + ny) % ny;
-        orr[t] = j * nx + i;
-        vr[t] = q < FRX * FRY;
+        orr[t] = (unsigned)((j * nx + i) * sizeof(T));
     }
     // first-colour work: thread tid < FRX*FRY/2 takes the tid-th first-colour
     // point of the tile + 1-cell halo (rows of FRX = 34 hold 17 of each colour)
@@ -536,44 +570,50 @@ k_sweep_fused(const T *__restrict__ uin, T *__restrict__ uout, const T *__restri
     const bool blk_on = tid < FTX * FTY / 2;
     const int q2 = blk_on ? tid : tid - FTX * FTY / 2;
     const int by = q2 / (FTX / 2), bt = q2 % (FTX / 2);
+    const int c1 = blk_on ? 1 - c0 : c0;
+    const int j_out = j0 + by;
 
-    T pu[2][FNH], pe[2][FNH], pf[2][FNR];
+    T pu[FPD][FNH], pe[FPD][FNH], pf[FPD][FNR];
     // Loads are unconditional: plane indices are clamped into the ghosted
     // range, which is harmless because values of planes outside [-1, nw] (f:
     // outside [0, nw)) are never used.  Keeping the loads free of branches and
-    // selects lets them stay in flight for two steps.
+    // selects lets them stay in flight for FPD steps.
     auto fetch = [&](int k, T *du, T *de, T *df) {
-        const int kc = min(max(k, -1), nw), kfc = min(max(k, 0), nw - 1);
-        const size_t g = (size_t)(kc + 1) * plane, gf = (size_t)kfc * plane;
+        const int kk = min(max(k, -1), nw), kf = min(max(k, 0), nw - 1);
+        const T *bu = uin + (size_t)(kk + 1) * plane, *be = e + (size_t)(kk + 1) * plane;
+        const T *bf = f + (size_t)kf * plane;
 #pragma unroll
         for (int t = 0; t < FNH; ++t) {
-            du[t] = uin[g + oh[t]];
-            de[t] = e[g + oh[t]];
+            du[t] = ld_off(bu, oh[t]);
+            de[t] = ld_off(be, oh[t]);
         }
 #pragma unroll
-        for (int t = 0; t < FNR; ++t) df[t] = f[gf + orr[t]];
+        for (int t = 0; t < FNR; ++t) df[t] = ld_off(bf, orr[t]);
     };
-    auto stash = [&](int k, const T *du, const T *de, const T *df) {
-        T *lu = su[(k + 3) % 3], *le = se[(k + 4) % 4], *lf = sf[(k + 3) % 3];
+    // Ring slot of plane p: its local index p - k0 + 2 modulo the ring depth.
+    // Step ls works on m = k0 - 1 + ls, so plane m + d has local index
+    // ls + 1 + d; ls is passed modulo 8 (a compile-time constant below).
+    auto stash = [&](int lp, const T *du, const T *de, const T *df) {
+        T *lu = su[lp & 3], *le = se[lp & 7], *lf = sf[lp & 3];
 #pragma unroll
         for (int t = 0; t < FNH; ++t) { lu[tid + t * FNT] = du[t]; le[tid + t * FNT] = de[t]; }
 #pragma unroll
         for (int t = 0; t < FNR; ++t) lf[tid + t * FNT] = df[t];
     };
-    auto update = [&](const T *em, const T *ep, const T *en, int h, T uxp, T uxm, T uyp, T uym, T uzp, T uzm,
+    auto update = [&](const T *el, const T *ep, const T *en, int h, T uxp, T uxm, T uyp, T uym, T uzp, T uzm,
                       T fv) {
-        const T e0 = em[h];
-        const T wxp = cx * (e0 + em[h + 1]), wxm = cx * (e0 + em[h - 1]);
-        const T wyp = cy * (e0 + em[h + FHX]), wym = cy * (e0 + em[h - FHX]);
+        const T e0 = el[h];
+        const T wxp = cx * (e0 + el[h + 1]), wxm = cx * (e0 + el[h - 1]);
+        const T wyp = cy * (e0 + el[h + FHX]), wym = cy * (e0 + el[h - FHX]);
         const T wzp = cz * (e0 + ep[h]), wzm = cz * (e0 + en[h]);
-        const T off = wxp * uxp + wxm * uxm + wyp * uyp + wym * uym + wzp * uzp + wzm * uzm;
-        const T dg = wxp + wxm + wyp + wym + wzp + wzm;
-        return (T(0.5) * off - fv) / (T(0.5) * dg);
+        const T off = T(0.5) * (wxp * uxp + wxm * uxm + wyp * uyp + wym * uym + wzp * uzp + wzm * uzm);
+        const T dg = T(0.5) * (wxp + wxm + wyp + wym + wzp + wzm);
+        return gs_value(off, fv, dg);
     };
-    auto step = [&](int m, T *du, T *de, T *df) {
-        __syncthreads();
-        stash(m + 1, du, de, df);  // plane m + 1, fetched two steps ago
-        fetch(m + 3, du, de, df);  // in flight for the next two steps
+    auto step = [&](int ls, int m, T *du, T *de, T *df) {
+        const int l0 = ls + 1;     // local index of plane m
+        stash(l0 + 1, du, de, df);    // plane m + 1, fetched FPD steps ago
+        fetch(m + 1 + FPD, du, de, df);  // in flight for the next FPD steps
         __syncthreads();
         if (red_on) {  // first colour at plane m on the tile + 1-cell halo
             const int off = (c0 - base_par - ry - m + 1) & 1;
@@ -581,54 +621,53 @@ k_sweep_fused(const T *__restrict__ uin, T *__restrict__ uout, const T *__restri
             const int q = (ry + 1) * FRX + (x + 1), h = (ry + 2) * FHX + (x + 2);
             T v = T(0);
             if (m >= 0 && m < nw) {
-                const T *um = su[(m + 3) % 3];
-                v = update(se[(m + 4) % 4], se[(m + 5) % 4], se[(m + 3) % 4], h, um[h + 1], um[h - 1],
-                           um[h + FHX], um[h - FHX], su[(m + 4) % 3][h], su[(m + 2) % 3][h], sf[(m + 3) % 3][q]);
+                const T *um = su[l0 & 3];
+                v = update(se[l0 & 7], se[(l0 + 1) & 7], se[(l0 + 7) & 7], h, um[h + 1], um[h - 1], um[h + FHX],
+                           um[h - FHX], su[(l0 + 1) & 3][h], su[(l0 + 3) & 3][h], sf[l0 & 3][q]);
             }
-            sr[(m + 3) % 3][q] = v;
-            // the other-colour slot of this position pair keeps a defined value
-            sr[(m + 3) % 3][q + (off ? -1 : 1)] = T(0);
+            sr[l0 & 3][q] = v;
         }
         __syncthreads();
         const int k = m - 1;  // second colour at plane k on the tile, write plane k
         {
-            const int c1 = blk_on ? 1 - c0 : c0;
+            const int lk = l0 + 7;  // local index of plane k, kept non-negative
             const int off = (c1 - base_par - by - k) & 1;
             const int x = 2 * bt + off;
-            const int i = i0 + x, j = j0 + by;
-            const bool valid = k >= k0 && k < k1 && i < nx && j < ny;
+            const int i = i0 + x;
             const int r = (by + 1) * FRX + (x + 1);
-            const T *rm = sr[(k + 3) % 3];
+            const T *rm = sr[lk & 3];
             T v = rm[r];
             if (blk_on) {
                 const int h = (by + 2) * FHX + (x + 2);
-                v = update(se[(k + 4) % 4], se[(k + 5) % 4], se[(k + 3) % 4], h, rm[r + 1], rm[r - 1],
-                           rm[r + FRX], rm[r - FRX], sr[(k + 4) % 3][r], sr[(k + 2) % 3][r], sf[(k + 3) % 3][r]);
+                v = update(se[lk & 7], se[(lk + 1) & 7], se[(lk + 7) & 7], h, rm[r + 1], rm[r - 1], rm[r + FRX],
+                           rm[r - FRX], sr[(lk + 1) & 3][r], sr[(lk + 3) & 3][r], sf[lk & 3][r]);
             }
             // Every thread stores once per step, so the compiler can count the
             // outstanding memory operations exactly (a conditional store would
             // make it wait for all prefetched loads).  Steps or positions that
             // own no point store a zero into the ghost plane 0 of uout, which
             // already holds zeros and is never written otherwise.
-            const size_t dst = valid ? (size_t)(k + 1) * plane + (size_t)j * nx + i
-                                     : (size_t)((i < nx && j < ny) ? j * nx + i : 0);
-            uout[dst] = valid ? v : T(0);
+            const bool ij_ok = i < nx && j_out < ny;
+            const bool valid = ij_ok && k >= k0 && k < k1;
+            T *dst = uout + (valid ? (size_t)(k + 1) * plane : 0) + (ij_ok ? (size_t)j_out * nx + i : 0);
+            *dst = valid ? v : T(0);
         }
     };
-    // k0 is a multiple of the (even) chunk length: step m uses register set (m + 1) & 1
+    // Prologue: planes k0 - 2 and k0 - 1 go straight to their ring slots
+    // (local indices 0 and 1), planes k0 .. k0 + FPD - 1 are put in flight.
     fetch(k0 - 2, pu[0], pe[0], pf[0]);
-    stash(k0 - 2, pu[0], pe[0], pf[0]);
+    stash(0, pu[0], pe[0], pf[0]);
     fetch(k0 - 1, pu[1], pe[1], pf[1]);
-    stash(k0 - 1, pu[1], pe[1], pf[1]);
-    fetch(k0, pu[0], pe[0], pf[0]);
-    fetch(k0 + 1, pu[1], pe[1], pf[1]);
-    // steps m = k0-1 .. k1, padded to an even count (an extra step past k1
-    // only recomputes ring values and writes nothing)
-    const int pairs = (k1 - k0 + 3) / 2;
-    for (int it = 0; it < pairs; ++it) {
-        const int m = k0 - 1 + 2 * it;
-        step(m, pu[0], pe[0], pf[0]);
-        step(m + 1, pu[1], pe[1], pf[1]);
+    stash(1, pu[1], pe[1], pf[1]);
+#pragma unroll
+    for (int d = 0; d < FPD; ++d) fetch(k0 + d, pu[d], pe[d], pf[d]);
+    // steps m = k0-1 .. k1; step ls stashes plane m + 1 from register set ls % FPD
+    const int nsteps = k1 - k0 + 2;
+    for (int base = 0; base < nsteps; base += FUNROLL) {
+#pragma unroll
+        for (int s = 0; s < FUNROLL; ++s) {
+            if (base + s < nsteps) step(s, k0 - 1 + base + s, pu[s % FPD], pe[s % FPD], pf[s % FPD]);
+        }
     }
 }
 
@@ -920,12 +959,45 @@ void launch_coarsen_eps(hipStream_t s, const Level &F, const Level &C) {
     k_coarsen_eps<T><<<grid1d(n), 256, 0, s>>>(F.eps.as<T>(), C.eps.as<T>(), F.nx, F.ny, C.nx, C.ny, C.nw, C.zc ? 1 : 0);
     DWP_LAUNCH_CHECK();
 }
+// Chunk length (planes per block, even) of the fused sweep.  A block costs
+// about kc + 3 plane steps; blocks run in ceil(blocks / slots) rounds, where
+// slots = resident blocks on the whole device.  The cost model
+// rounds * (kc + 3) picks the chunk that fills the last round best.
+static int fused_chunk(int tiles, int nw, int slots) {
+    int best = 16;
+    long best_cost = -1;
+    for (int kc = 8; kc <= 64; kc += 2) {
+        const long blocks = (long)tiles * ((nw + kc - 1) / kc);
+        const long rounds = (blocks + slots - 1) / slots;
+        const long cost = rounds * (kc + 3);
+        if (best_cost < 0 || cost < best_cost) { best_cost = cost; best = kc; }
+    }
+    return best;
+}
+
+template <class T>
+static int fused_slots() {
+    static int slots[64] = {0};
+    int dev = 0;
+    DWP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) fail(DWP_EINVAL, "internal: device index out of range");
+    if (!slots[dev]) {
+        int cus = 0, per = 0;
+        DWP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        DWP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_fused<T>, FNT, 0));
+        slots[dev] = std::max(1, cus * per);
+    }
+    return slots[dev];
+}
+
 template <class T>
 void launch_sweep_fused(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color) {
     LevelArgs a = level_args(L);
-    const int tx = (L.nx + FTX - 1) / FTX, ty = (L.ny + FTY - 1) / FTY, tz = (L.nw + FKC - 1) / FKC;
+    const int tx = (L.nx + FTX - 1) / FTX, ty = (L.ny + FTY - 1) / FTY;
+    const int kc = fused_chunk(tx * ty, L.nw, fused_slots<T>());
+    const int tz = (L.nw + kc - 1) / kc;
     const int nb = tx * ty * tz, padded = (nb + 7) / 8 * 8;
-    k_sweep_fused<T><<<padded, FNT, 0, s>>>(uin, uout, L.eps.as<T>(), L.f.as<T>(), a, first_color, tx, ty, nb);
+    k_sweep_fused<T><<<padded, FNT, 0, s>>>(uin, uout, L.eps.as<T>(), L.f.as<T>(), a, first_color, tx, ty, kc, nb);
     DWP_LAUNCH_CHECK();
 }
 

@@ -33,7 +33,7 @@ def test_plan_rejects_bad_grid_sizes(n):
 @pytest.mark.parametrize("kw", [dict(precision=2), dict(tol=0.0), dict(tol=1.5), dict(restart=0),
                                 dict(restart=64), dict(cycles=0), dict(pre=0, post=0), dict(max_outer=0),
                                 dict(z_wet_lo=8.0, z_wet_hi=8.5), dict(z_wet_lo=0.0, z_wet_hi=20.0),
-                                dict(profile=2), dict(scaled_dry=3)])
+                                dict(profile=3), dict(scaled_dry=3)])
 def test_plan_rejects_bad_options(kw):
     with pytest.raises(B.DWPError) as e:
         B.plan((32, 32, 64), (10.0, 10.0, 20.0), **kw)
