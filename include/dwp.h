@@ -185,8 +185,10 @@ int dwp_eps_pair_gradient(dwp_ctx *ctx, const double *a_dev, const double *b_dev
 
 /* dE/dR (n x 3, host) for the last solution: sum_n (dE/d eps_n) d eps_n/dR_I
  * + h^3 sum_n phi_n d rho_n / dR_I (Eq. 11).  The atoms and parameters must
- * be those eps and rho were built from.  params == NULL means eps does not
- * depend on the atoms (caller-supplied eps): only the charge term is
+ * be those eps and rho were built from: the switch term reuses the switch
+ * product stored by dwp_build_epsilon, and positions, radii or parameters
+ * that differ from that build give DWP_ESTATE.  params == NULL means eps does
+ * not depend on the atoms (caller-supplied eps): only the charge term is
  * returned.  Forces are F = -dE/dR. */
 int dwp_forces(dwp_ctx *ctx, int n, const double *xyz_host, const double *radius_host,
                const double *q_host, const double *sigma_host, const dwp_eps_params *params,

@@ -154,6 +154,8 @@ struct dwp_ctx {
     // atom bookkeeping of the last build_epsilon
     int eps_natoms = -1;
     bool eps_exclusion = false;
+    std::vector<double> atom_rec;      // host copy of the last atom upload
+    std::vector<double> eps_geometry;  // switch geometry of the last build_epsilon
 };
 
 namespace dwp {

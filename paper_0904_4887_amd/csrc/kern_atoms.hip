@@ -8,10 +8,11 @@
 // atoms (the smooth counterpart of the paper's Eq. 19).
 //
 // Forces: dE/dR_I = sum_n g_n d eps_n/dR_I + h^3 sum_n phi_n d rho_n/dR_I with
-// g = dE/d eps.  The switch part uses the product of the OTHER switches at
-// each node, evaluated directly (never as S / s_I, since s_I may vanish).  The
-// height-factor part of buried atoms depends on z only and is reduced per
-// plane first.  All sums are per block, then per atom in a fixed order.
+// g = dE/d eps.  The switch part needs the product of the OTHER switches at
+// each node; it is S_n / s_I(n) with S_n = prod_i s_i(n) kept from the eps
+// build (s_I > 0 wherever its derivative is non-zero).  The height-factor part
+// of buried atoms depends on z only and is reduced per plane first.  All sums
+// are per block, then per atom in a fixed order.
 //
 // Packed atom record (8 doubles): x, y, z, radius, q, sigma, buried, 0.
 #include "dwp_internal.h"
@@ -157,14 +158,17 @@ __global__ void k_height(const double *__restrict__ atoms, int natoms, int nz, d
 }
 
 // ---------------------------------------------------------------- forces
-// Block = (atom a, chunk c) over the cube of nodes around atom a.
+// Block = (atom a, chunk of the (x, y) columns of the cube around atom a).
+// A thread walks one column in z over the chord inside the cut-off ball.
+// The product of the OTHER switches at a node is S_n / s_a(n), with S_n the
+// product of all switches stored when eps was built: on the shell where
+// atom a's switch varies (|t| < 6), s_a >= erfc(6)/2 > 0, and S_n = 0
+// exactly where any other switch vanishes, so the quotient is the product
+// itself up to rounding.
 __global__ void __launch_bounds__(AT_THREADS)
-k_forces(const double *__restrict__ atoms, int natoms, Box b, int eps_mode, double eps_inf, double delta,
-         const double *__restrict__ phi, const double *__restrict__ g, const double *__restrict__ Hz,
-         int nchunk, double *__restrict__ fpart) {
-    __shared__ double ax[AT_THREADS], ay[AT_THREADS], az[AT_THREADS], ar[AT_THREADS];
-    __shared__ int scan[AT_THREADS];
-    __shared__ int cnt;
+k_forces(const double *__restrict__ atoms, Box b, int eps_mode, double eps_inf, double delta,
+         const double *__restrict__ phi, const double *__restrict__ g, const double *__restrict__ S,
+         const double *__restrict__ Hz, int nchunk, double *__restrict__ fpart) {
     __shared__ double red[3][AT_THREADS / 64];
     const int a = blockIdx.x / nchunk, chunk = blockIdx.x % nchunk;
     const double *ra = atoms + (size_t)a * AREC;
@@ -173,74 +177,53 @@ k_forces(const double *__restrict__ atoms, int natoms, Box b, int eps_mode, doub
     const double crho = 9.0 * Sg;
     const double Rc = fmax(ceps, crho);
     const double h3 = b.hx * b.hy * b.hz;
-    const double gnorm = Q * pow(2.0 * PI * Sg * Sg, -1.5);
+    const double gnorm = h3 * Q * pow(2.0 * PI * Sg * Sg, -1.5) / (Sg * Sg);
+    const double inv2s2 = 1.0 / (2.0 * Sg * Sg);
+    const double wz_eps = -(eps_inf - 1.0) / (delta * SQRT_PI);
     // node ranges (unwrapped indices)
     const int ilo = (int)ceil((X - Rc) / b.hx), ihi = (int)floor((X + Rc) / b.hx);
     const int jlo = (int)ceil((Y - Rc) / b.hy), jhi = (int)floor((Y + Rc) / b.hy);
     const int klo = (int)ceil((Z - Rc) / b.hz), khi = (int)floor((Z + Rc) / b.hz);
-    const int cx = ihi - ilo + 1, cy = jhi - jlo + 1, cz = khi - klo + 1;
-    const long total = (long)cx * cy * cz;
-    // neighbours whose switch can be != 1 where atom a's switch varies
-    int m = 0;
-    if (eps_mode) {
-        for (int base = 0; base < natoms; base += AT_THREADS) {
-            const int j = base + threadIdx.x;
-            int keep = 0;
-            double px = 0, py = 0, pz = 0, pr = 0;
-            if (j < natoms && j != a) {
-                const double *r = atoms + (size_t)j * AREC;
-                px = r[0]; py = r[1]; pz = r[2]; pr = r[3];
-                const double dx = min_image(px - X, b.Lx, b.iLx), dy = min_image(py - Y, b.Ly, b.iLy),
-                             dz = min_image(pz - Z, b.Lz, b.iLz);
-                const double lim = ceps + pr + 6.0 * delta;
-                keep = dx * dx + dy * dy + dz * dz < lim * lim;
-            }
-            int tot;
-            const int slot = block_compact(keep, scan, &tot);
-            if (keep && m + slot < AT_THREADS) { ax[m + slot] = px; ay[m + slot] = py; az[m + slot] = pz; ar[m + slot] = pr; }
-            if (threadIdx.x == 0) cnt = m + tot;
-            __syncthreads();
-            m = cnt;
-            __syncthreads();
-        }
-        if (m > AT_THREADS) m = AT_THREADS;  // guarded by the host (see launch_forces)
-    }
-    const long per = (total + nchunk - 1) / nchunk;
-    const long q0 = (long)chunk * per, q1 = min(total, q0 + per);
+    const int cx = ihi - ilo + 1, cy = jhi - jlo + 1;
+    const int ncol = cx * cy;
+    const int per = (ncol + nchunk - 1) / nchunk;
+    const int c0 = chunk * per, c1 = min(ncol, c0 + per);
+    const size_t plane = (size_t)b.nx * b.ny;
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    for (long q = q0 + threadIdx.x; q < q1; q += AT_THREADS) {
-        const int ii = (int)(q % cx), jj = (int)((q / cx) % cy), kk = (int)(q / ((long)cx * cy));
-        const int iu = ilo + ii, ju = jlo + jj, ku = klo + kk;
-        const int i = ((iu % b.nx) + b.nx) % b.nx, j = ((ju % b.ny) + b.ny) % b.ny, k = ((ku % b.nz) + b.nz) % b.nz;
-        const double x = i * b.hx, y = j * b.hy, z = k * b.hz;
-        const double dx = min_image(x - X, b.Lx, b.iLx), dy = min_image(y - Y, b.Ly, b.iLy), dz = min_image(z - Z, b.Lz, b.iLz);
-        const double d2 = dx * dx + dy * dy + dz * dz;
-        const size_t c = ((size_t)k * b.ny + j) * b.nx + i;
-        // charge term: d rho_n / dR_a = q G(d) (r_n - R_a) / sigma^2
-        if (d2 < crho * crho) {
-            const double w = h3 * phi[c] * gnorm * exp(-d2 / (2.0 * Sg * Sg)) / (Sg * Sg);
-            fx += w * dx; fy += w * dy; fz += w * dz;
-        }
-        if (eps_mode) {
-            const double d = sqrt(d2);
-            const double t = (d - Ra) / delta;
-            if (t > -6.0 && t < 6.0 && d > 0.0) {
-                double P = 1.0;
-                for (int s = 0; s < m; ++s) {
-                    const double ex = min_image(x - ax[s], b.Lx, b.iLx), ey = min_image(y - ay[s], b.Ly, b.iLy),
-                                 ez = min_image(z - az[s], b.Lz, b.iLz);
-                    const double ts = (sqrt(ex * ex + ey * ey + ez * ez) - ar[s]) / delta;
-                    if (ts <= -6.0) { P = 0.0; break; }
-                    if (ts < 6.0) P *= 0.5 * (1.0 + erf(ts));
-                }
-                if (P != 0.0) {
-                    const double H = Hz ? Hz[k] : 1.0;
-                    const double ds = exp(-t * t) / (delta * SQRT_PI);
-                    // d d / dR_a = -(r - R_a) / d
-                    const double w = -g[c] * (eps_inf - 1.0) * H * P * ds / d;
-                    fx += w * dx; fy += w * dy; fz += w * dz;
+    for (int col = c0 + (int)threadIdx.x; col < c1; col += AT_THREADS) {
+        const int iu = ilo + col % cx, ju = jlo + col / cx;
+        const int i = ((iu % b.nx) + b.nx) % b.nx, j = ((ju % b.ny) + b.ny) % b.ny;
+        const double dx = min_image(i * b.hx - X, b.Lx, b.iLx), dy = min_image(j * b.hy - Y, b.Ly, b.iLy);
+        const double dxy2 = dx * dx + dy * dy;
+        if (dxy2 >= Rc * Rc) continue;
+        const double dzm = sqrt(Rc * Rc - dxy2);
+        const int kl = max(klo, (int)ceil((Z - dzm) / b.hz)), kh = min(khi, (int)floor((Z + dzm) / b.hz));
+        const size_t colbase = (size_t)j * b.nx + i;
+        int k = ((kl % b.nz) + b.nz) % b.nz;
+        for (int ku = kl; ku <= kh; ++ku) {
+            const double dz = min_image(k * b.hz - Z, b.Lz, b.iLz);
+            const double d2 = dx * dx + dy * dy + dz * dz;
+            const size_t c = (size_t)k * plane + colbase;
+            // charge term: d rho_n / dR_a = q G(d) (r_n - R_a) / sigma^2
+            if (d2 < crho * crho) {
+                const double w = gnorm * phi[c] * exp(-d2 * inv2s2);
+                fx += w * dx; fy += w * dy; fz += w * dz;
+            }
+            if (eps_mode) {
+                const double d = sqrt(d2);
+                const double t = (d - Ra) / delta;
+                if (t > -6.0 && t < 6.0 && d > 0.0) {
+                    const double Sv = S[c];
+                    if (Sv != 0.0) {
+                        const double H = Hz ? Hz[k] : 1.0;
+                        const double sa = 0.5 * (1.0 + erf(t));
+                        // d eps / dR_a = (eps_inf - 1) H (S / s_a) s_a'(t) (-(r - R_a) / (d delta))
+                        const double w = wz_eps * g[c] * H * (Sv / sa) * exp(-t * t) / d;
+                        fx += w * dx; fy += w * dy; fz += w * dz;
+                    }
                 }
             }
+            k = (k + 1 == b.nz) ? 0 : k + 1;
         }
     }
     // block reduction of (fx, fy, fz)
@@ -347,7 +330,7 @@ void launch_build_eps(hipStream_t s, const Plan &p, int n, const double *atoms_d
     }
     dim3 g((p.nx + TX - 1) / TX, (p.ny + TY - 1) / TY, (p.nz + TZ - 1) / TZ);
     k_build<0><<<g, AT_THREADS, 0, s>>>(atoms_dev, n, b, ap.eps_inf, ap.delta, ap.exclusion ? Hz : nullptr, eps,
-                                        ap.exclusion ? S : nullptr);
+                                        S);
     DWP_LAUNCH_CHECK();
 }
 
@@ -369,8 +352,8 @@ void launch_forces(hipStream_t s, const Plan &p, int n, const double *atoms_dev,
     Box b = make_box(p);
     const int nch = chunks_for(n);
     const bool excl = ap && ap->exclusion;
-    k_forces<<<n * nch, AT_THREADS, 0, s>>>(atoms_dev, n, b, ap ? 1 : 0, ap ? ap->eps_inf : 1.0,
-                                            ap ? ap->delta : 1.0, phi, g, excl ? Hz : nullptr, nch, fpart);
+    k_forces<<<n * nch, AT_THREADS, 0, s>>>(atoms_dev, b, ap ? 1 : 0, ap ? ap->eps_inf : 1.0,
+                                            ap ? ap->delta : 1.0, phi, g, S, excl ? Hz : nullptr, nch, fpart);
     DWP_LAUNCH_CHECK();
     double *Q = fpart + (size_t)n * nch * 3;
     double *hf = Q + p.nz;

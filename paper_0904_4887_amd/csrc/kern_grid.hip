@@ -288,6 +288,22 @@ template <> __device__ __forceinline__ double cxv<double>(const LevelArgs &a, in
     return d == 0 ? a.cx : (d == 1 ? a.cy : a.cz);
 }
 
+// Gauss-Seidel value (off - f) / diag through the hardware reciprocal.  The
+// smoother only shapes the preconditioner, so the last bit of the quotient
+// does not matter; in FP64 two Newton steps bring the estimate to full
+// precision.
+__device__ __forceinline__ float gs_value(float off, float f, float diag) {
+    return (off - f) * __builtin_amdgcn_rcpf(diag);
+}
+__device__ __forceinline__ double gs_value(double off, double f, double diag) {
+    double r = __builtin_amdgcn_rcp(diag);
+    double e = __builtin_fma(-diag, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-diag, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    return (off - f) * r;
+}
+
 // Neighbour sums at ghosted index g of slab point (i, j): returns the
 // off-diagonal sum  sum_m w_m u_m  and the diagonal  sum_m w_m,
 // w_m = 1/2 (eps_n + eps_m) / h_d^2.
@@ -345,7 +361,7 @@ k_level_smooth(T *__restrict__ u, const T *__restrict__ e, const T *__restrict__
     const size_t g = li + plane;
     T off, diag;
     level_sums(u, e, a, i, j, g, off, diag);
-    u[g] = (off - f[li]) / diag;
+    u[g] = gs_value(off, f[li], diag);
 }
 
 // Coarsest level: `sweeps` red-black sweeps by one workgroup.
@@ -367,7 +383,7 @@ k_level_coarse(T *__restrict__ u, const T *__restrict__ e, const T *__restrict__
                 const size_t g = li + plane;
                 T off, diag;
                 level_sums(u, e, a, i, j, g, off, diag);
-                u[g] = (off - f[li]) / diag;
+                u[g] = gs_value(off, f[li], diag);
             }
             __syncthreads();
         }
@@ -501,22 +517,6 @@ constexpr int FNH = (FHX * FHY + FNT - 1) / FNT;  // halo-2 elements per thread
 constexpr int FNR = (FRX * FRY + FNT - 1) / FNT;  // halo-1 elements per thread
 constexpr int FUNROLL = 8;
 constexpr int FPD = 2;  // prefetch distance in plane steps (divides FUNROLL)
-
-// Gauss-Seidel value (off - f) / diag through the hardware reciprocal.  The
-// smoother only shapes the preconditioner, so the last bit of the quotient
-// does not matter; in FP64 two Newton steps bring the estimate to full
-// precision.
-__device__ __forceinline__ float gs_value(float off, float f, float diag) {
-    return (off - f) * __builtin_amdgcn_rcpf(diag);
-}
-__device__ __forceinline__ double gs_value(double off, double f, double diag) {
-    double r = __builtin_amdgcn_rcp(diag);
-    double e = __builtin_fma(-diag, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    e = __builtin_fma(-diag, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    return (off - f) * r;
-}
 
 template <class T>
 __device__ __forceinline__ T ld_off(const T *base, unsigned byte_off) {
@@ -700,7 +700,7 @@ __device__ void bt_smooth(const LevelDesc<T> &d, int color) {
         const size_t li = (size_t)kk * plane + (size_t)j * d.a.nx + i;
         T off, diag;
         level_sums(d.u, d.e, d.a, i, j, li + plane, off, diag);
-        d.u[li + plane] = (off - d.f[li]) / diag;
+        d.u[li + plane] = gs_value(off, d.f[li], diag);
     }
     __syncthreads();
 }

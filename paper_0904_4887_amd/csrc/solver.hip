@@ -486,27 +486,22 @@ void upload_atoms(dwp_ctx *c, int n, const double *xyz, const double *radius, co
         }
         rec[8 * a + 6] = (ep && ep->exclusion && xyz[3 * a + 2] <= ep->z_lim) ? 1.0 : 0.0;
     }
-    if (ep && radius) {
-        // the force kernel keeps at most 256 switch neighbours per atom
-        for (int a = 0; a < n; ++a) {
-            int cnt = 0;
-            for (int b2 = 0; b2 < n; ++b2) {
-                if (b2 == a) continue;
-                double d2 = 0;
-                for (int d = 0; d < 3; ++d) {
-                    double dd = rec[8 * a + d] - rec[8 * b2 + d];
-                    dd -= p.L[d] * std::nearbyint(dd / p.L[d]);
-                    d2 += dd * dd;
-                }
-                const double lim = radius[a] + radius[b2] + 12.0 * ep->delta;
-                if (d2 < lim * lim) ++cnt;
-            }
-            if (cnt > 255) fail(DWP_EINVAL, "more than 255 overlapping switches around one atom");
-        }
-    }
     c->atoms.alloc(sizeof(double) * rec.size());
     DWP_HIP(hipMemcpyAsync(c->atoms.p, rec.data(), sizeof(double) * rec.size(), hipMemcpyHostToDevice, c->stream));
     sync(c);  // rec goes out of scope
+    c->atom_rec.swap(rec);
+}
+
+// The switch geometry (wrapped positions, radii, buried flags) and the eps
+// parameters of an upload, as a flat list for comparison with the eps build.
+std::vector<double> switch_geometry(const dwp_ctx *c, const dwp_eps_params *ep) {
+    std::vector<double> g;
+    const size_t n = c->atom_rec.size() / 8;
+    g.reserve(5 * n + 5);
+    for (size_t a = 0; a < n; ++a)
+        for (int d : {0, 1, 2, 3, 6}) g.push_back(c->atom_rec[8 * a + d]);
+    g.insert(g.end(), {ep->eps_inf, ep->delta, (double)ep->exclusion, ep->z_lim, ep->delta_z});
+    return g;
 }
 
 void validate_grid(int nx, int ny, int nz, double Lx, double Ly, double Lz) {
@@ -598,6 +593,7 @@ void set_epsilon_impl(dwp_ctx *c, const double *eps_dev) {
     c->have_solution = false;
     c->eps_natoms = -1;
     c->eps_exclusion = false;
+    c->eps_geometry.clear();
 }
 
 void build_epsilon_impl(dwp_ctx *c, int n, const double *xyz, const double *radius, const dwp_eps_params *ep) {
@@ -606,10 +602,11 @@ void build_epsilon_impl(dwp_ctx *c, int n, const double *xyz, const double *radi
     if (!radius) fail(DWP_EINVAL, "radius is NULL");
     upload_atoms(c, n, xyz, radius, nullptr, nullptr, ep);
     AtomParams ap = atom_params(ep);
-    if (ep->exclusion) c->S.alloc(sizeof(double) * c->plan.N);
-    PROF(c, PG_BUILD, (ep->exclusion ? 16.0 : 8.0) * c->plan.N,
+    c->S.alloc(sizeof(double) * c->plan.N);
+    PROF(c, PG_BUILD, 16.0 * c->plan.N,
          launch_build_eps(c->stream, c->plan, n, c->atoms.as<double>(), ap, c->Hz.as<double>(), c->eps.as<double>(),
-                          ep->exclusion ? c->S.as<double>() : nullptr));
+                          c->S.as<double>()));
+    c->eps_geometry = switch_geometry(c, ep);
     prepare_eps(c);
     c->have_eps = true;
     c->have_solution = false;
@@ -685,6 +682,9 @@ void forces_impl(dwp_ctx *c, int n, const double *xyz, const double *radius, con
         if ((ep->exclusion != 0) != c->eps_exclusion) fail(DWP_ESTATE, "exclusion differs from the eps build");
     }
     upload_atoms(c, n, xyz, ep ? radius : nullptr, q, sigma, ep);
+    // the switch term divides the switch product S stored by the eps build
+    if (ep && switch_geometry(c, ep) != c->eps_geometry)
+        fail(DWP_ESTATE, "positions, radii or eps parameters differ from the last dwp_build_epsilon");
     Plan &p = c->plan;
     AtomParams ap{};
     if (ep) ap = atom_params(ep);

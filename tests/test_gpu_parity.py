@@ -142,6 +142,13 @@ def test_forces_and_eps_gradient_match_oracle(torch, exclusion):
     phi_o = O.solve(rho, eps, s.h, tol=1e-13)
     F_o = O.forces(w.n, w.L, w.xyz, w.radius, w.q, w.sigma, w.eps_params, phi_o, O.eps_gradient(phi_o, s.h))
     assert np.abs(F - F_o).max() <= 1e-8 * np.abs(F_o).max()
+    # the switch term needs the atoms eps was built from
+    from paper_0904_4887_amd.binding import DWPError, DWP_ESTATE
+    moved = w.xyz.copy()
+    moved[3, 0] += 0.01
+    with pytest.raises(DWPError) as e:
+        s.forces(moved, w.q, w.sigma, w.radius, w.eps_params)
+    assert e.value.status == DWP_ESTATE
 
 
 # ---------------------------------------------------------------- error paths
