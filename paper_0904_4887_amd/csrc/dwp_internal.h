@@ -236,6 +236,9 @@ void launch_multidot(hipStream_t s, const double *V, size_t ldv, int nv, const d
 // w -= sum_i c[i] V_i ; if norm_out: *norm_out = ||w||^2
 void launch_axpy_multi(hipStream_t s, double *w, const double *V, size_t ldv, int nv,
                        const double *c, size_t n, double sign, double *partial, double *norm_out);
+bool orth_update_supported(const double *V, size_t ldv, int nv, size_t n);
+void launch_orth_update(hipStream_t s, double *w, const double *V, size_t ldv, int nv, double *hc, size_t n,
+                        double *partial);
 // energy sums: out[0] = sum rho phi (compensated), out[1] = sum_faces eps_f (D_f phi)^2
 void launch_energy(hipStream_t s, const Plan &p, const double *rho, const double *phi,
                    const double *eps, double *partial, double *out);

@@ -91,6 +91,127 @@ k_multidot(const double *__restrict__ V, size_t ldv, int v0, int nv, const doubl
     }
 }
 
+// Sums over the block of NV per-thread values: out[q] valid in thread q.
+template <int NV>
+__device__ __forceinline__ void block_sums(const double (&v)[NV], double (*sh)[RED_THREADS / 64], double *out) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        const double r = wave_sum(v[q]);
+        if (lane == 0) sh[q][wid] = r;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < NV) {
+        double r = 0.0;
+        for (int w = 0; w < RED_THREADS / 64; ++w) r += sh[threadIdx.x][w];
+        out[threadIdx.x] = r;
+    }
+}
+
+// Pair-vectorised projection: NV dot products V_{v0+q} . w and (with_norm)
+// w . w over n2 element pairs (16-byte loads; every vector 16-byte aligned).
+template <int NV>
+__global__ void __launch_bounds__(RED_THREADS)
+k_multidot2(const double *__restrict__ V, size_t ldv, int v0, const double *__restrict__ w, size_t n2,
+            double *__restrict__ partial, int stride, int with_norm) {
+    __shared__ double sh[NV + 1][RED_THREADS / 64];
+    __shared__ double res[NV + 1];
+    const double2 *w2 = reinterpret_cast<const double2 *>(w);
+    double acc[NV + 1];
+#pragma unroll
+    for (int q = 0; q <= NV; ++q) acc[q] = 0.0;
+    for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n2; t += (size_t)gridDim.x * RED_THREADS) {
+        const double2 wt = w2[t];
+        double2 vq[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) vq[q] = reinterpret_cast<const double2 *>(V + (size_t)(v0 + q) * ldv)[t];
+        acc[NV] += wt.x * wt.x + wt.y * wt.y;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) acc[q] += vq[q].x * wt.x + vq[q].y * wt.y;
+    }
+    block_sums<NV + 1>(acc, sh, res);
+    if ((int)threadIdx.x < NV) partial[(size_t)blockIdx.x * stride + v0 + threadIdx.x] = res[threadIdx.x];
+    if (with_norm && threadIdx.x == NV) partial[(size_t)blockIdx.x * stride + NORM_SLOT] = res[NV];
+}
+
+// New Arnoldi vector in one pass: w <- (w - sum_q h_q V_q) / beta with
+// beta^2 = ||w||^2 - sum_q h_q^2 (Pythagoras on the projection just computed;
+// h at hc[0..NV), ||w||^2 at hc[NORM_SLOT]).  When cancellation leaves no
+// reliable beta (beta^2 <= 1e-20 ||w||^2) the divisor is 1.  Block 0 stores
+// the divisor at *beta_out; partial[b] receives block b's share of the new
+// squared norm, which the caller uses to rescale when it is not 1.
+template <int NV>
+__global__ void __launch_bounds__(RED_THREADS)
+k_orth_update2(double *__restrict__ w, const double *__restrict__ V, size_t ldv, const double *__restrict__ hc,
+               size_t n2, double *__restrict__ partial, double *__restrict__ beta_out) {
+    __shared__ double sh[1][RED_THREADS / 64];
+    __shared__ double cs[NV + 1];
+    __shared__ double res[1];
+    if (threadIdx.x == 0) {
+        double h2 = 0.0;
+        for (int q = 0; q < NV; ++q) h2 += hc[q] * hc[q];
+        const double w2n = hc[NORM_SLOT], b2 = w2n - h2;
+        const double beta = (b2 > 1e-20 * w2n) ? sqrt(b2) : 1.0;
+        cs[NV] = 1.0 / beta;
+        if (blockIdx.x == 0) *beta_out = beta;
+    }
+    if ((int)threadIdx.x < NV) cs[threadIdx.x] = -hc[threadIdx.x];
+    __syncthreads();
+    const double sc = cs[NV];
+    double2 *w2 = reinterpret_cast<double2 *>(w);
+    double nrm[1] = {0.0};
+    for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n2; t += (size_t)gridDim.x * RED_THREADS) {
+        double2 acc = w2[t];
+        double2 vq[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) vq[q] = reinterpret_cast<const double2 *>(V + (size_t)q * ldv)[t];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            acc.x += cs[q] * vq[q].x;
+            acc.y += cs[q] * vq[q].y;
+        }
+        acc.x *= sc;
+        acc.y *= sc;
+        w2[t] = acc;
+        nrm[0] += acc.x * acc.x + acc.y * acc.y;
+    }
+    block_sums<1>(nrm, sh, res);
+    if (threadIdx.x == 0) partial[blockIdx.x] = res[0];
+}
+
+// x <- x / nu with nu = sqrt(*nu2), unless nu is 0 or within 1e-8 of 1.
+__global__ void __launch_bounds__(RED_THREADS)
+k_rescale_if(double *__restrict__ x, const double *__restrict__ nu2, size_t n) {
+    const double nu = sqrt(*nu2);
+    if (nu == 0.0 || fabs(nu - 1.0) <= 1e-8) return;
+    const double s = 1.0 / nu;
+    for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n; t += (size_t)gridDim.x * RED_THREADS)
+        x[t] *= s;
+}
+
+// Pair-vectorised w += sign * sum_q c[q] V_q (no norm).
+template <int NV>
+__global__ void __launch_bounds__(RED_THREADS)
+k_axpy2(double *__restrict__ w, const double *__restrict__ V, size_t ldv, const double *__restrict__ c, size_t n2,
+        double sign) {
+    __shared__ double cs[NV];
+    if ((int)threadIdx.x < NV) cs[threadIdx.x] = sign * c[threadIdx.x];
+    __syncthreads();
+    double2 *w2 = reinterpret_cast<double2 *>(w);
+    for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n2; t += (size_t)gridDim.x * RED_THREADS) {
+        double2 acc = w2[t];
+        double2 vq[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) vq[q] = reinterpret_cast<const double2 *>(V + (size_t)q * ldv)[t];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            acc.x += cs[q] * vq[q].x;
+            acc.y += cs[q] * vq[q].y;
+        }
+        w2[t] = acc;
+    }
+}
+
 // out[idx] = sum_b partial[b * stride + idx], one block per idx, fixed order
 __global__ void __launch_bounds__(RED_THREADS)
 k_reduce_partials(const double *__restrict__ partial, int nblocks, int stride, double *__restrict__ out) {
@@ -195,14 +316,38 @@ k_energy_final(const double *__restrict__ partial, int nblocks, double *__restri
 
 }  // namespace
 
+constexpr int MD2_GROUP = 16;  // dot products per pass of the pair-vectorised multidot
+
+bool pair_ok(const void *a, size_t ldv, size_t n) {
+    return n % 2 == 0 && ldv % 2 == 0 && (reinterpret_cast<uintptr_t>(a) & 15) == 0;
+}
+
+#define DWP_NV_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
 void launch_multidot(hipStream_t s, const double *V, size_t ldv, int nv, const double *w, size_t n,
                      double *partial, double *out, double *norm_out) {
     if (nv > 64) fail(DWP_EINVAL, "multidot: at most 64 vectors");
-    for (int v0 = 0; v0 < nv; v0 += MD_GROUP) {
-        const int g = nv - v0 < MD_GROUP ? nv - v0 : MD_GROUP;
-        k_multidot<<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, v0, g, w, n, partial, MD_STRIDE,
-                                                      (v0 == 0 && norm_out) ? 1 : 0);
-        DWP_LAUNCH_CHECK();
+    if (pair_ok(V, ldv, n) && pair_ok(w, 0, n)) {
+        for (int v0 = 0; v0 < nv; v0 += MD2_GROUP) {
+            const int g = nv - v0 < MD2_GROUP ? nv - v0 : MD2_GROUP;
+            const int wn = (v0 == 0 && norm_out) ? 1 : 0;
+            switch (g) {
+#define DWP_MD_CASE(K)                                                                                       \
+    case K:                                                                                                  \
+        k_multidot2<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, v0, w, n / 2, partial, MD_STRIDE, wn);     \
+        break;
+                DWP_NV_CASES(DWP_MD_CASE)
+#undef DWP_MD_CASE
+            }
+            DWP_LAUNCH_CHECK();
+        }
+    } else {
+        for (int v0 = 0; v0 < nv; v0 += MD_GROUP) {
+            const int g = nv - v0 < MD_GROUP ? nv - v0 : MD_GROUP;
+            k_multidot<<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, v0, g, w, n, partial, MD_STRIDE,
+                                                          (v0 == 0 && norm_out) ? 1 : 0);
+            DWP_LAUNCH_CHECK();
+        }
     }
     k_reduce_partials<<<nv, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, MD_STRIDE, out);
     DWP_LAUNCH_CHECK();
@@ -226,12 +371,45 @@ void launch_sum(hipStream_t s, const double *x, size_t n, double *partial, doubl
 void launch_axpy_multi(hipStream_t s, double *w, const double *V, size_t ldv, int nv, const double *c, size_t n,
                        double sign, double *partial, double *norm_out) {
     if (nv > 64) fail(DWP_EINVAL, "axpy_multi: at most 64 vectors");
+    if (!norm_out && nv <= 16 && pair_ok(V, ldv, n) && pair_ok(w, 0, n)) {
+        switch (nv) {
+#define DWP_AX_CASE(K)                                                                     \
+    case K: k_axpy2<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, V, ldv, c, n / 2, sign); break;
+            DWP_NV_CASES(DWP_AX_CASE)
+#undef DWP_AX_CASE
+        }
+        DWP_LAUNCH_CHECK();
+        return;
+    }
     k_axpy_multi<<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, V, ldv, nv, c, n, sign, norm_out ? partial : nullptr);
     DWP_LAUNCH_CHECK();
     if (norm_out) {
         k_reduce_partials<<<1, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, 1, norm_out);
         DWP_LAUNCH_CHECK();
     }
+}
+
+bool orth_update_supported(const double *V, size_t ldv, int nv, size_t n) {
+    return nv >= 1 && nv <= 16 && pair_ok(V, ldv, n);
+}
+
+// w <- (w - sum_q hc[q] V_q) / beta (see k_orth_update2); hc[65] receives the
+// squared norm of the result and hc[66] the divisor beta; the result is then
+// rescaled to unit norm unless that norm is 0 or within 1e-8 of 1.
+void launch_orth_update(hipStream_t s, double *w, const double *V, size_t ldv, int nv, double *hc, size_t n,
+                        double *partial) {
+    if (!orth_update_supported(V, ldv, nv, n) || !pair_ok(w, 0, n)) fail(DWP_EINVAL, "internal: orth update layout");
+    switch (nv) {
+#define DWP_OU_CASE(K)                                                                                     \
+    case K: k_orth_update2<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, V, ldv, hc, n / 2, partial, hc + 66); break;
+        DWP_NV_CASES(DWP_OU_CASE)
+#undef DWP_OU_CASE
+    }
+    DWP_LAUNCH_CHECK();
+    k_reduce_partials<<<1, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, 1, hc + 65);
+    DWP_LAUNCH_CHECK();
+    k_rescale_if<<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, hc + 65, n);
+    DWP_LAUNCH_CHECK();
 }
 
 void launch_energy(hipStream_t s, const Plan &p, const double *rho, const double *phi, const double *eps,

@@ -325,8 +325,10 @@ void check_finite_dev(dwp_ctx *c, const double *x, const char *what) {
 // Each restart cycle is enqueued without host round trips: the Gram-Schmidt
 // coefficients, the norm of the new basis vector and its normalisation stay on
 // the device (one projection pass and one update pass of classical
-// Gram-Schmidt per step), and the host reads the whole Hessenberg matrix once
-// per cycle to solve the small least-squares problem.  A cycle always runs its
+// Gram-Schmidt per step; the update divides by the norm that Pythagoras gives
+// from the projection, so no separate normalisation pass is needed), and the
+// host reads the whole Hessenberg matrix once per cycle to solve the small
+// least-squares problem.  A cycle always runs its
 // m steps (capped by max_outer); the true residual is recomputed at the start
 // of every cycle, so the result meets the tolerance whatever the loss of
 // orthogonality.  Returns the number of steps; *rel receives the final true
@@ -339,10 +341,13 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
     const int m = o.restart;
     double *V = c->V.as<double>(), *Z = c->Z.as<double>();
     double *coef = c->coef.as<double>();
-    double *Hd = coef + HESS_OFFSET;   // column j at Hd + j * 72: [0..j] dots, 64 ||w||^2, 65 ||w'||^2
+    // column j at Hd + j * 72: [0..j] dots, 64 ||w||^2, 65 squared norm of the
+    // new vector before any rescaling, 66 the divisor of the fused update
+    double *Hd = coef + HESS_OFFSET;
     double *beta2 = coef + 8;
     double *part = c->partial.as<double>();
     std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), y(m);
+    std::vector<char> fused(m, 0);
     auto Hij = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
     int iters = 0;
     *restarts = 0;
@@ -365,8 +370,13 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
             PROF(c, PG_APPLY, 24.0 * N, launch_apply_full(s, p, Zj, c->eps.as<double>(), nullptr, Vn, false));
             const double md = 8.0 * N * (j + 2), ax = 8.0 * N * (j + 3);
             PROF(c, PG_MULTIDOT, md, launch_multidot(s, V, N, j + 1, Vn, N, part, hc, hc + 64));
-            PROF(c, PG_AXPY, ax, launch_axpy_multi(s, Vn, V, N, j + 1, hc, N, -1.0, part, hc + 65));
-            PROF(c, PG_VEC, 16.0 * N, launch_scale_dev(s, Vn, nullptr, hc + 65, N, 0));
+            fused[j] = orth_update_supported(V, N, j + 1, N);
+            if (fused[j]) {
+                PROF(c, PG_AXPY, ax, launch_orth_update(s, Vn, V, N, j + 1, hc, N, part));
+            } else {
+                PROF(c, PG_AXPY, ax, launch_axpy_multi(s, Vn, V, N, j + 1, hc, N, -1.0, part, hc + 65));
+                PROF(c, PG_VEC, 16.0 * N, launch_scale_dev(s, Vn, nullptr, hc + 65, N, 0));
+            }
         }
         iters += mm;
         DWP_HIP(hipMemcpyAsync(c->host, Hd, sizeof(double) * HESS_STRIDE * mm, hipMemcpyDeviceToHost, s));
@@ -379,7 +389,11 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
         for (int j = 0; j < mm; ++j) {
             const double *hc = c->host + (size_t)j * HESS_STRIDE;
             for (int i = 0; i <= j; ++i) Hij(i, j) = hc[i];
-            const double hn = std::sqrt(std::max(hc[65], 0.0));
+            // Fused update: the stored vector is (w - V h) / beta, rescaled by
+            // its norm nu only when nu is off 1 by more than 1e-8 (the same
+            // test the device made).  Otherwise: explicit norm.
+            double hn = std::sqrt(std::max(hc[65], 0.0));
+            if (fused[j] && hn != 0.0) hn = std::fabs(hn - 1.0) <= 1e-8 ? hc[66] : hc[66] * hn;
             if (!std::isfinite(hn)) fail(DWP_ENONFINITE, "Krylov basis is not finite");
             Hij(j + 1, j) = hn;
             for (int i = 0; i < j; ++i) {
