@@ -26,10 +26,26 @@ namespace {
 constexpr int FFT_THREADS = 512;
 constexpr int MAX_STAGES = 12;
 
+// Division by a small positive d through one multiply-high: with
+// m = floor(2^32 / d) + 1, floor(i * m / 2^32) = floor(i / d) whenever
+// i * d < 2^32, which holds for every index here (i, d < 2^16).  d = 1 is
+// handled by the callers.
+struct Div {
+    unsigned m;
+    int d;
+};
+Div make_div(int d) { return Div{d > 1 ? (unsigned)(0xFFFFFFFFu / (unsigned)d + 1u) : 0u, d}; }
+__device__ __forceinline__ int udiv(int i, Div q) { return q.d == 1 ? i : (int)__umulhi((unsigned)i, q.m); }
+
+// Radix plan of one axis with the per-stage constants: radix r, product p of
+// the earlier radices (and its divider), and the twiddle stride n / (p r).
 struct Radices {
     int n;
     int nst;
     int r[MAX_STAGES];
+    int p[MAX_STAGES];
+    unsigned pm[MAX_STAGES];
+    int tstride[MAX_STAGES];
 };
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -92,24 +108,24 @@ template <> __device__ __forceinline__ void dft<8>(double2 *x, bool inv) {
     x[7] = csub(ev[3], t3);
 }
 
-// One Stockham stage of radix R on B lines of length n held in LDS; element
-// t of line l sits at buf[l * ls + t * es].  p = product of the radices of
-// the earlier stages.  Butterfly i of a line reads x_q = buf[i + q n/R],
-// twiddles x_q by exp(-+2 pi i q (i mod p) / (p R)), and writes output r to
-// (i - i mod p) R + i mod p + r p.
+// One Stockham stage of radix R on B = 2^lb lines of length n held in LDS;
+// element t of line l sits at buf[l * ls + t * es].  p = product of the
+// radices of the earlier stages.  Butterfly i of a line reads
+// x_q = buf[i + q n/R], twiddles x_q by exp(-+2 pi i q (i mod p) / (p R)),
+// and writes output r to (i - i mod p) R + i mod p + r p.
 template <int R>
-__device__ void stage(double2 *buf, int n, int p, int B, int es, int ls, const double2 *__restrict__ tw,
-                      bool inv) {
+__device__ void stage(double2 *buf, int n, int p, unsigned pm, int tstride, int lb, int es, int ls,
+                      const double2 *__restrict__ tw, bool inv) {
     constexpr int K = (4096 / R + FFT_THREADS - 1) / FFT_THREADS;
     const int T = n / R;
-    const int items = B * T;
-    const int tstride = n / (p * R);
+    const int items = T << lb;
+    const int bmask = (1 << lb) - 1;
     double2 x[K][R];
 #pragma unroll
     for (int m = 0; m < K; ++m) {
         const int w = threadIdx.x + m * FFT_THREADS;
         if (w < items) {
-            const int l = w % B, i = w / B;
+            const int l = w & bmask, i = w >> lb;
 #pragma unroll
             for (int q = 0; q < R; ++q) x[m][q] = buf[l * ls + (i + q * T) * es];
         }
@@ -119,12 +135,13 @@ __device__ void stage(double2 *buf, int n, int p, int B, int es, int ls, const d
     for (int m = 0; m < K; ++m) {
         const int w = threadIdx.x + m * FFT_THREADS;
         if (w < items) {
-            const int l = w % B, i = w / B;
-            const int k = i % p;
+            const int l = w & bmask, i = w >> lb;
+            const int k = p > 1 ? i - p * (int)__umulhi((unsigned)i, pm) : 0;
             if (p > 1) {
+                const int kt = k * tstride;
 #pragma unroll
                 for (int q = 1; q < R; ++q) {
-                    double2 t = tw[q * k * tstride];
+                    double2 t = tw[q * kt];
                     if (inv) t.y = -t.y;
                     x[m][q] = cmul(x[m][q], t);
                 }
@@ -138,34 +155,32 @@ __device__ void stage(double2 *buf, int n, int p, int B, int es, int ls, const d
     __syncthreads();
 }
 
-__device__ void fft_lines(double2 *buf, const Radices &rd, int B, int es, int ls,
+__device__ void fft_lines(double2 *buf, const Radices &rd, int lb, int es, int ls,
                           const double2 *__restrict__ tw, bool inv) {
-    int p = 1;
     for (int s = 0; s < rd.nst; ++s) {
         const int R = rd.r[s];
-        if (R == 8) stage<8>(buf, rd.n, p, B, es, ls, tw, inv);
-        else if (R == 4) stage<4>(buf, rd.n, p, B, es, ls, tw, inv);
-        else if (R == 3) stage<3>(buf, rd.n, p, B, es, ls, tw, inv);
-        else stage<2>(buf, rd.n, p, B, es, ls, tw, inv);
-        p *= R;
+        if (R == 8) stage<8>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
+        else if (R == 4) stage<4>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
+        else if (R == 3) stage<3>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
+        else stage<2>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
     }
 }
 
 // ---------------------------------------------------------------- x passes
-// Rows are the nx-long x lines of the [nz][ny][nx] grid; B complex lines per
-// block carry 2B real rows.  LDS lines are padded to n + 1 elements.
+// Rows are the nx-long x lines of the [nz][ny][nx] grid; B = 2^lb complex
+// lines per block carry 2B real rows.  LDS lines are padded to n + 1 elements.
 __global__ void __launch_bounds__(FFT_THREADS)
 k_fft_x_fwd(const double *__restrict__ in, const double *__restrict__ sinv, double2 *__restrict__ out,
-            Radices rd, const double2 *__restrict__ tw, int B, int nrows, int nkx, int ldc) {
+            Radices rd, const double2 *__restrict__ tw, int lb, int nrows, int nkx, int ldc, Div dn, Div dk) {
     extern __shared__ double2 lds[];
-    const int n = rd.n, ls = n + 1;
+    const int n = rd.n, ls = n + 1, B = 1 << lb;
     const int r0 = blockIdx.x * 2 * B;
     for (int e = threadIdx.x; e < B * n; e += FFT_THREADS) {
-        const int l = e / n, t = e % n;
+        const int l = udiv(e, dn), t = e - l * n;
         const int ra = r0 + 2 * l, rb = ra + 1;
         double a = 0.0, b = 0.0;
         if (rb < nrows) {
-            const size_t ia = (size_t)ra * n + t, ib = (size_t)rb * n + t;
+            const size_t ia = (size_t)ra * n + t, ib = ia + n;
             a = in[ia];
             b = in[ib];
             if (sinv) { a *= sinv[ia]; b *= sinv[ib]; }
@@ -173,9 +188,9 @@ k_fft_x_fwd(const double *__restrict__ in, const double *__restrict__ sinv, doub
         lds[l * ls + t] = make_double2(a, b);
     }
     __syncthreads();
-    fft_lines(lds, rd, B, 1, ls, tw, false);
+    fft_lines(lds, rd, lb, 1, ls, tw, false);
     for (int e = threadIdx.x; e < B * nkx; e += FFT_THREADS) {
-        const int l = e / nkx, k = e % nkx;
+        const int l = udiv(e, dk), k = e - l * nkx;
         const int ra = r0 + 2 * l, rb = ra + 1;
         if (rb >= nrows) continue;
         const double2 z = lds[l * ls + k];
@@ -190,12 +205,12 @@ k_fft_x_fwd(const double *__restrict__ in, const double *__restrict__ sinv, doub
 
 __global__ void __launch_bounds__(FFT_THREADS)
 k_fft_x_inv(const double2 *__restrict__ in, const double *__restrict__ sinv, double *__restrict__ out,
-            Radices rd, const double2 *__restrict__ tw, int B, int nrows, int nkx, int ldc) {
+            Radices rd, const double2 *__restrict__ tw, int lb, int nrows, int nkx, int ldc, Div dn) {
     extern __shared__ double2 lds[];
-    const int n = rd.n, ls = n + 1;
+    const int n = rd.n, ls = n + 1, B = 1 << lb;
     const int r0 = blockIdx.x * 2 * B;
     for (int e = threadIdx.x; e < B * n; e += FFT_THREADS) {
-        const int l = e / n, k = e % n;
+        const int l = udiv(e, dn), k = e - l * n;
         const int ra = r0 + 2 * l, rb = ra + 1;
         double2 z = make_double2(0.0, 0.0);
         if (rb < nrows) {
@@ -208,13 +223,13 @@ k_fft_x_inv(const double2 *__restrict__ in, const double *__restrict__ sinv, dou
         lds[l * ls + k] = z;
     }
     __syncthreads();
-    fft_lines(lds, rd, B, 1, ls, tw, true);
+    fft_lines(lds, rd, lb, 1, ls, tw, true);
     for (int e = threadIdx.x; e < B * n; e += FFT_THREADS) {
-        const int l = e / n, t = e % n;
+        const int l = udiv(e, dn), t = e - l * n;
         const int ra = r0 + 2 * l, rb = ra + 1;
         if (rb >= nrows) continue;
         const double2 z = lds[l * ls + t];
-        const size_t ia = (size_t)ra * n + t, ib = (size_t)rb * n + t;
+        const size_t ia = (size_t)ra * n + t, ib = ia + n;
         if (sinv) {
             out[ia] = z.x * sinv[ia];
             out[ib] = z.y * sinv[ib];
@@ -226,63 +241,70 @@ k_fft_x_inv(const double2 *__restrict__ in, const double *__restrict__ sinv, dou
 }
 
 // ---------------------------------------------------------------- y pass
-// Block (tile of B consecutive kx, plane z): lines along y, LDS element
-// (y, l) at y * B + l.
+// Block (tile of B = 2^lb consecutive kx, plane z): lines along y, LDS
+// element (y, l) at y * B + l.
 __global__ void __launch_bounds__(FFT_THREADS)
-k_fft_y(double2 *__restrict__ c, Radices rd, const double2 *__restrict__ tw, int B, int nkx, int ldc, int inv) {
+k_fft_y(double2 *__restrict__ c, Radices rd, const double2 *__restrict__ tw, int lb, int nkx, int ldc, int inv) {
     extern __shared__ double2 lds[];
-    const int ny = rd.n;
+    const int ny = rd.n, B = 1 << lb, bmask = B - 1;
     const int kx0 = blockIdx.x * B;
     const int z = blockIdx.y;
     const int bw = min(B, nkx - kx0);
     const size_t base = (size_t)z * ny * ldc + kx0;
     for (int e = threadIdx.x; e < B * ny; e += FFT_THREADS) {
-        const int y = e / B, l = e % B;
-        lds[y * B + l] = (l < bw) ? c[base + (size_t)y * ldc + l] : make_double2(0.0, 0.0);
+        const int y = e >> lb, l = e & bmask;
+        lds[e] = (l < bw) ? c[base + (size_t)y * ldc + l] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    fft_lines(lds, rd, B, B, 1, tw, inv != 0);
+    fft_lines(lds, rd, lb, B, 1, tw, inv != 0);
     for (int e = threadIdx.x; e < B * ny; e += FFT_THREADS) {
-        const int y = e / B, l = e % B;
-        if (l < bw) c[base + (size_t)y * ldc + l] = lds[y * B + l];
+        const int y = e >> lb, l = e & bmask;
+        if (l < bw) c[base + (size_t)y * ldc + l] = lds[e];
     }
 }
 
 // ---------------------------------------------------------------- z pass + Green
+// -1 / lambda through the hardware reciprocal and two Newton steps.
+__device__ __forceinline__ double neg_recip(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = __builtin_fma(-d, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-d, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    return -r;
+}
+
 __global__ void __launch_bounds__(FFT_THREADS)
-k_fft_z_green(double2 *__restrict__ c, Radices rd, const double2 *__restrict__ tw, int B, int nkx, int ldc, int ny,
+k_fft_z_green(double2 *__restrict__ c, Radices rd, const double2 *__restrict__ tw, int lb, int nkx, int ldc, int ny,
               const double *__restrict__ lamx, const double *__restrict__ lamy,
               const double *__restrict__ lamz, double inv_n) {
     extern __shared__ double2 lds[];
-    const int nz = rd.n;
+    const int nz = rd.n, B = 1 << lb, bmask = B - 1;
     const int kx0 = blockIdx.x * B;
     const int y = blockIdx.y;
     const int bw = min(B, nkx - kx0);
     const size_t zstride = (size_t)ny * ldc;
     const size_t base = (size_t)y * ldc + kx0;
     for (int e = threadIdx.x; e < B * nz; e += FFT_THREADS) {
-        const int z = e / B, l = e % B;
-        lds[z * B + l] = (l < bw) ? c[base + (size_t)z * zstride + l] : make_double2(0.0, 0.0);
+        const int z = e >> lb, l = e & bmask;
+        lds[e] = (l < bw) ? c[base + (size_t)z * zstride + l] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    fft_lines(lds, rd, B, B, 1, tw, false);
+    fft_lines(lds, rd, lb, B, 1, tw, false);
     const double ly = lamy[y];
     for (int e = threadIdx.x; e < B * nz; e += FFT_THREADS) {
-        const int z = e / B, l = e % B;
+        const int z = e >> lb, l = e & bmask;
         const int kx = kx0 + l;
         double g = 0.0;
-        if (l < bw) {
-            const double lam = lamx[kx] + ly + lamz[z];
-            g = (kx == 0 && y == 0 && z == 0) ? 0.0 : -inv_n / lam;
-        }
-        double2 v = lds[z * B + l];
-        lds[z * B + l] = make_double2(v.x * g, v.y * g);
+        if (l < bw && (kx | y | z) != 0) g = inv_n * neg_recip(lamx[kx] + ly + lamz[z]);
+        const double2 v = lds[e];
+        lds[e] = make_double2(v.x * g, v.y * g);
     }
     __syncthreads();
-    fft_lines(lds, rd, B, B, 1, tw, true);
+    fft_lines(lds, rd, lb, B, 1, tw, true);
     for (int e = threadIdx.x; e < B * nz; e += FFT_THREADS) {
-        const int z = e / B, l = e % B;
-        if (l < bw) c[base + (size_t)z * zstride + l] = lds[z * B + l];
+        const int z = e >> lb, l = e & bmask;
+        if (l < bw) c[base + (size_t)z * zstride + l] = lds[e];
     }
 }
 
@@ -290,18 +312,23 @@ Radices radices_of(const FFTAxis &ax) {
     Radices r{};
     r.n = ax.n;
     r.nst = (int)ax.radices.size();
-    for (int s = 0; s < r.nst; ++s) r.r[s] = ax.radices[s];
+    int p = 1;
+    for (int s = 0; s < r.nst; ++s) {
+        r.r[s] = ax.radices[s];
+        r.p[s] = p;
+        r.pm[s] = make_div(p).m;
+        r.tstride[s] = ax.n / (p * ax.radices[s]);
+        p *= ax.radices[s];
+    }
     return r;
 }
 
-// Lines per block: at most budget / n, capped at 16, rounded down to a
-// multiple of 8 (whole 128-byte segments of the padded spectrum) when >= 8.
-int tile_lines(int n, int budget) {
-    int B = budget / n;
-    if (B > 16) B = 16;
-    if (B >= 8) B -= B % 8;
-    if (B < 1) B = 1;
-    return B;
+// Lines per block: the largest power of two with B * n <= budget, capped at
+// 16 (16 lines of the padded spectrum are 256 contiguous bytes).
+int tile_log2(int n, int budget) {
+    int lb = 0;
+    while (lb < 4 && (2 << lb) * n <= budget) ++lb;
+    return lb;
 }
 
 }  // namespace
@@ -347,37 +374,38 @@ void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const
     auto pe = [&](int ev, int g, double b) { if (prof) prof->end(st, ev, g, b); };
     int ev;
     const int nrows = p.ny * p.nz;
-    const int Bx = tile_lines(p.nx, 2048);
+    const int lbx = tile_log2(p.nx, 2048), Bx = 1 << lbx;
     const int gx = (nrows + 2 * Bx - 1) / (2 * Bx);
     const size_t ldsx = sizeof(double2) * Bx * (p.nx + 1);
+    const Div dn = make_div(p.nx), dk = make_div(p.nkx);
     ev = pb(PG_FFT_X);
-    k_fft_x_fwd<<<gx, FFT_THREADS, ldsx, st>>>(r, sinv, cbuf, radices_of(ax), ax.tw.as<double2>(), Bx, nrows, p.nkx,
-                                               p.ldc);
+    k_fft_x_fwd<<<gx, FFT_THREADS, ldsx, st>>>(r, sinv, cbuf, radices_of(ax), ax.tw.as<double2>(), lbx, nrows, p.nkx,
+                                               p.ldc, dn, dk);
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_X, bx);
-    const int By = tile_lines(p.ny, 4096);
+    const int lby = tile_log2(p.ny, 4096), By = 1 << lby;
     dim3 gy((p.nkx + By - 1) / By, p.nz);
     ev = pb(PG_FFT_Y);
-    k_fft_y<<<gy, FFT_THREADS, sizeof(double2) * By * p.ny, st>>>(cbuf, radices_of(ay), ay.tw.as<double2>(), By, p.nkx,
-                                                                  p.ldc, 0);
+    k_fft_y<<<gy, FFT_THREADS, sizeof(double2) * By * p.ny, st>>>(cbuf, radices_of(ay), ay.tw.as<double2>(), lby,
+                                                                  p.nkx, p.ldc, 0);
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_Y, 32.0 * C);
-    const int Bz = tile_lines(p.nz, 4096);
+    const int lbz = tile_log2(p.nz, 4096), Bz = 1 << lbz;
     dim3 gz((p.nkx + Bz - 1) / Bz, p.ny);
     ev = pb(PG_FFT_Z);
     k_fft_z_green<<<gz, FFT_THREADS, sizeof(double2) * Bz * p.nz, st>>>(
-        cbuf, radices_of(az), az.tw.as<double2>(), Bz, p.nkx, p.ldc, p.ny, ax.lam.as<double>(), ay.lam.as<double>(),
+        cbuf, radices_of(az), az.tw.as<double2>(), lbz, p.nkx, p.ldc, p.ny, ax.lam.as<double>(), ay.lam.as<double>(),
         az.lam.as<double>(), 1.0 / (double)p.N);
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_Z, 32.0 * C);
     ev = pb(PG_FFT_Y);
-    k_fft_y<<<gy, FFT_THREADS, sizeof(double2) * By * p.ny, st>>>(cbuf, radices_of(ay), ay.tw.as<double2>(), By, p.nkx,
-                                                                  p.ldc, 1);
+    k_fft_y<<<gy, FFT_THREADS, sizeof(double2) * By * p.ny, st>>>(cbuf, radices_of(ay), ay.tw.as<double2>(), lby,
+                                                                  p.nkx, p.ldc, 1);
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_Y, 32.0 * C);
     ev = pb(PG_FFT_X);
-    k_fft_x_inv<<<gx, FFT_THREADS, ldsx, st>>>(cbuf, sinv, out, radices_of(ax), ax.tw.as<double2>(), Bx, nrows, p.nkx,
-                                               p.ldc);
+    k_fft_x_inv<<<gx, FFT_THREADS, ldsx, st>>>(cbuf, sinv, out, radices_of(ax), ax.tw.as<double2>(), lbx, nrows, p.nkx,
+                                               p.ldc, dn);
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_X, bx);
 }
