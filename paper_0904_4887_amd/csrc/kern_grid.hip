@@ -59,6 +59,11 @@ __device__ __forceinline__ int xcd_tile(int nb_real) {
     return (blockIdx.x % 8) * per + blockIdx.x / 8;
 }
 
+template <class T>
+__device__ __forceinline__ T ld_at(const T *base, unsigned byte_off) {
+    return *(const T *)((const char *)base + byte_off);
+}
+
 template <class T, int MODE>
 __global__ void __launch_bounds__(BX *BY)
 k_apply_zmarch(const double *__restrict__ phi, const double *__restrict__ eps, const double *__restrict__ b,
@@ -70,45 +75,48 @@ k_apply_zmarch(const double *__restrict__ phi, const double *__restrict__ eps, c
     const int i = tx * BX + threadIdx.x, j = ty * BY + threadIdx.y;
     if (i >= nx || j >= ny) return;
     const size_t plane = (size_t)nx * ny;
-    const size_t col = (size_t)j * nx + i;
-    const int ixp = wrap_p(i, nx) - i, ixm = wrap_m(i, nx) - i;
-    const long jyp = (long)(wrap_p(j, ny) - j) * nx, jym = (long)(wrap_m(j, ny) - j) * nx;
+    // byte offsets inside a plane (the plane base pointers are uniform)
+    const int col = j * nx + i;
+    const unsigned oc = (unsigned)col * 8u;
+    const unsigned oxp = (unsigned)(j * nx + wrap_p(i, nx)) * 8u, oxm = (unsigned)(j * nx + wrap_m(i, nx)) * 8u;
+    const unsigned oyp = (unsigned)(wrap_p(j, ny) * nx + i) * 8u, oym = (unsigned)(wrap_m(j, ny) * nx + i) * 8u;
     const int kk0 = tz * ZM, kk1 = min(nplanes, kk0 + ZM);
     auto boxk = [&](int kk) { return MODE == 2 ? (k_w0 + kk) % nz : kk; };
+    auto P = [&](int k) { return phi + (size_t)k * plane; };
+    auto E = [&](int k) { return eps + (size_t)k * plane; };
     // Software pipeline: the centre values of plane k+1 and the in-plane
     // neighbours of plane k are loaded one plane ahead of their use.
     int k = boxk(kk0);
-    size_t c = (size_t)k * plane + col;
-    const size_t cm0 = (size_t)wrap_m(k, nz) * plane + col;
-    double pm = phi[cm0], em = eps[cm0], p0 = phi[c], e0 = eps[c];
+    const int km = wrap_m(k, nz);
+    double pm = ld_at(P(km), oc), em = ld_at(E(km), oc), p0 = ld_at(P(k), oc), e0 = ld_at(E(k), oc);
     double nb[8];
-    auto load_nb = [&](size_t cc, double *o) {
-        o[0] = phi[cc + ixp]; o[1] = eps[cc + ixp]; o[2] = phi[cc + ixm]; o[3] = eps[cc + ixm];
-        o[4] = phi[cc + jyp]; o[5] = eps[cc + jyp]; o[6] = phi[cc + jym]; o[7] = eps[cc + jym];
+    auto load_nb = [&](int kq, double *o) {
+        const double *pp = P(kq), *ee = E(kq);
+        o[0] = ld_at(pp, oxp); o[1] = ld_at(ee, oxp); o[2] = ld_at(pp, oxm); o[3] = ld_at(ee, oxm);
+        o[4] = ld_at(pp, oyp); o[5] = ld_at(ee, oyp); o[6] = ld_at(pp, oym); o[7] = ld_at(ee, oym);
     };
-    load_nb(c, nb);
+    load_nb(k, nb);
     int kp = wrap_p(k, nz);
-    size_t cp = (size_t)kp * plane + col;
-    double pp = phi[cp], ep = eps[cp];
+    double pp = ld_at(P(kp), oc), ep = ld_at(E(kp), oc);
     for (int kk = kk0; kk < kk1; ++kk) {
         // prefetch for plane kk + 1 (clamped inside the chunk: always a valid address)
         const bool more = kk + 1 < kk1;
         const int kn = wrap_p(kp, nz);
-        const size_t cn = (size_t)(more ? kn : kp) * plane + col;
+        const int kq = more ? kn : kp;
         double nb2[8];
-        load_nb(cp, nb2);
-        const double pq = phi[cn], eq = eps[cn];
+        load_nb(kp, nb2);
+        const double pq = ld_at(P(kq), oc), eq = ld_at(E(kq), oc);
         double acc = cx * ((e0 + nb[1]) * (nb[0] - p0) + (e0 + nb[3]) * (nb[2] - p0)) +
                      cy * ((e0 + nb[5]) * (nb[4] - p0) + (e0 + nb[7]) * (nb[6] - p0)) +
                      cz * ((e0 + ep) * (pp - p0) + (e0 + em) * (pm - p0));
         acc *= 0.5;
-        if (MODE == 0) out[c] = (T)acc;
-        else if (MODE == 1) out[c] = (T)(b[c] - acc);
-        else out[(size_t)kk * plane + col] = (T)(b[c] - acc);
+        if (MODE == 0) out[(size_t)k * plane + col] = (T)acc;
+        else if (MODE == 1) out[(size_t)k * plane + col] = (T)(ld_at(b + (size_t)k * plane, oc) - acc);
+        else out[(size_t)kk * plane + col] = (T)(ld_at(b + (size_t)k * plane, oc) - acc);
         pm = p0; em = e0; p0 = pp; e0 = ep; pp = pq; ep = eq;
 #pragma unroll
         for (int q = 0; q < 8; ++q) nb[q] = nb2[q];
-        k = kp; c = cp; kp = kn; cp = cn;
+        k = kp; kp = kn;
     }
 }
 
@@ -245,17 +253,24 @@ k_wet_residual(const double *__restrict__ v, const double *__restrict__ dD,
     fW[(size_t)kk * plane + (size_t)j * nx + i] = (T)(v[c] - 0.5 * acc);
 }
 
-// z at box plane (k_w0 + kk) mod nz += uW (ghosted plane kk + 1)
-template <class T>
-__global__ void k_wet_add(const T *__restrict__ uW, double *__restrict__ z, int nx, int ny, int nz,
-                          int k_w0, int nw) {
-    const size_t plane = (size_t)nx * ny;
-    const size_t total = plane * nw;
-    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
-        const int kk = (int)(t / plane);
-        const size_t rem = t - (size_t)kk * plane;
-        const int k = (k_w0 + kk) % nz;
-        z[(size_t)k * plane + rem] += (double)uW[(size_t)(kk + 1) * plane + rem];
+// z at box plane (k_w0 + kk) mod nz += uW (ghosted plane kk + 1).  Grid:
+// (plane chunks, kk); PAIRS: two consecutive points per thread (plane even,
+// z 16-byte aligned).
+template <class T, bool PAIRS>
+__global__ void k_wet_add(const T *__restrict__ uW, double *__restrict__ z, int plane, int nz, int k_w0) {
+    const int kk = blockIdx.y;
+    const int k = (k_w0 + kk) % nz;
+    const T *src = uW + (size_t)(kk + 1) * plane;
+    double *dst = z + (size_t)k * plane;
+    const int q = (PAIRS ? 2 : 1) * (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (q >= plane) return;
+    if (PAIRS) {
+        double2 v = *reinterpret_cast<double2 *>(dst + q);
+        v.x += (double)src[q];
+        v.y += (double)src[q + 1];
+        *reinterpret_cast<double2 *>(dst + q) = v;
+    } else {
+        dst[q] += (double)src[q];
     }
 }
 
@@ -327,6 +342,28 @@ __device__ __forceinline__ void level_sums(const T *__restrict__ u, const T *__r
     diag = T(0.5) * (wxp + wxm + wyp + wym + wzp + wzm);
 }
 
+// The same sums for kernels whose block lies in one plane: u0 and e0 point
+// at the ghosted plane BELOW the point (uniform over the block), so every
+// neighbour sits at a non-negative 32-bit offset from them.
+template <class T>
+__device__ __forceinline__ void level_sums_u(const T *__restrict__ u0, const T *__restrict__ e0p,
+                                             const LevelArgs &a, int i, int j, T &off, T &diag, T &uc) {
+    const int plane = a.nx * a.ny;
+    const int c = plane + j * a.nx + i;
+    const int rowb = c - i;
+    const int xp = rowb + wrap_p(i, a.nx), xm = rowb + wrap_m(i, a.nx);
+    const int yp = c + (wrap_p(j, a.ny) - j) * a.nx, ym = c + (wrap_m(j, a.ny) - j) * a.nx;
+    const T e0 = e0p[c];
+    const T cx = cxv<T>(a, 0), cy = cxv<T>(a, 1), cz = cxv<T>(a, 2);
+    const T wxp = cx * (e0 + e0p[xp]), wxm = cx * (e0 + e0p[xm]);
+    const T wyp = cy * (e0 + e0p[yp]), wym = cy * (e0 + e0p[ym]);
+    const T wzp = cz * (e0 + e0p[c + plane]), wzm = cz * (e0 + e0p[c - plane]);
+    off = T(0.5) * (wxp * u0[xp] + wxm * u0[xm] + wyp * u0[yp] + wym * u0[ym] + wzp * u0[c + plane] +
+                    wzm * u0[c - plane]);
+    diag = T(0.5) * (wxp + wxm + wyp + wym + wzp + wzm);
+    uc = u0[c];
+}
+
 // r = f - A u at every slab point (r, f not ghosted)
 template <class T>
 __global__ void __launch_bounds__(BX *BY)
@@ -337,11 +374,13 @@ k_level_residual(const T *__restrict__ u, const T *__restrict__ e, const T *__re
     const int kk = blockIdx.z;
     if (i >= a.nx || j >= a.ny) return;
     const size_t plane = (size_t)a.nx * a.ny;
-    const size_t li = (size_t)kk * plane + (size_t)j * a.nx + i;
-    const size_t g = li + plane;
-    T off, diag;
-    level_sums(u, e, a, i, j, g, off, diag);
-    r[li] = f[li] - (off - diag * u[g]);
+    const T *u0 = u + (size_t)kk * plane, *e0 = e + (size_t)kk * plane;
+    const T *fk = f + (size_t)kk * plane;
+    T *rk = r + (size_t)kk * plane;
+    T off, diag, uc;
+    level_sums_u(u0, e0, a, i, j, off, diag, uc);
+    const int li = j * a.nx + i;
+    rk[li] = fk[li] - (off - diag * uc);
 }
 
 // One colour of red-black Gauss-Seidel: points with (i + j + kk) % 2 == color
@@ -357,11 +396,12 @@ k_level_smooth(T *__restrict__ u, const T *__restrict__ e, const T *__restrict__
     const int i = 2 * t + ((j + kk + color) & 1);
     if (i >= a.nx || j >= a.ny) return;
     const size_t plane = (size_t)a.nx * a.ny;
-    const size_t li = (size_t)kk * plane + (size_t)j * a.nx + i;
-    const size_t g = li + plane;
-    T off, diag;
-    level_sums(u, e, a, i, j, g, off, diag);
-    u[g] = gs_value(off, f[li], diag);
+    T *u0 = u + (size_t)kk * plane;
+    const T *e0 = e + (size_t)kk * plane;
+    T off, diag, uc;
+    level_sums_u<T>(u0, e0, a, i, j, off, diag, uc);
+    const int li = j * a.nx + i;
+    u0[a.nx * a.ny + li] = gs_value(off, f[(size_t)kk * plane + li], diag);
 }
 
 // Coarsest level: `sweeps` red-black sweeps by one workgroup.
@@ -393,66 +433,63 @@ k_level_coarse(T *__restrict__ u, const T *__restrict__ e, const T *__restrict__
 // Full weighting: 1/4, 1/2, 1/4 along every coarsened direction (periodic in
 // x, y; in z the three fine planes 2kc, 2kc+1, 2kc+2 all lie inside the slab).
 // The coarse unknowns (ghosted array uc) are zeroed in the same launch.
+// Grid: (x tiles, y tiles, coarse plane kc).
 template <class T>
-__global__ void k_restrict(const T *__restrict__ rf, T *__restrict__ fc, T *__restrict__ uc, int nxf, int nyf,
-                           int nxc, int nyc, int nwc, int zc) {
-    const size_t ng = (size_t)nxc * nyc * (nwc + 2);
-    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < ng; q += (size_t)gridDim.x * blockDim.x)
-        uc[q] = T(0);
+__global__ void __launch_bounds__(BX *BY)
+k_restrict(const T *__restrict__ rf, T *__restrict__ fc, T *__restrict__ uc, int nxf, int nyf, int nxc, int nyc,
+           int nwc, int zc) {
+    const int ic = blockIdx.x * BX + threadIdx.x, jc = blockIdx.y * BY + threadIdx.y, kc = blockIdx.z;
+    if (ic >= nxc || jc >= nyc) return;
     const size_t planec = (size_t)nxc * nyc, planef = (size_t)nxf * nyf;
-    const size_t total = planec * nwc;
+    const int cidx = jc * nxc + ic;
+    uc[(size_t)(kc + 1) * planec + cidx] = T(0);
+    if (kc == 0) uc[cidx] = T(0);
+    if (kc == nwc - 1) uc[(size_t)(nwc + 1) * planec + cidx] = T(0);
     const T w3[3] = {T(0.25), T(0.5), T(0.25)};
-    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < total; q += (size_t)gridDim.x * blockDim.x) {
-        const int ic = (int)(q % nxc);
-        const int jc = (int)((q / nxc) % nyc);
-        const int kc = (int)(q / planec);
-        T acc = T(0);
-        const int nzt = zc ? 3 : 1;
-        for (int dz = 0; dz < nzt; ++dz) {
-            const int kf = zc ? 2 * kc + dz : kc;
-            const T wz = zc ? w3[dz] : T(1);
-            for (int dy = -1; dy <= 1; ++dy) {
-                const int jf = (2 * jc + dy + nyf) % nyf;
-                const T wy = w3[dy + 1];
-                const size_t rb = (size_t)kf * planef + (size_t)jf * nxf;
-                const int i0 = 2 * ic;
-                const T sx = T(0.25) * rf[rb + (i0 == 0 ? nxf - 1 : i0 - 1)] + T(0.5) * rf[rb + i0] +
-                             T(0.25) * rf[rb + (i0 + 1 == nxf ? 0 : i0 + 1)];
-                acc += wz * wy * sx;
-            }
+    const int i0 = 2 * ic;
+    const int im = i0 == 0 ? nxf - 1 : i0 - 1, ip = i0 + 1 == nxf ? 0 : i0 + 1;
+    T acc = T(0);
+    const int nzt = zc ? 3 : 1;
+    for (int dz = 0; dz < nzt; ++dz) {
+        const int kf = zc ? 2 * kc + dz : kc;
+        const T wz = zc ? w3[dz] : T(1);
+        const T *pf = rf + (size_t)kf * planef;
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int jf = (2 * jc + dy + nyf) % nyf;
+            const T *row = pf + jf * nxf;
+            const T sx = T(0.25) * row[im] + T(0.5) * row[i0] + T(0.25) * row[ip];
+            acc += wz * w3[dy + 1] * sx;
         }
-        fc[q] = acc;
     }
+    fc[(size_t)kc * planec + cidx] = acc;
 }
 
-// Trilinear interpolation of the coarse correction, added to the fine unknowns.
+// Trilinear interpolation of the coarse correction, added to the fine
+// unknowns.  Grid: (x tiles, y tiles, fine plane kf).
 template <class T>
-__global__ void k_prolong_add(T *__restrict__ uf, const T *__restrict__ uc, int nxf, int nyf,
-                              int nwf, int nxc, int nyc, int zc) {
+__global__ void __launch_bounds__(BX *BY)
+k_prolong_add(T *__restrict__ uf, const T *__restrict__ uc, int nxf, int nyf, int nxc, int nyc, int zc) {
+    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, kf = blockIdx.z;
+    if (i >= nxf || j >= nyf) return;
     const size_t planef = (size_t)nxf * nyf, planec = (size_t)nxc * nyc;
-    const size_t total = planef * nwf;
-    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < total; q += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(q % nxf);
-        const int j = (int)((q / nxf) % nyf);
-        const int kf = (int)(q / planef);
-        int ix[2], jy[2], pz[2];
-        T wx[2], wyv[2], wz[2];
-        int nxs, nys, nzs;
-        if (i & 1) { ix[0] = i >> 1; ix[1] = (ix[0] + 1 == nxc) ? 0 : ix[0] + 1; wx[0] = wx[1] = T(0.5); nxs = 2; }
-        else { ix[0] = i >> 1; wx[0] = T(1); nxs = 1; }
-        if (j & 1) { jy[0] = j >> 1; jy[1] = (jy[0] + 1 == nyc) ? 0 : jy[0] + 1; wyv[0] = wyv[1] = T(0.5); nys = 2; }
-        else { jy[0] = j >> 1; wyv[0] = T(1); nys = 1; }
-        if (zc) {
-            if (kf & 1) { pz[0] = (kf - 1) / 2 + 1; wz[0] = T(1); nzs = 1; }
-            else { pz[0] = kf / 2; pz[1] = kf / 2 + 1; wz[0] = wz[1] = T(0.5); nzs = 2; }
-        } else { pz[0] = kf + 1; wz[0] = T(1); nzs = 1; }
-        T acc = T(0);
-        for (int a = 0; a < nzs; ++a)
-            for (int b = 0; b < nys; ++b)
-                for (int c = 0; c < nxs; ++c)
-                    acc += wz[a] * wyv[b] * wx[c] * uc[(size_t)pz[a] * planec + (size_t)jy[b] * nxc + ix[c]];
-        uf[q + planef] += acc;
+    int ix[2], jy[2], pz[2];
+    T wx[2], wyv[2], wz[2];
+    int nxs, nys, nzs;
+    if (i & 1) { ix[0] = i >> 1; ix[1] = (ix[0] + 1 == nxc) ? 0 : ix[0] + 1; wx[0] = wx[1] = T(0.5); nxs = 2; }
+    else { ix[0] = i >> 1; ix[1] = 0; wx[0] = T(1); wx[1] = T(0); nxs = 1; }
+    if (j & 1) { jy[0] = j >> 1; jy[1] = (jy[0] + 1 == nyc) ? 0 : jy[0] + 1; wyv[0] = wyv[1] = T(0.5); nys = 2; }
+    else { jy[0] = j >> 1; jy[1] = 0; wyv[0] = T(1); wyv[1] = T(0); nys = 1; }
+    if (zc) {
+        if (kf & 1) { pz[0] = (kf - 1) / 2 + 1; pz[1] = 0; wz[0] = T(1); wz[1] = T(0); nzs = 1; }
+        else { pz[0] = kf / 2; pz[1] = kf / 2 + 1; wz[0] = wz[1] = T(0.5); nzs = 2; }
+    } else { pz[0] = kf + 1; pz[1] = 0; wz[0] = T(1); wz[1] = T(0); nzs = 1; }
+    T acc = T(0);
+    for (int a = 0; a < nzs; ++a) {
+        const T *pc = uc + (size_t)pz[a] * planec;
+        for (int b = 0; b < nys; ++b)
+            for (int c = 0; c < nxs; ++c) acc += wz[a] * wyv[b] * wx[c] * pc[jy[b] * nxc + ix[c]];
     }
+    uf[(size_t)(kf + 1) * planef + j * nxf + i] += acc;
 }
 
 // Coarse node eps by full weighting of the fine node eps (ghost planes map to
@@ -909,8 +946,12 @@ void launch_wet_residual(hipStream_t s, const Plan &p, const double *v, const do
 }
 template <class T>
 void launch_wet_add(hipStream_t s, const Plan &p, const T *uW, double *z) {
-    const size_t n = (size_t)p.nx * p.ny * p.nw;
-    k_wet_add<T><<<grid1d(n), 256, 0, s>>>(uW, z, p.nx, p.ny, p.nz, p.k_w0, p.nw);
+    const int plane = p.nx * p.ny;
+    const bool pairs = plane % 2 == 0 && (reinterpret_cast<uintptr_t>(z) & 15) == 0;
+    const int per = pairs ? plane / 2 : plane;
+    dim3 g((per + 255) / 256, p.nw);
+    if (pairs) k_wet_add<T, true><<<g, 256, 0, s>>>(uW, z, plane, p.nz, p.k_w0);
+    else k_wet_add<T, false><<<g, 256, 0, s>>>(uW, z, plane, p.nz, p.k_w0);
     DWP_LAUNCH_CHECK();
 }
 template <class T>
@@ -943,14 +984,14 @@ void launch_level_coarse_solve(hipStream_t s, const Level &L, int sweeps) {
 }
 template <class T>
 void launch_restrict(hipStream_t s, const Level &F, const Level &C, const T *rf, T *fc) {
-    const size_t n = C.n_interior();
-    k_restrict<T><<<grid1d(n), 256, 0, s>>>(rf, fc, C.u.as<T>(), F.nx, F.ny, C.nx, C.ny, C.nw, C.zc ? 1 : 0);
+    dim3 g((C.nx + BX - 1) / BX, (C.ny + BY - 1) / BY, C.nw), blk(BX, BY);
+    k_restrict<T><<<g, blk, 0, s>>>(rf, fc, C.u.as<T>(), F.nx, F.ny, C.nx, C.ny, C.nw, C.zc ? 1 : 0);
     DWP_LAUNCH_CHECK();
 }
 template <class T>
 void launch_prolong_add(hipStream_t s, const Level &F, const Level &C) {
-    const size_t n = F.n_interior();
-    k_prolong_add<T><<<grid1d(n), 256, 0, s>>>(F.u.as<T>(), C.u.as<T>(), F.nx, F.ny, F.nw, C.nx, C.ny, C.zc ? 1 : 0);
+    dim3 g((F.nx + BX - 1) / BX, (F.ny + BY - 1) / BY, F.nw), blk(BX, BY);
+    k_prolong_add<T><<<g, blk, 0, s>>>(F.u.as<T>(), C.u.as<T>(), F.nx, F.ny, C.nx, C.ny, C.zc ? 1 : 0);
     DWP_LAUNCH_CHECK();
 }
 template <class T>
