@@ -120,6 +120,108 @@ k_apply_zmarch(const double *__restrict__ phi, const double *__restrict__ eps, c
     }
 }
 
+// The same operator with the plane tile staged in LDS.  A block owns a tile
+// of 64 x 8 points for a chunk of ZCH planes; each thread owns two adjacent x
+// points.  Per plane step the block loads the next plane's tile (phi and eps,
+// 1-cell halo in y, 2 in x to keep 16-byte alignment) with 16-byte loads into
+// a two-slot LDS ring, each thread loads its own two centre values three
+// planes ahead, and the in-plane neighbours come from LDS while the z
+// neighbours stay in registers.  One barrier per step: the slot written at
+// step k was last read at step k-1.  Needs nx even and every array 16-byte
+// aligned (the launcher checks).
+constexpr int ATX = 64, ATY = 8;            // points per tile
+constexpr int AHX2 = (ATX + 4) / 2;         // double2 per LDS row (x halo 2)
+constexpr int AHY = ATY + 2;                // rows (y halo 1)
+constexpr int AQ = AHX2 * AHY;              // double2 items per field per plane
+constexpr int AQT = (AQ + 255) / 256;       // per thread
+constexpr int ZCH = 16;                     // planes per block
+
+template <class T, int MODE>
+__global__ void __launch_bounds__(256)
+k_apply_tile(const double *__restrict__ phi, const double *__restrict__ eps, const double *__restrict__ b,
+             T *__restrict__ out, int nx, int ny, int nz, double cx, double cy, double cz, int k_w0, int nplanes,
+             int tiles_x, int tiles_y, int nb_real) {
+    __shared__ double2 sp[2][AQT * 256], se[2][AQT * 256];
+    const int t = xcd_tile(nb_real);
+    if (t >= nb_real) return;
+    const int i0 = (t % tiles_x) * ATX, j0 = ((t / tiles_x) % tiles_y) * ATY;
+    const int kk0 = (t / (tiles_x * tiles_y)) * ZCH, kk1 = min(nplanes, kk0 + ZCH);
+    const int tid = threadIdx.x + 32 * threadIdx.y;
+    const size_t plane = (size_t)nx * ny;
+    unsigned oq[AQT];
+#pragma unroll
+    for (int m = 0; m < AQT; ++m) {
+        const int q = min(tid + 256 * m, AQ - 1);  // padding lanes repeat the last item
+        const int xr = q % AHX2, yr = q / AHX2;
+        const int x = ((i0 - 2 + 2 * xr) % nx + nx) % nx, y = ((j0 - 1 + yr) % ny + ny) % ny;
+        oq[m] = (unsigned)(y * nx + x) * 8u;
+    }
+    const int lx = threadIdx.x, ly = threadIdx.y;
+    const int gi = i0 + 2 * lx, gj = j0 + ly;
+    const bool own = gi < nx && gj < ny;
+    const unsigned oc = own ? (unsigned)(gj * nx + gi) * 8u : 0u;
+    auto wrapk = [&](int k) { return k < 0 ? k + nz : (k >= nz ? k - nz : k); };
+    auto P = [&](int k) { return phi + (size_t)wrapk(k) * plane; };
+    auto E = [&](int k) { return eps + (size_t)wrapk(k) * plane; };
+    const int kb0 = MODE == 2 ? (k_w0 + kk0) % nz : kk0;  // box plane of the first step
+    double2 tp[AQT], te[AQT];
+    auto fetch_tile = [&](int k) {
+        const double *pp = P(k), *ee = E(k);
+#pragma unroll
+        for (int m = 0; m < AQT; ++m) {
+            tp[m] = ld_at((const double2 *)pp, oq[m]);
+            te[m] = ld_at((const double2 *)ee, oq[m]);
+        }
+    };
+    auto stash = [&](int slot) {
+#pragma unroll
+        for (int m = 0; m < AQT; ++m) {
+            sp[slot][tid + 256 * m] = tp[m];
+            se[slot][tid + 256 * m] = te[m];
+        }
+    };
+    double2 pm = ld_at((const double2 *)P(kb0 - 1), oc), em = ld_at((const double2 *)E(kb0 - 1), oc);
+    double2 p0 = ld_at((const double2 *)P(kb0), oc), e0 = ld_at((const double2 *)E(kb0), oc);
+    double2 pp = ld_at((const double2 *)P(kb0 + 1), oc), ep = ld_at((const double2 *)E(kb0 + 1), oc);
+    fetch_tile(kb0);
+    stash(0);
+    fetch_tile(kb0 + 1);
+    double2 pn = ld_at((const double2 *)P(kb0 + 2), oc), en = ld_at((const double2 *)E(kb0 + 2), oc);
+    const int r = ly + 1, c2 = lx + 1;
+    for (int kk = kk0; kk < kk1; ++kk) {
+        const int s = (kk - kk0) & 1;
+        const int k = wrapk(kb0 + (kk - kk0));  // box plane of this step
+        __syncthreads();
+        stash(s ^ 1);  // plane k + 1
+        fetch_tile(k + 2);
+        const double2 pq = ld_at((const double2 *)P(k + 3), oc), eq = ld_at((const double2 *)E(k + 3), oc);
+        const double2 *lp = sp[s], *le = se[s];
+        const double2 xl_p = lp[r * AHX2 + c2 - 1], xl_e = le[r * AHX2 + c2 - 1];
+        const double2 xr_p = lp[r * AHX2 + c2 + 1], xr_e = le[r * AHX2 + c2 + 1];
+        const double2 yu_p = lp[(r + 1) * AHX2 + c2], yu_e = le[(r + 1) * AHX2 + c2];
+        const double2 yd_p = lp[(r - 1) * AHX2 + c2], yd_e = le[(r - 1) * AHX2 + c2];
+        double a0 = cx * ((e0.x + e0.y) * (p0.y - p0.x) + (e0.x + xl_e.y) * (xl_p.y - p0.x)) +
+                    cy * ((e0.x + yu_e.x) * (yu_p.x - p0.x) + (e0.x + yd_e.x) * (yd_p.x - p0.x)) +
+                    cz * ((e0.x + ep.x) * (pp.x - p0.x) + (e0.x + em.x) * (pm.x - p0.x));
+        double a1 = cx * ((e0.y + xr_e.x) * (xr_p.x - p0.y) + (e0.y + e0.x) * (p0.x - p0.y)) +
+                    cy * ((e0.y + yu_e.y) * (yu_p.y - p0.y) + (e0.y + yd_e.y) * (yd_p.y - p0.y)) +
+                    cz * ((e0.y + ep.y) * (pp.y - p0.y) + (e0.y + em.y) * (pm.y - p0.y));
+        a0 *= 0.5;
+        a1 *= 0.5;
+        if (own) {
+            if (MODE == 0) {
+                *(double2 *)((char *)(out + (size_t)k * plane) + oc) = make_double2(a0, a1);
+            } else {
+                const double2 bv = ld_at((const double2 *)(b + (size_t)k * plane), oc);
+                const size_t dst = (size_t)(MODE == 1 ? k : kk) * plane + (size_t)(gj * nx + gi);
+                out[dst] = (T)(bv.x - a0);
+                out[dst + 1] = (T)(bv.y - a1);
+            }
+        }
+        pm = p0; em = e0; p0 = pp; e0 = ep; pp = pn; ep = en; pn = pq; en = eq;
+    }
+}
+
 // dE/d eps_n = -(h^3 / 8 pi) sum_d 1/2 [(D+ phi)^2 + (D- phi)^2]
 __global__ void __launch_bounds__(BX *BY)
 k_eps_gradient(const double *__restrict__ phi, double *__restrict__ g, int nx, int ny, int nz,
@@ -870,9 +972,21 @@ LevelArgs level_args(const Level &L) {
 }  // namespace
 
 // ============================================================== launchers
+static bool al16(const void *q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; }
+
 template <class T, int MODE>
 void launch_zmarch(hipStream_t s, const Plan &p, const double *phi, const double *eps, const double *b, T *out,
                    int nplanes) {
+    const bool tile_ok = p.nx % 2 == 0 && al16(phi) && al16(eps) && (MODE == 0 || al16(b)) && al16(out);
+    if (tile_ok) {
+        const int tx = (p.nx + ATX - 1) / ATX, ty = (p.ny + ATY - 1) / ATY, tz = (nplanes + ZCH - 1) / ZCH;
+        const int nb = tx * ty * tz, padded = (nb + 7) / 8 * 8;
+        k_apply_tile<T, MODE><<<padded, dim3(32, 8), 0, s>>>(phi, eps, b, out, p.nx, p.ny, p.nz,
+                                                             1.0 / (p.h[0] * p.h[0]), 1.0 / (p.h[1] * p.h[1]),
+                                                             1.0 / (p.h[2] * p.h[2]), p.k_w0, nplanes, tx, ty, nb);
+        DWP_LAUNCH_CHECK();
+        return;
+    }
     const int tx = (p.nx + BX - 1) / BX, ty = (p.ny + BY - 1) / BY, tz = (nplanes + ZM - 1) / ZM;
     const int nb = tx * ty * tz;
     const int padded = (nb + 7) / 8 * 8;
