@@ -649,11 +649,8 @@ __global__ void k_coarsen_eps(const T *__restrict__ ef, T *__restrict__ ec, int 
 // (read by the second colour one step later than by the first; 8 are kept).
 // The step loop is unrolled by 8 so that every ring slot is a constant.
 constexpr int FTX = 32, FTY = 8;
-constexpr int FHX = FTX + 4, FHY = FTY + 4;  // 2-cell halo
-constexpr int FRX = FTX + 2, FRY = FTY + 2;  // 1-cell halo
+constexpr int FRX = FTX + 2, FRY = FTY + 2;  // first-colour values: tile + 1-cell halo
 constexpr int FNT = FTX * FTY;               // threads
-constexpr int FNH = (FHX * FHY + FNT - 1) / FNT;  // halo-2 elements per thread
-constexpr int FNR = (FRX * FRY + FNT - 1) / FNT;  // halo-1 elements per thread
 constexpr int FUNROLL = 8;
 constexpr int FPD = 2;  // prefetch distance in plane steps (divides FUNROLL)
 
@@ -662,15 +659,40 @@ __device__ __forceinline__ T ld_off(const T *base, unsigned byte_off) {
     return *(const T *)((const char *)base + byte_off);
 }
 
-template <class T>
+// W-wide vector of T (16 or 8 bytes) for the tile loads: clang's native
+// vector types, which stay in registers (the HIP float4 / double2 structs held
+// in arrays can end up in scratch memory).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <class T, int W> struct FVec;
+template <> struct FVec<float, 4> { using V = f32x4; };
+template <> struct FVec<float, 2> { using V = f32x2; };
+template <> struct FVec<double, 2> { using V = f64x2; };
+
+// Tiles are loaded as W-wide vectors: the x range starts HL = W cells left of
+// the tile (a multiple of W, at least the 2-cell halo) and rows are
+// LW = FTX + 2 HL cells long.  u and eps carry a 2-cell halo in y, f a 1-cell
+// halo.  nx must be a multiple of W so that no vector straddles the wrap.
+template <int W> struct FLayout {
+    static constexpr int HL = W < 2 ? 2 : W;
+    static constexpr int LW = FTX + 2 * HL;
+    static constexpr int VR = LW / W;               // vectors per row
+    static constexpr int NVU = VR * (FTY + 4);      // u / eps vectors per plane
+    static constexpr int NVF = VR * (FTY + 2);      // f vectors per plane
+    static_assert(NVU <= FNT && NVF <= FNT, "one vector per thread");
+};
+
+template <class T, int W>
 __global__ void __launch_bounds__(FNT)
 k_sweep_fused(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ e, const T *__restrict__ f,
               LevelArgs a, int c0, int tiles_x, int tiles_y, int kc, int nb_real) {
-    // plane buffers padded to a whole number of per-thread elements, so that
-    // every thread stores unconditionally (the padding is never read)
-    __shared__ T su[4][FNH * FNT];
-    __shared__ T se[8][FNH * FNT];
-    __shared__ T sf[4][FNR * FNT];
+    using L = FLayout<W>;
+    using V = typename FVec<T, W>::V;
+    constexpr int LW = L::LW, HL = L::HL;
+    __shared__ __align__(16) T su[4][L::NVU * W];
+    __shared__ __align__(16) T se[8][L::NVU * W];
+    __shared__ __align__(16) T sf[4][L::NVF * W];
     __shared__ T sr[4][FRY * FRX];
     // XCD-aware order: each XCD gets a contiguous run of tiles (x fastest,
     // then y, then z chunk), so neighbouring tiles share its L2.
@@ -683,22 +705,23 @@ k_sweep_fused(const T *__restrict__ uin, T *__restrict__ uout, const T *__restri
     const T cx = cxv<T>(a, 0), cy = cxv<T>(a, 1), cz = cxv<T>(a, 2);
     const int tid = threadIdx.x;
     const int base_par = (i0 + j0) & 1;  // colour of local (x, y, m) = (base_par + x + y + m) & 1
-    // byte offsets inside a plane of the halo-2 and halo-1 positions this
-    // thread loads (periodic wrap in x and y)
-    unsigned oh[FNH], orr[FNR];
-#pragma unroll
-    for (int t = 0; t < FNH; ++t) {
-        const int q = tid + t * FNT;
-        const int x = q % FHX - 2, y = q / FHX - 2;
-        const int i = ((i0 + x) % nx + nx) % nx, j = ((j0 + y) % ny + ny) % ny;
-        oh[t] = (unsigned)((j * nx + i) * sizeof(T));
+    // This thread's vector of the u / eps tile and of the f tile: byte offset
+    // inside a plane (periodic wrap) and LDS element index.  Threads past the
+    // last vector repeat it and skip the LDS store.
+    const bool su_on = tid < L::NVU, sf_on = tid < L::NVF;
+    unsigned ohu, ohf;
+    int lhu, lhf;
+    {
+        const int q = min(tid, L::NVU - 1), xr = q % L::VR, yr = q / L::VR;
+        const int i = ((i0 - HL + W * xr) % nx + nx) % nx, j = ((j0 - 2 + yr) % ny + ny) % ny;
+        ohu = (unsigned)((j * nx + i) * sizeof(T));
+        lhu = yr * LW + W * xr;
     }
-#pragma unroll
-    for (int t = 0; t < FNR; ++t) {
-        const int q = tid + t * FNT;
-        const int x = q % FRX - 1, y = q / FRX - 1;
-        const int i = ((i0 + x) % nx + nx) % nx, j = ((j0 + y) % ny + ny) % ny;
-        orr[t] = (unsigned)((j * nx + i) * sizeof(T));
+    {
+        const int q = min(tid, L::NVF - 1), xr = q % L::VR, yr = q / L::VR;
+        const int i = ((i0 - HL + W * xr) % nx + nx) % nx, j = ((j0 - 1 + yr) % ny + ny) % ny;
+        ohf = (unsigned)((j * nx + i) * sizeof(T));
+        lhf = yr * LW + W * xr;
     }
     // first-colour work: thread tid < FRX*FRY/2 takes the tid-th first-colour
     // point of the tile + 1-cell halo (rows of FRX = 34 hold 17 of each colour)
@@ -712,57 +735,54 @@ k_sweep_fused(const T *__restrict__ uin, T *__restrict__ uout, const T *__restri
     const int c1 = blk_on ? 1 - c0 : c0;
     const int j_out = j0 + by;
 
-    T pu[FPD][FNH], pe[FPD][FNH], pf[FPD][FNR];
+    V pu[FPD], pe[FPD], pf[FPD];
     // Loads are unconditional: plane indices are clamped into the ghosted
     // range, which is harmless because values of planes outside [-1, nw] (f:
     // outside [0, nw)) are never used.  Keeping the loads free of branches and
     // selects lets them stay in flight for FPD steps.
-    auto fetch = [&](int k, T *du, T *de, T *df) {
+    auto fetch = [&](int k, V &du, V &de, V &df) {
         const int kk = min(max(k, -1), nw), kf = min(max(k, 0), nw - 1);
         const T *bu = uin + (size_t)(kk + 1) * plane, *be = e + (size_t)(kk + 1) * plane;
         const T *bf = f + (size_t)kf * plane;
-#pragma unroll
-        for (int t = 0; t < FNH; ++t) {
-            du[t] = ld_off(bu, oh[t]);
-            de[t] = ld_off(be, oh[t]);
-        }
-#pragma unroll
-        for (int t = 0; t < FNR; ++t) df[t] = ld_off(bf, orr[t]);
+        du = *(const V *)((const char *)bu + ohu);
+        de = *(const V *)((const char *)be + ohu);
+        df = *(const V *)((const char *)bf + ohf);
     };
     // Ring slot of plane p: its local index p - k0 + 2 modulo the ring depth.
     // Step ls works on m = k0 - 1 + ls, so plane m + d has local index
     // ls + 1 + d; ls is passed modulo 8 (a compile-time constant below).
-    auto stash = [&](int lp, const T *du, const T *de, const T *df) {
-        T *lu = su[lp & 3], *le = se[lp & 7], *lf = sf[lp & 3];
-#pragma unroll
-        for (int t = 0; t < FNH; ++t) { lu[tid + t * FNT] = du[t]; le[tid + t * FNT] = de[t]; }
-#pragma unroll
-        for (int t = 0; t < FNR; ++t) lf[tid + t * FNT] = df[t];
+    auto stash = [&](int lp, const V &du, const V &de, const V &df) {
+        if (su_on) {
+            *(V *)&su[lp & 3][lhu] = du;
+            *(V *)&se[lp & 7][lhu] = de;
+        }
+        if (sf_on) *(V *)&sf[lp & 3][lhf] = df;
     };
     auto update = [&](const T *el, const T *ep, const T *en, int h, T uxp, T uxm, T uyp, T uym, T uzp, T uzm,
                       T fv) {
         const T e0 = el[h];
         const T wxp = cx * (e0 + el[h + 1]), wxm = cx * (e0 + el[h - 1]);
-        const T wyp = cy * (e0 + el[h + FHX]), wym = cy * (e0 + el[h - FHX]);
+        const T wyp = cy * (e0 + el[h + LW]), wym = cy * (e0 + el[h - LW]);
         const T wzp = cz * (e0 + ep[h]), wzm = cz * (e0 + en[h]);
         const T off = T(0.5) * (wxp * uxp + wxm * uxm + wyp * uyp + wym * uym + wzp * uzp + wzm * uzm);
         const T dg = T(0.5) * (wxp + wxm + wyp + wym + wzp + wzm);
         return gs_value(off, fv, dg);
     };
-    auto step = [&](int ls, int m, T *du, T *de, T *df) {
+    auto step = [&](int ls, int m, V &du, V &de, V &df) {
         const int l0 = ls + 1;     // local index of plane m
-        stash(l0 + 1, du, de, df);    // plane m + 1, fetched FPD steps ago
+        stash(l0 + 1, du, de, df);  // plane m + 1, fetched FPD steps ago
         fetch(m + 1 + FPD, du, de, df);  // in flight for the next FPD steps
         __syncthreads();
         if (red_on) {  // first colour at plane m on the tile + 1-cell halo
             const int off = (c0 - base_par - ry - m + 1) & 1;
             const int x = -1 + 2 * rt + off;
-            const int q = (ry + 1) * FRX + (x + 1), h = (ry + 2) * FHX + (x + 2);
+            const int q = (ry + 1) * FRX + (x + 1);
+            const int h = (ry + 2) * LW + (x + HL), hf = (ry + 1) * LW + (x + HL);
             T v = T(0);
             if (m >= 0 && m < nw) {
                 const T *um = su[l0 & 3];
-                v = update(se[l0 & 7], se[(l0 + 1) & 7], se[(l0 + 7) & 7], h, um[h + 1], um[h - 1], um[h + FHX],
-                           um[h - FHX], su[(l0 + 1) & 3][h], su[(l0 + 3) & 3][h], sf[l0 & 3][q]);
+                v = update(se[l0 & 7], se[(l0 + 1) & 7], se[(l0 + 7) & 7], h, um[h + 1], um[h - 1], um[h + LW],
+                           um[h - LW], su[(l0 + 1) & 3][h], su[(l0 + 3) & 3][h], sf[l0 & 3][hf]);
             }
             sr[l0 & 3][q] = v;
         }
@@ -777,9 +797,9 @@ k_sweep_fused(const T *__restrict__ uin, T *__restrict__ uout, const T *__restri
             const T *rm = sr[lk & 3];
             T v = rm[r];
             if (blk_on) {
-                const int h = (by + 2) * FHX + (x + 2);
+                const int h = (by + 2) * LW + (x + HL), hf = (by + 1) * LW + (x + HL);
                 v = update(se[lk & 7], se[(lk + 1) & 7], se[(lk + 7) & 7], h, rm[r + 1], rm[r - 1], rm[r + FRX],
-                           rm[r - FRX], sr[(lk + 1) & 3][r], sr[(lk + 3) & 3][r], sf[lk & 3][r]);
+                           rm[r - FRX], sr[(lk + 1) & 3][r], sr[(lk + 3) & 3][r], sf[lk & 3][hf]);
             }
             // Every thread stores once per step, so the compiler can count the
             // outstanding memory operations exactly (a conditional store would
@@ -1130,7 +1150,7 @@ static int fused_chunk(int tiles, int nw, int slots) {
     return best;
 }
 
-template <class T>
+template <class T, int W>
 static int fused_slots() {
     static int slots[64] = {0};
     int dev = 0;
@@ -1139,21 +1159,33 @@ static int fused_slots() {
     if (!slots[dev]) {
         int cus = 0, per = 0;
         DWP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        DWP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_fused<T>, FNT, 0));
+        DWP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_fused<T, W>, FNT, 0));
         slots[dev] = std::max(1, cus * per);
     }
     return slots[dev];
 }
 
-template <class T>
-void launch_sweep_fused(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color) {
+template <class T, int W>
+static void sweep_fused_w(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color) {
     LevelArgs a = level_args(L);
     const int tx = (L.nx + FTX - 1) / FTX, ty = (L.ny + FTY - 1) / FTY;
-    const int kc = fused_chunk(tx * ty, L.nw, fused_slots<T>());
+    const int kc = fused_chunk(tx * ty, L.nw, fused_slots<T, W>());
     const int tz = (L.nw + kc - 1) / kc;
     const int nb = tx * ty * tz, padded = (nb + 7) / 8 * 8;
-    k_sweep_fused<T><<<padded, FNT, 0, s>>>(uin, uout, L.eps.as<T>(), L.f.as<T>(), a, first_color, tx, ty, kc, nb);
+    k_sweep_fused<T, W><<<padded, FNT, 0, s>>>(uin, uout, L.eps.as<T>(), L.f.as<T>(), a, first_color, tx, ty, kc, nb);
     DWP_LAUNCH_CHECK();
+}
+
+// 16-byte tile loads when nx allows (float: nx % 4 == 0), else 8-byte ones;
+// the level arrays come from hipMalloc and planes are whole vectors.
+template <>
+void launch_sweep_fused<float>(hipStream_t s, const Level &L, const float *uin, float *uout, int first_color) {
+    if (L.nx % 4 == 0) sweep_fused_w<float, 4>(s, L, uin, uout, first_color);
+    else sweep_fused_w<float, 2>(s, L, uin, uout, first_color);
+}
+template <>
+void launch_sweep_fused<double>(hipStream_t s, const Level &L, const double *uin, double *uout, int first_color) {
+    sweep_fused_w<double, 2>(s, L, uin, uout, first_color);
 }
 
 template <class T>
@@ -1196,8 +1228,7 @@ void launch_zero(hipStream_t s, T *x, size_t n) {
     template void launch_prolong_add<T>(hipStream_t, const Level &, const Level &);                   \
     template void launch_coarsen_eps<T>(hipStream_t, const Level &, const Level &);                   \
     template void launch_zero<T>(hipStream_t, T *, size_t);                                          \
-    template void launch_vcycle_bottom<T>(hipStream_t, const std::vector<Level *> &, size_t, int, int, int); \
-    template void launch_sweep_fused<T>(hipStream_t, const Level &, const T *, T *, int);
+    template void launch_vcycle_bottom<T>(hipStream_t, const std::vector<Level *> &, size_t, int, int, int);
 DWP_INST(float)
 DWP_INST(double)
 
