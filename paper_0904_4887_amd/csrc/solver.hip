@@ -327,12 +327,14 @@ void check_finite_dev(dwp_ctx *c, const double *x, const char *what) {
 // the device (one projection pass and one update pass of classical
 // Gram-Schmidt per step; the update divides by the norm that Pythagoras gives
 // from the projection, so no separate normalisation pass is needed), and the
-// host reads the whole Hessenberg matrix once per cycle to solve the small
-// least-squares problem.  A cycle always runs its
-// m steps (capped by max_outer); the true residual is recomputed at the start
-// of every cycle, so the result meets the tolerance whatever the loss of
-// orthogonality.  Returns the number of steps; *rel receives the final true
-// relative residual.
+// host reads the Hessenberg columns to solve the small least-squares problem.
+// The host looks at the columns only after the step from which the cycle may
+// meet the tolerance (predicted from the per-step residual reduction of the
+// previous cycle), and from there after every step, so that a cycle stops at
+// the first step whose least-squares residual meets the tolerance.  The true
+// residual is recomputed at the start of every cycle, so the result meets the
+// tolerance whatever the loss of orthogonality.  Returns the number of steps;
+// *rel receives the final true relative residual.
 int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, double *rel) {
     Plan &p = c->plan;
     const dwp_opts &o = c->opts;
@@ -349,6 +351,8 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
     std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), y(m);
     std::vector<char> fused(m, 0);
     auto Hij = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
+    const double target = o.tol * bnorm;
+    double rate = -1.0;  // per-step residual reduction of the last cycle (< 0: unknown)
     int iters = 0;
     *restarts = 0;
     for (;;) {
@@ -363,31 +367,21 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
         ++*restarts;
         PROF(c, PG_VEC, 16.0 * N, launch_scale_dev(s, V, nullptr, beta2, N, 0));
         const int mm = std::min(m, o.max_outer - iters);
-        for (int j = 0; j < mm; ++j) {
-            double *Vj = V + (size_t)j * N, *Vn = V + (size_t)(j + 1) * N, *Zj = Z + (size_t)j * N;
-            double *hc = Hd + (size_t)j * HESS_STRIDE;
-            apply_split(c, Vj, Zj);
-            PROF(c, PG_APPLY, 24.0 * N, launch_apply_full(s, p, Zj, c->eps.as<double>(), nullptr, Vn, false));
-            const double md = 8.0 * N * (j + 2), ax = 8.0 * N * (j + 3);
-            PROF(c, PG_MULTIDOT, md, launch_multidot(s, V, N, j + 1, Vn, N, part, hc, hc + 64));
-            fused[j] = orth_update_supported(V, N, j + 1, N);
-            if (fused[j]) {
-                PROF(c, PG_AXPY, ax, launch_orth_update(s, Vn, V, N, j + 1, hc, N, part));
-            } else {
-                PROF(c, PG_AXPY, ax, launch_axpy_multi(s, Vn, V, N, j + 1, hc, N, -1.0, part, hc + 65));
-                PROF(c, PG_VEC, 16.0 * N, launch_scale_dev(s, Vn, nullptr, hc + 65, N, 0));
-            }
+        // first step after which the host checks the least-squares residual
+        int check_from = mm;
+        if (rate > 0.0 && rate < 1.0) {
+            const double need = std::log(target / beta) / std::log(rate);
+            check_from = std::max(1, std::min(mm, (int)std::floor(need) - 1));
+        } else if (o.warm_start && *restarts == 1) {
+            check_from = std::max(1, mm / 2);
         }
-        iters += mm;
-        DWP_HIP(hipMemcpyAsync(c->host, Hd, sizeof(double) * HESS_STRIDE * mm, hipMemcpyDeviceToHost, s));
-        sync(c);
-        // Hessenberg matrix, Givens rotations, least squares (host, (m+1) x m)
         std::fill(H.begin(), H.end(), 0.0);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
-        int k = 0;
-        for (int j = 0; j < mm; ++j) {
-            const double *hc = c->host + (size_t)j * HESS_STRIDE;
+        int k = 0;        // columns folded into the least-squares problem
+        bool stop = false;
+        // fold column j (read back from the device) into the QR of H
+        auto fold = [&](int j, const double *hc) {
             for (int i = 0; i <= j; ++i) Hij(i, j) = hc[i];
             // Fused update: the stored vector is (w - V h) / beta, rescaled by
             // its norm nu only when nu is off 1 by more than 1e-8 (the same
@@ -409,8 +403,37 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
             g[j + 1] = -sn[j] * g[j];
             g[j] = cs[j] * g[j];
             k = j + 1;
-            if (hn == 0.0) break;  // exact solution in the current space
+            // exact solution in the current space, or the tolerance is met
+            if (hn == 0.0 || std::fabs(g[j + 1]) <= target) stop = true;
+        };
+        int steps = 0;
+        for (int j = 0; j < mm && !stop; ++j) {
+            double *Vj = V + (size_t)j * N, *Vn = V + (size_t)(j + 1) * N, *Zj = Z + (size_t)j * N;
+            double *hc = Hd + (size_t)j * HESS_STRIDE;
+            apply_split(c, Vj, Zj);
+            PROF(c, PG_APPLY, 24.0 * N, launch_apply_full(s, p, Zj, c->eps.as<double>(), nullptr, Vn, false));
+            const double md = 8.0 * N * (j + 2), ax = 8.0 * N * (j + 3);
+            PROF(c, PG_MULTIDOT, md, launch_multidot(s, V, N, j + 1, Vn, N, part, hc, hc + 64));
+            fused[j] = orth_update_supported(V, N, j + 1, N);
+            if (fused[j]) {
+                PROF(c, PG_AXPY, ax, launch_orth_update(s, Vn, V, N, j + 1, hc, N, part));
+            } else {
+                PROF(c, PG_AXPY, ax, launch_axpy_multi(s, Vn, V, N, j + 1, hc, N, -1.0, part, hc + 65));
+                PROF(c, PG_VEC, 16.0 * N, launch_scale_dev(s, Vn, nullptr, hc + 65, N, 0));
+            }
+            steps = j + 1;
+            if (steps >= check_from || steps == mm) {
+                // read the columns not yet folded and fold them
+                const int n_new = steps - k;
+                DWP_HIP(hipMemcpyAsync(c->host, Hd + (size_t)k * HESS_STRIDE, sizeof(double) * HESS_STRIDE * n_new,
+                                       hipMemcpyDeviceToHost, s));
+                sync(c);
+                const int k0 = k;
+                for (int jj = k0; jj < steps && !stop; ++jj) fold(jj, c->host + (size_t)(jj - k0) * HESS_STRIDE);
+            }
         }
+        iters += steps;
+        if (k > 0 && std::fabs(g[k]) > 0.0) rate = std::pow(std::fabs(g[k]) / beta, 1.0 / k);
         // y = H^{-1} g (upper triangular), x += Z y
         for (int i = k - 1; i >= 0; --i) {
             double t = g[i];
