@@ -211,7 +211,7 @@ void launch_zero(hipStream_t s, T *x, size_t n);
 // One red-black sweep (first_color, then the other) from uin to uout in a
 // single pass; uin, uout: ghosted arrays of level L (ghost planes zero).
 template <class T>
-void launch_sweep_fused(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color);
+void launch_sweep_fused(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color, bool zero_in);
 // The rest of a V-cycle from level l0 down, in one single-workgroup kernel.
 template <class T>
 void launch_vcycle_bottom(hipStream_t s, const std::vector<Level *> &levels, size_t l0, int pre, int post,

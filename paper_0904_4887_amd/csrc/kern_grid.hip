@@ -683,7 +683,9 @@ template <int W> struct FLayout {
     static_assert(NVU <= FNT && NVF <= FNT, "one vector per thread");
 };
 
-template <class T, int W>
+// ZIN: u_in is known to be zero (the first sweep of a V-cycle on a level
+// whose correction starts from zero): its loads are skipped.
+template <class T, int W, bool ZIN>
 __global__ void __launch_bounds__(FNT)
 k_sweep_fused(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ e, const T *__restrict__ f,
               LevelArgs a, int c0, int tiles_x, int tiles_y, int kc, int nb_real) {
@@ -744,7 +746,8 @@ k_sweep_fused(const T *__restrict__ uin, T *__restrict__ uout, const T *__restri
         const int kk = min(max(k, -1), nw), kf = min(max(k, 0), nw - 1);
         const T *bu = uin + (size_t)(kk + 1) * plane, *be = e + (size_t)(kk + 1) * plane;
         const T *bf = f + (size_t)kf * plane;
-        du = *(const V *)((const char *)bu + ohu);
+        if constexpr (ZIN) du = V(0);
+        else du = *(const V *)((const char *)bu + ohu);
         de = *(const V *)((const char *)be + ohu);
         df = *(const V *)((const char *)bf + ohf);
     };
@@ -1150,7 +1153,7 @@ static int fused_chunk(int tiles, int nw, int slots) {
     return best;
 }
 
-template <class T, int W>
+template <class T, int W, bool ZIN>
 static int fused_slots() {
     static int slots[64] = {0};
     int dev = 0;
@@ -1159,33 +1162,41 @@ static int fused_slots() {
     if (!slots[dev]) {
         int cus = 0, per = 0;
         DWP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        DWP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_fused<T, W>, FNT, 0));
+        DWP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_fused<T, W, ZIN>, FNT, 0));
         slots[dev] = std::max(1, cus * per);
     }
     return slots[dev];
 }
 
-template <class T, int W>
+template <class T, int W, bool ZIN>
 static void sweep_fused_w(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color) {
     LevelArgs a = level_args(L);
     const int tx = (L.nx + FTX - 1) / FTX, ty = (L.ny + FTY - 1) / FTY;
-    const int kc = fused_chunk(tx * ty, L.nw, fused_slots<T, W>());
+    const int kc = fused_chunk(tx * ty, L.nw, fused_slots<T, W, ZIN>());
     const int tz = (L.nw + kc - 1) / kc;
     const int nb = tx * ty * tz, padded = (nb + 7) / 8 * 8;
-    k_sweep_fused<T, W><<<padded, FNT, 0, s>>>(uin, uout, L.eps.as<T>(), L.f.as<T>(), a, first_color, tx, ty, kc, nb);
+    k_sweep_fused<T, W, ZIN><<<padded, FNT, 0, s>>>(uin, uout, L.eps.as<T>(), L.f.as<T>(), a, first_color, tx, ty,
+                                                   kc, nb);
     DWP_LAUNCH_CHECK();
+}
+template <class T, int W>
+static void sweep_fused_z(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color, bool zero_in) {
+    if (zero_in) sweep_fused_w<T, W, true>(s, L, uin, uout, first_color);
+    else sweep_fused_w<T, W, false>(s, L, uin, uout, first_color);
 }
 
 // 16-byte tile loads when nx allows (float: nx % 4 == 0), else 8-byte ones;
 // the level arrays come from hipMalloc and planes are whole vectors.
 template <>
-void launch_sweep_fused<float>(hipStream_t s, const Level &L, const float *uin, float *uout, int first_color) {
-    if (L.nx % 4 == 0) sweep_fused_w<float, 4>(s, L, uin, uout, first_color);
-    else sweep_fused_w<float, 2>(s, L, uin, uout, first_color);
+void launch_sweep_fused<float>(hipStream_t s, const Level &L, const float *uin, float *uout, int first_color,
+                               bool zero_in) {
+    if (L.nx % 4 == 0) sweep_fused_z<float, 4>(s, L, uin, uout, first_color, zero_in);
+    else sweep_fused_z<float, 2>(s, L, uin, uout, first_color, zero_in);
 }
 template <>
-void launch_sweep_fused<double>(hipStream_t s, const Level &L, const double *uin, double *uout, int first_color) {
-    sweep_fused_w<double, 2>(s, L, uin, uout, first_color);
+void launch_sweep_fused<double>(hipStream_t s, const Level &L, const double *uin, double *uout, int first_color,
+                                bool zero_in) {
+    sweep_fused_z<double, 2>(s, L, uin, uout, first_color, zero_in);
 }
 
 template <class T>

@@ -256,14 +256,21 @@ void to_host(dwp_ctx *c, const double *dev, size_t n) {
     sync(c);
 }
 
+// One V-cycle from level l down.  Coarse levels enter with a zero correction
+// (the restriction zeroes it); on the fine level, u_unset says that the
+// correction array holds stale values that must act as zero (first cycle),
+// otherwise it holds the previous cycle's correction.
 template <class T>
-void vcycle(dwp_ctx *c, size_t l) {
+void vcycle(dwp_ctx *c, size_t l, bool u_unset) {
     Plan &p = c->plan;
     Level &L = *p.levels[l];
     hipStream_t s = c->stream;
     const double ts = (double)sizeof(T);
     const int sg = l == 0 ? PG_RBGS_FINE : PG_RBGS_COARSE;
     const double pass_bytes = 2.0 * ts * (double)L.n_interior();  // half of read u, eps, f + write u
+    const bool fused = c->opts.smoother == 1 && L.n_interior() >= FUSED_MIN_POINTS;
+    if (u_unset && !(fused && c->opts.pre > 0))
+        PROF(c, PG_WET, ts * (double)L.n_ghosted(), launch_zero<T>(s, L.u.as<T>(), L.n_ghosted()));
     if (l >= p.bottom) {
         double nb = 0.0;
         for (size_t q = l; q < p.levels.size(); ++q) nb += (double)p.levels[q]->n_interior();
@@ -271,21 +278,26 @@ void vcycle(dwp_ctx *c, size_t l) {
              launch_vcycle_bottom<T>(s, p.levels, l, c->opts.pre, c->opts.post, c->opts.coarse_sweeps));
         return;
     }
+    // the first pre-sweep starts from a zero correction on coarse levels and
+    // in the first cycle on the fine level
+    bool zero_in = l > 0 || u_unset;
     auto smooth = [&](int first) {
-        if (c->opts.smoother == 1 && L.n_interior() >= FUSED_MIN_POINTS) {
-            PROF(c, sg, 2.0 * pass_bytes, launch_sweep_fused<T>(s, L, L.u.as<T>(), L.u2.as<T>(), first));
+        if (fused) {
+            const double b = zero_in ? 1.5 * pass_bytes : 2.0 * pass_bytes;
+            PROF(c, sg, b, launch_sweep_fused<T>(s, L, L.u.as<T>(), L.u2.as<T>(), first, zero_in));
             std::swap(L.u.p, L.u2.p);
         } else {
             PROF(c, sg, pass_bytes, launch_level_smooth<T>(s, L, first));
             PROF(c, sg, pass_bytes, launch_level_smooth<T>(s, L, 1 - first));
         }
+        zero_in = false;
     };
     for (int k = 0; k < c->opts.pre; ++k) smooth(0);
     Level &C = *p.levels[l + 1];
     PROF(c, PG_MG_OTHER, 4.0 * ts * L.n_interior(), launch_level_residual<T>(s, L, L.r.as<T>()));
     PROF(c, PG_MG_OTHER, ts * (L.n_interior() + C.n_interior() + C.n_ghosted()),
          launch_restrict<T>(s, L, C, L.r.as<T>(), C.f.as<T>()));
-    vcycle<T>(c, l + 1);
+    vcycle<T>(c, l + 1, false);
     PROF(c, PG_MG_OTHER, ts * (C.n_interior() + 2.0 * L.n_interior()), launch_prolong_add<T>(s, L, C));
     for (int k = 0; k < c->opts.post; ++k) smooth(1);
 }
@@ -300,8 +312,7 @@ void split_impl(dwp_ctx *c, const double *v, double *z) {
     Level &F = *p.levels[0];
     const double nW = (double)F.n_interior();
     PROF(c, PG_WET, (24.0 + sizeof(T)) * nW, launch_wet_residual<T>(s, p, v, z, c->eps.as<double>(), F.f.as<T>()));
-    PROF(c, PG_WET, sizeof(T) * (double)F.n_ghosted(), launch_zero<T>(s, F.u.as<T>(), F.n_ghosted()));
-    for (int k = 0; k < c->opts.cycles; ++k) vcycle<T>(c, 0);
+    for (int k = 0; k < c->opts.cycles; ++k) vcycle<T>(c, 0, k == 0);
     PROF(c, PG_WET, (16.0 + sizeof(T)) * nW, launch_wet_add<T>(s, p, F.u.as<T>(), z));
 }
 
