@@ -151,6 +151,57 @@ def md_loop(w, steps, torch, precision="mixed"):
     return per
 
 
+def copy_ceiling(torch):
+    """Measured device copy bandwidth (1 GiB read + 1 GiB written per copy)."""
+    x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(2):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    del x, y
+    return round(2.0 * (1 << 30) / dt / 1e9, 1)
+
+
+def hbm_resident_smoother(torch, n=(512, 512, 512), reps=4):
+    """The fine-level fused sweep on a grid whose wet field set is far larger
+    than the 256 MB last-level cache: the 512^3 box with the planar tanh
+    permittivity of the smallest workload stretched to it, wet region the top
+    70 %; the split preconditioner is applied `reps` times and only the
+    fine-level sweeps are timed (HIP events on the library's stream)."""
+    from paper_0904_4887_amd.binding import Solver
+    L = (0.1 * n[0], 0.1 * n[1], 0.1 * n[2])
+    z = np.arange(n[2]) * L[2] / n[2]
+    prof = 1.0 + (W.EPS_INF - 1.0) * 0.5 * (1.0 + np.tanh((z - 0.5 * L[2]) / 1.0))
+    eps = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(prof[:, None, None], (n[2], n[1], n[0])))).cuda()
+    out = {}
+    for prec in ("mixed", "fp64"):
+        s = Solver(0)
+        s.set_grid(n, L, z_wet_lo=0.3 * L[2], z_wet_hi=L[2], precision=1 if prec == "mixed" else 0, profile=2,
+                   restart=1)
+        s.set_epsilon(eps)
+        r = torch.randn(n[2], n[1], n[0], dtype=torch.float64, device="cuda")
+        s.apply_split(r)
+        torch.cuda.synchronize()
+        s.profile_reset()
+        for _ in range(reps):
+            s.apply_split(r)
+        torch.cuda.synchronize()
+        p = s.profile().get("rbgs_fine")
+        s.close()
+        if p and p["ms"] > 0:
+            out[prec] = {"GB/s": round(p["bytes"] / p["ms"] / 1e6, 1), "avg_launch_us": round(1e3 * p["ms"] / p["launches"], 2),
+                         "launches": p["launches"], "algorithmic_bytes_per_launch": p["bytes"] / p["launches"]}
+    del eps
+    torch.cuda.empty_cache()
+    return {"grid": list(n), "wet_fraction": 0.7, **out}
+
+
 def golden_iters(name):
     p = os.path.join(ROOT, "tests", "golden", f"oracle_{name}.json")
     if os.path.exists(p):
@@ -256,6 +307,14 @@ def main():
                                    "iters_cold": per[0]["iters"],
                                    "iters_warm_mean": round(float(np.mean([p["iters"] for p in per[1:]])), 2)}
         print(f"# md: {[p['ms'] for p in per]} ms, iters {[p['iters'] for p in per]}", file=sys.stderr, flush=True)
+
+    if not args.no_compare:
+        extra["hbm_resident_smoother_512"] = hbm_resident_smoother(torch)
+        print(f"# smoother 512^3: {extra['hbm_resident_smoother_512']}", file=sys.stderr, flush=True)
+    copy_gbs = copy_ceiling(torch)
+    if roof:
+        roof["copy_ceiling_gbs"] = copy_gbs
+        roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
 
     cpu = None
     if not args.no_cpu:
