@@ -823,13 +823,14 @@ k_sweep_fused(const T *__restrict__ uin, T *__restrict__ uout, const T *__restri
     stash(1, pu[1], pe[1], pf[1]);
 #pragma unroll
     for (int d = 0; d < FPD; ++d) fetch(k0 + d, pu[d], pe[d], pf[d]);
-    // steps m = k0-1 .. k1; step ls stashes plane m + 1 from register set ls % FPD
-    const int nsteps = k1 - k0 + 2;
+    // Steps m = k0-1 .. k0+kc, kc + 2 of them, a multiple of FUNROLL (the
+    // launcher picks kc that way): no step is conditional, so the prefetched
+    // registers rotate without copies (a copy would wait for the loads).  In a
+    // chunk cut short by the top of the slab the extra steps write nothing.
+    const int nsteps = kc + 2;
     for (int base = 0; base < nsteps; base += FUNROLL) {
 #pragma unroll
-        for (int s = 0; s < FUNROLL; ++s) {
-            if (base + s < nsteps) step(s, k0 - 1 + base + s, pu[s % FPD], pe[s % FPD], pf[s % FPD]);
-        }
+        for (int s = 0; s < FUNROLL; ++s) step(s, k0 - 1 + base + s, pu[s % FPD], pe[s % FPD], pf[s % FPD]);
     }
 }
 
@@ -1137,17 +1138,17 @@ void launch_coarsen_eps(hipStream_t s, const Level &F, const Level &C) {
     k_coarsen_eps<T><<<grid1d(n), 256, 0, s>>>(F.eps.as<T>(), C.eps.as<T>(), F.nx, F.ny, C.nx, C.ny, C.nw, C.zc ? 1 : 0);
     DWP_LAUNCH_CHECK();
 }
-// Chunk length (planes per block, even) of the fused sweep.  A block costs
-// about kc + 3 plane steps; blocks run in ceil(blocks / slots) rounds, where
-// slots = resident blocks on the whole device.  The cost model
-// rounds * (kc + 3) picks the chunk that fills the last round best.
+// Chunk length (planes per block) of the fused sweep: kc + 2 plane steps, a
+// multiple of FUNROLL.  Blocks run in ceil(blocks / slots) rounds, where
+// slots = resident blocks on the whole device; the cost model
+// rounds * (kc + 2) picks the chunk that fills the last round best.
 static int fused_chunk(int tiles, int nw, int slots) {
-    int best = 16;
+    int best = FUNROLL - 2;
     long best_cost = -1;
-    for (int kc = 8; kc <= 64; kc += 2) {
+    for (int kc = FUNROLL - 2; kc <= 8 * FUNROLL - 2; kc += FUNROLL) {
         const long blocks = (long)tiles * ((nw + kc - 1) / kc);
         const long rounds = (blocks + slots - 1) / slots;
-        const long cost = rounds * (kc + 3);
+        const long cost = rounds * (kc + 2);
         if (best_cost < 0 || cost < best_cost) { best_cost = cost; best = kc; }
     }
     return best;
