@@ -71,10 +71,11 @@ def run_steps(s, w, steps, warmup, torch):
     return (t1 - t0) / steps, E, infos, F, prof
 
 
-def solver_for(w, precision, torch, profile=0):
+def solver_for(w, precision, torch, profile=0, **extra):
     from paper_0904_4887_amd.binding import Solver
     s = Solver(0)
-    s.set_grid(w.n, w.L, **w.solver_opts(tol=1e-8, precision=1 if precision == "mixed" else 0, profile=profile))
+    s.set_grid(w.n, w.L, **w.solver_opts(tol=1e-8, precision=1 if precision == "mixed" else 0, profile=profile,
+                                         **extra))
     return s
 
 
@@ -291,6 +292,14 @@ def main():
                         "rel_energy_diff_vs_main": abs(E2 - E) / abs(E)}
         s2.close()
         print(f"# {other}: {1e3 * sec2:.2f} ms/step", file=sys.stderr, flush=True)
+        if args.precision == "mixed":
+            s4 = solver_for(w, "mixed", torch, fft_fp32=1)
+            sec4, E4, inf4, _, _ = run_steps(s4, w, max(2, args.steps // 2), 1, torch)
+            extra["mixed_fft_fp32"] = {"steps_per_s": round(1.0 / sec4, 3), "ms_per_step": round(1e3 * sec4, 2),
+                                       "iters": inf4[-1]["outer_iters"], "energy": E4,
+                                       "rel_energy_diff_vs_main": abs(E4 - E) / abs(E)}
+            s4.close()
+            print(f"# mixed with float32 dry update: {1e3 * sec4:.2f} ms/step", file=sys.stderr, flush=True)
         we = make_workload(args.workload, not args.exclusion)
         s3 = solver_for(we, args.precision, torch)
         sec3, E3, inf3, _, _ = run_steps(s3, we, max(2, args.steps // 2), 1, torch)

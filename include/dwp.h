@@ -76,7 +76,7 @@ typedef struct {
     int scaled_dry;        /* 1: dry update s * L^-1 (s * r), s = eps^-1/2     */
     double tol;            /* stop at ||b - A phi||_2 <= tol ||b||_2           */
     int max_outer;         /* cap on preconditioned Krylov iterations          */
-    int restart;           /* FGMRES restart length m (1..64)                  */
+    int restart;           /* FGMRES restart length m (1..63)                  */
     int warm_start;        /* 1: phi_dev holds the initial guess on entry      */
     int profile;           /* 1: time every kernel group with HIP events on    */
                            /* the context stream (see dwp_profile); 2: only    */
@@ -85,6 +85,9 @@ typedef struct {
                            /* 1 = one fused pass per sweep (out of place),     */
                            /* 0 = one launch per colour (in place); the two    */
                            /* give the same sweep up to rounding               */
+    int fft_fp32;          /* 1 (mixed precision only): the FFT dry update     */
+                           /* runs its spectrum and transforms in float32; the */
+                           /* real input and output stay float64.  0: float64  */
 } dwp_opts;
 
 /* Per-solve report. */
@@ -199,7 +202,7 @@ int dwp_forces(dwp_ctx *ctx, int n, const double *xyz_host, const double *radius
 int dwp_apply_operator(dwp_ctx *ctx, const double *phi_dev, double *out_dev);
 /* out = zero-mean psi with L psi = r - mean r, L the 7-point vacuum Laplacian,
  * by the library's 3-D FFT and discrete Green's function (Eq. 15 on the
- * grid). */
+ * grid), always in float64 (fft_fp32 applies inside the split only). */
 int dwp_vacuum_solve(dwp_ctx *ctx, const double *r_dev, double *out_dev);
 /* out = one application of the dry/wet split to r (the preconditioner of the
  * coupled iteration). */

@@ -83,6 +83,7 @@ struct FFTAxis {
     std::vector<int> radices;     // product = n
     DevBuf tw;                    // n complex twiddles exp(-2 pi i t / n), double2
     DevBuf lam;                   // n (or nkx for x) discrete symbol values
+    DevBuf tw32, lam32;           // the same in float32 (float32 dry-update variant)
 };
 
 // Kernel groups timed when profiling is on.
@@ -221,10 +222,11 @@ constexpr size_t FUSED_MIN_POINTS = 1u << 20;  // levels this large use the fuse
 
 // kern_fft.hip
 void fft_plan_axis(FFTAxis &ax, int n, double h, bool half);
-// out = s .* L^{-1} (s .* r) (s == nullptr: unscaled), zero mean
+// out = s .* L^{-1} (s .* r) (s == nullptr: unscaled), zero mean; fp32: the
+// spectrum (cbuf, sized for float64) and the transforms in float32
 void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay,
-                         const FFTAxis &az, const double *r, const double *sinv, double2 *cbuf,
-                         double *out, Profiler *prof);
+                         const FFTAxis &az, const double *r, const double *sinv, void *cbuf,
+                         double *out, Profiler *prof, bool fp32);
 
 // kern_blas.hip: deterministic reductions
 void launch_dot(hipStream_t s, const double *x, const double *y, size_t n, double *partial,

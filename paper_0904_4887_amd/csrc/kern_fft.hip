@@ -14,7 +14,9 @@
 //   x  : inverse of two rows at once (C2R)
 // Each 1-D transform is a Stockham autosort FFT with radix-8, -4, -3 and -2
 // stages; a stage reads its inputs into registers, synchronises, and writes
-// its outputs back in place.
+// its outputs back in place.  The spectrum and the transforms run in float64,
+// or in float32 (S = float) for the mixed-precision variant; the real input
+// and output grids are float64 either way.
 #include "dwp_internal.h"
 
 #include <cmath>
@@ -48,79 +50,95 @@ struct Radices {
     int tstride[MAX_STAGES];
 };
 
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+// Complex arithmetic on double2 / float2.
+template <class S> struct CT;
+template <> struct CT<double> { using T = double2; };
+template <> struct CT<float> { using T = float2; };
+template <class S> using cplx = typename CT<S>::T;
+template <class C> __device__ __forceinline__ C mk(decltype(C::x) a, decltype(C::x) b) { C r; r.x = a; r.y = b; return r; }
+
+template <class C> __device__ __forceinline__ C cmul(C a, C b) {
+    return mk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+template <class C> __device__ __forceinline__ C cadd(C a, C b) { return mk<C>(a.x + b.x, a.y + b.y); }
+template <class C> __device__ __forceinline__ C csub(C a, C b) { return mk<C>(a.x - b.x, a.y - b.y); }
 // multiply by -i (forward) or +i (inverse)
-__device__ __forceinline__ double2 rot(double2 a, bool inv) {
-    return inv ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+template <class C> __device__ __forceinline__ C rot(C a, bool inv) {
+    return inv ? mk<C>(-a.y, a.x) : mk<C>(a.y, -a.x);
 }
 
-template <int R> __device__ __forceinline__ void dft(double2 *x, bool inv);
+template <int R, class C> struct DFT;
 
-template <> __device__ __forceinline__ void dft<2>(double2 *x, bool) {
-    const double2 a = x[0], b = x[1];
-    x[0] = cadd(a, b);
-    x[1] = csub(a, b);
-}
-template <> __device__ __forceinline__ void dft<4>(double2 *x, bool inv) {
-    const double2 a = cadd(x[0], x[2]), b = csub(x[0], x[2]);
-    const double2 c = cadd(x[1], x[3]), d = csub(x[1], x[3]);
-    x[0] = cadd(a, c);
-    x[2] = csub(a, c);
-    const double2 rd = rot(d, inv);  // -i d (forward)
-    x[1] = cadd(b, rd);
-    x[3] = csub(b, rd);
-}
-template <> __device__ __forceinline__ void dft<3>(double2 *x, bool inv) {
-    // w = exp(-2 pi i / 3) = -1/2 - i sqrt(3)/2
-    const double s3 = 0.86602540378443864676;
-    const double2 t1 = cadd(x[1], x[2]);
-    const double2 t2 = make_double2(x[0].x - 0.5 * t1.x, x[0].y - 0.5 * t1.y);
-    const double2 d = csub(x[1], x[2]);
-    const double2 rd = rot(make_double2(s3 * d.x, s3 * d.y), inv);  // -i s3 d (forward)
-    x[0] = cadd(x[0], t1);
-    x[1] = cadd(t2, rd);
-    x[2] = csub(t2, rd);
-}
-
-template <> __device__ __forceinline__ void dft<8>(double2 *x, bool inv) {
-    // two radix-4 transforms of the even and odd inputs, then one radix-2 layer
-    // with the eighth roots of unity w8^k = exp(-+i pi k / 4)
-    double2 ev[4] = {x[0], x[2], x[4], x[6]}, od[4] = {x[1], x[3], x[5], x[7]};
-    dft<4>(ev, inv);
-    dft<4>(od, inv);
-    const double c = 0.70710678118654752440;
-    const double2 t1 = inv ? make_double2(c * (od[1].x - od[1].y), c * (od[1].x + od[1].y))
-                           : make_double2(c * (od[1].x + od[1].y), c * (od[1].y - od[1].x));
-    const double2 t2 = rot(od[2], inv);
-    const double2 t3 = inv ? make_double2(-c * (od[3].x + od[3].y), c * (od[3].x - od[3].y))
-                           : make_double2(c * (od[3].y - od[3].x), -c * (od[3].x + od[3].y));
-    x[0] = cadd(ev[0], od[0]);
-    x[4] = csub(ev[0], od[0]);
-    x[1] = cadd(ev[1], t1);
-    x[5] = csub(ev[1], t1);
-    x[2] = cadd(ev[2], t2);
-    x[6] = csub(ev[2], t2);
-    x[3] = cadd(ev[3], t3);
-    x[7] = csub(ev[3], t3);
-}
+template <class C> struct DFT<2, C> {
+    static __device__ __forceinline__ void run(C *x, bool) {
+        const C a = x[0], b = x[1];
+        x[0] = cadd(a, b);
+        x[1] = csub(a, b);
+    }
+};
+template <class C> struct DFT<4, C> {
+    static __device__ __forceinline__ void run(C *x, bool inv) {
+        const C a = cadd(x[0], x[2]), b = csub(x[0], x[2]);
+        const C c = cadd(x[1], x[3]), d = csub(x[1], x[3]);
+        x[0] = cadd(a, c);
+        x[2] = csub(a, c);
+        const C rd = rot(d, inv);  // -i d (forward)
+        x[1] = cadd(b, rd);
+        x[3] = csub(b, rd);
+    }
+};
+template <class C> struct DFT<3, C> {
+    static __device__ __forceinline__ void run(C *x, bool inv) {
+        using S = decltype(C::x);
+        // w = exp(-2 pi i / 3) = -1/2 - i sqrt(3)/2
+        const S s3 = (S)0.86602540378443864676;
+        const C t1 = cadd(x[1], x[2]);
+        const C t2 = mk<C>(x[0].x - (S)0.5 * t1.x, x[0].y - (S)0.5 * t1.y);
+        const C d = csub(x[1], x[2]);
+        const C rd = rot(mk<C>(s3 * d.x, s3 * d.y), inv);  // -i s3 d (forward)
+        x[0] = cadd(x[0], t1);
+        x[1] = cadd(t2, rd);
+        x[2] = csub(t2, rd);
+    }
+};
+template <class C> struct DFT<8, C> {
+    static __device__ __forceinline__ void run(C *x, bool inv) {
+        using S = decltype(C::x);
+        // two radix-4 transforms of the even and odd inputs, then one radix-2
+        // layer with the eighth roots of unity w8^k = exp(-+i pi k / 4)
+        C ev[4] = {x[0], x[2], x[4], x[6]}, od[4] = {x[1], x[3], x[5], x[7]};
+        DFT<4, C>::run(ev, inv);
+        DFT<4, C>::run(od, inv);
+        const S c = (S)0.70710678118654752440;
+        const C t1 = inv ? mk<C>(c * (od[1].x - od[1].y), c * (od[1].x + od[1].y))
+                         : mk<C>(c * (od[1].x + od[1].y), c * (od[1].y - od[1].x));
+        const C t2 = rot(od[2], inv);
+        const C t3 = inv ? mk<C>(-c * (od[3].x + od[3].y), c * (od[3].x - od[3].y))
+                         : mk<C>(c * (od[3].y - od[3].x), -c * (od[3].x + od[3].y));
+        x[0] = cadd(ev[0], od[0]);
+        x[4] = csub(ev[0], od[0]);
+        x[1] = cadd(ev[1], t1);
+        x[5] = csub(ev[1], t1);
+        x[2] = cadd(ev[2], t2);
+        x[6] = csub(ev[2], t2);
+        x[3] = cadd(ev[3], t3);
+        x[7] = csub(ev[3], t3);
+    }
+};
 
 // One Stockham stage of radix R on B = 2^lb lines of length n held in LDS;
 // element t of line l sits at buf[l * ls + t * es].  p = product of the
 // radices of the earlier stages.  Butterfly i of a line reads
 // x_q = buf[i + q n/R], twiddles x_q by exp(-+2 pi i q (i mod p) / (p R)),
 // and writes output r to (i - i mod p) R + i mod p + r p.
-template <int R>
-__device__ void stage(double2 *buf, int n, int p, unsigned pm, int tstride, int lb, int es, int ls,
-                      const double2 *__restrict__ tw, bool inv) {
+template <int R, class C>
+__device__ void stage(C *buf, int n, int p, unsigned pm, int tstride, int lb, int es, int ls,
+                      const C *__restrict__ tw, bool inv) {
     constexpr int K = (4096 / R + FFT_THREADS - 1) / FFT_THREADS;
     const int T = n / R;
     const int items = T << lb;
     const int bmask = (1 << lb) - 1;
-    double2 x[K][R];
+    C x[K][R];
 #pragma unroll
     for (int m = 0; m < K; ++m) {
         const int w = threadIdx.x + m * FFT_THREADS;
@@ -141,12 +159,12 @@ __device__ void stage(double2 *buf, int n, int p, unsigned pm, int tstride, int 
                 const int kt = k * tstride;
 #pragma unroll
                 for (int q = 1; q < R; ++q) {
-                    double2 t = tw[q * kt];
+                    C t = tw[q * kt];
                     if (inv) t.y = -t.y;
                     x[m][q] = cmul(x[m][q], t);
                 }
             }
-            dft<R>(x[m], inv);
+            DFT<R, C>::run(x[m], inv);
             const int j = (i - k) * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) buf[l * ls + (j + r * p) * es] = x[m][r];
@@ -155,24 +173,27 @@ __device__ void stage(double2 *buf, int n, int p, unsigned pm, int tstride, int 
     __syncthreads();
 }
 
-__device__ void fft_lines(double2 *buf, const Radices &rd, int lb, int es, int ls,
-                          const double2 *__restrict__ tw, bool inv) {
+template <class C>
+__device__ void fft_lines(C *buf, const Radices &rd, int lb, int es, int ls, const C *__restrict__ tw, bool inv) {
     for (int s = 0; s < rd.nst; ++s) {
         const int R = rd.r[s];
-        if (R == 8) stage<8>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
-        else if (R == 4) stage<4>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
-        else if (R == 3) stage<3>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
-        else stage<2>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
+        if (R == 8) stage<8, C>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
+        else if (R == 4) stage<4, C>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
+        else if (R == 3) stage<3, C>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
+        else stage<2, C>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
     }
 }
 
 // ---------------------------------------------------------------- x passes
 // Rows are the nx-long x lines of the [nz][ny][nx] grid; B = 2^lb complex
 // lines per block carry 2B real rows.  LDS lines are padded to n + 1 elements.
+template <class S>
 __global__ void __launch_bounds__(FFT_THREADS)
-k_fft_x_fwd(const double *__restrict__ in, const double *__restrict__ sinv, double2 *__restrict__ out,
-            Radices rd, const double2 *__restrict__ tw, int lb, int nrows, int nkx, int ldc, Div dn, Div dk) {
-    extern __shared__ double2 lds[];
+k_fft_x_fwd(const double *__restrict__ in, const double *__restrict__ sinv, cplx<S> *__restrict__ out,
+            Radices rd, const cplx<S> *__restrict__ tw, int lb, int nrows, int nkx, int ldc, Div dn, Div dk) {
+    using C = cplx<S>;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    C *lds = reinterpret_cast<C *>(lds_raw);
     const int n = rd.n, ls = n + 1, B = 1 << lb;
     const int r0 = blockIdx.x * 2 * B;
     for (int e = threadIdx.x; e < B * n; e += FFT_THREADS) {
@@ -185,7 +206,7 @@ k_fft_x_fwd(const double *__restrict__ in, const double *__restrict__ sinv, doub
             b = in[ib];
             if (sinv) { a *= sinv[ia]; b *= sinv[ib]; }
         }
-        lds[l * ls + t] = make_double2(a, b);
+        lds[l * ls + t] = mk<C>((S)a, (S)b);
     }
     __syncthreads();
     fft_lines(lds, rd, lb, 1, ls, tw, false);
@@ -193,32 +214,34 @@ k_fft_x_fwd(const double *__restrict__ in, const double *__restrict__ sinv, doub
         const int l = udiv(e, dk), k = e - l * nkx;
         const int ra = r0 + 2 * l, rb = ra + 1;
         if (rb >= nrows) continue;
-        const double2 z = lds[l * ls + k];
-        const double2 zc = lds[l * ls + (k == 0 ? 0 : n - k)];  // Z[-k]
+        const C z = lds[l * ls + k];
+        const C zc = lds[l * ls + (k == 0 ? 0 : n - k)];  // Z[-k]
         // A = (Z + conj Z[-k]) / 2, B = (Z - conj Z[-k]) / (2 i)
-        const double2 A = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
-        const double2 Bv = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
-        out[(size_t)ra * ldc + k] = A;
-        out[(size_t)rb * ldc + k] = Bv;
+        const S h = (S)0.5;
+        out[(size_t)ra * ldc + k] = mk<C>(h * (z.x + zc.x), h * (z.y - zc.y));
+        out[(size_t)rb * ldc + k] = mk<C>(h * (z.y + zc.y), -h * (z.x - zc.x));
     }
 }
 
+template <class S>
 __global__ void __launch_bounds__(FFT_THREADS)
-k_fft_x_inv(const double2 *__restrict__ in, const double *__restrict__ sinv, double *__restrict__ out,
-            Radices rd, const double2 *__restrict__ tw, int lb, int nrows, int nkx, int ldc, Div dn) {
-    extern __shared__ double2 lds[];
+k_fft_x_inv(const cplx<S> *__restrict__ in, const double *__restrict__ sinv, double *__restrict__ out,
+            Radices rd, const cplx<S> *__restrict__ tw, int lb, int nrows, int nkx, int ldc, Div dn) {
+    using C = cplx<S>;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    C *lds = reinterpret_cast<C *>(lds_raw);
     const int n = rd.n, ls = n + 1, B = 1 << lb;
     const int r0 = blockIdx.x * 2 * B;
     for (int e = threadIdx.x; e < B * n; e += FFT_THREADS) {
         const int l = udiv(e, dn), k = e - l * n;
         const int ra = r0 + 2 * l, rb = ra + 1;
-        double2 z = make_double2(0.0, 0.0);
+        C z = mk<C>(0, 0);
         if (rb < nrows) {
             const int kk = (k < nkx) ? k : n - k;
-            double2 A = in[(size_t)ra * ldc + kk], Bv = in[(size_t)rb * ldc + kk];
-            if (kk == 0 || 2 * kk == n) { A.y = 0.0; Bv.y = 0.0; }
+            C A = in[(size_t)ra * ldc + kk], Bv = in[(size_t)rb * ldc + kk];
+            if (kk == 0 || 2 * kk == n) { A.y = 0; Bv.y = 0; }
             if (k >= nkx) { A.y = -A.y; Bv.y = -Bv.y; }  // Hermitian extension
-            z = make_double2(A.x - Bv.y, A.y + Bv.x);     // A + i B
+            z = mk<C>(A.x - Bv.y, A.y + Bv.x);           // A + i B
         }
         lds[l * ls + k] = z;
     }
@@ -228,14 +251,14 @@ k_fft_x_inv(const double2 *__restrict__ in, const double *__restrict__ sinv, dou
         const int l = udiv(e, dn), t = e - l * n;
         const int ra = r0 + 2 * l, rb = ra + 1;
         if (rb >= nrows) continue;
-        const double2 z = lds[l * ls + t];
+        const C z = lds[l * ls + t];
         const size_t ia = (size_t)ra * n + t, ib = ia + n;
         if (sinv) {
-            out[ia] = z.x * sinv[ia];
-            out[ib] = z.y * sinv[ib];
+            out[ia] = (double)z.x * sinv[ia];
+            out[ib] = (double)z.y * sinv[ib];
         } else {
-            out[ia] = z.x;
-            out[ib] = z.y;
+            out[ia] = (double)z.x;
+            out[ib] = (double)z.y;
         }
     }
 }
@@ -243,9 +266,12 @@ k_fft_x_inv(const double2 *__restrict__ in, const double *__restrict__ sinv, dou
 // ---------------------------------------------------------------- y pass
 // Block (tile of B = 2^lb consecutive kx, plane z): lines along y, LDS
 // element (y, l) at y * B + l.
+template <class S>
 __global__ void __launch_bounds__(FFT_THREADS)
-k_fft_y(double2 *__restrict__ c, Radices rd, const double2 *__restrict__ tw, int lb, int nkx, int ldc, int inv) {
-    extern __shared__ double2 lds[];
+k_fft_y(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ tw, int lb, int nkx, int ldc, int inv) {
+    using C = cplx<S>;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    C *lds = reinterpret_cast<C *>(lds_raw);
     const int ny = rd.n, B = 1 << lb, bmask = B - 1;
     const int kx0 = blockIdx.x * B;
     const int z = blockIdx.y;
@@ -253,7 +279,7 @@ k_fft_y(double2 *__restrict__ c, Radices rd, const double2 *__restrict__ tw, int
     const size_t base = (size_t)z * ny * ldc + kx0;
     for (int e = threadIdx.x; e < B * ny; e += FFT_THREADS) {
         const int y = e >> lb, l = e & bmask;
-        lds[e] = (l < bw) ? c[base + (size_t)y * ldc + l] : make_double2(0.0, 0.0);
+        lds[e] = (l < bw) ? c[base + (size_t)y * ldc + l] : mk<C>(0, 0);
     }
     __syncthreads();
     fft_lines(lds, rd, lb, B, 1, tw, inv != 0);
@@ -264,7 +290,7 @@ k_fft_y(double2 *__restrict__ c, Radices rd, const double2 *__restrict__ tw, int
 }
 
 // ---------------------------------------------------------------- z pass + Green
-// -1 / lambda through the hardware reciprocal and two Newton steps.
+// -1 / lambda through the hardware reciprocal (two Newton steps in float64).
 __device__ __forceinline__ double neg_recip(double d) {
     double r = __builtin_amdgcn_rcp(d);
     double e = __builtin_fma(-d, r, 1.0);
@@ -273,12 +299,15 @@ __device__ __forceinline__ double neg_recip(double d) {
     r = __builtin_fma(r, e, r);
     return -r;
 }
+__device__ __forceinline__ float neg_recip(float d) { return -__builtin_amdgcn_rcpf(d); }
 
+template <class S>
 __global__ void __launch_bounds__(FFT_THREADS)
-k_fft_z_green(double2 *__restrict__ c, Radices rd, const double2 *__restrict__ tw, int lb, int nkx, int ldc, int ny,
-              const double *__restrict__ lamx, const double *__restrict__ lamy,
-              const double *__restrict__ lamz, double inv_n) {
-    extern __shared__ double2 lds[];
+k_fft_z_green(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ tw, int lb, int nkx, int ldc, int ny,
+              const S *__restrict__ lamx, const S *__restrict__ lamy, const S *__restrict__ lamz, S inv_n) {
+    using C = cplx<S>;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    C *lds = reinterpret_cast<C *>(lds_raw);
     const int nz = rd.n, B = 1 << lb, bmask = B - 1;
     const int kx0 = blockIdx.x * B;
     const int y = blockIdx.y;
@@ -287,18 +316,18 @@ k_fft_z_green(double2 *__restrict__ c, Radices rd, const double2 *__restrict__ t
     const size_t base = (size_t)y * ldc + kx0;
     for (int e = threadIdx.x; e < B * nz; e += FFT_THREADS) {
         const int z = e >> lb, l = e & bmask;
-        lds[e] = (l < bw) ? c[base + (size_t)z * zstride + l] : make_double2(0.0, 0.0);
+        lds[e] = (l < bw) ? c[base + (size_t)z * zstride + l] : mk<C>(0, 0);
     }
     __syncthreads();
     fft_lines(lds, rd, lb, B, 1, tw, false);
-    const double ly = lamy[y];
+    const S ly = lamy[y];
     for (int e = threadIdx.x; e < B * nz; e += FFT_THREADS) {
         const int z = e >> lb, l = e & bmask;
         const int kx = kx0 + l;
-        double g = 0.0;
+        S g = 0;
         if (l < bw && (kx | y | z) != 0) g = inv_n * neg_recip(lamx[kx] + ly + lamz[z]);
-        const double2 v = lds[e];
-        lds[e] = make_double2(v.x * g, v.y * g);
+        const C v = lds[e];
+        lds[e] = mk<C>(v.x * g, v.y * g);
     }
     __syncthreads();
     fft_lines(lds, rd, lb, B, 1, tw, true);
@@ -347,67 +376,83 @@ void fft_plan_axis(FFTAxis &ax, int n, double h, bool half) {
     if (m != 1 || (int)ax.radices.size() > MAX_STAGES) fail(DWP_EINVAL, "grid size must be 2^a 3^b");
     const long double pi = 3.141592653589793238462643383279502884L;
     std::vector<double2> tw(n);
+    std::vector<float2> tw32(n);
     for (int t = 0; t < n; ++t) {
         const long double a = -2.0L * pi * (long double)t / (long double)n;
         tw[t] = make_double2((double)cosl(a), (double)sinl(a));
+        tw32[t] = make_float2((float)cosl(a), (float)sinl(a));
     }
     const int nl = half ? n / 2 + 1 : n;
     std::vector<double> lam(nl);
+    std::vector<float> lam32(nl);
     for (int k = 0; k < nl; ++k) {
         const long double s = sinl(pi * (long double)k / (long double)n);
         lam[k] = (double)(4.0L * s * s / ((long double)h * (long double)h));
+        lam32[k] = (float)lam[k];
     }
     ax.tw.alloc(sizeof(double2) * n);
     ax.lam.alloc(sizeof(double) * nl);
+    ax.tw32.alloc(sizeof(float2) * n);
+    ax.lam32.alloc(sizeof(float) * nl);
     DWP_HIP(hipMemcpy(ax.tw.p, tw.data(), sizeof(double2) * n, hipMemcpyHostToDevice));
     DWP_HIP(hipMemcpy(ax.lam.p, lam.data(), sizeof(double) * nl, hipMemcpyHostToDevice));
+    DWP_HIP(hipMemcpy(ax.tw32.p, tw32.data(), sizeof(float2) * n, hipMemcpyHostToDevice));
+    DWP_HIP(hipMemcpy(ax.lam32.p, lam32.data(), sizeof(float) * nl, hipMemcpyHostToDevice));
 }
 
-void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay,
-                         const FFTAxis &az, const double *r, const double *sinv, double2 *cbuf,
-                         double *out, Profiler *prof) {
+template <class S>
+static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay, const FFTAxis &az,
+                           const double *r, const double *sinv, void *cbuf_v, double *out, Profiler *prof) {
+    using C = cplx<S>;
+    C *cbuf = static_cast<C *>(cbuf_v);
+    auto TW = [](const FFTAxis &a) { return sizeof(S) == 8 ? a.tw.as<C>() : a.tw32.as<C>(); };
+    auto LAM = [](const FFTAxis &a) { return sizeof(S) == 8 ? a.lam.as<S>() : a.lam32.as<S>(); };
     // algorithmic bytes of each pass: the real grid (8 B / point, twice when
-    // scaled) and the half-spectrum (16 B / complex value) read and written once
-    const double C = (double)p.nkx * p.ny * p.nz;
-    const double bx = (sinv ? 16.0 : 8.0) * p.N + 16.0 * C;
+    // scaled) and the half-spectrum (one complex value) read and written once
+    const double Cn = (double)p.nkx * p.ny * p.nz, cb = (double)sizeof(C);
+    const double bx = (sinv ? 16.0 : 8.0) * p.N + cb * Cn;
     auto pb = [&](int g) { return prof ? prof->begin(st, g) : -1; };
     auto pe = [&](int ev, int g, double b) { if (prof) prof->end(st, ev, g, b); };
     int ev;
     const int nrows = p.ny * p.nz;
     const int lbx = tile_log2(p.nx, 2048), Bx = 1 << lbx;
     const int gx = (nrows + 2 * Bx - 1) / (2 * Bx);
-    const size_t ldsx = sizeof(double2) * Bx * (p.nx + 1);
+    const size_t ldsx = sizeof(C) * Bx * (p.nx + 1);
     const Div dn = make_div(p.nx), dk = make_div(p.nkx);
     ev = pb(PG_FFT_X);
-    k_fft_x_fwd<<<gx, FFT_THREADS, ldsx, st>>>(r, sinv, cbuf, radices_of(ax), ax.tw.as<double2>(), lbx, nrows, p.nkx,
-                                               p.ldc, dn, dk);
+    k_fft_x_fwd<S><<<gx, FFT_THREADS, ldsx, st>>>(r, sinv, cbuf, radices_of(ax), TW(ax), lbx, nrows, p.nkx, p.ldc, dn,
+                                                  dk);
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_X, bx);
     const int lby = tile_log2(p.ny, 4096), By = 1 << lby;
     dim3 gy((p.nkx + By - 1) / By, p.nz);
     ev = pb(PG_FFT_Y);
-    k_fft_y<<<gy, FFT_THREADS, sizeof(double2) * By * p.ny, st>>>(cbuf, radices_of(ay), ay.tw.as<double2>(), lby,
-                                                                  p.nkx, p.ldc, 0);
+    k_fft_y<S><<<gy, FFT_THREADS, sizeof(C) * By * p.ny, st>>>(cbuf, radices_of(ay), TW(ay), lby, p.nkx, p.ldc, 0);
     DWP_LAUNCH_CHECK();
-    pe(ev, PG_FFT_Y, 32.0 * C);
+    pe(ev, PG_FFT_Y, 2.0 * cb * Cn);
     const int lbz = tile_log2(p.nz, 4096), Bz = 1 << lbz;
     dim3 gz((p.nkx + Bz - 1) / Bz, p.ny);
     ev = pb(PG_FFT_Z);
-    k_fft_z_green<<<gz, FFT_THREADS, sizeof(double2) * Bz * p.nz, st>>>(
-        cbuf, radices_of(az), az.tw.as<double2>(), lbz, p.nkx, p.ldc, p.ny, ax.lam.as<double>(), ay.lam.as<double>(),
-        az.lam.as<double>(), 1.0 / (double)p.N);
+    k_fft_z_green<S><<<gz, FFT_THREADS, sizeof(C) * Bz * p.nz, st>>>(cbuf, radices_of(az), TW(az), lbz, p.nkx, p.ldc,
+                                                                      p.ny, LAM(ax), LAM(ay), LAM(az),
+                                                                      (S)(1.0 / (double)p.N));
     DWP_LAUNCH_CHECK();
-    pe(ev, PG_FFT_Z, 32.0 * C);
+    pe(ev, PG_FFT_Z, 2.0 * cb * Cn);
     ev = pb(PG_FFT_Y);
-    k_fft_y<<<gy, FFT_THREADS, sizeof(double2) * By * p.ny, st>>>(cbuf, radices_of(ay), ay.tw.as<double2>(), lby,
-                                                                  p.nkx, p.ldc, 1);
+    k_fft_y<S><<<gy, FFT_THREADS, sizeof(C) * By * p.ny, st>>>(cbuf, radices_of(ay), TW(ay), lby, p.nkx, p.ldc, 1);
     DWP_LAUNCH_CHECK();
-    pe(ev, PG_FFT_Y, 32.0 * C);
+    pe(ev, PG_FFT_Y, 2.0 * cb * Cn);
     ev = pb(PG_FFT_X);
-    k_fft_x_inv<<<gx, FFT_THREADS, ldsx, st>>>(cbuf, sinv, out, radices_of(ax), ax.tw.as<double2>(), lbx, nrows, p.nkx,
-                                               p.ldc, dn);
+    k_fft_x_inv<S><<<gx, FFT_THREADS, ldsx, st>>>(cbuf, sinv, out, radices_of(ax), TW(ax), lbx, nrows, p.nkx, p.ldc,
+                                                  dn);
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_X, bx);
+}
+
+void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay, const FFTAxis &az,
+                         const double *r, const double *sinv, void *cbuf, double *out, Profiler *prof, bool fp32) {
+    if (fp32) vacuum_solve_t<float>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
+    else vacuum_solve_t<double>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
 }
 
 }  // namespace dwp

@@ -307,8 +307,8 @@ void split_impl(dwp_ctx *c, const double *v, double *z) {
     Plan &p = c->plan;
     hipStream_t s = c->stream;
     const bool scaled = c->opts.scaled_dry != 0;
-    launch_vacuum_solve(s, p, c->fx, c->fy, c->fz, v, scaled ? c->sinv.as<double>() : nullptr,
-                        c->cbuf.as<double2>(), z, &c->prof);
+    launch_vacuum_solve(s, p, c->fx, c->fy, c->fz, v, scaled ? c->sinv.as<double>() : nullptr, c->cbuf.p, z,
+                        &c->prof, c->opts.fft_fp32 != 0);
     Level &F = *p.levels[0];
     const double nW = (double)F.n_interior();
     PROF(c, PG_WET, (24.0 + sizeof(T)) * nW, launch_wet_residual<T>(s, p, v, z, c->eps.as<double>(), F.f.as<T>()));
@@ -480,6 +480,8 @@ void validate_opts(const dwp_opts &o) {
     if (o.warm_start != 0 && o.warm_start != 1) fail(DWP_EINVAL, "warm_start must be 0 or 1");
     if (o.profile < 0 || o.profile > 2) fail(DWP_EINVAL, "profile must be 0, 1 or 2");
     if (o.smoother != 0 && o.smoother != 1) fail(DWP_EINVAL, "smoother must be 0 or 1");
+    if (o.fft_fp32 != 0 && o.fft_fp32 != 1) fail(DWP_EINVAL, "fft_fp32 must be 0 or 1");
+    if (o.fft_fp32 && o.precision != DWP_MIXED) fail(DWP_EINVAL, "fft_fp32 needs the mixed precision mode");
 }
 
 AtomParams atom_params(const dwp_eps_params *ep) {
@@ -790,6 +792,7 @@ void dwp_default_opts(dwp_opts *o) {
     o->warm_start = 0;
     o->profile = 0;
     o->smoother = 1;
+    o->fft_fp32 = 0;
 }
 
 int dwp_create(dwp_ctx **out, int device, void *stream) {
@@ -928,8 +931,8 @@ int dwp_vacuum_solve(dwp_ctx *c, const double *r, double *out) {
     dwp::need_grid(c);
     if (!r || !out) dwp::fail(DWP_EINVAL, "NULL pointer");
     DWP_HIP(hipSetDevice(c->device));
-    dwp::launch_vacuum_solve(c->stream, c->plan, c->fx, c->fy, c->fz, r, nullptr, c->cbuf.as<double2>(), out,
-                             nullptr);
+    dwp::launch_vacuum_solve(c->stream, c->plan, c->fx, c->fy, c->fz, r, nullptr, c->cbuf.p, out,
+                             nullptr, false);
     ABI_END(c)
 }
 

@@ -122,6 +122,20 @@ def test_solve_small_slab(torch, exclusion, precision):
 
 
 @pytest.mark.parametrize("exclusion", [False, True])
+def test_solve_small_slab_float32_dry_update(torch, exclusion):
+    """Mixed precision with the float32 FFT dry update: the preconditioner
+    changes, the float64 coupling still reaches the same solution."""
+    w = W.slab(n=(48, 48, 96), exclusion=exclusion)
+    s = _solver(torch, w.n, w.L, z_wet_lo=w.z_wet[0], z_wet_hi=w.z_wet[1], tol=1e-10, precision=1, fft_fp32=1)
+    s.build_epsilon(w.xyz, w.radius, w.eps_params)
+    rho_d = s.build_rho(w.xyz, w.q, w.sigma)
+    phi, E, info = s.solve(rho_d)
+    eps = O.eps_erf(w.n, w.L, w.xyz, w.radius, w.eps_params)
+    rho = O.rho_gauss(w.n, w.L, w.xyz, w.q, w.sigma)
+    _check_solution(torch, s, rho, eps, _host(phi), E, info, 1e-10, 1e-8)
+
+
+@pytest.mark.parametrize("exclusion", [False, True])
 def test_forces_and_eps_gradient_match_oracle(torch, exclusion):
     w = W.slab(n=(48, 48, 96), exclusion=exclusion)
     s = _solver(torch, w.n, w.L, z_wet_lo=w.z_wet[0], z_wet_hi=w.z_wet[1], tol=1e-12)
