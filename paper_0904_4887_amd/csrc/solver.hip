@@ -341,8 +341,10 @@ void check_finite_dev(dwp_ctx *c, const double *x, const char *what) {
 // host reads the Hessenberg columns to solve the small least-squares problem.
 // The host looks at the columns only after the step from which the cycle may
 // meet the tolerance (predicted from the per-step residual reduction of the
-// previous cycle), and from there after every step, so that a cycle stops at
-// the first step whose least-squares residual meets the tolerance.  The true
+// previous cycle; the first cycle is looked at after its first step and
+// predicted from that step's reduction), and from there after every step, so
+// that a cycle stops at the first step whose least-squares residual meets the
+// tolerance.  The true
 // residual is recomputed at the start of every cycle, so the result meets the
 // tolerance whatever the loss of orthogonality.  Returns the number of steps;
 // *rel receives the final true relative residual.
@@ -378,14 +380,15 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
         ++*restarts;
         PROF(c, PG_VEC, 16.0 * N, launch_scale_dev(s, V, nullptr, beta2, N, 0));
         const int mm = std::min(m, o.max_outer - iters);
-        // first step after which the host checks the least-squares residual
-        int check_from = mm;
-        if (rate > 0.0 && rate < 1.0) {
-            const double need = std::log(target / beta) / std::log(rate);
-            check_from = std::max(1, std::min(mm, (int)std::floor(need) - 1));
-        } else if (o.warm_start && *restarts == 1) {
-            check_from = std::max(1, mm / 2);
-        }
+        // First step after which the host checks the least-squares residual:
+        // predicted from the per-step reduction of the last cycle, or, in the
+        // first cycle, from the reduction of its first step (checked at once).
+        auto predict = [&](double r, int done) {
+            if (!(r > 0.0 && r < 1.0)) return mm;
+            const double need = std::log(target / beta) / std::log(r);
+            return std::max(done + 1, std::min(mm, (int)std::floor(need) - 1));
+        };
+        int check_from = rate > 0.0 ? predict(rate, 0) : 1;
         std::fill(H.begin(), H.end(), 0.0);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
@@ -441,6 +444,8 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
                 sync(c);
                 const int k0 = k;
                 for (int jj = k0; jj < steps && !stop; ++jj) fold(jj, c->host + (size_t)(jj - k0) * HESS_STRIDE);
+                if (rate <= 0.0 && steps == 1 && !stop)
+                    check_from = predict(std::fabs(g[1]) / beta, 1);
             }
         }
         iters += steps;
