@@ -567,31 +567,48 @@ k_restrict(const T *__restrict__ rf, T *__restrict__ fc, T *__restrict__ uc, int
 }
 
 // Trilinear interpolation of the coarse correction, added to the fine
-// unknowns.  Grid: (x tiles, y tiles, fine plane kf).
+// unknowns.  x and y are always coarsened by 2, z when zc.  One thread per
+// fine x pair (2 ic, 2 ic + 1): the even point takes the coarse value at ic,
+// the odd one the mean of ic and ic + 1, so both come from the same two coarse
+// values per contributing coarse row and nothing diverges inside a wave (one
+// wave spans a single fine row j; a block a single fine plane).  Grid: (pair
+// tiles, rows, fine plane kf).
 template <class T>
 __global__ void __launch_bounds__(BX *BY)
 k_prolong_add(T *__restrict__ uf, const T *__restrict__ uc, int nxf, int nyf, int nxc, int nyc, int zc) {
-    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, kf = blockIdx.z;
-    if (i >= nxf || j >= nyf) return;
+    const int ic = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, kf = blockIdx.z;
+    if (ic >= nxc || j >= nyf) return;
     const size_t planef = (size_t)nxf * nyf, planec = (size_t)nxc * nyc;
-    int ix[2], jy[2], pz[2];
-    T wx[2], wyv[2], wz[2];
-    int nxs, nys, nzs;
-    if (i & 1) { ix[0] = i >> 1; ix[1] = (ix[0] + 1 == nxc) ? 0 : ix[0] + 1; wx[0] = wx[1] = T(0.5); nxs = 2; }
-    else { ix[0] = i >> 1; ix[1] = 0; wx[0] = T(1); wx[1] = T(0); nxs = 1; }
-    if (j & 1) { jy[0] = j >> 1; jy[1] = (jy[0] + 1 == nyc) ? 0 : jy[0] + 1; wyv[0] = wyv[1] = T(0.5); nys = 2; }
-    else { jy[0] = j >> 1; jy[1] = 0; wyv[0] = T(1); wyv[1] = T(0); nys = 1; }
+    const int icp = ic + 1 == nxc ? 0 : ic + 1;
+    // coarse rows (y) and planes (z, ghosted index) with their weights
+    const int jc0 = j >> 1, jc1 = (j & 1) ? (jc0 + 1 == nyc ? 0 : jc0 + 1) : jc0;
+    const T wy1 = (j & 1) ? T(0.5) : T(0), wy0 = T(1) - wy1;
+    int pz0, pz1;
+    T wz1;
     if (zc) {
-        if (kf & 1) { pz[0] = (kf - 1) / 2 + 1; pz[1] = 0; wz[0] = T(1); wz[1] = T(0); nzs = 1; }
-        else { pz[0] = kf / 2; pz[1] = kf / 2 + 1; wz[0] = wz[1] = T(0.5); nzs = 2; }
-    } else { pz[0] = kf + 1; pz[1] = 0; wz[0] = T(1); wz[1] = T(0); nzs = 1; }
-    T acc = T(0);
-    for (int a = 0; a < nzs; ++a) {
-        const T *pc = uc + (size_t)pz[a] * planec;
-        for (int b = 0; b < nys; ++b)
-            for (int c = 0; c < nxs; ++c) acc += wz[a] * wyv[b] * wx[c] * pc[jy[b] * nxc + ix[c]];
+        if (kf & 1) { pz0 = pz1 = (kf - 1) / 2 + 1; wz1 = T(0); }
+        else { pz0 = kf / 2; pz1 = kf / 2 + 1; wz1 = T(0.5); }
+    } else {
+        pz0 = pz1 = kf + 1;
+        wz1 = T(0);
     }
-    uf[(size_t)(kf + 1) * planef + j * nxf + i] += acc;
+    const T wz0 = T(1) - wz1;
+    T ev = T(0), od = T(0);
+    auto row = [&](int pz, int jc, T w) {
+        const T *r = uc + (size_t)pz * planec + (size_t)jc * nxc;
+        const T a = r[ic], b = r[icp];
+        ev += w * a;
+        od += w * (T(0.5) * (a + b));
+    };
+    row(pz0, jc0, wz0 * wy0);
+    if (wy1 != T(0)) row(pz0, jc1, wz0 * wy1);
+    if (wz1 != T(0)) {
+        row(pz1, jc0, wz1 * wy0);
+        if (wy1 != T(0)) row(pz1, jc1, wz1 * wy1);
+    }
+    T *f = uf + (size_t)(kf + 1) * planef + (size_t)j * nxf + 2 * ic;
+    f[0] += ev;
+    f[1] += od;
 }
 
 // Coarse node eps by full weighting of the fine node eps (ghost planes map to
@@ -1128,7 +1145,8 @@ void launch_restrict(hipStream_t s, const Level &F, const Level &C, const T *rf,
 }
 template <class T>
 void launch_prolong_add(hipStream_t s, const Level &F, const Level &C) {
-    dim3 g((F.nx + BX - 1) / BX, (F.ny + BY - 1) / BY, F.nw), blk(BX, BY);
+    if (F.nx != 2 * C.nx || F.ny != 2 * C.ny) fail(DWP_EINVAL, "internal: prolongation needs x and y coarsened by 2");
+    dim3 g((C.nx + BX - 1) / BX, (F.ny + BY - 1) / BY, F.nw), blk(BX, BY);
     k_prolong_add<T><<<g, blk, 0, s>>>(F.u.as<T>(), C.u.as<T>(), F.nx, F.ny, C.nx, C.ny, C.zc ? 1 : 0);
     DWP_LAUNCH_CHECK();
 }
