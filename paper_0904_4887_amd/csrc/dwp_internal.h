@@ -173,7 +173,6 @@ void launch_apply_full(hipStream_t s, const Plan &p, const double *phi, const do
 void launch_eps_gradient(hipStream_t s, const Plan &p, const double *phi, double *g);
 void launch_eps_pair(hipStream_t s, const Plan &p, const double *a, const double *b, double scale, double *g);
 void launch_fill(hipStream_t s, double *x, double v, size_t n);
-void launch_axpby(hipStream_t s, double *y, double a, const double *x, double b, size_t n);
 void launch_scale_dev(hipStream_t s, double *x, const double *num, const double *den_sq,
                       size_t n, int mode);
 void launch_rhs(hipStream_t s, const double *rho, const double *sum, double inv_n, double *b, size_t n);
@@ -197,8 +196,6 @@ template <class T>
 void launch_level_residual(hipStream_t s, const Level &L, T *r);  // r = f - A u
 template <class T>
 void launch_level_smooth(hipStream_t s, const Level &L, int color);
-template <class T>
-void launch_level_coarse_solve(hipStream_t s, const Level &L, int sweeps);
 // fc = full weighting of the fine residual rf; also zeroes C.u
 template <class T>
 void launch_restrict(hipStream_t s, const Level &F, const Level &C, const T *rf, T *fc);

@@ -26,6 +26,8 @@ namespace dwp {
 namespace {
 
 constexpr int FFT_THREADS = 512;
+constexpr int FFT_MAXE = 4096;   // complex values per block (lines x length) at most
+constexpr int FFT_BUDGET_X = 2048, FFT_BUDGET_Y = 4096, FFT_BUDGET_Z = 4096;
 constexpr int MAX_STAGES = 12;
 
 // Division by a small positive d through one multiply-high: with
@@ -134,7 +136,7 @@ template <class C> struct DFT<8, C> {
 template <int R, class C>
 __device__ void stage(C *buf, int n, int p, unsigned pm, int tstride, int lb, int es, int ls,
                       const C *__restrict__ tw, bool inv) {
-    constexpr int K = (4096 / R + FFT_THREADS - 1) / FFT_THREADS;
+    constexpr int K = (FFT_MAXE / R + FFT_THREADS - 1) / FFT_THREADS;
     const int T = n / R;
     const int items = T << lb;
     const int bmask = (1 << lb) - 1;
@@ -415,7 +417,7 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
     auto pe = [&](int ev, int g, double b) { if (prof) prof->end(st, ev, g, b); };
     int ev;
     const int nrows = p.ny * p.nz;
-    const int lbx = tile_log2(p.nx, 2048), Bx = 1 << lbx;
+    const int lbx = tile_log2(p.nx, FFT_BUDGET_X), Bx = 1 << lbx;
     const int gx = (nrows + 2 * Bx - 1) / (2 * Bx);
     const size_t ldsx = sizeof(C) * Bx * (p.nx + 1);
     const Div dn = make_div(p.nx), dk = make_div(p.nkx);
@@ -424,13 +426,13 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
                                                   dk);
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_X, bx);
-    const int lby = tile_log2(p.ny, 4096), By = 1 << lby;
+    const int lby = tile_log2(p.ny, FFT_BUDGET_Y), By = 1 << lby;
     dim3 gy((p.nkx + By - 1) / By, p.nz);
     ev = pb(PG_FFT_Y);
     k_fft_y<S><<<gy, FFT_THREADS, sizeof(C) * By * p.ny, st>>>(cbuf, radices_of(ay), TW(ay), lby, p.nkx, p.ldc, 0);
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_Y, 2.0 * cb * Cn);
-    const int lbz = tile_log2(p.nz, 4096), Bz = 1 << lbz;
+    const int lbz = tile_log2(p.nz, FFT_BUDGET_Z), Bz = 1 << lbz;
     dim3 gz((p.nkx + Bz - 1) / Bz, p.ny);
     ev = pb(PG_FFT_Z);
     k_fft_z_green<S><<<gz, FFT_THREADS, sizeof(C) * Bz * p.nz, st>>>(cbuf, radices_of(az), TW(az), lbz, p.nkx, p.ldc,

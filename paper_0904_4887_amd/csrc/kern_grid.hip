@@ -20,31 +20,9 @@ __device__ __forceinline__ int wrap_p(int i, int n) { return (i + 1 == n) ? 0 : 
 __device__ __forceinline__ int wrap_m(int i, int n) { return (i == 0) ? n - 1 : i - 1; }
 
 // ---------------------------------------------------------------- full box
-__global__ void __launch_bounds__(BX *BY)
-k_apply_full(const double *__restrict__ phi, const double *__restrict__ eps,
-             const double *__restrict__ b, double *__restrict__ out, int nx, int ny, int nz,
-             double cx, double cy, double cz, int residual) {
-    const int i = blockIdx.x * BX + threadIdx.x;
-    const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= nx || j >= ny) return;
-    const size_t plane = (size_t)nx * ny;
-    const size_t row = (size_t)k * plane + (size_t)j * nx;
-    const size_t c = row + i;
-    const size_t xp = row + wrap_p(i, nx), xm = row + wrap_m(i, nx);
-    const size_t yp = (size_t)k * plane + (size_t)wrap_p(j, ny) * nx + i;
-    const size_t ym = (size_t)k * plane + (size_t)wrap_m(j, ny) * nx + i;
-    const size_t zp = (size_t)wrap_p(k, nz) * plane + (size_t)j * nx + i;
-    const size_t zm = (size_t)wrap_m(k, nz) * plane + (size_t)j * nx + i;
-    const double e0 = eps[c], p0 = phi[c];
-    double acc = cx * ((e0 + eps[xp]) * (phi[xp] - p0) + (e0 + eps[xm]) * (phi[xm] - p0)) +
-                 cy * ((e0 + eps[yp]) * (phi[yp] - p0) + (e0 + eps[ym]) * (phi[ym] - p0)) +
-                 cz * ((e0 + eps[zp]) * (phi[zp] - p0) + (e0 + eps[zm]) * (phi[zm] - p0));
-    acc *= 0.5;
-    out[c] = residual ? b[c] - acc : acc;
-}
 
-// z-marching form of the same operator: a thread owns one (i, j) column for
+// The operator on arrays that are not all 16-byte aligned (the tiled kernel
+// further down handles the aligned case): a thread owns one (i, j) column for
 // ZM consecutive planes and keeps phi and eps of planes k-1, k, k+1 in
 // registers, so each point loads its centre values once and its four in-plane
 // neighbours through the cache.  Blocks are renumbered so that each of the 8
@@ -279,10 +257,6 @@ __global__ void k_zero(T *x, size_t n) {
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
         x[t] = T(0);
 }
-__global__ void k_axpby(double *y, double a, const double *x, double b, size_t n) {
-    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
-        y[t] = a * x[t] + b * y[t];
-}
 // mode 0: x *= 1/sqrt(*den_sq) (0 when *den_sq is 0: a breakdown leaves a zero
 // vector); mode 1: x *= *num
 __global__ void k_scale_dev(double *x, const double *num, const double *den_sq, size_t n, int mode) {
@@ -329,31 +303,6 @@ __global__ void k_check(const double *x, size_t n, int *flags, int check_ge1) {
 }
 
 // ---------------------------------------------------------------- wet slab <-> box
-// fW[kk] = (v - A dD) at box plane (k_w0 + kk) mod nz
-template <class T>
-__global__ void __launch_bounds__(BX *BY)
-k_wet_residual(const double *__restrict__ v, const double *__restrict__ dD,
-               const double *__restrict__ eps, T *__restrict__ fW, int nx, int ny, int nz,
-               int k_w0, double cx, double cy, double cz) {
-    const int i = blockIdx.x * BX + threadIdx.x;
-    const int j = blockIdx.y * BY + threadIdx.y;
-    const int kk = blockIdx.z;
-    if (i >= nx || j >= ny) return;
-    const int k = (k_w0 + kk) % nz;
-    const size_t plane = (size_t)nx * ny;
-    const size_t row = (size_t)k * plane + (size_t)j * nx;
-    const size_t c = row + i;
-    const size_t xp = row + wrap_p(i, nx), xm = row + wrap_m(i, nx);
-    const size_t yp = (size_t)k * plane + (size_t)wrap_p(j, ny) * nx + i;
-    const size_t ym = (size_t)k * plane + (size_t)wrap_m(j, ny) * nx + i;
-    const size_t zp = (size_t)wrap_p(k, nz) * plane + (size_t)j * nx + i;
-    const size_t zm = (size_t)wrap_m(k, nz) * plane + (size_t)j * nx + i;
-    const double e0 = eps[c], p0 = dD[c];
-    double acc = cx * ((e0 + eps[xp]) * (dD[xp] - p0) + (e0 + eps[xm]) * (dD[xm] - p0)) +
-                 cy * ((e0 + eps[yp]) * (dD[yp] - p0) + (e0 + eps[ym]) * (dD[ym] - p0)) +
-                 cz * ((e0 + eps[zp]) * (dD[zp] - p0) + (e0 + eps[zm]) * (dD[zm] - p0));
-    fW[(size_t)kk * plane + (size_t)j * nx + i] = (T)(v[c] - 0.5 * acc);
-}
 
 // z at box plane (k_w0 + kk) mod nz += uW (ghosted plane kk + 1).  Grid:
 // (plane chunks, kk); PAIRS: two consecutive points per thread (plane even,
@@ -506,31 +455,6 @@ k_level_smooth(T *__restrict__ u, const T *__restrict__ e, const T *__restrict__
     u0[a.nx * a.ny + li] = gs_value(off, f[(size_t)kk * plane + li], diag);
 }
 
-// Coarsest level: `sweeps` red-black sweeps by one workgroup.
-template <class T>
-__global__ void __launch_bounds__(1024)
-k_level_coarse(T *__restrict__ u, const T *__restrict__ e, const T *__restrict__ f, LevelArgs a,
-               int sweeps) {
-    const int half = a.nx / 2;
-    const int per_color = half * a.ny * a.nw;
-    const size_t plane = (size_t)a.nx * a.ny;
-    for (int s = 0; s < sweeps; ++s) {
-        for (int color = 0; color < 2; ++color) {
-            for (int q = threadIdx.x; q < per_color; q += blockDim.x) {
-                const int t = q % half;
-                const int j = (q / half) % a.ny;
-                const int kk = q / (half * a.ny);
-                const int i = 2 * t + ((j + kk + color) & 1);
-                const size_t li = (size_t)kk * plane + (size_t)j * a.nx + i;
-                const size_t g = li + plane;
-                T off, diag;
-                level_sums(u, e, a, i, j, g, off, diag);
-                u[g] = gs_value(off, f[li], diag);
-            }
-            __syncthreads();
-        }
-    }
-}
 
 // Full weighting: 1/4, 1/2, 1/4 along every coarsened direction (periodic in
 // x, y; in z the three fine planes 2kc, 2kc+1, 2kc+2 all lie inside the slab).
@@ -1061,10 +985,6 @@ void launch_fill(hipStream_t s, double *x, double v, size_t n) {
     k_fill<<<grid1d(n), 256, 0, s>>>(x, v, n);
     DWP_LAUNCH_CHECK();
 }
-void launch_axpby(hipStream_t s, double *y, double a, const double *x, double b, size_t n) {
-    k_axpby<<<grid1d(n), 256, 0, s>>>(y, a, x, b, n);
-    DWP_LAUNCH_CHECK();
-}
 void launch_scale_dev(hipStream_t s, double *x, const double *num, const double *den_sq, size_t n, int mode) {
     k_scale_dev<<<grid1d(n), 256, 0, s>>>(x, num, den_sq, n, mode);
     DWP_LAUNCH_CHECK();
@@ -1129,12 +1049,6 @@ void launch_level_smooth(hipStream_t s, const Level &L, int color) {
     const int half = L.nx / 2;
     dim3 g((half + BX - 1) / BX, (L.ny + BY - 1) / BY, L.nw), blk(BX, BY);
     k_level_smooth<T><<<g, blk, 0, s>>>(L.u.as<T>(), L.eps.as<T>(), L.f.as<T>(), a, color);
-    DWP_LAUNCH_CHECK();
-}
-template <class T>
-void launch_level_coarse_solve(hipStream_t s, const Level &L, int sweeps) {
-    LevelArgs a = level_args(L);
-    k_level_coarse<T><<<1, 1024, 0, s>>>(L.u.as<T>(), L.eps.as<T>(), L.f.as<T>(), a, sweeps);
     DWP_LAUNCH_CHECK();
 }
 template <class T>
@@ -1253,7 +1167,6 @@ void launch_zero(hipStream_t s, T *x, size_t n) {
     template void launch_wet_eps<T>(hipStream_t, const Plan &, const double *, T *);                  \
     template void launch_level_residual<T>(hipStream_t, const Level &, T *);                          \
     template void launch_level_smooth<T>(hipStream_t, const Level &, int);                            \
-    template void launch_level_coarse_solve<T>(hipStream_t, const Level &, int);                      \
     template void launch_restrict<T>(hipStream_t, const Level &, const Level &, const T *, T *);      \
     template void launch_prolong_add<T>(hipStream_t, const Level &, const Level &);                   \
     template void launch_coarsen_eps<T>(hipStream_t, const Level &, const Level &);                   \
