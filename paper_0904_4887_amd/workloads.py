@@ -125,8 +125,9 @@ def _slab_workload(name, n, L, cells_xy, layer_dz, seed, z_cut, tol, precision, 
     # With a really dry region the eps^-1/2-scaled dry update needs fewer
     # coupling iterations; with solvent inside the "dry" region it needs more,
     # and there the coupling, not the multigrid, limits the iteration count, so
-    # a lighter V(1,1) cycle with a short coarsest solve costs no iterations.
-    opts = dict(scaled_dry=1) if exclusion else dict(pre=1, post=1, coarse_sweeps=16)
+    # a lighter V(1,1) cycle with a short coarsest solve (4 sweeps) costs no
+    # iterations.
+    opts = dict(scaled_dry=1) if exclusion else dict(pre=1, post=1, coarse_sweeps=4)
     return Workload(name=name, n=n, L=L, xyz=xyz, q=q, sigma=sigma, radius=radius,
                     eps_kind="erf", eps_params=params, z_wet=z_wet, tol=tol,
                     precision=precision, buried=buried, opts=opts)
