@@ -179,10 +179,23 @@ k_orth_update2(double *__restrict__ w, const double *__restrict__ V, size_t ldv,
     if (threadIdx.x == 0) partial[blockIdx.x] = res[0];
 }
 
-// x <- x / nu with nu = sqrt(*nu2), unless nu is 0 or within 1e-8 of 1.
+// nu^2 = sum of the nparts block partials (every block adds them in the same
+// fixed order, so all agree bitwise; block 0 stores it at *nu2); then
+// x <- x / nu unless nu is 0 or within 1e-8 of 1.
 __global__ void __launch_bounds__(RED_THREADS)
-k_rescale_if(double *__restrict__ x, const double *__restrict__ nu2, size_t n) {
-    const double nu = sqrt(*nu2);
+k_rescale_if(double *__restrict__ x, const double *__restrict__ partial, int nparts, double *__restrict__ nu2,
+             size_t n) {
+    __shared__ double sh[RED_THREADS / 64];
+    __shared__ double tot;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += RED_THREADS) v += partial[b];
+    const double r = block_sum(v, sh);
+    if (threadIdx.x == 0) {
+        tot = r;
+        if (blockIdx.x == 0) *nu2 = r;
+    }
+    __syncthreads();
+    const double nu = sqrt(tot);
     if (nu == 0.0 || fabs(nu - 1.0) <= 1e-8) return;
     const double s = 1.0 / nu;
     for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n; t += (size_t)gridDim.x * RED_THREADS)
@@ -212,15 +225,20 @@ k_axpy2(double *__restrict__ w, const double *__restrict__ V, size_t ldv, const 
     }
 }
 
-// out[idx] = sum_b partial[b * stride + idx], one block per idx, fixed order
+// out[idx] = sum_b partial[b * stride + idx], one block per idx, fixed order;
+// with norm_out, one more block adds column NORM_SLOT into *norm_out
 __global__ void __launch_bounds__(RED_THREADS)
-k_reduce_partials(const double *__restrict__ partial, int nblocks, int stride, double *__restrict__ out) {
+k_reduce_partials(const double *__restrict__ partial, int nblocks, int stride, double *__restrict__ out,
+                  int nout, double *__restrict__ norm_out) {
     __shared__ double sh[RED_THREADS / 64];
-    const int idx = blockIdx.x;
+    const int idx = blockIdx.x < nout ? (int)blockIdx.x : NORM_SLOT;
     double v = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += RED_THREADS) v += partial[(size_t)b * stride + idx];
     const double r = block_sum(v, sh);
-    if (threadIdx.x == 0) out[idx] = r;
+    if (threadIdx.x == 0) {
+        if ((int)blockIdx.x < nout) out[idx] = r;
+        else *norm_out = r;
+    }
 }
 
 __global__ void __launch_bounds__(RED_THREADS)
@@ -349,12 +367,9 @@ void launch_multidot(hipStream_t s, const double *V, size_t ldv, int nv, const d
             DWP_LAUNCH_CHECK();
         }
     }
-    k_reduce_partials<<<nv, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, MD_STRIDE, out);
+    k_reduce_partials<<<nv + (norm_out ? 1 : 0), RED_THREADS, 0, s>>>(partial, RED_BLOCKS, MD_STRIDE, out, nv,
+                                                                     norm_out);
     DWP_LAUNCH_CHECK();
-    if (norm_out) {
-        k_reduce_partials<<<1, RED_THREADS, 0, s>>>(partial + NORM_SLOT, RED_BLOCKS, MD_STRIDE, norm_out);
-        DWP_LAUNCH_CHECK();
-    }
 }
 
 void launch_dot(hipStream_t s, const double *x, const double *y, size_t n, double *partial, double *out) {
@@ -364,7 +379,7 @@ void launch_dot(hipStream_t s, const double *x, const double *y, size_t n, doubl
 void launch_sum(hipStream_t s, const double *x, size_t n, double *partial, double *out) {
     k_sum<<<RED_BLOCKS, RED_THREADS, 0, s>>>(x, n, partial);
     DWP_LAUNCH_CHECK();
-    k_reduce_partials<<<1, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, 1, out);
+    k_reduce_partials<<<1, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, 1, out, 1, nullptr);
     DWP_LAUNCH_CHECK();
 }
 
@@ -384,7 +399,7 @@ void launch_axpy_multi(hipStream_t s, double *w, const double *V, size_t ldv, in
     k_axpy_multi<<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, V, ldv, nv, c, n, sign, norm_out ? partial : nullptr);
     DWP_LAUNCH_CHECK();
     if (norm_out) {
-        k_reduce_partials<<<1, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, 1, norm_out);
+        k_reduce_partials<<<1, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, 1, norm_out, 1, nullptr);
         DWP_LAUNCH_CHECK();
     }
 }
@@ -406,9 +421,7 @@ void launch_orth_update(hipStream_t s, double *w, const double *V, size_t ldv, i
 #undef DWP_OU_CASE
     }
     DWP_LAUNCH_CHECK();
-    k_reduce_partials<<<1, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, 1, hc + 65);
-    DWP_LAUNCH_CHECK();
-    k_rescale_if<<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, hc + 65, n);
+    k_rescale_if<<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, partial, RED_BLOCKS, hc + 65, n);
     DWP_LAUNCH_CHECK();
 }
 
