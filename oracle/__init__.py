@@ -18,7 +18,9 @@ What it computes (paper, Sec. II.B-II.F and Appendix B):
     the product-of-erf switches and the Gaussian charges;
   * the paper's one-pass split (vacuum FFT, then a Dirichlet solve in the wet
     slab with the vacuum potential as boundary data, Sec. II.F) as a
-    diagnostic.
+    diagnostic;
+  * the density-dependent permittivity (Eq. 7), its derivative (Eq. 8) and the
+    potential term V_eps (Eq. 6) of Sec. II.B.
 
 Every pin of these functions lives in the CPU test-suite.  Parity unpinned:
 none of the functions above (the one-pass split is pinned only by its epsilon
@@ -28,7 +30,9 @@ from .poisson import (apply_A, vacuum_symbol, vacuum_solve, solve, energy,
                       energy_eps_form, eps_gradient, residual_norm)
 from .atoms import eps_erf, rho_gauss, forces, deps_dR_dense, drho_dR_dense
 from .split import one_pass_split
+from .density import eps_of_density, deps_drho, v_eps
 
 __all__ = ["apply_A", "vacuum_symbol", "vacuum_solve", "solve", "energy",
            "energy_eps_form", "eps_gradient", "residual_norm", "eps_erf",
-           "rho_gauss", "forces", "deps_dR_dense", "drho_dR_dense", "one_pass_split"]
+           "rho_gauss", "forces", "deps_dR_dense", "drho_dR_dense", "one_pass_split",
+           "eps_of_density", "deps_drho", "v_eps"]
