@@ -152,6 +152,43 @@ def md_loop(w, steps, torch, precision="mixed"):
     return per
 
 
+def density_steps(torch, n=(192, 192, 384), steps=4, warmup=1, precision="mixed"):
+    """Density-dependent permittivity (Eq. 7): eps and d eps/d rho from an
+    electron-density grid, the solve, and V_eps (Eq. 6), per step; the density
+    and the source are resident before timing."""
+    w = W.density_slab(n)
+    p = w.eps_params
+    s = solver_for(w, precision, torch)
+    rho_e = torch.from_numpy(W.electron_density(w)).cuda()
+    src = s.build_rho(w.xyz, w.q, w.sigma)
+    phi = s.empty()
+    v = s.empty()
+    infos = []
+
+    def step():
+        s.build_epsilon_density(rho_e, p["eps_inf"], p["rho0"], p["beta"])
+        _, E, info = s.solve(src, phi)
+        s.v_eps(out=v)
+        return E, info
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        E, info = step()
+        infos.append(info)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    vmax = float(v.abs().max())
+    pmax = float(phi.abs().max())
+    s.close()
+    return {"ms_per_step": round(1e3 * sec, 2), "steps_per_s": round(1.0 / sec, 3),
+            "iters": [i["outer_iters"] for i in infos], "energy": E, "z_wet": list(w.z_wet),
+            "rho0": p["rho0"], "beta": p["beta"], "max_abs_v_eps": vmax, "max_abs_phi": pmax,
+            "v_eps_over_phi": round(vmax / pmax, 3)}
+
+
 def copy_ceiling(torch):
     """Measured device copy bandwidth (1 GiB read + 1 GiB written per copy)."""
     x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
@@ -316,6 +353,10 @@ def main():
                                    "iters_cold": per[0]["iters"],
                                    "iters_warm_mean": round(float(np.mean([p["iters"] for p in per[1:]])), 2)}
         print(f"# md: {[p['ms'] for p in per]} ms, iters {[p['iters'] for p in per]}", file=sys.stderr, flush=True)
+
+    if not args.no_compare and w.n == (192, 192, 384):
+        extra["density_eps_192x192x384"] = density_steps(torch, precision=args.precision)
+        print(f"# density eps: {extra['density_eps_192x192x384']}", file=sys.stderr, flush=True)
 
     if not args.no_compare:
         extra["hbm_resident_smoother_512"] = hbm_resident_smoother(torch)

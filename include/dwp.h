@@ -159,6 +159,29 @@ int dwp_build_epsilon(dwp_ctx *ctx, int n, const double *xyz_host, const double 
                       const dwp_eps_params *params);
 int dwp_get_epsilon(dwp_ctx *ctx, double *eps_dev);
 
+/* Density-dependent permittivity (Sec. II.B): eps_n = eps(rho_n) by Eq. 7,
+ *   eps(rho) = 1 + (eps_inf - 1)/2 (1 + (1 - (rho/rho0)^(2 beta)) / (1 + (rho/rho0)^(2 beta))),
+ * from an electron-density grid rho_dev (N doubles on the device, the grid's
+ * x-fastest layout; read only during the call; negative values are read as
+ * zero density).  Also stores d eps/d rho (Eq. 8) in the context for
+ * dwp_v_eps.  eps_inf >= 1, rho0 > 0 and 0.5 < beta <= 1000 (2 beta > 1 keeps
+ * Eq. 8 finite at zero density), else DWP_EINVAL; a non-finite density gives
+ * DWP_ENONFINITE.  Replaces any earlier eps; dwp_forces then takes no
+ * permittivity term (params must be NULL, or DWP_ESTATE). */
+int dwp_build_epsilon_density(dwp_ctx *ctx, const double *rho_dev, double eps_inf, double rho0,
+                              double beta);
+
+/* V_eps of Eq. 6 for the last solution, on the grid: the derivative of the
+ * discrete energy with respect to the density that enters eps, per unit
+ * volume,
+ *   V_eps,n = (dE/d eps_n / h^3) (d eps/d rho)_n
+ *           = -(1/8 pi) sum_d 1/2 [(D+_d phi)_n^2 + (D-_d phi)_n^2] (d eps/d rho)_n,
+ * written to out_dev (N doubles, device).  add_phi = 1 adds phi_n: the
+ * density derivative of E per unit volume when the same density is the
+ * source and the argument of eps (Eq. 5).  DWP_ESTATE unless eps came from
+ * dwp_build_epsilon_density and dwp_solve has run since. */
+int dwp_v_eps(dwp_ctx *ctx, int add_phi, double *out_dev);
+
 /* Gaussian charges (the smeared ionic densities of Sec. II.C, here with
  * sigma_i a standard deviation): rho_n = sum_i q_i (2 pi sigma_i^2)^(-3/2)
  * exp(-d_in^2 / (2 sigma_i^2)), minimum image, cut off at 9 sigma_i

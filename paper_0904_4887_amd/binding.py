@@ -64,6 +64,8 @@ _SIGNATURES = {
     "dwp_set_epsilon": (C.c_int, [_P, _P]),
     "dwp_build_epsilon": (C.c_int, [_P, C.c_int, _D, _D, C.POINTER(EpsParams)]),
     "dwp_get_epsilon": (C.c_int, [_P, _P]),
+    "dwp_build_epsilon_density": (C.c_int, [_P, _P, C.c_double, C.c_double, C.c_double]),
+    "dwp_v_eps": (C.c_int, [_P, C.c_int, _P]),
     "dwp_build_rho": (C.c_int, [_P, C.c_int, _D, _D, _D, _P]),
     "dwp_solve": (C.c_int, [_P, _P, _P, _D, C.POINTER(Info)]),
     "dwp_eps_gradient": (C.c_int, [_P, _P]),
@@ -212,6 +214,17 @@ class Solver:
         r, rp = _hostd(radius)
         ep = eps_params(params)
         self._check(lib().dwp_build_epsilon(self._h, len(r), xp, rp, C.byref(ep)))
+
+    def build_epsilon_density(self, rho, eps_inf, rho0, beta):
+        """eps from an electron-density grid (Eq. 7); keeps d eps/d rho for v_eps."""
+        self._check(lib().dwp_build_epsilon_density(self._h, self._dev(rho, "rho"), float(eps_inf), float(rho0),
+                                                    float(beta)))
+
+    def v_eps(self, add_phi=False, out=None):
+        """V_eps (Eq. 6) of the last solution; add_phi: phi + V_eps (Eq. 5)."""
+        out = self.empty() if out is None else out
+        self._check(lib().dwp_v_eps(self._h, 1 if add_phi else 0, self._dev(out, "out")))
+        return out
 
     def get_epsilon(self):
         out = self.empty()

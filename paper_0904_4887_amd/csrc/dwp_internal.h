@@ -157,6 +157,7 @@ struct dwp_ctx {
     bool eps_exclusion = false;
     std::vector<double> atom_rec;      // host copy of the last atom upload
     std::vector<double> eps_geometry;  // switch geometry of the last build_epsilon
+    bool eps_density = false;          // eps built from a density grid; S holds d eps / d rho
 };
 
 namespace dwp {
@@ -171,6 +172,11 @@ constexpr int RED_THREADS = 256;
 void launch_apply_full(hipStream_t s, const Plan &p, const double *phi, const double *eps,
                        const double *b, double *out, bool residual);
 void launch_eps_gradient(hipStream_t s, const Plan &p, const double *phi, double *g);
+// out = V_eps = -(1/8 pi) G deps (Eq. 6; G as in the eps gradient), plus phi if add_phi (Eq. 5)
+void launch_v_eps(hipStream_t s, const Plan &p, const double *phi, const double *deps, bool add_phi, double *out);
+// eps and d eps/d rho from a density grid (Eqs. 7 and 8)
+void launch_eps_density(hipStream_t s, const double *rho, double *eps, double *deps, size_t n, double eps_inf,
+                        double rho0, double beta);
 void launch_eps_pair(hipStream_t s, const Plan &p, const double *a, const double *b, double scale, double *g);
 void launch_fill(hipStream_t s, double *x, double v, size_t n);
 void launch_scale_dev(hipStream_t s, double *x, const double *num, const double *den_sq,

@@ -200,10 +200,15 @@ k_apply_tile(const double *__restrict__ phi, const double *__restrict__ eps, con
     }
 }
 
-// dE/d eps_n = -(h^3 / 8 pi) sum_d 1/2 [(D+ phi)^2 + (D- phi)^2]
+// G_n = sum_d 1/2 [(D+ phi)^2 + (D- phi)^2] at node n (the faces around n carry
+// half of eps_n each).  MODE 0: g = scale G (scale = -h^3 / 8 pi: dE/d eps_n,
+// Eq. 11); MODE 1: g = scale G m_n (scale = -1 / 8 pi, m = d eps / d rho: V_eps
+// of Eq. 6 on the grid); MODE 2: g = phi_n + that (the density derivative of the
+// energy, Eq. 5).
+template <int MODE>
 __global__ void __launch_bounds__(BX *BY)
-k_eps_gradient(const double *__restrict__ phi, double *__restrict__ g, int nx, int ny, int nz,
-               double ihx, double ihy, double ihz, double scale) {
+k_eps_gradient(const double *__restrict__ phi, const double *__restrict__ m, double *__restrict__ g, int nx,
+               int ny, int nz, double ihx, double ihy, double ihz, double scale) {
     const int i = blockIdx.x * BX + threadIdx.x;
     const int j = blockIdx.y * BY + threadIdx.y;
     const int k = blockIdx.z;
@@ -217,7 +222,30 @@ k_eps_gradient(const double *__restrict__ phi, double *__restrict__ g, int nx, i
     double dym = (p0 - phi[(size_t)k * plane + (size_t)wrap_m(j, ny) * nx + i]) * ihy;
     double dzp = (phi[(size_t)wrap_p(k, nz) * plane + (size_t)j * nx + i] - p0) * ihz;
     double dzm = (p0 - phi[(size_t)wrap_m(k, nz) * plane + (size_t)j * nx + i]) * ihz;
-    g[c] = scale * 0.5 * (dxp * dxp + dxm * dxm + dyp * dyp + dym * dym + dzp * dzp + dzm * dzm);
+    double v = scale * 0.5 * (dxp * dxp + dxm * dxm + dyp * dyp + dym * dym + dzp * dzp + dzm * dzm);
+    if (MODE >= 1) v *= m[c];
+    if (MODE == 2) v += p0;
+    g[c] = v;
+}
+
+// Eq. 7 and its derivative Eq. 8 at every node, with the density read as
+// max(rho, 0): 1 + (eps_inf - 1)/2 (1 + (1 - p)/(1 + p)) = 1 + (eps_inf - 1)/(1 + p)
+// with p = (rho/rho_0)^(2 beta), and d eps/d rho = -(eps_inf - 1) 2 beta p / (rho (1 + p)^2).
+// Requires 2 beta > 1, so that the derivative is 0 at zero density.
+__global__ void k_eps_density(const double *__restrict__ rho, double *__restrict__ eps, double *__restrict__ deps,
+                              size_t n, double eps_inf, double inv_rho0, double two_beta) {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        const double r = fmax(rho[t], 0.0);
+        double e = eps_inf, d = 0.0;
+        if (r > 0.0) {
+            const double p = pow(r * inv_rho0, two_beta);
+            const double q = 1.0 / (1.0 + p);
+            e = 1.0 + (eps_inf - 1.0) * q;
+            d = (1.0 - eps_inf) * two_beta * (p / r) * q * q;
+        }
+        eps[t] = e;
+        deps[t] = d;
+    }
 }
 
 // out_n = scale * sum_d 1/2 [(D+_d a)(D+_d b) + (D-_d a)(D-_d b)]: the derivative
@@ -971,7 +999,26 @@ void launch_eps_gradient(hipStream_t s, const Plan &p, const double *phi, double
     const double h3 = p.h[0] * p.h[1] * p.h[2];
     const double scale = -h3 / (8.0 * 3.14159265358979323846);
     dim3 gr((p.nx + BX - 1) / BX, (p.ny + BY - 1) / BY, p.nz), blk(BX, BY);
-    k_eps_gradient<<<gr, blk, 0, s>>>(phi, g, p.nx, p.ny, p.nz, 1.0 / p.h[0], 1.0 / p.h[1], 1.0 / p.h[2], scale);
+    k_eps_gradient<0><<<gr, blk, 0, s>>>(phi, nullptr, g, p.nx, p.ny, p.nz, 1.0 / p.h[0], 1.0 / p.h[1],
+                                         1.0 / p.h[2], scale);
+    DWP_LAUNCH_CHECK();
+}
+
+void launch_v_eps(hipStream_t s, const Plan &p, const double *phi, const double *deps, bool add_phi, double *out) {
+    const double scale = -1.0 / (8.0 * 3.14159265358979323846);
+    dim3 gr((p.nx + BX - 1) / BX, (p.ny + BY - 1) / BY, p.nz), blk(BX, BY);
+    if (add_phi)
+        k_eps_gradient<2><<<gr, blk, 0, s>>>(phi, deps, out, p.nx, p.ny, p.nz, 1.0 / p.h[0], 1.0 / p.h[1],
+                                             1.0 / p.h[2], scale);
+    else
+        k_eps_gradient<1><<<gr, blk, 0, s>>>(phi, deps, out, p.nx, p.ny, p.nz, 1.0 / p.h[0], 1.0 / p.h[1],
+                                             1.0 / p.h[2], scale);
+    DWP_LAUNCH_CHECK();
+}
+
+void launch_eps_density(hipStream_t s, const double *rho, double *eps, double *deps, size_t n, double eps_inf,
+                        double rho0, double beta) {
+    k_eps_density<<<grid1d(n), 256, 0, s>>>(rho, eps, deps, n, eps_inf, 1.0 / rho0, 2.0 * beta);
     DWP_LAUNCH_CHECK();
 }
 

@@ -649,6 +649,27 @@ void set_epsilon_impl(dwp_ctx *c, const double *eps_dev) {
     c->eps_natoms = -1;
     c->eps_exclusion = false;
     c->eps_geometry.clear();
+    c->eps_density = false;
+}
+
+void build_epsilon_density_impl(dwp_ctx *c, const double *rho_e, double eps_inf, double rho0, double beta) {
+    need_grid(c);
+    if (!rho_e) fail(DWP_EINVAL, "rho_dev is NULL");
+    if (!(eps_inf >= 1.0) || !std::isfinite(eps_inf)) fail(DWP_EINVAL, "eps_inf must be finite and >= 1");
+    if (!(rho0 > 0.0) || !std::isfinite(rho0)) fail(DWP_EINVAL, "rho0 must be finite and > 0");
+    if (!(beta > 0.5) || !(beta <= 1000.0)) fail(DWP_EINVAL, "beta must lie in (0.5, 1000]");
+    check_finite_dev(c, rho_e, "rho");
+    c->S.alloc(sizeof(double) * c->plan.N);
+    PROF(c, PG_BUILD, 24.0 * c->plan.N,
+         launch_eps_density(c->stream, rho_e, c->eps.as<double>(), c->S.as<double>(), c->plan.N, eps_inf, rho0,
+                            beta));
+    prepare_eps(c);
+    c->have_eps = true;
+    c->have_solution = false;
+    c->eps_natoms = -1;
+    c->eps_exclusion = false;
+    c->eps_geometry.clear();
+    c->eps_density = true;
 }
 
 void build_epsilon_impl(dwp_ctx *c, int n, const double *xyz, const double *radius, const dwp_eps_params *ep) {
@@ -667,6 +688,7 @@ void build_epsilon_impl(dwp_ctx *c, int n, const double *xyz, const double *radi
     c->have_solution = false;
     c->eps_natoms = n;
     c->eps_exclusion = ep->exclusion != 0;
+    c->eps_density = false;
 }
 
 void solve_impl(dwp_ctx *c, const double *rho, double *phi, double *energy, dwp_info *info) {
@@ -901,6 +923,26 @@ int dwp_eps_gradient(dwp_ctx *c, double *g) {
     if (!g) dwp::fail(DWP_EINVAL, "dEdeps_dev is NULL");
     DWP_HIP(hipSetDevice(c->device));
     dwp::launch_eps_gradient(c->stream, c->plan, c->phi_last.as<double>(), g);
+    ABI_END(c)
+}
+
+int dwp_build_epsilon_density(dwp_ctx *c, const double *rho_dev, double eps_inf, double rho0, double beta) {
+    ABI_BEGIN(c)
+    DWP_HIP(hipSetDevice(c->device));
+    dwp::build_epsilon_density_impl(c, rho_dev, eps_inf, rho0, beta);
+    ABI_END(c)
+}
+
+int dwp_v_eps(dwp_ctx *c, int add_phi, double *out) {
+    ABI_BEGIN(c)
+    dwp::need_eps(c);
+    if (!c->eps_density) dwp::fail(DWP_ESTATE, "eps was not built from a density: call dwp_build_epsilon_density");
+    if (!c->have_solution) dwp::fail(DWP_ESTATE, "no solution: call dwp_solve first");
+    if (add_phi != 0 && add_phi != 1) dwp::fail(DWP_EINVAL, "add_phi must be 0 or 1");
+    if (!out) dwp::fail(DWP_EINVAL, "out_dev is NULL");
+    DWP_HIP(hipSetDevice(c->device));
+    PROF(c, dwp::PG_FORCES, 24.0 * c->plan.N,
+         dwp::launch_v_eps(c->stream, c->plan, c->phi_last.as<double>(), c->S.as<double>(), add_phi != 0, out));
     ABI_END(c)
 }
 

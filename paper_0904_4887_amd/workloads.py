@@ -40,8 +40,8 @@ class Workload:
     q: np.ndarray         # (natoms,) charges
     sigma: np.ndarray     # (natoms,) Gaussian standard deviations
     radius: np.ndarray    # (natoms,) switch radii (unused when eps is given)
-    eps_kind: str         # "tanh_z" (eps handed over as a grid) or "erf"
-    eps_params: dict      # eps_inf, delta, exclusion (0/1), z_lim, delta_z
+    eps_kind: str         # "tanh_z" (eps handed over as a grid), "erf" or "density"
+    eps_params: dict      # eps_inf, delta, exclusion (0/1), z_lim, delta_z (density: eps_inf, rho0, beta)
     z_wet: tuple          # (z_wet_lo, z_wet_hi) Angstrom
     tol: float            # relative residual tolerance of the solve
     precision: int = 0    # 0 = FP64, 1 = mixed FP32-in-FP64
@@ -169,6 +169,49 @@ def big_slab(n=(256, 256, 512), exclusion=False, tol=1e-8, precision=1, seed=5):
     nm = f"big_slab_{n[0]}x{n[1]}x{n[2]}" + ("_excl" if exclusion else "")
     return _slab_workload(nm, tuple(n), (23.6, 23.6, 60.0), 4, 2.8, seed, 21.0, tol,
                           precision, exclusion)
+
+
+RHO0 = 0.0027            # density threshold of Eq. 7, e/A^3 (4e-4 e/bohr^3)
+BETA = 1.3               # transition exponent of Eq. 7
+
+
+def density_slab(n=(192, 192, 384), tol=1e-8, precision=1, seed=7):
+    """The slab workload with eps taken from an electron density (Eq. 7).
+
+    Same cell, atoms and charges as slab(); eps_kind "density" with
+    eps_inf = 78.36, rho0 = 0.0027 e/A^3, beta = 1.3.  The electron density
+    is electron_density(); it is at least 0.35 e/A^3 (so eps - 1 < 3e-4) for
+    z in [4.5, 12.5] A, which is the dry region; W wraps from 12.5 A through
+    z = 0 to 4.5 A.
+    """
+    w = slab(n, tol=tol, precision=precision, seed=1, name=f"density_slab_{n[0]}x{n[1]}x{n[2]}")
+    w.eps_kind = "density"
+    w.eps_params = dict(eps_inf=EPS_INF, rho0=RHO0, beta=BETA, seed=seed)
+    w.z_wet = (12.5, w.L[2] + 4.5)
+    w.opts = dict(pre=1, post=1, coarse_sweeps=4)
+    return w
+
+
+def electron_density(w):
+    """Synthetic valence density of the density_slab workload, e/A^3.
+
+    A planar slab of height 0.5 e/A^3 on z in [4.5, 12.5] A, corrugated in
+    plane by a factor 1 + 0.3 cos(2 pi (x - x0)/a) cos(2 pi (y - y0)/a) with the
+    lattice period a = 5.9 A and a seeded phase (x0, y0), decaying as
+    exp(-d/0.45 A) at distance d outside the slab; it crosses rho0 about 2.2 A
+    from either face, the solid-solvent interfaces where V_eps peaks.
+    """
+    nx, ny, nz = w.n
+    hx, hy, hz = w.h
+    rng = np.random.default_rng(w.eps_params["seed"])
+    x0, y0 = rng.uniform(0.0, 5.9, size=2)
+    x = np.arange(nx) * hx
+    y = np.arange(ny) * hy
+    z = np.arange(nz) * hz
+    d = np.maximum(np.maximum(4.5 - z, z - 12.5), 0.0)
+    prof = 0.5 * np.exp(-d / 0.45)
+    corr = 1.0 + 0.3 * np.cos(2 * np.pi * (y[:, None] - y0) / 5.9) * np.cos(2 * np.pi * (x[None, :] - x0) / 5.9)
+    return prof[:, None, None] * corr[None, :, :]
 
 
 def md_displacements(natoms, steps, seed=6, scale=0.02):

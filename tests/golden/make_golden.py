@@ -30,6 +30,7 @@ def workloads():
         "slab_192x192x384": W.slab((192, 192, 384), tol=1e-8, precision=1),
         "slab_192x192x384_excl": W.slab((192, 192, 384), exclusion=True, tol=1e-8, precision=1),
         "big_slab_256x256x512": W.big_slab(),
+        "density_slab_192x192x384": W.density_slab((192, 192, 384)),
     }
 
 
@@ -42,8 +43,14 @@ def first_below(history, tol):
 
 def make(name, w):
     t0 = time.time()
+    rho_e = None
     if w.eps_kind == "tanh_z":
         eps = w.eps_grid()
+        params = None
+    elif w.eps_kind == "density":
+        p = w.eps_params
+        rho_e = W.electron_density(w)
+        eps = O.eps_of_density(rho_e, p["eps_inf"], p["rho0"], p["beta"])
         params = None
     else:
         eps = O.eps_erf(w.n, w.L, w.xyz, w.radius, w.eps_params)
@@ -63,6 +70,12 @@ def make(name, w):
                nodes=nodes.tolist(), phi=phi.ravel()[nodes].tolist(), g=g.ravel()[nodes].tolist(),
                phi2_mean=float(np.mean(phi * phi)), t_build_s=t1 - t0, t_solve_s=t2 - t1)
     del g
+    if rho_e is not None:
+        p = w.eps_params
+        out["v_eps"] = O.v_eps(phi, rho_e, w.h, p["eps_inf"], p["rho0"], p["beta"]).ravel()[nodes].tolist()
+        # the charge term of dE/dR (eps does not move with the atoms here)
+        F = O.forces(w.n, w.L, w.xyz, None, w.q, w.sigma, None, phi, None)
+        out["forces"] = F.tolist()
     if params is not None:
         t3 = time.time()
         F = O.forces(w.n, w.L, w.xyz, w.radius, w.q, w.sigma, params, phi, O.eps_gradient(phi, w.h))

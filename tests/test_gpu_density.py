@@ -1,0 +1,187 @@
+"""Density-dependent permittivity on the GPU (Sec. II.B, Eqs. 5-8), through the C ABI.
+
+* eps(rho) built on the device equals the oracle's Eq. 7 node by node, with
+  zero and negative densities among the inputs, at a small size and at the
+  full 192 x 192 x 384 grid;
+* V_eps (Eq. 6) from the device equals the oracle's V_eps of the same phi
+  node by node, and phi + V_eps (Eq. 5) likewise;
+* the device solve with that eps matches the oracle's solve, and V_eps of the
+  device solution matches V_eps of the oracle's solution;
+* h^3 V_eps is the derivative of the device energy with respect to the density
+  entering eps (central differences of two device solves), and h^3 (phi +
+  V_eps) the derivative when one density is source and eps argument (Eq. 5);
+* state and argument errors.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_0904_4887_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+P = dict(eps_inf=W.EPS_INF, rho0=W.RHO0, beta=W.BETA)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _density_with_edges(w, seed=0):
+    """The workload's density with some nodes set to zero and some negative."""
+    rho = W.electron_density(w).copy()
+    rng = np.random.default_rng(seed)
+    flat = rho.reshape(-1)
+    idx = rng.choice(flat.size, size=64, replace=False)
+    flat[idx[:32]] = 0.0
+    flat[idx[32:]] = -rng.uniform(1e-6, 1.0, size=32)
+    return rho
+
+
+def _solver(w, **extra):
+    from paper_0904_4887_amd.binding import Solver
+    s = Solver(0)
+    s.set_grid(w.n, w.L, **w.solver_opts(**extra))
+    return s
+
+
+@pytest.mark.parametrize("n", [(48, 48, 96), (24, 18, 72), (192, 192, 384)])
+def test_eps_of_density_matches_oracle(torch, n):
+    w = W.density_slab(n)
+    rho = _density_with_edges(w)
+    s = _solver(w)
+    s.build_epsilon_density(_dev(torch, rho), **P)
+    eps = s.get_epsilon().cpu().numpy()
+    ref = O.eps_of_density(rho, **P)
+    assert np.abs(eps - ref).max() <= 4e-15 * W.EPS_INF
+    assert eps.min() >= 1.0
+    s.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_and_v_eps_match_oracle(torch, precision):
+    w = W.density_slab((48, 48, 96), tol=1e-11 if precision == 0 else 1e-9, precision=precision)
+    rho_e = _density_with_edges(w, 1)
+    s = _solver(w)
+    s.build_epsilon_density(_dev(torch, rho_e), **P)
+    src = O.rho_gauss(w.n, w.L, w.xyz, w.q, w.sigma)
+    phi, E, info = s.solve(_dev(torch, src))
+    assert info["rel_res"] <= w.tol
+    ph = phi.cpu().numpy()
+    # the kernel against the oracle's V_eps of the same phi
+    v = s.v_eps().cpu().numpy()
+    ref_same = O.v_eps(ph, rho_e, w.h, **P)
+    assert np.abs(v - ref_same).max() <= 1e-13 * np.abs(ref_same).max()
+    vp = s.v_eps(add_phi=True).cpu().numpy()
+    assert np.abs(vp - (ph + ref_same)).max() <= 1e-13 * np.abs(ph + ref_same).max()
+    # the whole path against the oracle's own solve
+    eps = O.eps_of_density(rho_e, **P)
+    ref_phi = O.solve(src, eps, w.h, tol=1e-13, max_iter=1000)
+    scale = 1e3 * w.tol
+    assert np.abs(ph - ref_phi).max() <= scale * np.abs(ref_phi).max()
+    assert abs(E - O.energy(src, ref_phi, w.h)) <= scale * abs(E)
+    ref_v = O.v_eps(ref_phi, rho_e, w.h, **P)
+    assert np.abs(v - ref_v).max() <= 10 * scale * np.abs(ref_v).max()
+    # the charge term of the forces still holds with a density-built eps
+    F = s.forces(w.xyz, w.q, w.sigma)
+    F_ref = O.forces(w.n, w.L, w.xyz, None, w.q, w.sigma, None, ref_phi, None)
+    assert np.abs(F - F_ref).max() <= 10 * scale * np.abs(F_ref).max()
+    s.close()
+
+
+def _device_energy(torch, s, src_dev, rho_e):
+    s.build_epsilon_density(_dev(torch, rho_e), **P)
+    _, E, _ = s.solve(src_dev)
+    return E
+
+
+def test_v_eps_is_the_device_energy_derivative(torch):
+    w = W.density_slab((48, 48, 96), tol=1e-12, precision=0)
+    rho_e = W.electron_density(w)
+    s = _solver(w)
+    src = _dev(torch, O.rho_gauss(w.n, w.L, w.xyz, w.q, w.sigma))
+    s.build_epsilon_density(_dev(torch, rho_e), **P)
+    s.solve(src)
+    V = s.v_eps().cpu().numpy().reshape(-1)
+    h3 = w.h[0] * w.h[1] * w.h[2]
+    flat = rho_e.reshape(-1)
+    for q in np.argsort(-np.abs(V))[:2]:
+        d = 1e-3 * flat[q]
+        rp, rm = flat.copy(), flat.copy()
+        rp[q] += d
+        rm[q] -= d
+        fd = (_device_energy(torch, s, src, rp.reshape(rho_e.shape))
+              - _device_energy(torch, s, src, rm.reshape(rho_e.shape))) / (2 * d)
+        assert abs(fd - h3 * V[q]) <= 1e-4 * abs(h3 * V[q]), (q, fd, h3 * V[q])
+    s.close()
+
+
+def test_density_derivative_is_phi_plus_v_eps_on_device(torch):
+    # one density as source (neutralised by the mean) and as eps argument (Eq. 5)
+    # (such a source has a potential ~60 times larger than the slab's charges, and
+    # a relative residual of 1e-12 is below what float64 reaches for it)
+    w = W.density_slab((48, 48, 96), tol=1e-11, precision=0)
+    rho_e = W.electron_density(w)
+    s = _solver(w)
+
+    def energy(r):
+        d = _dev(torch, r)
+        s.build_epsilon_density(d, **P)
+        _, E, _ = s.solve(d)
+        return E
+
+    energy(rho_e)
+    G = s.v_eps(add_phi=True).cpu().numpy().reshape(-1)
+    V = s.v_eps().cpu().numpy().reshape(-1)
+    h3 = w.h[0] * w.h[1] * w.h[2]
+    flat = rho_e.reshape(-1)
+    # where V_eps peaks (phi is under 1% of the sum there) and where phi peaks
+    # inside the slab (V_eps ~ 0 there)
+    for q in [int(np.argmax(np.abs(V))), int(np.argmax(np.abs(G - V)))]:
+        d = 1e-3 * flat[q]
+        rp, rm = flat.copy(), flat.copy()
+        rp[q] += d
+        rm[q] -= d
+        fd = (energy(rp.reshape(rho_e.shape)) - energy(rm.reshape(rho_e.shape))) / (2 * d)
+        assert abs(fd - h3 * G[q]) <= 1e-3 * abs(h3 * G[q]), (q, fd, h3 * G[q], h3 * (G[q] - V[q]))
+    s.close()
+
+
+def test_density_state_and_argument_errors(torch):
+    from paper_0904_4887_amd.binding import DWPError, DWP_EINVAL, DWP_ENONFINITE, DWP_ESTATE
+    w = W.density_slab((16, 16, 32))
+    rho_e = W.electron_density(w)
+    s = _solver(w)
+    d = _dev(torch, rho_e)
+    with pytest.raises(DWPError) as e:        # no eps yet
+        s.v_eps()
+    assert e.value.status == DWP_ESTATE
+    for bad in (dict(P, beta=0.5), dict(P, rho0=0.0), dict(P, eps_inf=0.5), dict(P, beta=float("nan"))):
+        with pytest.raises(DWPError) as e:
+            s.build_epsilon_density(d, **bad)
+        assert e.value.status == DWP_EINVAL
+    nan = rho_e.copy()
+    nan[3, 2, 1] = np.nan
+    with pytest.raises(DWPError) as e:
+        s.build_epsilon_density(_dev(torch, nan), **P)
+    assert e.value.status == DWP_ENONFINITE
+    s.build_epsilon_density(d, **P)
+    with pytest.raises(DWPError) as e:        # no solution yet
+        s.v_eps()
+    assert e.value.status == DWP_ESTATE
+    s.solve(_dev(torch, O.rho_gauss(w.n, w.L, w.xyz, w.q, w.sigma)))
+    s.v_eps()
+    with pytest.raises(DWPError) as e:        # eps does not come from these atoms
+        s.forces(w.xyz, w.q, w.sigma, np.full(len(w.q), 1.5), dict(eps_inf=W.EPS_INF, delta=W.DELTA))
+    assert e.value.status == DWP_ESTATE
+    s.set_epsilon(s.get_epsilon())          # a caller-supplied eps has no V_eps
+    s.solve(_dev(torch, O.rho_gauss(w.n, w.L, w.xyz, w.q, w.sigma)))
+    with pytest.raises(DWPError) as e:
+        s.v_eps()
+    assert e.value.status == DWP_ESTATE
+    s.close()

@@ -3,7 +3,8 @@
 The oracle's results for these sizes take minutes to hours of CPU time, so
 they are stored under tests/golden/ (written by tests/golden/make_golden.py,
 which calls only the oracle): the energy in both forms, phi and dE/d eps at 64
-seeded nodes, and dE/dR of every atom.
+seeded nodes (V_eps too for a density-built permittivity), and dE/dR of every
+atom.
 """
 import json
 import os
@@ -26,6 +27,7 @@ CASES = {
     "slab_192x192x384_excl": (lambda: W.slab((192, 192, 384), exclusion=True, tol=1e-8, precision=1),
                               1e-8, 1e-6, 1e-5),
     "big_slab_256x256x512": (lambda: W.big_slab(), 1e-8, 1e-6, 1e-5),
+    "density_slab_192x192x384": (lambda: W.density_slab((192, 192, 384)), 1e-8, 1e-6, 1e-5),
 }
 
 
@@ -44,6 +46,9 @@ def test_full_size_matches_stored_oracle(name):
     s.set_grid(w.n, w.L, **w.solver_opts())
     if w.eps_kind == "tanh_z":
         s.set_epsilon(torch.from_numpy(w.eps_grid()).cuda())
+    elif w.eps_kind == "density":
+        p = w.eps_params
+        s.build_epsilon_density(torch.from_numpy(W.electron_density(w)).cuda(), p["eps_inf"], p["rho0"], p["beta"])
     else:
         s.build_epsilon(w.xyz, w.radius, w.eps_params)
     rho = s.build_rho(w.xyz, w.q, w.sigma)
@@ -57,8 +62,13 @@ def test_full_size_matches_stored_oracle(name):
     g = s.eps_gradient().reshape(-1)[torch.from_numpy(nodes).cuda()].cpu().numpy()
     ref_g = np.array(ref["g"])
     assert np.abs(g - ref_g).max() <= 10 * tol_phi * np.abs(ref_g).max()
+    if "v_eps" in ref:
+        v = s.v_eps().reshape(-1)[torch.from_numpy(nodes).cuda()].cpu().numpy()
+        ref_v = np.array(ref["v_eps"])
+        assert np.abs(v - ref_v).max() <= 10 * tol_phi * np.abs(ref_v).max()
     if tol_F is not None and "forces" in ref:
-        F = s.forces(w.xyz, w.q, w.sigma, w.radius, w.eps_params)
+        density = w.eps_kind == "density"
+        F = s.forces(w.xyz, w.q, w.sigma, None if density else w.radius, None if density else w.eps_params)
         F_ref = np.array(ref["forces"])
         assert np.abs(F - F_ref).max() <= tol_F * np.abs(F_ref).max()
     s.close()
