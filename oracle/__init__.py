@@ -20,7 +20,10 @@ What it computes (paper, Sec. II.B-II.F and Appendix B):
     slab with the vacuum potential as boundary data, Sec. II.F) as a
     diagnostic;
   * the density-dependent permittivity (Eq. 7), its derivative (Eq. 8) and the
-    potential term V_eps (Eq. 6) of Sec. II.B.
+    potential term V_eps (Eq. 6) of Sec. II.B;
+  * the paper's atom-defined permittivity: dummy density (Eq. 9), Eq. 10, the
+    solvent exclusion of Eq. 19, and its force term (Eqs. 11-12, with the sign
+    that differentiating Eqs. 9-10 gives).
 
 Every pin of these functions lives in the CPU test-suite.  Parity unpinned:
 none of the functions above (the one-pass split is pinned only by its epsilon
@@ -31,8 +34,10 @@ from .poisson import (apply_A, vacuum_symbol, vacuum_solve, solve, energy,
 from .atoms import eps_erf, rho_gauss, forces, deps_dR_dense, drho_dR_dense
 from .split import one_pass_split
 from .density import eps_of_density, deps_drho, v_eps
+from .gamma import gamma_density, eps_gamma, deps_gamma_dR_dense, forces_gamma
 
 __all__ = ["apply_A", "vacuum_symbol", "vacuum_solve", "solve", "energy",
            "energy_eps_form", "eps_gradient", "residual_norm", "eps_erf",
            "rho_gauss", "forces", "deps_dR_dense", "drho_dR_dense", "one_pass_split",
-           "eps_of_density", "deps_drho", "v_eps"]
+           "eps_of_density", "deps_drho", "v_eps", "gamma_density", "eps_gamma",
+           "deps_gamma_dR_dense", "forces_gamma"]

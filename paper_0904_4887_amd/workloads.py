@@ -40,8 +40,9 @@ class Workload:
     q: np.ndarray         # (natoms,) charges
     sigma: np.ndarray     # (natoms,) Gaussian standard deviations
     radius: np.ndarray    # (natoms,) switch radii (unused when eps is given)
-    eps_kind: str         # "tanh_z" (eps handed over as a grid), "erf" or "density"
-    eps_params: dict      # eps_inf, delta, exclusion (0/1), z_lim, delta_z (density: eps_inf, rho0, beta)
+    eps_kind: str         # "tanh_z" (eps handed over as a grid), "erf", "gamma" or "density"
+    eps_params: dict      # eps_inf, delta, exclusion (0/1), z_lim, delta_z (gamma: + model 1, beta,
+                          # decay; density: eps_inf, rho0, beta)
     z_wet: tuple          # (z_wet_lo, z_wet_hi) Angstrom
     tol: float            # relative residual tolerance of the solve
     precision: int = 0    # 0 = FP64, 1 = mixed FP32-in-FP64
@@ -169,6 +170,40 @@ def big_slab(n=(256, 256, 512), exclusion=False, tol=1e-8, precision=1, seed=5):
     nm = f"big_slab_{n[0]}x{n[1]}x{n[2]}" + ("_excl" if exclusion else "")
     return _slab_workload(nm, tuple(n), (23.6, 23.6, 60.0), 4, 2.8, seed, 21.0, tol,
                           precision, exclusion)
+
+
+BOHR = 0.529177210544   # Angstrom: the length unit of the exponent of Eq. 9
+BETA_GAMMA = 2.4         # exponent of Eq. 10 used with the paper's solvation tests
+
+
+def slab_gamma(n=(192, 192, 384), exclusion=False, tol=1e-8, precision=1, z_wet=None):
+    """The slab workload with the paper's own atom-defined dielectric.
+
+    Same cell, atoms and charges as slab(); eps_kind "gamma": the dummy density
+    of Eq. 9 (van der Waals radii 2.0 A for Ti and 1.6 A for O, exponent in
+    bohr) in Eq. 10 with beta = 2.4; with exclusion, Eq. 19 for the atoms of
+    every layer up to the second from the top (z_lim half way between the two
+    top layers).  Without exclusion the solvent fills the voids of the slab
+    and wraps under it; the dry region is z in [4.0, 13.0] A (W wraps from 13 A
+    through z = 0).  With exclusion eps is close to 1 below the top buried layer
+    and W starts 0.5 A below that layer's lowest atom.
+    """
+    nm = f"slab_gamma_{n[0]}x{n[1]}x{n[2]}" + ("_excl" if exclusion else "")
+    w = slab(n, exclusion=exclusion, tol=tol, precision=precision, seed=1, name=nm)
+    p = dict(eps_inf=EPS_INF, model=1, beta=BETA_GAMMA, decay=BOHR, exclusion=int(exclusion),
+             z_lim=w.eps_params["z_lim"], delta=DELTA, delta_z=DELTA)
+    w.eps_kind = "gamma"
+    w.eps_params = p
+    if z_wet is not None:
+        w.z_wet = tuple(z_wet)
+    elif exclusion:
+        top_buried = w.xyz[w.buried, 2]
+        z4 = top_buried[top_buried > top_buried.max() - 0.7]
+        w.z_wet = (float(z4.min()) - 0.5, w.L[2] + 2.0 * w.L[2] / n[2])
+    else:
+        w.z_wet = (13.0, w.L[2] + 4.0)
+    w.opts = dict(pre=1, post=1, coarse_sweeps=4)
+    return w
 
 
 RHO0 = 0.0027            # density threshold of Eq. 7, e/A^3 (4e-4 e/bohr^3)
