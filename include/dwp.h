@@ -106,7 +106,9 @@ typedef struct {
     double t_total_ms;       /* wall time of the solve                         */
 } dwp_info;
 
-/* Permittivity built from the atoms (dwp_build_epsilon):
+/* Permittivity built from the atoms (dwp_build_epsilon), two models.
+ *
+ * model 0 (product of switches):
  *   eps_n = 1 + (eps_inf - 1) * prod_i s_i(d_in) * H(z_n),
  *   s_i(d) = 1/2 [1 + erf((d - r_i) / delta)], d_in the minimum-image distance,
  * a product of smooth switches that plays the role of the paper's
@@ -116,13 +118,32 @@ typedef struct {
  *   h_i(z) = 1/2 [1 + erf((z - z_i) / delta_z)],  H(z) = prod_buried h_i(z),
  * with z the node height in [0, Lz): the smooth counterpart of Eq. 19, which
  * drives eps to 1 underneath the buried atoms so that the region below the
- * exposed face is really dry (Sec. II.F).  exclusion = 0 gives H = 1. */
+ * exposed face is really dry (Sec. II.F).  exclusion = 0 gives H = 1.
+ *
+ * model 1 (the paper's own form, Sec. II.D): the dummy density of Eq. 9 fed
+ * into Eq. 10,
+ *   gamma_n = sum_i exp(-s_in (d_in - R_i) / a),
+ *   eps_n = 1 + (eps_inf - 1) / (1 + gamma_n^(2 beta)),
+ * with R_i = radius_host[i] the van der Waals radius, a = decay the length
+ * unit of the exponent (1 bohr = 0.529177 Angstrom in the paper's atomic
+ * units), d_in the minimum-image distance (one term per atom) and s_in = 1,
+ * except that with exclusion = 1 a buried atom (z_i <= z_lim) has
+ * s_in = -1 at the nodes below it (z_n < z_i, heights in [0, Lz)): the solvent
+ * exclusion of Eq. 19, which saturates eps to 1 under the buried atoms.  Its
+ * force term is the derivative of this eps (the sign of the printed Eq. 12 is
+ * reversed); where a buried atom's z crosses a grid plane eps jumps, and the
+ * force is the derivative of the smooth pieces.  delta and delta_z are not
+ * used.  Needs 0.5 < beta <= 100, decay > 0, at most 4096 atoms, and the
+ * half-diagonal of the cell below 600 decay lengths (no overflow). */
 typedef struct {
     double eps_inf;  /* bulk solvent permittivity (> 1)            */
-    double delta;    /* switch width (Angstrom, > 0)               */
+    double delta;    /* switch width (Angstrom, > 0; model 0)      */
     int exclusion;   /* 0 or 1                                     */
     double z_lim;    /* buried atoms: z_i <= z_lim                 */
-    double delta_z;  /* width of the height factor (Angstrom, > 0) */
+    double delta_z;  /* width of the height factor (Angstrom, > 0; model 0) */
+    int model;       /* 0: product of switches; 1: Eqs. 9, 10, 19  */
+    double beta;     /* exponent of Eq. 10 (model 1)               */
+    double decay;    /* length unit of Eq. 9 (Angstrom; model 1)   */
 } dwp_eps_params;
 
 /* Defaults: FP64, W = [0.35 Lz, Lz), V(2,2), 64 coarse sweeps, 1 cycle,

@@ -48,7 +48,7 @@ class Info(C.Structure):
 
 class EpsParams(C.Structure):
     _fields_ = [("eps_inf", C.c_double), ("delta", C.c_double), ("exclusion", C.c_int), ("z_lim", C.c_double),
-                ("delta_z", C.c_double)]
+                ("delta_z", C.c_double), ("model", C.c_int), ("beta", C.c_double), ("decay", C.c_double)]
 
 
 _P = C.c_void_p
@@ -315,8 +315,11 @@ class Solver:
 def eps_params(p):
     if isinstance(p, EpsParams):
         return p
-    return EpsParams(float(p["eps_inf"]), float(p["delta"]), int(p.get("exclusion", 0)),
-                     float(p.get("z_lim", 0.0)), float(p.get("delta_z", p["delta"])))
+    model = int(p.get("model", 0))
+    delta = float(p.get("delta", 0.0 if model else p["delta"]))
+    return EpsParams(float(p["eps_inf"]), delta, int(p.get("exclusion", 0)),
+                     float(p.get("z_lim", 0.0)), float(p.get("delta_z", delta)), model,
+                     float(p.get("beta", 0.0)), float(p.get("decay", 0.0)))
 
 
 def header_symbols(path=None):

@@ -252,7 +252,12 @@ void launch_energy(hipStream_t s, const Plan &p, const double *rho, const double
 struct AtomParams {
     double eps_inf, delta, delta_z, z_lim;
     int exclusion;
+    int model;                    // 0: product of switches; 1: dummy density (Eqs. 9, 10, 19)
+    double beta, decay;           // model 1
 };
+constexpr int GAMMA_MAX_ATOMS = 4096;
+// S: N doubles (model 0: the switch product) or 2N (model 1: log gamma, then
+// d eps / d log gamma)
 void launch_build_eps(hipStream_t s, const Plan &p, int n, const double *atoms_dev,
                       const AtomParams &ap, double *Hz, double *eps, double *S);
 void launch_build_rho(hipStream_t s, const Plan &p, int n, const double *atoms_dev,
@@ -260,6 +265,6 @@ void launch_build_rho(hipStream_t s, const Plan &p, int n, const double *atoms_d
 void launch_forces(hipStream_t s, const Plan &p, int n, const double *atoms_dev,
                    const AtomParams *ap, const double *phi, const double *g, const double *S,
                    const double *Hz, double *fpart, double *out);
-size_t forces_partial_len(const Plan &p, int n);
+size_t forces_partial_len(const Plan &p, int n, int model);
 
 }  // namespace dwp

@@ -1,5 +1,7 @@
 // Atom-dependent kernels: the permittivity built from the atoms, the Gaussian
-// charge density, and the atomic forces dE/dR (paper Eq. 11, App. B).
+// charge density, and the atomic forces dE/dR (paper Eq. 11, App. B).  Two
+// permittivity models: the product of switches described next, and the
+// paper's dummy density (Eqs. 9, 10, 19) further down.
 //
 // Permittivity: eps_n = 1 + (eps_inf - 1) prod_i s_i(d_in) H(z_n) with
 // s_i(d) = 1/2 [1 + erf((d - r_i)/delta)] (exactly 0 below r_i - 6 delta and 1
@@ -155,6 +157,161 @@ __global__ void k_height(const double *__restrict__ atoms, int natoms, int nz, d
         if (t < 6.0) H *= 0.5 * (1.0 + erf(t));
     }
     Hz[k] = H;
+}
+
+// ------------------------------------------------------ dummy-density model
+// gamma_n = sum_a exp(t_an), t_an = -s_an (d_an - R_a) / decay (Eq. 9), with
+// s_an = -1 for a buried atom a above the node (Eq. 19), else +1; then
+// eps = 1 + (eps_inf - 1) q, q = 1 / (1 + gamma^(2 beta)) (Eq. 10), and the
+// force kernel's inputs log gamma and K = d eps / d log gamma = -(eps_inf - 1)
+// 2 beta q (1 - q).  Every atom contributes at every node (minimum image, no
+// cut-off); the cell size check on the host keeps |t| < 600, so gamma neither
+// overflows nor underflows.
+__device__ __forceinline__ double gamma_exponent(double d, double R, double sgn, double inv_decay) {
+    return -sgn * (d - R) * inv_decay;
+}
+
+__global__ void __launch_bounds__(AT_THREADS)
+k_build_gamma(const double *__restrict__ atoms, int natoms, Box b, double eps_inf, double two_beta,
+              double inv_decay, double *__restrict__ eps, double *__restrict__ S) {
+    __shared__ double ax[AT_THREADS], ay[AT_THREADS], az[AT_THREADS], ar[AT_THREADS], ab[AT_THREADS];
+    const int tx = threadIdx.x % TX, ty = (threadIdx.x / TX) % TY, tz = threadIdx.x / (TX * TY);
+    const int i = blockIdx.x * TX + tx, j = blockIdx.y * TY + ty, k = blockIdx.z * TZ + tz;
+    const bool live = i < b.nx && j < b.ny && k < b.nz;
+    const double x = i * b.hx, y = j * b.hy, z = k * b.hz;
+    double acc = 0.0;
+    for (int base = 0; base < natoms; base += AT_THREADS) {
+        const int a = base + threadIdx.x;
+        if (a < natoms) {
+            const double *r = atoms + (size_t)a * AREC;
+            ax[threadIdx.x] = r[0]; ay[threadIdx.x] = r[1]; az[threadIdx.x] = r[2];
+            ar[threadIdx.x] = r[3]; ab[threadIdx.x] = r[6];
+        }
+        __syncthreads();
+        const int m = min(AT_THREADS, natoms - base);
+        if (live) {
+            for (int q = 0; q < m; ++q) {
+                const double dx = min_image(x - ax[q], b.Lx, b.iLx);
+                const double dy = min_image(y - ay[q], b.Ly, b.iLy);
+                const double dz = min_image(z - az[q], b.Lz, b.iLz);
+                const double d = sqrt(dx * dx + dy * dy + dz * dz);
+                const double sgn = (ab[q] != 0.0 && z < az[q]) ? -1.0 : 1.0;
+                acc += exp(gamma_exponent(d, ar[q], sgn, inv_decay));
+            }
+        }
+        __syncthreads();
+    }
+    if (!live) return;
+    const size_t c = ((size_t)k * b.ny + j) * b.nx + i;
+    const size_t N = (size_t)b.nx * b.ny * b.nz;
+    const double lg = log(acc);
+    const double q = 1.0 / (1.0 + exp(two_beta * lg));   // exp overflows to inf: q = 0, eps = 1
+    eps[c] = 1.0 + (eps_inf - 1.0) * q;
+    S[c] = lg;
+    S[N + c] = -(eps_inf - 1.0) * two_beta * q * (1.0 - q);
+}
+
+// Permittivity term of dE/dR for the dummy-density model:
+//   dE/dR_a = sum_n g_n K_n exp(t_an - log gamma_n) s_an (r_n - R_a) / (decay d_an).
+// Atoms are taken GA at a time with their sums in registers; each block walks
+// its share of the nodes (one node per thread per step, grid-stride), so the
+// node data (g, K, log gamma) is read once per group of GA atoms.  At the end
+// of a group the block reduces its GA x 3 sums (waves, then the four waves in a
+// fixed order) and writes them as its partial.  Nodes with g K = 0 add nothing.
+constexpr int GA = 8;
+constexpr int GAMMA_FORCE_BLOCKS = 2048;
+
+__global__ void __launch_bounds__(AT_THREADS)
+k_forces_gamma(const double *__restrict__ atoms, int natoms, Box b, double inv_decay,
+               const double *__restrict__ g, const double *__restrict__ S, double *__restrict__ gpart) {
+    __shared__ double red[AT_THREADS / 64][GA * 3];
+    const size_t N = (size_t)b.nx * b.ny * b.nz;
+    const size_t plane = (size_t)b.nx * b.ny;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int g0 = 0; g0 < natoms; g0 += GA) {
+        double px[GA], py[GA], pz[GA], pr[GA], pb[GA];
+#pragma unroll
+        for (int q = 0; q < GA; ++q) {
+            const int a = min(g0 + q, natoms - 1);
+            const double *r = atoms + (size_t)a * AREC;
+            px[q] = r[0]; py[q] = r[1]; pz[q] = r[2]; pr[q] = r[3]; pb[q] = r[6];
+        }
+        double f[GA][3];
+#pragma unroll
+        for (int q = 0; q < GA; ++q) f[q][0] = f[q][1] = f[q][2] = 0.0;
+        // node index c and its (i, j, k), advanced by the grid stride without divisions
+        const size_t stride = (size_t)gridDim.x * AT_THREADS;
+        const size_t sk = stride / plane, sr = stride - sk * plane;
+        const int sj = (int)(sr / b.nx), si = (int)(sr - (size_t)sj * b.nx);
+        size_t c = (size_t)blockIdx.x * AT_THREADS + threadIdx.x;
+        size_t k = c / plane;
+        int j = (int)((c - k * plane) / b.nx), i = (int)(c - k * plane - (size_t)j * b.nx);
+        for (; c < N; c += stride) {
+            const double w = g[c] * S[N + c] * inv_decay;
+            const double lg = S[c];
+            const double x = i * b.hx, y = j * b.hy, z = k * b.hz;
+            i += si; j += sj; k += sk;
+            if (i >= b.nx) { i -= b.nx; ++j; }
+            if (j >= b.ny) { j -= b.ny; ++k; }
+            if (w == 0.0) continue;
+#pragma unroll
+            for (int q = 0; q < GA; ++q) {
+                const double dx = min_image(x - px[q], b.Lx, b.iLx);
+                const double dy = min_image(y - py[q], b.Ly, b.iLy);
+                const double dz = min_image(z - pz[q], b.Lz, b.iLz);
+                const double d = sqrt(dx * dx + dy * dy + dz * dz);
+                const double sgn = (pb[q] != 0.0 && z < pz[q]) ? -1.0 : 1.0;
+                const double e = w * exp(gamma_exponent(d, pr[q], sgn, inv_decay) - lg) * sgn;
+                const double v = d > 0.0 ? e / d : 0.0;
+                f[q][0] += v * dx; f[q][1] += v * dy; f[q][2] += v * dz;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < GA; ++q)
+#pragma unroll
+            for (int comp = 0; comp < 3; ++comp) {
+                double v = f[q][comp];
+                for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+                if (lane == 0) red[wid][q * 3 + comp] = v;
+            }
+        __syncthreads();
+        if ((int)threadIdx.x < GA * 3) {
+            const int q = threadIdx.x / 3;
+            if (g0 + q < natoms) {
+                double v = 0.0;
+                for (int w2 = 0; w2 < AT_THREADS / 64; ++w2) v += red[w2][threadIdx.x];
+                gpart[((size_t)blockIdx.x * natoms + g0) * 3 + threadIdx.x] = v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// out[a][c] = charge term (sum over its chunks) + permittivity term (sum over
+// the node blocks); one block per (atom, component), fixed-order reductions.
+__global__ void __launch_bounds__(AT_THREADS)
+k_forces_gamma_final(const double *__restrict__ fpart, int natoms, int nchunk,
+                     const double *__restrict__ gpart, int nblocks, double *__restrict__ out) {
+    __shared__ double red[AT_THREADS / 64];
+    const int t = blockIdx.x;
+    const int a = t / 3, c = t % 3;
+    double e = 0.0;
+    for (int q = threadIdx.x; q < nblocks; q += AT_THREADS) e += gpart[((size_t)q * natoms + a) * 3 + c];
+    for (int o = 32; o > 0; o >>= 1) e += __shfl_down(e, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int q = 0; q < nchunk; ++q) s += fpart[((size_t)a * nchunk + q) * 3 + c];
+        double v = 0.0;
+        for (int w = 0; w < AT_THREADS / 64; ++w) v += red[w];
+        out[t] = s + v;
+    }
+}
+
+int gamma_force_blocks(const Plan &p) {
+    const size_t tiles = (p.N + AT_THREADS - 1) / AT_THREADS;
+    return (int)std::min<size_t>(tiles, GAMMA_FORCE_BLOCKS);
 }
 
 // ---------------------------------------------------------------- forces
@@ -324,6 +481,12 @@ int chunks_for(int natoms) {
 void launch_build_eps(hipStream_t s, const Plan &p, int n, const double *atoms_dev, const AtomParams &ap,
                       double *Hz, double *eps, double *S) {
     Box b = make_box(p);
+    if (ap.model == 1) {
+        dim3 g((p.nx + TX - 1) / TX, (p.ny + TY - 1) / TY, (p.nz + TZ - 1) / TZ);
+        k_build_gamma<<<g, AT_THREADS, 0, s>>>(atoms_dev, n, b, ap.eps_inf, 2.0 * ap.beta, 1.0 / ap.decay, eps, S);
+        DWP_LAUNCH_CHECK();
+        return;
+    }
     if (ap.exclusion) {
         k_height<<<(p.nz + 127) / 128, 128, 0, s>>>(atoms_dev, n, p.nz, p.h[2], ap.delta_z, Hz);
         DWP_LAUNCH_CHECK();
@@ -341,8 +504,9 @@ void launch_build_rho(hipStream_t s, const Plan &p, int n, const double *atoms_d
     DWP_LAUNCH_CHECK();
 }
 
-size_t forces_partial_len(const Plan &p, int n) {
-    return (size_t)n * chunks_for(n) * 3 + (size_t)p.nz + (size_t)n + 64;
+size_t forces_partial_len(const Plan &p, int n, int model) {
+    const size_t gamma = model == 1 ? (size_t)gamma_force_blocks(p) * n * 3 : 0;
+    return (size_t)n * chunks_for(n) * 3 + (size_t)p.nz + (size_t)n + 64 + gamma;
 }
 
 // fpart: forces_partial_len doubles; out: 3n doubles (device)
@@ -351,6 +515,18 @@ void launch_forces(hipStream_t s, const Plan &p, int n, const double *atoms_dev,
                    double *out) {
     Box b = make_box(p);
     const int nch = chunks_for(n);
+    if (ap && ap->model == 1) {
+        // charge term by the atom-centred kernel, permittivity term by node blocks
+        k_forces<<<n * nch, AT_THREADS, 0, s>>>(atoms_dev, b, 0, 1.0, 1.0, phi, nullptr, nullptr, nullptr, nch, fpart);
+        DWP_LAUNCH_CHECK();
+        const int nb = gamma_force_blocks(p);
+        double *gpart = fpart + (size_t)n * nch * 3 + (size_t)p.nz + (size_t)n + 64;
+        k_forces_gamma<<<nb, AT_THREADS, 0, s>>>(atoms_dev, n, b, 1.0 / ap->decay, g, S, gpart);
+        DWP_LAUNCH_CHECK();
+        k_forces_gamma_final<<<3 * n, AT_THREADS, 0, s>>>(fpart, n, nch, gpart, nb, out);
+        DWP_LAUNCH_CHECK();
+        return;
+    }
     const bool excl = ap && ap->exclusion;
     k_forces<<<n * nch, AT_THREADS, 0, s>>>(atoms_dev, b, ap ? 1 : 0, ap ? ap->eps_inf : 1.0,
                                             ap ? ap->delta : 1.0, phi, g, S, excl ? Hz : nullptr, nch, fpart);

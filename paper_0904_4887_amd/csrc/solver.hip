@@ -496,16 +496,31 @@ AtomParams atom_params(const dwp_eps_params *ep) {
     a.delta_z = ep->delta_z;
     a.z_lim = ep->z_lim;
     a.exclusion = ep->exclusion;
+    a.model = ep->model;
+    a.beta = ep->beta;
+    a.decay = ep->decay;
     return a;
 }
 
-void validate_eps_params(const dwp_eps_params *ep) {
+void validate_eps_params(const dwp_ctx *c, int n, const dwp_eps_params *ep) {
     if (!ep) fail(DWP_EINVAL, "params is NULL");
     if (!(ep->eps_inf > 1.0) || !std::isfinite(ep->eps_inf)) fail(DWP_EINVAL, "eps_inf must be > 1");
-    if (!(ep->delta > 0.0) || !std::isfinite(ep->delta)) fail(DWP_EINVAL, "delta must be > 0");
     if (ep->exclusion != 0 && ep->exclusion != 1) fail(DWP_EINVAL, "exclusion must be 0 or 1");
-    if (ep->exclusion && (!(ep->delta_z > 0.0) || !std::isfinite(ep->z_lim)))
-        fail(DWP_EINVAL, "exclusion needs delta_z > 0 and a finite z_lim");
+    if (ep->model == 0) {
+        if (!(ep->delta > 0.0) || !std::isfinite(ep->delta)) fail(DWP_EINVAL, "delta must be > 0");
+        if (ep->exclusion && (!(ep->delta_z > 0.0) || !std::isfinite(ep->z_lim)))
+            fail(DWP_EINVAL, "exclusion needs delta_z > 0 and a finite z_lim");
+    } else if (ep->model == 1) {
+        if (!(ep->beta > 0.5) || !(ep->beta <= 100.0)) fail(DWP_EINVAL, "beta must lie in (0.5, 100]");
+        if (!(ep->decay > 0.0) || !std::isfinite(ep->decay)) fail(DWP_EINVAL, "decay must be > 0");
+        if (ep->exclusion && !std::isfinite(ep->z_lim)) fail(DWP_EINVAL, "exclusion needs a finite z_lim");
+        if (n > GAMMA_MAX_ATOMS) fail(DWP_EINVAL, "model 1 takes at most 4096 atoms");
+        const Plan &p = c->plan;
+        const double hd = 0.5 * std::sqrt(p.L[0] * p.L[0] + p.L[1] * p.L[1] + p.L[2] * p.L[2]);
+        if (!(hd < 600.0 * ep->decay)) fail(DWP_EINVAL, "the half-diagonal of the cell must be below 600 decay lengths");
+    } else {
+        fail(DWP_EINVAL, "model must be 0 or 1");
+    }
 }
 
 // Packs atoms (x, y, z wrapped into the cell) into the device buffer.
@@ -526,7 +541,7 @@ void upload_atoms(dwp_ctx *c, int n, const double *xyz, const double *radius, co
         }
         if (radius) {
             if (!(radius[a] > 0.0) || !std::isfinite(radius[a])) fail(DWP_EINVAL, "radius must be > 0");
-            if (ep && 2.0 * (radius[a] + 6.0 * ep->delta) >= Lmin)
+            if (ep && ep->model == 0 && 2.0 * (radius[a] + 6.0 * ep->delta) >= Lmin)
                 fail(DWP_EINVAL, "switch cutoff r + 6 delta must be below half the cell");
             rec[8 * a + 3] = radius[a];
         }
@@ -555,7 +570,8 @@ std::vector<double> switch_geometry(const dwp_ctx *c, const dwp_eps_params *ep) 
     g.reserve(5 * n + 5);
     for (size_t a = 0; a < n; ++a)
         for (int d : {0, 1, 2, 3, 6}) g.push_back(c->atom_rec[8 * a + d]);
-    g.insert(g.end(), {ep->eps_inf, ep->delta, (double)ep->exclusion, ep->z_lim, ep->delta_z});
+    g.insert(g.end(), {ep->eps_inf, ep->delta, (double)ep->exclusion, ep->z_lim, ep->delta_z, (double)ep->model,
+                       ep->beta, ep->decay});
     return g;
 }
 
@@ -674,12 +690,12 @@ void build_epsilon_density_impl(dwp_ctx *c, const double *rho_e, double eps_inf,
 
 void build_epsilon_impl(dwp_ctx *c, int n, const double *xyz, const double *radius, const dwp_eps_params *ep) {
     need_grid(c);
-    validate_eps_params(ep);
+    validate_eps_params(c, n, ep);
     if (!radius) fail(DWP_EINVAL, "radius is NULL");
     upload_atoms(c, n, xyz, radius, nullptr, nullptr, ep);
     AtomParams ap = atom_params(ep);
-    c->S.alloc(sizeof(double) * c->plan.N);
-    PROF(c, PG_BUILD, 16.0 * c->plan.N,
+    c->S.alloc(sizeof(double) * c->plan.N * (ep->model == 1 ? 2 : 1));
+    PROF(c, PG_BUILD, (ep->model == 1 ? 24.0 : 16.0) * c->plan.N,
          launch_build_eps(c->stream, c->plan, n, c->atoms.as<double>(), ap, c->Hz.as<double>(), c->eps.as<double>(),
                           c->S.as<double>()));
     c->eps_geometry = switch_geometry(c, ep);
@@ -753,7 +769,7 @@ void forces_impl(dwp_ctx *c, int n, const double *xyz, const double *radius, con
     if (!c->have_solution) fail(DWP_ESTATE, "no solution: call dwp_solve first");
     if (!q || !sigma || !out) fail(DWP_EINVAL, "q, sigma and dEdR must not be NULL");
     if (ep) {
-        validate_eps_params(ep);
+        validate_eps_params(c, n, ep);
         if (!radius) fail(DWP_EINVAL, "radius is NULL");
         if (c->eps_natoms != n) fail(DWP_ESTATE, "eps was not built from these atoms");
         if ((ep->exclusion != 0) != c->eps_exclusion) fail(DWP_ESTATE, "exclusion differs from the eps build");
@@ -766,8 +782,9 @@ void forces_impl(dwp_ctx *c, int n, const double *xyz, const double *radius, con
     AtomParams ap{};
     if (ep) ap = atom_params(ep);
     PROF(c, PG_FORCES, 16.0 * p.N, launch_eps_gradient(c->stream, p, c->phi_last.as<double>(), c->gbuf.as<double>()));
-    c->fpart.alloc(sizeof(double) * (forces_partial_len(p, n) + 3 * (size_t)n));
-    double *outd = c->fpart.as<double>() + forces_partial_len(p, n);
+    const int model = ep ? ep->model : 0;
+    c->fpart.alloc(sizeof(double) * (forces_partial_len(p, n, model) + 3 * (size_t)n));
+    double *outd = c->fpart.as<double>() + forces_partial_len(p, n, model);
     PROF(c, PG_FORCES, 16.0 * p.N,
          launch_forces(c->stream, p, n, c->atoms.as<double>(), ep ? &ap : nullptr, c->phi_last.as<double>(),
                        c->gbuf.as<double>(), c->S.as<double>(), c->Hz.as<double>(), c->fpart.as<double>(), outd));

@@ -31,6 +31,8 @@ def workloads():
         "slab_192x192x384_excl": W.slab((192, 192, 384), exclusion=True, tol=1e-8, precision=1),
         "big_slab_256x256x512": W.big_slab(),
         "density_slab_192x192x384": W.density_slab((192, 192, 384)),
+        "slab_gamma_192x192x384": W.slab_gamma((192, 192, 384)),
+        "slab_gamma_192x192x384_excl": W.slab_gamma((192, 192, 384), exclusion=True),
     }
 
 
@@ -47,6 +49,9 @@ def make(name, w):
     if w.eps_kind == "tanh_z":
         eps = w.eps_grid()
         params = None
+    elif w.eps_kind == "gamma":
+        eps = O.eps_gamma(w.n, w.L, w.xyz, w.radius, w.eps_params)
+        params = w.eps_params
     elif w.eps_kind == "density":
         p = w.eps_params
         rho_e = W.electron_density(w)
@@ -78,7 +83,10 @@ def make(name, w):
         out["forces"] = F.tolist()
     if params is not None:
         t3 = time.time()
-        F = O.forces(w.n, w.L, w.xyz, w.radius, w.q, w.sigma, params, phi, O.eps_gradient(phi, w.h))
+        if w.eps_kind == "gamma":
+            F = O.forces_gamma(w.n, w.L, w.xyz, w.radius, w.q, w.sigma, params, phi, O.eps_gradient(phi, w.h))
+        else:
+            F = O.forces(w.n, w.L, w.xyz, w.radius, w.q, w.sigma, params, phi, O.eps_gradient(phi, w.h))
         out["forces"] = F.tolist()
         out["t_forces_s"] = time.time() - t3
     with open(os.path.join(HERE, f"oracle_{name}.json"), "w") as f:

@@ -28,6 +28,8 @@ CASES = {
                               1e-8, 1e-6, 1e-5),
     "big_slab_256x256x512": (lambda: W.big_slab(), 1e-8, 1e-6, 1e-5),
     "density_slab_192x192x384": (lambda: W.density_slab((192, 192, 384)), 1e-8, 1e-6, 1e-5),
+    "slab_gamma_192x192x384": (lambda: W.slab_gamma((192, 192, 384)), 1e-8, 1e-6, 1e-5),
+    "slab_gamma_192x192x384_excl": (lambda: W.slab_gamma((192, 192, 384), exclusion=True), 1e-8, 1e-6, 1e-5),
 }
 
 
