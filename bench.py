@@ -189,6 +189,23 @@ def density_steps(torch, n=(192, 192, 384), steps=4, warmup=1, precision="mixed"
             "v_eps_over_phi": round(vmax / pmax, 3)}
 
 
+def gamma_steps(torch, exclusion, n=(192, 192, 384), steps=4, warmup=1, precision="mixed"):
+    """The full step with the paper's own permittivity (Eqs. 9, 10, 19):
+    eps from the dummy density, rho, the solve, the adjoint and the forces;
+    plus the per-group kernel times of one instrumented step."""
+    w = W.slab_gamma(n, exclusion=exclusion)
+    s = solver_for(w, precision, torch)
+    sec, E, infos, _, _ = run_steps(s, w, steps, warmup, torch)
+    s.close()
+    sp = solver_for(w, precision, torch, profile=1)
+    _, _, _, _, prof = run_steps(sp, w, 1, 1, torch)
+    sp.close()
+    return {"ms_per_step": round(1e3 * sec, 2), "steps_per_s": round(1.0 / sec, 3),
+            "iters": [i["outer_iters"] for i in infos], "energy": E, "z_wet": list(w.z_wet),
+            "beta": w.eps_params["beta"], "builders_ms": round(prof.get("builders", {}).get("ms", 0.0), 3),
+            "forces_ms": round(prof.get("forces", {}).get("ms", 0.0), 3)}
+
+
 def copy_ceiling(torch):
     """Measured device copy bandwidth (1 GiB read + 1 GiB written per copy)."""
     x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
@@ -355,6 +372,10 @@ def main():
         print(f"# md: {[p['ms'] for p in per]} ms, iters {[p['iters'] for p in per]}", file=sys.stderr, flush=True)
 
     if not args.no_compare and w.n == (192, 192, 384):
+        for ex in (False, True):
+            key = "gamma_eps_192x192x384" + ("_excl" if ex else "")
+            extra[key] = gamma_steps(torch, ex, precision=args.precision)
+            print(f"# {key}: {extra[key]}", file=sys.stderr, flush=True)
         extra["density_eps_192x192x384"] = density_steps(torch, precision=args.precision)
         print(f"# density eps: {extra['density_eps_192x192x384']}", file=sys.stderr, flush=True)
 
