@@ -23,7 +23,10 @@ What it computes (paper, Sec. II.B-II.F and Appendix B):
     potential term V_eps (Eq. 6) of Sec. II.B;
   * the paper's atom-defined permittivity: dummy density (Eq. 9), Eq. 10, the
     solvent exclusion of Eq. 19, and its force term (Eqs. 11-12, with the sign
-    that differentiating Eqs. 9-10 gives).
+    that differentiating Eqs. 9-10 gives);
+  * the paper's sixth-order non-conservative operator (Eqs. 16-18), its solve
+    (GMRES preconditioned with the second-order solve), the adjoint solve and
+    the energy gradients that need it.
 
 Every pin of these functions lives in the CPU test-suite.  Parity unpinned:
 none of the functions above (the one-pass split is pinned only by its epsilon
@@ -35,9 +38,12 @@ from .atoms import eps_erf, rho_gauss, forces, deps_dR_dense, drho_dR_dense
 from .split import one_pass_split
 from .density import eps_of_density, deps_drho, v_eps
 from .gamma import gamma_density, eps_gamma, deps_gamma_dR_dense, forces_gamma
+from .sixth import (apply_A6, apply_A6T, symbol6, vacuum_solve6, solve6, residual_norm6, adjoint6,
+                    eps_gradient6, charge_potential6)
 
 __all__ = ["apply_A", "vacuum_symbol", "vacuum_solve", "solve", "energy",
            "energy_eps_form", "eps_gradient", "residual_norm", "eps_erf",
            "rho_gauss", "forces", "deps_dR_dense", "drho_dR_dense", "one_pass_split",
            "eps_of_density", "deps_drho", "v_eps", "gamma_density", "eps_gamma",
-           "deps_gamma_dR_dense", "forces_gamma"]
+           "deps_gamma_dR_dense", "forces_gamma", "apply_A6", "apply_A6T", "symbol6", "vacuum_solve6",
+           "solve6", "residual_norm6", "adjoint6", "eps_gradient6", "charge_potential6"]
