@@ -88,6 +88,20 @@ typedef struct {
     int fft_fp32;          /* 1 (mixed precision only): the FFT dry update     */
                            /* runs its spectrum and transforms in float32; the */
                            /* real input and output stay float64.  0: float64  */
+    int order;             /* operator: 2 = the conservative 7-point form      */
+                           /* (default); 6 = the paper's sixth-order           */
+                           /* non-conservative form (Eqs. 16-18):              */
+                           /* A6 phi = sum_d (D1_d eps)(D1_d phi) + eps D2_d phi */
+                           /* with seven-point central D1, D2.  A6 is not      */
+                           /* symmetric and its range misses the constants by  */
+                           /* O(h^6): the solve returns the zero-mean phi with */
+                           /* A6 phi = b - c for a constant c (info.background)*/
+                           /* and the residual is measured after removing its  */
+                           /* mean.  The dry update then uses the symbol of    */
+                           /* Eq. 18 (exact for eps = 1); the wet multigrid    */
+                           /* keeps the 7-point operator (a preconditioner).   */
+                           /* Gradients and forces solve the adjoint problem   */
+                           /* once per solve.  Needs eps resolved by the grid. */
 } dwp_opts;
 
 /* Per-solve report. */
@@ -104,6 +118,7 @@ typedef struct {
     double energy_eps_form;  /* (h^3 / 8 pi) sum_faces eps_f (D_f phi)^2       */
     double mean_rho_removed; /* mean of rho that was projected out            */
     double t_total_ms;       /* wall time of the solve                         */
+    double background;       /* order 6: c = mean(b - A6 phi); order 2: 0      */
 } dwp_info;
 
 /* Permittivity built from the atoms (dwp_build_epsilon), two models.
@@ -219,7 +234,10 @@ int dwp_solve(dwp_ctx *ctx, const double *rho_dev, double *phi_dev, double *ener
               dwp_info *info);
 
 /* dE/d eps_n = -(h^3 / 8 pi) sum_d 1/2 [(D+_d phi)_n^2 + (D-_d phi)_n^2] for
- * the last solution (the discrete first term of Eq. 11).  N doubles. */
+ * the last solution (the discrete first term of Eq. 11).  N doubles.  With
+ * order 6: dE/d eps_n = sum_d D1_d(lambda D1_d phi)_n - lambda_n (sum_d D2_d
+ * phi)_n with lambda the zero-mean solution of Q A6^T lambda = h^3/2 Q rho
+ * (Q removes the mean), solved on the first call after a solve. */
 int dwp_eps_gradient(dwp_ctx *ctx, double *dEdeps_dev);
 
 /* out_n = scale * sum_d 1/2 [(D+_d a)_n (D+_d b)_n + (D-_d a)_n (D-_d b)_n]:

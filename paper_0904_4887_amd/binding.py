@@ -34,13 +34,14 @@ class Opts(C.Structure):
                 ("pre", C.c_int), ("post", C.c_int), ("coarse_sweeps", C.c_int), ("max_levels", C.c_int),
                 ("cycles", C.c_int), ("scaled_dry", C.c_int), ("tol", C.c_double), ("max_outer", C.c_int),
                 ("restart", C.c_int), ("warm_start", C.c_int), ("profile", C.c_int),
-                ("smoother", C.c_int), ("fft_fp32", C.c_int)]
+                ("smoother", C.c_int), ("fft_fp32", C.c_int), ("order", C.c_int)]
 
 
 class Info(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("vcycles", C.c_int), ("restarts", C.c_int), ("k_w0", C.c_int),
                 ("k_w1", C.c_int), ("n_levels", C.c_int), ("rel_res", C.c_double), ("energy", C.c_double),
-                ("energy_eps_form", C.c_double), ("mean_rho_removed", C.c_double), ("t_total_ms", C.c_double)]
+                ("energy_eps_form", C.c_double), ("mean_rho_removed", C.c_double), ("t_total_ms", C.c_double),
+                ("background", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

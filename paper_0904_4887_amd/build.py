@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdwp.so")
-SOURCES = ["kern_grid.hip", "kern_fft.hip", "kern_blas.hip", "kern_atoms.hip", "solver.hip"]
+SOURCES = ["kern_grid.hip", "kern_fft.hip", "kern_blas.hip", "kern_atoms.hip", "kern_sixth.hip", "solver.hip"]
 ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",

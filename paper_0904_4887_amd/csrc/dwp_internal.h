@@ -158,6 +158,13 @@ struct dwp_ctx {
     std::vector<double> atom_rec;      // host copy of the last atom upload
     std::vector<double> eps_geometry;  // switch geometry of the last build_epsilon
     bool eps_density = false;          // eps built from a density grid; S holds d eps / d rho
+    // sixth-order operator
+    dwp::DevBuf G6;               // D1_d eps, 3N
+    dwp::DevBuf lam, adj_rhs;     // adjoint solution and its right-hand side
+    bool have_adjoint = false;
+    bool transposed = false;      // the Krylov solve in progress is the adjoint one
+    int fft_order = 0;            // order the FFT symbol tables were built for
+    double background = 0.0;      // uniform background of the last order-6 solve
 };
 
 namespace dwp {
@@ -223,8 +230,23 @@ void launch_vcycle_bottom(hipStream_t s, const std::vector<Level *> &levels, siz
 constexpr size_t BOTTOM_MAX_POINTS = 8192;     // levels this small (and below) go to the bottom kernel
 constexpr size_t FUSED_MIN_POINTS = 1u << 20;  // levels this large use the fused sweep
 
+// kern_sixth.hip: the sixth-order operator (order = 6)
+void launch_d1eps(hipStream_t s, const Plan &p, const double *eps, double *G);    // G: 3N
+// out = A6 x (or A6^T x), or b - that when residual
+void launch_apply6(hipStream_t s, const Plan &p, const double *x, const double *eps, const double *G,
+                   const double *b, double *out, bool residual, bool trans);
+template <class T>
+void launch_wet_residual6(hipStream_t s, const Plan &p, const double *v, const double *dD, const double *eps,
+                          const double *G, T *fW, bool trans);
+void launch_grad6(hipStream_t s, const Plan &p, const double *phi, const double *lam, double *g);
+void launch_charge_potential(hipStream_t s, const Plan &p, const double *phi, const double *lam, double *psi);
+// out = gr * m / h^3 (+ add)
+void launch_scaled_product(hipStream_t s, const Plan &p, const double *gr, const double *m, const double *add,
+                           double *out);
+
 // kern_fft.hip
-void fft_plan_axis(FFTAxis &ax, int n, double h, bool half);
+// symbol of the operator of the given order (2: 7-point, 6: Eq. 18) along one axis
+void fft_plan_axis(FFTAxis &ax, int n, double h, bool half, int order);
 // out = s .* L^{-1} (s .* r) (s == nullptr: unscaled), zero mean; fp32: the
 // spectrum (cbuf, sized for float64) and the transforms in float32
 void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay,

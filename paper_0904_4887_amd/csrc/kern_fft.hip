@@ -367,7 +367,7 @@ int tile_log2(int n, int budget) {
 // Radix plan, twiddles and the discrete symbol 4 sin^2(pi m / n) / h^2 of one
 // axis (m < n / 2 + 1 when `half`).  Twiddles and symbol are evaluated in long
 // double on the host.
-void fft_plan_axis(FFTAxis &ax, int n, double h, bool half) {
+void fft_plan_axis(FFTAxis &ax, int n, double h, bool half, int order) {
     ax.n = n;
     ax.radices.clear();
     int m = n;
@@ -388,8 +388,16 @@ void fft_plan_axis(FFTAxis &ax, int n, double h, bool half) {
     std::vector<double> lam(nl);
     std::vector<float> lam32(nl);
     for (int k = 0; k < nl; ++k) {
-        const long double s = sinl(pi * (long double)k / (long double)n);
-        lam[k] = (double)(4.0L * s * s / ((long double)h * (long double)h));
+        if (order == 6) {
+            // minus the eigenvalue of the seven-point second derivative (Eq. 18)
+            const long double th = 2.0L * pi * (long double)k / (long double)n;
+            const long double v = -(-49.0L / 18.0L) - 2.0L * (1.5L * cosl(th) - 0.15L * cosl(2.0L * th) +
+                                                                 cosl(3.0L * th) / 90.0L);
+            lam[k] = (double)(v / ((long double)h * (long double)h));
+        } else {
+            const long double s = sinl(pi * (long double)k / (long double)n);
+            lam[k] = (double)(4.0L * s * s / ((long double)h * (long double)h));
+        }
         lam32[k] = (float)lam[k];
     }
     ax.tw.alloc(sizeof(double2) * n);

@@ -238,9 +238,23 @@ void prepare_level_eps(dwp_ctx *c) {
         launch_coarsen_eps<T>(c->stream, *p.levels[l - 1], *p.levels[l]);
 }
 
+// The FFT symbol tables for the operator order of the options.
+void plan_fft(dwp_ctx *c) {
+    const Plan &p = c->plan;
+    const int order = c->opts.order;
+    fft_plan_axis(c->fx, p.nx, p.h[0], true, order);
+    fft_plan_axis(c->fy, p.ny, p.h[1], false, order);
+    fft_plan_axis(c->fz, p.nz, p.h[2], false, order);
+    c->fft_order = order;
+}
+
 void prepare_eps(dwp_ctx *c) {
     ensure_levels(c);
     launch_rsqrt(c->stream, c->eps.as<double>(), c->sinv.as<double>(), c->plan.N);
+    if (c->opts.order == 6) {
+        c->G6.alloc(sizeof(double) * 3 * c->plan.N);
+        launch_d1eps(c->stream, c->plan, c->eps.as<double>(), c->G6.as<double>());
+    }
     if (c->opts.precision == DWP_MIXED) prepare_level_eps<float>(c);
     else prepare_level_eps<double>(c);
 }
@@ -311,7 +325,13 @@ void split_impl(dwp_ctx *c, const double *v, double *z) {
                         &c->prof, c->opts.fft_fp32 != 0);
     Level &F = *p.levels[0];
     const double nW = (double)F.n_interior();
-    PROF(c, PG_WET, (24.0 + sizeof(T)) * nW, launch_wet_residual<T>(s, p, v, z, c->eps.as<double>(), F.f.as<T>()));
+    if (c->opts.order == 6)
+        PROF(c, PG_WET, (16.0 + sizeof(T)) * nW,
+             launch_wet_residual6<T>(s, p, v, z, c->eps.as<double>(), c->G6.as<double>(), F.f.as<T>(),
+                                     c->transposed));
+    else
+        PROF(c, PG_WET, (24.0 + sizeof(T)) * nW,
+             launch_wet_residual<T>(s, p, v, z, c->eps.as<double>(), F.f.as<T>()));
     for (int k = 0; k < c->opts.cycles; ++k) vcycle<T>(c, 0, k == 0);
     PROF(c, PG_WET, (16.0 + sizeof(T)) * nW, launch_wet_add<T>(s, p, F.u.as<T>(), z));
 }
@@ -330,6 +350,26 @@ void check_finite_dev(dwp_ctx *c, const double *x, const char *what) {
     int f = 0;
     for (int b = 0; b < RED_BLOCKS; ++b) f |= hf[b];
     if (f & 1) fail(DWP_ENONFINITE, std::string(what) + " holds NaN or Inf");
+}
+
+// The outer operator on the full box: out = A x (residual: out = b - A x).
+// Order 6: A6 (A6^T in the adjoint solve) followed by the removal of the
+// mean, so the Krylov space stays in the zero-mean vectors where Q A6 is
+// invertible.
+void apply_operator(dwp_ctx *c, const double *x, const double *b, double *out, bool residual) {
+    Plan &p = c->plan;
+    hipStream_t s = c->stream;
+    const size_t N = p.N;
+    if (c->opts.order != 6) {
+        PROF(c, PG_APPLY, (residual ? 32.0 : 24.0) * N,
+             launch_apply_full(s, p, x, c->eps.as<double>(), b, out, residual));
+        return;
+    }
+    double *coef = c->coef.as<double>();
+    PROF(c, PG_APPLY, (residual ? 48.0 : 40.0) * N,
+         launch_apply6(s, p, x, c->eps.as<double>(), c->G6.as<double>(), b, out, residual, c->transposed));
+    PROF(c, PG_VEC, 8.0 * N, launch_sum(s, out, N, c->partial.as<double>(), coef + 410));
+    PROF(c, PG_VEC, 16.0 * N, launch_sub_mean(s, out, coef + 410, 1.0 / (double)N, N));
 }
 
 // FGMRES(m) with the split as right preconditioner; x is updated in place.
@@ -370,7 +410,7 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
     *restarts = 0;
     for (;;) {
         // r = b - A x into V_0, ||r||^2 on the device
-        PROF(c, PG_APPLY, 32.0 * N, launch_apply_full(s, p, x, c->eps.as<double>(), b, V, true));
+        apply_operator(c, x, b, V, true);
         PROF(c, PG_VEC, 8.0 * N, launch_dot(s, V, V, N, part, beta2));
         to_host(c, beta2, 1);
         const double beta = std::sqrt(c->host[0]);
@@ -425,7 +465,13 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
             double *Vj = V + (size_t)j * N, *Vn = V + (size_t)(j + 1) * N, *Zj = Z + (size_t)j * N;
             double *hc = Hd + (size_t)j * HESS_STRIDE;
             apply_split(c, Vj, Zj);
-            PROF(c, PG_APPLY, 24.0 * N, launch_apply_full(s, p, Zj, c->eps.as<double>(), nullptr, Vn, false));
+            if (c->transposed) {
+                // A6^T does not annihilate the constants (A6 does): keep the
+                // iterate in the zero-mean space where the adjoint is posed
+                PROF(c, PG_VEC, 8.0 * N, launch_sum(s, Zj, N, part, coef + 411));
+                PROF(c, PG_VEC, 16.0 * N, launch_sub_mean(s, Zj, coef + 411, 1.0 / (double)N, N));
+            }
+            apply_operator(c, Zj, nullptr, Vn, false);
             const double md = 8.0 * N * (j + 2), ax = 8.0 * N * (j + 3);
             PROF(c, PG_MULTIDOT, md, launch_multidot(s, V, N, j + 1, Vn, N, part, hc, hc + 64));
             fused[j] = orth_update_supported(V, N, j + 1, N);
@@ -487,6 +533,7 @@ void validate_opts(const dwp_opts &o) {
     if (o.smoother != 0 && o.smoother != 1) fail(DWP_EINVAL, "smoother must be 0 or 1");
     if (o.fft_fp32 != 0 && o.fft_fp32 != 1) fail(DWP_EINVAL, "fft_fp32 must be 0 or 1");
     if (o.fft_fp32 && o.precision != DWP_MIXED) fail(DWP_EINVAL, "fft_fp32 needs the mixed precision mode");
+    if (o.order != 2 && o.order != 6) fail(DWP_EINVAL, "order must be 2 or 6");
 }
 
 AtomParams atom_params(const dwp_eps_params *ep) {
@@ -611,9 +658,7 @@ void set_grid_impl(dwp_ctx *c, int nx, int ny, int nz, double Lx, double Ly, dou
     c->Hz.alloc(d * nz);
     c->partial.alloc(d * (size_t)RED_BLOCKS * 80);
     c->coef.alloc(d * (HESS_OFFSET + HESS_STRIDE * 64));
-    fft_plan_axis(c->fx, nx, p.h[0], true);
-    fft_plan_axis(c->fy, ny, p.h[1], false);
-    fft_plan_axis(c->fz, nz, p.h[2], false);
+    plan_fft(c);
     ensure_levels(c);
     c->have_grid = true;
 }
@@ -637,7 +682,9 @@ void set_opts_impl(dwp_ctx *c, const dwp_opts *o) {
                             (std::isnan(o->z_wet_hi) != std::isnan(old.z_wet_hi));
         if (replan) plan_wet(c);
         ensure_levels(c);
+        if (o->order != c->fft_order) plan_fft(c);
         if (c->have_eps) prepare_eps(c);
+        if (o->order != old.order) c->have_solution = false;
     } catch (...) {
         c->opts = old;
         c->prof.on = old.profile != 0;
@@ -740,11 +787,20 @@ void solve_impl(dwp_ctx *c, const double *rho, double *phi, double *energy, dwp_
     launch_sub_mean(s, phi, coef + 402, 1.0 / (double)N, N);
     launch_energy(s, p, rho, phi, c->eps.as<double>(), part, coef + 403);
     DWP_HIP(hipMemcpyAsync(c->phi_last.p, phi, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    c->background = 0.0;
+    if (c->opts.order == 6) {
+        // c = mean(b - A6 phi) = -mean(A6 phi)
+        launch_apply6(s, p, phi, c->eps.as<double>(), c->G6.as<double>(), nullptr, c->w.as<double>(), false, false);
+        launch_sum(s, c->w.as<double>(), N, part, coef + 405);
+        to_host(c, coef + 405, 1);
+        c->background = -c->host[0] / (double)N;
+    }
     to_host(c, coef + 403, 2);
     const double h3 = p.h[0] * p.h[1] * p.h[2];
     const double E = 0.5 * h3 * c->host[0];
     const double Eeps = h3 / (8.0 * 3.14159265358979323846) * c->host[1];
     c->have_solution = true;
+    c->have_adjoint = false;
     if (energy) *energy = E;
     if (info) {
         info->outer_iters = iters;
@@ -757,10 +813,69 @@ void solve_impl(dwp_ctx *c, const double *rho, double *phi, double *energy, dwp_
         info->energy = E;
         info->energy_eps_form = Eeps;
         info->mean_rho_removed = c->mean_rho;
+        info->background = c->background;
         info->t_total_ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     if (status != DWP_OK) fail(status, "tolerance not reached within max_outer iterations");
+}
+
+// Order 6: the zero-mean lambda with Q A6^T lambda = h^3/2 Q rho, by the same
+// FGMRES with the transposed operator (the right-hand side is -h^3/(8 pi) b).
+void ensure_adjoint(dwp_ctx *c) {
+    if (c->opts.order != 6 || c->have_adjoint) return;
+    Plan &p = c->plan;
+    hipStream_t s = c->stream;
+    const size_t N = p.N;
+    double *coef = c->coef.as<double>();
+    double *part = c->partial.as<double>();
+    c->lam.alloc(sizeof(double) * N);
+    c->adj_rhs.alloc(sizeof(double) * N);
+    const double h3 = p.h[0] * p.h[1] * p.h[2];
+    // adj_rhs = scale * b with scale = -h^3 / (8 pi): a multi-axpy with one vector
+    c->host[0] = -h3 / (8.0 * 3.14159265358979323846);
+    DWP_HIP(hipMemcpyAsync(coef + 406, c->host, sizeof(double), hipMemcpyHostToDevice, s));
+    launch_fill(s, c->adj_rhs.as<double>(), 0.0, N);
+    launch_axpy_multi(s, c->adj_rhs.as<double>(), c->b.as<double>(), N, 1, coef + 406, N, 1.0, part, nullptr);
+    launch_dot(s, c->adj_rhs.as<double>(), c->adj_rhs.as<double>(), N, part, coef + 407);
+    to_host(c, coef + 407, 1);
+    const double fnorm = std::sqrt(c->host[0]);
+    launch_fill(s, c->lam.as<double>(), 0.0, N);
+    if (fnorm > 0.0) {
+        int restarts = 0;
+        double rel = 0.0;
+        c->transposed = true;
+        try {
+            fgmres(c, c->adj_rhs.as<double>(), fnorm, c->lam.as<double>(), &restarts, &rel);
+        } catch (...) {
+            c->transposed = false;
+            throw;
+        }
+        c->transposed = false;
+        if (rel > c->opts.tol) fail(DWP_ENOCONV, "adjoint solve: tolerance not reached within max_outer iterations");
+        launch_sum(s, c->lam.as<double>(), N, part, coef + 408);
+        launch_sub_mean(s, c->lam.as<double>(), coef + 408, 1.0 / (double)N, N);
+    }
+    c->have_adjoint = true;
+}
+
+// dE/d eps for the last solution, for the operator of the options
+void eps_gradient_impl(dwp_ctx *c, double *g) {
+    if (c->opts.order == 6) {
+        ensure_adjoint(c);
+        PROF(c, PG_FORCES, 24.0 * c->plan.N,
+             launch_grad6(c->stream, c->plan, c->phi_last.as<double>(), c->lam.as<double>(), g));
+    } else {
+        PROF(c, PG_FORCES, 16.0 * c->plan.N, launch_eps_gradient(c->stream, c->plan, c->phi_last.as<double>(), g));
+    }
+}
+
+// The potential whose h^3 multiple is dE/d rho: phi (order 2), phi/2 - 4 pi lambda / h^3 (order 6).
+const double *charge_potential(dwp_ctx *c) {
+    if (c->opts.order != 6) return c->phi_last.as<double>();
+    ensure_adjoint(c);
+    launch_charge_potential(c->stream, c->plan, c->phi_last.as<double>(), c->lam.as<double>(), c->w.as<double>());
+    return c->w.as<double>();
 }
 
 void forces_impl(dwp_ctx *c, int n, const double *xyz, const double *radius, const double *q,
@@ -781,13 +896,14 @@ void forces_impl(dwp_ctx *c, int n, const double *xyz, const double *radius, con
     Plan &p = c->plan;
     AtomParams ap{};
     if (ep) ap = atom_params(ep);
-    PROF(c, PG_FORCES, 16.0 * p.N, launch_eps_gradient(c->stream, p, c->phi_last.as<double>(), c->gbuf.as<double>()));
+    eps_gradient_impl(c, c->gbuf.as<double>());
+    const double *pot = charge_potential(c);
     const int model = ep ? ep->model : 0;
     c->fpart.alloc(sizeof(double) * (forces_partial_len(p, n, model) + 3 * (size_t)n));
     double *outd = c->fpart.as<double>() + forces_partial_len(p, n, model);
     PROF(c, PG_FORCES, 16.0 * p.N,
-         launch_forces(c->stream, p, n, c->atoms.as<double>(), ep ? &ap : nullptr, c->phi_last.as<double>(),
-                       c->gbuf.as<double>(), c->S.as<double>(), c->Hz.as<double>(), c->fpart.as<double>(), outd));
+         launch_forces(c->stream, p, n, c->atoms.as<double>(), ep ? &ap : nullptr, pot, c->gbuf.as<double>(),
+                       c->S.as<double>(), c->Hz.as<double>(), c->fpart.as<double>(), outd));
     DWP_HIP(hipMemcpyAsync(out, outd, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c->stream));
     sync(c);
 }
@@ -837,6 +953,7 @@ void dwp_default_opts(dwp_opts *o) {
     o->profile = 0;
     o->smoother = 1;
     o->fft_fp32 = 0;
+    o->order = 2;
 }
 
 int dwp_create(dwp_ctx **out, int device, void *stream) {
@@ -939,7 +1056,7 @@ int dwp_eps_gradient(dwp_ctx *c, double *g) {
     if (!c->have_solution) dwp::fail(DWP_ESTATE, "no solution: call dwp_solve first");
     if (!g) dwp::fail(DWP_EINVAL, "dEdeps_dev is NULL");
     DWP_HIP(hipSetDevice(c->device));
-    dwp::launch_eps_gradient(c->stream, c->plan, c->phi_last.as<double>(), g);
+    dwp::eps_gradient_impl(c, g);
     ABI_END(c)
 }
 
@@ -958,8 +1075,14 @@ int dwp_v_eps(dwp_ctx *c, int add_phi, double *out) {
     if (add_phi != 0 && add_phi != 1) dwp::fail(DWP_EINVAL, "add_phi must be 0 or 1");
     if (!out) dwp::fail(DWP_EINVAL, "out_dev is NULL");
     DWP_HIP(hipSetDevice(c->device));
-    PROF(c, dwp::PG_FORCES, 24.0 * c->plan.N,
-         dwp::launch_v_eps(c->stream, c->plan, c->phi_last.as<double>(), c->S.as<double>(), add_phi != 0, out));
+    if (c->opts.order == 6) {
+        dwp::eps_gradient_impl(c, c->gbuf.as<double>());
+        const double *pot = add_phi ? dwp::charge_potential(c) : nullptr;
+        dwp::launch_scaled_product(c->stream, c->plan, c->gbuf.as<double>(), c->S.as<double>(), pot, out);
+    } else {
+        PROF(c, dwp::PG_FORCES, 24.0 * c->plan.N,
+             dwp::launch_v_eps(c->stream, c->plan, c->phi_last.as<double>(), c->S.as<double>(), add_phi != 0, out));
+    }
     ABI_END(c)
 }
 
@@ -986,7 +1109,11 @@ int dwp_apply_operator(dwp_ctx *c, const double *phi, double *out) {
     dwp::need_eps(c);
     if (!phi || !out) dwp::fail(DWP_EINVAL, "NULL pointer");
     DWP_HIP(hipSetDevice(c->device));
-    dwp::launch_apply_full(c->stream, c->plan, phi, c->eps.as<double>(), nullptr, out, false);
+    if (c->opts.order == 6)
+        dwp::launch_apply6(c->stream, c->plan, phi, c->eps.as<double>(), c->G6.as<double>(), nullptr, out, false,
+                           false);
+    else
+        dwp::launch_apply_full(c->stream, c->plan, phi, c->eps.as<double>(), nullptr, out, false);
     ABI_END(c)
 }
 

@@ -33,6 +33,7 @@ def workloads():
         "density_slab_192x192x384": W.density_slab((192, 192, 384)),
         "slab_gamma_192x192x384": W.slab_gamma((192, 192, 384)),
         "slab_gamma_192x192x384_excl": W.slab_gamma((192, 192, 384), exclusion=True),
+        "slab6_96x96x192": W.slab((96, 96, 192), tol=1e-10),
     }
 
 
@@ -43,7 +44,32 @@ def first_below(history, tol):
     return None
 
 
+def make_sixth(name, w):
+    """The sixth-order operator (Eqs. 16-18) on an atom-built slab: energy,
+    background constant, phi and dE/d eps (adjoint) at 64 nodes, dE/dR."""
+    from oracle import sixth as S
+    t0 = time.time()
+    eps = O.eps_erf(w.n, w.L, w.xyz, w.radius, w.eps_params)
+    rho = O.rho_gauss(w.n, w.L, w.xyz, w.q, w.sigma)
+    phi, info = S.solve6(rho, eps, w.h, tol=1e-12, return_info=True)
+    t1 = time.time()
+    lam = S.adjoint6(rho, eps, w.h, tol=1e-12)
+    g = S.eps_gradient6(phi, lam, w.h)
+    F = O.forces(w.n, w.L, w.xyz, w.radius, w.q, w.sigma, w.eps_params, S.charge_potential6(phi, lam, w.h), g)
+    rng = np.random.default_rng(12345)
+    nodes = np.sort(rng.choice(w.N, size=64, replace=False))
+    out = dict(name=name, n=list(w.n), L=list(w.L), order=6, energy=O.energy(rho, phi, w.h),
+               background=info["background"], oracle_gmres_iters=info["iters"], oracle_rel_res=info["rel_res"],
+               nodes=nodes.tolist(), phi=phi.ravel()[nodes].tolist(), g=g.ravel()[nodes].tolist(),
+               forces=F.tolist(), t_solve_s=t1 - t0, t_total_s=time.time() - t0)
+    with open(os.path.join(HERE, f"oracle_{name}.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print(name, "E", out["energy"], "gmres", info["iters"], "s", round(time.time() - t0, 1), flush=True)
+
+
 def make(name, w):
+    if name.startswith("slab6_"):
+        return make_sixth(name, w)
     t0 = time.time()
     rho_e = None
     if w.eps_kind == "tanh_z":

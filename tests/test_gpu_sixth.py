@@ -1,0 +1,160 @@
+"""The paper's sixth-order operator on the GPU (opts.order = 6; Sec. II.F,
+Eqs. 16-18), through the C ABI.
+
+* A6 applied by the device against the oracle's, node by node (random eps and
+  phi, ragged grids, axes as short as 8 where the stencil wraps);
+* the vacuum solve with the symbol of Eq. 18 against the oracle's;
+* the solve, its background constant, the energy, dE/d eps (adjoint solve)
+  and dE/dR against the oracle on a small system whose switches the grid
+  resolves, in float64 and in mixed precision;
+* dE/dR against central differences of the device energy on the slab at
+  96 x 96 x 192, and the stored oracle result there.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import sixth as S
+from paper_0904_4887_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _solver(n, L, **opts):
+    from paper_0904_4887_amd.binding import Solver
+    s = Solver(0)
+    s.set_grid(n, L, **dict(dict(order=6), **opts))
+    return s
+
+
+@pytest.mark.parametrize("n", [(8, 8, 8), (24, 18, 36), (64, 8, 48), (18, 72, 16)])
+def test_apply_matches_oracle(torch, n):
+    L = (0.3 * n[0], 0.25 * n[1], 0.2 * n[2])
+    eps, rho = W.random_fields(n, 31, eps_lo=1.0, eps_hi=20.0)
+    phi = np.random.default_rng(2).normal(size=eps.shape)
+    s = _solver(n, L, z_wet_lo=0.2 * L[2], z_wet_hi=0.9 * L[2])
+    s.set_epsilon(_dev(torch, eps))
+    out = s.apply_operator(_dev(torch, phi)).cpu().numpy()
+    h = s.h
+    ref = S.apply_A6(phi, eps, h)
+    assert np.abs(out - ref).max() <= 1e-13 * np.abs(ref).max()
+    s.close()
+
+
+@pytest.mark.parametrize("n", [(24, 36, 48), (16, 8, 96)])
+def test_vacuum_solve_uses_the_sixth_order_symbol(torch, n):
+    L = (6.0, 9.0, 12.0)
+    _, rho = W.random_fields(n, 32)
+    s = _solver(n, L, z_wet_lo=3.0, z_wet_hi=11.0)
+    out = s.vacuum_solve(_dev(torch, rho)).cpu().numpy()
+    ref = S.vacuum_solve6(rho, s.h)
+    assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
+    s.close()
+
+
+def _small_system():
+    # three Gaussian charges, erf switches of width 0.4 A on a 0.25 A grid
+    n, L = (32, 32, 32), (8.0, 8.0, 8.0)
+    xyz = np.array([[2.6, 3.5, 4.0], [5.1, 4.6, 3.7], [4.2, 2.1, 5.6]])
+    R = np.array([1.4, 1.2, 1.3])
+    q = np.array([1.0, -0.6, -0.4])
+    sig = np.array([0.42, 0.4, 0.38])
+    p = dict(eps_inf=W.EPS_INF, delta=0.4, exclusion=0, z_lim=0.0, delta_z=0.4)
+    return n, L, xyz, R, q, sig, p
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_gradient_and_forces_match_oracle(torch, precision):
+    n, L, xyz, R, q, sig, p = _small_system()
+    tol = 1e-11 if precision == 0 else 1e-9
+    s = _solver(n, L, z_wet_lo=1.0, z_wet_hi=7.5, tol=tol, precision=precision, scaled_dry=1)
+    s.build_epsilon(xyz, R, p)
+    rho = s.build_rho(xyz, q, sig)
+    phi, E, info = s.solve(rho)
+    assert info["rel_res"] <= tol
+    h = s.h
+    eps = O.eps_erf(n, L, xyz, R, p)
+    rho_o = O.rho_gauss(n, L, xyz, q, sig)
+    ref, oi = S.solve6(rho_o, eps, h, tol=1e-13, return_info=True)
+    scale = 1e3 * tol
+    assert np.abs(phi.cpu().numpy() - ref).max() <= scale * np.abs(ref).max()
+    assert abs(E - O.energy(rho_o, ref, h)) <= scale * abs(E)
+    b_scale = 4 * math.pi * np.abs(rho_o - rho_o.mean()).max()
+    assert abs(info["background"] - oi["background"]) <= scale * b_scale
+    lam = S.adjoint6(rho_o, eps, h, tol=1e-13)
+    g_ref = S.eps_gradient6(ref, lam, h)
+    g = s.eps_gradient().cpu().numpy()
+    assert np.abs(g - g_ref).max() <= 10 * scale * np.abs(g_ref).max()
+    F = s.forces(xyz, q, sig, R, p)
+    F_ref = O.forces(n, L, xyz, R, q, sig, p, S.charge_potential6(ref, lam, h), g_ref)
+    assert np.abs(F - F_ref).max() <= 10 * scale * np.abs(F_ref).max()
+    s.close()
+
+
+def test_forces_match_central_differences_on_the_slab(torch):
+    w = W.slab((96, 96, 192), tol=1e-12, precision=0)
+    from paper_0904_4887_amd.binding import Solver
+    s = Solver(0)
+    s.set_grid(w.n, w.L, **w.solver_opts(order=6, scaled_dry=1, pre=2, post=2, coarse_sweeps=64))
+    rho, phi = s.empty(), s.empty()
+
+    def energy(xyz):
+        s.build_epsilon(xyz, w.radius, w.eps_params)
+        s.build_rho(xyz, w.q, w.sigma, out=rho)
+        _, E, info = s.solve(rho, phi)
+        assert info["rel_res"] <= 1e-12
+        return E
+
+    energy(w.xyz)
+    F = s.forces(w.xyz, w.q, w.sigma, w.radius, w.eps_params)
+    step = 1e-4
+    errs = []
+    for a in (5, 40, 70):
+        for d in range(3):
+            xp, xm = w.xyz.copy(), w.xyz.copy()
+            xp[a, d] += step
+            xm[a, d] -= step
+            errs.append(abs((energy(xp) - energy(xm)) / (2 * step) - F[a, d]))
+    s.close()
+    assert max(errs) <= 1e-5 * np.abs(F).max(), (max(errs), np.abs(F).max())
+
+
+def test_slab_matches_stored_oracle(torch):
+    path = os.path.join(GOLDEN, "oracle_slab6_96x96x192.json")
+    if not os.path.exists(path):
+        pytest.skip("no stored oracle result for the sixth-order slab")
+    with open(path) as f:
+        ref = json.load(f)
+    w = W.slab((96, 96, 192), tol=1e-10, precision=0)
+    from paper_0904_4887_amd.binding import Solver
+    s = Solver(0)
+    s.set_grid(w.n, w.L, **w.solver_opts(order=6, scaled_dry=1, pre=2, post=2, coarse_sweeps=64))
+    s.build_epsilon(w.xyz, w.radius, w.eps_params)
+    rho = s.build_rho(w.xyz, w.q, w.sigma)
+    phi, E, info = s.solve(rho)
+    assert abs(E - ref["energy"]) <= 1e-9 * abs(ref["energy"])
+    nodes = np.array(ref["nodes"])
+    idx = torch.from_numpy(nodes).cuda()
+    ph = phi.reshape(-1)[idx].cpu().numpy()
+    assert np.abs(ph - np.array(ref["phi"])).max() <= 1e-7 * np.abs(ref["phi"]).max()
+    g = s.eps_gradient().reshape(-1)[idx].cpu().numpy()
+    assert np.abs(g - np.array(ref["g"])).max() <= 1e-6 * np.abs(ref["g"]).max()
+    F = s.forces(w.xyz, w.q, w.sigma, w.radius, w.eps_params)
+    assert np.abs(F - np.array(ref["forces"])).max() <= 1e-6 * np.abs(ref["forces"]).max()
+    assert abs(info["background"] - ref["background"]) <= 1e-8 * abs(ref["background"]) + 1e-12
+    s.close()
