@@ -206,6 +206,20 @@ def gamma_steps(torch, exclusion, n=(192, 192, 384), steps=4, warmup=1, precisio
             "forces_ms": round(prof.get("forces", {}).get("ms", 0.0), 3)}
 
 
+def sixth_order_steps(torch, n=(192, 192, 384), steps=2, warmup=1, precision="mixed"):
+    """The full step with the paper's sixth-order operator (Eqs. 16-18) on the
+    literal slab: eps, rho, the solve, and the forces, which need the adjoint
+    solve of the non-symmetric operator."""
+    w = W.slab(n, tol=1e-8)
+    w.opts = dict(scaled_dry=1, order=6)
+    s = solver_for(w, precision, torch)
+    sec, E, infos, _, _ = run_steps(s, w, steps, warmup, torch)
+    s.close()
+    return {"ms_per_step": round(1e3 * sec, 2), "steps_per_s": round(1.0 / sec, 3),
+            "iters": [i["outer_iters"] for i in infos], "energy": E, "background": infos[-1]["background"],
+            "opts": w.opts}
+
+
 def copy_ceiling(torch):
     """Measured device copy bandwidth (1 GiB read + 1 GiB written per copy)."""
     x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
@@ -378,6 +392,8 @@ def main():
             print(f"# {key}: {extra[key]}", file=sys.stderr, flush=True)
         extra["density_eps_192x192x384"] = density_steps(torch, precision=args.precision)
         print(f"# density eps: {extra['density_eps_192x192x384']}", file=sys.stderr, flush=True)
+        extra["sixth_order_192x192x384"] = sixth_order_steps(torch, precision=args.precision)
+        print(f"# sixth order: {extra['sixth_order_192x192x384']}", file=sys.stderr, flush=True)
 
     if not args.no_compare:
         extra["hbm_resident_smoother_512"] = hbm_resident_smoother(torch)
