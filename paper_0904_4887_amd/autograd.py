@@ -11,7 +11,8 @@ DielectricPoisson: (rho, eps) -> (phi, E) for a solver whose grid is set.
 
 SlabEnergy: atom positions -> E for the atom-built permittivity and Gaussian
   charges; backward = dE/dR from the library's force kernel, the permittivity
-  gradient chained through the switching functions plus the charge term.
+  gradient chained through the switching functions plus the charge term (with
+  the sixth-order operator the library solves the adjoint problem for it).
 
 Every step runs in libdwp; this module only moves tensors and scalars.
 """
@@ -26,6 +27,9 @@ import torch
 class DielectricPoisson(torch.autograd.Function):
     @staticmethod
     def forward(ctx, rho, eps, solver):
+        if solver.opts.order != 2:
+            raise ValueError("DielectricPoisson's backward relies on a symmetric operator: use order = 2 "
+                             "(the sixth-order operator's gradients come from eps_gradient and forces)")
         solver.set_epsilon(eps.detach().contiguous())
         phi, E, info = solver.solve(rho.detach().contiguous())
         ctx.solver = solver
