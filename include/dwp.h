@@ -244,7 +244,8 @@ int dwp_eps_gradient(dwp_ctx *ctx, double *dEdeps_dev);
  * -d(a.A b)/d eps_n times scale (no h^3 factor), for two grids a, b (N
  * doubles each).  With a = b = phi and scale = -h^3/(8 pi) it is
  * dwp_eps_gradient; with a = lambda (an adjoint solution) it gives the
- * permittivity gradient of a loss that depends on phi itself. */
+ * permittivity gradient of a loss that depends on phi itself.  It is the
+ * derivative of the second-order operator (order 2) whatever the options. */
 int dwp_eps_pair_gradient(dwp_ctx *ctx, const double *a_dev, const double *b_dev, double scale,
                           double *out_dev);
 
@@ -259,10 +260,14 @@ int dwp_forces(dwp_ctx *ctx, int n, const double *xyz_host, const double *radius
                const double *q_host, const double *sigma_host, const dwp_eps_params *params,
                double *dEdR_host);
 
-/* Building blocks, exposed for checking and for callers that compose them. */
+/* Building blocks, exposed for checking and for callers that compose them.
+ * dwp_apply_operator applies the operator of the options (order 6: A6, without
+ * the removal of the mean); dwp_vacuum_solve inverts the vacuum operator of
+ * that order (the 7-point or the Eq. 18 symbol). */
 /* out = A phi on the full periodic box with the current eps. */
 int dwp_apply_operator(dwp_ctx *ctx, const double *phi_dev, double *out_dev);
-/* out = zero-mean psi with L psi = r - mean r, L the 7-point vacuum Laplacian,
+/* out = zero-mean psi with L psi = r - mean r, L the vacuum operator (the
+ * 7-point Laplacian, or sum_d D2_d of Eq. 18 with order 6),
  * by the library's 3-D FFT and discrete Green's function (Eq. 15 on the
  * grid), always in float64 (fft_fp32 applies inside the split only). */
 int dwp_vacuum_solve(dwp_ctx *ctx, const double *r_dev, double *out_dev);
