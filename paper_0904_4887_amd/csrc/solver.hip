@@ -326,7 +326,7 @@ void split_impl(dwp_ctx *c, const double *v, double *z) {
     Level &F = *p.levels[0];
     const double nW = (double)F.n_interior();
     if (c->opts.order == 6)
-        PROF(c, PG_WET, (16.0 + sizeof(T)) * nW,
+        PROF(c, PG_WET, (48.0 + sizeof(T)) * nW,
              launch_wet_residual6<T>(s, p, v, z, c->eps.as<double>(), c->G6.as<double>(), F.f.as<T>(),
                                      c->transposed));
     else
@@ -366,7 +366,8 @@ void apply_operator(dwp_ctx *c, const double *x, const double *b, double *out, b
         return;
     }
     double *coef = c->coef.as<double>();
-    PROF(c, PG_APPLY, (residual ? 48.0 : 40.0) * N,
+    // x, eps and the three components of D1 eps read, out written (+ b read)
+    PROF(c, PG_APPLY, (residual ? 56.0 : 48.0) * N,
          launch_apply6(s, p, x, c->eps.as<double>(), c->G6.as<double>(), b, out, residual, c->transposed));
     PROF(c, PG_VEC, 8.0 * N, launch_sum(s, out, N, c->partial.as<double>(), coef + 410));
     PROF(c, PG_VEC, 16.0 * N, launch_sub_mean(s, out, coef + 410, 1.0 / (double)N, N));
