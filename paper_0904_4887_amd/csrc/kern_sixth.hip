@@ -7,10 +7,9 @@
 //   D1 f_i = (1/h) sum_{n=1..3} a_n (f_{i+n} - f_{i-n}),   a = (3/4, -3/20, 1/60),
 //   D2 f_i = (1/h^2) [b_0 f_i + sum_{n=1..3} b_n (f_{i+n} + f_{i-n})],
 //   b = (-49/18, 3/2, -3/20, 1/90).
-// G is computed once per permittivity.  One thread per node, neighbours read
-// through the caches (the 19-point star of x and, for the transpose, of eps
-// and G); every axis is periodic and at least 8 long, so a shift of up to 3
-// wraps at most once.
+// G is computed once per permittivity.  The operators are LDS-tiled (below);
+// the gradient kernel reads its wider stencil through the caches.  Every axis
+// is periodic and at least 8 long, so a shift of up to 3 wraps at most once.
 #include "dwp_internal.h"
 
 namespace dwp {
@@ -70,40 +69,6 @@ __device__ __forceinline__ double d2(const double *f, size_t c, const long long 
                   B3 * (f[c + p[2]] + f[c + m[2]]));
 }
 
-// products f g at offsets, for the transpose
-__device__ __forceinline__ double d1p(const double *f, const double *w, size_t c, const long long *p,
-                                      const long long *m, double ih) {
-    double s = 0.0;
-    const double a[3] = {A1, A2, A3};
-#pragma unroll
-    for (int n = 0; n < 3; ++n) s += a[n] * (f[c + p[n]] * w[c + p[n]] - f[c + m[n]] * w[c + m[n]]);
-    return ih * s;
-}
-
-__device__ __forceinline__ double d2p(const double *f, const double *w, size_t c, const long long *p,
-                                      const long long *m, double ih2) {
-    double s = B0 * f[c] * w[c];
-    const double b[3] = {B1, B2, B3};
-#pragma unroll
-    for (int n = 0; n < 3; ++n) s += b[n] * (f[c + p[n]] * w[c + p[n]] + f[c + m[n]] * w[c + m[n]]);
-    return ih2 * s;
-}
-
-template <bool TRANS>
-__device__ __forceinline__ double op6(const Grid6 &g, const double *__restrict__ x, const double *__restrict__ eps,
-                                      const double *__restrict__ G, size_t c, const Star &s) {
-    const double *Gx = G, *Gy = G + g.N, *Gz = G + 2 * g.N;
-    if (!TRANS) {
-        const double e = eps[c];
-        return Gx[c] * d1(x, c, s.xp, s.xm, g.ihx) + Gy[c] * d1(x, c, s.yp, s.ym, g.ihy) +
-               Gz[c] * d1(x, c, s.zp, s.zm, g.ihz) +
-               e * (d2(x, c, s.xp, s.xm, g.ihx2) + d2(x, c, s.yp, s.ym, g.ihy2) + d2(x, c, s.zp, s.zm, g.ihz2));
-    }
-    return -d1p(Gx, x, c, s.xp, s.xm, g.ihx) - d1p(Gy, x, c, s.yp, s.ym, g.ihy) - d1p(Gz, x, c, s.zp, s.zm, g.ihz) +
-           d2p(eps, x, c, s.xp, s.xm, g.ihx2) + d2p(eps, x, c, s.yp, s.ym, g.ihy2) +
-           d2p(eps, x, c, s.zp, s.zm, g.ihz2);
-}
-
 // G_d = D1_d eps for the three directions
 __global__ void __launch_bounds__(SX *SY) k_d1eps(Grid6 g, const double *__restrict__ eps, double *__restrict__ G) {
     const int i = blockIdx.x * SX + threadIdx.x, j = blockIdx.y * SY + threadIdx.y, k = blockIdx.z;
@@ -115,29 +80,127 @@ __global__ void __launch_bounds__(SX *SY) k_d1eps(Grid6 g, const double *__restr
     G[2 * g.N + c] = d1(eps, c, s.zp, s.zm, g.ihz);
 }
 
-// MODE 0: out = op x;  MODE 1: out = b - op x
-template <int MODE, bool TRANS>
-__global__ void __launch_bounds__(SX *SY)
-k_apply6(Grid6 g, const double *__restrict__ x, const double *__restrict__ eps, const double *__restrict__ G,
-         const double *__restrict__ b, double *__restrict__ out) {
-    const int i = blockIdx.x * SX + threadIdx.x, j = blockIdx.y * SY + threadIdx.y, k = blockIdx.z;
-    if (i >= g.nx || j >= g.ny) return;
-    const size_t c = (size_t)k * g.plane + (size_t)j * g.nx + i;
-    const double v = op6<TRANS>(g, x, eps, G, c, star(g, i, j, k));
-    out[c] = MODE == 0 ? v : b[c] - v;
-}
+// LDS-tiled form of the operator, its transpose and their residual forms.  A
+// block owns a 64 x 4 column tile and marches up a chunk of Z6 planes; at each
+// plane it stages the tile plus a 3-cell halo in x and y in LDS and keeps the
+// z neighbours (k-3 .. k+3) of its own column in registers, so that every
+// input element is read from memory about once per plane instead of once per
+// stencil point.
+//   forward:    LDS holds x;              registers hold x at k-3..k+3.
+//   transposed: LDS holds eps y, Gx y, Gy y (the products the transpose
+//               differentiates);         registers hold eps y and Gz y.
+// MODE 0: out = op x;  1: out = b - op x;  2: out (wet slab plane q, type T) =
+// b - op x at box plane (k_w0 + q) mod nz.
+constexpr int T6X = 64, T6Y = 4, H6 = 3;
+constexpr int L6X = T6X + 2 * H6, L6Y = T6Y + 2 * H6, L6N = L6X * L6Y;
+constexpr int T6N = T6X * T6Y;
+constexpr int T6L = (L6N + T6N - 1) / T6N;  // tile loads per thread
+constexpr int Z6 = 16;                      // planes per block
 
-// Wet residual: fW (slab plane q = box plane (k_w0 + q) mod nz) = v - op dD
-template <class T, bool TRANS>
-__global__ void __launch_bounds__(SX *SY)
-k_wet_residual6(Grid6 g, int k_w0, const double *__restrict__ v, const double *__restrict__ dD,
-                const double *__restrict__ eps, const double *__restrict__ G, T *__restrict__ fW) {
-    const int i = blockIdx.x * SX + threadIdx.x, j = blockIdx.y * SY + threadIdx.y, q = blockIdx.z;
-    if (i >= g.nx || j >= g.ny) return;
-    const int k = wrap(k_w0 + q, g.nz);
-    const size_t c = (size_t)k * g.plane + (size_t)j * g.nx + i;
-    const double r = v[c] - op6<TRANS>(g, dD, eps, G, c, star(g, i, j, k));
-    fW[(size_t)q * g.plane + (size_t)j * g.nx + i] = (T)r;
+template <int MODE, bool TRANS, class T>
+__global__ void __launch_bounds__(T6N)
+k_op6_tile(Grid6 g, int k_w0, int nplanes, int tiles_x, int tiles_y, const double *__restrict__ x,
+           const double *__restrict__ eps, const double *__restrict__ G, const double *__restrict__ b,
+           T *__restrict__ out) {
+    __shared__ double s0[L6N], s1[TRANS ? L6N : 1], s2[TRANS ? L6N : 1];
+    const int tid = threadIdx.x;
+    const int tile = blockIdx.x;
+    const int i0 = (tile % tiles_x) * T6X, j0 = ((tile / tiles_x) % tiles_y) * T6Y;
+    const int q0 = (tile / (tiles_x * tiles_y)) * Z6, q1 = min(nplanes, q0 + Z6);
+    const int lx = tid % T6X, ly = tid / T6X;
+    const int i = i0 + lx, j = j0 + ly;
+    const bool own = i < g.nx && j < g.ny;
+    const size_t cc = own ? (size_t)j * g.nx + i : 0;  // in-plane offset of this thread's node
+    const double *Gx = G, *Gy = G + g.N, *Gz = G + 2 * g.N;
+    // in-plane offsets of this thread's tile loads (periodic, any tile overhang)
+    size_t lo[T6L];
+#pragma unroll
+    for (int m = 0; m < T6L; ++m) {
+        const int q = min(tid + T6N * m, L6N - 1);
+        const int xr = q % L6X, yr = q / L6X;
+        const int gx = ((i0 - H6 + xr) % g.nx + g.nx) % g.nx, gy = ((j0 - H6 + yr) % g.ny + g.ny) % g.ny;
+        lo[m] = (size_t)gy * g.nx + gx;
+    }
+    auto zplane = [&](int k) { return (size_t)(((k % g.nz) + g.nz) % g.nz) * g.plane; };
+    const int kb = MODE == 2 ? k_w0 : 0;
+    // z queues: a[d] and c[d] for plane k - 3 + d
+    double a[7], c[7];
+    auto zload = [&](int k, double &av, double &cv) {
+        const size_t o = zplane(k) + cc;
+        if (TRANS) {
+            const double y = x[o];
+            av = eps[o] * y;
+            cv = Gz[o] * y;
+        } else {
+            av = x[o];
+            cv = 0.0;
+        }
+    };
+    const int kfirst = kb + q0;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) zload(kfirst - 3 + d, a[d], c[d]);
+    const int lc = (ly + H6) * L6X + lx + H6;
+    const double ihx = g.ihx, ihy = g.ihy, ihz = g.ihz, ihx2 = g.ihx2, ihy2 = g.ihy2, ihz2 = g.ihz2;
+    for (int q = q0; q < q1; ++q) {
+        const int k = kb + q;
+        zload(k + 3, a[6], c[6]);
+        const size_t zp = zplane(k);
+        __syncthreads();  // the previous plane's LDS reads are done
+#pragma unroll
+        for (int m = 0; m < T6L; ++m) {
+            const int t = tid + T6N * m;
+            if (t < L6N) {
+                const size_t o = zp + lo[m];
+                if (TRANS) {
+                    const double y = x[o];
+                    s0[t] = eps[o] * y;
+                    s1[t] = Gx[o] * y;
+                    s2[t] = Gy[o] * y;
+                } else {
+                    s0[t] = x[o];
+                }
+            }
+        }
+        __syncthreads();
+        if (own) {
+            const size_t o = zp + cc;
+            double v;
+            if (!TRANS) {
+                const double d1x = ihx * (A1 * (s0[lc + 1] - s0[lc - 1]) + A2 * (s0[lc + 2] - s0[lc - 2]) +
+                                          A3 * (s0[lc + 3] - s0[lc - 3]));
+                const double d1y = ihy * (A1 * (s0[lc + L6X] - s0[lc - L6X]) + A2 * (s0[lc + 2 * L6X] - s0[lc - 2 * L6X]) +
+                                          A3 * (s0[lc + 3 * L6X] - s0[lc - 3 * L6X]));
+                const double d1z = ihz * (A1 * (a[4] - a[2]) + A2 * (a[5] - a[1]) + A3 * (a[6] - a[0]));
+                const double xc = a[3];
+                const double d2 = ihx2 * (B0 * xc + B1 * (s0[lc + 1] + s0[lc - 1]) + B2 * (s0[lc + 2] + s0[lc - 2]) +
+                                          B3 * (s0[lc + 3] + s0[lc - 3])) +
+                                  ihy2 * (B0 * xc + B1 * (s0[lc + L6X] + s0[lc - L6X]) +
+                                          B2 * (s0[lc + 2 * L6X] + s0[lc - 2 * L6X]) +
+                                          B3 * (s0[lc + 3 * L6X] + s0[lc - 3 * L6X])) +
+                                  ihz2 * (B0 * xc + B1 * (a[4] + a[2]) + B2 * (a[5] + a[1]) + B3 * (a[6] + a[0]));
+                v = Gx[o] * d1x + Gy[o] * d1y + Gz[o] * d1z + eps[o] * d2;
+            } else {
+                const double d1x = ihx * (A1 * (s1[lc + 1] - s1[lc - 1]) + A2 * (s1[lc + 2] - s1[lc - 2]) +
+                                          A3 * (s1[lc + 3] - s1[lc - 3]));
+                const double d1y = ihy * (A1 * (s2[lc + L6X] - s2[lc - L6X]) + A2 * (s2[lc + 2 * L6X] - s2[lc - 2 * L6X]) +
+                                          A3 * (s2[lc + 3 * L6X] - s2[lc - 3 * L6X]));
+                const double d1z = ihz * (A1 * (c[4] - c[2]) + A2 * (c[5] - c[1]) + A3 * (c[6] - c[0]));
+                const double pc = a[3];
+                const double d2 = ihx2 * (B0 * pc + B1 * (s0[lc + 1] + s0[lc - 1]) + B2 * (s0[lc + 2] + s0[lc - 2]) +
+                                          B3 * (s0[lc + 3] + s0[lc - 3])) +
+                                  ihy2 * (B0 * pc + B1 * (s0[lc + L6X] + s0[lc - L6X]) +
+                                          B2 * (s0[lc + 2 * L6X] + s0[lc - 2 * L6X]) +
+                                          B3 * (s0[lc + 3 * L6X] + s0[lc - 3 * L6X])) +
+                                  ihz2 * (B0 * pc + B1 * (a[4] + a[2]) + B2 * (a[5] + a[1]) + B3 * (a[6] + a[0]));
+                v = -(d1x + d1y + d1z) + d2;
+            }
+            if (MODE == 0) out[o] = (T)v;
+            else if (MODE == 1) out[o] = (T)(b[o] - v);
+            else out[(size_t)q * g.plane + cc] = (T)(b[o] - v);
+        }
+#pragma unroll
+        for (int d = 0; d < 6; ++d) { a[d] = a[d + 1]; c[d] = c[d + 1]; }
+    }
 }
 
 // dE/d eps_n = sum_d D1_d(lam D1_d phi)_n - lam_n (sum_d D2_d phi)_n; the inner D1
@@ -228,28 +291,31 @@ void launch_d1eps(hipStream_t s, const Plan &p, const double *eps, double *G) {
     DWP_LAUNCH_CHECK();
 }
 
+template <int MODE, bool TRANS, class T>
+static void launch_op6_tile(hipStream_t s, const Plan &p, int k_w0, int nplanes, const double *x, const double *eps,
+                            const double *G, const double *b, T *out) {
+    const Grid6 g = make_grid6(p);
+    const int tx = (p.nx + T6X - 1) / T6X, ty = (p.ny + T6Y - 1) / T6Y, tz = (nplanes + Z6 - 1) / Z6;
+    k_op6_tile<MODE, TRANS, T><<<tx * ty * tz, T6N, 0, s>>>(g, k_w0, nplanes, tx, ty, x, eps, G, b, out);
+    DWP_LAUNCH_CHECK();
+}
+
 void launch_apply6(hipStream_t s, const Plan &p, const double *x, const double *eps, const double *G,
                    const double *b, double *out, bool residual, bool trans) {
-    const Grid6 g = make_grid6(p);
-    dim3 gr((p.nx + SX - 1) / SX, (p.ny + SY - 1) / SY, p.nz), blk(SX, SY);
     if (residual) {
-        if (trans) k_apply6<1, true><<<gr, blk, 0, s>>>(g, x, eps, G, b, out);
-        else k_apply6<1, false><<<gr, blk, 0, s>>>(g, x, eps, G, b, out);
+        if (trans) launch_op6_tile<1, true, double>(s, p, 0, p.nz, x, eps, G, b, out);
+        else launch_op6_tile<1, false, double>(s, p, 0, p.nz, x, eps, G, b, out);
     } else {
-        if (trans) k_apply6<0, true><<<gr, blk, 0, s>>>(g, x, eps, G, b, out);
-        else k_apply6<0, false><<<gr, blk, 0, s>>>(g, x, eps, G, b, out);
+        if (trans) launch_op6_tile<0, true, double>(s, p, 0, p.nz, x, eps, G, b, out);
+        else launch_op6_tile<0, false, double>(s, p, 0, p.nz, x, eps, G, b, out);
     }
-    DWP_LAUNCH_CHECK();
 }
 
 template <class T>
 void launch_wet_residual6(hipStream_t s, const Plan &p, const double *v, const double *dD, const double *eps,
                           const double *G, T *fW, bool trans) {
-    const Grid6 g = make_grid6(p);
-    dim3 gr((p.nx + SX - 1) / SX, (p.ny + SY - 1) / SY, p.nw), blk(SX, SY);
-    if (trans) k_wet_residual6<T, true><<<gr, blk, 0, s>>>(g, p.k_w0, v, dD, eps, G, fW);
-    else k_wet_residual6<T, false><<<gr, blk, 0, s>>>(g, p.k_w0, v, dD, eps, G, fW);
-    DWP_LAUNCH_CHECK();
+    if (trans) launch_op6_tile<2, true, T>(s, p, p.k_w0, p.nw, dD, eps, G, v, fW);
+    else launch_op6_tile<2, false, T>(s, p, p.k_w0, p.nw, dD, eps, G, v, fW);
 }
 template void launch_wet_residual6<float>(hipStream_t, const Plan &, const double *, const double *, const double *,
                                           const double *, float *, bool);

@@ -158,3 +158,29 @@ def test_slab_matches_stored_oracle(torch):
     assert np.abs(F - np.array(ref["forces"])).max() <= 1e-6 * np.abs(ref["forces"]).max()
     assert abs(info["background"] - ref["background"]) <= 1e-8 * abs(ref["background"]) + 1e-12
     s.close()
+
+
+def test_switching_the_order_on_one_context(torch):
+    # order 6 -> 2 -> 6 on one context gives the results of fresh contexts
+    n, L, xyz, R, q, sig, p = _small_system()
+    opts = dict(z_wet_lo=1.0, z_wet_hi=7.5, tol=1e-10, precision=0, scaled_dry=1)
+
+    def fresh(order):
+        s = _solver(n, L, **dict(opts, order=order))
+        s.build_epsilon(xyz, R, p)
+        _, E, _ = s.solve(s.build_rho(xyz, q, sig))
+        F = s.forces(xyz, q, sig, R, p)
+        s.close()
+        return E, F
+
+    ref = {o: fresh(o) for o in (2, 6)}
+    s = _solver(n, L, **dict(opts, order=6))
+    s.build_epsilon(xyz, R, p)
+    rho = s.build_rho(xyz, q, sig)
+    for order in (6, 2, 6):
+        s.set_opts(order=order)
+        _, E, _ = s.solve(rho)
+        F = s.forces(xyz, q, sig, R, p)
+        assert E == ref[order][0] and np.array_equal(F, ref[order][1]), order
+    assert abs(ref[6][0] - ref[2][0]) > 1e-6 * abs(ref[2][0])   # the two operators differ
+    s.close()
