@@ -617,7 +617,7 @@ __global__ void k_coarsen_eps(const T *__restrict__ ef, T *__restrict__ ec, int 
 // step m.  That needs 4 planes of u, f and first-colour values and 5 of eps
 // (read by the second colour one step later than by the first; 8 are kept).
 // The step loop is unrolled by 8 so that every ring slot is a constant.
-constexpr int FTX = 32, FTY = 8;
+constexpr int FTX = 32, FTY = 16;
 constexpr int FRX = FTX + 2, FRY = FTY + 2;  // first-colour values: tile + 1-cell halo
 constexpr int FNT = FTX * FTY;               // threads
 constexpr int FUNROLL = 8;
