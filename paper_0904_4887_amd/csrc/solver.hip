@@ -293,8 +293,9 @@ void vcycle(dwp_ctx *c, size_t l, bool u_unset) {
         return;
     }
     // the first pre-sweep starts from a zero correction on coarse levels and
-    // in the first cycle on the fine level
-    bool zero_in = l > 0 || u_unset;
+    // in the first cycle on the fine level; without pre-sweeps the first sweep
+    // comes after the coarse-grid correction, so its input is not zero
+    bool zero_in = (l > 0 || u_unset) && c->opts.pre > 0;
     auto smooth = [&](int first) {
         if (fused) {
             const double b = zero_in ? 1.5 * pass_bytes : 2.0 * pass_bytes;

@@ -195,18 +195,21 @@ def test_error_paths(torch):
     assert info["rel_res"] <= 1e-10
 
 
-@pytest.mark.parametrize("precision,cycles", [(0, 1), (1, 1), (1, 2)])
-def test_fused_sweep_equals_colour_passes(torch, precision, cycles):
+@pytest.mark.parametrize("precision,cycles,pre,post", [(0, 1, 2, 2), (1, 1, 2, 2), (1, 2, 2, 2), (0, 1, 0, 1),
+                                                    (1, 2, 0, 2)])
+def test_fused_sweep_equals_colour_passes(torch, precision, cycles, pre, post):
     """The fused out-of-place sweep and the two in-place colour passes are the
     same Gauss-Seidel sweep: one application of the split agrees to rounding.
     The fine wet level of this grid (96 x 96 x 151) is above the size from
-    which the fused kernel takes over, so both kernels really run."""
+    which the fused kernel takes over, so both kernels really run.  Without
+    pre-sweeps the first fused sweep follows the coarse-grid correction and
+    must read it (its zero-input variant would drop it)."""
     from paper_0904_4887_amd.binding import plan
     w = W.slab(n=(96, 96, 192), exclusion=True)
     fine = plan(w.n, w.L, z_wet_lo=w.z_wet[0], z_wet_hi=w.z_wet[1])["levels"][0]
     assert fine[0] * fine[1] * fine[2] >= 1 << 20
     s = _solver(torch, w.n, w.L, z_wet_lo=w.z_wet[0], z_wet_hi=w.z_wet[1], precision=precision, smoother=1,
-                cycles=cycles)
+                cycles=cycles, pre=pre, post=post)
     s.build_epsilon(w.xyz, w.radius, w.eps_params)
     rng = np.random.default_rng(3)
     r = _dev(torch, rng.normal(size=s.shape))
