@@ -184,3 +184,29 @@ def test_switching_the_order_on_one_context(torch):
         assert E == ref[order][0] and np.array_equal(F, ref[order][1]), order
     assert abs(ref[6][0] - ref[2][0]) > 1e-6 * abs(ref[2][0])   # the two operators differ
     s.close()
+
+
+def test_v_eps_with_the_sixth_order_operator(torch):
+    # a permittivity from a smooth density blob (Eq. 7); V_eps and dE/d rho come
+    # from the adjoint solve of the non-symmetric operator
+    n, L = (24, 24, 32), (6.0, 6.0, 8.0)
+    h = tuple(L[d] / n[d] for d in range(3))
+    z, y, x = np.meshgrid(*(np.arange(n[d]) * h[d] for d in (2, 1, 0)), indexing="ij")
+    rho_e = 0.05 * np.exp(-((x - 3.0) ** 2 + (y - 3.0) ** 2 + (z - 4.0) ** 2) / (2 * 1.2 ** 2))
+    src = np.exp(-((x - 2.5) ** 2 + (y - 3.2) ** 2 + (z - 3.6) ** 2) / 0.5) \
+        - np.exp(-((x - 3.6) ** 2 + (y - 2.7) ** 2 + (z - 4.5) ** 2) / 0.4)
+    P = dict(eps_inf=W.EPS_INF, rho0=0.01, beta=1.3)
+    s = _solver(n, L, z_wet_lo=1.0, z_wet_hi=7.0, tol=1e-11, precision=0, scaled_dry=1)
+    s.build_epsilon_density(_dev(torch, rho_e), **P)
+    s.solve(_dev(torch, src))
+    V = s.v_eps().cpu().numpy()
+    G = s.v_eps(add_phi=True).cpu().numpy()
+    eps = O.eps_of_density(rho_e, **P)
+    ref = S.solve6(src, eps, h, tol=1e-13)
+    lam = S.adjoint6(src, eps, h, tol=1e-13)
+    h3 = h[0] * h[1] * h[2]
+    V_ref = S.eps_gradient6(ref, lam, h) / h3 * O.deps_drho(rho_e, **P)
+    G_ref = S.charge_potential6(ref, lam, h) + V_ref
+    assert np.abs(V - V_ref).max() <= 1e-7 * np.abs(V_ref).max()
+    assert np.abs(G - G_ref).max() <= 1e-7 * np.abs(G_ref).max()
+    s.close()
