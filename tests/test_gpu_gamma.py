@@ -138,3 +138,26 @@ def test_gamma_model_errors(torch):
     assert e.value.status == DWP_ESTATE
     s.forces(w.xyz, w.q, w.sigma, w.radius, w.eps_params)
     s.close()
+
+
+@pytest.mark.parametrize("exclusion", [0, 1])
+def test_atom_on_a_node(torch, exclusion):
+    # an atom exactly on a grid node (d = 0 there: that node adds no force) next
+    # to one off the grid; with exclusion the first is buried
+    n, L = (16, 16, 24), (6.0, 6.0, 9.0)
+    h = (L[0] / n[0], L[1] / n[1], L[2] / n[2])
+    xyz = np.array([[5 * h[0], 7 * h[1], 10 * h[2]], [3.9, 3.1, 5.3]])
+    R, q, sig = np.array([1.6, 1.4]), np.array([1.0, -1.0]), np.array([0.3, 0.3])
+    p = dict(eps_inf=W.EPS_INF, model=1, beta=2.4, decay=W.BOHR, exclusion=exclusion, z_lim=5.0)
+    from paper_0904_4887_amd.binding import Solver
+    s = Solver(0)
+    s.set_grid(n, L, z_wet_lo=0.5, z_wet_hi=8.5, tol=1e-11, scaled_dry=1)
+    s.build_epsilon(xyz, R, p)
+    eps = s.get_epsilon().cpu().numpy()
+    assert np.abs(eps - O.eps_gamma(n, L, xyz, R, p)).max() <= EPS_TOL
+    phi, E, info = s.solve(s.build_rho(xyz, q, sig))
+    F = s.forces(xyz, q, sig, R, p)
+    ph = phi.cpu().numpy()
+    F_same = O.forces_gamma(n, L, xyz, R, q, sig, p, ph, O.eps_gradient(ph, s.h))
+    assert np.abs(F - F_same).max() <= 1e-10 * np.abs(F_same).max()
+    s.close()
