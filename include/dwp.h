@@ -135,7 +135,7 @@ typedef struct {
  * drives eps to 1 underneath the buried atoms so that the region below the
  * exposed face is really dry (Sec. II.F).  exclusion = 0 gives H = 1.
  *
- * model 1 (the paper's own form, Sec. II.D): the dummy density of Eq. 9 fed
+ * model 1 (the paper's own form, Sec. II.E): the dummy density of Eq. 9 fed
  * into Eq. 10,
  *   gamma_n = sum_i exp(-s_in (d_in - R_i) / a),
  *   eps_n = 1 + (eps_inf - 1) / (1 + gamma_n^(2 beta)),
@@ -195,7 +195,7 @@ int dwp_build_epsilon(dwp_ctx *ctx, int n, const double *xyz_host, const double 
                       const dwp_eps_params *params);
 int dwp_get_epsilon(dwp_ctx *ctx, double *eps_dev);
 
-/* Density-dependent permittivity (Sec. II.B): eps_n = eps(rho_n) by Eq. 7,
+/* Density-dependent permittivity (Secs. II.C-II.D): eps_n = eps(rho_n) by Eq. 7,
  *   eps(rho) = 1 + (eps_inf - 1)/2 (1 + (1 - (rho/rho0)^(2 beta)) / (1 + (rho/rho0)^(2 beta))),
  * from an electron-density grid rho_dev (N doubles on the device, the grid's
  * x-fastest layout; read only during the call; negative values are read as

@@ -20,7 +20,7 @@ What it computes (paper, Sec. II.B-II.F and Appendix B):
     slab with the vacuum potential as boundary data, Sec. II.F) as a
     diagnostic;
   * the density-dependent permittivity (Eq. 7), its derivative (Eq. 8) and the
-    potential term V_eps (Eq. 6) of Sec. II.B;
+    potential term V_eps (Eq. 6) of Secs. II.C-II.D;
   * the paper's atom-defined permittivity: dummy density (Eq. 9), Eq. 10, the
     solvent exclusion of Eq. 19, and its force term (Eqs. 11-12, with the sign
     that differentiating Eqs. 9-10 gives);

@@ -1,4 +1,4 @@
-"""The density-dependent dielectric of the paper's Sec. II.B and its
+"""The density-dependent dielectric of the paper's Secs. II.C-II.D and its
 potential term, for the oracle.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).

@@ -1,4 +1,4 @@
-"""The paper's atom-defined dielectric (Sec. II.D): the dummy density of
+"""The paper's atom-defined dielectric (Sec. II.E): the dummy density of
 Eq. 9, the permittivity of Eq. 10, the solvent exclusion of Eq. 19 and the
 permittivity term of the forces (Eqs. 11-12).
 

@@ -1,4 +1,4 @@
-"""Density-dependent permittivity on the GPU (Sec. II.B, Eqs. 5-8), through the C ABI.
+"""Density-dependent permittivity on the GPU (Secs. II.C-II.D, Eqs. 5-8), through the C ABI.
 
 * eps(rho) built on the device equals the oracle's Eq. 7 node by node, with
   zero and negative densities among the inputs, at a small size and at the

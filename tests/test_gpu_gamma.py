@@ -1,4 +1,4 @@
-"""The paper's atom-defined dielectric on the GPU (Sec. II.D: Eqs. 9, 10, 12, 19),
+"""The paper's atom-defined dielectric on the GPU (Secs. II.E-II.F: Eqs. 9, 10, 12, 19),
 through the C ABI (dwp_eps_params.model = 1).
 
 * eps against the oracle node by node (both exclusion modes, a ragged grid,

@@ -1,4 +1,4 @@
-"""Pins of the oracle's density-dependent dielectric (Eqs. 5-8, Sec. II.B).
+"""Pins of the oracle's density-dependent dielectric (Eqs. 5-8, Secs. II.C-II.D).
 
 Checked against what the paper and the mathematics fix, never against a
 retyped formula: the closed-form values of Eq. 7 at rho = 0, rho_0 and

@@ -1,4 +1,4 @@
-"""Pins of the oracle's atom-defined dielectric (Sec. II.D: Eqs. 9, 10, 12, 19).
+"""Pins of the oracle's atom-defined dielectric (Secs. II.E-II.F: Eqs. 9, 10, 12, 19).
 
 Against what the mathematics fixes, not a retyped formula:
 * one atom: Eq. 10 with Eq. 9 is a logistic function of the distance,
