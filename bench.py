@@ -125,6 +125,43 @@ def cpu_baseline(w, golden_iters):
                       f"workload; eps/rho builds and forces not included (NumPy, one thread)"}
 
 
+def cpu_widened(gpu_ms):
+    """The oracle beside the widened paths, on bounded samples (one thread):
+    the dummy-density permittivity at 1/64 of the 192x192x384 nodes, scaled to
+    the grid; the density permittivity and V_eps on the full grid; one
+    application of the sixth-order operator on the full grid.  Each is set
+    against the GPU's time for the same work (kernel means from the profile
+    groups of the timed entries, passed in as gpu_ms)."""
+    import oracle as O
+    from oracle import sixth as S
+    from threadpoolctl import threadpool_limits
+    out = {}
+    with threadpool_limits(limits=1):
+        w = W.slab_gamma((192, 192, 384))
+        nodes = np.arange(0, w.N, 64)
+        t0 = time.perf_counter()
+        O.eps_gamma(w.n, w.L, w.xyz, w.radius, w.eps_params, nodes=nodes)
+        t_gamma = (time.perf_counter() - t0) * 64
+        out["gamma_eps_build"] = {"oracle_s": round(t_gamma, 2), "sample": "1/64 of the nodes, x64",
+                                  "gpu_ms": gpu_ms.get("gamma_build")}
+        wd = W.density_slab((192, 192, 384))
+        rho_e = W.electron_density(wd)
+        p = wd.eps_params
+        phi = np.random.default_rng(0).normal(size=rho_e.shape)
+        t0 = time.perf_counter()
+        O.eps_of_density(rho_e, p["eps_inf"], p["rho0"], p["beta"])
+        O.v_eps(phi, rho_e, wd.h, p["eps_inf"], p["rho0"], p["beta"])
+        out["density_eps_and_v_eps"] = {"oracle_s": round(time.perf_counter() - t0, 2), "sample": "full grid",
+                                        "gpu_ms": gpu_ms.get("density")}
+        eps = np.full(rho_e.shape, 2.0)
+        t0 = time.perf_counter()
+        S.apply_A6(phi, eps, wd.h)
+        out["sixth_order_apply"] = {"oracle_s": round(time.perf_counter() - t0, 2), "sample": "full grid",
+                                    "gpu_ms": gpu_ms.get("sixth_apply")}
+    out["cores"] = 1
+    return out
+
+
 def md_loop(w, steps, torch, precision="mixed"):
     """MD-like steps: R += N(0, 0.02 A) per step (cumulative), eps and rho
     rebuilt, phi warm-started from the previous step, forces every step."""
@@ -150,6 +187,18 @@ def md_loop(w, steps, torch, precision="mixed"):
                         max_force=float(np.abs(F).max())))
     s.close()
     return per
+
+
+def gpu_wall_ms(torch, fn, reps=3):
+    """Median wall time of fn() in ms, with the device synchronised around it."""
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(1e3 * (time.perf_counter() - t0))
+    return round(float(np.median(ts)), 3)
 
 
 def density_steps(torch, n=(192, 192, 384), steps=4, warmup=1, precision="mixed"):
@@ -182,11 +231,15 @@ def density_steps(torch, n=(192, 192, 384), steps=4, warmup=1, precision="mixed"
     sec = (time.perf_counter() - t0) / steps
     vmax = float(v.abs().max())
     pmax = float(phi.abs().max())
+    # the permittivity and V_eps alone (no solve), for the oracle comparison
+    t_eps = gpu_wall_ms(torch, lambda: s.build_epsilon_density(rho_e, p["eps_inf"], p["rho0"], p["beta"]))
+    s.solve(src, phi)
+    t_v = gpu_wall_ms(torch, lambda: s.v_eps(out=v))
     s.close()
     return {"ms_per_step": round(1e3 * sec, 2), "steps_per_s": round(1.0 / sec, 3),
             "iters": [i["outer_iters"] for i in infos], "energy": E, "z_wet": list(w.z_wet),
             "rho0": p["rho0"], "beta": p["beta"], "max_abs_v_eps": vmax, "max_abs_phi": pmax,
-            "v_eps_over_phi": round(vmax / pmax, 3)}
+            "v_eps_over_phi": round(vmax / pmax, 3), "eps_build_ms": t_eps, "v_eps_ms": t_v}
 
 
 def gamma_steps(torch, exclusion, n=(192, 192, 384), steps=4, warmup=1, precision="mixed"):
@@ -196,6 +249,7 @@ def gamma_steps(torch, exclusion, n=(192, 192, 384), steps=4, warmup=1, precisio
     w = W.slab_gamma(n, exclusion=exclusion)
     s = solver_for(w, precision, torch)
     sec, E, infos, _, _ = run_steps(s, w, steps, warmup, torch)
+    t_build = gpu_wall_ms(torch, lambda: s.build_epsilon(w.xyz, w.radius, w.eps_params))
     s.close()
     sp = solver_for(w, precision, torch, profile=1)
     _, _, _, _, prof = run_steps(sp, w, 1, 1, torch)
@@ -203,7 +257,7 @@ def gamma_steps(torch, exclusion, n=(192, 192, 384), steps=4, warmup=1, precisio
     return {"ms_per_step": round(1e3 * sec, 2), "steps_per_s": round(1.0 / sec, 3),
             "iters": [i["outer_iters"] for i in infos], "energy": E, "z_wet": list(w.z_wet),
             "beta": w.eps_params["beta"], "builders_ms": round(prof.get("builders", {}).get("ms", 0.0), 3),
-            "forces_ms": round(prof.get("forces", {}).get("ms", 0.0), 3)}
+            "forces_ms": round(prof.get("forces", {}).get("ms", 0.0), 3), "eps_build_ms": t_build}
 
 
 def sixth_order_steps(torch, n=(192, 192, 384), steps=2, warmup=1, precision="mixed"):
@@ -214,10 +268,12 @@ def sixth_order_steps(torch, n=(192, 192, 384), steps=2, warmup=1, precision="mi
     w.opts = dict(scaled_dry=1, order=6)
     s = solver_for(w, precision, torch)
     sec, E, infos, _, _ = run_steps(s, w, steps, warmup, torch)
+    x = s.empty().normal_()
+    t_apply = gpu_wall_ms(torch, lambda: s.apply_operator(x), reps=5)
     s.close()
     return {"ms_per_step": round(1e3 * sec, 2), "steps_per_s": round(1.0 / sec, 3),
             "iters": [i["outer_iters"] for i in infos], "energy": E, "background": infos[-1]["background"],
-            "opts": w.opts}
+            "opts": w.opts, "apply_ms": t_apply}
 
 
 def copy_ceiling(torch):
@@ -409,6 +465,13 @@ def main():
         if gi is None:
             gi = 130
         cpu = cpu_baseline(w, gi)
+        if "sixth_order_192x192x384" in extra:
+            dd = extra["density_eps_192x192x384"]
+            gpu_ms = {"gamma_build": extra["gamma_eps_192x192x384"]["eps_build_ms"],
+                      "density": round(dd["eps_build_ms"] + dd["v_eps_ms"], 3),
+                      "sixth_apply": extra["sixth_order_192x192x384"]["apply_ms"]}
+            extra["oracle_beside_widened"] = cpu_widened(gpu_ms)
+            print(f"# oracle beside widened paths: {extra['oracle_beside_widened']}", file=sys.stderr, flush=True)
 
     line = {
         "metric": METRIC, "value": round(1.0 / sec, 4), "unit": "solves/s", "n_gpus": 1,
