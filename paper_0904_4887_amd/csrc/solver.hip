@@ -842,7 +842,10 @@ void ensure_adjoint(dwp_ctx *c) {
     launch_dot(s, c->adj_rhs.as<double>(), c->adj_rhs.as<double>(), N, part, coef + 407);
     to_host(c, coef + 407, 1);
     const double fnorm = std::sqrt(c->host[0]);
+    // initial guess: the adjoint of the symmetric part, -h^3 phi / (8 pi) (the
+    // same scale as the right-hand side; exact for a symmetric operator)
     launch_fill(s, c->lam.as<double>(), 0.0, N);
+    launch_axpy_multi(s, c->lam.as<double>(), c->phi_last.as<double>(), N, 1, coef + 406, N, 1.0, part, nullptr);
     if (fnorm > 0.0) {
         int restarts = 0;
         double rel = 0.0;
