@@ -45,7 +45,10 @@ def make_workload(name, exclusion):
     return W.slab(n=n, exclusion=exclusion, tol=1e-8)
 
 
-def run_steps(s, w, steps, warmup, torch):
+def run_steps(s, w, steps, warmup, torch, keep=None):
+    """Time `steps` whole steps after `warmup` untimed ones; returns seconds per
+    step, the last energy, the per-step infos, the last dE/dR and the profile
+    groups; with keep (a dict), also keep["phi"] (the last solution)."""
     rho = s.empty()
     phi = s.empty()
     infos = []
@@ -68,6 +71,8 @@ def run_steps(s, w, steps, warmup, torch):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = s.profile()
+    if keep is not None:
+        keep["phi"] = phi
     return (t1 - t0) / steps, E, infos, F, prof
 
 
@@ -101,28 +106,75 @@ def stored_traffic(kernel):
         return None
 
 
-def cpu_baseline(w, golden_iters):
-    """The FP64 oracle's solve, timed on a bounded sample: a few PCG iterations
-    of the full-size problem, scaled by the iteration count the oracle needs
-    for a 1e-8 residual on this workload."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, n_small=(96, 96, 192)):
+    """The FP64 oracle's whole step, timed on the host: permittivity and charge
+    density from the workload's atoms, the solve to a 1e-8 residual (PCG with
+    the vacuum FFT preconditioner, cold start), dE/d eps and dE/dR of every
+    atom, on the same slab recipe at a grid that finishes in tens of seconds
+    (96 x 96 x 192, same cell and atoms); scaled to the workload's grid by its
+    point count (the builds and the force sums grow with the atom-node pairs,
+    the solve with points x iterations, the oracle's own iteration count at the
+    workload size being taken from its stored run)."""
     import oracle as O
     from threadpoolctl import threadpool_limits
+    ws = W.slab(n_small, tol=1e-8)
     with threadpool_limits(limits=1):
-        eps = O.eps_erf(w.n, w.L, w.xyz, w.radius, w.eps_params, nodes=np.arange(0, w.N, 997))
-        del eps
-        rho = np.zeros((w.n[2], w.n[1], w.n[0]))
-        rho[::7, ::5, ::3] = 1.0
-        eps = np.ones_like(rho)
-        its = 3
         t0 = time.perf_counter()
-        O.solve(rho, eps, w.h, tol=1e-300, max_iter=its)
-        dt = (time.perf_counter() - t0) / its
-    n_iters = golden_iters
-    t_solve = dt * n_iters
-    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{its} PCG iterations of the oracle's full-grid {w.n[0]}x{w.n[1]}x{w.n[2]} solve "
-                      f"({dt:.2f} s each), scaled by its {n_iters} iterations to a 1e-8 residual on this "
-                      f"workload; eps/rho builds and forces not included (NumPy, one thread)"}
+        eps = O.eps_erf(ws.n, ws.L, ws.xyz, ws.radius, ws.eps_params)
+        rho = O.rho_gauss(ws.n, ws.L, ws.xyz, ws.q, ws.sigma)
+        t1 = time.perf_counter()
+        phi, info = O.solve(rho, eps, ws.h, tol=1e-8, return_info=True)
+        t2 = time.perf_counter()
+        O.energy(rho, phi, ws.h)
+        O.forces(ws.n, ws.L, ws.xyz, ws.radius, ws.q, ws.sigma, ws.eps_params, phi, O.eps_gradient(phi, ws.h))
+        t3 = time.perf_counter()
+    ratio = (w.n[0] * w.n[1] * w.n[2]) / (ws.n[0] * ws.n[1] * ws.n[2])
+    it_big = golden_iters(w.name) or info["iters"]
+    t_est = ratio * ((t1 - t0) + (t3 - t2) + (t2 - t1) * it_big / info["iters"])
+    return {"value": round(1.0 / t_est, 6), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"the oracle's whole step (eps and rho from the atoms, PCG solve to 1e-8, dE/d eps, dE/dR) "
+                      f"on the same slab recipe at {ws.n[0]}x{ws.n[1]}x{ws.n[2]}, measured "
+                      f"{t3 - t0:.1f} s ({t1 - t0:.1f} build, {t2 - t1:.1f} solve in {info['iters']} iterations, "
+                      f"{t3 - t2:.1f} forces); scaled x{ratio:g} in points and x{it_big}/{info['iters']} in "
+                      f"iterations to {w.n[0]}x{w.n[1]}x{w.n[2]}; NumPy/SciPy, one thread",
+            "measured_small": {"grid": list(ws.n), "s_per_step": round(t3 - t0, 2), "build_s": round(t1 - t0, 2),
+                               "solve_s": round(t2 - t1, 2), "iters": info["iters"], "forces_s": round(t3 - t2, 2)},
+            "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
+
+
+def errors_vs_oracle(name, E, info, phi, F, torch):
+    """Per-result errors against the stored FP64 oracle solution: relative
+    energy error (E = 1/2 h^3 sum rho phi, and the variational form 2E - E_eps,
+    whose error is second order in the residual), max |phi - phi_o| / max |phi_o|
+    over the stored nodes, and max |dE/dR - dE/dR_o| / max |dE/dR_o|."""
+    p = os.path.join(ROOT, "tests", "golden", f"oracle_{name}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        ref = json.load(f)
+    Eo = ref["energy"]
+    nodes = torch.from_numpy(np.array(ref["nodes"])).to(phi.device)
+    ph = phi.reshape(-1)[nodes].cpu().numpy()
+    po = np.array(ref["phi"])
+    out = {"rel_energy_err": abs(E - Eo) / abs(Eo),
+           "rel_energy_err_variational": abs(2.0 * E - info["energy_eps_form"] - Eo) / abs(Eo),
+           "max_phi_err_rel": float(np.abs(ph - po).max() / np.abs(po).max()),
+           "phi_nodes": len(po), "rel_res": info["rel_res"]}
+    if F is not None and "forces" in ref:
+        Fo = np.array(ref["forces"])
+        out["max_force_err_rel"] = float(np.abs(F - Fo).max() / np.abs(Fo).max())
+    return out
 
 
 def cpu_widened(gpu_ms):
@@ -327,6 +379,33 @@ def hbm_resident_smoother(torch, n=(512, 512, 512), reps=4):
     return {"grid": list(n), "wet_fraction": 0.7, **out}
 
 
+def coupling_variants(w, precision, torch, steps=3):
+    """The literal slab's coupling under other solver parameters at the same
+    tolerance (the wet cut and the cycle change the preconditioner, not the
+    result): (i) the FFT dry update alone (no wet correction); (ii) the wet
+    region extended from the top of the slab through the solvent above it and
+    across the periodic wrap to the bottom of the slab, so that the FFT's dry
+    region is the slab's interior; (iii) that cut with V(2,2) cycles and a
+    64-sweep coarsest solve."""
+    top = float(w.xyz[:, 2].max())
+    bot = float(w.xyz[:, 2].min())
+    cut = (top + 0.5, w.L[2] + bot)
+    out = {}
+    for key, kw in [("fft_only", dict(cycles=0)),
+                    ("slab_interior_dry", dict(z_wet_lo=cut[0], z_wet_hi=cut[1])),
+                    ("slab_interior_dry_v22", dict(z_wet_lo=cut[0], z_wet_hi=cut[1], pre=2, post=2,
+                                                   coarse_sweeps=64))]:
+        sv = solver_for(w, precision, torch, **kw)
+        keep = {}
+        sec, E, infos, F, _ = run_steps(sv, w, steps, 1, torch, keep=keep)
+        out[key] = {"ms_per_step": round(1e3 * sec, 2), "iters": infos[-1]["outer_iters"], "energy": E,
+                    "z_wet": [kw.get("z_wet_lo", w.z_wet[0]), kw.get("z_wet_hi", w.z_wet[1])],
+                    "phases_ms": {k: round(infos[-1][k], 2) for k in ("t_fft_ms", "t_mg_ms", "t_krylov_ms")},
+                    "vs_oracle": errors_vs_oracle(w.name, E, infos[-1], keep["phi"], F, torch)}
+        sv.close()
+    return out
+
+
 def golden_iters(name):
     p = os.path.join(ROOT, "tests", "golden", f"oracle_{name}.json")
     if os.path.exists(p):
@@ -379,10 +458,13 @@ def main():
     s = solver_for(w, args.precision, torch, profile=2)
     print(f"# bench: {w.name} {args.precision} exclusion={args.exclusion} steps={args.steps} "
           f"warmup={args.warmup}", file=sys.stderr, flush=True)
-    sec, E, infos, F, prof = run_steps(s, w, args.steps, args.warmup, torch)
+    keep = {}
+    sec, E, infos, F, prof = run_steps(s, w, args.steps, args.warmup, torch, keep=keep)
     iters = [i["outer_iters"] for i in infos]
     solve_ms = float(np.median([i["t_total_ms"] for i in infos]))
-    print(f"# main: {1e3 * sec:.2f} ms/step, iters {iters}, E {E:.12f}", file=sys.stderr, flush=True)
+    phases = {k: round(float(np.median([i[k] for i in infos])), 3) for k in ("t_fft_ms", "t_mg_ms", "t_krylov_ms")}
+    print(f"# main: {1e3 * sec:.2f} ms/step, iters {iters}, E {E:.12f}, phases {phases}", file=sys.stderr, flush=True)
+    err_main = errors_vs_oracle(w.name, E, infos[-1], keep["phi"], F, torch)
 
     # roofline of the fine-level smoother (the dominant kernel of the wet solve),
     # from the HIP events recorded around each of its launches in the timed steps
@@ -399,6 +481,11 @@ def main():
                 "traffic": stored_traffic("k_sweep_fused<float, 4, *>") if args.precision == "mixed" and w.n == (192, 192, 384) else None,
                 "avg_launch_us": round(1e3 * avg_ms, 2), "launches": dom["launches"],
                 "algorithmic_bytes_per_launch": per_launch}
+    # the same steps with no instrumentation at all
+    s0 = solver_for(w, args.precision, torch, profile=0)
+    sec0, _, _, _, _ = run_steps(s0, w, args.steps, 1, torch)
+    s0.close()
+    print(f"# main, no instrumentation: {1e3 * sec0:.2f} ms/step", file=sys.stderr, flush=True)
     # per-kernel-group breakdown from a separate, fully instrumented short run
     sb = solver_for(w, args.precision, torch, profile=1)
     secb, _, _, _, profb = run_steps(sb, w, 2, 0, torch)
@@ -406,32 +493,41 @@ def main():
     kernels = {k: {"ms_per_step": round(v["ms"] / 2, 3), "launches_per_step": v["launches"] / 2,
                    "GB/s": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)} for k, v in profb.items()}
 
-    extra = {}
+    extra = {"uninstrumented_ms_per_step": round(1e3 * sec0, 3)}
     if not args.no_compare:
         other = "fp64" if args.precision == "mixed" else "mixed"
         s2 = solver_for(w, other, torch)
-        sec2, E2, inf2, _, prof2 = run_steps(s2, w, max(2, args.steps // 2), 1, torch)
+        keep2 = {}
+        sec2, E2, inf2, F2, prof2 = run_steps(s2, w, max(2, args.steps // 2), 1, torch, keep=keep2)
         extra[other] = {"steps_per_s": round(1.0 / sec2, 3), "ms_per_step": round(1e3 * sec2, 2),
                         "iters": inf2[-1]["outer_iters"], "energy": E2,
-                        "rel_energy_diff_vs_main": abs(E2 - E) / abs(E)}
+                        "rel_energy_diff_vs_main": abs(E2 - E) / abs(E),
+                        "vs_oracle": errors_vs_oracle(w.name, E2, inf2[-1], keep2["phi"], F2, torch)}
         s2.close()
         print(f"# {other}: {1e3 * sec2:.2f} ms/step", file=sys.stderr, flush=True)
         if args.precision == "mixed":
             s4 = solver_for(w, "mixed", torch, fft_fp32=1)
-            sec4, E4, inf4, _, _ = run_steps(s4, w, max(2, args.steps // 2), 1, torch)
+            keep4 = {}
+            sec4, E4, inf4, F4, _ = run_steps(s4, w, max(2, args.steps // 2), 1, torch, keep=keep4)
             extra["mixed_fft_fp32"] = {"steps_per_s": round(1.0 / sec4, 3), "ms_per_step": round(1e3 * sec4, 2),
                                        "iters": inf4[-1]["outer_iters"], "energy": E4,
-                                       "rel_energy_diff_vs_main": abs(E4 - E) / abs(E)}
+                                       "rel_energy_diff_vs_main": abs(E4 - E) / abs(E),
+                                       "vs_oracle": errors_vs_oracle(w.name, E4, inf4[-1], keep4["phi"], F4, torch)}
             s4.close()
             print(f"# mixed with float32 dry update: {1e3 * sec4:.2f} ms/step", file=sys.stderr, flush=True)
         we = make_workload(args.workload, not args.exclusion)
         s3 = solver_for(we, args.precision, torch)
-        sec3, E3, inf3, _, _ = run_steps(s3, we, max(2, args.steps // 2), 1, torch)
+        keep3 = {}
+        sec3, E3, inf3, F3, _ = run_steps(s3, we, max(2, args.steps // 2), 1, torch, keep=keep3)
         extra["exclusion" if not args.exclusion else "no_exclusion"] = {
             "steps_per_s": round(1.0 / sec3, 3), "ms_per_step": round(1e3 * sec3, 2),
-            "iters": inf3[-1]["outer_iters"], "energy": E3, "z_wet": list(we.z_wet)}
+            "iters": inf3[-1]["outer_iters"], "energy": E3, "z_wet": list(we.z_wet),
+            "vs_oracle": errors_vs_oracle(we.name, E3, inf3[-1], keep3["phi"], F3, torch)}
         s3.close()
         print(f"# other mode: {1e3 * sec3:.2f} ms/step", file=sys.stderr, flush=True)
+        if not args.exclusion:
+            extra["coupling_variants"] = coupling_variants(w, args.precision, torch)
+            print(f"# coupling variants: {extra['coupling_variants']}", file=sys.stderr, flush=True)
 
     if not args.no_compare and args.md_steps > 0:
         wb = W.big_slab(exclusion=args.exclusion, tol=1e-8)
@@ -461,10 +557,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        gi = golden_iters(w.name if not args.exclusion else w.name)
-        if gi is None:
-            gi = 130
-        cpu = cpu_baseline(w, gi)
+        cpu = cpu_baseline(w)
         if "sixth_order_192x192x384" in extra:
             dd = extra["density_eps_192x192x384"]
             gpu_ms = {"gamma_build": extra["gamma_eps_192x192x384"]["eps_build_ms"],
@@ -482,7 +575,8 @@ def main():
                                f"{'exclusion rule' if args.exclusion else 'literal product-erf eps'}, "
                                f"dry z<{w.z_wet[0]:.2f} A, tol 1e-8, cold start",
                    "grid": list(w.n), "precision": args.precision, "step": "build_eps+build_rho+solve+adjoint+forces"},
-        "solve_iters": iters[-1], "solve_ms_median": round(solve_ms, 3), "energy": E,
+        "solve_iters": iters[-1], "solve_ms_median": round(solve_ms, 3), "solve_phases_ms": phases,
+        "energy": E, "vs_oracle": err_main,
         "smoother_hbm_gbs": smoother_gbs, "kernels": kernels,
         "roofline": roof, "cpu_baseline": cpu, "compare": extra,
     }

@@ -72,7 +72,10 @@ typedef struct {
     int pre, post;         /* red-black Gauss-Seidel sweeps per V-cycle level  */
     int coarse_sweeps;     /* sweeps on the coarsest level                     */
     int max_levels;        /* upper bound on multigrid levels (>= 1)           */
-    int cycles;            /* V-cycles per application of the split            */
+    int cycles;            /* V-cycles per application of the split (0..64;    */
+                           /* 0: no wet correction, the split is the FFT dry   */
+                           /* update alone; many: the wet solve converges and  */
+                           /* one application is the paper's one-pass scheme)  */
     int scaled_dry;        /* 1: dry update s * L^-1 (s * r), s = eps^-1/2     */
     double tol;            /* stop at ||b - A phi||_2 <= tol ||b||_2           */
     int max_outer;         /* cap on preconditioned Krylov iterations          */
@@ -119,6 +122,13 @@ typedef struct {
     double mean_rho_removed; /* mean of rho that was projected out            */
     double t_total_ms;       /* wall time of the solve                         */
     double background;       /* order 6: c = mean(b - A6 phi); order 2: 0      */
+    /* Device time of the solve's phases, from HIP events recorded on the   */
+    /* context stream at the phase boundaries of every Krylov step:         */
+    double t_fft_ms;         /* the FFT dry updates (Eq. 15 on the grid)       */
+    double t_mg_ms;          /* wet residual, V-cycles and the combination     */
+    double t_krylov_ms;      /* operator applications, Gram-Schmidt, restarts  */
+                             /* (together: the solve from its first residual   */
+                             /* to its last update, setup and energy excluded) */
 } dwp_info;
 
 /* Permittivity built from the atoms (dwp_build_epsilon), two models.
@@ -232,6 +242,26 @@ int dwp_build_rho(dwp_ctx *ctx, int n, const double *xyz_host, const double *q_h
  * with the best iterate in phi_dev if max_outer is reached. */
 int dwp_solve(dwp_ctx *ctx, const double *rho_dev, double *phi_dev, double *energy_host,
               dwp_info *info);
+
+/* Vector-Jacobian product of the map (rho, eps) -> (phi, E) of dwp_solve at
+ * its solution, for the symmetric second-order operator (order 2; order 6
+ * gives DWP_EINVAL): given the cotangents g_E of E and g_phi of phi,
+ *   grad_rho = g_E h^3 phi - 4 pi lambda,
+ *   grad_eps_n = sum_d 1/2 [(D+_d u)_n (D+_d phi)_n + (D-_d u)_n (D-_d phi)_n],
+ *   u = lambda - g_E (h^3 / 8 pi) phi,
+ * where lambda is the zero-mean solution of A lambda = g_phi - mean(g_phi)
+ * (the adjoint problem of Eq. 3; A is symmetric), solved by the same coupled
+ * FFT/multigrid iteration with the current options, from zero.  The g_E
+ * terms are dE/d rho (Sec. II.C) and dE/d eps (first term of Eq. 11); the
+ * lambda terms the derivative of a loss through phi.  phi_dev must be the
+ * solution of the current eps (the caller keeps it; the library reads it),
+ * g_phi_dev may be NULL (lambda = 0), grad_rho_dev and grad_eps_dev receive
+ * N doubles each.  Does not change the state dwp_eps_gradient, dwp_forces
+ * and dwp_v_eps read (the last solution), only scratch buffers.  *info
+ * (nullable) reports the adjoint solve; DWP_ENOCONV if it misses the
+ * tolerance (outputs written from the best iterate). */
+int dwp_backward(dwp_ctx *ctx, const double *phi_dev, double g_E, const double *g_phi_dev,
+                 double *grad_rho_dev, double *grad_eps_dev, dwp_info *info);
 
 /* dE/d eps_n = -(h^3 / 8 pi) sum_d 1/2 [(D+_d phi)_n^2 + (D-_d phi)_n^2] for
  * the last solution (the discrete first term of Eq. 11).  N doubles.  With

@@ -3,11 +3,13 @@
 DielectricPoisson: (rho, eps) -> (phi, E) for a solver whose grid is set.
   E = 1/2 h^3 sum rho phi (the Hartree energy of Sec. II.C); phi the zero-mean
   solution of A(eps) phi = -4 pi (rho - mean rho).
-  Backward (Eq. 11 and App. A-B in discrete form):
-    dE/drho = h^3 phi,   dE/deps = -(h^3/8 pi) sum_d 1/2[(D+ phi)^2 + (D- phi)^2]
-  (the hand-written adjoint kernel), and for a gradient g_phi flowing into phi
-  one adjoint solve A lam = P g_phi (A is symmetric; P removes the mean):
-    dL/drho = -4 pi lam,  dL/deps_n = sum_d 1/2[(D+ lam)(D+ phi) + (D- lam)(D- phi)].
+  Backward (Eq. 11 and App. A-B in discrete form) is one library call,
+  dwp_backward: dE/drho = h^3 phi, dE/deps from the hand-written adjoint
+  kernel, and for a gradient g_phi flowing into phi one adjoint solve
+  A lam = P g_phi (A is symmetric; P removes the mean) with
+  dL/drho = -4 pi lam and dL/deps from the face-product kernel.  The forward
+  pass's permittivity, options and phi are kept, so a later forward call or
+  set_epsilon on the same solver does not change the gradients.
 
 SlabEnergy: atom positions -> E for the atom-built permittivity and Gaussian
   charges; backward = dE/dR from the library's force kernel, the permittivity
@@ -17,8 +19,6 @@ SlabEnergy: atom positions -> E for the atom-built permittivity and Gaussian
 Every step runs in libdwp; this module only moves tensors and scalars.
 """
 from __future__ import annotations
-
-import math
 
 import numpy as np
 import torch
@@ -30,29 +30,32 @@ class DielectricPoisson(torch.autograd.Function):
         if solver.opts.order != 2:
             raise ValueError("DielectricPoisson's backward relies on a symmetric operator: use order = 2 "
                              "(the sixth-order operator's gradients come from eps_gradient and forces)")
-        solver.set_epsilon(eps.detach().contiguous())
+        eps_c = eps.detach().contiguous()
+        solver.set_epsilon(eps_c)
         phi, E, info = solver.solve(rho.detach().contiguous())
         ctx.solver = solver
-        ctx.save_for_backward(phi)
+        ctx.epoch = solver.epoch
+        ctx.opts = bytes(solver.opts)
+        ctx.save_for_backward(phi, eps_c)
         return phi.clone(), torch.tensor(E, dtype=torch.float64, device=rho.device)
 
     @staticmethod
     def backward(ctx, g_phi, g_E):
-        (phi,) = ctx.saved_tensors
+        phi, eps = ctx.saved_tensors
         s = ctx.solver
-        h3 = float(np.prod(s.h))
-        grad_rho = torch.zeros_like(phi)
-        grad_eps = torch.zeros_like(phi)
-        if g_E is not None:
-            ge = float(g_E)
-            if ge != 0.0:
-                grad_rho += ge * h3 * phi
-                grad_eps += ge * s.eps_pair_gradient(phi, phi, -h3 / (8.0 * math.pi))
-        if g_phi is not None and bool(torch.any(g_phi != 0)):
-            # A lam = P g_phi  <=>  solve with rho' = -g_phi / (4 pi)
-            lam, _, _ = s.solve((-g_phi / (4.0 * math.pi)).contiguous())
-            grad_rho += -4.0 * math.pi * lam
-            grad_eps += s.eps_pair_gradient(lam, phi, 1.0)
+        if s.epoch != ctx.epoch or bytes(s.opts) != ctx.opts:
+            # the solver was used for something else since the forward pass:
+            # restore the forward's options and permittivity
+            saved = type(s.opts).from_buffer_copy(ctx.opts)
+            s.set_opts(**{k: getattr(saved, k) for k, _ in saved._fields_})
+            s.set_epsilon(eps)
+            ctx.epoch = s.epoch
+        ge = 0.0 if g_E is None else float(g_E)
+        if g_phi is not None and not bool(torch.any(g_phi != 0)):
+            g_phi = None
+        if g_phi is not None:
+            g_phi = g_phi.detach().to(torch.float64).contiguous()
+        grad_rho, grad_eps, _ = s.backward(phi, ge, g_phi)
         return grad_rho, grad_eps, None
 
 

@@ -41,7 +41,8 @@ class Info(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("vcycles", C.c_int), ("restarts", C.c_int), ("k_w0", C.c_int),
                 ("k_w1", C.c_int), ("n_levels", C.c_int), ("rel_res", C.c_double), ("energy", C.c_double),
                 ("energy_eps_form", C.c_double), ("mean_rho_removed", C.c_double), ("t_total_ms", C.c_double),
-                ("background", C.c_double)]
+                ("background", C.c_double), ("t_fft_ms", C.c_double), ("t_mg_ms", C.c_double),
+                ("t_krylov_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -69,6 +70,7 @@ _SIGNATURES = {
     "dwp_v_eps": (C.c_int, [_P, C.c_int, _P]),
     "dwp_build_rho": (C.c_int, [_P, C.c_int, _D, _D, _D, _P]),
     "dwp_solve": (C.c_int, [_P, _P, _P, _D, C.POINTER(Info)]),
+    "dwp_backward": (C.c_int, [_P, _P, C.c_double, _P, _P, _P, C.POINTER(Info)]),
     "dwp_eps_gradient": (C.c_int, [_P, _P]),
     "dwp_eps_pair_gradient": (C.c_int, [_P, _P, _P, C.c_double, _P]),
     "dwp_forces": (C.c_int, [_P, C.c_int, _D, _D, _D, _D, C.POINTER(EpsParams), _D]),
@@ -150,6 +152,7 @@ class Solver:
         self.n = None
         self.L = None
         self.opts = None
+        self.epoch = 0  # bumped by every call that changes the grid, the options or eps
 
     def close(self):
         if getattr(self, "_h", None):
@@ -192,12 +195,14 @@ class Solver:
         return self._torch.empty(self.shape, dtype=self._torch.float64, device=self.device)
 
     def set_grid(self, n, L, **opts):
+        self.epoch += 1
         o = default_opts(**opts)
         self._check(lib().dwp_set_grid(self._h, int(n[0]), int(n[1]), int(n[2]), float(L[0]), float(L[1]),
                                        float(L[2]), C.byref(o)))
         self.n, self.L, self.opts = tuple(int(x) for x in n), tuple(float(x) for x in L), o
 
     def set_opts(self, **opts):
+        self.epoch += 1
         o = Opts()
         C.memmove(C.byref(o), C.byref(self.opts), C.sizeof(Opts))
         for k, v in opts.items():
@@ -208,9 +213,11 @@ class Solver:
         self.opts = o
 
     def set_epsilon(self, eps):
+        self.epoch += 1
         self._check(lib().dwp_set_epsilon(self._h, self._dev(eps, "eps")))
 
     def build_epsilon(self, xyz, radius, params):
+        self.epoch += 1
         x, xp = _hostd(xyz)
         r, rp = _hostd(radius)
         ep = eps_params(params)
@@ -218,6 +225,7 @@ class Solver:
 
     def build_epsilon_density(self, rho, eps_inf, rho0, beta):
         """eps from an electron-density grid (Eq. 7); keeps d eps/d rho for v_eps."""
+        self.epoch += 1
         self._check(lib().dwp_build_epsilon_density(self._h, self._dev(rho, "rho"), float(eps_inf), float(rho0),
                                                     float(beta)))
 
@@ -241,15 +249,30 @@ class Solver:
         return out
 
     def solve(self, rho, phi=None, allow_noconv=False):
-        """Returns (phi, E, info dict).  With opts.warm_start, phi is the guess."""
+        """Returns (phi, E, info dict).  With opts.warm_start, phi is the guess
+        (a new phi starts from zero)."""
         if phi is None:
-            phi = self.empty()
+            phi = self._torch.zeros(self.shape, dtype=self._torch.float64, device=self.device)
         e = C.c_double()
         info = Info()
         st = lib().dwp_solve(self._h, self._dev(rho, "rho"), self._dev(phi, "phi"), C.byref(e), C.byref(info))
         if not (allow_noconv and st == DWP_ENOCONV):
             self._check(st)
         return phi, e.value, info.as_dict()
+
+    def backward(self, phi, g_E, g_phi=None, grad_rho=None, grad_eps=None, allow_noconv=False):
+        """(grad_rho, grad_eps, info) of the map (rho, eps) -> (phi, E) at the
+        solution phi of the current eps, for cotangents g_E (float) and g_phi
+        (tensor or None); the adjoint solve runs in the library."""
+        grad_rho = self.empty() if grad_rho is None else grad_rho
+        grad_eps = self.empty() if grad_eps is None else grad_eps
+        gp = None if g_phi is None else self._dev(g_phi, "g_phi")
+        info = Info()
+        st = lib().dwp_backward(self._h, self._dev(phi, "phi"), float(g_E), gp, self._dev(grad_rho, "grad_rho"),
+                                self._dev(grad_eps, "grad_eps"), C.byref(info))
+        if not (allow_noconv and st == DWP_ENOCONV):
+            self._check(st)
+        return grad_rho, grad_eps, info.as_dict()
 
     def eps_gradient(self, out=None):
         out = self.empty() if out is None else out

@@ -127,6 +127,23 @@ struct Profiler {
 
 const char *prof_group_name(int g);
 
+// Phase timers of a solve: an event is recorded on the stream where a phase
+// begins; the time from one mark to the next is charged to the earlier mark's
+// phase.
+enum SolvePhase { PH_FFT = 0, PH_MG, PH_KRYLOV, PH_COUNT };
+
+struct PhaseTimer {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<int> phase;       // phase of each recorded mark
+    size_t used = 0;
+    void start();
+    void mark(hipStream_t s, int ph);
+    // after a stream sync: ms[PH_COUNT] from the recorded marks; stops
+    void finish(double *ms);
+    ~PhaseTimer();
+};
+
 }  // namespace dwp
 
 struct dwp_ctx {
@@ -165,6 +182,8 @@ struct dwp_ctx {
     bool transposed = false;      // the Krylov solve in progress is the adjoint one
     int fft_order = 0;            // order the FFT symbol tables were built for
     double background = 0.0;      // uniform background of the last order-6 solve
+    dwp::PhaseTimer phases;       // phase timers of the solve in progress
+    dwp::DevBuf bw_rhs, bw_lam;   // adjoint right-hand side and solution of dwp_backward
 };
 
 namespace dwp {
@@ -191,6 +210,8 @@ void launch_scale_dev(hipStream_t s, double *x, const double *num, const double 
 void launch_rhs(hipStream_t s, const double *rho, const double *sum, double inv_n, double *b, size_t n);
 void launch_sub_mean(hipStream_t s, double *x, const double *sum, double inv_n, size_t n);
 void launch_mul(hipStream_t s, double *y, const double *a, const double *x, size_t n);
+// out = a x + b y (y == nullptr: out = a x)
+void launch_axpby(hipStream_t s, double *out, double a, const double *x, double b, const double *y, size_t n);
 void launch_rsqrt(hipStream_t s, const double *eps, double *sinv, size_t n);
 void launch_check_eps(hipStream_t s, const double *eps, size_t n, int *flags);
 void launch_check_finite(hipStream_t s, const double *x, size_t n, int *flags);

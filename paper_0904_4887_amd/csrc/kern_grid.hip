@@ -308,6 +308,10 @@ __global__ void k_mul(double *y, const double *a, const double *x, size_t n) {
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
         y[t] = a[t] * x[t];
 }
+__global__ void k_axpby(double *out, double a, const double *x, double b, const double *y, size_t n) {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        out[t] = y ? a * x[t] + b * y[t] : a * x[t];
+}
 __global__ void k_rsqrt(const double *eps, double *s, size_t n) {
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
         s[t] = 1.0 / sqrt(eps[t]);
@@ -1046,6 +1050,10 @@ void launch_sub_mean(hipStream_t s, double *x, const double *sum, double inv_n, 
 }
 void launch_mul(hipStream_t s, double *y, const double *a, const double *x, size_t n) {
     k_mul<<<grid1d(n), 256, 0, s>>>(y, a, x, n);
+    DWP_LAUNCH_CHECK();
+}
+void launch_axpby(hipStream_t s, double *out, double a, const double *x, double b, const double *y, size_t n) {
+    k_axpby<<<grid1d(n), 256, 0, s>>>(out, a, x, b, y, n);
     DWP_LAUNCH_CHECK();
 }
 void launch_rsqrt(hipStream_t s, const double *eps, double *sinv, size_t n) {

@@ -88,6 +88,40 @@ Profiler::~Profiler() {
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
 }
 
+void PhaseTimer::start() {
+    on = true;
+    used = 0;
+    phase.clear();
+}
+
+void PhaseTimer::mark(hipStream_t s, int ph) {
+    if (!on) return;
+    if (used == pool.size()) {
+        hipEvent_t e;
+        DWP_HIP(hipEventCreate(&e));
+        pool.push_back(e);
+    }
+    DWP_HIP(hipEventRecord(pool[used], s));
+    phase.push_back(ph);
+    ++used;
+}
+
+void PhaseTimer::finish(double *ms) {
+    for (int q = 0; q < PH_COUNT; ++q) ms[q] = 0.0;
+    for (size_t i = 0; i + 1 < used; ++i) {
+        float t = 0.f;
+        DWP_HIP(hipEventElapsedTime(&t, pool[i], pool[i + 1]));
+        ms[phase[i]] += t;
+    }
+    on = false;
+    used = 0;
+    phase.clear();
+}
+
+PhaseTimer::~PhaseTimer() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
 #define PROF(c, group, nbytes, stmt)                                \
     do {                                                           \
         const int ev_ = (c)->prof.begin((c)->stream, (group));      \
@@ -202,9 +236,13 @@ void plan_wet(dwp_ctx *c) {
         L->plane = (size_t)d.nx * d.ny;
         p.levels.push_back(L);
     }
-    // the bottom kernel takes every level from the first one that fits
+    // the bottom kernel takes every level from the first one that fits; a
+    // coarsest level too large for one workgroup (x or y could not be halved
+    // further) is smoothed by the grid-wide level kernels instead
     p.bottom = p.levels.size() - 1;
-    while (p.bottom > 0 && p.levels[p.bottom - 1]->n_interior() <= BOTTOM_MAX_POINTS) --p.bottom;
+    if (p.levels.back()->n_interior() > BOTTOM_MAX_POINTS) p.bottom = p.levels.size();
+    while (p.bottom > 0 && p.bottom < p.levels.size() && p.levels[p.bottom - 1]->n_interior() <= BOTTOM_MAX_POINTS)
+        --p.bottom;
     if (p.levels.size() - p.bottom > 10) p.bottom = p.levels.size() - 10;
 }
 
@@ -283,7 +321,12 @@ void vcycle(dwp_ctx *c, size_t l, bool u_unset) {
     const int sg = l == 0 ? PG_RBGS_FINE : PG_RBGS_COARSE;
     const double pass_bytes = 2.0 * ts * (double)L.n_interior();  // half of read u, eps, f + write u
     const bool fused = c->opts.smoother == 1 && L.n_interior() >= FUSED_MIN_POINTS;
-    if (u_unset && !(fused && c->opts.pre > 0))
+    const bool coarsest = l + 1 == p.levels.size();
+    // the first sweep starts from a zero correction on coarse levels and in
+    // the first cycle on the fine level, except that without pre-sweeps it
+    // comes after the coarse-grid correction (then its input is not zero)
+    bool zero_in = (l > 0 || u_unset) && (coarsest || c->opts.pre > 0);
+    if (u_unset && !(fused && zero_in))
         PROF(c, PG_WET, ts * (double)L.n_ghosted(), launch_zero<T>(s, L.u.as<T>(), L.n_ghosted()));
     if (l >= p.bottom) {
         double nb = 0.0;
@@ -292,10 +335,6 @@ void vcycle(dwp_ctx *c, size_t l, bool u_unset) {
              launch_vcycle_bottom<T>(s, p.levels, l, c->opts.pre, c->opts.post, c->opts.coarse_sweeps));
         return;
     }
-    // the first pre-sweep starts from a zero correction on coarse levels and
-    // in the first cycle on the fine level; without pre-sweeps the first sweep
-    // comes after the coarse-grid correction, so its input is not zero
-    bool zero_in = (l > 0 || u_unset) && c->opts.pre > 0;
     auto smooth = [&](int first) {
         if (fused) {
             const double b = zero_in ? 1.5 * pass_bytes : 2.0 * pass_bytes;
@@ -307,6 +346,10 @@ void vcycle(dwp_ctx *c, size_t l, bool u_unset) {
         }
         zero_in = false;
     };
+    if (coarsest) {  // too large for the bottom kernel: coarse_sweeps sweeps here
+        for (int k = 0; k < c->opts.coarse_sweeps; ++k) smooth(0);
+        return;
+    }
     for (int k = 0; k < c->opts.pre; ++k) smooth(0);
     Level &C = *p.levels[l + 1];
     PROF(c, PG_MG_OTHER, 4.0 * ts * L.n_interior(), launch_level_residual<T>(s, L, L.r.as<T>()));
@@ -322,8 +365,14 @@ void split_impl(dwp_ctx *c, const double *v, double *z) {
     Plan &p = c->plan;
     hipStream_t s = c->stream;
     const bool scaled = c->opts.scaled_dry != 0;
+    c->phases.mark(s, PH_FFT);
     launch_vacuum_solve(s, p, c->fx, c->fy, c->fz, v, scaled ? c->sinv.as<double>() : nullptr, c->cbuf.p, z,
                         &c->prof, c->opts.fft_fp32 != 0);
+    c->phases.mark(s, PH_MG);
+    if (c->opts.cycles == 0) {  // no wet correction: the split is the dry update alone
+        c->phases.mark(s, PH_KRYLOV);
+        return;
+    }
     Level &F = *p.levels[0];
     const double nW = (double)F.n_interior();
     if (c->opts.order == 6)
@@ -335,6 +384,7 @@ void split_impl(dwp_ctx *c, const double *v, double *z) {
              launch_wet_residual<T>(s, p, v, z, c->eps.as<double>(), F.f.as<T>()));
     for (int k = 0; k < c->opts.cycles; ++k) vcycle<T>(c, 0, k == 0);
     PROF(c, PG_WET, (16.0 + sizeof(T)) * nW, launch_wet_add<T>(s, p, F.u.as<T>(), z));
+    c->phases.mark(s, PH_KRYLOV);
 }
 
 void apply_split(dwp_ctx *c, const double *v, double *z) {
@@ -525,7 +575,7 @@ void validate_opts(const dwp_opts &o) {
         fail(DWP_EINVAL, "pre/post sweeps out of range");
     if (o.coarse_sweeps < 1 || o.coarse_sweeps > 100000) fail(DWP_EINVAL, "coarse_sweeps out of range");
     if (o.max_levels < 1 || o.max_levels > 32) fail(DWP_EINVAL, "max_levels out of range");
-    if (o.cycles < 1 || o.cycles > 16) fail(DWP_EINVAL, "cycles out of range");
+    if (o.cycles < 0 || o.cycles > 64) fail(DWP_EINVAL, "cycles out of range");
     if (!(o.tol > 0.0) || !(o.tol < 1.0)) fail(DWP_EINVAL, "tol must lie in (0, 1)");
     if (o.max_outer < 1) fail(DWP_EINVAL, "max_outer must be >= 1");
     if (o.restart < 1 || o.restart > 63) fail(DWP_EINVAL, "restart must lie in [1, 63]");
@@ -778,8 +828,19 @@ void solve_impl(dwp_ctx *c, const double *rho, double *phi, double *energy, dwp_
     int iters = 0, restarts = 0;
     double rel = 0.0;
     int status = DWP_OK;
+    double t_ph[PH_COUNT] = {0.0, 0.0, 0.0};
     if (bnorm > 0.0) {
-        iters = fgmres(c, c->b.as<double>(), bnorm, phi, &restarts, &rel);
+        c->phases.start();
+        c->phases.mark(s, PH_KRYLOV);
+        try {
+            iters = fgmres(c, c->b.as<double>(), bnorm, phi, &restarts, &rel);
+        } catch (...) {
+            c->phases.on = false;
+            throw;
+        }
+        c->phases.mark(s, PH_KRYLOV);
+        sync(c);
+        c->phases.finish(t_ph);
         if (rel > c->opts.tol) status = DWP_ENOCONV;
     } else {
         launch_fill(s, phi, 0.0, N);
@@ -818,6 +879,9 @@ void solve_impl(dwp_ctx *c, const double *rho, double *phi, double *energy, dwp_
         info->background = c->background;
         info->t_total_ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        info->t_fft_ms = t_ph[PH_FFT];
+        info->t_mg_ms = t_ph[PH_MG];
+        info->t_krylov_ms = t_ph[PH_KRYLOV];
     }
     if (status != DWP_OK) fail(status, "tolerance not reached within max_outer iterations");
 }
@@ -862,6 +926,84 @@ void ensure_adjoint(dwp_ctx *c) {
         launch_sub_mean(s, c->lam.as<double>(), coef + 408, 1.0 / (double)N, N);
     }
     c->have_adjoint = true;
+}
+
+// Vector-Jacobian product of (rho, eps) -> (phi, E) at the solution phi of
+// the current eps (order 2).  The adjoint problem A lambda = g_phi - mean
+// runs through the same FGMRES as the solve, on buffers of its own, so the
+// last solution (phi_last, b) stays what dwp_solve left.
+void backward_impl(dwp_ctx *c, const double *phi, double gE, const double *gphi, double *grad_rho,
+                   double *grad_eps, dwp_info *info) {
+    need_eps(c);
+    if (c->opts.order != 2) fail(DWP_EINVAL, "dwp_backward needs the symmetric second-order operator (order 2)");
+    if (!phi || !grad_rho || !grad_eps) fail(DWP_EINVAL, "phi_dev, grad_rho_dev and grad_eps_dev must not be NULL");
+    if (!std::isfinite(gE)) fail(DWP_EINVAL, "g_E must be finite");
+    Plan &p = c->plan;
+    hipStream_t s = c->stream;
+    const size_t N = p.N;
+    double *coef = c->coef.as<double>();
+    double *part = c->partial.as<double>();
+    const auto t0 = std::chrono::steady_clock::now();
+    check_finite_dev(c, phi, "phi");
+    const double h3 = p.h[0] * p.h[1] * p.h[2];
+    const double four_pi = 4.0 * 3.14159265358979323846;
+    int iters = 0, restarts = 0, status = DWP_OK;
+    double rel = 0.0;
+    double t_ph[PH_COUNT] = {0.0, 0.0, 0.0};
+    const double *lam = nullptr;
+    if (gphi) {
+        check_finite_dev(c, gphi, "g_phi");
+        c->bw_rhs.alloc(sizeof(double) * N);
+        c->bw_lam.alloc(sizeof(double) * N);
+        double *rhs = c->bw_rhs.as<double>(), *x = c->bw_lam.as<double>();
+        launch_sum(s, gphi, N, part, coef + 420);
+        launch_axpby(s, rhs, 1.0, gphi, 0.0, nullptr, N);
+        launch_sub_mean(s, rhs, coef + 420, 1.0 / (double)N, N);
+        launch_dot(s, rhs, rhs, N, part, coef + 421);
+        to_host(c, coef + 421, 1);
+        const double bnorm = std::sqrt(c->host[0]);
+        launch_fill(s, x, 0.0, N);
+        if (bnorm > 0.0) {
+            c->phases.start();
+            c->phases.mark(s, PH_KRYLOV);
+            try {
+                iters = fgmres(c, rhs, bnorm, x, &restarts, &rel);
+            } catch (...) {
+                c->phases.on = false;
+                throw;
+            }
+            c->phases.mark(s, PH_KRYLOV);
+            sync(c);
+            c->phases.finish(t_ph);
+            if (rel > c->opts.tol) status = DWP_ENOCONV;
+            launch_sum(s, x, N, part, coef + 422);
+            launch_sub_mean(s, x, coef + 422, 1.0 / (double)N, N);
+        }
+        lam = x;
+    }
+    // grad_rho = g_E h^3 phi - 4 pi lambda
+    launch_axpby(s, grad_rho, gE * h3, phi, -four_pi, lam, N);
+    // grad_eps = G(u, phi), u = lambda - g_E h^3 / (8 pi) phi (G is bilinear)
+    double *u = c->w.as<double>();
+    launch_axpby(s, u, -gE * h3 / (2.0 * four_pi), phi, 1.0, lam, N);
+    PROF(c, PG_FORCES, 24.0 * N, launch_eps_pair(s, p, u, phi, 1.0, grad_eps));
+    sync(c);
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->outer_iters = iters;
+        info->vcycles = iters * c->opts.cycles;
+        info->restarts = restarts;
+        info->k_w0 = p.k_w0;
+        info->k_w1 = p.k_w1;
+        info->n_levels = (int)p.levels.size();
+        info->rel_res = rel;
+        info->t_total_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        info->t_fft_ms = t_ph[PH_FFT];
+        info->t_mg_ms = t_ph[PH_MG];
+        info->t_krylov_ms = t_ph[PH_KRYLOV];
+    }
+    if (status != DWP_OK) fail(status, "adjoint solve: tolerance not reached within max_outer iterations");
 }
 
 // dE/d eps for the last solution, for the operator of the options
@@ -1052,6 +1194,14 @@ int dwp_solve(dwp_ctx *c, const double *rho, double *phi, double *energy, dwp_in
     ABI_BEGIN(c)
     DWP_HIP(hipSetDevice(c->device));
     dwp::solve_impl(c, rho, phi, energy, info);
+    ABI_END(c)
+}
+
+int dwp_backward(dwp_ctx *c, const double *phi, double gE, const double *gphi, double *grad_rho,
+                 double *grad_eps, dwp_info *info) {
+    ABI_BEGIN(c)
+    DWP_HIP(hipSetDevice(c->device));
+    dwp::backward_impl(c, phi, gE, gphi, grad_rho, grad_eps, info);
     ABI_END(c)
 }
 

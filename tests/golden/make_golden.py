@@ -34,7 +34,20 @@ def workloads():
         "slab_gamma_192x192x384": W.slab_gamma((192, 192, 384)),
         "slab_gamma_192x192x384_excl": W.slab_gamma((192, 192, 384), exclusion=True),
         "slab6_96x96x192": W.slab((96, 96, 192), tol=1e-10),
+        "big_slab_256x256x512_md3": md_workload(W.big_slab(), 3),
     }
+
+
+def md_workload(w, steps):
+    """The workload after `steps` MD-like displacements: R += N(0, 0.02 A) per
+    step, cumulative, the same draws as the warm-started MD loop."""
+    disp = W.md_displacements(len(w.q), steps + 1)
+    xyz = w.xyz.copy()
+    for t in range(1, steps + 1):
+        xyz = np.mod(xyz + disp[t], np.array(w.L))
+    w.xyz = xyz
+    w.name = f"{w.name}_md{steps}"
+    return w
 
 
 def first_below(history, tol):

@@ -32,7 +32,7 @@ def test_plan_rejects_bad_grid_sizes(n):
 
 
 @pytest.mark.parametrize("kw", [dict(precision=2), dict(tol=0.0), dict(tol=1.5), dict(restart=0),
-                                dict(restart=64), dict(cycles=0), dict(pre=0, post=0), dict(max_outer=0),
+                                dict(restart=64), dict(cycles=-1), dict(cycles=65), dict(pre=0, post=0), dict(max_outer=0),
                                 dict(z_wet_lo=8.0, z_wet_hi=8.5), dict(z_wet_lo=0.0, z_wet_hi=20.0),
                                 dict(profile=3), dict(scaled_dry=3), dict(fft_fp32=2),
                                 dict(fft_fp32=1, precision=0), dict(smoother=2), dict(order=4)])

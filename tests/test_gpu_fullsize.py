@@ -17,13 +17,16 @@ from paper_0904_4887_amd import workloads as W
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
-# name -> (workload, E tol, phi tol (x max|phi| at the samples), force tol (x max|F|))
+# name -> (workload, E tol, phi tol (x max|phi| at the samples), force tol (x max|F|)[, stored result])
 CASES = {
     "tanh_box_32x32x64": (lambda: W.tanh_box(), 1e-10, 1e-8, None),
     "slab_96x96x192": (lambda: W.slab((96, 96, 192)), 1e-10, 1e-8, 1e-7),
     "slab_96x96x192_excl": (lambda: W.slab((96, 96, 192), exclusion=True), 1e-10, 1e-8, 1e-7),
     "slab_128x128x256": (lambda: W.slab((128, 128, 256), tol=1e-12), 1e-10, 1e-9, 1e-8),
     "slab_192x192x384": (lambda: W.slab((192, 192, 384), tol=1e-8, precision=1), 1e-8, 1e-6, 1e-5),
+    # the same slab solved entirely in float64 at the same tolerance
+    "slab_192x192x384_fp64": (lambda: W.slab((192, 192, 384), tol=1e-8, precision=0), 1e-8, 1e-6, 1e-5,
+                              "slab_192x192x384"),
     "slab_192x192x384_excl": (lambda: W.slab((192, 192, 384), exclusion=True, tol=1e-8, precision=1),
                               1e-8, 1e-6, 1e-5),
     "big_slab_256x256x512": (lambda: W.big_slab(), 1e-8, 1e-6, 1e-5),
@@ -35,12 +38,14 @@ CASES = {
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_full_size_matches_stored_oracle(name):
-    path = os.path.join(GOLDEN, f"oracle_{name}.json")
+    case = CASES[name]
+    make, tol_E, tol_phi, tol_F = case[:4]
+    stored = case[4] if len(case) > 4 else name
+    path = os.path.join(GOLDEN, f"oracle_{stored}.json")
     if not os.path.exists(path):
-        pytest.skip(f"no stored oracle result for {name}")
+        pytest.skip(f"no stored oracle result for {stored}")
     import torch
     from paper_0904_4887_amd.binding import Solver
-    make, tol_E, tol_phi, tol_F = CASES[name]
     w = make()
     with open(path) as f:
         ref = json.load(f)
@@ -73,4 +78,44 @@ def test_full_size_matches_stored_oracle(name):
         F = s.forces(w.xyz, w.q, w.sigma, None if density else w.radius, None if density else w.eps_params)
         F_ref = np.array(ref["forces"])
         assert np.abs(F - F_ref).max() <= tol_F * np.abs(F_ref).max()
+    s.close()
+
+
+def test_big_slab_md_steps_match_stored_oracle():
+    """The 256 x 256 x 512 slab through the warm-started MD loop: a cold solve
+    at the initial atoms, then three steps of cumulative N(0, 0.02 A)
+    displacements, each solved from the previous phi; after the third step
+    the energy, phi at the stored nodes and dE/dR match the oracle's solution
+    at the displaced positions."""
+    path = os.path.join(GOLDEN, "oracle_big_slab_256x256x512_md3.json")
+    if not os.path.exists(path):
+        pytest.skip("no stored oracle result for big_slab_256x256x512_md3")
+    import torch
+    from paper_0904_4887_amd.binding import Solver
+    with open(path) as f:
+        ref = json.load(f)
+    w = W.big_slab()
+    s = Solver(0)
+    s.set_grid(w.n, w.L, **w.solver_opts())
+    disp = W.md_displacements(len(w.q), 4)
+    xyz = w.xyz.copy()
+    rho, phi = s.empty(), s.empty().zero_()
+    iters = []
+    for t in range(4):
+        if t:
+            xyz = np.mod(xyz + disp[t], np.array(w.L))
+        s.set_opts(warm_start=1 if t else 0)
+        s.build_epsilon(xyz, w.radius, w.eps_params)
+        s.build_rho(xyz, w.q, w.sigma, out=rho)
+        _, E, info = s.solve(rho, phi)
+        assert info["rel_res"] <= w.tol
+        iters.append(info["outer_iters"])
+    assert abs(E - ref["energy"]) <= 1e-8 * abs(ref["energy"]), (E, ref["energy"])
+    nodes = torch.from_numpy(np.array(ref["nodes"])).cuda()
+    ref_phi = np.array(ref["phi"])
+    assert np.abs(phi.reshape(-1)[nodes].cpu().numpy() - ref_phi).max() <= 1e-6 * np.abs(ref_phi).max()
+    F = s.forces(xyz, w.q, w.sigma, w.radius, w.eps_params)
+    F_ref = np.array(ref["forces"])
+    assert np.abs(F - F_ref).max() <= 1e-5 * np.abs(F_ref).max()
+    assert max(iters[1:]) <= iters[0]  # the warm start never costs iterations
     s.close()

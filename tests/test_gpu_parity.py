@@ -217,3 +217,28 @@ def test_fused_sweep_equals_colour_passes(torch, precision, cycles, pre, post):
     s.set_opts(smoother=0)
     z0 = _host(s.apply_split(r))
     assert _rel(z1, z0) <= (1e-12 if precision == 0 else 2e-5)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("n", [(216, 216, 48), (162, 108, 96)])
+def test_fused_sweep_equals_colour_passes_ragged_tiles(torch, n, precision):
+    """The fused sweep against the two colour passes on grids whose x and y
+    extents are not multiples of its 32 x 16 tile (tiles overhang the
+    periodic wrap in x and y).  On 162 x 108 nx is 2 mod 4, so the float32
+    variant loads 8-byte vectors; x cannot be halved there, so that grid has
+    a single multigrid level, smoothed by the grid-wide kernels."""
+    from paper_0904_4887_amd.binding import plan
+    L = (0.07 * n[0], 0.07 * n[1], 0.1 * n[2])
+    opts = dict(z_wet_lo=0.3 * L[2], z_wet_hi=L[2], precision=precision, smoother=1, coarse_sweeps=3)
+    lv = plan(n, L, **opts)["levels"]
+    assert lv[0][0] * lv[0][1] * lv[0][2] >= 1 << 20
+    s = _solver(torch, n, L, **opts)
+    eps, _ = W.random_fields(n, 17)
+    s.set_epsilon(_dev(torch, eps))
+    rng = np.random.default_rng(4)
+    r = _dev(torch, rng.normal(size=s.shape))
+    z1 = _host(s.apply_split(r))
+    s.set_opts(smoother=0)
+    z0 = _host(s.apply_split(r))
+    assert np.isfinite(z1).all()
+    assert _rel(z1, z0) <= (1e-12 if precision == 0 else 2e-5)
