@@ -290,6 +290,25 @@ int dwp_forces(dwp_ctx *ctx, int n, const double *xyz_host, const double *radius
                const double *q_host, const double *sigma_host, const dwp_eps_params *params,
                double *dEdR_host);
 
+/* dwp_forces for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, result and kernels as dwp_forces, but the packed atoms (8 n
+ * doubles), the force partial sums and the device copy of dE/dR (3 n doubles)
+ * live in a static device array of 2^21 doubles (16 MiB) that every GPU the
+ * library runs on holds until the process ends; the call makes no device
+ * allocation of any kind (dwp_forces grows context buffers to fit n).  Inputs
+ * that need more scratch than that give DWP_EINVAL before any device work:
+ * about 8 n + 3 max(n, 8192) + 3 n + nz doubles with the switch model or a
+ * caller eps (up to ~1.4e5 atoms), plus 6144 n with model 1 (up to ~330
+ * atoms).  Second-order operator only (order 6 gives DWP_EINVAL).  Every call
+ * on one GPU, from any context, shares that GPU's array and leaves its
+ * contents behind; each call writes every slot before reading it, so nothing
+ * needs clearing, but calls that overlap on one GPU (two streams or two host
+ * threads) race and must be serialised by the caller. */
+int dwp_forces_noalloc(dwp_ctx *ctx, int n, const double *xyz_host, const double *radius_host,
+                       const double *q_host, const double *sigma_host, const dwp_eps_params *params,
+                       double *dEdR_host);
+
 /* Building blocks, exposed for checking and for callers that compose them.
  * dwp_apply_operator applies the operator of the options (order 6: A6, without
  * the removal of the mean); dwp_vacuum_solve inverts the vacuum operator of

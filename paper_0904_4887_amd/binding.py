@@ -74,6 +74,7 @@ _SIGNATURES = {
     "dwp_eps_gradient": (C.c_int, [_P, _P]),
     "dwp_eps_pair_gradient": (C.c_int, [_P, _P, _P, C.c_double, _P]),
     "dwp_forces": (C.c_int, [_P, C.c_int, _D, _D, _D, _D, C.POINTER(EpsParams), _D]),
+    "dwp_forces_noalloc": (C.c_int, [_P, C.c_int, _D, _D, _D, _D, C.POINTER(EpsParams), _D]),
     "dwp_apply_operator": (C.c_int, [_P, _P, _P]),
     "dwp_vacuum_solve": (C.c_int, [_P, _P, _P]),
     "dwp_apply_split": (C.c_int, [_P, _P, _P]),
@@ -299,6 +300,22 @@ class Solver:
         else:
             rp, epp = None, None
         self._check(lib().dwp_forces(self._h, n, xp, rp, qp, sp, epp, out.ctypes.data_as(_D)))
+        return out
+
+    def forces_noalloc(self, xyz, q, sigma, radius=None, params=None):
+        """forces() through dwp_forces_noalloc (no device allocation)."""
+        x, xp = _hostd(xyz)
+        qq, qp = _hostd(q)
+        s, sp = _hostd(sigma)
+        n = len(qq)
+        out = np.zeros((n, 3))
+        if params is not None:
+            r, rp = _hostd(radius)
+            ep = eps_params(params)
+            epp = C.byref(ep)
+        else:
+            rp, epp = None, None
+        self._check(lib().dwp_forces_noalloc(self._h, n, xp, rp, qp, sp, epp, out.ctypes.data_as(_D)))
         return out
 
     def apply_operator(self, phi, out=None):

@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <mutex>
 
 namespace dwp {
 
@@ -622,9 +623,10 @@ void validate_eps_params(const dwp_ctx *c, int n, const dwp_eps_params *ep) {
     }
 }
 
-// Packs atoms (x, y, z wrapped into the cell) into the device buffer.
+// Packs atoms (x, y, z wrapped into the cell) into the context's device
+// buffer, or into dst (8 n doubles on the device) when given.
 void upload_atoms(dwp_ctx *c, int n, const double *xyz, const double *radius, const double *q,
-                  const double *sigma, const dwp_eps_params *ep) {
+                  const double *sigma, const dwp_eps_params *ep, double *dst = nullptr) {
     const Plan &p = c->plan;
     if (n < 1 || n > 1000000) fail(DWP_EINVAL, "atom count out of range");
     if (!xyz) fail(DWP_EINVAL, "xyz is NULL");
@@ -655,8 +657,11 @@ void upload_atoms(dwp_ctx *c, int n, const double *xyz, const double *radius, co
         }
         rec[8 * a + 6] = (ep && ep->exclusion && xyz[3 * a + 2] <= ep->z_lim) ? 1.0 : 0.0;
     }
-    c->atoms.alloc(sizeof(double) * rec.size());
-    DWP_HIP(hipMemcpyAsync(c->atoms.p, rec.data(), sizeof(double) * rec.size(), hipMemcpyHostToDevice, c->stream));
+    if (!dst) {
+        c->atoms.alloc(sizeof(double) * rec.size());
+        dst = c->atoms.as<double>();
+    }
+    DWP_HIP(hipMemcpyAsync(dst, rec.data(), sizeof(double) * rec.size(), hipMemcpyHostToDevice, c->stream));
     sync(c);  // rec goes out of scope
     c->atom_rec.swap(rec);
 }
@@ -1060,6 +1065,79 @@ thread_local std::string g_create_err;
 }  // namespace
 }  // namespace dwp
 
+// Device scratch of dwp_forces_noalloc: every GPU the library runs on holds its
+// own copy until the process ends.  Host code never passes this name to a
+// kernel or a copy (on the host it is only a stand-in for the symbol): it uses
+// the device address resolved once per device by resolve_scratch().
+constexpr size_t NOALLOC_SCRATCH_DOUBLES = (size_t)1 << 21;  // 16 MiB
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
+namespace dwp {
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[MAX_DEVICES] = {nullptr};
+
+// The device address of `scratch` on device `dev`, which must be current.
+double *resolve_scratch(int dev) {
+    if (dev < 0 || dev >= MAX_DEVICES) fail(DWP_EINVAL, "device index out of range for the static scratch");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            fail(DWP_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = static_cast<double *>(ptr);
+    }
+    return g_scratch_dev[dev];
+}
+
+// dwp_forces with the packed atoms, the force partials and the device copy of
+// the result in the static scratch: no device allocation.  Every partial slot
+// the force kernels read is written earlier in the same call, so the stale
+// contents of the previous call need no clearing.
+void forces_noalloc_impl(dwp_ctx *c, int n, const double *xyz, const double *radius, const double *q,
+                         const double *sigma, const dwp_eps_params *ep, double *out) {
+    need_eps(c);
+    if (!c->have_solution) fail(DWP_ESTATE, "no solution: call dwp_solve first");
+    if (!q || !sigma || !out) fail(DWP_EINVAL, "q, sigma and dEdR must not be NULL");
+    if (c->opts.order != 2)
+        fail(DWP_EINVAL, "dwp_forces_noalloc takes the second-order operator only (order 6 needs the adjoint "
+                         "solve's buffers)");
+    if (n < 1 || n > 1000000) fail(DWP_EINVAL, "atom count out of range");
+    if (ep) {
+        validate_eps_params(c, n, ep);
+        if (!radius) fail(DWP_EINVAL, "radius is NULL");
+        if (c->eps_natoms != n) fail(DWP_ESTATE, "eps was not built from these atoms");
+        if ((ep->exclusion != 0) != c->eps_exclusion) fail(DWP_ESTATE, "exclusion differs from the eps build");
+    }
+    const Plan &p = c->plan;
+    const int model = ep ? ep->model : 0;
+    const size_t plen = forces_partial_len(p, n, model);
+    const size_t need = 8 * (size_t)n + plen + 3 * (size_t)n;
+    if (need > NOALLOC_SCRATCH_DOUBLES)
+        fail(DWP_EINVAL, "dwp_forces_noalloc: " + std::to_string(n) + " atoms need " + std::to_string(need) +
+                             " doubles of scratch, the static scratch holds " +
+                             std::to_string(NOALLOC_SCRATCH_DOUBLES));
+    double *base = g_scratch_dev[c->device];
+    if (!base) base = resolve_scratch(c->device);
+    double *atoms = base, *fpart = base + 8 * (size_t)n, *outd = fpart + plen;
+    upload_atoms(c, n, xyz, ep ? radius : nullptr, q, sigma, ep, atoms);
+    if (ep && switch_geometry(c, ep) != c->eps_geometry)
+        fail(DWP_ESTATE, "positions, radii or eps parameters differ from the last dwp_build_epsilon");
+    AtomParams ap{};
+    if (ep) ap = atom_params(ep);
+    launch_eps_gradient(c->stream, p, c->phi_last.as<double>(), c->gbuf.as<double>());
+    launch_forces(c->stream, p, n, atoms, ep ? &ap : nullptr, c->phi_last.as<double>(), c->gbuf.as<double>(),
+                  c->S.as<double>(), c->Hz.as<double>(), fpart, outd);
+    DWP_HIP(hipMemcpyAsync(out, outd, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+}
+
+}  // namespace
+}  // namespace dwp
+
 // ============================================================== C ABI
 using dwp::Error;
 
@@ -1116,6 +1194,8 @@ int dwp_create(dwp_ctx **out, int device, void *stream) {
         c->stream = static_cast<hipStream_t>(stream);
         c->host_len = 8192;
         DWP_HIP(hipHostMalloc(reinterpret_cast<void **>(&c->host), sizeof(double) * c->host_len, hipHostMallocDefault));
+        // the static scratch's address on this device, once per device
+        if (device < dwp::MAX_DEVICES && !dwp::g_scratch_dev[device]) dwp::resolve_scratch(device);
         dwp_default_opts(&c->opts);
     } catch (const Error &e) {
         dwp::g_create_err = e.msg;
@@ -1256,6 +1336,14 @@ int dwp_forces(dwp_ctx *c, int n, const double *xyz, const double *radius, const
     ABI_BEGIN(c)
     DWP_HIP(hipSetDevice(c->device));
     dwp::forces_impl(c, n, xyz, radius, q, sigma, ep, out);
+    ABI_END(c)
+}
+
+int dwp_forces_noalloc(dwp_ctx *c, int n, const double *xyz, const double *radius, const double *q,
+                       const double *sigma, const dwp_eps_params *ep, double *out) {
+    ABI_BEGIN(c)
+    DWP_HIP(hipSetDevice(c->device));
+    dwp::forces_noalloc_impl(c, n, xyz, radius, q, sigma, ep, out);
     ABI_END(c)
 }
 
