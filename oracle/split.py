@@ -15,9 +15,32 @@ from __future__ import annotations
 import math
 
 import numpy as np
+from scipy.fft import dst
 from scipy.sparse.linalg import LinearOperator, cg
 
 from .poisson import apply_A, vacuum_solve
+
+
+def dirichlet_laplace_solve(v, h):
+    """u with -L u = v on a slab of planes (axis 0), L the constant-coefficient
+    7-point Laplacian, zero Dirichlet data on the planes just outside the slab,
+    x and y periodic.
+
+    Eigen-decomposition: Fourier modes in x and y, sine modes sin(pi k j / (m + 1))
+    (j = 1..m, k = 1..m) in z, whose eigenvalue of -L is the sum over the axes of
+    (2 - 2 cos theta_d) / h_d^2 with theta = 2 pi m_x / nx, 2 pi m_y / ny,
+    pi k / (m + 1).  Only a preconditioner here: it sets how fast the wet solve
+    converges, not what it converges to.
+    """
+    m, ny, nx = v.shape
+    lx = (2.0 - 2.0 * np.cos(2.0 * math.pi * np.arange(nx // 2 + 1) / nx)) / h[0] ** 2
+    ly = (2.0 - 2.0 * np.cos(2.0 * math.pi * np.arange(ny) / ny)) / h[1] ** 2
+    lz = (2.0 - 2.0 * np.cos(math.pi * np.arange(1, m + 1) / (m + 1))) / h[2] ** 2
+    lam = lz[:, None, None] + ly[None, :, None] + lx[None, None, :]
+    vh = dst(np.fft.rfft2(v, axes=(1, 2)), type=1, axis=0)
+    # DST-I applied twice is 2 (m + 1) times the identity
+    uh = dst(vh / lam, type=1, axis=0) / (2.0 * (m + 1))
+    return np.fft.irfft2(uh, s=(ny, nx), axes=(1, 2))
 
 
 def one_pass_split(rho, eps, h, k0, k1, tol=1e-13, maxiter=20000):
@@ -39,13 +62,18 @@ def one_pass_split(rho, eps, h, k0, k1, tol=1e-13, maxiter=20000):
 
     dry_part = np.where(mask, 0.0, phi_vac)
     rhs = -(b - apply_A(dry_part, eps, h))[mask]
-    # Jacobi preconditioner: the diagonal of -A is sum over faces eps_f / h^2
-    diag = np.zeros_like(rho)
-    for d, ax in zip(range(3), (2, 1, 0)):
-        diag += 0.5 * (2 * eps + np.roll(eps, -1, ax) + np.roll(eps, 1, ax)) / h[d] ** 2
-    dinv = 1.0 / diag[mask]
+    # Preconditioner eps^-1/2 (-L_D)^-1 eps^-1/2 with the constant-coefficient
+    # Dirichlet Laplacian of the slab (planes taken in slab order, k0 first)
+    planes = np.arange(k0, k1) % nz
+    sw = 1.0 / np.sqrt(eps)
+
+    def prec(xw):
+        full = extend(xw) * sw
+        full[planes] = dirichlet_laplace_solve(full[planes], h)
+        return (full * sw)[mask]
+
     A = LinearOperator((nW, nW), matvec=op, dtype=np.float64)
-    M = LinearOperator((nW, nW), matvec=lambda v: dinv * v, dtype=np.float64)
+    M = LinearOperator((nW, nW), matvec=prec, dtype=np.float64)
     xw, info = cg(A, rhs, rtol=tol, atol=0.0, maxiter=maxiter, M=M)
     if info != 0:
         raise RuntimeError(f"wet-slab Dirichlet solve did not converge (info={info})")

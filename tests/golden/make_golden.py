@@ -5,7 +5,11 @@ JSON file per workload in this directory, holding the energy in both forms,
 the oracle's PCG iteration counts, phi and dE/d eps at 64 seeded nodes, the
 mean of phi^2, and dE/dR of every atom (atom-built permittivities only).
 
+With "one_pass" first, it writes instead the error of the paper's one-pass
+split for the five headline configurations (or the names given).
+
 Usage: python tests/golden/make_golden.py [name ...]
+       python tests/golden/make_golden.py one_pass [name ...]
 """
 import json
 import os
@@ -133,8 +137,39 @@ def make(name, w):
     print(name, "E", E, "iters", info["iters"], "solve s", round(t2 - t1, 1), flush=True)
 
 
+# the five headline configurations, smallest first
+ONE_PASS = ("tanh_box_32x32x64", "slab_96x96x192", "slab_128x128x256", "slab_192x192x384",
+            "big_slab_256x256x512")
+
+
+def make_one_pass(name, w):
+    """The error of the paper's one-pass dry/wet split (Sec. II.F) against the
+    exact solution of the same discrete problem, on the configured wet slab:
+    relative energy error, relative L2 and max-norm errors of phi."""
+    t0 = time.time()
+    eps = w.eps_grid() if w.eps_kind == "tanh_z" else O.eps_erf(w.n, w.L, w.xyz, w.radius, w.eps_params)
+    rho = O.rho_gauss(w.n, w.L, w.xyz, w.q, w.sigma)
+    phi = O.solve(rho, eps, w.h, tol=1e-12, max_iter=3000)
+    k0, k1 = W.wet_planes(w.n[2], w.L[2], w.z_wet)
+    phi_a = O.one_pass_split(rho, eps, w.h, k0, k1, tol=1e-12)
+    E, E_a = O.energy(rho, phi, w.h), O.energy(rho, phi_a, w.h)
+    d = phi_a - phi
+    out = dict(name=name, n=list(w.n), L=list(w.L), z_wet=list(w.z_wet), wet_planes=[int(k0), int(k1)],
+               energy=E, energy_one_pass=E_a, rel_energy_error=(E_a - E) / abs(E),
+               rel_l2_phi_error=float(np.linalg.norm(d) / np.linalg.norm(phi)),
+               rel_max_phi_error=float(np.abs(d).max() / np.abs(phi).max()), t_s=time.time() - t0)
+    with open(os.path.join(HERE, f"oracle_one_pass_{name}.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print("one-pass", name, "rel E", out["rel_energy_error"], "rel L2 phi", out["rel_l2_phi_error"],
+          "s", round(out["t_s"], 1), flush=True)
+
+
 if __name__ == "__main__":
     ws = workloads()
-    names = sys.argv[1:] or list(ws)
-    for nm in names:
+    args = sys.argv[1:]
+    if args and args[0] == "one_pass":
+        for nm in args[1:] or ONE_PASS:
+            make_one_pass(nm, ws[nm])
+        sys.exit(0)
+    for nm in args or list(ws):
         make(nm, ws[nm])
