@@ -105,6 +105,25 @@ typedef struct {
                            /* keeps the 7-point operator (a preconditioner).   */
                            /* Gradients and forces solve the adjoint problem   */
                            /* once per solve.  Needs eps resolved by the grid. */
+                           /* The 7-point wet V-cycle is a poor approximation  */
+                           /* of A6 near the switch functions: on the slab     */
+                           /* workloads cycles = 0 (the FFT dry update alone)  */
+                           /* with scaled_dry = 0 converges fastest, and with  */
+                           /* the exclusion rule of Eq. 19 every cycles >= 1   */
+                           /* setting stalls (DWP_ENOCONV at max_outer).       */
+    int smooth6;           /* order 6 only: 1 = the finest wet level smooths   */
+                           /* (weighted Jacobi, weight 2/3) and forms the      */
+                           /* residual it restricts with the sixth-order       */
+                           /* operator itself, zero Dirichlet data on the      */
+                           /* three planes beyond W; the coarser levels keep   */
+                           /* the 7-point operator (so does the adjoint solve  */
+                           /* of dwp_eps_gradient / dwp_forces).  0 = 7-point  */
+                           /* everywhere                                       */
+    int krylov_fp32;       /* mixed precision, order 2, restart <= 16: 1 =     */
+                           /* the Arnoldi basis V is stored in float32 (its    */
+                           /* dot products, the Hessenberg matrix, Z and the   */
+                           /* iterate stay float64; every restart recomputes   */
+                           /* the true residual in float64).  0 = float64 V    */
 } dwp_opts;
 
 /* Per-solve report. */

@@ -158,6 +158,7 @@ struct dwp_ctx {
     // full-box float64 arrays
     dwp::DevBuf eps, sinv, S, b, r, w, phi_last, gbuf;
     dwp::DevBuf V, Z;             // Krylov bases, (restart + 1) N and restart N
+    dwp::DevBuf V32;              // float32 Arnoldi basis, (restart + 1) N (opts.krylov_fp32)
     dwp::DevBuf cbuf;             // FFT workspace, nkx * ny * nz double2
     dwp::DevBuf Hz;               // per-plane height factor (exclusion)
     dwp::DevBuf partial;          // reduction partials
@@ -221,6 +222,11 @@ template <class T>
 void launch_wet_residual(hipStream_t s, const Plan &p, const double *v, const double *dD,
                          const double *eps, T *fW);
 template <class T>
+void launch_wet_residual_v32(hipStream_t s, const Plan &p, const float *v, const double *dD, const double *eps,
+                             T *fW);
+// out = A phi rounded to float32 (a float32 Krylov basis vector)
+void launch_apply_full_f32(hipStream_t s, const Plan &p, const double *phi, const double *eps, float *out);
+template <class T>
 void launch_wet_add(hipStream_t s, const Plan &p, const T *uW, double *z);
 template <class T>
 void launch_wet_eps(hipStream_t s, const Plan &p, const double *eps, T *epsW);
@@ -233,6 +239,9 @@ void launch_level_smooth(hipStream_t s, const Level &L, int color);
 // fc = full weighting of the fine residual rf; also zeroes C.u
 template <class T>
 void launch_restrict(hipStream_t s, const Level &F, const Level &C, const T *rf, T *fc);
+// fc = full weighting of the fine residual f - A u (never stored), coarse u zeroed
+template <class T>
+void launch_resid_restrict(hipStream_t s, const Level &F, const Level &C);
 template <class T>
 void launch_prolong_add(hipStream_t s, const Level &F, const Level &C);
 
@@ -259,6 +268,11 @@ void launch_apply6(hipStream_t s, const Plan &p, const double *x, const double *
 template <class T>
 void launch_wet_residual6(hipStream_t s, const Plan &p, const double *v, const double *dD, const double *eps,
                           const double *G, T *fW, bool trans);
+// finest wet level, sixth-order operator (slab unknowns zero outside W):
+// smooth: one weighted-Jacobi sweep u -> out (ghosted); else out = f - A6 u
+template <class T>
+void launch_wet6(hipStream_t s, const Plan &p, const Level &L, const T *u, T *out, const double *eps, const double *G,
+                 bool smooth, double omega);
 void launch_grad6(hipStream_t s, const Plan &p, const double *phi, const double *lam, double *g);
 void launch_charge_potential(hipStream_t s, const Plan &p, const double *phi, const double *lam, double *psi);
 // out = gr * m / h^3 (+ add)
@@ -272,6 +286,10 @@ void fft_plan_axis(FFTAxis &ax, int n, double h, bool half, int order);
 // spectrum (cbuf, sized for float64) and the transforms in float32
 void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay,
                          const FFTAxis &az, const double *r, const double *sinv, void *cbuf,
+                         double *out, Profiler *prof, bool fp32);
+// the same with a float32 input (a float32 Krylov basis vector)
+void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay,
+                         const FFTAxis &az, const float *r, const double *sinv, void *cbuf,
                          double *out, Profiler *prof, bool fp32);
 
 // kern_blas.hip: deterministic reductions
@@ -287,6 +305,14 @@ void launch_axpy_multi(hipStream_t s, double *w, const double *V, size_t ldv, in
 bool orth_update_supported(const double *V, size_t ldv, int nv, size_t n);
 void launch_orth_update(hipStream_t s, double *w, const double *V, size_t ldv, int nv, double *hc, size_t n,
                         double *partial);
+// float32 Krylov basis (mixed precision): projections and update in float64
+// arithmetic on float32 vectors (n and ldv multiples of 4, 16-byte aligned)
+bool krylov32_supported(const float *V, size_t ldv, size_t n);
+void launch_multidot32(hipStream_t s, const float *V, size_t ldv, int nv, const float *w, size_t n, double *partial,
+                       double *out, double *norm_out);
+void launch_orth_update32(hipStream_t s, float *w, const float *V, size_t ldv, int nv, double *hc, size_t n,
+                          double *partial);
+void launch_scale_to32(hipStream_t s, float *x32, const double *r, const double *den_sq, size_t n);
 // energy sums: out[0] = sum rho phi (compensated), out[1] = sum_faces eps_f (D_f phi)^2
 void launch_energy(hipStream_t s, const Plan &p, const double *rho, const double *phi,
                    const double *eps, double *partial, double *out);

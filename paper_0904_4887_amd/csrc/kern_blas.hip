@@ -179,6 +179,103 @@ k_orth_update2(double *__restrict__ w, const double *__restrict__ V, size_t ldv,
     if (threadIdx.x == 0) partial[blockIdx.x] = res[0];
 }
 
+// The same projection and update for a float32 Krylov basis (V and w in
+// float32, four per 16-byte load; every product and sum in float64).
+template <int NV>
+__global__ void __launch_bounds__(RED_THREADS)
+k_multidot4f(const float *__restrict__ V, size_t ldv, int v0, const float *__restrict__ w, size_t n4,
+             double *__restrict__ partial, int stride, int with_norm) {
+    __shared__ double sh[NV + 1][RED_THREADS / 64];
+    __shared__ double res[NV + 1];
+    const float4 *w4 = reinterpret_cast<const float4 *>(w);
+    double acc[NV + 1];
+#pragma unroll
+    for (int q = 0; q <= NV; ++q) acc[q] = 0.0;
+    for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n4; t += (size_t)gridDim.x * RED_THREADS) {
+        const float4 wt = w4[t];
+        float4 vq[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) vq[q] = reinterpret_cast<const float4 *>(V + (size_t)(v0 + q) * ldv)[t];
+        const double a = wt.x, b = wt.y, c = wt.z, d = wt.w;
+        acc[NV] += a * a + b * b + c * c + d * d;
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+            acc[q] += (double)vq[q].x * a + (double)vq[q].y * b + (double)vq[q].z * c + (double)vq[q].w * d;
+    }
+    block_sums<NV + 1>(acc, sh, res);
+    if ((int)threadIdx.x < NV) partial[(size_t)blockIdx.x * stride + v0 + threadIdx.x] = res[threadIdx.x];
+    if (with_norm && threadIdx.x == NV) partial[(size_t)blockIdx.x * stride + NORM_SLOT] = res[NV];
+}
+
+template <int NV>
+__global__ void __launch_bounds__(RED_THREADS)
+k_orth_update4f(float *__restrict__ w, const float *__restrict__ V, size_t ldv, const double *__restrict__ hc,
+                size_t n4, double *__restrict__ partial, double *__restrict__ beta_out) {
+    __shared__ double sh[1][RED_THREADS / 64];
+    __shared__ double cs[NV + 1];
+    __shared__ double res[1];
+    if (threadIdx.x == 0) {
+        double h2 = 0.0;
+        for (int q = 0; q < NV; ++q) h2 += hc[q] * hc[q];
+        const double w2n = hc[NORM_SLOT], b2 = w2n - h2;
+        const double beta = (b2 > 1e-20 * w2n) ? sqrt(b2) : 1.0;
+        cs[NV] = 1.0 / beta;
+        if (blockIdx.x == 0) *beta_out = beta;
+    }
+    if ((int)threadIdx.x < NV) cs[threadIdx.x] = -hc[threadIdx.x];
+    __syncthreads();
+    const double sc = cs[NV];
+    float4 *w4 = reinterpret_cast<float4 *>(w);
+    double nrm[1] = {0.0};
+    for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n4; t += (size_t)gridDim.x * RED_THREADS) {
+        const float4 wv = w4[t];
+        double a = wv.x, b = wv.y, c = wv.z, d = wv.w;
+        float4 vq[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) vq[q] = reinterpret_cast<const float4 *>(V + (size_t)q * ldv)[t];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            a += cs[q] * (double)vq[q].x;
+            b += cs[q] * (double)vq[q].y;
+            c += cs[q] * (double)vq[q].z;
+            d += cs[q] * (double)vq[q].w;
+        }
+        const float4 o = make_float4((float)(a * sc), (float)(b * sc), (float)(c * sc), (float)(d * sc));
+        w4[t] = o;
+        nrm[0] += (double)o.x * o.x + (double)o.y * o.y + (double)o.z * o.z + (double)o.w * o.w;
+    }
+    block_sums<1>(nrm, sh, res);
+    if (threadIdx.x == 0) partial[blockIdx.x] = res[0];
+}
+
+__global__ void __launch_bounds__(RED_THREADS)
+k_rescale_if_f(float *__restrict__ x, const double *__restrict__ partial, int nparts, double *__restrict__ nu2,
+               size_t n) {
+    __shared__ double sh[RED_THREADS / 64];
+    __shared__ double tot;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += RED_THREADS) v += partial[b];
+    const double r = block_sum(v, sh);
+    if (threadIdx.x == 0) {
+        tot = r;
+        if (blockIdx.x == 0) *nu2 = r;
+    }
+    __syncthreads();
+    const double nu = sqrt(tot);
+    if (nu == 0.0 || fabs(nu - 1.0) <= 1e-8) return;
+    const double s = 1.0 / nu;
+    for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n; t += (size_t)gridDim.x * RED_THREADS)
+        x[t] = (float)((double)x[t] * s);
+}
+
+// x32 = r / sqrt(*den_sq) rounded to float32 (0 when *den_sq is 0)
+__global__ void k_scale_to_f(float *__restrict__ x32, const double *__restrict__ r, const double *__restrict__ den_sq,
+                             size_t n) {
+    const double s = *den_sq > 0.0 ? 1.0 / sqrt(*den_sq) : 0.0;
+    for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n; t += (size_t)gridDim.x * RED_THREADS)
+        x32[t] = (float)(r[t] * s);
+}
+
 // nu^2 = sum of the nparts block partials (every block adds them in the same
 // fixed order, so all agree bitwise; block 0 stores it at *nu2); then
 // x <- x / nu unless nu is 0 or within 1e-8 of 1.
@@ -422,6 +519,53 @@ void launch_orth_update(hipStream_t s, double *w, const double *V, size_t ldv, i
     }
     DWP_LAUNCH_CHECK();
     k_rescale_if<<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, partial, RED_BLOCKS, hc + 65, n);
+    DWP_LAUNCH_CHECK();
+}
+
+static bool quad_ok(const void *a, size_t ldv, size_t n) {
+    return n % 4 == 0 && ldv % 4 == 0 && (reinterpret_cast<uintptr_t>(a) & 15) == 0;
+}
+
+bool krylov32_supported(const float *V, size_t ldv, size_t n) { return quad_ok(V, ldv, n); }
+
+void launch_multidot32(hipStream_t s, const float *V, size_t ldv, int nv, const float *w, size_t n, double *partial,
+                       double *out, double *norm_out) {
+    if (nv > 64 || !quad_ok(V, ldv, n) || !quad_ok(w, 0, n)) fail(DWP_EINVAL, "internal: float32 multidot layout");
+    for (int v0 = 0; v0 < nv; v0 += MD2_GROUP) {
+        const int g = nv - v0 < MD2_GROUP ? nv - v0 : MD2_GROUP;
+        const int wn = (v0 == 0 && norm_out) ? 1 : 0;
+        switch (g) {
+#define DWP_MD4_CASE(K)                                                                                      \
+    case K:                                                                                                  \
+        k_multidot4f<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, v0, w, n / 4, partial, MD_STRIDE, wn);    \
+        break;
+            DWP_NV_CASES(DWP_MD4_CASE)
+#undef DWP_MD4_CASE
+        }
+        DWP_LAUNCH_CHECK();
+    }
+    k_reduce_partials<<<nv + (norm_out ? 1 : 0), RED_THREADS, 0, s>>>(partial, RED_BLOCKS, MD_STRIDE, out, nv,
+                                                                     norm_out);
+    DWP_LAUNCH_CHECK();
+}
+
+void launch_orth_update32(hipStream_t s, float *w, const float *V, size_t ldv, int nv, double *hc, size_t n,
+                          double *partial) {
+    if (nv < 1 || nv > 16 || !quad_ok(V, ldv, n) || !quad_ok(w, 0, n))
+        fail(DWP_EINVAL, "internal: float32 orth update layout");
+    switch (nv) {
+#define DWP_OU4_CASE(K)                                                                                     \
+    case K: k_orth_update4f<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, V, ldv, hc, n / 4, partial, hc + 66); break;
+        DWP_NV_CASES(DWP_OU4_CASE)
+#undef DWP_OU4_CASE
+    }
+    DWP_LAUNCH_CHECK();
+    k_rescale_if_f<<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, partial, RED_BLOCKS, hc + 65, n);
+    DWP_LAUNCH_CHECK();
+}
+
+void launch_scale_to32(hipStream_t s, float *x32, const double *r, const double *den_sq, size_t n) {
+    k_scale_to_f<<<RED_BLOCKS, RED_THREADS, 0, s>>>(x32, r, den_sq, n);
     DWP_LAUNCH_CHECK();
 }
 

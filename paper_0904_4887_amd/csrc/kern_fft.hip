@@ -189,9 +189,9 @@ __device__ void fft_lines(C *buf, const Radices &rd, int lb, int es, int ls, con
 // ---------------------------------------------------------------- x passes
 // Rows are the nx-long x lines of the [nz][ny][nx] grid; B = 2^lb complex
 // lines per block carry 2B real rows.  LDS lines are padded to n + 1 elements.
-template <class S>
+template <class S, class TI>
 __global__ void __launch_bounds__(FFT_THREADS)
-k_fft_x_fwd(const double *__restrict__ in, const double *__restrict__ sinv, cplx<S> *__restrict__ out,
+k_fft_x_fwd(const TI *__restrict__ in, const double *__restrict__ sinv, cplx<S> *__restrict__ out,
             Radices rd, const cplx<S> *__restrict__ tw, int lb, int nrows, int nkx, int ldc, Div dn, Div dk) {
     using C = cplx<S>;
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -204,8 +204,8 @@ k_fft_x_fwd(const double *__restrict__ in, const double *__restrict__ sinv, cplx
         double a = 0.0, b = 0.0;
         if (rb < nrows) {
             const size_t ia = (size_t)ra * n + t, ib = ia + n;
-            a = in[ia];
-            b = in[ib];
+            a = (double)in[ia];
+            b = (double)in[ib];
             if (sinv) { a *= sinv[ia]; b *= sinv[ib]; }
         }
         lds[l * ls + t] = mk<C>((S)a, (S)b);
@@ -410,9 +410,9 @@ void fft_plan_axis(FFTAxis &ax, int n, double h, bool half, int order) {
     DWP_HIP(hipMemcpy(ax.lam32.p, lam32.data(), sizeof(float) * nl, hipMemcpyHostToDevice));
 }
 
-template <class S>
+template <class S, class TI>
 static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay, const FFTAxis &az,
-                           const double *r, const double *sinv, void *cbuf_v, double *out, Profiler *prof) {
+                           const TI *r, const double *sinv, void *cbuf_v, double *out, Profiler *prof) {
     using C = cplx<S>;
     C *cbuf = static_cast<C *>(cbuf_v);
     auto TW = [](const FFTAxis &a) { return sizeof(S) == 8 ? a.tw.as<C>() : a.tw32.as<C>(); };
@@ -420,7 +420,8 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
     // algorithmic bytes of each pass: the real grid (8 B / point, twice when
     // scaled) and the half-spectrum (one complex value) read and written once
     const double Cn = (double)p.nkx * p.ny * p.nz, cb = (double)sizeof(C);
-    const double bx = (sinv ? 16.0 : 8.0) * p.N + cb * Cn;
+    const double bx = (sinv ? 8.0 + sizeof(TI) : (double)sizeof(TI)) * p.N + cb * Cn;
+    const double bxi = (sinv ? 16.0 : 8.0) * p.N + cb * Cn;
     auto pb = [&](int g) { return prof ? prof->begin(st, g) : -1; };
     auto pe = [&](int ev, int g, double b) { if (prof) prof->end(st, ev, g, b); };
     int ev;
@@ -430,7 +431,7 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
     const size_t ldsx = sizeof(C) * Bx * (p.nx + 1);
     const Div dn = make_div(p.nx), dk = make_div(p.nkx);
     ev = pb(PG_FFT_X);
-    k_fft_x_fwd<S><<<gx, FFT_THREADS, ldsx, st>>>(r, sinv, cbuf, radices_of(ax), TW(ax), lbx, nrows, p.nkx, p.ldc, dn,
+    k_fft_x_fwd<S, TI><<<gx, FFT_THREADS, ldsx, st>>>(r, sinv, cbuf, radices_of(ax), TW(ax), lbx, nrows, p.nkx, p.ldc, dn,
                                                   dk);
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_X, bx);
@@ -456,13 +457,18 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
     k_fft_x_inv<S><<<gx, FFT_THREADS, ldsx, st>>>(cbuf, sinv, out, radices_of(ax), TW(ax), lbx, nrows, p.nkx, p.ldc,
                                                   dn);
     DWP_LAUNCH_CHECK();
-    pe(ev, PG_FFT_X, bx);
+    pe(ev, PG_FFT_X, bxi);
 }
 
 void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay, const FFTAxis &az,
                          const double *r, const double *sinv, void *cbuf, double *out, Profiler *prof, bool fp32) {
-    if (fp32) vacuum_solve_t<float>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
-    else vacuum_solve_t<double>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
+    if (fp32) vacuum_solve_t<float, double>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
+    else vacuum_solve_t<double, double>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
+}
+void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay, const FFTAxis &az,
+                         const float *r, const double *sinv, void *cbuf, double *out, Profiler *prof, bool fp32) {
+    if (fp32) vacuum_solve_t<float, float>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
+    else vacuum_solve_t<double, float>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
 }
 
 }  // namespace dwp

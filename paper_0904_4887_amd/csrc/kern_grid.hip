@@ -42,9 +42,9 @@ __device__ __forceinline__ T ld_at(const T *base, unsigned byte_off) {
     return *(const T *)((const char *)base + byte_off);
 }
 
-template <class T, int MODE>
+template <class T, int MODE, class TB>
 __global__ void __launch_bounds__(BX *BY)
-k_apply_zmarch(const double *__restrict__ phi, const double *__restrict__ eps, const double *__restrict__ b,
+k_apply_zmarch(const double *__restrict__ phi, const double *__restrict__ eps, const TB *__restrict__ b,
                T *__restrict__ out, int nx, int ny, int nz, double cx, double cy, double cz, int k_w0,
                int nplanes, int tiles_x, int tiles_y, int nb_real) {
     const int t = xcd_tile(nb_real);
@@ -89,8 +89,8 @@ k_apply_zmarch(const double *__restrict__ phi, const double *__restrict__ eps, c
                      cz * ((e0 + ep) * (pp - p0) + (e0 + em) * (pm - p0));
         acc *= 0.5;
         if (MODE == 0) out[(size_t)k * plane + col] = (T)acc;
-        else if (MODE == 1) out[(size_t)k * plane + col] = (T)(ld_at(b + (size_t)k * plane, oc) - acc);
-        else out[(size_t)kk * plane + col] = (T)(ld_at(b + (size_t)k * plane, oc) - acc);
+        else if (MODE == 1) out[(size_t)k * plane + col] = (T)((double)b[(size_t)k * plane + col] - acc);
+        else out[(size_t)kk * plane + col] = (T)((double)b[(size_t)k * plane + col] - acc);
         pm = p0; em = e0; p0 = pp; e0 = ep; pp = pq; ep = eq;
 #pragma unroll
         for (int q = 0; q < 8; ++q) nb[q] = nb2[q];
@@ -114,9 +114,9 @@ constexpr int AQ = AHX2 * AHY;              // double2 items per field per plane
 constexpr int AQT = (AQ + 255) / 256;       // per thread
 constexpr int ZCH = 16;                     // planes per block
 
-template <class T, int MODE>
+template <class T, int MODE, class TB>
 __global__ void __launch_bounds__(256)
-k_apply_tile(const double *__restrict__ phi, const double *__restrict__ eps, const double *__restrict__ b,
+k_apply_tile(const double *__restrict__ phi, const double *__restrict__ eps, const TB *__restrict__ b,
              T *__restrict__ out, int nx, int ny, int nz, double cx, double cy, double cz, int k_w0, int nplanes,
              int tiles_x, int tiles_y, int nb_real) {
     __shared__ double2 sp[2][AQT * 256], se[2][AQT * 256];
@@ -187,13 +187,24 @@ k_apply_tile(const double *__restrict__ phi, const double *__restrict__ eps, con
         a0 *= 0.5;
         a1 *= 0.5;
         if (own) {
+            const size_t dst = (size_t)(MODE == 2 ? kk : k) * plane + (size_t)(gj * nx + gi);
             if (MODE == 0) {
-                *(double2 *)((char *)(out + (size_t)k * plane) + oc) = make_double2(a0, a1);
+                if constexpr (sizeof(T) == 8) {
+                    *(double2 *)((char *)(out + (size_t)k * plane) + oc) = make_double2(a0, a1);
+                } else {
+                    *(float2 *)(out + dst) = make_float2((float)a0, (float)a1);
+                }
             } else {
-                const double2 bv = ld_at((const double2 *)(b + (size_t)k * plane), oc);
-                const size_t dst = (size_t)(MODE == 1 ? k : kk) * plane + (size_t)(gj * nx + gi);
-                out[dst] = (T)(bv.x - a0);
-                out[dst + 1] = (T)(bv.y - a1);
+                double bx, by;
+                if constexpr (sizeof(TB) == 8) {
+                    const double2 bv = ld_at((const double2 *)(b + (size_t)k * plane), oc);
+                    bx = bv.x; by = bv.y;
+                } else {
+                    const float2 bv = *(const float2 *)(b + (size_t)k * plane + (size_t)(gj * nx + gi));
+                    bx = bv.x; by = bv.y;
+                }
+                out[dst] = (T)(bx - a0);
+                out[dst + 1] = (T)(by - a1);
             }
         }
         pm = p0; em = e0; p0 = pp; e0 = ep; pp = pn; ep = en; pn = pq; en = eq;
@@ -807,6 +818,161 @@ k_sweep_fused(const T *__restrict__ uin, T *__restrict__ uout, const T *__restri
     }
 }
 
+// ---------------------------------------------------------------- residual + restriction
+// fc = full weighting of the fine residual r = f - A u, in one pass, with the
+// coarse unknowns zeroed (the coarse level starts its cycle from a zero
+// correction); r itself is never written.  A block owns a tile of RCX x RCY
+// coarse columns (one thread each) and marches up a chunk of fine planes.
+// Each plane step stages u and eps of the plane above (tile + 2-cell halo,
+// vector loads issued one step ahead) and f of the current plane in LDS rings,
+// computes the fine residual of the current plane at the (2 RCX + 1) x
+// (2 RCY + 1) points the 3 x 3 stencils of the tile cover, and each thread
+// then forms its coarse column's in-plane weighted sum R.  Without z
+// coarsening R is the coarse value of the same plane; with z coarsening fine
+// plane 2 kc + dz adds R with weight 1/4, 1/2, 1/4 to coarse plane kc, so an
+// even fine plane closes one coarse plane and opens the next.
+constexpr int RCX = 16, RCY = 16;            // coarse columns per tile (threads)
+constexpr int RNT = RCX * RCY;               // 256
+constexpr int RFX = 2 * RCX, RFY = 2 * RCY;  // fine points per tile
+constexpr int RRX = RFX + 1, RRY = RFY + 1;  // fine residual points the stencils cover
+template <int W> struct RLay {
+    static constexpr int HL = W < 2 ? 2 : W;  // x halo of the staged rows (>= 2, a multiple of W)
+    static constexpr int LW = RFX + 2 * HL;   // staged row length
+    static constexpr int VR = LW / W;
+    static constexpr int NU = RFY + 4, NF = RFY + 2;  // staged rows of u / eps and of f
+    static constexpr int NVU = VR * NU, NVF = VR * NF;
+    static constexpr int MU = (NVU + RNT - 1) / RNT, MF = (NVF + RNT - 1) / RNT;
+};
+
+template <class T, int W, bool ZC>
+__global__ void __launch_bounds__(RNT)
+k_resid_restrict(const T *__restrict__ u, const T *__restrict__ e, const T *__restrict__ f, T *__restrict__ fc,
+                 T *__restrict__ uc, LevelArgs a, int nxc, int nyc, int nwc, int tiles_x, int tiles_y, int kcc,
+                 int nb_real) {
+    using Ly = RLay<W>;
+    using V = typename FVec<T, W>::V;
+    constexpr int LW = Ly::LW, HL = Ly::HL;
+    __shared__ __align__(16) T su[3][Ly::NVU * W];
+    __shared__ __align__(16) T se[3][Ly::NVU * W];
+    __shared__ __align__(16) T sf[Ly::NVF * W];
+    __shared__ T rr[RRY * RRX];
+    const int tile = xcd_tile(nb_real);
+    if (tile >= nb_real) return;
+    const int nx = a.nx, ny = a.ny, nw = a.nw;
+    const size_t plane = (size_t)nx * ny, planec = (size_t)nxc * nyc;
+    const int x0 = (tile % tiles_x) * RFX, y0 = ((tile / tiles_x) % tiles_y) * RFY;
+    const int c0 = (tile / (tiles_x * tiles_y)) * kcc, c1 = min(nwc, c0 + kcc);  // coarse planes
+    const int k0 = ZC ? 2 * c0 : c0, k1 = ZC ? 2 * c1 + 1 : c1;                   // fine planes [k0, k1)
+    const T cx = cxv<T>(a, 0), cy = cxv<T>(a, 1), cz = cxv<T>(a, 2);
+    const int tid = threadIdx.x;
+    // staged vectors of this thread: byte offset in a plane, LDS index (-1: none)
+    unsigned ou[Ly::MU], of[Ly::MF];
+    int lu[Ly::MU], lf[Ly::MF];
+#pragma unroll
+    for (int m = 0; m < Ly::MU; ++m) {
+        const int q = tid + RNT * m, qq = min(q, Ly::NVU - 1);
+        const int row = qq / Ly::VR, col = qq % Ly::VR;
+        const int x = ((x0 - HL + W * col) % nx + nx) % nx, y = ((y0 - 2 + row) % ny + ny) % ny;
+        ou[m] = (unsigned)((y * nx + x) * sizeof(T));
+        lu[m] = q < Ly::NVU ? row * LW + W * col : -1;
+    }
+#pragma unroll
+    for (int m = 0; m < Ly::MF; ++m) {
+        const int q = tid + RNT * m, qq = min(q, Ly::NVF - 1);
+        const int row = qq / Ly::VR, col = qq % Ly::VR;
+        const int x = ((x0 - HL + W * col) % nx + nx) % nx, y = ((y0 - 1 + row) % ny + ny) % ny;
+        of[m] = (unsigned)((y * nx + x) * sizeof(T));
+        lf[m] = q < Ly::NVF ? row * LW + W * col : -1;
+    }
+    V pu[Ly::MU], pe[Ly::MU], pf[Ly::MF];
+    // loads are unconditional, planes clamped into the arrays
+    auto fetch = [&](int k) {
+        const int kk = min(max(k, -1), nw), kf = min(max(k - 1, 0), nw - 1);  // u, eps of k; f of k - 1
+        const T *bu = u + (size_t)(kk + 1) * plane, *be = e + (size_t)(kk + 1) * plane, *bf = f + (size_t)kf * plane;
+#pragma unroll
+        for (int m = 0; m < Ly::MU; ++m) {
+            pu[m] = *(const V *)((const char *)bu + ou[m]);
+            pe[m] = *(const V *)((const char *)be + ou[m]);
+        }
+#pragma unroll
+        for (int m = 0; m < Ly::MF; ++m) pf[m] = *(const V *)((const char *)bf + of[m]);
+    };
+    auto slot = [](int k) { return ((k % 3) + 3) % 3; };
+    auto stash_ue = [&](int k) {
+#pragma unroll
+        for (int m = 0; m < Ly::MU; ++m)
+            if (lu[m] >= 0) {
+                *(V *)&su[slot(k)][lu[m]] = pu[m];
+                *(V *)&se[slot(k)][lu[m]] = pe[m];
+            }
+    };
+    auto stash_f = [&]() {
+#pragma unroll
+        for (int m = 0; m < Ly::MF; ++m)
+            if (lf[m] >= 0) *(V *)&sf[lf[m]] = pf[m];
+    };
+    // restriction weights of this thread's coarse column
+    const int tx = tid % RCX, ty = tid / RCX;
+    const int ic = x0 / 2 + tx, jc = y0 / 2 + ty;
+    const bool own = ic < nxc && jc < nyc;
+    const size_t cidx = own ? (size_t)jc * nxc + ic : 0;
+    const int rc = (2 * ty + 1) * RRX + (2 * tx + 1);  // centre of its 3 x 3 stencil in rr
+    // prologue: planes k0 - 1 and k0 into the ring, k0 + 1 (and f of k0) in flight
+    fetch(k0 - 1);
+    stash_ue(k0 - 1);
+    fetch(k0);
+    stash_ue(k0);
+    fetch(k0 + 1);
+    T acc = T(0);
+    for (int k = k0; k < k1; ++k) {
+        stash_ue(k + 1);
+        stash_f();  // f of plane k
+        fetch(k + 2);
+        __syncthreads();
+        {
+            const T *U0 = su[slot(k)], *Um = su[slot(k - 1)], *Up = su[slot(k + 1)];
+            const T *E0 = se[slot(k)], *Em = se[slot(k - 1)], *Ep = se[slot(k + 1)];
+            for (int q = tid; q < RRX * RRY; q += RNT) {
+                const int rx = q % RRX, ry = q / RRX;
+                const int h = (ry + 1) * LW + rx - 1 + HL, hf = ry * LW + rx - 1 + HL;
+                const T e0 = E0[h], u0 = U0[h];
+                const T wxp = cx * (e0 + E0[h + 1]), wxm = cx * (e0 + E0[h - 1]);
+                const T wyp = cy * (e0 + E0[h + LW]), wym = cy * (e0 + E0[h - LW]);
+                const T wzp = cz * (e0 + Ep[h]), wzm = cz * (e0 + Em[h]);
+                const T off = T(0.5) * (wxp * U0[h + 1] + wxm * U0[h - 1] + wyp * U0[h + LW] + wym * U0[h - LW] +
+                                        wzp * Up[h] + wzm * Um[h]);
+                const T dg = T(0.5) * (wxp + wxm + wyp + wym + wzp + wzm);
+                rr[q] = sf[hf] - (off - dg * u0);
+            }
+        }
+        __syncthreads();
+        const T sx0 = T(0.25) * rr[rc - RRX - 1] + T(0.5) * rr[rc - RRX] + T(0.25) * rr[rc - RRX + 1];
+        const T sx1 = T(0.25) * rr[rc - 1] + T(0.5) * rr[rc] + T(0.25) * rr[rc + 1];
+        const T sx2 = T(0.25) * rr[rc + RRX - 1] + T(0.5) * rr[rc + RRX] + T(0.25) * rr[rc + RRX + 1];
+        const T R = T(0.25) * sx0 + T(0.5) * sx1 + T(0.25) * sx2;
+        int kc_done = -1;
+        T out = T(0);
+        if (!ZC) {
+            kc_done = k;
+            out = R;
+        } else if ((k & 1) == 0) {
+            if (k > k0) {
+                kc_done = k / 2 - 1;
+                out = acc + T(0.25) * R;
+            }
+            acc = T(0.25) * R;
+        } else {
+            acc += T(0.5) * R;
+        }
+        if (own && kc_done >= 0) {
+            fc[(size_t)kc_done * planec + cidx] = out;
+            uc[(size_t)(kc_done + 1) * planec + cidx] = T(0);
+            if (kc_done == 0) uc[cidx] = T(0);
+            if (kc_done == nwc - 1) uc[(size_t)(nwc + 1) * planec + cidx] = T(0);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- V-cycle bottom
 // Levels small enough for one workgroup run the rest of the V-cycle inside a
 // single kernel (one CU), phases separated by barriers: this replaces a few
@@ -971,14 +1137,14 @@ LevelArgs level_args(const Level &L) {
 // ============================================================== launchers
 static bool al16(const void *q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; }
 
-template <class T, int MODE>
-void launch_zmarch(hipStream_t s, const Plan &p, const double *phi, const double *eps, const double *b, T *out,
+template <class T, int MODE, class TB = double>
+void launch_zmarch(hipStream_t s, const Plan &p, const double *phi, const double *eps, const TB *b, T *out,
                    int nplanes) {
     const bool tile_ok = p.nx % 2 == 0 && al16(phi) && al16(eps) && (MODE == 0 || al16(b)) && al16(out);
     if (tile_ok) {
         const int tx = (p.nx + ATX - 1) / ATX, ty = (p.ny + ATY - 1) / ATY, tz = (nplanes + ZCH - 1) / ZCH;
         const int nb = tx * ty * tz, padded = (nb + 7) / 8 * 8;
-        k_apply_tile<T, MODE><<<padded, dim3(32, 8), 0, s>>>(phi, eps, b, out, p.nx, p.ny, p.nz,
+        k_apply_tile<T, MODE, TB><<<padded, dim3(32, 8), 0, s>>>(phi, eps, b, out, p.nx, p.ny, p.nz,
                                                              1.0 / (p.h[0] * p.h[0]), 1.0 / (p.h[1] * p.h[1]),
                                                              1.0 / (p.h[2] * p.h[2]), p.k_w0, nplanes, tx, ty, nb);
         DWP_LAUNCH_CHECK();
@@ -987,7 +1153,7 @@ void launch_zmarch(hipStream_t s, const Plan &p, const double *phi, const double
     const int tx = (p.nx + BX - 1) / BX, ty = (p.ny + BY - 1) / BY, tz = (nplanes + ZM - 1) / ZM;
     const int nb = tx * ty * tz;
     const int padded = (nb + 7) / 8 * 8;
-    k_apply_zmarch<T, MODE><<<padded, dim3(BX, BY), 0, s>>>(phi, eps, b, out, p.nx, p.ny, p.nz, 1.0 / (p.h[0] * p.h[0]),
+    k_apply_zmarch<T, MODE, TB><<<padded, dim3(BX, BY), 0, s>>>(phi, eps, b, out, p.nx, p.ny, p.nz, 1.0 / (p.h[0] * p.h[0]),
                                                             1.0 / (p.h[1] * p.h[1]), 1.0 / (p.h[2] * p.h[2]), p.k_w0,
                                                             nplanes, tx, ty, nb);
     DWP_LAUNCH_CHECK();
@@ -1075,6 +1241,14 @@ void launch_wet_residual(hipStream_t s, const Plan &p, const double *v, const do
     launch_zmarch<T, 2>(s, p, dD, eps, v, fW, p.nw);
 }
 template <class T>
+void launch_wet_residual_v32(hipStream_t s, const Plan &p, const float *v, const double *dD, const double *eps,
+                             T *fW) {
+    launch_zmarch<T, 2, float>(s, p, dD, eps, v, fW, p.nw);
+}
+void launch_apply_full_f32(hipStream_t s, const Plan &p, const double *phi, const double *eps, float *out) {
+    launch_zmarch<float, 0>(s, p, phi, eps, (const double *)nullptr, out, p.nz);
+}
+template <class T>
 void launch_wet_add(hipStream_t s, const Plan &p, const T *uW, double *z) {
     const int plane = p.nx * p.ny;
     const bool pairs = plane % 2 == 0 && (reinterpret_cast<uintptr_t>(z) & 15) == 0;
@@ -1112,6 +1286,49 @@ void launch_restrict(hipStream_t s, const Level &F, const Level &C, const T *rf,
     k_restrict<T><<<g, blk, 0, s>>>(rf, fc, C.u.as<T>(), F.nx, F.ny, C.nx, C.ny, C.nw, C.zc ? 1 : 0);
     DWP_LAUNCH_CHECK();
 }
+template <class T, int W, bool ZC>
+static void resid_restrict_w(hipStream_t s, const Level &F, const Level &C) {
+    LevelArgs a = level_args(F);
+    const int tx = (F.nx + RFX - 1) / RFX, ty = (F.ny + RFY - 1) / RFY;
+    // coarse planes per block: blocks run in ceil(blocks / slots) rounds of
+    // (fine planes + 2) serial plane steps; pick the chunk with the fewest
+    // steps in all (ties: the longer chunk, fewer halo planes re-read)
+    static int slots[64] = {0};
+    int dev = 0;
+    DWP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) fail(DWP_EINVAL, "internal: device index out of range");
+    if (!slots[dev]) {
+        int cus = 0, per = 0;
+        DWP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        DWP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_resid_restrict<T, W, ZC>, RNT, 0));
+        slots[dev] = std::max(1, cus * per);
+    }
+    int kcc = 1;
+    long best = -1;
+    for (int kq = 1; kq <= C.nw; ++kq) {
+        const long blocks = (long)tx * ty * ((C.nw + kq - 1) / kq);
+        const long cost = (blocks + slots[dev] - 1) / slots[dev] * ((ZC ? 2 * kq + 1 : kq) + 2);
+        if (best < 0 || cost <= best) { best = cost; kcc = kq; }
+    }
+    const int tz = (C.nw + kcc - 1) / kcc;
+    const int nb = tx * ty * tz, padded = (nb + 7) / 8 * 8;
+    k_resid_restrict<T, W, ZC><<<padded, RNT, 0, s>>>(F.u.as<T>(), F.eps.as<T>(), F.f.as<T>(), C.f.as<T>(),
+                                                      C.u.as<T>(), a, C.nx, C.ny, C.nw, tx, ty, kcc, nb);
+    DWP_LAUNCH_CHECK();
+}
+
+// Vector width of the staged rows: 16-byte loads need nx to be a multiple
+// of the vector (always true for a level that has a coarser one: x is halved
+// only when nx is a multiple of 4).
+template <class T>
+void launch_resid_restrict(hipStream_t s, const Level &F, const Level &C) {
+    if (F.nx != 2 * C.nx || F.ny != 2 * C.ny || F.nx % 4 != 0 || (C.zc ? F.nw != 2 * C.nw + 1 : F.nw != C.nw))
+        fail(DWP_EINVAL, "internal: residual-restriction needs x and y halved (z halved or kept)");
+    constexpr int W = sizeof(T) == 4 ? 4 : 2;
+    if (C.zc) resid_restrict_w<T, W, true>(s, F, C);
+    else resid_restrict_w<T, W, false>(s, F, C);
+}
+
 template <class T>
 void launch_prolong_add(hipStream_t s, const Level &F, const Level &C) {
     if (F.nx != 2 * C.nx || F.ny != 2 * C.ny) fail(DWP_EINVAL, "internal: prolongation needs x and y coarsened by 2");
@@ -1218,11 +1435,14 @@ void launch_zero(hipStream_t s, T *x, size_t n) {
 #define DWP_INST(T)                                                                                  \
     template void launch_wet_residual<T>(hipStream_t, const Plan &, const double *, const double *,  \
                                          const double *, T *);                                      \
+    template void launch_wet_residual_v32<T>(hipStream_t, const Plan &, const float *, const double *,  \
+                                             const double *, T *);                                       \
     template void launch_wet_add<T>(hipStream_t, const Plan &, const T *, double *);                  \
     template void launch_wet_eps<T>(hipStream_t, const Plan &, const double *, T *);                  \
     template void launch_level_residual<T>(hipStream_t, const Level &, T *);                          \
     template void launch_level_smooth<T>(hipStream_t, const Level &, int);                            \
     template void launch_restrict<T>(hipStream_t, const Level &, const Level &, const T *, T *);      \
+    template void launch_resid_restrict<T>(hipStream_t, const Level &, const Level &);                \
     template void launch_prolong_add<T>(hipStream_t, const Level &, const Level &);                   \
     template void launch_coarsen_eps<T>(hipStream_t, const Level &, const Level &);                   \
     template void launch_zero<T>(hipStream_t, T *, size_t);                                          \

@@ -282,6 +282,57 @@ int grid1d6(size_t n) {
     return (int)(b > 4096 ? 4096 : b);
 }
 
+// The sixth-order operator on the finest level of the wet multigrid: the
+// slab's unknowns u (a ghosted level array, slab plane q at plane q + 1) are
+// taken as zero on every plane outside the slab -- the Dirichlet data of the
+// wet solve, reaching the three planes the seven-point stencils span beyond
+// it -- and eps, G = D1 eps are the full-box arrays, slab plane q being box
+// plane (k_w0 + q) mod nz.  MODE 0: one weighted-Jacobi sweep of A6_WW u = f,
+// uout = u + omega (f - A6 u) / d, d = B0 eps sum_d 1/h_d^2 the diagonal of A6
+// (the seven-point stencils couple points of equal red-black colour, so the
+// colour ordering of the second-order smoother does not carry over); MODE 1:
+// out = f - A6 u (slab planes, not ghosted).  Sums in float64.
+template <class T, int MODE>
+__global__ void __launch_bounds__(SX *SY)
+k_wet6(const T *__restrict__ u, T *__restrict__ out, const T *__restrict__ f, const double *__restrict__ eps,
+       const double *__restrict__ G, Grid6 g, int k_w0, int nw, double omega) {
+    const int i = blockIdx.x * SX + threadIdx.x, j = blockIdx.y * SY + threadIdx.y, q = blockIdx.z;
+    if (i >= g.nx || j >= g.ny) return;
+    const size_t pl = g.plane;
+    const size_t c = (size_t)j * g.nx + i;
+    const size_t cb = (size_t)((k_w0 + q) % g.nz) * pl + c;
+    auto U = [&](int qq, size_t off) -> double {
+        return (qq < 0 || qq >= nw) ? 0.0 : (double)u[(size_t)(qq + 1) * pl + off];
+    };
+    const size_t row = (size_t)j * g.nx;
+    const double u0 = U(q, c);
+    double xs[3], ys[3], zs[3], xd[3], yd[3], zd[3];
+#pragma unroll
+    for (int n = 1; n <= 3; ++n) {
+        const double xp = U(q, row + wrap(i + n, g.nx)), xm = U(q, row + wrap(i - n, g.nx));
+        const double yp = U(q, (size_t)wrap(j + n, g.ny) * g.nx + i), ym = U(q, (size_t)wrap(j - n, g.ny) * g.nx + i);
+        const double zp = U(q + n, c), zm = U(q - n, c);
+        xs[n - 1] = xp + xm; xd[n - 1] = xp - xm;
+        ys[n - 1] = yp + ym; yd[n - 1] = yp - ym;
+        zs[n - 1] = zp + zm; zd[n - 1] = zp - zm;
+    }
+    const double d1x = g.ihx * (A1 * xd[0] + A2 * xd[1] + A3 * xd[2]);
+    const double d1y = g.ihy * (A1 * yd[0] + A2 * yd[1] + A3 * yd[2]);
+    const double d1z = g.ihz * (A1 * zd[0] + A2 * zd[1] + A3 * zd[2]);
+    const double d2x = g.ihx2 * (B0 * u0 + B1 * xs[0] + B2 * xs[1] + B3 * xs[2]);
+    const double d2y = g.ihy2 * (B0 * u0 + B1 * ys[0] + B2 * ys[1] + B3 * ys[2]);
+    const double d2z = g.ihz2 * (B0 * u0 + B1 * zs[0] + B2 * zs[1] + B3 * zs[2]);
+    const double e = eps[cb];
+    const double a6 = G[cb] * d1x + G[g.N + cb] * d1y + G[2 * g.N + cb] * d1z + e * (d2x + d2y + d2z);
+    const double fv = (double)f[(size_t)q * pl + c];
+    if (MODE == 0) {
+        const double d = e * B0 * (g.ihx2 + g.ihy2 + g.ihz2);
+        out[(size_t)(q + 1) * pl + c] = (T)(u0 + omega * (fv - a6) / d);
+    } else {
+        out[(size_t)q * pl + c] = (T)(fv - a6);
+    }
+}
+
 }  // namespace
 
 void launch_d1eps(hipStream_t s, const Plan &p, const double *eps, double *G) {
@@ -317,6 +368,20 @@ void launch_wet_residual6(hipStream_t s, const Plan &p, const double *v, const d
     if (trans) launch_op6_tile<2, true, T>(s, p, p.k_w0, p.nw, dD, eps, G, v, fW);
     else launch_op6_tile<2, false, T>(s, p, p.k_w0, p.nw, dD, eps, G, v, fW);
 }
+template <class T>
+void launch_wet6(hipStream_t s, const Plan &p, const Level &L, const T *u, T *out, const double *eps, const double *G,
+                 bool smooth, double omega) {
+    if (L.nx != p.nx || L.ny != p.ny || L.nw != p.nw) fail(DWP_EINVAL, "internal: not the finest wet level");
+    dim3 gr((p.nx + SX - 1) / SX, (p.ny + SY - 1) / SY, L.nw), blk(SX, SY);
+    if (smooth) k_wet6<T, 0><<<gr, blk, 0, s>>>(u, out, L.f.as<T>(), eps, G, make_grid6(p), p.k_w0, L.nw, omega);
+    else k_wet6<T, 1><<<gr, blk, 0, s>>>(u, out, L.f.as<T>(), eps, G, make_grid6(p), p.k_w0, L.nw, omega);
+    DWP_LAUNCH_CHECK();
+}
+template void launch_wet6<float>(hipStream_t, const Plan &, const Level &, const float *, float *, const double *,
+                                 const double *, bool, double);
+template void launch_wet6<double>(hipStream_t, const Plan &, const Level &, const double *, double *, const double *,
+                                  const double *, bool, double);
+
 template void launch_wet_residual6<float>(hipStream_t, const Plan &, const double *, const double *, const double *,
                                           const double *, float *, bool);
 template void launch_wet_residual6<double>(hipStream_t, const Plan &, const double *, const double *,

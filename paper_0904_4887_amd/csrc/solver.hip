@@ -321,7 +321,11 @@ void vcycle(dwp_ctx *c, size_t l, bool u_unset) {
     const double ts = (double)sizeof(T);
     const int sg = l == 0 ? PG_RBGS_FINE : PG_RBGS_COARSE;
     const double pass_bytes = 2.0 * ts * (double)L.n_interior();  // half of read u, eps, f + write u
-    const bool fused = c->opts.smoother == 1 && L.n_interior() >= FUSED_MIN_POINTS;
+    // the finest level smooths the sixth-order operator itself (weighted
+    // Jacobi); the adjoint solve keeps the symmetric 7-point smoother, which
+    // approximates A6^T as well as it approximates A6
+    const bool six = l == 0 && c->opts.order == 6 && c->opts.smooth6 == 1 && !c->transposed;
+    const bool fused = !six && c->opts.smoother == 1 && L.n_interior() >= FUSED_MIN_POINTS;
     const bool coarsest = l + 1 == p.levels.size();
     // the first sweep starts from a zero correction on coarse levels and in
     // the first cycle on the fine level, except that without pre-sweeps it
@@ -337,7 +341,13 @@ void vcycle(dwp_ctx *c, size_t l, bool u_unset) {
         return;
     }
     auto smooth = [&](int first) {
-        if (fused) {
+        if (six) {
+            // u, eps, f and the three components of D1 eps read per point, u written
+            PROF(c, sg, (2.0 * ts + 32.0) * (double)L.n_interior(),
+                 launch_wet6<T>(s, p, L, L.u.as<T>(), L.u2.as<T>(), c->eps.as<double>(), c->G6.as<double>(), true,
+                                2.0 / 3.0));
+            std::swap(L.u.p, L.u2.p);
+        } else if (fused) {
             const double b = zero_in ? 1.5 * pass_bytes : 2.0 * pass_bytes;
             PROF(c, sg, b, launch_sweep_fused<T>(s, L, L.u.as<T>(), L.u2.as<T>(), first, zero_in));
             std::swap(L.u.p, L.u2.p);
@@ -353,16 +363,25 @@ void vcycle(dwp_ctx *c, size_t l, bool u_unset) {
     }
     for (int k = 0; k < c->opts.pre; ++k) smooth(0);
     Level &C = *p.levels[l + 1];
-    PROF(c, PG_MG_OTHER, 4.0 * ts * L.n_interior(), launch_level_residual<T>(s, L, L.r.as<T>()));
-    PROF(c, PG_MG_OTHER, ts * (L.n_interior() + C.n_interior() + C.n_ghosted()),
-         launch_restrict<T>(s, L, C, L.r.as<T>(), C.f.as<T>()));
+    if (six) {
+        // the sixth-order residual, then full weighting (which zeroes the coarse unknowns)
+        PROF(c, PG_MG_OTHER, (3.0 * ts + 32.0) * (double)L.n_interior(),
+             launch_wet6<T>(s, p, L, L.u.as<T>(), L.r.as<T>(), c->eps.as<double>(), c->G6.as<double>(), false, 0.0));
+        PROF(c, PG_MG_OTHER, ts * (L.n_interior() + C.n_interior() + C.n_ghosted()),
+             launch_restrict<T>(s, L, C, L.r.as<T>(), C.f.as<T>()));
+    } else {
+        // residual and full-weighting restriction in one pass (u, eps, f read;
+        // the coarse right-hand side written and the coarse unknowns zeroed)
+        PROF(c, PG_MG_OTHER, ts * (3.0 * L.n_interior() + C.n_interior() + C.n_ghosted()),
+             launch_resid_restrict<T>(s, L, C));
+    }
     vcycle<T>(c, l + 1, false);
     PROF(c, PG_MG_OTHER, ts * (C.n_interior() + 2.0 * L.n_interior()), launch_prolong_add<T>(s, L, C));
     for (int k = 0; k < c->opts.post; ++k) smooth(1);
 }
 
-template <class T>
-void split_impl(dwp_ctx *c, const double *v, double *z) {
+template <class T, class TV>
+void split_impl(dwp_ctx *c, const TV *v, double *z) {
     Plan &p = c->plan;
     hipStream_t s = c->stream;
     const bool scaled = c->opts.scaled_dry != 0;
@@ -376,22 +395,27 @@ void split_impl(dwp_ctx *c, const double *v, double *z) {
     }
     Level &F = *p.levels[0];
     const double nW = (double)F.n_interior();
-    if (c->opts.order == 6)
+    if constexpr (sizeof(TV) == 4) {
+        PROF(c, PG_WET, (20.0 + sizeof(T)) * nW, launch_wet_residual_v32<T>(s, p, v, z, c->eps.as<double>(), F.f.as<T>()));
+    } else if (c->opts.order == 6) {
         PROF(c, PG_WET, (48.0 + sizeof(T)) * nW,
              launch_wet_residual6<T>(s, p, v, z, c->eps.as<double>(), c->G6.as<double>(), F.f.as<T>(),
                                      c->transposed));
-    else
+    } else {
         PROF(c, PG_WET, (24.0 + sizeof(T)) * nW,
              launch_wet_residual<T>(s, p, v, z, c->eps.as<double>(), F.f.as<T>()));
+    }
     for (int k = 0; k < c->opts.cycles; ++k) vcycle<T>(c, 0, k == 0);
     PROF(c, PG_WET, (16.0 + sizeof(T)) * nW, launch_wet_add<T>(s, p, F.u.as<T>(), z));
     c->phases.mark(s, PH_KRYLOV);
 }
 
 void apply_split(dwp_ctx *c, const double *v, double *z) {
-    if (c->opts.precision == DWP_MIXED) split_impl<float>(c, v, z);
-    else split_impl<double>(c, v, z);
+    if (c->opts.precision == DWP_MIXED) split_impl<float, double>(c, v, z);
+    else split_impl<double, double>(c, v, z);
 }
+// the split of a float32 Krylov vector (mixed precision, second order)
+void apply_split(dwp_ctx *c, const float *v, double *z) { split_impl<float, float>(c, v, z); }
 
 void check_finite_dev(dwp_ctx *c, const double *x, const char *what) {
     int *flags = reinterpret_cast<int *>(c->partial.as<double>());
@@ -448,6 +472,12 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
     const size_t N = p.N;
     const int m = o.restart;
     double *V = c->V.as<double>(), *Z = c->Z.as<double>();
+    // mixed precision with krylov_fp32: the Arnoldi basis in float32 (every
+    // product, sum and the coupling update x += Z y stay float64; each restart
+    // recomputes the true residual in float64)
+    const bool v32 = c->opts.krylov_fp32 != 0 && c->opts.precision == DWP_MIXED && c->opts.order == 2 &&
+                     c->V32.bytes >= sizeof(float) * N * (m + 1) && krylov32_supported(c->V32.as<float>(), N, N);
+    float *V32 = c->V32.as<float>();
     double *coef = c->coef.as<double>();
     // column j at Hd + j * 72: [0..j] dots, 64 ||w||^2, 65 squared norm of the
     // new vector before any rescaling, 66 the divisor of the fused update
@@ -462,16 +492,19 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
     int iters = 0;
     *restarts = 0;
     for (;;) {
-        // r = b - A x into V_0, ||r||^2 on the device
-        apply_operator(c, x, b, V, true);
-        PROF(c, PG_VEC, 8.0 * N, launch_dot(s, V, V, N, part, beta2));
+        // r = b - A x into V_0 (float64; with a float32 basis into r first),
+        // ||r||^2 on the device
+        double *r0 = v32 ? c->r.as<double>() : V;
+        apply_operator(c, x, b, r0, true);
+        PROF(c, PG_VEC, 8.0 * N, launch_dot(s, r0, r0, N, part, beta2));
         to_host(c, beta2, 1);
         const double beta = std::sqrt(c->host[0]);
         if (!std::isfinite(beta)) fail(DWP_ENONFINITE, "residual is not finite");
         *rel = beta / bnorm;
         if (*rel <= o.tol || iters >= o.max_outer) return iters;
         ++*restarts;
-        PROF(c, PG_VEC, 16.0 * N, launch_scale_dev(s, V, nullptr, beta2, N, 0));
+        if (v32) PROF(c, PG_VEC, 12.0 * N, launch_scale_to32(s, V32, r0, beta2, N));
+        else PROF(c, PG_VEC, 16.0 * N, launch_scale_dev(s, V, nullptr, beta2, N, 0));
         const int mm = std::min(m, o.max_outer - iters);
         // First step after which the host checks the least-squares residual:
         // predicted from the per-step reduction of the last cycle, or, in the
@@ -517,22 +550,32 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
         for (int j = 0; j < mm && !stop; ++j) {
             double *Vj = V + (size_t)j * N, *Vn = V + (size_t)(j + 1) * N, *Zj = Z + (size_t)j * N;
             double *hc = Hd + (size_t)j * HESS_STRIDE;
-            apply_split(c, Vj, Zj);
-            if (c->transposed) {
-                // A6^T does not annihilate the constants (A6 does): keep the
-                // iterate in the zero-mean space where the adjoint is posed
-                PROF(c, PG_VEC, 8.0 * N, launch_sum(s, Zj, N, part, coef + 411));
-                PROF(c, PG_VEC, 16.0 * N, launch_sub_mean(s, Zj, coef + 411, 1.0 / (double)N, N));
-            }
-            apply_operator(c, Zj, nullptr, Vn, false);
-            const double md = 8.0 * N * (j + 2), ax = 8.0 * N * (j + 3);
-            PROF(c, PG_MULTIDOT, md, launch_multidot(s, V, N, j + 1, Vn, N, part, hc, hc + 64));
-            fused[j] = orth_update_supported(V, N, j + 1, N);
-            if (fused[j]) {
-                PROF(c, PG_AXPY, ax, launch_orth_update(s, Vn, V, N, j + 1, hc, N, part));
+            if (v32) {
+                float *Vj32 = V32 + (size_t)j * N, *Vn32 = V32 + (size_t)(j + 1) * N;
+                apply_split(c, (const float *)Vj32, Zj);
+                // A z (float64 in, float32 out), then the projection and update on float32 vectors
+                PROF(c, PG_APPLY, 20.0 * N, launch_apply_full_f32(s, p, Zj, c->eps.as<double>(), Vn32));
+                PROF(c, PG_MULTIDOT, 4.0 * N * (j + 2), launch_multidot32(s, V32, N, j + 1, Vn32, N, part, hc, hc + 64));
+                fused[j] = 1;  // restart <= 16 is checked with the options
+                PROF(c, PG_AXPY, 4.0 * N * (j + 3), launch_orth_update32(s, Vn32, V32, N, j + 1, hc, N, part));
             } else {
-                PROF(c, PG_AXPY, ax, launch_axpy_multi(s, Vn, V, N, j + 1, hc, N, -1.0, part, hc + 65));
-                PROF(c, PG_VEC, 16.0 * N, launch_scale_dev(s, Vn, nullptr, hc + 65, N, 0));
+                apply_split(c, Vj, Zj);
+                if (c->transposed) {
+                    // A6^T does not annihilate the constants (A6 does): keep the
+                    // iterate in the zero-mean space where the adjoint is posed
+                    PROF(c, PG_VEC, 8.0 * N, launch_sum(s, Zj, N, part, coef + 411));
+                    PROF(c, PG_VEC, 16.0 * N, launch_sub_mean(s, Zj, coef + 411, 1.0 / (double)N, N));
+                }
+                apply_operator(c, Zj, nullptr, Vn, false);
+                const double md = 8.0 * N * (j + 2), ax = 8.0 * N * (j + 3);
+                PROF(c, PG_MULTIDOT, md, launch_multidot(s, V, N, j + 1, Vn, N, part, hc, hc + 64));
+                fused[j] = orth_update_supported(V, N, j + 1, N);
+                if (fused[j]) {
+                    PROF(c, PG_AXPY, ax, launch_orth_update(s, Vn, V, N, j + 1, hc, N, part));
+                } else {
+                    PROF(c, PG_AXPY, ax, launch_axpy_multi(s, Vn, V, N, j + 1, hc, N, -1.0, part, hc + 65));
+                    PROF(c, PG_VEC, 16.0 * N, launch_scale_dev(s, Vn, nullptr, hc + 65, N, 0));
+                }
             }
             steps = j + 1;
             if (steps >= check_from || steps == mm) {
@@ -587,6 +630,12 @@ void validate_opts(const dwp_opts &o) {
     if (o.fft_fp32 != 0 && o.fft_fp32 != 1) fail(DWP_EINVAL, "fft_fp32 must be 0 or 1");
     if (o.fft_fp32 && o.precision != DWP_MIXED) fail(DWP_EINVAL, "fft_fp32 needs the mixed precision mode");
     if (o.order != 2 && o.order != 6) fail(DWP_EINVAL, "order must be 2 or 6");
+    if (o.smooth6 != 0 && o.smooth6 != 1) fail(DWP_EINVAL, "smooth6 must be 0 or 1");
+    if (o.smooth6 && o.order != 6) fail(DWP_EINVAL, "smooth6 needs the sixth-order operator (order 6)");
+    if (o.krylov_fp32 != 0 && o.krylov_fp32 != 1) fail(DWP_EINVAL, "krylov_fp32 must be 0 or 1");
+    if (o.krylov_fp32 && (o.precision != DWP_MIXED || o.order != 2))
+        fail(DWP_EINVAL, "krylov_fp32 needs the mixed precision mode and the second-order operator");
+    if (o.krylov_fp32 && o.restart > 16) fail(DWP_EINVAL, "krylov_fp32 takes restart lengths up to 16");
 }
 
 AtomParams atom_params(const dwp_eps_params *ep) {
@@ -711,6 +760,7 @@ void set_grid_impl(dwp_ctx *c, int nx, int ny, int nz, double Lx, double Ly, dou
     c->w.alloc(d * N); c->phi_last.alloc(d * N); c->gbuf.alloc(d * N);
     c->V.alloc(d * N * (opts.restart + 1));
     c->Z.alloc(d * N * opts.restart);
+    if (opts.krylov_fp32) c->V32.alloc(sizeof(float) * N * (opts.restart + 1));
     c->cbuf.alloc(sizeof(double2) * (size_t)p.ldc * ny * nz);
     c->Hz.alloc(d * nz);
     c->partial.alloc(d * (size_t)RED_BLOCKS * 80);
@@ -733,6 +783,7 @@ void set_opts_impl(dwp_ctx *c, const dwp_opts *o) {
             c->V.alloc(sizeof(double) * c->plan.N * (o->restart + 1));
             c->Z.alloc(sizeof(double) * c->plan.N * o->restart);
         }
+        if (o->krylov_fp32) c->V32.alloc(sizeof(float) * c->plan.N * (o->restart + 1));
         const bool replan = o->z_wet_lo != old.z_wet_lo || o->z_wet_hi != old.z_wet_hi ||
                             o->max_levels != old.max_levels ||
                             (std::isnan(o->z_wet_lo) != std::isnan(old.z_wet_lo)) ||
@@ -1179,6 +1230,8 @@ void dwp_default_opts(dwp_opts *o) {
     o->smoother = 1;
     o->fft_fp32 = 0;
     o->order = 2;
+    o->smooth6 = 0;
+    o->krylov_fp32 = 0;
 }
 
 int dwp_create(dwp_ctx **out, int device, void *stream) {

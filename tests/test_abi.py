@@ -21,7 +21,7 @@ def test_default_opts():
     assert o.precision == 0 and o.pre == 2 and o.post == 2 and o.cycles == 1
     assert math.isnan(o.z_wet_lo) and math.isnan(o.z_wet_hi)
     assert o.tol == 1e-10 and o.restart == 10 and o.warm_start == 0 and o.profile == 0
-    assert o.smoother == 1 and o.fft_fp32 == 0 and o.order == 2
+    assert o.smoother == 1 and o.fft_fp32 == 0 and o.order == 2 and o.smooth6 == 0 and o.krylov_fp32 == 0
 
 
 @pytest.mark.parametrize("n", [(30, 32, 64), (32, 32, 6), (32, 32, 70), (32, 32, 8192), (33, 32, 64)])
@@ -35,7 +35,11 @@ def test_plan_rejects_bad_grid_sizes(n):
                                 dict(restart=64), dict(cycles=-1), dict(cycles=65), dict(pre=0, post=0), dict(max_outer=0),
                                 dict(z_wet_lo=8.0, z_wet_hi=8.5), dict(z_wet_lo=0.0, z_wet_hi=20.0),
                                 dict(profile=3), dict(scaled_dry=3), dict(fft_fp32=2),
-                                dict(fft_fp32=1, precision=0), dict(smoother=2), dict(order=4)])
+                                dict(fft_fp32=1, precision=0), dict(smoother=2), dict(order=4),
+                                dict(smooth6=2), dict(smooth6=1), dict(smooth6=1, order=2),
+                                dict(krylov_fp32=2), dict(krylov_fp32=1, precision=0),
+                                dict(krylov_fp32=1, precision=1, order=6),
+                                dict(krylov_fp32=1, precision=1, restart=17)])
 def test_plan_rejects_bad_options(kw):
     with pytest.raises(B.DWPError) as e:
         B.plan((32, 32, 64), (10.0, 10.0, 20.0), **kw)

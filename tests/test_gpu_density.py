@@ -67,7 +67,10 @@ def test_eps_of_density_matches_oracle(torch, n):
 def test_solve_and_v_eps_match_oracle(torch, precision):
     w = W.density_slab((48, 48, 96), tol=1e-11 if precision == 0 else 1e-9, precision=precision)
     rho_e = _density_with_edges(w, 1)
-    s = _solver(w)
+    # the zero and negative densities put isolated eps = eps_inf nodes inside the
+    # dry slab, which the vacuum dry update cannot see: about 400-600 coupling
+    # iterations, so the cap is raised (the test is about parity, not speed)
+    s = _solver(w, max_outer=3000)
     s.build_epsilon_density(_dev(torch, rho_e), **P)
     src = O.rho_gauss(w.n, w.L, w.xyz, w.q, w.sigma)
     phi, E, info = s.solve(_dev(torch, src))

@@ -4,7 +4,8 @@ The 96 x 96 x 192 slab (the literal workload, solver options as benchmarked)
 has a fine wet level of more than 2^20 points, so every sweep of its finest
 multigrid level goes through the fused single-pass kernel.  phi and dE/d eps
 are compared with the oracle node by node over the whole grid, in float64 and
-in mixed precision, against one live oracle solve.
+in mixed precision (with a float64 and with a float32 Arnoldi basis), against
+one live oracle solve.
 """
 import numpy as np
 import pytest
@@ -24,11 +25,11 @@ def case():
     return w, rho, phi, O.energy(rho, phi, w.h), O.eps_gradient(phi, w.h)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_whole_field_matches_oracle_where_fused_sweep_runs(case, precision):
+@pytest.mark.parametrize("precision,krylov_fp32", [(0, 0), (1, 0), (1, 1)])
+def test_whole_field_matches_oracle_where_fused_sweep_runs(case, precision, krylov_fp32):
     from paper_0904_4887_amd.binding import Solver, plan
     w, rho, phi_o, E_o, g_o = case
-    opts = w.solver_opts(precision=precision)
+    opts = w.solver_opts(precision=precision, krylov_fp32=krylov_fp32)
     fine = plan(w.n, w.L, **opts)["levels"][0]
     assert fine[0] * fine[1] * fine[2] >= 1 << 20  # the fused sweep takes this level
     s = Solver(0)
