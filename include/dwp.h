@@ -120,10 +120,11 @@ typedef struct {
                            /* of dwp_eps_gradient / dwp_forces).  0 = 7-point  */
                            /* everywhere                                       */
     int krylov_fp32;       /* mixed precision, order 2, restart <= 16: 1 =     */
-                           /* the Arnoldi basis V is stored in float32 (its    */
-                           /* dot products, the Hessenberg matrix, Z and the   */
-                           /* iterate stay float64; every restart recomputes   */
-                           /* the true residual in float64).  0 = float64 V    */
+                           /* the Krylov bases V and Z are stored in float32   */
+                           /* (every dot product, the Hessenberg matrix, the   */
+                           /* operator's arithmetic and the iterate stay       */
+                           /* float64; every restart recomputes the true       */
+                           /* residual in float64).  0 = float64 bases         */
 } dwp_opts;
 
 /* Per-solve report. */

@@ -224,10 +224,16 @@ void launch_wet_residual(hipStream_t s, const Plan &p, const double *v, const do
 template <class T>
 void launch_wet_residual_v32(hipStream_t s, const Plan &p, const float *v, const double *dD, const double *eps,
                              T *fW);
-// out = A phi rounded to float32 (a float32 Krylov basis vector)
+template <class T>
+void launch_wet_residual_v32(hipStream_t s, const Plan &p, const float *v, const float *dD, const double *eps,
+                             T *fW);
+// out = A phi rounded to float32 (a float32 Krylov basis vector); phi float64 or float32
 void launch_apply_full_f32(hipStream_t s, const Plan &p, const double *phi, const double *eps, float *out);
+void launch_apply_full_f32(hipStream_t s, const Plan &p, const float *phi, const double *eps, float *out);
 template <class T>
 void launch_wet_add(hipStream_t s, const Plan &p, const T *uW, double *z);
+template <class T>
+void launch_wet_add(hipStream_t s, const Plan &p, const T *uW, float *z);
 template <class T>
 void launch_wet_eps(hipStream_t s, const Plan &p, const double *eps, T *epsW);
 
@@ -287,10 +293,14 @@ void fft_plan_axis(FFTAxis &ax, int n, double h, bool half, int order);
 void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay,
                          const FFTAxis &az, const double *r, const double *sinv, void *cbuf,
                          double *out, Profiler *prof, bool fp32);
-// the same with a float32 input (a float32 Krylov basis vector)
+// the same with a float32 input (a float32 Krylov basis vector), and with a
+// float32 output too (a float32 preconditioned basis vector)
 void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay,
                          const FFTAxis &az, const float *r, const double *sinv, void *cbuf,
                          double *out, Profiler *prof, bool fp32);
+void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay,
+                         const FFTAxis &az, const float *r, const double *sinv, void *cbuf,
+                         float *out, Profiler *prof, bool fp32);
 
 // kern_blas.hip: deterministic reductions
 void launch_dot(hipStream_t s, const double *x, const double *y, size_t n, double *partial,
@@ -313,6 +323,8 @@ void launch_multidot32(hipStream_t s, const float *V, size_t ldv, int nv, const 
 void launch_orth_update32(hipStream_t s, float *w, const float *V, size_t ldv, int nv, double *hc, size_t n,
                           double *partial);
 void launch_scale_to32(hipStream_t s, float *x32, const double *r, const double *den_sq, size_t n);
+// x += sum_q c[q] Z_q with float32 Z_q (nv <= 16), float64 x and sums
+void launch_axpy_multi32(hipStream_t s, double *x, const float *Z, size_t ldz, int nv, const double *c, size_t n);
 // energy sums: out[0] = sum rho phi (compensated), out[1] = sum_faces eps_f (D_f phi)^2
 void launch_energy(hipStream_t s, const Plan &p, const double *rho, const double *phi,
                    const double *eps, double *partial, double *out);

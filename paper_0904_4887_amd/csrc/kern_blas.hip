@@ -322,6 +322,32 @@ k_axpy2(double *__restrict__ w, const double *__restrict__ V, size_t ldv, const 
     }
 }
 
+// x += sum_q c[q] Z_q with float32 Z_q: four points per thread (16-byte loads
+// of Z, two 16-byte loads and stores of x), float64 sums.
+template <int NV>
+__global__ void __launch_bounds__(RED_THREADS)
+k_axpy4f(double *__restrict__ x, const float *__restrict__ Z, size_t ldz, const double *__restrict__ c, size_t n4) {
+    __shared__ double cs[NV];
+    if ((int)threadIdx.x < NV) cs[threadIdx.x] = c[threadIdx.x];
+    __syncthreads();
+    double2 *x2 = reinterpret_cast<double2 *>(x);
+    for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n4; t += (size_t)gridDim.x * RED_THREADS) {
+        double2 a = x2[2 * t], b = x2[2 * t + 1];
+        float4 zq[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) zq[q] = reinterpret_cast<const float4 *>(Z + (size_t)q * ldz)[t];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            a.x += cs[q] * (double)zq[q].x;
+            a.y += cs[q] * (double)zq[q].y;
+            b.x += cs[q] * (double)zq[q].z;
+            b.y += cs[q] * (double)zq[q].w;
+        }
+        x2[2 * t] = a;
+        x2[2 * t + 1] = b;
+    }
+}
+
 // out[idx] = sum_b partial[b * stride + idx], one block per idx, fixed order;
 // with norm_out, one more block adds column NORM_SLOT into *norm_out
 __global__ void __launch_bounds__(RED_THREADS)
@@ -527,6 +553,17 @@ static bool quad_ok(const void *a, size_t ldv, size_t n) {
 }
 
 bool krylov32_supported(const float *V, size_t ldv, size_t n) { return quad_ok(V, ldv, n); }
+
+void launch_axpy_multi32(hipStream_t s, double *x, const float *Z, size_t ldz, int nv, const double *c, size_t n) {
+    if (nv < 1 || nv > 16 || !quad_ok(Z, ldz, n) || !quad_ok(x, 0, n)) fail(DWP_EINVAL, "internal: float32 axpy layout");
+    switch (nv) {
+#define DWP_AX4_CASE(K)                                                                     \
+    case K: k_axpy4f<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(x, Z, ldz, c, n / 4); break;
+        DWP_NV_CASES(DWP_AX4_CASE)
+#undef DWP_AX4_CASE
+    }
+    DWP_LAUNCH_CHECK();
+}
 
 void launch_multidot32(hipStream_t s, const float *V, size_t ldv, int nv, const float *w, size_t n, double *partial,
                        double *out, double *norm_out) {

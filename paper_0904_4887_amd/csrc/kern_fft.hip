@@ -225,9 +225,9 @@ k_fft_x_fwd(const TI *__restrict__ in, const double *__restrict__ sinv, cplx<S> 
     }
 }
 
-template <class S>
+template <class S, class TO>
 __global__ void __launch_bounds__(FFT_THREADS)
-k_fft_x_inv(const cplx<S> *__restrict__ in, const double *__restrict__ sinv, double *__restrict__ out,
+k_fft_x_inv(const cplx<S> *__restrict__ in, const double *__restrict__ sinv, TO *__restrict__ out,
             Radices rd, const cplx<S> *__restrict__ tw, int lb, int nrows, int nkx, int ldc, Div dn) {
     using C = cplx<S>;
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -256,11 +256,11 @@ k_fft_x_inv(const cplx<S> *__restrict__ in, const double *__restrict__ sinv, dou
         const C z = lds[l * ls + t];
         const size_t ia = (size_t)ra * n + t, ib = ia + n;
         if (sinv) {
-            out[ia] = (double)z.x * sinv[ia];
-            out[ib] = (double)z.y * sinv[ib];
+            out[ia] = (TO)((double)z.x * sinv[ia]);
+            out[ib] = (TO)((double)z.y * sinv[ib]);
         } else {
-            out[ia] = (double)z.x;
-            out[ib] = (double)z.y;
+            out[ia] = (TO)z.x;
+            out[ib] = (TO)z.y;
         }
     }
 }
@@ -410,9 +410,9 @@ void fft_plan_axis(FFTAxis &ax, int n, double h, bool half, int order) {
     DWP_HIP(hipMemcpy(ax.lam32.p, lam32.data(), sizeof(float) * nl, hipMemcpyHostToDevice));
 }
 
-template <class S, class TI>
+template <class S, class TI, class TO>
 static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay, const FFTAxis &az,
-                           const TI *r, const double *sinv, void *cbuf_v, double *out, Profiler *prof) {
+                           const TI *r, const double *sinv, void *cbuf_v, TO *out, Profiler *prof) {
     using C = cplx<S>;
     C *cbuf = static_cast<C *>(cbuf_v);
     auto TW = [](const FFTAxis &a) { return sizeof(S) == 8 ? a.tw.as<C>() : a.tw32.as<C>(); };
@@ -421,7 +421,7 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
     // scaled) and the half-spectrum (one complex value) read and written once
     const double Cn = (double)p.nkx * p.ny * p.nz, cb = (double)sizeof(C);
     const double bx = (sinv ? 8.0 + sizeof(TI) : (double)sizeof(TI)) * p.N + cb * Cn;
-    const double bxi = (sinv ? 16.0 : 8.0) * p.N + cb * Cn;
+    const double bxi = (sinv ? 8.0 + sizeof(TO) : (double)sizeof(TO)) * p.N + cb * Cn;
     auto pb = [&](int g) { return prof ? prof->begin(st, g) : -1; };
     auto pe = [&](int ev, int g, double b) { if (prof) prof->end(st, ev, g, b); };
     int ev;
@@ -454,21 +454,26 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_Y, 2.0 * cb * Cn);
     ev = pb(PG_FFT_X);
-    k_fft_x_inv<S><<<gx, FFT_THREADS, ldsx, st>>>(cbuf, sinv, out, radices_of(ax), TW(ax), lbx, nrows, p.nkx, p.ldc,
-                                                  dn);
+    k_fft_x_inv<S, TO><<<gx, FFT_THREADS, ldsx, st>>>(cbuf, sinv, out, radices_of(ax), TW(ax), lbx, nrows, p.nkx,
+                                                      p.ldc, dn);
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_X, bxi);
 }
 
 void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay, const FFTAxis &az,
                          const double *r, const double *sinv, void *cbuf, double *out, Profiler *prof, bool fp32) {
-    if (fp32) vacuum_solve_t<float, double>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
-    else vacuum_solve_t<double, double>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
+    if (fp32) vacuum_solve_t<float, double, double>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
+    else vacuum_solve_t<double, double, double>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
 }
 void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay, const FFTAxis &az,
                          const float *r, const double *sinv, void *cbuf, double *out, Profiler *prof, bool fp32) {
-    if (fp32) vacuum_solve_t<float, float>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
-    else vacuum_solve_t<double, float>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
+    if (fp32) vacuum_solve_t<float, float, double>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
+    else vacuum_solve_t<double, float, double>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
+}
+void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay, const FFTAxis &az,
+                         const float *r, const double *sinv, void *cbuf, float *out, Profiler *prof, bool fp32) {
+    if (fp32) vacuum_solve_t<float, float, float>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
+    else vacuum_solve_t<double, float, float>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
 }
 
 }  // namespace dwp

@@ -42,9 +42,9 @@ __device__ __forceinline__ T ld_at(const T *base, unsigned byte_off) {
     return *(const T *)((const char *)base + byte_off);
 }
 
-template <class T, int MODE, class TB>
+template <class T, int MODE, class TB, class TP>
 __global__ void __launch_bounds__(BX *BY)
-k_apply_zmarch(const double *__restrict__ phi, const double *__restrict__ eps, const TB *__restrict__ b,
+k_apply_zmarch(const TP *__restrict__ phi, const double *__restrict__ eps, const TB *__restrict__ b,
                T *__restrict__ out, int nx, int ny, int nz, double cx, double cy, double cz, int k_w0,
                int nplanes, int tiles_x, int tiles_y, int nb_real) {
     const int t = xcd_tile(nb_real);
@@ -55,27 +55,30 @@ k_apply_zmarch(const double *__restrict__ phi, const double *__restrict__ eps, c
     const size_t plane = (size_t)nx * ny;
     // byte offsets inside a plane (the plane base pointers are uniform)
     const int col = j * nx + i;
-    const unsigned oc = (unsigned)col * 8u;
-    const unsigned oxp = (unsigned)(j * nx + wrap_p(i, nx)) * 8u, oxm = (unsigned)(j * nx + wrap_m(i, nx)) * 8u;
-    const unsigned oyp = (unsigned)(wrap_p(j, ny) * nx + i) * 8u, oym = (unsigned)(wrap_m(j, ny) * nx + i) * 8u;
+    // element offsets inside a plane (phi and eps are read at the same ones)
+    const unsigned oc = (unsigned)col;
+    const unsigned oxp = (unsigned)(j * nx + wrap_p(i, nx)), oxm = (unsigned)(j * nx + wrap_m(i, nx));
+    const unsigned oyp = (unsigned)(wrap_p(j, ny) * nx + i), oym = (unsigned)(wrap_m(j, ny) * nx + i);
     const int kk0 = tz * ZM, kk1 = min(nplanes, kk0 + ZM);
     auto boxk = [&](int kk) { return MODE == 2 ? (k_w0 + kk) % nz : kk; };
     auto P = [&](int k) { return phi + (size_t)k * plane; };
     auto E = [&](int k) { return eps + (size_t)k * plane; };
+    auto lp = [](const TP *base, unsigned o) { return (double)base[o]; };
     // Software pipeline: the centre values of plane k+1 and the in-plane
     // neighbours of plane k are loaded one plane ahead of their use.
     int k = boxk(kk0);
     const int km = wrap_m(k, nz);
-    double pm = ld_at(P(km), oc), em = ld_at(E(km), oc), p0 = ld_at(P(k), oc), e0 = ld_at(E(k), oc);
+    double pm = lp(P(km), oc), em = E(km)[oc], p0 = lp(P(k), oc), e0 = E(k)[oc];
     double nb[8];
     auto load_nb = [&](int kq, double *o) {
-        const double *pp = P(kq), *ee = E(kq);
-        o[0] = ld_at(pp, oxp); o[1] = ld_at(ee, oxp); o[2] = ld_at(pp, oxm); o[3] = ld_at(ee, oxm);
-        o[4] = ld_at(pp, oyp); o[5] = ld_at(ee, oyp); o[6] = ld_at(pp, oym); o[7] = ld_at(ee, oym);
+        const TP *pq = P(kq);
+        const double *ee = E(kq);
+        o[0] = lp(pq, oxp); o[1] = ee[oxp]; o[2] = lp(pq, oxm); o[3] = ee[oxm];
+        o[4] = lp(pq, oyp); o[5] = ee[oyp]; o[6] = lp(pq, oym); o[7] = ee[oym];
     };
     load_nb(k, nb);
     int kp = wrap_p(k, nz);
-    double pp = ld_at(P(kp), oc), ep = ld_at(E(kp), oc);
+    double pp = lp(P(kp), oc), ep = E(kp)[oc];
     for (int kk = kk0; kk < kk1; ++kk) {
         // prefetch for plane kk + 1 (clamped inside the chunk: always a valid address)
         const bool more = kk + 1 < kk1;
@@ -83,7 +86,7 @@ k_apply_zmarch(const double *__restrict__ phi, const double *__restrict__ eps, c
         const int kq = more ? kn : kp;
         double nb2[8];
         load_nb(kp, nb2);
-        const double pq = ld_at(P(kq), oc), eq = ld_at(E(kq), oc);
+        const double pq = lp(P(kq), oc), eq = E(kq)[oc];
         double acc = cx * ((e0 + nb[1]) * (nb[0] - p0) + (e0 + nb[3]) * (nb[2] - p0)) +
                      cy * ((e0 + nb[5]) * (nb[4] - p0) + (e0 + nb[7]) * (nb[6] - p0)) +
                      cz * ((e0 + ep) * (pp - p0) + (e0 + em) * (pm - p0));
@@ -114,9 +117,16 @@ constexpr int AQ = AHX2 * AHY;              // double2 items per field per plane
 constexpr int AQT = (AQ + 255) / 256;       // per thread
 constexpr int ZCH = 16;                     // planes per block
 
-template <class T, int MODE, class TB>
+// two consecutive values of a float64 or float32 field at element offset o, as double2
+__device__ __forceinline__ double2 ld2(const double *base, unsigned o) { return ld_at((const double2 *)base, o * 8u); }
+__device__ __forceinline__ double2 ld2(const float *base, unsigned o) {
+    const float2 v = ld_at((const float2 *)base, o * 4u);
+    return make_double2(v.x, v.y);
+}
+
+template <class T, int MODE, class TB, class TP>
 __global__ void __launch_bounds__(256)
-k_apply_tile(const double *__restrict__ phi, const double *__restrict__ eps, const TB *__restrict__ b,
+k_apply_tile(const TP *__restrict__ phi, const double *__restrict__ eps, const TB *__restrict__ b,
              T *__restrict__ out, int nx, int ny, int nz, double cx, double cy, double cz, int k_w0, int nplanes,
              int tiles_x, int tiles_y, int nb_real) {
     __shared__ double2 sp[2][AQT * 256], se[2][AQT * 256];
@@ -132,23 +142,24 @@ k_apply_tile(const double *__restrict__ phi, const double *__restrict__ eps, con
         const int q = min(tid + 256 * m, AQ - 1);  // padding lanes repeat the last item
         const int xr = q % AHX2, yr = q / AHX2;
         const int x = ((i0 - 2 + 2 * xr) % nx + nx) % nx, y = ((j0 - 1 + yr) % ny + ny) % ny;
-        oq[m] = (unsigned)(y * nx + x) * 8u;
+        oq[m] = (unsigned)(y * nx + x);  // element offset
     }
     const int lx = threadIdx.x, ly = threadIdx.y;
     const int gi = i0 + 2 * lx, gj = j0 + ly;
     const bool own = gi < nx && gj < ny;
-    const unsigned oc = own ? (unsigned)(gj * nx + gi) * 8u : 0u;
+    const unsigned oc = own ? (unsigned)(gj * nx + gi) : 0u;  // element offset
     auto wrapk = [&](int k) { return k < 0 ? k + nz : (k >= nz ? k - nz : k); };
     auto P = [&](int k) { return phi + (size_t)wrapk(k) * plane; };
     auto E = [&](int k) { return eps + (size_t)wrapk(k) * plane; };
     const int kb0 = MODE == 2 ? (k_w0 + kk0) % nz : kk0;  // box plane of the first step
     double2 tp[AQT], te[AQT];
     auto fetch_tile = [&](int k) {
-        const double *pp = P(k), *ee = E(k);
+        const TP *pp = P(k);
+        const double *ee = E(k);
 #pragma unroll
         for (int m = 0; m < AQT; ++m) {
-            tp[m] = ld_at((const double2 *)pp, oq[m]);
-            te[m] = ld_at((const double2 *)ee, oq[m]);
+            tp[m] = ld2(pp, oq[m]);
+            te[m] = ld2(ee, oq[m]);
         }
     };
     auto stash = [&](int slot) {
@@ -158,13 +169,13 @@ k_apply_tile(const double *__restrict__ phi, const double *__restrict__ eps, con
             se[slot][tid + 256 * m] = te[m];
         }
     };
-    double2 pm = ld_at((const double2 *)P(kb0 - 1), oc), em = ld_at((const double2 *)E(kb0 - 1), oc);
-    double2 p0 = ld_at((const double2 *)P(kb0), oc), e0 = ld_at((const double2 *)E(kb0), oc);
-    double2 pp = ld_at((const double2 *)P(kb0 + 1), oc), ep = ld_at((const double2 *)E(kb0 + 1), oc);
+    double2 pm = ld2(P(kb0 - 1), oc), em = ld2(E(kb0 - 1), oc);
+    double2 p0 = ld2(P(kb0), oc), e0 = ld2(E(kb0), oc);
+    double2 pp = ld2(P(kb0 + 1), oc), ep = ld2(E(kb0 + 1), oc);
     fetch_tile(kb0);
     stash(0);
     fetch_tile(kb0 + 1);
-    double2 pn = ld_at((const double2 *)P(kb0 + 2), oc), en = ld_at((const double2 *)E(kb0 + 2), oc);
+    double2 pn = ld2(P(kb0 + 2), oc), en = ld2(E(kb0 + 2), oc);
     const int r = ly + 1, c2 = lx + 1;
     for (int kk = kk0; kk < kk1; ++kk) {
         const int s = (kk - kk0) & 1;
@@ -172,7 +183,7 @@ k_apply_tile(const double *__restrict__ phi, const double *__restrict__ eps, con
         __syncthreads();
         stash(s ^ 1);  // plane k + 1
         fetch_tile(k + 2);
-        const double2 pq = ld_at((const double2 *)P(k + 3), oc), eq = ld_at((const double2 *)E(k + 3), oc);
+        const double2 pq = ld2(P(k + 3), oc), eq = ld2(E(k + 3), oc);
         const double2 *lp = sp[s], *le = se[s];
         const double2 xl_p = lp[r * AHX2 + c2 - 1], xl_e = le[r * AHX2 + c2 - 1];
         const double2 xr_p = lp[r * AHX2 + c2 + 1], xr_e = le[r * AHX2 + c2 + 1];
@@ -190,19 +201,13 @@ k_apply_tile(const double *__restrict__ phi, const double *__restrict__ eps, con
             const size_t dst = (size_t)(MODE == 2 ? kk : k) * plane + (size_t)(gj * nx + gi);
             if (MODE == 0) {
                 if constexpr (sizeof(T) == 8) {
-                    *(double2 *)((char *)(out + (size_t)k * plane) + oc) = make_double2(a0, a1);
+                    *(double2 *)(out + dst) = make_double2(a0, a1);
                 } else {
                     *(float2 *)(out + dst) = make_float2((float)a0, (float)a1);
                 }
             } else {
-                double bx, by;
-                if constexpr (sizeof(TB) == 8) {
-                    const double2 bv = ld_at((const double2 *)(b + (size_t)k * plane), oc);
-                    bx = bv.x; by = bv.y;
-                } else {
-                    const float2 bv = *(const float2 *)(b + (size_t)k * plane + (size_t)(gj * nx + gi));
-                    bx = bv.x; by = bv.y;
-                }
+                const double2 bv = ld2(b + (size_t)k * plane, oc);
+                const double bx = bv.x, by = bv.y;
                 out[dst] = (T)(bx - a0);
                 out[dst + 1] = (T)(by - a1);
             }
@@ -350,21 +355,26 @@ __global__ void k_check(const double *x, size_t n, int *flags, int check_ge1) {
 // z at box plane (k_w0 + kk) mod nz += uW (ghosted plane kk + 1).  Grid:
 // (plane chunks, kk); PAIRS: two consecutive points per thread (plane even,
 // z 16-byte aligned).
-template <class T, bool PAIRS>
-__global__ void k_wet_add(const T *__restrict__ uW, double *__restrict__ z, int plane, int nz, int k_w0) {
+template <class T, bool PAIRS, class TZ>
+__global__ void k_wet_add(const T *__restrict__ uW, TZ *__restrict__ z, int plane, int nz, int k_w0) {
     const int kk = blockIdx.y;
     const int k = (k_w0 + kk) % nz;
     const T *src = uW + (size_t)(kk + 1) * plane;
-    double *dst = z + (size_t)k * plane;
+    TZ *dst = z + (size_t)k * plane;
     const int q = (PAIRS ? 2 : 1) * (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (q >= plane) return;
-    if (PAIRS) {
+    if constexpr (PAIRS && sizeof(TZ) == 8) {
         double2 v = *reinterpret_cast<double2 *>(dst + q);
         v.x += (double)src[q];
         v.y += (double)src[q + 1];
         *reinterpret_cast<double2 *>(dst + q) = v;
+    } else if constexpr (PAIRS) {
+        float2 v = *reinterpret_cast<float2 *>(dst + q);
+        v.x = (float)((double)v.x + (double)src[q]);
+        v.y = (float)((double)v.y + (double)src[q + 1]);
+        *reinterpret_cast<float2 *>(dst + q) = v;
     } else {
-        dst[q] += (double)src[q];
+        dst[q] = (TZ)((double)dst[q] + (double)src[q]);
     }
 }
 
@@ -1137,14 +1147,14 @@ LevelArgs level_args(const Level &L) {
 // ============================================================== launchers
 static bool al16(const void *q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; }
 
-template <class T, int MODE, class TB = double>
-void launch_zmarch(hipStream_t s, const Plan &p, const double *phi, const double *eps, const TB *b, T *out,
+template <class T, int MODE, class TB = double, class TP = double>
+void launch_zmarch(hipStream_t s, const Plan &p, const TP *phi, const double *eps, const TB *b, T *out,
                    int nplanes) {
     const bool tile_ok = p.nx % 2 == 0 && al16(phi) && al16(eps) && (MODE == 0 || al16(b)) && al16(out);
     if (tile_ok) {
         const int tx = (p.nx + ATX - 1) / ATX, ty = (p.ny + ATY - 1) / ATY, tz = (nplanes + ZCH - 1) / ZCH;
         const int nb = tx * ty * tz, padded = (nb + 7) / 8 * 8;
-        k_apply_tile<T, MODE, TB><<<padded, dim3(32, 8), 0, s>>>(phi, eps, b, out, p.nx, p.ny, p.nz,
+        k_apply_tile<T, MODE, TB, TP><<<padded, dim3(32, 8), 0, s>>>(phi, eps, b, out, p.nx, p.ny, p.nz,
                                                              1.0 / (p.h[0] * p.h[0]), 1.0 / (p.h[1] * p.h[1]),
                                                              1.0 / (p.h[2] * p.h[2]), p.k_w0, nplanes, tx, ty, nb);
         DWP_LAUNCH_CHECK();
@@ -1153,7 +1163,7 @@ void launch_zmarch(hipStream_t s, const Plan &p, const double *phi, const double
     const int tx = (p.nx + BX - 1) / BX, ty = (p.ny + BY - 1) / BY, tz = (nplanes + ZM - 1) / ZM;
     const int nb = tx * ty * tz;
     const int padded = (nb + 7) / 8 * 8;
-    k_apply_zmarch<T, MODE, TB><<<padded, dim3(BX, BY), 0, s>>>(phi, eps, b, out, p.nx, p.ny, p.nz, 1.0 / (p.h[0] * p.h[0]),
+    k_apply_zmarch<T, MODE, TB, TP><<<padded, dim3(BX, BY), 0, s>>>(phi, eps, b, out, p.nx, p.ny, p.nz, 1.0 / (p.h[0] * p.h[0]),
                                                             1.0 / (p.h[1] * p.h[1]), 1.0 / (p.h[2] * p.h[2]), p.k_w0,
                                                             nplanes, tx, ty, nb);
     DWP_LAUNCH_CHECK();
@@ -1245,19 +1255,31 @@ void launch_wet_residual_v32(hipStream_t s, const Plan &p, const float *v, const
                              T *fW) {
     launch_zmarch<T, 2, float>(s, p, dD, eps, v, fW, p.nw);
 }
+template <class T>
+void launch_wet_residual_v32(hipStream_t s, const Plan &p, const float *v, const float *dD, const double *eps,
+                             T *fW) {
+    launch_zmarch<T, 2, float, float>(s, p, dD, eps, v, fW, p.nw);
+}
 void launch_apply_full_f32(hipStream_t s, const Plan &p, const double *phi, const double *eps, float *out) {
     launch_zmarch<float, 0>(s, p, phi, eps, (const double *)nullptr, out, p.nz);
 }
-template <class T>
-void launch_wet_add(hipStream_t s, const Plan &p, const T *uW, double *z) {
+void launch_apply_full_f32(hipStream_t s, const Plan &p, const float *phi, const double *eps, float *out) {
+    launch_zmarch<float, 0, double, float>(s, p, phi, eps, (const double *)nullptr, out, p.nz);
+}
+template <class T, class TZ>
+static void wet_add_t(hipStream_t s, const Plan &p, const T *uW, TZ *z) {
     const int plane = p.nx * p.ny;
     const bool pairs = plane % 2 == 0 && (reinterpret_cast<uintptr_t>(z) & 15) == 0;
     const int per = pairs ? plane / 2 : plane;
     dim3 g((per + 255) / 256, p.nw);
-    if (pairs) k_wet_add<T, true><<<g, 256, 0, s>>>(uW, z, plane, p.nz, p.k_w0);
-    else k_wet_add<T, false><<<g, 256, 0, s>>>(uW, z, plane, p.nz, p.k_w0);
+    if (pairs) k_wet_add<T, true, TZ><<<g, 256, 0, s>>>(uW, z, plane, p.nz, p.k_w0);
+    else k_wet_add<T, false, TZ><<<g, 256, 0, s>>>(uW, z, plane, p.nz, p.k_w0);
     DWP_LAUNCH_CHECK();
 }
+template <class T>
+void launch_wet_add(hipStream_t s, const Plan &p, const T *uW, double *z) { wet_add_t<T, double>(s, p, uW, z); }
+template <class T>
+void launch_wet_add(hipStream_t s, const Plan &p, const T *uW, float *z) { wet_add_t<T, float>(s, p, uW, z); }
 template <class T>
 void launch_wet_eps(hipStream_t s, const Plan &p, const double *eps, T *epsW) {
     const size_t n = (size_t)p.nx * p.ny * (p.nw + 2);
@@ -1437,7 +1459,10 @@ void launch_zero(hipStream_t s, T *x, size_t n) {
                                          const double *, T *);                                      \
     template void launch_wet_residual_v32<T>(hipStream_t, const Plan &, const float *, const double *,  \
                                              const double *, T *);                                       \
+    template void launch_wet_residual_v32<T>(hipStream_t, const Plan &, const float *, const float *,   \
+                                             const double *, T *);                                       \
     template void launch_wet_add<T>(hipStream_t, const Plan &, const T *, double *);                  \
+    template void launch_wet_add<T>(hipStream_t, const Plan &, const T *, float *);                   \
     template void launch_wet_eps<T>(hipStream_t, const Plan &, const double *, T *);                  \
     template void launch_level_residual<T>(hipStream_t, const Level &, T *);                          \
     template void launch_level_smooth<T>(hipStream_t, const Level &, int);                            \

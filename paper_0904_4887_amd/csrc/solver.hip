@@ -380,8 +380,8 @@ void vcycle(dwp_ctx *c, size_t l, bool u_unset) {
     for (int k = 0; k < c->opts.post; ++k) smooth(1);
 }
 
-template <class T, class TV>
-void split_impl(dwp_ctx *c, const TV *v, double *z) {
+template <class T, class TV, class TZ>
+void split_impl(dwp_ctx *c, const TV *v, TZ *z) {
     Plan &p = c->plan;
     hipStream_t s = c->stream;
     const bool scaled = c->opts.scaled_dry != 0;
@@ -396,7 +396,8 @@ void split_impl(dwp_ctx *c, const TV *v, double *z) {
     Level &F = *p.levels[0];
     const double nW = (double)F.n_interior();
     if constexpr (sizeof(TV) == 4) {
-        PROF(c, PG_WET, (20.0 + sizeof(T)) * nW, launch_wet_residual_v32<T>(s, p, v, z, c->eps.as<double>(), F.f.as<T>()));
+        PROF(c, PG_WET, (12.0 + sizeof(TZ) + sizeof(T)) * nW,
+             launch_wet_residual_v32<T>(s, p, v, z, c->eps.as<double>(), F.f.as<T>()));
     } else if (c->opts.order == 6) {
         PROF(c, PG_WET, (48.0 + sizeof(T)) * nW,
              launch_wet_residual6<T>(s, p, v, z, c->eps.as<double>(), c->G6.as<double>(), F.f.as<T>(),
@@ -406,16 +407,18 @@ void split_impl(dwp_ctx *c, const TV *v, double *z) {
              launch_wet_residual<T>(s, p, v, z, c->eps.as<double>(), F.f.as<T>()));
     }
     for (int k = 0; k < c->opts.cycles; ++k) vcycle<T>(c, 0, k == 0);
-    PROF(c, PG_WET, (16.0 + sizeof(T)) * nW, launch_wet_add<T>(s, p, F.u.as<T>(), z));
+    PROF(c, PG_WET, (2.0 * sizeof(TZ) + sizeof(T)) * nW, launch_wet_add<T>(s, p, F.u.as<T>(), z));
     c->phases.mark(s, PH_KRYLOV);
 }
 
 void apply_split(dwp_ctx *c, const double *v, double *z) {
-    if (c->opts.precision == DWP_MIXED) split_impl<float, double>(c, v, z);
-    else split_impl<double, double>(c, v, z);
+    if (c->opts.precision == DWP_MIXED) split_impl<float, double, double>(c, v, z);
+    else split_impl<double, double, double>(c, v, z);
 }
-// the split of a float32 Krylov vector (mixed precision, second order)
-void apply_split(dwp_ctx *c, const float *v, double *z) { split_impl<float, float>(c, v, z); }
+// the split of a float32 Krylov vector into a float32 one (mixed precision,
+// second order): z is rounded to float32 where it is stored, and the Krylov
+// method uses the stored z as it is
+void apply_split(dwp_ctx *c, const float *v, float *z) { split_impl<float, float, float>(c, v, z); }
 
 void check_finite_dev(dwp_ctx *c, const double *x, const char *what) {
     int *flags = reinterpret_cast<int *>(c->partial.as<double>());
@@ -476,8 +479,10 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
     // product, sum and the coupling update x += Z y stay float64; each restart
     // recomputes the true residual in float64)
     const bool v32 = c->opts.krylov_fp32 != 0 && c->opts.precision == DWP_MIXED && c->opts.order == 2 &&
-                     c->V32.bytes >= sizeof(float) * N * (m + 1) && krylov32_supported(c->V32.as<float>(), N, N);
+                     c->V32.bytes >= sizeof(float) * N * (m + 1) && krylov32_supported(c->V32.as<float>(), N, N) &&
+                     krylov32_supported(c->Z.as<float>(), N, N);
     float *V32 = c->V32.as<float>();
+    float *Z32 = c->Z.as<float>();  // with v32 the Z buffer holds float32 vectors
     double *coef = c->coef.as<double>();
     // column j at Hd + j * 72: [0..j] dots, 64 ||w||^2, 65 squared norm of the
     // new vector before any rescaling, 66 the divisor of the fused update
@@ -551,10 +556,10 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
             double *Vj = V + (size_t)j * N, *Vn = V + (size_t)(j + 1) * N, *Zj = Z + (size_t)j * N;
             double *hc = Hd + (size_t)j * HESS_STRIDE;
             if (v32) {
-                float *Vj32 = V32 + (size_t)j * N, *Vn32 = V32 + (size_t)(j + 1) * N;
-                apply_split(c, (const float *)Vj32, Zj);
-                // A z (float64 in, float32 out), then the projection and update on float32 vectors
-                PROF(c, PG_APPLY, 20.0 * N, launch_apply_full_f32(s, p, Zj, c->eps.as<double>(), Vn32));
+                float *Vj32 = V32 + (size_t)j * N, *Vn32 = V32 + (size_t)(j + 1) * N, *Zj32 = Z32 + (size_t)j * N;
+                apply_split(c, (const float *)Vj32, Zj32);
+                // A z (float64 arithmetic, float32 out), then the projection and update on float32 vectors
+                PROF(c, PG_APPLY, 16.0 * N, launch_apply_full_f32(s, p, (const float *)Zj32, c->eps.as<double>(), Vn32));
                 PROF(c, PG_MULTIDOT, 4.0 * N * (j + 2), launch_multidot32(s, V32, N, j + 1, Vn32, N, part, hc, hc + 64));
                 fused[j] = 1;  // restart <= 16 is checked with the options
                 PROF(c, PG_AXPY, 4.0 * N * (j + 3), launch_orth_update32(s, Vn32, V32, N, j + 1, hc, N, part));
@@ -600,7 +605,8 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
         }
         for (int i = 0; i < k; ++i) c->host[i] = y[i];
         DWP_HIP(hipMemcpyAsync(coef + 192, c->host, sizeof(double) * k, hipMemcpyHostToDevice, s));
-        PROF(c, PG_AXPY, 8.0 * N * (k + 2), launch_axpy_multi(s, x, Z, N, k, coef + 192, N, 1.0, part, nullptr));
+        if (v32) PROF(c, PG_AXPY, (4.0 * k + 16.0) * N, launch_axpy_multi32(s, x, Z32, N, k, coef + 192, N));
+        else PROF(c, PG_AXPY, 8.0 * N * (k + 2), launch_axpy_multi(s, x, Z, N, k, coef + 192, N, 1.0, part, nullptr));
         sync(c);  // the staging buffer is reused next
     }
 }
