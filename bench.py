@@ -186,6 +186,22 @@ def errors_vs_oracle(name, E, info, phi, F, torch):
     return out
 
 
+def one_pass_errors():
+    """The stored error of the paper's one-pass dry/wet split (the FFT, then
+    one wet solve with the FFT potential as boundary data) against the exact
+    discrete solution, for the five headline configurations: written by the
+    oracle alone (tests/golden/make_golden.py one_pass)."""
+    out = {}
+    for name in ("tanh_box_32x32x64", "slab_96x96x192", "slab_128x128x256", "slab_192x192x384",
+                 "big_slab_256x256x512"):
+        p = os.path.join(ROOT, "tests", "golden", f"oracle_one_pass_{name}.json")
+        if os.path.exists(p):
+            with open(p) as f:
+                d = json.load(f)
+            out[name] = {k: d[k] for k in ("rel_energy_error", "rel_l2_phi_error", "rel_max_phi_error")}
+    return out
+
+
 def cpu_widened(gpu_ms):
     """The oracle beside the widened paths, on bounded samples (one thread):
     the dummy-density permittivity at 1/64 of the 192x192x384 nodes, scaled to
@@ -526,7 +542,8 @@ def main():
     kernels = {k: {"ms_per_step": round(v["ms"] / 2, 3), "launches_per_step": v["launches"] / 2,
                    "GB/s": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)} for k, v in profb.items()}
 
-    extra = {"smoother_instrumented_ms_per_step": round(1e3 * sec, 3)}
+    extra = {"smoother_instrumented_ms_per_step": round(1e3 * sec, 3),
+             "one_pass_split_error_oracle": one_pass_errors()}
     if not args.no_compare:
         other = "fp64" if args.precision == "mixed" else "mixed"
         s2 = solver_for(w, other, torch)

@@ -264,6 +264,7 @@ template <class T>
 void launch_vcycle_bottom(hipStream_t s, const std::vector<Level *> &levels, size_t l0, int pre, int post,
                           int coarse_sweeps);
 constexpr size_t BOTTOM_MAX_POINTS = 8192;     // levels this small (and below) go to the bottom kernel
+constexpr size_t BOTTOM_LDS_BYTES = 160 * 1024;  // the bottom set runs out of LDS when it fits this
 constexpr size_t FUSED_MIN_POINTS = 1u << 20;  // levels this large use the fused sweep
 
 // kern_sixth.hip: the sixth-order operator (order = 6)
@@ -318,6 +319,9 @@ void launch_orth_update(hipStream_t s, double *w, const double *V, size_t ldv, i
 // float32 Krylov basis (mixed precision): projections and update in float64
 // arithmetic on float32 vectors (n and ldv multiples of 4, 16-byte aligned)
 bool krylov32_supported(const float *V, size_t ldv, size_t n);
+// the float32 orth update rescales its result to unit norm only when that norm
+// is off 1 by more than this (float64 vectors: 1e-8)
+constexpr double RESCALE_TOL_F32 = 1e-6;
 void launch_multidot32(hipStream_t s, const float *V, size_t ldv, int nv, const float *w, size_t n, double *partial,
                        double *out, double *norm_out);
 void launch_orth_update32(hipStream_t s, float *w, const float *V, size_t ldv, int nv, double *hc, size_t n,

@@ -261,8 +261,10 @@ k_rescale_if_f(float *__restrict__ x, const double *__restrict__ partial, int np
         if (blockIdx.x == 0) *nu2 = r;
     }
     __syncthreads();
+    // float32 storage leaves |nu - 1| near 1e-7 even when beta is exact, so
+    // the stored vector is taken as it is unless it is off by more than 1e-6
     const double nu = sqrt(tot);
-    if (nu == 0.0 || fabs(nu - 1.0) <= 1e-8) return;
+    if (nu == 0.0 || fabs(nu - 1.0) <= RESCALE_TOL_F32) return;
     const double s = 1.0 / nu;
     for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n; t += (size_t)gridDim.x * RED_THREADS)
         x[t] = (float)((double)x[t] * s);

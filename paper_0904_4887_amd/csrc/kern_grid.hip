@@ -1125,6 +1125,63 @@ __global__ void __launch_bounds__(1024) k_vcycle_bottom(Bottom<T> B) {
     }
 }
 
+// The same V-cycle with every array of the bottom set in LDS (up to 160 KB
+// per workgroup on gfx950): the first level's u and f and every level's eps
+// are staged in once, u is written back at the end, and every phase between
+// reads and writes LDS only.  off[4 l + {0,1,2,3}] are the element offsets of
+// level l's u (ghosted), f, r (interior) and eps (ghosted) in LDS.
+struct BottomLds {
+    int off[4 * MAX_BOTTOM];
+};
+template <class T>
+__global__ void __launch_bounds__(1024) k_vcycle_bottom_lds(Bottom<T> B, BottomLds O) {
+    extern __shared__ __align__(16) unsigned char bl_raw[];
+    T *lds = reinterpret_cast<T *>(bl_raw);
+    auto D = [&](int l) {
+        LevelDesc<T> d = B.L[l];
+        d.u = lds + O.off[4 * l];
+        d.f = lds + O.off[4 * l + 1];
+        d.r = lds + O.off[4 * l + 2];
+        d.e = lds + O.off[4 * l + 3];
+        return d;
+    };
+    for (int l = 0; l < B.nl; ++l) {
+        const LevelArgs &a = B.L[l].a;
+        const int ng = a.nx * a.ny * (a.nw + 2);
+        T *e = lds + O.off[4 * l + 3];
+        for (int q = threadIdx.x; q < ng; q += blockDim.x) e[q] = B.L[l].e[q];
+    }
+    {
+        const LevelArgs &a = B.L[0].a;
+        const int ni = a.nx * a.ny * a.nw, ng = ni + 2 * a.nx * a.ny;
+        T *u = lds + O.off[0], *f = lds + O.off[1];
+        for (int q = threadIdx.x; q < ng; q += blockDim.x) u[q] = B.L[0].u[q];
+        for (int q = threadIdx.x; q < ni; q += blockDim.x) f[q] = B.L[0].f[q];
+    }
+    __syncthreads();
+    for (int l = 0; l + 1 < B.nl; ++l) {
+        const LevelDesc<T> d = D(l);
+        for (int k = 0; k < B.pre; ++k) { bt_smooth(d, 0); bt_smooth(d, 1); }
+        bt_residual(d);
+        bt_restrict_zero(d, D(l + 1));
+    }
+    {
+        const LevelDesc<T> c = D(B.nl - 1);
+        for (int k = 0; k < B.coarse; ++k) { bt_smooth(c, 0); bt_smooth(c, 1); }
+    }
+    for (int l = B.nl - 2; l >= 0; --l) {
+        const LevelDesc<T> d = D(l);
+        bt_prolong(d, D(l + 1));
+        for (int k = 0; k < B.post; ++k) { bt_smooth(d, 1); bt_smooth(d, 0); }
+    }
+    {
+        const LevelArgs &a = B.L[0].a;
+        const int ng = a.nx * a.ny * (a.nw + 2);
+        const T *u = lds + O.off[0];
+        for (int q = threadIdx.x; q < ng; q += blockDim.x) B.L[0].u[q] = u[q];
+    }
+}
+
 inline int grid1d(size_t n, int threads = 256) {
     size_t b = (n + threads - 1) / threads;
     if (b > 16384) b = 16384;
@@ -1444,7 +1501,30 @@ void launch_vcycle_bottom(hipStream_t s, const std::vector<Level *> &levels, siz
     B.pre = pre;
     B.post = post;
     B.coarse = coarse_sweeps;
-    k_vcycle_bottom<T><<<1, 1024, 0, s>>>(B);
+    // LDS layout of the whole bottom set, if it fits one workgroup's LDS
+    BottomLds O{};
+    size_t at = 0;
+    for (int l = 0; l < B.nl; ++l) {
+        const Level &L = *levels[l0 + l];
+        const size_t ng = L.n_ghosted(), ni = L.n_interior();
+        O.off[4 * l] = (int)at; at += ng;
+        O.off[4 * l + 1] = (int)at; at += ni;
+        O.off[4 * l + 2] = (int)at; at += ni;
+        O.off[4 * l + 3] = (int)at; at += ng;
+        at = (at + 3) / 4 * 4;  // keep every array 16-byte aligned
+    }
+    const size_t bytes = at * sizeof(T);
+    if (bytes <= BOTTOM_LDS_BYTES) {
+        static bool attr_set = false;  // per process: the attribute belongs to the kernel, not the device
+        if (!attr_set) {
+            DWP_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_vcycle_bottom_lds<T>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)BOTTOM_LDS_BYTES));
+            attr_set = true;
+        }
+        k_vcycle_bottom_lds<T><<<1, 1024, bytes, s>>>(B, O);
+    } else {
+        k_vcycle_bottom<T><<<1, 1024, 0, s>>>(B);
+    }
     DWP_LAUNCH_CHECK();
 }
 

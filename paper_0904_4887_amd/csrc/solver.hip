@@ -529,10 +529,12 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
         auto fold = [&](int j, const double *hc) {
             for (int i = 0; i <= j; ++i) Hij(i, j) = hc[i];
             // Fused update: the stored vector is (w - V h) / beta, rescaled by
-            // its norm nu only when nu is off 1 by more than 1e-8 (the same
-            // test the device made).  Otherwise: explicit norm.
+            // its norm nu only when nu is off 1 by more than 1e-8 (1e-6 for a
+            // float32 basis; the same test the device made).  Otherwise:
+            // explicit norm.
             double hn = std::sqrt(std::max(hc[65], 0.0));
-            if (fused[j] && hn != 0.0) hn = std::fabs(hn - 1.0) <= 1e-8 ? hc[66] : hc[66] * hn;
+            const double rtol = v32 ? RESCALE_TOL_F32 : 1e-8;
+            if (fused[j] && hn != 0.0) hn = std::fabs(hn - 1.0) <= rtol ? hc[66] : hc[66] * hn;
             if (!std::isfinite(hn)) fail(DWP_ENONFINITE, "Krylov basis is not finite");
             Hij(j + 1, j) = hn;
             for (int i = 0; i < j; ++i) {

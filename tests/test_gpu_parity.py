@@ -242,3 +242,28 @@ def test_fused_sweep_equals_colour_passes_ragged_tiles(torch, n, precision):
     z0 = _host(s.apply_split(r))
     assert np.isfinite(z1).all()
     assert _rel(z1, z0) <= (1e-12 if precision == 0 else 2e-5)
+
+
+def test_bottom_vcycle_out_of_lds_matches_the_global_memory_one(torch):
+    """The levels at the bottom of the hierarchy (12 x 12 x 37 and 6 x 6 x 18
+    here) run in one workgroup; in float32 they fit its LDS (96 KB) and run out
+    of it, in float64 (192 KB) they run from global memory.  One application
+    of the split agrees between the two precisions to float32 rounding, while
+    dropping the bottom levels changes it a hundred times more, so an error in
+    either bottom kernel would show."""
+    from paper_0904_4887_amd.binding import plan
+    w = W.slab(n=(96, 96, 192), exclusion=True)
+    opts = dict(z_wet_lo=w.z_wet[0], z_wet_hi=w.z_wet[1], pre=2, post=2, coarse_sweeps=8)
+    lv = plan(w.n, w.L, **opts)["levels"]
+    assert [tuple(x) for x in lv[-2:]] == [(12, 12, 37), (6, 6, 18)]
+    rng = np.random.default_rng(5)
+    r = rng.normal(size=(w.n[2], w.n[1], w.n[0]))
+    z = {}
+    for key, kw in (("lds", dict(precision=1)), ("global", dict(precision=0)),
+                    ("no_bottom", dict(precision=0, max_levels=len(lv) - 2))):
+        s = _solver(torch, w.n, w.L, **opts, **kw)
+        s.build_epsilon(w.xyz, w.radius, w.eps_params)
+        z[key] = _host(s.apply_split(_dev(torch, r)))
+        s.close()
+    d_lds, d_drop = _rel(z["lds"], z["global"]), _rel(z["no_bottom"], z["global"])
+    assert d_lds <= 1e-4 and d_drop >= 100 * d_lds, (d_lds, d_drop)
