@@ -159,6 +159,7 @@ struct dwp_ctx {
     dwp::DevBuf eps, sinv, S, b, r, w, phi_last, gbuf;
     dwp::DevBuf V, Z;             // Krylov bases, (restart + 1) N and restart N
     dwp::DevBuf V32;              // float32 Arnoldi basis, (restart + 1) N (opts.krylov_fp32)
+    dwp::DevBuf eps32;            // eps rounded to float32, N (opts.krylov_fp32: the Krylov operator's copy)
     dwp::DevBuf cbuf;             // FFT workspace, nkx * ny * nz double2
     dwp::DevBuf Hz;               // per-plane height factor (exclusion)
     dwp::DevBuf partial;          // reduction partials
@@ -224,12 +225,15 @@ void launch_wet_residual(hipStream_t s, const Plan &p, const double *v, const do
 template <class T>
 void launch_wet_residual_v32(hipStream_t s, const Plan &p, const float *v, const double *dD, const double *eps,
                              T *fW);
+// with float32 Krylov vectors: eps rounded to float32 as well (the arithmetic stays float64)
 template <class T>
-void launch_wet_residual_v32(hipStream_t s, const Plan &p, const float *v, const float *dD, const double *eps,
+void launch_wet_residual_v32(hipStream_t s, const Plan &p, const float *v, const float *dD, const float *eps,
                              T *fW);
-// out = A phi rounded to float32 (a float32 Krylov basis vector); phi float64 or float32
+// out = A phi rounded to float32 (a float32 Krylov basis vector); phi and eps
+// float64, or both float32
 void launch_apply_full_f32(hipStream_t s, const Plan &p, const double *phi, const double *eps, float *out);
-void launch_apply_full_f32(hipStream_t s, const Plan &p, const float *phi, const double *eps, float *out);
+void launch_apply_full_f32(hipStream_t s, const Plan &p, const float *phi, const float *eps, float *out);
+void launch_to_f32(hipStream_t s, const double *x, float *y, size_t n);
 template <class T>
 void launch_wet_add(hipStream_t s, const Plan &p, const T *uW, double *z);
 template <class T>

@@ -42,9 +42,9 @@ __device__ __forceinline__ T ld_at(const T *base, unsigned byte_off) {
     return *(const T *)((const char *)base + byte_off);
 }
 
-template <class T, int MODE, class TB, class TP>
+template <class T, int MODE, class TB, class TP, class TE>
 __global__ void __launch_bounds__(BX *BY)
-k_apply_zmarch(const TP *__restrict__ phi, const double *__restrict__ eps, const TB *__restrict__ b,
+k_apply_zmarch(const TP *__restrict__ phi, const TE *__restrict__ eps, const TB *__restrict__ b,
                T *__restrict__ out, int nx, int ny, int nz, double cx, double cy, double cz, int k_w0,
                int nplanes, int tiles_x, int tiles_y, int nb_real) {
     const int t = xcd_tile(nb_real);
@@ -72,7 +72,7 @@ k_apply_zmarch(const TP *__restrict__ phi, const double *__restrict__ eps, const
     double nb[8];
     auto load_nb = [&](int kq, double *o) {
         const TP *pq = P(kq);
-        const double *ee = E(kq);
+        const TE *ee = E(kq);
         o[0] = lp(pq, oxp); o[1] = ee[oxp]; o[2] = lp(pq, oxm); o[3] = ee[oxm];
         o[4] = lp(pq, oyp); o[5] = ee[oyp]; o[6] = lp(pq, oym); o[7] = ee[oym];
     };
@@ -102,7 +102,7 @@ k_apply_zmarch(const TP *__restrict__ phi, const double *__restrict__ eps, const
 }
 
 // The same operator with the plane tile staged in LDS.  A block owns a tile
-// of 64 x 8 points for a chunk of ZCH planes; each thread owns two adjacent x
+// of 64 x 8 points for a chunk of apply_zch planes; each thread owns two adjacent x
 // points.  Per plane step the block loads the next plane's tile (phi and eps,
 // 1-cell halo in y, 2 in x to keep 16-byte alignment) with 16-byte loads into
 // a two-slot LDS ring, each thread loads its own two centre values three
@@ -115,7 +115,9 @@ constexpr int AHX2 = (ATX + 4) / 2;         // double2 per LDS row (x halo 2)
 constexpr int AHY = ATY + 2;                // rows (y halo 1)
 constexpr int AQ = AHX2 * AHY;              // double2 items per field per plane
 constexpr int AQT = (AQ + 255) / 256;       // per thread
-constexpr int ZCH = 16;                     // planes per block
+// planes per block: 16 for the full-box operator, 12 for the wet residual
+// (measured best at 192 x 192 x 384 among 8, 12, 16, 24 and 32)
+template <int MODE> constexpr int apply_zch() { return MODE == 2 ? 12 : 16; }
 
 // two consecutive values of a float64 or float32 field at element offset o, as double2
 __device__ __forceinline__ double2 ld2(const double *base, unsigned o) { return ld_at((const double2 *)base, o * 8u); }
@@ -124,15 +126,16 @@ __device__ __forceinline__ double2 ld2(const float *base, unsigned o) {
     return make_double2(v.x, v.y);
 }
 
-template <class T, int MODE, class TB, class TP>
+template <class T, int MODE, class TB, class TP, class TE>
 __global__ void __launch_bounds__(256)
-k_apply_tile(const TP *__restrict__ phi, const double *__restrict__ eps, const TB *__restrict__ b,
+k_apply_tile(const TP *__restrict__ phi, const TE *__restrict__ eps, const TB *__restrict__ b,
              T *__restrict__ out, int nx, int ny, int nz, double cx, double cy, double cz, int k_w0, int nplanes,
              int tiles_x, int tiles_y, int nb_real) {
     __shared__ double2 sp[2][AQT * 256], se[2][AQT * 256];
     const int t = xcd_tile(nb_real);
     if (t >= nb_real) return;
     const int i0 = (t % tiles_x) * ATX, j0 = ((t / tiles_x) % tiles_y) * ATY;
+    constexpr int ZCH = apply_zch<MODE>();
     const int kk0 = (t / (tiles_x * tiles_y)) * ZCH, kk1 = min(nplanes, kk0 + ZCH);
     const int tid = threadIdx.x + 32 * threadIdx.y;
     const size_t plane = (size_t)nx * ny;
@@ -155,7 +158,7 @@ k_apply_tile(const TP *__restrict__ phi, const double *__restrict__ eps, const T
     double2 tp[AQT], te[AQT];
     auto fetch_tile = [&](int k) {
         const TP *pp = P(k);
-        const double *ee = E(k);
+        const TE *ee = E(k);
 #pragma unroll
         for (int m = 0; m < AQT; ++m) {
             tp[m] = ld2(pp, oq[m]);
@@ -1204,14 +1207,15 @@ LevelArgs level_args(const Level &L) {
 // ============================================================== launchers
 static bool al16(const void *q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; }
 
-template <class T, int MODE, class TB = double, class TP = double>
-void launch_zmarch(hipStream_t s, const Plan &p, const TP *phi, const double *eps, const TB *b, T *out,
+template <class T, int MODE, class TB = double, class TP = double, class TE = double>
+void launch_zmarch(hipStream_t s, const Plan &p, const TP *phi, const TE *eps, const TB *b, T *out,
                    int nplanes) {
     const bool tile_ok = p.nx % 2 == 0 && al16(phi) && al16(eps) && (MODE == 0 || al16(b)) && al16(out);
     if (tile_ok) {
+        constexpr int ZCH = apply_zch<MODE>();
         const int tx = (p.nx + ATX - 1) / ATX, ty = (p.ny + ATY - 1) / ATY, tz = (nplanes + ZCH - 1) / ZCH;
         const int nb = tx * ty * tz, padded = (nb + 7) / 8 * 8;
-        k_apply_tile<T, MODE, TB, TP><<<padded, dim3(32, 8), 0, s>>>(phi, eps, b, out, p.nx, p.ny, p.nz,
+        k_apply_tile<T, MODE, TB, TP, TE><<<padded, dim3(32, 8), 0, s>>>(phi, eps, b, out, p.nx, p.ny, p.nz,
                                                              1.0 / (p.h[0] * p.h[0]), 1.0 / (p.h[1] * p.h[1]),
                                                              1.0 / (p.h[2] * p.h[2]), p.k_w0, nplanes, tx, ty, nb);
         DWP_LAUNCH_CHECK();
@@ -1220,7 +1224,7 @@ void launch_zmarch(hipStream_t s, const Plan &p, const TP *phi, const double *ep
     const int tx = (p.nx + BX - 1) / BX, ty = (p.ny + BY - 1) / BY, tz = (nplanes + ZM - 1) / ZM;
     const int nb = tx * ty * tz;
     const int padded = (nb + 7) / 8 * 8;
-    k_apply_zmarch<T, MODE, TB, TP><<<padded, dim3(BX, BY), 0, s>>>(phi, eps, b, out, p.nx, p.ny, p.nz, 1.0 / (p.h[0] * p.h[0]),
+    k_apply_zmarch<T, MODE, TB, TP, TE><<<padded, dim3(BX, BY), 0, s>>>(phi, eps, b, out, p.nx, p.ny, p.nz, 1.0 / (p.h[0] * p.h[0]),
                                                             1.0 / (p.h[1] * p.h[1]), 1.0 / (p.h[2] * p.h[2]), p.k_w0,
                                                             nplanes, tx, ty, nb);
     DWP_LAUNCH_CHECK();
@@ -1313,15 +1317,23 @@ void launch_wet_residual_v32(hipStream_t s, const Plan &p, const float *v, const
     launch_zmarch<T, 2, float>(s, p, dD, eps, v, fW, p.nw);
 }
 template <class T>
-void launch_wet_residual_v32(hipStream_t s, const Plan &p, const float *v, const float *dD, const double *eps,
+void launch_wet_residual_v32(hipStream_t s, const Plan &p, const float *v, const float *dD, const float *eps,
                              T *fW) {
-    launch_zmarch<T, 2, float, float>(s, p, dD, eps, v, fW, p.nw);
+    launch_zmarch<T, 2, float, float, float>(s, p, dD, eps, v, fW, p.nw);
 }
 void launch_apply_full_f32(hipStream_t s, const Plan &p, const double *phi, const double *eps, float *out) {
     launch_zmarch<float, 0>(s, p, phi, eps, (const double *)nullptr, out, p.nz);
 }
-void launch_apply_full_f32(hipStream_t s, const Plan &p, const float *phi, const double *eps, float *out) {
-    launch_zmarch<float, 0, double, float>(s, p, phi, eps, (const double *)nullptr, out, p.nz);
+void launch_apply_full_f32(hipStream_t s, const Plan &p, const float *phi, const float *eps, float *out) {
+    launch_zmarch<float, 0, double, float, float>(s, p, phi, eps, (const double *)nullptr, out, p.nz);
+}
+__global__ void k_to_f32(const double *__restrict__ x, float *__restrict__ y, size_t n) {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        y[t] = (float)x[t];
+}
+void launch_to_f32(hipStream_t s, const double *x, float *y, size_t n) {
+    k_to_f32<<<grid1d(n), 256, 0, s>>>(x, y, n);
+    DWP_LAUNCH_CHECK();
 }
 template <class T, class TZ>
 static void wet_add_t(hipStream_t s, const Plan &p, const T *uW, TZ *z) {
@@ -1540,7 +1552,7 @@ void launch_zero(hipStream_t s, T *x, size_t n) {
     template void launch_wet_residual_v32<T>(hipStream_t, const Plan &, const float *, const double *,  \
                                              const double *, T *);                                       \
     template void launch_wet_residual_v32<T>(hipStream_t, const Plan &, const float *, const float *,   \
-                                             const double *, T *);                                       \
+                                             const float *, T *);                                        \
     template void launch_wet_add<T>(hipStream_t, const Plan &, const T *, double *);                  \
     template void launch_wet_add<T>(hipStream_t, const Plan &, const T *, float *);                   \
     template void launch_wet_eps<T>(hipStream_t, const Plan &, const double *, T *);                  \

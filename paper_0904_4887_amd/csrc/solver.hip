@@ -296,6 +296,10 @@ void prepare_eps(dwp_ctx *c) {
     }
     if (c->opts.precision == DWP_MIXED) prepare_level_eps<float>(c);
     else prepare_level_eps<double>(c);
+    if (c->opts.krylov_fp32) {
+        c->eps32.alloc(sizeof(float) * c->plan.N);
+        launch_to_f32(c->stream, c->eps.as<double>(), c->eps32.as<float>(), c->plan.N);
+    }
 }
 
 void sync(dwp_ctx *c) {
@@ -396,8 +400,8 @@ void split_impl(dwp_ctx *c, const TV *v, TZ *z) {
     Level &F = *p.levels[0];
     const double nW = (double)F.n_interior();
     if constexpr (sizeof(TV) == 4) {
-        PROF(c, PG_WET, (12.0 + sizeof(TZ) + sizeof(T)) * nW,
-             launch_wet_residual_v32<T>(s, p, v, z, c->eps.as<double>(), F.f.as<T>()));
+        PROF(c, PG_WET, (8.0 + sizeof(TZ) + sizeof(T)) * nW,
+             launch_wet_residual_v32<T>(s, p, v, z, c->eps32.as<float>(), F.f.as<T>()));
     } else if (c->opts.order == 6) {
         PROF(c, PG_WET, (48.0 + sizeof(T)) * nW,
              launch_wet_residual6<T>(s, p, v, z, c->eps.as<double>(), c->G6.as<double>(), F.f.as<T>(),
@@ -480,7 +484,7 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
     // recomputes the true residual in float64)
     const bool v32 = c->opts.krylov_fp32 != 0 && c->opts.precision == DWP_MIXED && c->opts.order == 2 &&
                      c->V32.bytes >= sizeof(float) * N * (m + 1) && krylov32_supported(c->V32.as<float>(), N, N) &&
-                     krylov32_supported(c->Z.as<float>(), N, N);
+                     krylov32_supported(c->Z.as<float>(), N, N) && c->eps32.bytes >= sizeof(float) * N;
     float *V32 = c->V32.as<float>();
     float *Z32 = c->Z.as<float>();  // with v32 the Z buffer holds float32 vectors
     double *coef = c->coef.as<double>();
@@ -561,7 +565,7 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
                 float *Vj32 = V32 + (size_t)j * N, *Vn32 = V32 + (size_t)(j + 1) * N, *Zj32 = Z32 + (size_t)j * N;
                 apply_split(c, (const float *)Vj32, Zj32);
                 // A z (float64 arithmetic, float32 out), then the projection and update on float32 vectors
-                PROF(c, PG_APPLY, 16.0 * N, launch_apply_full_f32(s, p, (const float *)Zj32, c->eps.as<double>(), Vn32));
+                PROF(c, PG_APPLY, 12.0 * N, launch_apply_full_f32(s, p, (const float *)Zj32, c->eps32.as<float>(), Vn32));
                 PROF(c, PG_MULTIDOT, 4.0 * N * (j + 2), launch_multidot32(s, V32, N, j + 1, Vn32, N, part, hc, hc + 64));
                 fused[j] = 1;  // restart <= 16 is checked with the options
                 PROF(c, PG_AXPY, 4.0 * N * (j + 3), launch_orth_update32(s, Vn32, V32, N, j + 1, hc, N, part));
