@@ -83,9 +83,11 @@ def solver_for(w, precision, torch, profile=0, **extra):
     from paper_0904_4887_amd.binding import Solver
     order = extra.get("order", w.opts.get("order", 2))
     if precision == "mixed":
-        # the whole preconditioner in float32: the dry update too
-        extra.setdefault("fft_fp32", 1)
-        if order == 2:
+        # the whole preconditioner in float32: the dry update too (unless the
+        # workload's own options say otherwise)
+        if "fft_fp32" not in w.opts:
+            extra.setdefault("fft_fp32", 1)
+        if order == 2 and "krylov_fp32" not in w.opts:
             extra.setdefault("krylov_fp32", 1)
     s = Solver(0)
     s.set_grid(w.n, w.L, **w.solver_opts(tol=1e-8, precision=1 if precision == "mixed" else 0, profile=profile,
@@ -362,10 +364,11 @@ def sixth_order_steps(torch, n=(192, 192, 384), steps=2, warmup=1, precision="mi
     out["with_wet_vcycle"] = {"ms_per_step": round(1e3 * sec, 2), "iters": infos[-1]["outer_iters"],
                               "energy": E, "opts": dict(w.opts)}
     # the exclusion slab: every setting with the wet V-cycle stalls; the FFT
-    # dry update alone converges, and with restart 60 so does the adjoint solve
+    # dry update alone converges, and with restart 60 so does the adjoint
+    # solve, in float64 (with the float32 dry update the coupling stalls)
     from paper_0904_4887_amd.binding import DWPError
     we = W.slab(n, exclusion=True, tol=1e-8)
-    we.opts = dict(order=6, cycles=0, scaled_dry=0, restart=60)
+    we.opts = dict(order=6, cycles=0, scaled_dry=0, restart=60, fft_fp32=0)
     s = solver_for(we, precision, torch, max_outer=3000)
     try:
         sec, E, infos, _, _ = run_steps(s, we, 1, 1, torch)

@@ -338,7 +338,8 @@ int dwp_apply_operator(dwp_ctx *ctx, const double *phi_dev, double *out_dev);
 /* out = zero-mean psi with L psi = r - mean r, L the vacuum operator (the
  * 7-point Laplacian, or sum_d D2_d of Eq. 18 with order 6),
  * by the library's 3-D FFT and discrete Green's function (Eq. 15 on the
- * grid), always in float64 (fft_fp32 applies inside the split only). */
+ * grid), with the spectrum in float32 when opts.fft_fp32 is set (as inside
+ * the split; input and output stay float64), else in float64. */
 int dwp_vacuum_solve(dwp_ctx *ctx, const double *r_dev, double *out_dev);
 /* out = one application of the dry/wet split to r (the preconditioner of the
  * coupled iteration). */

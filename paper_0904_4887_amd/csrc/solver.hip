@@ -1431,7 +1431,7 @@ int dwp_vacuum_solve(dwp_ctx *c, const double *r, double *out) {
     if (!r || !out) dwp::fail(DWP_EINVAL, "NULL pointer");
     DWP_HIP(hipSetDevice(c->device));
     dwp::launch_vacuum_solve(c->stream, c->plan, c->fx, c->fy, c->fz, r, nullptr, c->cbuf.p, out,
-                             nullptr, false);
+                             nullptr, c->opts.fft_fp32 != 0);
     ABI_END(c)
 }
 

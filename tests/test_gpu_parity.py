@@ -267,3 +267,18 @@ def test_bottom_vcycle_out_of_lds_matches_the_global_memory_one(torch):
         s.close()
     d_lds, d_drop = _rel(z["lds"], z["global"]), _rel(z["no_bottom"], z["global"])
     assert d_lds <= 1e-4 and d_drop >= 100 * d_lds, (d_lds, d_drop)
+
+
+@pytest.mark.parametrize("n", [(24, 36, 48), (96, 96, 192), (192, 192, 384), (256, 256, 32), (18, 54, 48),
+                               (16, 8, 512)])
+def test_float32_vacuum_solve_matches_oracle(torch, n):
+    """The dry update with its spectrum in float32 (fft_fp32), as the
+    building block runs it: agrees with the float64 oracle to float32
+    rounding on grids with radix-2, 3, 4 and 8 stages and long z."""
+    L = (0.2 * n[0], 0.3 * n[1], 0.1 * n[2])
+    rng = np.random.default_rng(19)
+    r = rng.normal(size=(n[2], n[1], n[0]))
+    s = _solver(torch, n, L, z_wet_lo=0.3 * L[2], z_wet_hi=L[2], precision=1, fft_fp32=1)
+    out = _host(s.vacuum_solve(_dev(torch, r)))
+    ref = O.vacuum_solve(r, s.h)
+    assert _rel(out, ref) <= 2e-5
