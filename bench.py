@@ -95,21 +95,42 @@ def solver_for(w, precision, torch, profile=0, **extra):
     return s
 
 
-def stored_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary,
-    if that summary was taken on the current source of the kernel, else None."""
+def sweep_source_digest():
+    """sha256 of the fused sweep's source: the text of kern_grid.hip from its
+    tile layout (`template <int W> struct FLayout`) to the banner of the next
+    kernel (`// ---...--- residual + restriction`), followed by the text of its
+    launchers, from `static int fused_chunk` to the end of
+    `launch_sweep_fused<double>`.  Edits elsewhere in the file leave it alone."""
     import hashlib
     src = os.path.join(ROOT, "paper_0904_4887_amd", "csrc", "kern_grid.hip")
-    summ = os.path.join(ROOT, "profiles", "sweep_fused_slab_192x192x384_mixed.md")
-    if not (os.path.exists(src) and os.path.exists(summ)):
+    if not os.path.exists(src):
         return None
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    text = open(src).read()
+    try:
+        a = text.index("template <int W> struct FLayout")
+        b = text.index("residual + restriction", a)
+        c = text.index("static int fused_chunk")
+        d = text.index("void launch_sweep_fused<double>", c)
+        d = text.index("\n}\n", d) + 3
+    except ValueError:
+        return None
+    return hashlib.sha256((text[a:b] + text[c:d]).encode()).hexdigest()
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary,
+    if that summary was taken on the current source of the kernel and its
+    launchers (sweep_source_digest), else None."""
+    summ = os.path.join(ROOT, "profiles", "sweep_fused_slab_192x192x384_mixed.md")
+    digest = sweep_source_digest()
+    if digest is None or not os.path.exists(summ):
+        return None
     vals = {}
     for line in open(summ):
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kern_grid.hip sha256") != digest or vals.get("kernel") != kernel:
+    if vals.get("k_sweep_fused source sha256") != digest or vals.get("kernel") != kernel:
         return None
     try:
         return float(vals["hbm bytes per launch"])

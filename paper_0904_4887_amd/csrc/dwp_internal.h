@@ -222,16 +222,13 @@ void launch_check_finite(hipStream_t s, const double *x, size_t n, int *flags);
 template <class T>
 void launch_wet_residual(hipStream_t s, const Plan &p, const double *v, const double *dD,
                          const double *eps, T *fW);
-template <class T>
-void launch_wet_residual_v32(hipStream_t s, const Plan &p, const float *v, const double *dD, const double *eps,
-                             T *fW);
-// with float32 Krylov vectors: eps rounded to float32 as well (the arithmetic stays float64)
+// the wet residual of a float32 Krylov vector v with the float32 dry update dD
+// and eps rounded to float32 (the arithmetic stays float64)
 template <class T>
 void launch_wet_residual_v32(hipStream_t s, const Plan &p, const float *v, const float *dD, const float *eps,
                              T *fW);
-// out = A phi rounded to float32 (a float32 Krylov basis vector); phi and eps
-// float64, or both float32
-void launch_apply_full_f32(hipStream_t s, const Plan &p, const double *phi, const double *eps, float *out);
+// out = A phi rounded to float32 for float32 phi and eps (a float32 Krylov
+// basis vector; float64 arithmetic)
 void launch_apply_full_f32(hipStream_t s, const Plan &p, const float *phi, const float *eps, float *out);
 void launch_to_f32(hipStream_t s, const double *x, float *y, size_t n);
 template <class T>
@@ -298,11 +295,7 @@ void fft_plan_axis(FFTAxis &ax, int n, double h, bool half, int order);
 void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay,
                          const FFTAxis &az, const double *r, const double *sinv, void *cbuf,
                          double *out, Profiler *prof, bool fp32);
-// the same with a float32 input (a float32 Krylov basis vector), and with a
-// float32 output too (a float32 preconditioned basis vector)
-void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay,
-                         const FFTAxis &az, const float *r, const double *sinv, void *cbuf,
-                         double *out, Profiler *prof, bool fp32);
+// the same from a float32 Krylov basis vector to a float32 preconditioned one
 void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay,
                          const FFTAxis &az, const float *r, const double *sinv, void *cbuf,
                          float *out, Profiler *prof, bool fp32);

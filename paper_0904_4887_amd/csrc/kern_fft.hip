@@ -466,11 +466,6 @@ void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const
     else vacuum_solve_t<double, double, double>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
 }
 void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay, const FFTAxis &az,
-                         const float *r, const double *sinv, void *cbuf, double *out, Profiler *prof, bool fp32) {
-    if (fp32) vacuum_solve_t<float, float, double>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
-    else vacuum_solve_t<double, float, double>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
-}
-void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay, const FFTAxis &az,
                          const float *r, const double *sinv, void *cbuf, float *out, Profiler *prof, bool fp32) {
     if (fp32) vacuum_solve_t<float, float, float>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
     else vacuum_solve_t<double, float, float>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);

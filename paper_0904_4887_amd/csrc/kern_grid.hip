@@ -1312,17 +1312,9 @@ void launch_wet_residual(hipStream_t s, const Plan &p, const double *v, const do
     launch_zmarch<T, 2>(s, p, dD, eps, v, fW, p.nw);
 }
 template <class T>
-void launch_wet_residual_v32(hipStream_t s, const Plan &p, const float *v, const double *dD, const double *eps,
-                             T *fW) {
-    launch_zmarch<T, 2, float>(s, p, dD, eps, v, fW, p.nw);
-}
-template <class T>
 void launch_wet_residual_v32(hipStream_t s, const Plan &p, const float *v, const float *dD, const float *eps,
                              T *fW) {
     launch_zmarch<T, 2, float, float, float>(s, p, dD, eps, v, fW, p.nw);
-}
-void launch_apply_full_f32(hipStream_t s, const Plan &p, const double *phi, const double *eps, float *out) {
-    launch_zmarch<float, 0>(s, p, phi, eps, (const double *)nullptr, out, p.nz);
 }
 void launch_apply_full_f32(hipStream_t s, const Plan &p, const float *phi, const float *eps, float *out) {
     launch_zmarch<float, 0, double, float, float>(s, p, phi, eps, (const double *)nullptr, out, p.nz);
@@ -1549,8 +1541,6 @@ void launch_zero(hipStream_t s, T *x, size_t n) {
 #define DWP_INST(T)                                                                                  \
     template void launch_wet_residual<T>(hipStream_t, const Plan &, const double *, const double *,  \
                                          const double *, T *);                                      \
-    template void launch_wet_residual_v32<T>(hipStream_t, const Plan &, const float *, const double *,  \
-                                             const double *, T *);                                       \
     template void launch_wet_residual_v32<T>(hipStream_t, const Plan &, const float *, const float *,   \
                                              const float *, T *);                                        \
     template void launch_wet_add<T>(hipStream_t, const Plan &, const T *, double *);                  \
