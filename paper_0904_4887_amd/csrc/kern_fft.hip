@@ -265,18 +265,36 @@ k_fft_x_inv(const cplx<S> *__restrict__ in, const double *__restrict__ sinv, TO 
     }
 }
 
+// Block -> (line tile, row) of the y and z passes, XCD-aware: the grid is
+// one-dimensional and padded to a multiple of 8; hardware block b runs on XCD
+// b mod 8, which gets the contiguous run of tiles [xcd * per, (xcd + 1) * per),
+// so the line tiles of one row (which share the 128-byte cache lines at their
+// edges) run side by side on one XCD and its L2 serves the shared lines once.
+// Returns false for the padding blocks.
+__device__ __forceinline__ bool xcd_tile2(int ntx, int nty, int &tx, int &ty) {
+    const int per = gridDim.x / 8;
+    const int t = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (t >= ntx * nty) return false;
+    ty = t / ntx;
+    tx = t - ty * ntx;
+    return true;
+}
+inline int xcd_grid(int n) { return (n + 7) / 8 * 8; }
+
 // ---------------------------------------------------------------- y pass
 // Block (tile of B = 2^lb consecutive kx, plane z): lines along y, LDS
 // element (y, l) at y * B + l.
 template <class S>
 __global__ void __launch_bounds__(FFT_THREADS)
-k_fft_y(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ tw, int lb, int nkx, int ldc, int inv) {
+k_fft_y(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ tw, int lb, int nkx, int ldc, int nz,
+        int inv) {
     using C = cplx<S>;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     C *lds = reinterpret_cast<C *>(lds_raw);
     const int ny = rd.n, B = 1 << lb, bmask = B - 1;
-    const int kx0 = blockIdx.x * B;
-    const int z = blockIdx.y;
+    int bt, z;
+    if (!xcd_tile2((nkx + B - 1) / B, nz, bt, z)) return;
+    const int kx0 = bt * B;
     const int bw = min(B, nkx - kx0);
     const size_t base = (size_t)z * ny * ldc + kx0;
     for (int e = threadIdx.x; e < B * ny; e += FFT_THREADS) {
@@ -311,8 +329,9 @@ k_fft_z_green(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ t
     extern __shared__ __align__(16) unsigned char lds_raw[];
     C *lds = reinterpret_cast<C *>(lds_raw);
     const int nz = rd.n, B = 1 << lb, bmask = B - 1;
-    const int kx0 = blockIdx.x * B;
-    const int y = blockIdx.y;
+    int bt, y;
+    if (!xcd_tile2((nkx + B - 1) / B, ny, bt, y)) return;
+    const int kx0 = bt * B;
     const int bw = min(B, nkx - kx0);
     const size_t zstride = (size_t)ny * ldc;
     const size_t base = (size_t)y * ldc + kx0;
@@ -436,13 +455,14 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_X, bx);
     const int lby = tile_log2(p.ny, FFT_BUDGET_Y), By = 1 << lby;
-    dim3 gy((p.nkx + By - 1) / By, p.nz);
+    const int gy = xcd_grid((p.nkx + By - 1) / By * p.nz);
     ev = pb(PG_FFT_Y);
-    k_fft_y<S><<<gy, FFT_THREADS, sizeof(C) * By * p.ny, st>>>(cbuf, radices_of(ay), TW(ay), lby, p.nkx, p.ldc, 0);
+    k_fft_y<S><<<gy, FFT_THREADS, sizeof(C) * By * p.ny, st>>>(cbuf, radices_of(ay), TW(ay), lby, p.nkx, p.ldc, p.nz,
+                                                              0);
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_Y, 2.0 * cb * Cn);
     const int lbz = tile_log2(p.nz, FFT_BUDGET_Z), Bz = 1 << lbz;
-    dim3 gz((p.nkx + Bz - 1) / Bz, p.ny);
+    const int gz = xcd_grid((p.nkx + Bz - 1) / Bz * p.ny);
     ev = pb(PG_FFT_Z);
     k_fft_z_green<S><<<gz, FFT_THREADS, sizeof(C) * Bz * p.nz, st>>>(cbuf, radices_of(az), TW(az), lbz, p.nkx, p.ldc,
                                                                       p.ny, LAM(ax), LAM(ay), LAM(az),
@@ -450,7 +470,8 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_Z, 2.0 * cb * Cn);
     ev = pb(PG_FFT_Y);
-    k_fft_y<S><<<gy, FFT_THREADS, sizeof(C) * By * p.ny, st>>>(cbuf, radices_of(ay), TW(ay), lby, p.nkx, p.ldc, 1);
+    k_fft_y<S><<<gy, FFT_THREADS, sizeof(C) * By * p.ny, st>>>(cbuf, radices_of(ay), TW(ay), lby, p.nkx, p.ldc, p.nz,
+                                                              1);
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_Y, 2.0 * cb * Cn);
     ev = pb(PG_FFT_X);

@@ -17,7 +17,12 @@ from paper_0904_4887_amd import workloads as W
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
-# name -> (workload, E tol, phi tol (x max|phi| at the samples), force tol (x max|F|)[, stored result])
+# the mixed-precision configuration the benchmark runs: float32 dry update and
+# float32 Krylov vectors around the float32 multigrid
+HEADLINE = dict(fft_fp32=1, krylov_fp32=1)
+
+# name -> (workload, E tol, phi tol (x max|phi| at the samples), force tol (x max|F|)[, stored result
+# [, extra solver options]])
 CASES = {
     "tanh_box_32x32x64": (lambda: W.tanh_box(), 1e-10, 1e-8, None),
     "slab_96x96x192": (lambda: W.slab((96, 96, 192)), 1e-10, 1e-8, 1e-7),
@@ -29,7 +34,10 @@ CASES = {
                               "slab_192x192x384"),
     "slab_192x192x384_excl": (lambda: W.slab((192, 192, 384), exclusion=True, tol=1e-8, precision=1),
                               1e-8, 1e-6, 1e-5),
+    "slab_192x192x384_headline": (lambda: W.slab((192, 192, 384), tol=1e-8, precision=1), 1e-8, 1e-6, 1e-5,
+                                  "slab_192x192x384", HEADLINE),
     "big_slab_256x256x512": (lambda: W.big_slab(), 1e-8, 1e-6, 1e-5),
+    "big_slab_256x256x512_headline": (lambda: W.big_slab(), 1e-8, 1e-6, 1e-5, "big_slab_256x256x512", HEADLINE),
     "density_slab_192x192x384": (lambda: W.density_slab((192, 192, 384)), 1e-8, 1e-6, 1e-5),
     "slab_gamma_192x192x384": (lambda: W.slab_gamma((192, 192, 384)), 1e-8, 1e-6, 1e-5),
     "slab_gamma_192x192x384_excl": (lambda: W.slab_gamma((192, 192, 384), exclusion=True), 1e-8, 1e-6, 1e-5),
@@ -41,6 +49,7 @@ def test_full_size_matches_stored_oracle(name):
     case = CASES[name]
     make, tol_E, tol_phi, tol_F = case[:4]
     stored = case[4] if len(case) > 4 else name
+    extra = case[5] if len(case) > 5 else {}
     path = os.path.join(GOLDEN, f"oracle_{stored}.json")
     if not os.path.exists(path):
         pytest.skip(f"no stored oracle result for {stored}")
@@ -50,7 +59,7 @@ def test_full_size_matches_stored_oracle(name):
     with open(path) as f:
         ref = json.load(f)
     s = Solver(0)
-    s.set_grid(w.n, w.L, **w.solver_opts())
+    s.set_grid(w.n, w.L, **w.solver_opts(**extra))
     if w.eps_kind == "tanh_z":
         s.set_epsilon(torch.from_numpy(w.eps_grid()).cuda())
     elif w.eps_kind == "density":
@@ -81,7 +90,8 @@ def test_full_size_matches_stored_oracle(name):
     s.close()
 
 
-def test_big_slab_md_steps_match_stored_oracle():
+@pytest.mark.parametrize("extra", [{}, HEADLINE], ids=["mixed", "headline"])
+def test_big_slab_md_steps_match_stored_oracle(extra):
     """The 256 x 256 x 512 slab through the warm-started MD loop: a cold solve
     at the initial atoms, then three steps of cumulative N(0, 0.02 A)
     displacements, each solved from the previous phi; after the third step
@@ -96,7 +106,7 @@ def test_big_slab_md_steps_match_stored_oracle():
         ref = json.load(f)
     w = W.big_slab()
     s = Solver(0)
-    s.set_grid(w.n, w.L, **w.solver_opts())
+    s.set_grid(w.n, w.L, **w.solver_opts(**extra))
     disp = W.md_displacements(len(w.q), 4)
     xyz = w.xyz.copy()
     rho, phi = s.empty(), s.empty().zero_()
