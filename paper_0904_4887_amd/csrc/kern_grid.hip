@@ -1519,11 +1519,16 @@ void launch_vcycle_bottom(hipStream_t s, const std::vector<Level *> &levels, siz
     }
     const size_t bytes = at * sizeof(T);
     if (bytes <= BOTTOM_LDS_BYTES) {
-        static bool attr_set = false;  // per process: the attribute belongs to the kernel, not the device
-        if (!attr_set) {
+        // the dynamic-LDS limit is raised once per device (the contexts of one
+        // process may sit on several)
+        static bool attr_set[64] = {false};
+        int dev = 0;
+        DWP_HIP(hipGetDevice(&dev));
+        if (dev < 0 || dev >= 64) fail(DWP_EINVAL, "internal: device index out of range");
+        if (!attr_set[dev]) {
             DWP_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_vcycle_bottom_lds<T>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)BOTTOM_LDS_BYTES));
-            attr_set = true;
+            attr_set[dev] = true;
         }
         k_vcycle_bottom_lds<T><<<1, 1024, bytes, s>>>(B, O);
     } else {

@@ -45,3 +45,27 @@ def test_whole_field_matches_oracle_where_fused_sweep_runs(case, precision, kryl
     # a residual of 1e-10 leaves phi accurate to about kappa * 1e-10
     assert np.abs(phi - phi_o).max() <= 1e-8 * np.abs(phi_o).max()
     assert np.abs(g - g_o).max() <= 1e-7 * np.abs(g_o).max()
+
+
+def test_switching_the_krylov_precision_on_one_context(case):
+    # float64 -> float32 -> float64 Krylov bases on one context: the float32
+    # leg meets the same bars, and the last leg repeats the first bit for bit
+    # (the float32 buffers and the float32 copy of eps leave nothing behind)
+    from paper_0904_4887_amd.binding import Solver
+    w, rho, phi_o, E_o, g_o = case
+    s = Solver(0)
+    s.set_grid(w.n, w.L, **w.solver_opts(precision=1, fft_fp32=1))
+    s.build_epsilon(w.xyz, w.radius, w.eps_params)
+    rho_d = s.build_rho(w.xyz, w.q, w.sigma)
+    Es, phis = [], []
+    for k32 in (0, 1, 0):
+        s.set_opts(krylov_fp32=k32)
+        phi_d, E, info = s.solve(rho_d)
+        assert info["rel_res"] <= 1e-10
+        Es.append(E)
+        phis.append(phi_d.cpu().numpy())
+    s.close()
+    assert Es[2] == Es[0] and np.array_equal(phis[2], phis[0])
+    for E, phi in zip(Es, phis):
+        assert abs(E - E_o) <= 1e-10 * abs(E_o)
+        assert np.abs(phi - phi_o).max() <= 1e-8 * np.abs(phi_o).max()
