@@ -282,3 +282,20 @@ def test_float32_vacuum_solve_matches_oracle(torch, n):
     out = _host(s.vacuum_solve(_dev(torch, r)))
     ref = O.vacuum_solve(r, s.h)
     assert _rel(out, ref) <= 2e-5
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("n", [(4096, 8, 8), (8, 4096, 8), (8, 8, 4096)])
+def test_vacuum_solve_at_the_longest_axis(torch, n, fp32):
+    """The largest extent the planner accepts (4096) along each axis in turn: a
+    line of 4096 values is one FFT block by itself (the x pass then stages 4097
+    complex values in LDS).  The smallest eigenvalue of the 4096-long axis,
+    (2 pi / 4096)^2 / h^2, amplifies rounding about 64 times more than on the
+    512-long axes of the other tests, and the bars scale with it."""
+    L = (0.05 * n[0], 0.05 * n[1], 0.05 * n[2])
+    rng = np.random.default_rng(23)
+    r = rng.normal(size=(n[2], n[1], n[0]))
+    s = _solver(torch, n, L, z_wet_lo=0.3 * L[2], z_wet_hi=L[2], precision=fp32, fft_fp32=fp32)
+    out = _host(s.vacuum_solve(_dev(torch, r)))
+    ref = O.vacuum_solve(r, s.h)
+    assert _rel(out, ref) <= (5e-4 if fp32 else 1e-10)
