@@ -311,8 +311,14 @@ void launch_multidot(hipStream_t s, const double *V, size_t ldv, int nv, const d
 void launch_axpy_multi(hipStream_t s, double *w, const double *V, size_t ldv, int nv,
                        const double *c, size_t n, double sign, double *partial, double *norm_out);
 bool orth_update_supported(const double *V, size_t ldv, int nv, size_t n);
+// mean_free: w is an operator output whose mean must go too (its sum at hc[67]
+// from launch_multidot_sum); the constant direction is removed in the same pass
 void launch_orth_update(hipStream_t s, double *w, const double *V, size_t ldv, int nv, double *hc, size_t n,
-                        double *partial);
+                        double *partial, bool mean_free = false);
+// the projection of launch_multidot (nv <= 16, 16-byte aligned) with the sum of
+// w's elements into *sum_out as well
+void launch_multidot_sum(hipStream_t s, const double *V, size_t ldv, int nv, const double *w, size_t n,
+                         double *partial, double *out, double *norm_out, double *sum_out);
 // float32 Krylov basis (mixed precision): projections and update in float64
 // arithmetic on float32 vectors (n and ldv multiples of 4, 16-byte aligned)
 bool krylov32_supported(const float *V, size_t ldv, size_t n);

@@ -14,6 +14,8 @@ namespace {
 constexpr int MD_GROUP = 8;   // dot products per pass of multidot
 constexpr int MD_STRIDE = 72; // partial slots per block: 64 dots + the norm
 constexpr int NORM_SLOT = 64;
+constexpr int SUM_SLOT = 65;   // partial column of the sum of w's elements (mean-free Arnoldi step)
+constexpr int HC_SUM = 67;     // where that sum lands in the Hessenberg column
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -110,28 +112,31 @@ __device__ __forceinline__ void block_sums(const double (&v)[NV], double (*sh)[R
 
 // Pair-vectorised projection: NV dot products V_{v0+q} . w and (with_norm)
 // w . w over n2 element pairs (16-byte loads; every vector 16-byte aligned).
-template <int NV>
+template <int NV, bool SUM = false>
 __global__ void __launch_bounds__(RED_THREADS)
 k_multidot2(const double *__restrict__ V, size_t ldv, int v0, const double *__restrict__ w, size_t n2,
             double *__restrict__ partial, int stride, int with_norm) {
-    __shared__ double sh[NV + 1][RED_THREADS / 64];
-    __shared__ double res[NV + 1];
+    constexpr int NA = NV + 1 + (SUM ? 1 : 0);  // dots, ||w||^2 [, sum of w]
+    __shared__ double sh[NA][RED_THREADS / 64];
+    __shared__ double res[NA];
     const double2 *w2 = reinterpret_cast<const double2 *>(w);
-    double acc[NV + 1];
+    double acc[NA];
 #pragma unroll
-    for (int q = 0; q <= NV; ++q) acc[q] = 0.0;
+    for (int q = 0; q < NA; ++q) acc[q] = 0.0;
     for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n2; t += (size_t)gridDim.x * RED_THREADS) {
         const double2 wt = w2[t];
         double2 vq[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) vq[q] = reinterpret_cast<const double2 *>(V + (size_t)(v0 + q) * ldv)[t];
         acc[NV] += wt.x * wt.x + wt.y * wt.y;
+        if constexpr (SUM) acc[NV + 1] += wt.x + wt.y;
 #pragma unroll
         for (int q = 0; q < NV; ++q) acc[q] += vq[q].x * wt.x + vq[q].y * wt.y;
     }
-    block_sums<NV + 1>(acc, sh, res);
+    block_sums<NA>(acc, sh, res);
     if ((int)threadIdx.x < NV) partial[(size_t)blockIdx.x * stride + v0 + threadIdx.x] = res[threadIdx.x];
     if (with_norm && threadIdx.x == NV) partial[(size_t)blockIdx.x * stride + NORM_SLOT] = res[NV];
+    if (SUM && with_norm && (int)threadIdx.x == NV + 1) partial[(size_t)blockIdx.x * stride + SUM_SLOT] = res[NV + 1];
 }
 
 // New Arnoldi vector in one pass: w <- (w - sum_q h_q V_q) / beta with
@@ -140,19 +145,30 @@ k_multidot2(const double *__restrict__ V, size_t ldv, int v0, const double *__re
 // reliable beta (beta^2 <= 1e-20 ||w||^2) the divisor is 1.  Block 0 stores
 // the divisor at *beta_out; partial[b] receives block b's share of the new
 // squared norm, which the caller uses to rescale when it is not 1.
-template <int NV>
+// SUM: w is not yet mean-free (the operator's output before the removal of its
+// mean); the constant direction is taken out in the same pass: with mu the
+// mean of w (hc[SUM_SLOT] / n), w <- (w - sum_q h_q V_q - mu) / beta and
+// beta^2 = ||w||^2 - sum_q h_q^2 - n mu^2, which holds because every V_q is
+// mean-free.
+template <int NV, bool SUM = false>
 __global__ void __launch_bounds__(RED_THREADS)
 k_orth_update2(double *__restrict__ w, const double *__restrict__ V, size_t ldv, const double *__restrict__ hc,
                size_t n2, double *__restrict__ partial, double *__restrict__ beta_out) {
     __shared__ double sh[1][RED_THREADS / 64];
-    __shared__ double cs[NV + 1];
+    __shared__ double cs[NV + 2];
     __shared__ double res[1];
     if (threadIdx.x == 0) {
         double h2 = 0.0;
         for (int q = 0; q < NV; ++q) h2 += hc[q] * hc[q];
+        double mu = 0.0;
+        if constexpr (SUM) {
+            mu = hc[HC_SUM] / (2.0 * (double)n2);
+            h2 += mu * hc[HC_SUM];
+        }
         const double w2n = hc[NORM_SLOT], b2 = w2n - h2;
         const double beta = (b2 > 1e-20 * w2n) ? sqrt(b2) : 1.0;
         cs[NV] = 1.0 / beta;
+        cs[NV + 1] = -mu;
         if (blockIdx.x == 0) *beta_out = beta;
     }
     if ((int)threadIdx.x < NV) cs[threadIdx.x] = -hc[threadIdx.x];
@@ -162,6 +178,10 @@ k_orth_update2(double *__restrict__ w, const double *__restrict__ V, size_t ldv,
     double nrm[1] = {0.0};
     for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n2; t += (size_t)gridDim.x * RED_THREADS) {
         double2 acc = w2[t];
+        if constexpr (SUM) {
+            acc.x += cs[NV + 1];
+            acc.y += cs[NV + 1];
+        }
         double2 vq[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) vq[q] = reinterpret_cast<const double2 *>(V + (size_t)q * ldv)[t];
@@ -354,15 +374,17 @@ k_axpy4f(double *__restrict__ x, const float *__restrict__ Z, size_t ldz, const 
 // with norm_out, one more block adds column NORM_SLOT into *norm_out
 __global__ void __launch_bounds__(RED_THREADS)
 k_reduce_partials(const double *__restrict__ partial, int nblocks, int stride, double *__restrict__ out,
-                  int nout, double *__restrict__ norm_out) {
+                  int nout, double *__restrict__ norm_out, double *__restrict__ sum_out = nullptr) {
     __shared__ double sh[RED_THREADS / 64];
-    const int idx = blockIdx.x < nout ? (int)blockIdx.x : NORM_SLOT;
+    const int b0 = (int)blockIdx.x;
+    const int idx = b0 < nout ? b0 : (b0 == nout ? NORM_SLOT : SUM_SLOT);
     double v = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += RED_THREADS) v += partial[(size_t)b * stride + idx];
     const double r = block_sum(v, sh);
     if (threadIdx.x == 0) {
-        if ((int)blockIdx.x < nout) out[idx] = r;
-        else *norm_out = r;
+        if (b0 < nout) out[idx] = r;
+        else if (b0 == nout) *norm_out = r;
+        else *sum_out = r;
     }
 }
 
@@ -467,6 +489,25 @@ bool pair_ok(const void *a, size_t ldv, size_t n) {
 
 #define DWP_NV_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
+// With the sum of w as well (into *sum_out), for the mean-free Arnoldi step:
+// 16-byte-aligned vectors and at most MD2_GROUP vectors only.
+void launch_multidot_sum(hipStream_t s, const double *V, size_t ldv, int nv, const double *w, size_t n,
+                         double *partial, double *out, double *norm_out, double *sum_out) {
+    if (nv < 1 || nv > MD2_GROUP || !pair_ok(V, ldv, n) || !pair_ok(w, 0, n))
+        fail(DWP_EINVAL, "internal: mean-free multidot layout");
+    switch (nv) {
+#define DWP_MDS_CASE(K)                                                                                      \
+    case K:                                                                                                  \
+        k_multidot2<K, true><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, 0, w, n / 2, partial, MD_STRIDE, 1); \
+        break;
+        DWP_NV_CASES(DWP_MDS_CASE)
+#undef DWP_MDS_CASE
+    }
+    DWP_LAUNCH_CHECK();
+    k_reduce_partials<<<nv + 2, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, MD_STRIDE, out, nv, norm_out, sum_out);
+    DWP_LAUNCH_CHECK();
+}
+
 void launch_multidot(hipStream_t s, const double *V, size_t ldv, int nv, const double *w, size_t n,
                      double *partial, double *out, double *norm_out) {
     if (nv > 64) fail(DWP_EINVAL, "multidot: at most 64 vectors");
@@ -537,13 +578,23 @@ bool orth_update_supported(const double *V, size_t ldv, int nv, size_t n) {
 // squared norm of the result and hc[66] the divisor beta; the result is then
 // rescaled to unit norm unless that norm is 0 or within 1e-8 of 1.
 void launch_orth_update(hipStream_t s, double *w, const double *V, size_t ldv, int nv, double *hc, size_t n,
-                        double *partial) {
+                        double *partial, bool mean_free) {
     if (!orth_update_supported(V, ldv, nv, n) || !pair_ok(w, 0, n)) fail(DWP_EINVAL, "internal: orth update layout");
-    switch (nv) {
+    if (mean_free) {
+        switch (nv) {
+#define DWP_OUS_CASE(K)                                                                                         \
+    case K: k_orth_update2<K, true><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, V, ldv, hc, n / 2, partial, hc + 66); \
+        break;
+            DWP_NV_CASES(DWP_OUS_CASE)
+#undef DWP_OUS_CASE
+        }
+    } else {
+        switch (nv) {
 #define DWP_OU_CASE(K)                                                                                     \
     case K: k_orth_update2<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, V, ldv, hc, n / 2, partial, hc + 66); break;
-        DWP_NV_CASES(DWP_OU_CASE)
+            DWP_NV_CASES(DWP_OU_CASE)
 #undef DWP_OU_CASE
+        }
     }
     DWP_LAUNCH_CHECK();
     k_rescale_if<<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, partial, RED_BLOCKS, hc + 65, n);

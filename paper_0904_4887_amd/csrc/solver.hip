@@ -577,13 +577,25 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
                     PROF(c, PG_VEC, 8.0 * N, launch_sum(s, Zj, N, part, coef + 411));
                     PROF(c, PG_VEC, 16.0 * N, launch_sub_mean(s, Zj, coef + 411, 1.0 / (double)N, N));
                 }
-                apply_operator(c, Zj, nullptr, Vn, false);
                 const double md = 8.0 * N * (j + 2), ax = 8.0 * N * (j + 3);
-                PROF(c, PG_MULTIDOT, md, launch_multidot(s, V, N, j + 1, Vn, N, part, hc, hc + 64));
                 fused[j] = orth_update_supported(V, N, j + 1, N);
-                if (fused[j]) {
+                if (c->opts.order == 6 && fused[j]) {
+                    // A6 z (A6^T z) without the separate removal of its mean: the
+                    // projection also sums the new vector and the update takes
+                    // the constant direction out with the others
+                    PROF(c, PG_APPLY, 48.0 * N,
+                         launch_apply6(s, p, Zj, c->eps.as<double>(), c->G6.as<double>(), nullptr, Vn, false,
+                                       c->transposed));
+                    PROF(c, PG_MULTIDOT, md,
+                         launch_multidot_sum(s, V, N, j + 1, Vn, N, part, hc, hc + 64, hc + 67));
+                    PROF(c, PG_AXPY, ax, launch_orth_update(s, Vn, V, N, j + 1, hc, N, part, true));
+                } else if (fused[j]) {
+                    apply_operator(c, Zj, nullptr, Vn, false);
+                    PROF(c, PG_MULTIDOT, md, launch_multidot(s, V, N, j + 1, Vn, N, part, hc, hc + 64));
                     PROF(c, PG_AXPY, ax, launch_orth_update(s, Vn, V, N, j + 1, hc, N, part));
                 } else {
+                    apply_operator(c, Zj, nullptr, Vn, false);
+                    PROF(c, PG_MULTIDOT, md, launch_multidot(s, V, N, j + 1, Vn, N, part, hc, hc + 64));
                     PROF(c, PG_AXPY, ax, launch_axpy_multi(s, Vn, V, N, j + 1, hc, N, -1.0, part, hc + 65));
                     PROF(c, PG_VEC, 16.0 * N, launch_scale_dev(s, Vn, nullptr, hc + 65, N, 0));
                 }
