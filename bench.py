@@ -78,8 +78,10 @@ def run_steps(s, w, steps, warmup, torch, keep=None):
 
 def solver_for(w, precision, torch, profile=0, **extra):
     """A solver for workload w at tol 1e-8.  Mixed precision runs the dry
-    update in float32 (fft_fp32) and, with the second-order operator, keeps
-    the Arnoldi basis in float32 (krylov_fp32), unless extra says otherwise."""
+    update in float32 (fft_fp32) and, where the library supports it (second
+    order, or sixth order with the FFT dry update alone; restart <= 16), keeps
+    the Krylov vectors in float32 (krylov_fp32), unless the workload or extra
+    says otherwise."""
     from paper_0904_4887_amd.binding import Solver
     order = extra.get("order", w.opts.get("order", 2))
     if precision == "mixed":
@@ -87,7 +89,9 @@ def solver_for(w, precision, torch, profile=0, **extra):
         # workload's own options say otherwise)
         if "fft_fp32" not in w.opts:
             extra.setdefault("fft_fp32", 1)
-        if order == 2 and "krylov_fp32" not in w.opts:
+        cycles = extra.get("cycles", w.opts.get("cycles", 1))
+        restart = extra.get("restart", w.opts.get("restart", 10))
+        if (order == 2 or cycles == 0) and restart <= 16 and "krylov_fp32" not in w.opts:
             extra.setdefault("krylov_fp32", 1)
     s = Solver(0)
     s.set_grid(w.n, w.L, **w.solver_opts(tol=1e-8, precision=1 if precision == "mixed" else 0, profile=profile,
@@ -369,7 +373,7 @@ def sixth_order_steps(torch, n=(192, 192, 384), steps=2, warmup=1, precision="mi
     w = W.slab(n, tol=1e-8)
     # the FFT dry update alone, unscaled: with A6 as the outer operator the
     # 7-point wet V-cycle slows the coupling down (the entry "with_wet_vcycle")
-    w.opts = dict(order=6, cycles=0, scaled_dry=0)
+    w.opts = dict(order=6, cycles=0, scaled_dry=0, restart=16)
     s = solver_for(w, precision, torch)
     sec, E, infos, _, _ = run_steps(s, w, steps, warmup, torch)
     x = s.empty().normal_()

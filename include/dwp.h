@@ -119,7 +119,8 @@ typedef struct {
                            /* the 7-point operator (so does the adjoint solve  */
                            /* of dwp_eps_gradient / dwp_forces).  0 = 7-point  */
                            /* everywhere                                       */
-    int krylov_fp32;       /* mixed precision, order 2, restart <= 16: 1 =     */
+    int krylov_fp32;       /* mixed precision, restart <= 16 (order 6: with    */
+                           /* cycles = 0 only): 1 =                            */
                            /* the Krylov bases V and Z are stored in float32   */
                            /* (every dot product, the Hessenberg matrix, the   */
                            /* operator's arithmetic and the iterate stay       */

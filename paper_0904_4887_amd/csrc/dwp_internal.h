@@ -160,6 +160,7 @@ struct dwp_ctx {
     dwp::DevBuf V, Z;             // Krylov bases, (restart + 1) N and restart N
     dwp::DevBuf V32;              // float32 Arnoldi basis, (restart + 1) N (opts.krylov_fp32)
     dwp::DevBuf eps32;            // eps rounded to float32, N (opts.krylov_fp32: the Krylov operator's copy)
+    dwp::DevBuf G632;             // D1 eps rounded to float32, 3 N (krylov_fp32 with order 6)
     dwp::DevBuf cbuf;             // FFT workspace, nkx * ny * nz double2
     dwp::DevBuf Hz;               // per-plane height factor (exclusion)
     dwp::DevBuf partial;          // reduction partials
@@ -273,6 +274,10 @@ void launch_d1eps(hipStream_t s, const Plan &p, const double *eps, double *G);  
 // out = A6 x (or A6^T x), or b - that when residual
 void launch_apply6(hipStream_t s, const Plan &p, const double *x, const double *eps, const double *G,
                    const double *b, double *out, bool residual, bool trans);
+// A6 (A6^T) applied to a float32 Krylov vector with eps and D1 eps rounded to
+// float32; float64 arithmetic, float32 out, no removal of the mean
+void launch_apply6_f32(hipStream_t s, const Plan &p, const float *x, const float *eps, const float *G, float *out,
+                       bool trans);
 template <class T>
 void launch_wet_residual6(hipStream_t s, const Plan &p, const double *v, const double *dD, const double *eps,
                           const double *G, T *fW, bool trans);
@@ -328,7 +333,12 @@ constexpr double RESCALE_TOL_F32 = 1e-6;
 void launch_multidot32(hipStream_t s, const float *V, size_t ldv, int nv, const float *w, size_t n, double *partial,
                        double *out, double *norm_out);
 void launch_orth_update32(hipStream_t s, float *w, const float *V, size_t ldv, int nv, double *hc, size_t n,
-                          double *partial);
+                          double *partial, bool mean_free = false);
+// the float32 projection with the sum of w as well (mean-free Arnoldi step)
+void launch_multidot32_sum(hipStream_t s, const float *V, size_t ldv, int nv, const float *w, size_t n,
+                           double *partial, double *out, double *norm_out, double *sum_out);
+// x -= mean(x) for a float32 vector (the sum lands at *sum_out)
+void launch_sub_mean32(hipStream_t s, float *x, size_t n, double *partial, double *sum_out);
 void launch_scale_to32(hipStream_t s, float *x32, const double *r, const double *den_sq, size_t n);
 // x += sum_q c[q] Z_q with float32 Z_q (nv <= 16), float64 x and sums
 void launch_axpy_multi32(hipStream_t s, double *x, const float *Z, size_t ldz, int nv, const double *c, size_t n);

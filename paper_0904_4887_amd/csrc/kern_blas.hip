@@ -201,16 +201,17 @@ k_orth_update2(double *__restrict__ w, const double *__restrict__ V, size_t ldv,
 
 // The same projection and update for a float32 Krylov basis (V and w in
 // float32, four per 16-byte load; every product and sum in float64).
-template <int NV>
+template <int NV, bool SUM = false>
 __global__ void __launch_bounds__(RED_THREADS)
 k_multidot4f(const float *__restrict__ V, size_t ldv, int v0, const float *__restrict__ w, size_t n4,
              double *__restrict__ partial, int stride, int with_norm) {
-    __shared__ double sh[NV + 1][RED_THREADS / 64];
-    __shared__ double res[NV + 1];
+    constexpr int NA = NV + 1 + (SUM ? 1 : 0);  // dots, ||w||^2 [, sum of w]
+    __shared__ double sh[NA][RED_THREADS / 64];
+    __shared__ double res[NA];
     const float4 *w4 = reinterpret_cast<const float4 *>(w);
-    double acc[NV + 1];
+    double acc[NA];
 #pragma unroll
-    for (int q = 0; q <= NV; ++q) acc[q] = 0.0;
+    for (int q = 0; q < NA; ++q) acc[q] = 0.0;
     for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n4; t += (size_t)gridDim.x * RED_THREADS) {
         const float4 wt = w4[t];
         float4 vq[NV];
@@ -218,28 +219,36 @@ k_multidot4f(const float *__restrict__ V, size_t ldv, int v0, const float *__res
         for (int q = 0; q < NV; ++q) vq[q] = reinterpret_cast<const float4 *>(V + (size_t)(v0 + q) * ldv)[t];
         const double a = wt.x, b = wt.y, c = wt.z, d = wt.w;
         acc[NV] += a * a + b * b + c * c + d * d;
+        if constexpr (SUM) acc[NV + 1] += (a + b) + (c + d);
 #pragma unroll
         for (int q = 0; q < NV; ++q)
             acc[q] += (double)vq[q].x * a + (double)vq[q].y * b + (double)vq[q].z * c + (double)vq[q].w * d;
     }
-    block_sums<NV + 1>(acc, sh, res);
+    block_sums<NA>(acc, sh, res);
     if ((int)threadIdx.x < NV) partial[(size_t)blockIdx.x * stride + v0 + threadIdx.x] = res[threadIdx.x];
     if (with_norm && threadIdx.x == NV) partial[(size_t)blockIdx.x * stride + NORM_SLOT] = res[NV];
+    if (SUM && with_norm && (int)threadIdx.x == NV + 1) partial[(size_t)blockIdx.x * stride + SUM_SLOT] = res[NV + 1];
 }
 
-template <int NV>
+template <int NV, bool SUM = false>
 __global__ void __launch_bounds__(RED_THREADS)
 k_orth_update4f(float *__restrict__ w, const float *__restrict__ V, size_t ldv, const double *__restrict__ hc,
                 size_t n4, double *__restrict__ partial, double *__restrict__ beta_out) {
     __shared__ double sh[1][RED_THREADS / 64];
-    __shared__ double cs[NV + 1];
+    __shared__ double cs[NV + 2];
     __shared__ double res[1];
     if (threadIdx.x == 0) {
         double h2 = 0.0;
         for (int q = 0; q < NV; ++q) h2 += hc[q] * hc[q];
+        double mu = 0.0;
+        if constexpr (SUM) {  // the mean of w goes too (see k_orth_update2)
+            mu = hc[HC_SUM] / (4.0 * (double)n4);
+            h2 += mu * hc[HC_SUM];
+        }
         const double w2n = hc[NORM_SLOT], b2 = w2n - h2;
         const double beta = (b2 > 1e-20 * w2n) ? sqrt(b2) : 1.0;
         cs[NV] = 1.0 / beta;
+        cs[NV + 1] = -mu;
         if (blockIdx.x == 0) *beta_out = beta;
     }
     if ((int)threadIdx.x < NV) cs[threadIdx.x] = -hc[threadIdx.x];
@@ -250,6 +259,12 @@ k_orth_update4f(float *__restrict__ w, const float *__restrict__ V, size_t ldv, 
     for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n4; t += (size_t)gridDim.x * RED_THREADS) {
         const float4 wv = w4[t];
         double a = wv.x, b = wv.y, c = wv.z, d = wv.w;
+        if constexpr (SUM) {
+            a += cs[NV + 1];
+            b += cs[NV + 1];
+            c += cs[NV + 1];
+            d += cs[NV + 1];
+        }
         float4 vq[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) vq[q] = reinterpret_cast<const float4 *>(V + (size_t)q * ldv)[t];
@@ -639,18 +654,67 @@ void launch_multidot32(hipStream_t s, const float *V, size_t ldv, int nv, const 
     DWP_LAUNCH_CHECK();
 }
 
+void launch_multidot32_sum(hipStream_t s, const float *V, size_t ldv, int nv, const float *w, size_t n,
+                           double *partial, double *out, double *norm_out, double *sum_out) {
+    if (nv < 1 || nv > MD2_GROUP || !quad_ok(V, ldv, n) || !quad_ok(w, 0, n))
+        fail(DWP_EINVAL, "internal: float32 mean-free multidot layout");
+    switch (nv) {
+#define DWP_MD4S_CASE(K)                                                                                       \
+    case K:                                                                                                    \
+        k_multidot4f<K, true><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, 0, w, n / 4, partial, MD_STRIDE, 1);  \
+        break;
+        DWP_NV_CASES(DWP_MD4S_CASE)
+#undef DWP_MD4S_CASE
+    }
+    DWP_LAUNCH_CHECK();
+    k_reduce_partials<<<nv + 2, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, MD_STRIDE, out, nv, norm_out, sum_out);
+    DWP_LAUNCH_CHECK();
+}
+
 void launch_orth_update32(hipStream_t s, float *w, const float *V, size_t ldv, int nv, double *hc, size_t n,
-                          double *partial) {
+                          double *partial, bool mean_free) {
     if (nv < 1 || nv > 16 || !quad_ok(V, ldv, n) || !quad_ok(w, 0, n))
         fail(DWP_EINVAL, "internal: float32 orth update layout");
-    switch (nv) {
+    if (mean_free) {
+        switch (nv) {
+#define DWP_OU4S_CASE(K)                                                                                           \
+    case K: k_orth_update4f<K, true><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, V, ldv, hc, n / 4, partial, hc + 66); \
+        break;
+            DWP_NV_CASES(DWP_OU4S_CASE)
+#undef DWP_OU4S_CASE
+        }
+    } else {
+        switch (nv) {
 #define DWP_OU4_CASE(K)                                                                                     \
     case K: k_orth_update4f<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, V, ldv, hc, n / 4, partial, hc + 66); break;
-        DWP_NV_CASES(DWP_OU4_CASE)
+            DWP_NV_CASES(DWP_OU4_CASE)
 #undef DWP_OU4_CASE
+        }
     }
     DWP_LAUNCH_CHECK();
     k_rescale_if_f<<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, partial, RED_BLOCKS, hc + 65, n);
+    DWP_LAUNCH_CHECK();
+}
+
+__global__ void __launch_bounds__(RED_THREADS) k_sum_f(const float *__restrict__ x, size_t n, double *partial) {
+    __shared__ double sh[RED_THREADS / 64];
+    double v = 0.0;
+    for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n; t += (size_t)gridDim.x * RED_THREADS)
+        v += (double)x[t];
+    const double r = block_sum(v, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+__global__ void k_sub_mean_f(float *x, const double *sum, double inv_n, size_t n) {
+    const double m = *sum * inv_n;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        x[t] = (float)((double)x[t] - m);
+}
+void launch_sub_mean32(hipStream_t s, float *x, size_t n, double *partial, double *sum_out) {
+    k_sum_f<<<RED_BLOCKS, RED_THREADS, 0, s>>>(x, n, partial);
+    DWP_LAUNCH_CHECK();
+    k_reduce_partials<<<1, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, 1, sum_out, 1, nullptr);
+    DWP_LAUNCH_CHECK();
+    k_sub_mean_f<<<RED_BLOCKS, RED_THREADS, 0, s>>>(x, sum_out, 1.0 / (double)n, n);
     DWP_LAUNCH_CHECK();
 }
 

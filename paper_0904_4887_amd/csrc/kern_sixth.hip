@@ -97,10 +97,12 @@ constexpr int T6N = T6X * T6Y;
 constexpr int T6L = (L6N + T6N - 1) / T6N;  // tile loads per thread
 constexpr int Z6 = 16;                      // planes per block
 
-template <int MODE, bool TRANS, class T>
+// TX, TE: storage of x and of eps, G (float32 for a float32 Krylov vector); the
+// arithmetic is float64 either way
+template <int MODE, bool TRANS, class T, class TX = double, class TE = double>
 __global__ void __launch_bounds__(T6N)
-k_op6_tile(Grid6 g, int k_w0, int nplanes, int tiles_x, int tiles_y, const double *__restrict__ x,
-           const double *__restrict__ eps, const double *__restrict__ G, const double *__restrict__ b,
+k_op6_tile(Grid6 g, int k_w0, int nplanes, int tiles_x, int tiles_y, const TX *__restrict__ x,
+           const TE *__restrict__ eps, const TE *__restrict__ G, const double *__restrict__ b,
            T *__restrict__ out) {
     __shared__ double s0[L6N], s1[TRANS ? L6N : 1], s2[TRANS ? L6N : 1];
     const int tid = threadIdx.x;
@@ -111,7 +113,7 @@ k_op6_tile(Grid6 g, int k_w0, int nplanes, int tiles_x, int tiles_y, const doubl
     const int i = i0 + lx, j = j0 + ly;
     const bool own = i < g.nx && j < g.ny;
     const size_t cc = own ? (size_t)j * g.nx + i : 0;  // in-plane offset of this thread's node
-    const double *Gx = G, *Gy = G + g.N, *Gz = G + 2 * g.N;
+    const TE *Gx = G, *Gy = G + g.N, *Gz = G + 2 * g.N;
     // in-plane offsets of this thread's tile loads (periodic, any tile overhang)
     size_t lo[T6L];
 #pragma unroll
@@ -128,11 +130,11 @@ k_op6_tile(Grid6 g, int k_w0, int nplanes, int tiles_x, int tiles_y, const doubl
     auto zload = [&](int k, double &av, double &cv) {
         const size_t o = zplane(k) + cc;
         if (TRANS) {
-            const double y = x[o];
-            av = eps[o] * y;
-            cv = Gz[o] * y;
+            const double y = (double)x[o];
+            av = (double)eps[o] * y;
+            cv = (double)Gz[o] * y;
         } else {
-            av = x[o];
+            av = (double)x[o];
             cv = 0.0;
         }
     };
@@ -152,12 +154,12 @@ k_op6_tile(Grid6 g, int k_w0, int nplanes, int tiles_x, int tiles_y, const doubl
             if (t < L6N) {
                 const size_t o = zp + lo[m];
                 if (TRANS) {
-                    const double y = x[o];
-                    s0[t] = eps[o] * y;
-                    s1[t] = Gx[o] * y;
-                    s2[t] = Gy[o] * y;
+                    const double y = (double)x[o];
+                    s0[t] = (double)eps[o] * y;
+                    s1[t] = (double)Gx[o] * y;
+                    s2[t] = (double)Gy[o] * y;
                 } else {
-                    s0[t] = x[o];
+                    s0[t] = (double)x[o];
                 }
             }
         }
@@ -178,7 +180,7 @@ k_op6_tile(Grid6 g, int k_w0, int nplanes, int tiles_x, int tiles_y, const doubl
                                           B2 * (s0[lc + 2 * L6X] + s0[lc - 2 * L6X]) +
                                           B3 * (s0[lc + 3 * L6X] + s0[lc - 3 * L6X])) +
                                   ihz2 * (B0 * xc + B1 * (a[4] + a[2]) + B2 * (a[5] + a[1]) + B3 * (a[6] + a[0]));
-                v = Gx[o] * d1x + Gy[o] * d1y + Gz[o] * d1z + eps[o] * d2;
+                v = (double)Gx[o] * d1x + (double)Gy[o] * d1y + (double)Gz[o] * d1z + (double)eps[o] * d2;
             } else {
                 const double d1x = ihx * (A1 * (s1[lc + 1] - s1[lc - 1]) + A2 * (s1[lc + 2] - s1[lc - 2]) +
                                           A3 * (s1[lc + 3] - s1[lc - 3]));
@@ -342,13 +344,19 @@ void launch_d1eps(hipStream_t s, const Plan &p, const double *eps, double *G) {
     DWP_LAUNCH_CHECK();
 }
 
-template <int MODE, bool TRANS, class T>
-static void launch_op6_tile(hipStream_t s, const Plan &p, int k_w0, int nplanes, const double *x, const double *eps,
-                            const double *G, const double *b, T *out) {
+template <int MODE, bool TRANS, class T, class TX = double, class TE = double>
+static void launch_op6_tile(hipStream_t s, const Plan &p, int k_w0, int nplanes, const TX *x, const TE *eps,
+                            const TE *G, const double *b, T *out) {
     const Grid6 g = make_grid6(p);
     const int tx = (p.nx + T6X - 1) / T6X, ty = (p.ny + T6Y - 1) / T6Y, tz = (nplanes + Z6 - 1) / Z6;
-    k_op6_tile<MODE, TRANS, T><<<tx * ty * tz, T6N, 0, s>>>(g, k_w0, nplanes, tx, ty, x, eps, G, b, out);
+    k_op6_tile<MODE, TRANS, T, TX, TE><<<tx * ty * tz, T6N, 0, s>>>(g, k_w0, nplanes, tx, ty, x, eps, G, b, out);
     DWP_LAUNCH_CHECK();
+}
+
+void launch_apply6_f32(hipStream_t s, const Plan &p, const float *x, const float *eps, const float *G, float *out,
+                       bool trans) {
+    if (trans) launch_op6_tile<0, true, float, float, float>(s, p, 0, p.nz, x, eps, G, nullptr, out);
+    else launch_op6_tile<0, false, float, float, float>(s, p, 0, p.nz, x, eps, G, nullptr, out);
 }
 
 void launch_apply6(hipStream_t s, const Plan &p, const double *x, const double *eps, const double *G,

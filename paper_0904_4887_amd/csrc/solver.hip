@@ -299,6 +299,10 @@ void prepare_eps(dwp_ctx *c) {
     if (c->opts.krylov_fp32) {
         c->eps32.alloc(sizeof(float) * c->plan.N);
         launch_to_f32(c->stream, c->eps.as<double>(), c->eps32.as<float>(), c->plan.N);
+        if (c->opts.order == 6) {
+            c->G632.alloc(sizeof(float) * 3 * c->plan.N);
+            launch_to_f32(c->stream, c->G6.as<double>(), c->G632.as<float>(), 3 * c->plan.N);
+        }
     }
 }
 
@@ -482,7 +486,9 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
     // mixed precision with krylov_fp32: the Arnoldi basis in float32 (every
     // product, sum and the coupling update x += Z y stay float64; each restart
     // recomputes the true residual in float64)
-    const bool v32 = c->opts.krylov_fp32 != 0 && c->opts.precision == DWP_MIXED && c->opts.order == 2 &&
+    const bool six = c->opts.order == 6;
+    const bool v32 = c->opts.krylov_fp32 != 0 && c->opts.precision == DWP_MIXED &&
+                     (!six || (c->opts.cycles == 0 && c->G632.bytes >= sizeof(float) * 3 * N)) &&
                      c->V32.bytes >= sizeof(float) * N * (m + 1) && krylov32_supported(c->V32.as<float>(), N, N) &&
                      krylov32_supported(c->Z.as<float>(), N, N) && c->eps32.bytes >= sizeof(float) * N;
     float *V32 = c->V32.as<float>();
@@ -564,11 +570,25 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
             if (v32) {
                 float *Vj32 = V32 + (size_t)j * N, *Vn32 = V32 + (size_t)(j + 1) * N, *Zj32 = Z32 + (size_t)j * N;
                 apply_split(c, (const float *)Vj32, Zj32);
-                // A z (float64 arithmetic, float32 out), then the projection and update on float32 vectors
-                PROF(c, PG_APPLY, 12.0 * N, launch_apply_full_f32(s, p, (const float *)Zj32, c->eps32.as<float>(), Vn32));
-                PROF(c, PG_MULTIDOT, 4.0 * N * (j + 2), launch_multidot32(s, V32, N, j + 1, Vn32, N, part, hc, hc + 64));
                 fused[j] = 1;  // restart <= 16 is checked with the options
-                PROF(c, PG_AXPY, 4.0 * N * (j + 3), launch_orth_update32(s, Vn32, V32, N, j + 1, hc, N, part));
+                if (six) {
+                    // the adjoint's directions stay mean-free; A6 (A6^T) z without
+                    // the removal of its mean, which the mean-free update does
+                    if (c->transposed) PROF(c, PG_VEC, 16.0 * N, launch_sub_mean32(s, Zj32, N, part, coef + 411));
+                    PROF(c, PG_APPLY, 24.0 * N,
+                         launch_apply6_f32(s, p, (const float *)Zj32, c->eps32.as<float>(), c->G632.as<float>(), Vn32,
+                                           c->transposed));
+                    PROF(c, PG_MULTIDOT, 4.0 * N * (j + 2),
+                         launch_multidot32_sum(s, V32, N, j + 1, Vn32, N, part, hc, hc + 64, hc + 67));
+                    PROF(c, PG_AXPY, 4.0 * N * (j + 3), launch_orth_update32(s, Vn32, V32, N, j + 1, hc, N, part, true));
+                } else {
+                    // A z (float64 arithmetic, float32 out), then the projection and update on float32 vectors
+                    PROF(c, PG_APPLY, 12.0 * N,
+                         launch_apply_full_f32(s, p, (const float *)Zj32, c->eps32.as<float>(), Vn32));
+                    PROF(c, PG_MULTIDOT, 4.0 * N * (j + 2),
+                         launch_multidot32(s, V32, N, j + 1, Vn32, N, part, hc, hc + 64));
+                    PROF(c, PG_AXPY, 4.0 * N * (j + 3), launch_orth_update32(s, Vn32, V32, N, j + 1, hc, N, part));
+                }
             } else {
                 apply_split(c, Vj, Zj);
                 if (c->transposed) {
@@ -657,8 +677,9 @@ void validate_opts(const dwp_opts &o) {
     if (o.smooth6 != 0 && o.smooth6 != 1) fail(DWP_EINVAL, "smooth6 must be 0 or 1");
     if (o.smooth6 && o.order != 6) fail(DWP_EINVAL, "smooth6 needs the sixth-order operator (order 6)");
     if (o.krylov_fp32 != 0 && o.krylov_fp32 != 1) fail(DWP_EINVAL, "krylov_fp32 must be 0 or 1");
-    if (o.krylov_fp32 && (o.precision != DWP_MIXED || o.order != 2))
-        fail(DWP_EINVAL, "krylov_fp32 needs the mixed precision mode and the second-order operator");
+    if (o.krylov_fp32 && o.precision != DWP_MIXED) fail(DWP_EINVAL, "krylov_fp32 needs the mixed precision mode");
+    if (o.krylov_fp32 && o.order == 6 && o.cycles != 0)
+        fail(DWP_EINVAL, "krylov_fp32 with the sixth-order operator needs cycles = 0 (the FFT dry update alone)");
     if (o.krylov_fp32 && o.restart > 16) fail(DWP_EINVAL, "krylov_fp32 takes restart lengths up to 16");
 }
 

@@ -85,3 +85,10 @@ def test_create_without_device_fails_cleanly():
     assert len(B.lib().dwp_last_error(None)) > 0
     # NULL contexts are rejected, never dereferenced
     assert B.lib().dwp_solve(None, None, None, None, None) == B.DWP_EINVAL
+
+
+def test_plan_accepts_float32_krylov_vectors_where_supported():
+    # second order at any cycle count; sixth order with the FFT dry update alone
+    for kw in (dict(krylov_fp32=1, precision=1), dict(krylov_fp32=1, precision=1, restart=16),
+               dict(krylov_fp32=1, precision=1, order=6, cycles=0)):
+        B.plan((32, 32, 64), (10.0, 10.0, 20.0), **kw)

@@ -78,11 +78,14 @@ def _small_system():
     return n, L, xyz, R, q, sig, p
 
 
-@pytest.mark.parametrize("precision,smooth6", [(0, 0), (1, 0), (0, 1), (1, 1)])
-def test_solve_gradient_and_forces_match_oracle(torch, precision, smooth6):
+@pytest.mark.parametrize("precision,extra", [(0, {}), (1, {}), (0, dict(smooth6=1)), (1, dict(smooth6=1)),
+                                             (1, dict(cycles=0, scaled_dry=0, fft_fp32=1, krylov_fp32=1))],
+                         ids=["fp64", "mixed", "fp64-smooth6", "mixed-smooth6", "mixed-fft-f32-krylov"])
+def test_solve_gradient_and_forces_match_oracle(torch, precision, extra):
     n, L, xyz, R, q, sig, p = _small_system()
     tol = 1e-11 if precision == 0 else 1e-9
-    s = _solver(n, L, z_wet_lo=1.0, z_wet_hi=7.5, tol=tol, precision=precision, scaled_dry=1, smooth6=smooth6)
+    opts = dict(dict(z_wet_lo=1.0, z_wet_hi=7.5, tol=tol, precision=precision, scaled_dry=1), **extra)
+    s = _solver(n, L, **opts)
     s.build_epsilon(xyz, R, p)
     rho = s.build_rho(xyz, q, sig)
     phi, E, info = s.solve(rho)
@@ -134,8 +137,10 @@ def test_forces_match_central_differences_on_the_slab(torch):
     assert max(errs) <= 1e-5 * np.abs(F).max(), (max(errs), np.abs(F).max())
 
 
-@pytest.mark.parametrize("smooth6", [0, 1])
-def test_slab_matches_stored_oracle(torch, smooth6):
+@pytest.mark.parametrize("extra", [dict(smooth6=0), dict(smooth6=1),
+                                   dict(precision=1, cycles=0, scaled_dry=0, fft_fp32=1, krylov_fp32=1)],
+                         ids=["vcycle", "smooth6", "mixed-fft-f32-krylov"])
+def test_slab_matches_stored_oracle(torch, extra):
     path = os.path.join(GOLDEN, "oracle_slab6_96x96x192.json")
     if not os.path.exists(path):
         pytest.skip("no stored oracle result for the sixth-order slab")
@@ -144,7 +149,7 @@ def test_slab_matches_stored_oracle(torch, smooth6):
     w = W.slab((96, 96, 192), tol=1e-10, precision=0)
     from paper_0904_4887_amd.binding import Solver
     s = Solver(0)
-    s.set_grid(w.n, w.L, **w.solver_opts(order=6, scaled_dry=1, pre=2, post=2, coarse_sweeps=64, smooth6=smooth6))
+    s.set_grid(w.n, w.L, **w.solver_opts(**dict(dict(order=6, scaled_dry=1, pre=2, post=2, coarse_sweeps=64), **extra)))
     s.build_epsilon(w.xyz, w.radius, w.eps_params)
     rho = s.build_rho(w.xyz, w.q, w.sigma)
     phi, E, info = s.solve(rho)
