@@ -100,32 +100,34 @@ def solver_for(w, precision, torch, profile=0, **extra):
 
 
 def sweep_source_digest():
-    """sha256 of the fused sweep's source: the text of kern_grid.hip from its
-    tile layout (`template <int W> struct FLayout`) to the banner of the next
-    kernel (`// ---...--- residual + restriction`), followed by the text of its
-    launchers, from `static int fused_chunk` to the end of
-    `launch_sweep_fused<double>`.  Edits elsewhere in the file leave it alone."""
+    """sha256 of the fine-level sweep's source: band_sweep.h (the row-band
+    kernel's per-thread code), then the text of kern_grid.hip from the row-band
+    kernel (`// Row-band variant of the fused sweep`) to the banner of the next
+    kernel (`// ---...--- residual + restriction`), then the text of its
+    launchers, from `// Row-band sweep: returns false` to the end of
+    `launch_sweep_fused<double>`.  Edits elsewhere leave it alone."""
     import hashlib
-    src = os.path.join(ROOT, "paper_0904_4887_amd", "csrc", "kern_grid.hip")
-    if not os.path.exists(src):
+    csrc = os.path.join(ROOT, "paper_0904_4887_amd", "csrc")
+    src, hdr = os.path.join(csrc, "kern_grid.hip"), os.path.join(csrc, "band_sweep.h")
+    if not (os.path.exists(src) and os.path.exists(hdr)):
         return None
     text = open(src).read()
     try:
-        a = text.index("template <int W> struct FLayout")
+        a = text.index("// Row-band variant of the fused sweep")
         b = text.index("residual + restriction", a)
-        c = text.index("static int fused_chunk")
+        c = text.index("// Row-band sweep: returns false")
         d = text.index("void launch_sweep_fused<double>", c)
         d = text.index("\n}\n", d) + 3
     except ValueError:
         return None
-    return hashlib.sha256((text[a:b] + text[c:d]).encode()).hexdigest()
+    return hashlib.sha256((open(hdr).read() + text[a:b] + text[c:d]).encode()).hexdigest()
 
 
 def stored_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary,
     if that summary was taken on the current source of the kernel and its
     launchers (sweep_source_digest), else None."""
-    summ = os.path.join(ROOT, "profiles", "sweep_fused_slab_192x192x384_mixed.md")
+    summ = os.path.join(ROOT, "profiles", "sweep_band_slab_192x192x384_mixed.md")
     digest = sweep_source_digest()
     if digest is None or not os.path.exists(summ):
         return None
@@ -134,7 +136,7 @@ def stored_traffic(kernel):
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("k_sweep_fused source sha256") != digest or vals.get("kernel") != kernel:
+    if vals.get("source sha256") != digest or vals.get("kernel") != kernel:
         return None
     try:
         return float(vals["hbm bytes per launch"])
@@ -544,7 +546,8 @@ def main():
     err_main = errors_vs_oracle(w.name, E, infos[-1], keep["phi"], F, torch)
 
     # roofline of the fine-level smoother (the dominant kernel of the wet solve),
-    # from the HIP events recorded around each of its launches in the timed steps
+    # from the HIP events that each of its launches in the timed steps records
+    # at the kernel's start and end (hipExtLaunchKernel)
     roof = None
     dom = prof.get("rbgs_fine")
     smoother_gbs = None
@@ -553,9 +556,9 @@ def main():
         per_launch = dom["bytes"] / dom["launches"]
         gbs = per_launch / (avg_ms * 1e-3) / 1e9
         smoother_gbs = round(gbs, 1)
-        roof = {"kernel": "k_sweep_fused (fine-level red-black Gauss-Seidel sweep)", "bound": "hbm",
+        roof = {"kernel": "k_sweep_band (fine-level red-black Gauss-Seidel sweep on bands of whole rows)", "bound": "hbm",
                 "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                "traffic": stored_traffic("k_sweep_fused<float, 4, *>") if args.precision == "mixed" and w.n == (192, 192, 384) else None,
+                "traffic": stored_traffic("k_sweep_band<float, 4, *>") if args.precision == "mixed" and w.n == (192, 192, 384) else None,
                 "avg_launch_us": round(1e3 * avg_ms, 2), "launches": dom["launches"],
                 "algorithmic_bytes_per_launch": per_launch}
     # the headline: the same steps with no instrumentation at all

@@ -85,9 +85,13 @@ typedef struct {
                            /* the context stream (see dwp_profile); 2: only    */
                            /* the fine-level smoother (least overhead); 0 off  */
     int smoother;          /* red-black Gauss-Seidel on the large levels:      */
-                           /* 1 = one fused pass per sweep (out of place),     */
-                           /* 0 = one launch per colour (in place); the two    */
-                           /* give the same sweep up to rounding               */
+                           /* 1 = one fused pass per sweep (out of place), on  */
+                           /* blocks of whole grid rows where that shape fits  */
+                           /* (nx a multiple of the vector width, at most 1024 */
+                           /* threads, an even band height dividing ny), else  */
+                           /* on 32 x 16 tiles; 2 = the fused pass on tiles    */
+                           /* always; 0 = one launch per colour (in place);    */
+                           /* all give the same sweep up to rounding           */
     int fft_fp32;          /* 1 (mixed precision only): the FFT dry update     */
                            /* runs its spectrum and transforms in float32; the */
                            /* real input and output stay float64.  0: float64  */

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstddef>
 #include <cstdint>
@@ -120,6 +121,11 @@ struct Profiler {
     size_t next = 0;
     int begin(hipStream_t s, int group = -1);                 // -1 when off
     void end(hipStream_t s, int ev, int group, double bytes);
+    // An event pair for a launch that records them itself at the kernel's
+    // start and end (hipExtLaunchKernel): reserve, launch, then done.
+    int reserve(int group);                                   // -1 when off
+    hipEvent_t event(int ev, int k) const { return ev < 0 ? nullptr : pool[ev + k]; }
+    void done(int ev, int group, double bytes);
     void collect();                                           // after a stream sync
     void reset();
     ~Profiler();
@@ -260,7 +266,8 @@ void launch_zero(hipStream_t s, T *x, size_t n);
 // One red-black sweep (first_color, then the other) from uin to uout in a
 // single pass; uin, uout: ghosted arrays of level L (ghost planes zero).
 template <class T>
-void launch_sweep_fused(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color, bool zero_in);
+void launch_sweep_fused(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color, bool zero_in,
+                        bool tiles_only, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // The rest of a V-cycle from level l0 down, in one single-workgroup kernel.
 template <class T>
 void launch_vcycle_bottom(hipStream_t s, const std::vector<Level *> &levels, size_t l0, int pre, int post,

@@ -425,6 +425,11 @@ __device__ __forceinline__ double gs_value(double off, double f, double diag) {
     r = __builtin_fma(r, e, r);
     return (off - f) * r;
 }
+}  // namespace
+}  // namespace dwp
+#include "band_sweep.h"
+namespace dwp {
+namespace {
 
 // Neighbour sums at ghosted index g of slab point (i, j): returns the
 // off-diagonal sum  sum_m w_m u_m  and the diagonal  sum_m w_m,
@@ -829,6 +834,48 @@ k_sweep_fused(const T *__restrict__ uin, T *__restrict__ uout, const T *__restri
 #pragma unroll
         for (int s = 0; s < FUNROLL; ++s) step(s, k0 - 1 + base + s, pu[s % FPD], pe[s % FPD], pf[s % FPD]);
     }
+}
+
+// Row-band variant of the fused sweep (per-thread code in band_sweep.h): one
+// W-wide vector of one band row per thread, (ty + 4) * nx / W threads.
+// Planes loaded ahead: one for the general float32 variant with 4-wide
+// vectors (measured in the slab solve: 2 % faster than two, whose registers
+// it does not need), two otherwise.  One block of (ty + 4) * nx / W threads
+// per CU is the measured optimum at 192 x 192: capping registers for two
+// (six wavefronts per SIMD) spills and shortens the z chunks, 40 % slower.
+template <class T, int W, bool ZIN> constexpr int band_pd() { return ZIN || W == 2 ? 2 : 1; }
+template <class T, int W, bool ZIN, bool DOWN>
+__device__ __forceinline__ void band_march(const BandArgs<T> &a, T *lds, int band, int chunk) {
+    BandSweep<T, W, ZIN, DOWN, band_pd<T, W, ZIN>()> b;
+    b.init(a, lds, band, chunk, threadIdx.x);
+    b.prologue();
+    __syncthreads();
+    // an even number of steps (one past the chunk writes nothing), so that
+    // the prefetch slot of each step is a constant
+    const int m0 = b.first(), n = b.nsteps();
+    for (int st = 0; st < n; st += 2) {
+        b.template step<0>(m0 + b.D * st);
+        __syncthreads();
+        b.template step<1>(m0 + b.D * (st + 1));
+        __syncthreads();
+    }
+}
+// Tile t -> (band, chunk): groups of gb consecutive bands (gb divides the band
+// count), chunks in order inside a group, so that the contiguous run of tiles
+// each XCD receives covers a few neighbouring bands over a run of neighbouring
+// chunks, whose shared halo rows and planes then meet in that XCD's L2.  Odd
+// chunks march down, even ones up.
+template <class T, int W, bool ZIN>
+__global__ void __launch_bounds__(1024) k_sweep_band(BandArgs<T> a, int nb_real, int gb) {
+    extern __shared__ __align__(16) unsigned char band_lds[];
+    const int t = xcd_tile(nb_real);
+    if (t >= nb_real) return;
+    const int nchunks = (a.nw + a.kc - 1) / a.kc;
+    const int g = t / (gb * nchunks), q = t - g * gb * nchunks;
+    const int chunk = q / gb, band = g * gb + (q - (q / gb) * gb);
+    T *lds = reinterpret_cast<T *>(band_lds);
+    if (chunk & 1) band_march<T, W, ZIN, true>(a, lds, band, chunk);
+    else band_march<T, W, ZIN, false>(a, lds, band, chunk);
 }
 
 // ---------------------------------------------------------------- residual + restriction
@@ -1457,34 +1504,105 @@ static int fused_slots() {
 }
 
 template <class T, int W, bool ZIN>
-static void sweep_fused_w(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color) {
+static void sweep_fused_w(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color,
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
     LevelArgs a = level_args(L);
     const int tx = (L.nx + FTX - 1) / FTX, ty = (L.ny + FTY - 1) / FTY;
     const int kc = fused_chunk(tx * ty, L.nw, fused_slots<T, W, ZIN>());
     const int tz = (L.nw + kc - 1) / kc;
     const int nb = tx * ty * tz, padded = (nb + 7) / 8 * 8;
-    k_sweep_fused<T, W, ZIN><<<padded, FNT, 0, s>>>(uin, uout, L.eps.as<T>(), L.f.as<T>(), a, first_color, tx, ty,
-                                                   kc, nb);
+    hipExtLaunchKernelGGL(k_sweep_fused<T, W, ZIN>, dim3(padded), dim3(FNT), 0, s, e0, e1, 0, uin, uout,
+                          L.eps.as<T>(), L.f.as<T>(), a, first_color, tx, ty, kc, nb);
     DWP_LAUNCH_CHECK();
 }
 template <class T, int W>
-static void sweep_fused_z(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color, bool zero_in) {
-    if (zero_in) sweep_fused_w<T, W, true>(s, L, uin, uout, first_color);
-    else sweep_fused_w<T, W, false>(s, L, uin, uout, first_color);
+static void sweep_fused_z(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color, bool zero_in,
+                          hipEvent_t e0, hipEvent_t e1) {
+    if (zero_in) sweep_fused_w<T, W, true>(s, L, uin, uout, first_color, e0, e1);
+    else sweep_fused_w<T, W, false>(s, L, uin, uout, first_color, e0, e1);
+}
+
+// Row-band sweep: returns false (and launches nothing) where the band shape
+// does not fit -- nx not a multiple of W, more than 1024 threads per block,
+// or no band height ty in BAND_ROWS that divides ny.  ty = 0 picks the first
+// height that fits; the chunk kc is chosen by the same round-filling cost
+// model as the tiled kernel's.
+constexpr int BAND_ROWS[] = {12, 8, 16, 6, 4};
+template <class T, int W, bool ZIN>
+static bool sweep_band_w(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color, int ty,
+                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+    if (L.nx % W || L.nx < 2 * W) return false;
+    auto fits = [&](int t) {
+        const long nt = (long)(t + 4) * (L.nx / W);
+        const size_t bytes = sizeof(T) * (size_t)band_lds_elems(L.nx, t);
+        return t >= 2 && t % 2 == 0 && L.ny % t == 0 && L.ny >= t + 4 && nt <= 1024 && bytes <= BOTTOM_LDS_BYTES;
+    };
+    if (ty == 0)
+        for (int t : BAND_ROWS)
+            if (fits(t)) { ty = t; break; }
+    if (ty == 0 || !fits(ty)) return false;
+    const int nt = (ty + 4) * (L.nx / W);
+    const size_t bytes = sizeof(T) * (size_t)band_lds_elems(L.nx, ty);
+    // per device: the dynamic-LDS limit raised once, the CU count, and the
+    // resident blocks per CU for each band height (they depend on ty only)
+    static int cus[64] = {0};
+    static int per_cu[64][17] = {{0}};
+    int dev = 0;
+    DWP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64 || ty > 16) fail(DWP_EINVAL, "internal: device index or band height out of range");
+    if (!cus[dev]) {
+        DWP_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sweep_band<T, W, ZIN>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)BOTTOM_LDS_BYTES));
+        DWP_HIP(hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev));
+    }
+    int &per = per_cu[dev][ty];
+    if (!per) DWP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_band<T, W, ZIN>, nt, bytes));
+    if (per < 1) return false;
+    const int bands = L.ny / ty;
+    const long slots = (long)cus[dev] * per;
+    int kc = 1;
+    long best = -1;
+    for (int c = 1; c <= 64; ++c) {
+        const long blocks = (long)bands * ((L.nw + c - 1) / c);
+        const long cost = (blocks + slots - 1) / slots * (c + 2);
+        if (best < 0 || cost < best) { best = cost; kc = c; }
+    }
+    const int nb = bands * ((L.nw + kc - 1) / kc), padded = (nb + 7) / 8 * 8;
+    const int gb = bands % 4 == 0 ? 4 : (bands % 2 == 0 ? 2 : 1);
+    const LevelArgs la = level_args(L);
+    const bool f32 = sizeof(T) == 4;
+    BandArgs<T> a{uin, uout, L.eps.as<T>(), L.f.as<T>(), L.nx, L.ny, L.nw, ty, bands, kc, first_color,
+                  (T)(f32 ? la.cxf : la.cx), (T)(f32 ? la.cyf : la.cy), (T)(f32 ? la.czf : la.cz)};
+    hipExtLaunchKernelGGL(k_sweep_band<T, W, ZIN>, dim3(padded), dim3(nt), (uint32_t)bytes, s, e0, e1, 0, a, nb, gb);
+    DWP_LAUNCH_CHECK();
+    return true;
 }
 
 // 16-byte tile loads when nx allows (float: nx % 4 == 0), else 8-byte ones;
 // the level arrays come from hipMalloc and planes are whole vectors.
+// The row-band kernel where its shape fits (unless tiles_only), else the
+// tiled one.
+template <class T, int W>
+static bool sweep_band_z(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color, bool zero_in,
+                         hipEvent_t e0, hipEvent_t e1) {
+    return zero_in ? sweep_band_w<T, W, true>(s, L, uin, uout, first_color, 0, e0, e1)
+                   : sweep_band_w<T, W, false>(s, L, uin, uout, first_color, 0, e0, e1);
+}
 template <>
 void launch_sweep_fused<float>(hipStream_t s, const Level &L, const float *uin, float *uout, int first_color,
-                               bool zero_in) {
-    if (L.nx % 4 == 0) sweep_fused_z<float, 4>(s, L, uin, uout, first_color, zero_in);
-    else sweep_fused_z<float, 2>(s, L, uin, uout, first_color, zero_in);
+                               bool zero_in, bool tiles_only, hipEvent_t e0, hipEvent_t e1) {
+    if (L.nx % 4 == 0) {
+        if (tiles_only || !sweep_band_z<float, 4>(s, L, uin, uout, first_color, zero_in, e0, e1))
+            sweep_fused_z<float, 4>(s, L, uin, uout, first_color, zero_in, e0, e1);
+    } else if (tiles_only || !sweep_band_z<float, 2>(s, L, uin, uout, first_color, zero_in, e0, e1)) {
+        sweep_fused_z<float, 2>(s, L, uin, uout, first_color, zero_in, e0, e1);
+    }
 }
 template <>
 void launch_sweep_fused<double>(hipStream_t s, const Level &L, const double *uin, double *uout, int first_color,
-                                bool zero_in) {
-    sweep_fused_z<double, 2>(s, L, uin, uout, first_color, zero_in);
+                                bool zero_in, bool tiles_only, hipEvent_t e0, hipEvent_t e1) {
+    if (tiles_only || !sweep_band_z<double, 2>(s, L, uin, uout, first_color, zero_in, e0, e1))
+        sweep_fused_z<double, 2>(s, L, uin, uout, first_color, zero_in, e0, e1);
 }
 
 template <class T>

@@ -50,7 +50,7 @@ static const char *const kGroupNames[PG_COUNT] = {
 
 const char *prof_group_name(int g) { return (g >= 0 && g < PG_COUNT) ? kGroupNames[g] : ""; }
 
-int Profiler::begin(hipStream_t s, int group) {
+int Profiler::reserve(int group) {
     if (!on || (only >= 0 && group != only)) return -1;
     while (next + 2 > pool.size()) {
         hipEvent_t e;
@@ -59,14 +59,23 @@ int Profiler::begin(hipStream_t s, int group) {
     }
     const int ev = (int)next;
     next += 2;
-    DWP_HIP(hipEventRecord(pool[ev], s));
+    return ev;
+}
+
+void Profiler::done(int ev, int group, double b) {
+    if (ev >= 0) pending.push_back(Pending{group, ev, b});
+}
+
+int Profiler::begin(hipStream_t s, int group) {
+    const int ev = reserve(group);
+    if (ev >= 0) DWP_HIP(hipEventRecord(pool[ev], s));
     return ev;
 }
 
 void Profiler::end(hipStream_t s, int ev, int group, double b) {
     if (ev < 0) return;
     DWP_HIP(hipEventRecord(pool[ev + 1], s));
-    pending.push_back(Pending{group, ev, b});
+    done(ev, group, b);
 }
 
 void Profiler::collect() {
@@ -333,7 +342,7 @@ void vcycle(dwp_ctx *c, size_t l, bool u_unset) {
     // Jacobi); the adjoint solve keeps the symmetric 7-point smoother, which
     // approximates A6^T as well as it approximates A6
     const bool six = l == 0 && c->opts.order == 6 && c->opts.smooth6 == 1 && !c->transposed;
-    const bool fused = !six && c->opts.smoother == 1 && L.n_interior() >= FUSED_MIN_POINTS;
+    const bool fused = !six && c->opts.smoother != 0 && L.n_interior() >= FUSED_MIN_POINTS;
     const bool coarsest = l + 1 == p.levels.size();
     // the first sweep starts from a zero correction on coarse levels and in
     // the first cycle on the fine level, except that without pre-sweeps it
@@ -357,7 +366,12 @@ void vcycle(dwp_ctx *c, size_t l, bool u_unset) {
             std::swap(L.u.p, L.u2.p);
         } else if (fused) {
             const double b = zero_in ? 1.5 * pass_bytes : 2.0 * pass_bytes;
-            PROF(c, sg, b, launch_sweep_fused<T>(s, L, L.u.as<T>(), L.u2.as<T>(), first, zero_in));
+            // timed by events that the launch itself records at the kernel's
+            // start and end
+            const int ev = c->prof.reserve(sg);
+            launch_sweep_fused<T>(s, L, L.u.as<T>(), L.u2.as<T>(), first, zero_in, c->opts.smoother == 2,
+                                  c->prof.event(ev, 0), c->prof.event(ev, 1));
+            c->prof.done(ev, sg, b);
             std::swap(L.u.p, L.u2.p);
         } else {
             PROF(c, sg, pass_bytes, launch_level_smooth<T>(s, L, first));
@@ -670,7 +684,7 @@ void validate_opts(const dwp_opts &o) {
     if (o.scaled_dry != 0 && o.scaled_dry != 1) fail(DWP_EINVAL, "scaled_dry must be 0 or 1");
     if (o.warm_start != 0 && o.warm_start != 1) fail(DWP_EINVAL, "warm_start must be 0 or 1");
     if (o.profile < 0 || o.profile > 2) fail(DWP_EINVAL, "profile must be 0, 1 or 2");
-    if (o.smoother != 0 && o.smoother != 1) fail(DWP_EINVAL, "smoother must be 0 or 1");
+    if (o.smoother < 0 || o.smoother > 2) fail(DWP_EINVAL, "smoother must be 0, 1 or 2");
     if (o.fft_fp32 != 0 && o.fft_fp32 != 1) fail(DWP_EINVAL, "fft_fp32 must be 0 or 1");
     if (o.fft_fp32 && o.precision != DWP_MIXED) fail(DWP_EINVAL, "fft_fp32 needs the mixed precision mode");
     if (o.order != 2 && o.order != 6) fail(DWP_EINVAL, "order must be 2 or 6");

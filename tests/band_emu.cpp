@@ -1,0 +1,125 @@
+// Host stepping of the row-band red-black sweep: every thread of every block
+// runs the kernel's own per-thread code (band_sweep.h) in plain C++, each
+// global and LDS access is checked against its buffer, and the output is
+// compared with two in-place colour passes.  Threads of a step run in both
+// orders, which must agree: no thread may read, within one step, a value
+// another thread writes in it (the kernel has one barrier per step).
+#include <cstdio>
+#include <cstdlib>
+#include <cmath>
+#include <vector>
+#include <random>
+#include <algorithm>
+#define __host__
+#define __device__
+#define __forceinline__ inline
+#include <limits>
+#define BAND_CHECK(i, n) do { if (!((size_t)(i) < (size_t)(n))) { fprintf(stderr, "OOB %s:%d %zu >= %zu\n", __FILE__, __LINE__, (size_t)(i), (size_t)(n)); abort(); } } while (0)
+// the device divides by the hardware reciprocal; here plain division (the
+// comparison below is with colour passes that use the same function)
+namespace dwp {
+inline float gs_value(float off, float f, float diag) { return (off - f) / diag; }
+inline double gs_value(double off, double f, double diag) { return (off - f) / diag; }
+}
+#include "band_sweep.h"
+using namespace dwp;
+
+// one block: every thread's prologue, then the steps with a barrier between
+// them (threads of a step in order, or in reverse)
+template <class T, int W, bool ZIN, bool DOWN, int PD>
+void march(const BandArgs<T> &a, T *lds, int band, int chunk, int nt, bool reverse) {
+    std::vector<BandSweep<T, W, ZIN, DOWN, PD>> th(nt);
+    for (int t = 0; t < nt; ++t) { th[t].init(a, lds, band, chunk, t); th[t].prologue(); }
+    const int m0 = th[0].first(), n = th[0].nsteps(), D = DOWN ? -1 : 1;
+    for (int st = 0; st < n; st += 2) {
+        for (int q = 0; q < nt; ++q) th[reverse ? nt - 1 - q : q].template step<0>(m0 + D * st);
+        for (int q = 0; q < nt; ++q) th[reverse ? nt - 1 - q : q].template step<1>(m0 + D * (st + 1));
+    }
+}
+
+template <class T, int W, bool ZIN>
+int run(int nx, int ny, int nw, int ty, int kc, int c0, bool reverse, unsigned seed) {
+    const size_t plane = (size_t)nx * ny;
+    std::vector<T> u((nw + 2) * plane, T(0)), e((nw + 2) * plane), f(nw * plane), out((nw + 2) * plane, T(0));
+    std::mt19937 g(seed);
+    std::uniform_real_distribution<double> U(0, 1);
+    for (auto &x : e) x = (T)(1.0 + 77.0 * U(g));
+    if (!ZIN) for (size_t i = plane; i < (nw + 1) * plane; ++i) u[i] = (T)(U(g) - 0.5);
+    for (auto &x : f) x = (T)(10.0 * (U(g) - 0.5));
+    const T cx = (T)1.3, cy = (T)0.7, cz = (T)0.4;
+    // reference: two colour passes in place on a copy of u
+    std::vector<T> ref = u;
+    auto at = [&](int i, int j, int k) -> size_t { return (size_t)(k + 1) * plane + (size_t)((j + ny) % ny) * nx + (i + nx) % nx; };
+    for (int col = 0; col < 2; ++col) {
+        const int cc = col == 0 ? c0 : 1 - c0;
+        for (int k = 0; k < nw; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    if (((i + j + k) & 1) != cc) continue;
+                    const T e0 = e[at(i, j, k)];
+                    ref[at(i, j, k)] = band_point<T>(cx, cy, cz, e0, e[at(i + 1, j, k)], e[at(i - 1, j, k)], e[at(i, j + 1, k)],
+                                                     e[at(i, j - 1, k)], e[at(i, j, k + 1)], e[at(i, j, k - 1)],
+                                                     ref[at(i + 1, j, k)], ref[at(i - 1, j, k)], ref[at(i, j + 1, k)],
+                                                     ref[at(i, j - 1, k)], ref[at(i, j, k + 1)], ref[at(i, j, k - 1)],
+                                                     f[(size_t)k * plane + (size_t)j * nx + i]);
+                }
+    }
+    const int bands = ny / ty, nchunks = (nw + kc - 1) / kc, nb = bands * nchunks, nt = (ty + 4) * (nx / W);
+    const int gb = bands % 4 == 0 ? 4 : (bands % 2 == 0 ? 2 : 1);
+    BandArgs<T> a{u.data(), out.data(), e.data(), f.data(), nx, ny, nw, ty, bands, kc, c0, cx, cy, cz};
+    std::vector<int> seen(nb, 0);
+    for (int t = 0; t < nb; ++t) {
+        // the kernel's tile -> (band, chunk) decoding; odd chunks march down
+        const int g = t / (gb * nchunks), q = t - g * gb * nchunks;
+        const int chunk = q / gb, band = g * gb + (q - (q / gb) * gb);
+        BAND_CHECK(band, bands);
+        BAND_CHECK(chunk, nchunks);
+        ++seen[chunk * bands + band];
+        std::vector<T> lds(band_lds_elems(nx, ty), std::numeric_limits<T>::quiet_NaN());
+        // both prefetch depths the kernel may use, alternating over the tiles
+        if (chunk & 1) {
+            if (t & 1) march<T, W, ZIN, true, 1>(a, lds.data(), band, chunk, nt, reverse);
+            else march<T, W, ZIN, true, 2>(a, lds.data(), band, chunk, nt, reverse);
+        } else {
+            if (t & 1) march<T, W, ZIN, false, 2>(a, lds.data(), band, chunk, nt, reverse);
+            else march<T, W, ZIN, false, 1>(a, lds.data(), band, chunk, nt, reverse);
+        }
+    }
+    for (int v : seen)
+        if (v != 1) { printf("tile mapping is not a bijection\n"); return 1; }
+    double md = 0, mref = 0;
+    size_t bad = 0;
+    for (size_t i = 0; i < out.size(); ++i) {
+        const bool ghost = i < plane || i >= (nw + 1) * plane;
+        const double want = ghost ? 0.0 : (double)ref[i];
+        const double d = std::fabs((double)out[i] - want);
+        if (!(d <= 0.0)) ++bad;
+        if (std::isnan(d)) md = INFINITY; else md = std::max(md, d);
+        mref = std::max(mref, std::fabs(want));
+    }
+    printf("%s W=%d ZIN=%d %dx%dx%d ty=%d kc=%d c0=%d rev=%d: blocks %d threads %d  maxdiff %.3g (max %.3g) mismatches %zu\n",
+           sizeof(T) == 4 ? "f32" : "f64", W, (int)ZIN, nx, ny, nw, ty, kc, c0, (int)reverse, nb, nt, md, mref, bad);
+    return bad != 0;
+}
+
+int main() {
+    int fails = 0;
+    for (int rev = 0; rev < 2; ++rev)
+        for (int c0 = 0; c0 < 2; ++c0) {
+            fails += run<float, 4, false>(24, 24, 13, 4, 4, c0, rev, 1);
+            fails += run<float, 4, false>(32, 16, 9, 8, 2, c0, rev, 2);
+            fails += run<float, 4, true>(24, 24, 13, 4, 6, c0, rev, 3);
+            fails += run<float, 2, false>(18, 12, 11, 6, 4, c0, rev, 4);
+            fails += run<float, 2, true>(18, 12, 11, 6, 4, c0, rev, 5);
+            fails += run<double, 2, false>(20, 24, 10, 12, 8, c0, rev, 6);
+            fails += run<double, 2, true>(20, 24, 10, 12, 8, c0, rev, 7);
+            fails += run<float, 4, false>(192, 24, 21, 12, 6, c0, rev, 8);
+            fails += run<float, 4, false>(16, 8, 5, 4, 64, c0, rev, 9);
+            fails += run<float, 4, false>(8, 8, 1, 4, 2, c0, rev, 10);
+            fails += run<float, 4, false>(24, 32, 23, 8, 3, c0, rev, 11);
+            fails += run<double, 2, true>(12, 16, 17, 4, 5, c0, rev, 12);
+            fails += run<float, 2, false>(10, 36, 9, 6, 1, c0, rev, 13);
+        }
+    printf("%s (%d failing cases)\n", fails ? "FAIL" : "OK", fails);
+    return fails != 0;
+}

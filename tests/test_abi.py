@@ -35,7 +35,7 @@ def test_plan_rejects_bad_grid_sizes(n):
                                 dict(restart=64), dict(cycles=-1), dict(cycles=65), dict(pre=0, post=0), dict(max_outer=0),
                                 dict(z_wet_lo=8.0, z_wet_hi=8.5), dict(z_wet_lo=0.0, z_wet_hi=20.0),
                                 dict(profile=3), dict(scaled_dry=3), dict(fft_fp32=2),
-                                dict(fft_fp32=1, precision=0), dict(smoother=2), dict(order=4),
+                                dict(fft_fp32=1, precision=0), dict(smoother=3), dict(order=4),
                                 dict(smooth6=2), dict(smooth6=1), dict(smooth6=1, order=2),
                                 dict(krylov_fp32=2), dict(krylov_fp32=1, precision=0),
                                 dict(krylov_fp32=1, precision=1, order=6),

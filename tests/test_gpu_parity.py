@@ -195,20 +195,22 @@ def test_error_paths(torch):
     assert info["rel_res"] <= 1e-10
 
 
+@pytest.mark.parametrize("smoother", [1, 2])
 @pytest.mark.parametrize("precision,cycles,pre,post", [(0, 1, 2, 2), (1, 1, 2, 2), (1, 2, 2, 2), (0, 1, 0, 1),
                                                     (1, 2, 0, 2)])
-def test_fused_sweep_equals_colour_passes(torch, precision, cycles, pre, post):
+def test_fused_sweep_equals_colour_passes(torch, precision, cycles, pre, post, smoother):
     """The fused out-of-place sweep and the two in-place colour passes are the
     same Gauss-Seidel sweep: one application of the split agrees to rounding.
     The fine wet level of this grid (96 x 96 x 151) is above the size from
-    which the fused kernel takes over, so both kernels really run.  Without
-    pre-sweeps the first fused sweep follows the coarse-grid correction and
-    must read it (its zero-input variant would drop it)."""
+    which the fused kernel takes over, so both kernels really run: the fused
+    one on bands of 12 whole rows (smoother 1) or on 32 x 16 tiles (smoother
+    2).  Without pre-sweeps the first fused sweep follows the coarse-grid
+    correction and must read it (its zero-input variant would drop it)."""
     from paper_0904_4887_amd.binding import plan
     w = W.slab(n=(96, 96, 192), exclusion=True)
     fine = plan(w.n, w.L, z_wet_lo=w.z_wet[0], z_wet_hi=w.z_wet[1])["levels"][0]
     assert fine[0] * fine[1] * fine[2] >= 1 << 20
-    s = _solver(torch, w.n, w.L, z_wet_lo=w.z_wet[0], z_wet_hi=w.z_wet[1], precision=precision, smoother=1,
+    s = _solver(torch, w.n, w.L, z_wet_lo=w.z_wet[0], z_wet_hi=w.z_wet[1], precision=precision, smoother=smoother,
                 cycles=cycles, pre=pre, post=post)
     s.build_epsilon(w.xyz, w.radius, w.eps_params)
     rng = np.random.default_rng(3)
@@ -219,17 +221,21 @@ def test_fused_sweep_equals_colour_passes(torch, precision, cycles, pre, post):
     assert _rel(z1, z0) <= (1e-12 if precision == 0 else 2e-5)
 
 
+@pytest.mark.parametrize("smoother", [1, 2])
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("n", [(216, 216, 48), (162, 108, 96)])
-def test_fused_sweep_equals_colour_passes_ragged_tiles(torch, n, precision):
+def test_fused_sweep_equals_colour_passes_ragged_tiles(torch, n, precision, smoother):
     """The fused sweep against the two colour passes on grids whose x and y
     extents are not multiples of its 32 x 16 tile (tiles overhang the
     periodic wrap in x and y).  On 162 x 108 nx is 2 mod 4, so the float32
     variant loads 8-byte vectors; x cannot be halved there, so that grid has
-    a single multigrid level, smoothed by the grid-wide kernels."""
+    a single multigrid level, smoothed by the grid-wide kernels.  With
+    smoother 1 the row-band kernel takes these levels with bands of 12 rows
+    (216, float32), 4 rows (216, float64) and 6 rows (108), with 4- and
+    2-wide vectors."""
     from paper_0904_4887_amd.binding import plan
     L = (0.07 * n[0], 0.07 * n[1], 0.1 * n[2])
-    opts = dict(z_wet_lo=0.3 * L[2], z_wet_hi=L[2], precision=precision, smoother=1, coarse_sweeps=3)
+    opts = dict(z_wet_lo=0.3 * L[2], z_wet_hi=L[2], precision=precision, smoother=smoother, coarse_sweeps=3)
     lv = plan(n, L, **opts)["levels"]
     assert lv[0][0] * lv[0][1] * lv[0][2] >= 1 << 20
     s = _solver(torch, n, L, **opts)
