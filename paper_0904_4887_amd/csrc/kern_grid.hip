@@ -428,8 +428,30 @@ __device__ __forceinline__ double gs_value(double off, double f, double diag) {
 }  // namespace
 }  // namespace dwp
 #include "band_sweep.h"
+#include "band_apply.h"
 namespace dwp {
 namespace {
+
+// Row-band variant of k_apply_tile (per-thread code in band_apply.h):
+// (ty + 2) * nx / W threads, the tile -> (band, chunk) order of k_sweep_band.
+template <int MODE, class TS, class TB>
+__global__ void __launch_bounds__(1024) k_apply_band(ApplyArgs<TS, TB> a, int nb_real, int gb) {
+    extern __shared__ __align__(16) unsigned char apply_lds[];
+    const int t = xcd_tile(nb_real);
+    if (t >= nb_real) return;
+    const int nchunks = (a.nplanes + a.kc - 1) / a.kc;
+    const int g = t / (gb * nchunks), q = t - g * gb * nchunks;
+    const int chunk = q / gb, band = g * gb + (q - (q / gb) * gb);
+    BandApply<MODE, TS, TB> b;
+    b.init(a, reinterpret_cast<TS *>(apply_lds), band, chunk, threadIdx.x);
+    b.prologue();
+    __syncthreads();
+    for (int kk = b.kk0; kk < b.kk1; ++kk) {
+        b.step(kk);
+        __syncthreads();
+    }
+}
+
 
 // Neighbour sums at ghosted index g of slab point (i, j): returns the
 // off-diagonal sum  sum_m w_m u_m  and the diagonal  sum_m w_m,
@@ -1254,9 +1276,65 @@ LevelArgs level_args(const Level &L) {
 // ============================================================== launchers
 static bool al16(const void *q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; }
 
+// The operator on row bands: false (nothing launched) where the shape does
+// not fit -- nx not a multiple of the vector width, more than 1024 threads,
+// no band height in APPLY_ROWS dividing ny.  The chunk length fills whole
+// rounds of resident blocks.
+constexpr int APPLY_ROWS[] = {16, 12, 8, 6, 4};
+template <int MODE, class TS, class TB>
+static bool apply_band(hipStream_t s, const Plan &p, const TS *phi, const TS *eps, const TB *b, TS *out,
+                       int nplanes) {
+    constexpr int W = ApplyVec<TS>::W;
+    if (p.nx % W || !al16(phi) || !al16(eps) || !al16(out) || (MODE != 0 && !al16(b))) return false;
+    int ty = 0;
+    for (int t : APPLY_ROWS)
+        if (p.ny % t == 0 && p.ny >= t + 2 && (t + 2) * (p.nx / W) <= 1024 &&
+            sizeof(TS) * (size_t)apply_lds_elems(p.nx, t) <= BOTTOM_LDS_BYTES) {
+            ty = t;
+            break;
+        }
+    if (!ty) return false;
+    const int nt = (ty + 2) * (p.nx / W);
+    const size_t bytes = sizeof(TS) * (size_t)apply_lds_elems(p.nx, ty);
+    static int cus[64] = {0};
+    static int per_cu[64][17] = {{0}};
+    int dev = 0;
+    DWP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) fail(DWP_EINVAL, "internal: device index out of range");
+    if (!cus[dev]) {
+        DWP_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_apply_band<MODE, TS, TB>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)BOTTOM_LDS_BYTES));
+        DWP_HIP(hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev));
+    }
+    int &per = per_cu[dev][ty];
+    if (!per) DWP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_apply_band<MODE, TS, TB>, nt, bytes));
+    if (per < 1) return false;
+    const int bands = p.ny / ty;
+    const long slots = (long)cus[dev] * per;
+    int kc = 1;
+    long best = -1;
+    for (int c = 1; c <= 64; ++c) {
+        const long blocks = (long)bands * ((nplanes + c - 1) / c);
+        const long cost = (blocks + slots - 1) / slots * (c + 2);
+        if (best < 0 || cost < best) { best = cost; kc = c; }
+    }
+    const int nb = bands * ((nplanes + kc - 1) / kc), padded = (nb + 7) / 8 * 8;
+    const int gb = bands % 4 == 0 ? 4 : (bands % 2 == 0 ? 2 : 1);
+    ApplyArgs<TS, TB> a{phi, eps, b, out, p.nx, p.ny, p.nz, p.k_w0, nplanes, ty, bands, kc,
+                        1.0 / (p.h[0] * p.h[0]), 1.0 / (p.h[1] * p.h[1]), 1.0 / (p.h[2] * p.h[2])};
+    k_apply_band<MODE, TS, TB><<<padded, nt, bytes, s>>>(a, nb, gb);
+    DWP_LAUNCH_CHECK();
+    return true;
+}
+
 template <class T, int MODE, class TB = double, class TP = double, class TE = double>
 void launch_zmarch(hipStream_t s, const Plan &p, const TP *phi, const TE *eps, const TB *b, T *out,
                    int nplanes) {
+    // row bands where phi, eps and out share one storage type (and b too)
+    if constexpr (std::is_same<TP, TE>::value && std::is_same<T, TP>::value &&
+                  (MODE == 0 || std::is_same<TB, TP>::value)) {
+        if (apply_band<MODE, T, TB>(s, p, phi, eps, b, out, nplanes)) return;
+    }
     const bool tile_ok = p.nx % 2 == 0 && al16(phi) && al16(eps) && (MODE == 0 || al16(b)) && al16(out);
     if (tile_ok) {
         constexpr int ZCH = apply_zch<MODE>();

@@ -22,6 +22,7 @@ inline float gs_value(float off, float f, float diag) { return (off - f) / diag;
 inline double gs_value(double off, double f, double diag) { return (off - f) / diag; }
 }
 #include "band_sweep.h"
+#include "band_apply.h"
 using namespace dwp;
 
 // one block: every thread's prologue, then the steps with a barrier between
@@ -102,6 +103,64 @@ int run(int nx, int ny, int nw, int ty, int kc, int c0, bool reverse, unsigned s
     return bad != 0;
 }
 
+// The row-band operator (band_apply.h) against the 7-point operator written
+// out point by point in float64, on the box (MODE 0, 1) or on wet planes that
+// wrap around the periodic z (MODE 2).
+template <int MODE, class TS>
+int run_apply(int nx, int ny, int nz, int nplanes, int k_w0, int ty, int kc, bool reverse, unsigned seed) {
+    const size_t plane = (size_t)nx * ny;
+    std::vector<TS> phi(nz * plane), eps(nz * plane), b(nz * plane), out((MODE == 2 ? nplanes : nz) * plane, TS(-7));
+    std::mt19937 g(seed);
+    std::uniform_real_distribution<double> U(0, 1);
+    for (auto &x : phi) x = (TS)(U(g) - 0.5);
+    for (auto &x : eps) x = (TS)(1.0 + 77.0 * U(g));
+    for (auto &x : b) x = (TS)(U(g) - 0.5);
+    const double cx = 1.7, cy = 0.9, cz = 0.35;
+    const int bands = ny / ty, nchunks = (nplanes + kc - 1) / kc, nb = bands * nchunks;
+    const int W = ApplyVec<TS>::W, nt = (ty + 2) * (nx / W);
+    const int gb = bands % 4 == 0 ? 4 : (bands % 2 == 0 ? 2 : 1);
+    ApplyArgs<TS, TS> a{phi.data(), eps.data(), b.data(), out.data(), nx, ny, nz, k_w0, nplanes, ty, bands, kc,
+                        cx, cy, cz};
+    std::vector<int> seen(nb, 0);
+    for (int t = 0; t < nb; ++t) {
+        const int gg = t / (gb * nchunks), q = t - gg * gb * nchunks;
+        const int chunk = q / gb, band = gg * gb + (q - (q / gb) * gb);
+        BAND_CHECK(band, bands);
+        BAND_CHECK(chunk, nchunks);
+        ++seen[chunk * bands + band];
+        std::vector<TS> lds(apply_lds_elems(nx, ty), std::numeric_limits<TS>::quiet_NaN());
+        std::vector<BandApply<MODE, TS, TS>> th(nt);
+        for (int i = 0; i < nt; ++i) { th[i].init(a, lds.data(), band, chunk, i); th[i].prologue(); }
+        for (int kk = th[0].kk0; kk < th[0].kk1; ++kk)
+            for (int i = 0; i < nt; ++i) th[reverse ? nt - 1 - i : i].step(kk);
+    }
+    for (int v : seen)
+        if (v != 1) { printf("tile mapping is not a bijection\n"); return 1; }
+    auto at = [&](int i, int j, int k) -> size_t {
+        return (size_t)((k % nz + nz) % nz) * plane + (size_t)((j + ny) % ny) * nx + (i + nx) % nx;
+    };
+    size_t bad = 0;
+    double md = 0;
+    for (int kk = 0; kk < (MODE == 2 ? nplanes : nz); ++kk)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const int k = MODE == 2 ? k_w0 + kk : kk;
+                const double p0 = phi[at(i, j, k)], e0 = eps[at(i, j, k)];
+                auto t = [&](int di, int dj, int dk) {
+                    return ((double)e0 + (double)eps[at(i + di, j + dj, k + dk)]) * ((double)phi[at(i + di, j + dj, k + dk)] - p0);
+                };
+                double v = cx * (t(1, 0, 0) + t(-1, 0, 0)) + cy * (t(0, 1, 0) + t(0, -1, 0)) + cz * (t(0, 0, 1) + t(0, 0, -1));
+                v *= 0.5;
+                const TS want = MODE == 0 ? (TS)v : (TS)((double)b[at(i, j, k)] - v);
+                const TS got = out[(size_t)kk * plane + (size_t)j * nx + i];
+                if (got != want) ++bad;
+                md = std::max(md, std::fabs((double)got - (double)want));
+            }
+    printf("apply MODE %d %s %dx%dx%d planes %d from %d ty=%d kc=%d rev=%d: blocks %d threads %d maxdiff %.3g mismatches %zu\n",
+           MODE, sizeof(TS) == 4 ? "f32" : "f64", nx, ny, nz, nplanes, k_w0, ty, kc, (int)reverse, nb, nt, md, bad);
+    return bad != 0;
+}
+
 int main() {
     int fails = 0;
     for (int rev = 0; rev < 2; ++rev)
@@ -120,6 +179,14 @@ int main() {
             fails += run<double, 2, true>(12, 16, 17, 4, 5, c0, rev, 12);
             fails += run<float, 2, false>(10, 36, 9, 6, 1, c0, rev, 13);
         }
+    for (int rev = 0; rev < 2; ++rev) {
+        fails += run_apply<0, float>(24, 32, 20, 20, 0, 8, 6, rev, 21);
+        fails += run_apply<0, double>(16, 12, 9, 9, 0, 4, 4, rev, 22);
+        fails += run_apply<1, double>(12, 12, 10, 10, 0, 6, 3, rev, 23);
+        fails += run_apply<2, float>(32, 16, 24, 11, 17, 16, 4, rev, 24);  // wet planes 17 .. 27 wrap past 24
+        fails += run_apply<2, double>(8, 24, 12, 12, 0, 12, 5, rev, 25);
+        fails += run_apply<2, float>(192, 12, 10, 7, 2, 4, 64, rev, 26);
+    }
     printf("%s (%d failing cases)\n", fails ? "FAIL" : "OK", fails);
     return fails != 0;
 }
