@@ -266,6 +266,8 @@ void launch_zero(hipStream_t s, T *x, size_t n);
 // One red-black sweep (first_color, then the other) from uin to uout in a
 // single pass; uin, uout: ghosted arrays of level L (ghost planes zero).
 template <class T>
+bool sweep_band_fits(const Level &L);  // the row-band fused sweep takes this level
+template <class T>
 void launch_sweep_fused(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color, bool zero_in,
                         bool tiles_only, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // The rest of a V-cycle from level l0 down, in one single-workgroup kernel.
@@ -275,6 +277,7 @@ void launch_vcycle_bottom(hipStream_t s, const std::vector<Level *> &levels, siz
 constexpr size_t BOTTOM_MAX_POINTS = 8192;     // levels this small (and below) go to the bottom kernel
 constexpr size_t BOTTOM_LDS_BYTES = 160 * 1024;  // the bottom set runs out of LDS when it fits this
 constexpr size_t FUSED_MIN_POINTS = 1u << 20;  // levels this large use the fused sweep
+constexpr size_t BAND_MIN_POINTS = 1u << 14;   // the row-band fused sweep from this size where it fits
 
 // kern_sixth.hip: the sixth-order operator (order = 6)
 void launch_d1eps(hipStream_t s, const Plan &p, const double *eps, double *G);    // G: 3N

@@ -7,6 +7,7 @@
 //   (A u)_n = sum over the 6 neighbours m of n of
 //             1/2 (eps_n + eps_m) (u_m - u_n) / h_d^2.
 #include <algorithm>
+#include <mutex>
 
 #include "dwp_internal.h"
 
@@ -1276,6 +1277,46 @@ LevelArgs level_args(const Level &L) {
 // ============================================================== launchers
 static bool al16(const void *q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; }
 
+// Resident blocks per CU of a kernel at a block shape (threads, dynamic LDS
+// bytes), cached per device: the occupancy query is a host call per launch
+// otherwise.  The raised dynamic-LDS limit is set the first time a kernel is
+// seen on a device.
+struct OccKey {
+    const void *fn;
+    int dev, nt;
+    size_t bytes;
+    int per;
+};
+static int occupancy(const void *fn, int nt, size_t bytes) {
+    static OccKey cache[64];
+    static int used = 0;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lock(mu);
+    int dev = 0;
+    DWP_HIP(hipGetDevice(&dev));
+    bool seen = false;
+    for (int i = 0; i < used; ++i) {
+        const OccKey &k = cache[i];
+        if (k.fn == fn && k.dev == dev) {
+            seen = true;
+            if (k.nt == nt && k.bytes == bytes) return k.per;
+        }
+    }
+    if (!seen) DWP_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)BOTTOM_LDS_BYTES));
+    int per = 0;
+    DWP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, nt, bytes));
+    if (used < 64) cache[used++] = OccKey{fn, dev, nt, bytes, per};
+    return per;
+}
+static int cu_count() {
+    static int cus[64] = {0};
+    int dev = 0;
+    DWP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) fail(DWP_EINVAL, "internal: device index out of range");
+    if (!cus[dev]) DWP_HIP(hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev));
+    return cus[dev];
+}
+
 // The operator on row bands: false (nothing launched) where the shape does
 // not fit -- nx not a multiple of the vector width, more than 1024 threads,
 // no band height in APPLY_ROWS dividing ny.  The chunk length fills whole
@@ -1296,21 +1337,10 @@ static bool apply_band(hipStream_t s, const Plan &p, const TS *phi, const TS *ep
     if (!ty) return false;
     const int nt = (ty + 2) * (p.nx / W);
     const size_t bytes = sizeof(TS) * (size_t)apply_lds_elems(p.nx, ty);
-    static int cus[64] = {0};
-    static int per_cu[64][17] = {{0}};
-    int dev = 0;
-    DWP_HIP(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64) fail(DWP_EINVAL, "internal: device index out of range");
-    if (!cus[dev]) {
-        DWP_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_apply_band<MODE, TS, TB>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)BOTTOM_LDS_BYTES));
-        DWP_HIP(hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev));
-    }
-    int &per = per_cu[dev][ty];
-    if (!per) DWP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_apply_band<MODE, TS, TB>, nt, bytes));
+    const int per = occupancy(reinterpret_cast<const void *>(&k_apply_band<MODE, TS, TB>), nt, bytes);
     if (per < 1) return false;
     const int bands = p.ny / ty;
-    const long slots = (long)cus[dev] * per;
+    const long slots = (long)cu_count() * per;
     int kc = 1;
     long best = -1;
     for (int c = 1; c <= 64; ++c) {
@@ -1606,38 +1636,30 @@ static void sweep_fused_z(hipStream_t s, const Level &L, const T *uin, T *uout, 
 // height that fits; the chunk kc is chosen by the same round-filling cost
 // model as the tiled kernel's.
 constexpr int BAND_ROWS[] = {12, 8, 16, 6, 4};
+template <class T, int W>
+static bool band_rows_fit(const Level &L, int t) {
+    const long nt = (long)(t + 4) * (L.nx / W);
+    const size_t bytes = sizeof(T) * (size_t)band_lds_elems(L.nx, t);
+    return L.nx % W == 0 && L.nx >= 2 * W && t >= 2 && t % 2 == 0 && L.ny % t == 0 && L.ny >= t + 4 && nt <= 1024 &&
+           bytes <= BOTTOM_LDS_BYTES;
+}
+template <class T, int W>
+static int band_rows(const Level &L) {
+    for (int t : BAND_ROWS)
+        if (band_rows_fit<T, W>(L, t)) return t;
+    return 0;
+}
 template <class T, int W, bool ZIN>
 static bool sweep_band_w(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color, int ty,
                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
-    if (L.nx % W || L.nx < 2 * W) return false;
-    auto fits = [&](int t) {
-        const long nt = (long)(t + 4) * (L.nx / W);
-        const size_t bytes = sizeof(T) * (size_t)band_lds_elems(L.nx, t);
-        return t >= 2 && t % 2 == 0 && L.ny % t == 0 && L.ny >= t + 4 && nt <= 1024 && bytes <= BOTTOM_LDS_BYTES;
-    };
-    if (ty == 0)
-        for (int t : BAND_ROWS)
-            if (fits(t)) { ty = t; break; }
-    if (ty == 0 || !fits(ty)) return false;
+    if (ty == 0) ty = band_rows<T, W>(L);
+    if (ty == 0 || !band_rows_fit<T, W>(L, ty)) return false;
     const int nt = (ty + 4) * (L.nx / W);
     const size_t bytes = sizeof(T) * (size_t)band_lds_elems(L.nx, ty);
-    // per device: the dynamic-LDS limit raised once, the CU count, and the
-    // resident blocks per CU for each band height (they depend on ty only)
-    static int cus[64] = {0};
-    static int per_cu[64][17] = {{0}};
-    int dev = 0;
-    DWP_HIP(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64 || ty > 16) fail(DWP_EINVAL, "internal: device index or band height out of range");
-    if (!cus[dev]) {
-        DWP_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sweep_band<T, W, ZIN>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)BOTTOM_LDS_BYTES));
-        DWP_HIP(hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev));
-    }
-    int &per = per_cu[dev][ty];
-    if (!per) DWP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_band<T, W, ZIN>, nt, bytes));
+    const int per = occupancy(reinterpret_cast<const void *>(&k_sweep_band<T, W, ZIN>), nt, bytes);
     if (per < 1) return false;
     const int bands = L.ny / ty;
-    const long slots = (long)cus[dev] * per;
+    const long slots = (long)cu_count() * per;
     int kc = 1;
     long best = -1;
     for (int c = 1; c <= 64; ++c) {
@@ -1658,6 +1680,14 @@ static bool sweep_band_w(hipStream_t s, const Level &L, const T *uin, T *uout, i
 
 // 16-byte tile loads when nx allows (float: nx % 4 == 0), else 8-byte ones;
 // the level arrays come from hipMalloc and planes are whole vectors.
+template <>
+bool sweep_band_fits<float>(const Level &L) {
+    return L.nx % 4 == 0 ? band_rows<float, 4>(L) != 0 : band_rows<float, 2>(L) != 0;
+}
+template <>
+bool sweep_band_fits<double>(const Level &L) {
+    return band_rows<double, 2>(L) != 0;
+}
 // The row-band kernel where its shape fits (unless tiles_only), else the
 // tiled one.
 template <class T, int W>

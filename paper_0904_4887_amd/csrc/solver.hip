@@ -342,7 +342,13 @@ void vcycle(dwp_ctx *c, size_t l, bool u_unset) {
     // Jacobi); the adjoint solve keeps the symmetric 7-point smoother, which
     // approximates A6^T as well as it approximates A6
     const bool six = l == 0 && c->opts.order == 6 && c->opts.smooth6 == 1 && !c->transposed;
-    const bool fused = !six && c->opts.smoother != 0 && L.n_interior() >= FUSED_MIN_POINTS;
+    // the fused sweep on the large levels; the row-band one also on smaller
+    // levels down to BAND_MIN_POINTS, where one launch per sweep instead of
+    // two matters more than its z halo
+    const size_t npts = L.n_interior();
+    const bool fused = !six && c->opts.smoother != 0 &&
+                       (npts >= FUSED_MIN_POINTS ||
+                        (c->opts.smoother == 1 && npts >= BAND_MIN_POINTS && sweep_band_fits<T>(L)));
     const bool coarsest = l + 1 == p.levels.size();
     // the first sweep starts from a zero correction on coarse levels and in
     // the first cycle on the fine level, except that without pre-sweeps it
