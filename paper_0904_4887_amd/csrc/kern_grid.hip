@@ -430,6 +430,7 @@ __device__ __forceinline__ double gs_value(double off, double f, double diag) {
 }  // namespace dwp
 #include "band_sweep.h"
 #include "band_apply.h"
+#include "band_restrict.h"
 namespace dwp {
 namespace {
 
@@ -452,6 +453,27 @@ __global__ void __launch_bounds__(1024) k_apply_band(ApplyArgs<TS, TB> a, int nb
         __syncthreads();
     }
 }
+
+// Row-band variant of k_resid_restrict (per-thread code in band_restrict.h):
+// (2 tyc + 3) * nx / W threads, the tile -> (band, chunk) order of k_sweep_band.
+template <class T, int W, bool ZC>
+__global__ void __launch_bounds__(1024) k_resid_restrict_band(RestrictArgs<T> a, int nb_real, int gb) {
+    extern __shared__ __align__(16) unsigned char restrict_lds[];
+    const int t = xcd_tile(nb_real);
+    if (t >= nb_real) return;
+    const int nchunks = (a.nwc + a.kcc - 1) / a.kcc;
+    const int g = t / (gb * nchunks), q = t - g * gb * nchunks;
+    const int chunk = q / gb, band = g * gb + (q - (q / gb) * gb);
+    BandRestrict<T, W, ZC> b;
+    b.init(a, reinterpret_cast<T *>(restrict_lds), band, chunk, threadIdx.x);
+    b.prologue();
+    __syncthreads();
+    for (int k = b.k0; k <= b.k1; ++k) {
+        b.step(k);
+        __syncthreads();
+    }
+}
+
 
 
 // Neighbour sums at ghosted index g of slab point (i, j): returns the
@@ -1558,13 +1580,54 @@ static void resid_restrict_w(hipStream_t s, const Level &F, const Level &C) {
 // Vector width of the staged rows: 16-byte loads need nx to be a multiple
 // of the vector (always true for a level that has a coarser one: x is halved
 // only when nx is a multiple of 4).
+// Row bands of tyc coarse rows (RESTRICT_ROWS, the first that divides nyc
+// within 1024 threads and the LDS); false where none fits.
+constexpr int RESTRICT_ROWS[] = {6, 8, 4, 12, 2};
+template <class T, int W, bool ZC>
+static bool resid_restrict_band(hipStream_t s, const Level &F, const Level &C) {
+    int tyc = 0;
+    for (int t : RESTRICT_ROWS)
+        if (C.ny % t == 0 && (2 * t + 3) * (F.nx / W) <= 1024 && F.ny >= 2 * t + 3 &&
+            sizeof(T) * (size_t)restrict_lds_elems(F.nx, t) <= BOTTOM_LDS_BYTES) {
+            tyc = t;
+            break;
+        }
+    if (!tyc) return false;
+    const int nt = (2 * tyc + 3) * (F.nx / W);
+    const size_t bytes = sizeof(T) * (size_t)restrict_lds_elems(F.nx, tyc);
+    const int per = occupancy(reinterpret_cast<const void *>(&k_resid_restrict_band<T, W, ZC>), nt, bytes);
+    if (per < 1) return false;
+    const int bands = C.ny / tyc;
+    const long slots = (long)cu_count() * per;
+    int kcc = 1;
+    long best = -1;
+    for (int c = 1; c <= 64; ++c) {
+        const long blocks = (long)bands * ((C.nw + c - 1) / c);
+        const long cost = (blocks + slots - 1) / slots * ((ZC ? 2 * c + 1 : c) + 2);
+        if (best < 0 || cost < best) { best = cost; kcc = c; }
+    }
+    const int nb = bands * ((C.nw + kcc - 1) / kcc), padded = (nb + 7) / 8 * 8;
+    const int gb = bands % 4 == 0 ? 4 : (bands % 2 == 0 ? 2 : 1);
+    const LevelArgs la = level_args(F);
+    const bool f32 = sizeof(T) == 4;
+    RestrictArgs<T> a{F.u.as<T>(), F.eps.as<T>(), F.f.as<T>(), C.f.as<T>(), C.u.as<T>(), F.nx, F.ny, F.nw,
+                      C.nx, C.ny, C.nw, tyc, bands, kcc,
+                      (T)(f32 ? la.cxf : la.cx), (T)(f32 ? la.cyf : la.cy), (T)(f32 ? la.czf : la.cz)};
+    k_resid_restrict_band<T, W, ZC><<<padded, nt, bytes, s>>>(a, nb, gb);
+    DWP_LAUNCH_CHECK();
+    return true;
+}
+
 template <class T>
 void launch_resid_restrict(hipStream_t s, const Level &F, const Level &C) {
     if (F.nx != 2 * C.nx || F.ny != 2 * C.ny || F.nx % 4 != 0 || (C.zc ? F.nw != 2 * C.nw + 1 : F.nw != C.nw))
         fail(DWP_EINVAL, "internal: residual-restriction needs x and y halved (z halved or kept)");
     constexpr int W = sizeof(T) == 4 ? 4 : 2;
-    if (C.zc) resid_restrict_w<T, W, true>(s, F, C);
-    else resid_restrict_w<T, W, false>(s, F, C);
+    if (C.zc) {
+        if (!resid_restrict_band<T, W, true>(s, F, C)) resid_restrict_w<T, W, true>(s, F, C);
+    } else if (!resid_restrict_band<T, W, false>(s, F, C)) {
+        resid_restrict_w<T, W, false>(s, F, C);
+    }
 }
 
 template <class T>

@@ -23,6 +23,7 @@ inline double gs_value(double off, double f, double diag) { return (off - f) / d
 }
 #include "band_sweep.h"
 #include "band_apply.h"
+#include "band_restrict.h"
 using namespace dwp;
 
 // one block: every thread's prologue, then the steps with a barrier between
@@ -161,6 +162,87 @@ int run_apply(int nx, int ny, int nz, int nplanes, int k_w0, int ty, int kc, boo
     return bad != 0;
 }
 
+// The row-band residual + full-weighting restriction (band_restrict.h)
+// against the residual and the weighting written out point by point, with z
+// coarsened or kept.
+template <class T, int W, bool ZC>
+int run_restrict(int nx, int ny, int nw, int tyc, int kcc, bool reverse, unsigned seed) {
+    const size_t plane = (size_t)nx * ny;
+    const int nxc = nx / 2, nyc = ny / 2, nwc = ZC ? (nw - 1) / 2 : nw;
+    const size_t planec = (size_t)nxc * nyc;
+    std::vector<T> u((nw + 2) * plane, T(0)), e((nw + 2) * plane), f(nw * plane);
+    std::vector<T> fc(nwc * planec, T(7)), uc((nwc + 2) * planec, T(7));
+    std::mt19937 g(seed);
+    std::uniform_real_distribution<double> U(0, 1);
+    for (size_t i = plane; i < (nw + 1) * plane; ++i) u[i] = (T)(U(g) - 0.5);
+    for (auto &x : e) x = (T)(1.0 + 77.0 * U(g));
+    for (auto &x : f) x = (T)(10.0 * (U(g) - 0.5));
+    const T cx = (T)1.3, cy = (T)0.7, cz = (T)0.4;
+    const int bands = nyc / tyc, nchunks = (nwc + kcc - 1) / kcc, nb = bands * nchunks, nt = (2 * tyc + 3) * (nx / W);
+    const int gb = bands % 4 == 0 ? 4 : (bands % 2 == 0 ? 2 : 1);
+    RestrictArgs<T> a{u.data(), e.data(), f.data(), fc.data(), uc.data(), nx, ny, nw, nxc, nyc, nwc, tyc, bands, kcc,
+                      cx, cy, cz};
+    std::vector<int> seen(nb, 0);
+    for (int t = 0; t < nb; ++t) {
+        const int gg = t / (gb * nchunks), q = t - gg * gb * nchunks;
+        const int chunk = q / gb, band = gg * gb + (q - (q / gb) * gb);
+        BAND_CHECK(band, bands);
+        BAND_CHECK(chunk, nchunks);
+        ++seen[chunk * bands + band];
+        std::vector<T> lds(restrict_lds_elems(nx, tyc), std::numeric_limits<T>::quiet_NaN());
+        std::vector<BandRestrict<T, W, ZC>> th(nt);
+        for (int i = 0; i < nt; ++i) { th[i].init(a, lds.data(), band, chunk, i); th[i].prologue(); }
+        for (int k = th[0].k0; k <= th[0].k1; ++k)
+            for (int i = 0; i < nt; ++i) th[reverse ? nt - 1 - i : i].step(k);
+    }
+    for (int v : seen)
+        if (v != 1) { printf("tile mapping is not a bijection\n"); return 1; }
+    auto at = [&](int i, int j, int k) -> size_t { return (size_t)(k + 1) * plane + (size_t)((j + ny) % ny) * nx + (i + nx) % nx; };
+    std::vector<T> res(nw * plane);
+    for (int k = 0; k < nw; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const T e0 = e[at(i, j, k)], u0 = u[at(i, j, k)];
+                const T wxp = cx * (e0 + e[at(i + 1, j, k)]), wxm = cx * (e0 + e[at(i - 1, j, k)]);
+                const T wyp = cy * (e0 + e[at(i, j + 1, k)]), wym = cy * (e0 + e[at(i, j - 1, k)]);
+                const T wzp = cz * (e0 + e[at(i, j, k + 1)]), wzm = cz * (e0 + e[at(i, j, k - 1)]);
+                const T off = T(0.5) * (wxp * u[at(i + 1, j, k)] + wxm * u[at(i - 1, j, k)] + wyp * u[at(i, j + 1, k)] +
+                                        wym * u[at(i, j - 1, k)] + wzp * u[at(i, j, k + 1)] + wzm * u[at(i, j, k - 1)]);
+                const T dg = T(0.5) * (wxp + wxm + wyp + wym + wzp + wzm);
+                res[(size_t)k * plane + (size_t)j * nx + i] = f[(size_t)k * plane + (size_t)j * nx + i] - (off - dg * u0);
+            }
+    auto rat = [&](int i, int j, int k) { return res[(size_t)k * plane + (size_t)((j + ny) % ny) * nx + (i + nx) % nx]; };
+    auto Rin = [&](int ic, int jc, int k) {
+        T sx[3];
+        for (int d = 0; d < 3; ++d) {
+            const int j = 2 * jc - 1 + d;
+            sx[d] = T(0.25) * rat(2 * ic - 1, j, k) + T(0.5) * rat(2 * ic, j, k) + T(0.25) * rat(2 * ic + 1, j, k);
+        }
+        return T(0.25) * sx[0] + T(0.5) * sx[1] + T(0.25) * sx[2];
+    };
+    size_t bad = 0;
+    double md = 0;
+    for (int kc = 0; kc < nwc; ++kc)
+        for (int jc = 0; jc < nyc; ++jc)
+            for (int ic = 0; ic < nxc; ++ic) {
+                T want;
+                if (!ZC) want = Rin(ic, jc, kc);
+                else {
+                    T acc = T(0.25) * Rin(ic, jc, 2 * kc);
+                    acc += T(0.5) * Rin(ic, jc, 2 * kc + 1);
+                    want = acc + T(0.25) * Rin(ic, jc, 2 * kc + 2);
+                }
+                const T got = fc[(size_t)kc * planec + (size_t)jc * nxc + ic];
+                if (got != want) ++bad;
+                md = std::max(md, std::fabs((double)got - (double)want));
+            }
+    for (T v : uc)
+        if (v != T(0)) ++bad;
+    printf("restrict %s W=%d ZC=%d %dx%dx%d tyc=%d kcc=%d rev=%d: blocks %d threads %d maxdiff %.3g mismatches %zu\n",
+           sizeof(T) == 4 ? "f32" : "f64", W, (int)ZC, nx, ny, nw, tyc, kcc, (int)reverse, nb, nt, md, bad);
+    return bad != 0;
+}
+
 int main() {
     int fails = 0;
     for (int rev = 0; rev < 2; ++rev)
@@ -186,6 +268,14 @@ int main() {
         fails += run_apply<2, float>(32, 16, 24, 11, 17, 16, 4, rev, 24);  // wet planes 17 .. 27 wrap past 24
         fails += run_apply<2, double>(8, 24, 12, 12, 0, 12, 5, rev, 25);
         fails += run_apply<2, float>(192, 12, 10, 7, 2, 4, 64, rev, 26);
+    }
+    for (int rev = 0; rev < 2; ++rev) {
+        fails += run_restrict<float, 4, true>(16, 24, 15, 6, 2, rev, 31);
+        fails += run_restrict<float, 4, false>(24, 16, 9, 4, 3, rev, 32);
+        fails += run_restrict<double, 2, true>(12, 16, 11, 2, 1, rev, 33);
+        fails += run_restrict<double, 2, false>(8, 24, 7, 6, 4, rev, 34);
+        fails += run_restrict<float, 4, true>(48, 32, 21, 8, 64, rev, 35);
+        fails += run_restrict<float, 2, true>(12, 8, 5, 2, 1, rev, 36);
     }
     printf("%s (%d failing cases)\n", fails ? "FAIL" : "OK", fails);
     return fails != 0;
