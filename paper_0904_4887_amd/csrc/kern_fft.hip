@@ -27,7 +27,12 @@ namespace {
 
 constexpr int FFT_THREADS = 512;
 constexpr int FFT_MAXE = 4096;   // complex values per block (lines x length) at most
-constexpr int FFT_BUDGET_X = 2048, FFT_BUDGET_Y = 4096, FFT_BUDGET_Z = 4096;
+// Lines per block: B * n within the budget (see tile_log2), never above the
+// per-block maximum, with the LDS of a block within 64 KB.  The float32 x
+// passes take 16 lines of 192 (measured: 0.5 ms per step less than 8).  A
+// float32 z pass of 16 lines of 384 (a per-block maximum of 8192 for that
+// kernel alone: 124 VGPRs, half the waves) measured 40 % slower than 8.
+constexpr int FFT_BUDGET_X = 2048, FFT_BUDGET_X32 = 4096, FFT_BUDGET_Y = 4096, FFT_BUDGET_Z = 4096;
 constexpr int MAX_STAGES = 12;
 
 // Division by a small positive d through one multiply-high: with
@@ -133,10 +138,10 @@ template <class C> struct DFT<8, C> {
 // radices of the earlier stages.  Butterfly i of a line reads
 // x_q = buf[i + q n/R], twiddles x_q by exp(-+2 pi i q (i mod p) / (p R)),
 // and writes output r to (i - i mod p) R + i mod p + r p.
-template <int R, class C>
+template <int R, class C, int MAXE>
 __device__ void stage(C *buf, int n, int p, unsigned pm, int tstride, int lb, int es, int ls,
                       const C *__restrict__ tw, bool inv) {
-    constexpr int K = (FFT_MAXE / R + FFT_THREADS - 1) / FFT_THREADS;
+    constexpr int K = (MAXE / R + FFT_THREADS - 1) / FFT_THREADS;
     const int T = n / R;
     const int items = T << lb;
     const int bmask = (1 << lb) - 1;
@@ -175,14 +180,14 @@ __device__ void stage(C *buf, int n, int p, unsigned pm, int tstride, int lb, in
     __syncthreads();
 }
 
-template <class C>
+template <class C, int MAXE = FFT_MAXE>
 __device__ void fft_lines(C *buf, const Radices &rd, int lb, int es, int ls, const C *__restrict__ tw, bool inv) {
     for (int s = 0; s < rd.nst; ++s) {
         const int R = rd.r[s];
-        if (R == 8) stage<8, C>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
-        else if (R == 4) stage<4, C>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
-        else if (R == 3) stage<3, C>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
-        else stage<2, C>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
+        if (R == 8) stage<8, C, MAXE>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
+        else if (R == 4) stage<4, C, MAXE>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
+        else if (R == 3) stage<3, C, MAXE>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
+        else stage<2, C, MAXE>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
     }
 }
 
@@ -321,7 +326,7 @@ __device__ __forceinline__ double neg_recip(double d) {
 }
 __device__ __forceinline__ float neg_recip(float d) { return -__builtin_amdgcn_rcpf(d); }
 
-template <class S>
+template <class S, int MAXE = FFT_MAXE>
 __global__ void __launch_bounds__(FFT_THREADS)
 k_fft_z_green(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ tw, int lb, int nkx, int ldc, int ny,
               const S *__restrict__ lamx, const S *__restrict__ lamy, const S *__restrict__ lamz, S inv_n) {
@@ -340,7 +345,7 @@ k_fft_z_green(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ t
         lds[e] = (l < bw) ? c[base + (size_t)z * zstride + l] : mk<C>(0, 0);
     }
     __syncthreads();
-    fft_lines(lds, rd, lb, B, 1, tw, false);
+    fft_lines<C, MAXE>(lds, rd, lb, B, 1, tw, false);
     const S ly = lamy[y];
     for (int e = threadIdx.x; e < B * nz; e += FFT_THREADS) {
         const int z = e >> lb, l = e & bmask;
@@ -351,7 +356,7 @@ k_fft_z_green(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ t
         lds[e] = mk<C>(v.x * g, v.y * g);
     }
     __syncthreads();
-    fft_lines(lds, rd, lb, B, 1, tw, true);
+    fft_lines<C, MAXE>(lds, rd, lb, B, 1, tw, true);
     for (int e = threadIdx.x; e < B * nz; e += FFT_THREADS) {
         const int z = e >> lb, l = e & bmask;
         if (l < bw) c[base + (size_t)z * zstride + l] = lds[e];
@@ -445,7 +450,7 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
     auto pe = [&](int ev, int g, double b) { if (prof) prof->end(st, ev, g, b); };
     int ev;
     const int nrows = p.ny * p.nz;
-    const int lbx = tile_log2(p.nx, FFT_BUDGET_X), Bx = 1 << lbx;
+    const int lbx = tile_log2(p.nx, sizeof(S) == 4 ? FFT_BUDGET_X32 : FFT_BUDGET_X), Bx = 1 << lbx;
     const int gx = (nrows + 2 * Bx - 1) / (2 * Bx);
     const size_t ldsx = sizeof(C) * Bx * (p.nx + 1);
     const Div dn = make_div(p.nx), dk = make_div(p.nkx);
