@@ -130,6 +130,18 @@ typedef struct {
                            /* operator's arithmetic and the iterate stay       */
                            /* float64; every restart recomputes the true       */
                            /* residual in float64).  0 = float64 bases         */
+    int krylov_fp16;       /* with krylov_fp32 = 1 and the second-order        */
+                           /* operator: 1 = the Arnoldi basis V of a restart   */
+                           /* cycle is stored in float16 (Z stays float32, the */
+                           /* current vector is kept in float32 too for the    */
+                           /* preconditioner; the arithmetic is as above, the  */
+                           /* true residual is still recomputed in float64 at  */
+                           /* every restart, so the tolerance still holds for  */
+                           /* the float64 residual), except the first cycle    */
+                           /* of a solve and any cycle after one that reduced  */
+                           /* the residual more than 100-fold: there a float16 */
+                           /* basis would limit the cycle, which runs on the   */
+                           /* float32 basis.  0 = as krylov_fp32 says          */
 } dwp_opts;
 
 /* Per-solve report. */

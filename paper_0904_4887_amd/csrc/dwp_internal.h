@@ -350,6 +350,17 @@ void launch_multidot32_sum(hipStream_t s, const float *V, size_t ldv, int nv, co
 // x -= mean(x) for a float32 vector (the sum lands at *sum_out)
 void launch_sub_mean32(hipStream_t s, float *x, size_t n, double *partial, double *sum_out);
 void launch_scale_to32(hipStream_t s, float *x32, const double *r, const double *den_sq, size_t n);
+// float16 Krylov basis (mixed precision, second order): the basis V in
+// float16, the current vector also in float32 (w, the preconditioner's
+// input); projections and update in float64 arithmetic (n and ldv multiples
+// of 8, 16-byte aligned)
+bool krylov16_supported(const void *V, size_t ldv, size_t n);
+void launch_multidot16(hipStream_t s, const _Float16 *V, size_t ldv, int nv, const float *w, size_t n,
+                       double *partial, double *out, double *norm_out);
+// w <- (w - sum_q h_q V_q) / beta in float32, and into vn (float16)
+void launch_orth_update16(hipStream_t s, float *w, _Float16 *vn, const _Float16 *V, size_t ldv, int nv, double *hc,
+                          size_t n, double *partial);
+void launch_scale_to16(hipStream_t s, float *x32, _Float16 *xh, const double *r, const double *den_sq, size_t n);
 // x += sum_q c[q] Z_q with float32 Z_q (nv <= 16), float64 x and sums
 void launch_axpy_multi32(hipStream_t s, double *x, const float *Z, size_t ldz, int nv, const double *c, size_t n);
 // energy sums: out[0] = sum rho phi (compensated), out[1] = sum_faces eps_f (D_f phi)^2

@@ -283,6 +283,132 @@ k_orth_update4f(float *__restrict__ w, const float *__restrict__ V, size_t ldv, 
     if (threadIdx.x == 0) partial[blockIdx.x] = res[0];
 }
 
+// The projection and update for a float16 Krylov basis: V in float16 (eight
+// per 16-byte load), the new vector w in float32 (the one the preconditioner
+// reads), every product and sum in float64.  The update writes the normalised
+// vector twice: into the basis (float16) and back into w (float32).
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef float f8 __attribute__((ext_vector_type(8)));
+
+template <int NV>
+__global__ void __launch_bounds__(RED_THREADS)
+k_multidot8h(const _Float16 *__restrict__ V, size_t ldv, int v0, const float *__restrict__ w, size_t n8,
+             double *__restrict__ partial, int stride, int with_norm) {
+    constexpr int NA = NV + 1;  // dots, ||w||^2
+    __shared__ double sh[NA][RED_THREADS / 64];
+    __shared__ double res[NA];
+    const f8 *w8 = reinterpret_cast<const f8 *>(w);
+    double acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = 0.0;
+    for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n8; t += (size_t)gridDim.x * RED_THREADS) {
+        const f8 wt = w8[t];
+        h8 vq[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) vq[q] = reinterpret_cast<const h8 *>(V + (size_t)(v0 + q) * ldv)[t];
+        double wd[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) wd[e] = wt[e];
+        acc[NV] += ((wd[0] * wd[0] + wd[1] * wd[1]) + (wd[2] * wd[2] + wd[3] * wd[3])) +
+                   ((wd[4] * wd[4] + wd[5] * wd[5]) + (wd[6] * wd[6] + wd[7] * wd[7]));
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double d = 0.0;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) d += (double)(float)vq[q][e] * wd[e];
+            acc[q] += d;
+        }
+    }
+    block_sums<NA>(acc, sh, res);
+    if ((int)threadIdx.x < NV) partial[(size_t)blockIdx.x * stride + v0 + threadIdx.x] = res[threadIdx.x];
+    if (with_norm && threadIdx.x == NV) partial[(size_t)blockIdx.x * stride + NORM_SLOT] = res[NV];
+}
+
+template <int NV>
+__global__ void __launch_bounds__(RED_THREADS)
+k_orth_update8h(float *__restrict__ w, _Float16 *__restrict__ vn, const _Float16 *__restrict__ V, size_t ldv,
+                const double *__restrict__ hc, size_t n8, double *__restrict__ partial, double *__restrict__ beta_out) {
+    __shared__ double sh[1][RED_THREADS / 64];
+    __shared__ double cs[NV + 1];
+    __shared__ double res[1];
+    if (threadIdx.x == 0) {
+        double h2 = 0.0;
+        for (int q = 0; q < NV; ++q) h2 += hc[q] * hc[q];
+        const double w2n = hc[NORM_SLOT], b2 = w2n - h2;
+        const double beta = (b2 > 1e-20 * w2n) ? sqrt(b2) : 1.0;
+        cs[NV] = 1.0 / beta;
+        if (blockIdx.x == 0) *beta_out = beta;
+    }
+    if ((int)threadIdx.x < NV) cs[threadIdx.x] = -hc[threadIdx.x];
+    __syncthreads();
+    const double sc = cs[NV];
+    f8 *w8 = reinterpret_cast<f8 *>(w);
+    h8 *vn8 = reinterpret_cast<h8 *>(vn);
+    double nrm[1] = {0.0};
+    for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n8; t += (size_t)gridDim.x * RED_THREADS) {
+        const f8 wv = w8[t];
+        double a[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a[e] = wv[e];
+        h8 vq[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) vq[q] = reinterpret_cast<const h8 *>(V + (size_t)q * ldv)[t];
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) a[e] += cs[q] * (double)(float)vq[q][e];
+        f8 o;
+        h8 oh;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            o[e] = (float)(a[e] * sc);
+            oh[e] = (_Float16)o[e];
+            nrm[0] += (double)o[e] * (double)o[e];
+        }
+        w8[t] = o;
+        vn8[t] = oh;
+    }
+    block_sums<1>(nrm, sh, res);
+    if (threadIdx.x == 0) partial[blockIdx.x] = res[0];
+}
+
+// As k_rescale_if_f for the float32 copy x, rewriting the float16 basis
+// vector xh from it when it is rescaled.
+__global__ void __launch_bounds__(RED_THREADS)
+k_rescale_if_fh(float *__restrict__ x, _Float16 *__restrict__ xh, const double *__restrict__ partial, int nparts,
+                double *__restrict__ nu2, size_t n) {
+    __shared__ double sh[RED_THREADS / 64];
+    __shared__ double tot;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += RED_THREADS) v += partial[b];
+    const double r = block_sum(v, sh);
+    if (threadIdx.x == 0) {
+        tot = r;
+        if (blockIdx.x == 0) *nu2 = r;
+    }
+    __syncthreads();
+    const double nu = sqrt(tot);
+    if (nu == 0.0 || fabs(nu - 1.0) <= RESCALE_TOL_F32) return;
+    const double s = 1.0 / nu;
+    for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n; t += (size_t)gridDim.x * RED_THREADS) {
+        const float y = (float)((double)x[t] * s);
+        x[t] = y;
+        xh[t] = (_Float16)y;
+    }
+}
+
+// x32 = r / sqrt(*den_sq) rounded to float32, and xh the same rounded on to
+// float16 (0 when *den_sq is 0)
+__global__ void k_scale_to_fh(float *__restrict__ x32, _Float16 *__restrict__ xh, const double *__restrict__ r,
+                              const double *__restrict__ den_sq, size_t n) {
+    const double s = *den_sq > 0.0 ? 1.0 / sqrt(*den_sq) : 0.0;
+    for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n; t += (size_t)gridDim.x * RED_THREADS) {
+        const float y = (float)(r[t] * s);
+        x32[t] = y;
+        xh[t] = (_Float16)y;
+    }
+}
+
 __global__ void __launch_bounds__(RED_THREADS)
 k_rescale_if_f(float *__restrict__ x, const double *__restrict__ partial, int nparts, double *__restrict__ nu2,
                size_t n) {
@@ -693,6 +819,54 @@ void launch_orth_update32(hipStream_t s, float *w, const float *V, size_t ldv, i
     }
     DWP_LAUNCH_CHECK();
     k_rescale_if_f<<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, partial, RED_BLOCKS, hc + 65, n);
+    DWP_LAUNCH_CHECK();
+}
+
+static bool oct_ok(const void *a, size_t ldv, size_t n) {
+    return n % 8 == 0 && ldv % 8 == 0 && (reinterpret_cast<uintptr_t>(a) & 15) == 0;
+}
+
+bool krylov16_supported(const void *V, size_t ldv, size_t n) { return oct_ok(V, ldv, n); }
+
+void launch_multidot16(hipStream_t s, const _Float16 *V, size_t ldv, int nv, const float *w, size_t n,
+                       double *partial, double *out, double *norm_out) {
+    if (nv > 64 || !oct_ok(V, ldv, n) || !oct_ok(w, 0, n)) fail(DWP_EINVAL, "internal: float16 multidot layout");
+    for (int v0 = 0; v0 < nv; v0 += MD2_GROUP) {
+        const int g = nv - v0 < MD2_GROUP ? nv - v0 : MD2_GROUP;
+        const int wn = (v0 == 0 && norm_out) ? 1 : 0;
+        switch (g) {
+#define DWP_MD8_CASE(K)                                                                                      \
+    case K:                                                                                                  \
+        k_multidot8h<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, v0, w, n / 8, partial, MD_STRIDE, wn);    \
+        break;
+            DWP_NV_CASES(DWP_MD8_CASE)
+#undef DWP_MD8_CASE
+        }
+        DWP_LAUNCH_CHECK();
+    }
+    k_reduce_partials<<<nv + (norm_out ? 1 : 0), RED_THREADS, 0, s>>>(partial, RED_BLOCKS, MD_STRIDE, out, nv,
+                                                                     norm_out);
+    DWP_LAUNCH_CHECK();
+}
+
+void launch_orth_update16(hipStream_t s, float *w, _Float16 *vn, const _Float16 *V, size_t ldv, int nv, double *hc,
+                          size_t n, double *partial) {
+    if (nv < 1 || nv > 16 || !oct_ok(V, ldv, n) || !oct_ok(vn, 0, n) || !oct_ok(w, 0, n))
+        fail(DWP_EINVAL, "internal: float16 orth update layout");
+    switch (nv) {
+#define DWP_OU8_CASE(K)                                                                                          \
+    case K: k_orth_update8h<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, vn, V, ldv, hc, n / 8, partial, hc + 66); \
+        break;
+        DWP_NV_CASES(DWP_OU8_CASE)
+#undef DWP_OU8_CASE
+    }
+    DWP_LAUNCH_CHECK();
+    k_rescale_if_fh<<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, vn, partial, RED_BLOCKS, hc + 65, n);
+    DWP_LAUNCH_CHECK();
+}
+
+void launch_scale_to16(hipStream_t s, float *x32, _Float16 *xh, const double *r, const double *den_sq, size_t n) {
+    k_scale_to_fh<<<RED_BLOCKS, RED_THREADS, 0, s>>>(x32, xh, r, den_sq, n);
     DWP_LAUNCH_CHECK();
 }
 

@@ -505,7 +505,8 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
     double *V = c->V.as<double>(), *Z = c->Z.as<double>();
     // mixed precision with krylov_fp32: the Arnoldi basis in float32 (every
     // product, sum and the coupling update x += Z y stay float64; each restart
-    // recomputes the true residual in float64)
+    // recomputes the true residual in float64); with krylov_fp16 too, the
+    // basis V in float16
     const bool six = c->opts.order == 6;
     const bool v32 = c->opts.krylov_fp32 != 0 && c->opts.precision == DWP_MIXED &&
                      (!six || (c->opts.cycles == 0 && c->G632.bytes >= sizeof(float) * 3 * N)) &&
@@ -513,6 +514,21 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
                      krylov32_supported(c->Z.as<float>(), N, N) && c->eps32.bytes >= sizeof(float) * N;
     float *V32 = c->V32.as<float>();
     float *Z32 = c->Z.as<float>();  // with v32 the Z buffer holds float32 vectors
+    // krylov_fp16 (second order): the V32 buffer holds the basis in float16
+    // and, after it, the current vector in float32 (the preconditioner's input
+    // and the new vector w of each step)
+    const size_t v16_bytes = (sizeof(_Float16) * N * (m + 1) + 255) / 256 * 256;
+    _Float16 *V16 = reinterpret_cast<_Float16 *>(V32);
+    float *vcur = reinterpret_cast<float *>(reinterpret_cast<char *>(V32) + v16_bytes);
+    const bool v16_ok = v32 && !six && c->opts.krylov_fp16 != 0 && v16_bytes + sizeof(float) * N <= c->V32.bytes &&
+                        krylov16_supported(V16, N, N) && krylov16_supported(vcur, N, N);
+    // A cycle on a float16 basis cannot reduce the residual much below the
+    // basis' rounding (2^-11), which costs iterations where cycles reduce it a
+    // lot: the first cycle of a solve, and every cycle after one that reduced
+    // it more than V16_MAX_REDUCTION-fold, runs on the float32 basis.
+    constexpr double V16_MAX_REDUCTION = 100.0;
+    double beta_prev = -1.0;
+    bool v16 = false;
     double *coef = c->coef.as<double>();
     // column j at Hd + j * 72: [0..j] dots, 64 ||w||^2, 65 squared norm of the
     // new vector before any rescaling, 66 the divisor of the fused update
@@ -538,7 +554,10 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
         *rel = beta / bnorm;
         if (*rel <= o.tol || iters >= o.max_outer) return iters;
         ++*restarts;
-        if (v32) PROF(c, PG_VEC, 12.0 * N, launch_scale_to32(s, V32, r0, beta2, N));
+        v16 = v16_ok && beta_prev > 0.0 && beta * V16_MAX_REDUCTION >= beta_prev;
+        beta_prev = beta;
+        if (v16) PROF(c, PG_VEC, 14.0 * N, launch_scale_to16(s, vcur, V16, r0, beta2, N));
+        else if (v32) PROF(c, PG_VEC, 12.0 * N, launch_scale_to32(s, V32, r0, beta2, N));
         else PROF(c, PG_VEC, 16.0 * N, launch_scale_dev(s, V, nullptr, beta2, N, 0));
         const int mm = std::min(m, o.max_outer - iters);
         // First step after which the host checks the least-squares residual:
@@ -587,7 +606,19 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
         for (int j = 0; j < mm && !stop; ++j) {
             double *Vj = V + (size_t)j * N, *Vn = V + (size_t)(j + 1) * N, *Zj = Z + (size_t)j * N;
             double *hc = Hd + (size_t)j * HESS_STRIDE;
-            if (v32) {
+            if (v16) {
+                // v_j in float32 (vcur) -> z_j; w = A z_j into vcur; project
+                // on the float16 basis; the normalised vector into the basis
+                // and into vcur
+                float *Zj32 = Z32 + (size_t)j * N;
+                apply_split(c, (const float *)vcur, Zj32);
+                fused[j] = 1;
+                PROF(c, PG_APPLY, 12.0 * N, launch_apply_full_f32(s, p, (const float *)Zj32, c->eps32.as<float>(), vcur));
+                PROF(c, PG_MULTIDOT, (2.0 * (j + 1) + 4.0) * N,
+                     launch_multidot16(s, V16, N, j + 1, vcur, N, part, hc, hc + 64));
+                PROF(c, PG_AXPY, (2.0 * (j + 1) + 10.0) * N,
+                     launch_orth_update16(s, vcur, V16 + (size_t)(j + 1) * N, V16, N, j + 1, hc, N, part));
+            } else if (v32) {
                 float *Vj32 = V32 + (size_t)j * N, *Vn32 = V32 + (size_t)(j + 1) * N, *Zj32 = Z32 + (size_t)j * N;
                 apply_split(c, (const float *)Vj32, Zj32);
                 fused[j] = 1;  // restart <= 16 is checked with the options
@@ -701,6 +732,9 @@ void validate_opts(const dwp_opts &o) {
     if (o.krylov_fp32 && o.order == 6 && o.cycles != 0)
         fail(DWP_EINVAL, "krylov_fp32 with the sixth-order operator needs cycles = 0 (the FFT dry update alone)");
     if (o.krylov_fp32 && o.restart > 16) fail(DWP_EINVAL, "krylov_fp32 takes restart lengths up to 16");
+    if (o.krylov_fp16 != 0 && o.krylov_fp16 != 1) fail(DWP_EINVAL, "krylov_fp16 must be 0 or 1");
+    if (o.krylov_fp16 && (o.krylov_fp32 != 1 || o.order != 2))
+        fail(DWP_EINVAL, "krylov_fp16 needs krylov_fp32 = 1 and the second-order operator");
 }
 
 AtomParams atom_params(const dwp_eps_params *ep) {
@@ -1297,6 +1331,7 @@ void dwp_default_opts(dwp_opts *o) {
     o->order = 2;
     o->smooth6 = 0;
     o->krylov_fp32 = 0;
+    o->krylov_fp16 = 0;
 }
 
 int dwp_create(dwp_ctx **out, int device, void *stream) {

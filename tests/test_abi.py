@@ -22,6 +22,7 @@ def test_default_opts():
     assert math.isnan(o.z_wet_lo) and math.isnan(o.z_wet_hi)
     assert o.tol == 1e-10 and o.restart == 10 and o.warm_start == 0 and o.profile == 0
     assert o.smoother == 1 and o.fft_fp32 == 0 and o.order == 2 and o.smooth6 == 0 and o.krylov_fp32 == 0
+    assert o.krylov_fp16 == 0
 
 
 @pytest.mark.parametrize("n", [(30, 32, 64), (32, 32, 6), (32, 32, 70), (32, 32, 8192), (33, 32, 64)])
@@ -39,7 +40,9 @@ def test_plan_rejects_bad_grid_sizes(n):
                                 dict(smooth6=2), dict(smooth6=1), dict(smooth6=1, order=2),
                                 dict(krylov_fp32=2), dict(krylov_fp32=1, precision=0),
                                 dict(krylov_fp32=1, precision=1, order=6),
-                                dict(krylov_fp32=1, precision=1, restart=17)])
+                                dict(krylov_fp32=1, precision=1, restart=17),
+                                dict(krylov_fp16=2), dict(krylov_fp16=1, precision=1),
+                                dict(krylov_fp16=1, krylov_fp32=1, precision=1, order=6, cycles=0)])
 def test_plan_rejects_bad_options(kw):
     with pytest.raises(B.DWPError) as e:
         B.plan((32, 32, 64), (10.0, 10.0, 20.0), **kw)
@@ -90,5 +93,6 @@ def test_create_without_device_fails_cleanly():
 def test_plan_accepts_float32_krylov_vectors_where_supported():
     # second order at any cycle count; sixth order with the FFT dry update alone
     for kw in (dict(krylov_fp32=1, precision=1), dict(krylov_fp32=1, precision=1, restart=16),
-               dict(krylov_fp32=1, precision=1, order=6, cycles=0)):
+               dict(krylov_fp32=1, precision=1, order=6, cycles=0),
+               dict(krylov_fp32=1, krylov_fp16=1, precision=1)):
         B.plan((32, 32, 64), (10.0, 10.0, 20.0), **kw)

@@ -4,8 +4,8 @@ The 96 x 96 x 192 slab (the literal workload, solver options as benchmarked)
 has a fine wet level of more than 2^20 points, so every sweep of its finest
 multigrid level goes through the fused single-pass kernel.  phi and dE/d eps
 are compared with the oracle node by node over the whole grid, in float64 and
-in mixed precision (with a float64 and with a float32 Arnoldi basis), against
-one live oracle solve.
+in mixed precision (with a float64, a float32 and a float16 Arnoldi basis),
+against one live oracle solve.
 """
 import numpy as np
 import pytest
@@ -25,11 +25,11 @@ def case():
     return w, rho, phi, O.energy(rho, phi, w.h), O.eps_gradient(phi, w.h)
 
 
-@pytest.mark.parametrize("precision,krylov_fp32", [(0, 0), (1, 0), (1, 1)])
-def test_whole_field_matches_oracle_where_fused_sweep_runs(case, precision, krylov_fp32):
+@pytest.mark.parametrize("precision,krylov_fp32,krylov_fp16", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (1, 1, 1)])
+def test_whole_field_matches_oracle_where_fused_sweep_runs(case, precision, krylov_fp32, krylov_fp16):
     from paper_0904_4887_amd.binding import Solver, plan
     w, rho, phi_o, E_o, g_o = case
-    opts = w.solver_opts(precision=precision, krylov_fp32=krylov_fp32)
+    opts = w.solver_opts(precision=precision, krylov_fp32=krylov_fp32, krylov_fp16=krylov_fp16)
     fine = plan(w.n, w.L, **opts)["levels"][0]
     assert fine[0] * fine[1] * fine[2] >= 1 << 20  # the fused sweep takes this level
     s = Solver(0)
@@ -48,9 +48,10 @@ def test_whole_field_matches_oracle_where_fused_sweep_runs(case, precision, kryl
 
 
 def test_switching_the_krylov_precision_on_one_context(case):
-    # float64 -> float32 -> float64 Krylov bases on one context: the float32
-    # leg meets the same bars, and the last leg repeats the first bit for bit
-    # (the float32 buffers and the float32 copy of eps leave nothing behind)
+    # float64 -> float32 -> float16 -> float64 Krylov bases on one context:
+    # the float32 and float16 legs meet the same bars, and the last leg
+    # repeats the first bit for bit (the reduced-precision buffers and the
+    # float32 copy of eps leave nothing behind)
     from paper_0904_4887_amd.binding import Solver
     w, rho, phi_o, E_o, g_o = case
     s = Solver(0)
@@ -58,14 +59,14 @@ def test_switching_the_krylov_precision_on_one_context(case):
     s.build_epsilon(w.xyz, w.radius, w.eps_params)
     rho_d = s.build_rho(w.xyz, w.q, w.sigma)
     Es, phis = [], []
-    for k32 in (0, 1, 0):
-        s.set_opts(krylov_fp32=k32)
+    for k32, k16 in ((0, 0), (1, 0), (1, 1), (0, 0)):
+        s.set_opts(krylov_fp32=k32, krylov_fp16=k16)
         phi_d, E, info = s.solve(rho_d)
         assert info["rel_res"] <= 1e-10
         Es.append(E)
         phis.append(phi_d.cpu().numpy())
     s.close()
-    assert Es[2] == Es[0] and np.array_equal(phis[2], phis[0])
+    assert Es[3] == Es[0] and np.array_equal(phis[3], phis[0])
     for E, phi in zip(Es, phis):
         assert abs(E - E_o) <= 1e-10 * abs(E_o)
         assert np.abs(phi - phi_o).max() <= 1e-8 * np.abs(phi_o).max()
