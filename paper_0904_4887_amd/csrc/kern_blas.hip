@@ -285,8 +285,11 @@ k_orth_update4f(float *__restrict__ w, const float *__restrict__ V, size_t ldv, 
 
 // The projection and update for a float16 Krylov basis: V in float16 (eight
 // per 16-byte load), the new vector w in float32 (the one the preconditioner
-// reads), every product and sum in float64.  The update writes the normalised
-// vector twice: into the basis (float16) and back into w (float32).
+// reads).  The products and the sums over a thread's eight points are float32
+// (a float16 value times a float32 one rounds at 2^-24 relative, far below the
+// basis' own 2^-11), everything summed over points is float64.  The update
+// writes the normalised vector twice: into the basis (float16) and back into
+// w (float32).
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f8 __attribute__((ext_vector_type(8)));
 
@@ -313,10 +316,10 @@ k_multidot8h(const _Float16 *__restrict__ V, size_t ldv, int v0, const float *__
                    ((wd[4] * wd[4] + wd[5] * wd[5]) + (wd[6] * wd[6] + wd[7] * wd[7]));
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
-            double d = 0.0;
+            float d = 0.0f;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) d += (double)(float)vq[q][e] * wd[e];
-            acc[q] += d;
+            for (int e = 0; e < 8; ++e) d = __builtin_fmaf((float)vq[q][e], wt[e], d);
+            acc[q] += (double)d;
         }
     }
     block_sums<NA>(acc, sh, res);
@@ -342,29 +345,35 @@ k_orth_update8h(float *__restrict__ w, _Float16 *__restrict__ vn, const _Float16
     if ((int)threadIdx.x < NV) cs[threadIdx.x] = -hc[threadIdx.x];
     __syncthreads();
     const double sc = cs[NV];
+    float csf[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) csf[q] = (float)cs[q];
     f8 *w8 = reinterpret_cast<f8 *>(w);
     h8 *vn8 = reinterpret_cast<h8 *>(vn);
     double nrm[1] = {0.0};
     for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n8; t += (size_t)gridDim.x * RED_THREADS) {
         const f8 wv = w8[t];
-        double a[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) a[e] = wv[e];
         h8 vq[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) vq[q] = reinterpret_cast<const h8 *>(V + (size_t)q * ldv)[t];
+        // the projection sum_q h_q V_q per point in float32, subtracted from w in float64
+        float pr[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) pr[e] = 0.0f;
 #pragma unroll
         for (int q = 0; q < NV; ++q)
 #pragma unroll
-            for (int e = 0; e < 8; ++e) a[e] += cs[q] * (double)(float)vq[q][e];
+            for (int e = 0; e < 8; ++e) pr[e] = __builtin_fmaf(csf[q], (float)vq[q][e], pr[e]);
         f8 o;
         h8 oh;
+        float nr = 0.0f;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            o[e] = (float)(a[e] * sc);
+            o[e] = (float)(((double)wv[e] + (double)pr[e]) * sc);
             oh[e] = (_Float16)o[e];
-            nrm[0] += (double)o[e] * (double)o[e];
+            nr = __builtin_fmaf(o[e], o[e], nr);
         }
+        nrm[0] += (double)nr;
         w8[t] = o;
         vn8[t] = oh;
     }
