@@ -19,6 +19,7 @@
 // and output grids are float64 either way.
 #include "dwp_internal.h"
 
+#include <atomic>
 #include <cmath>
 
 namespace dwp {
@@ -28,11 +29,16 @@ namespace {
 constexpr int FFT_THREADS = 512;
 constexpr int FFT_MAXE = 4096;   // complex values per block (lines x length) at most
 // Lines per block: B * n within the budget (see tile_log2), never above the
-// per-block maximum, with the LDS of a block within 64 KB.  The float32 x
+// per-block maximum, with the lines of a block within 64 KB of LDS (the n
+// twiddles of the axis follow them, up to 64 KB more for n = 4096 in float64,
+// where the kernel's LDS limit is raised).  The float32 x
 // passes take 16 lines of 192 (measured: 0.5 ms per step less than 8).  A
 // float32 z pass of 16 lines of 384 (a per-block maximum of 8192 for that
 // kernel alone: 124 VGPRs, half the waves) measured 40 % slower than 8.
-constexpr int FFT_BUDGET_X = 2048, FFT_BUDGET_X32 = 4096, FFT_BUDGET_Y = 4096, FFT_BUDGET_Z = 4096;
+constexpr int FFT_BUDGET_X = 2048, FFT_BUDGET_X32 = 4096, FFT_BUDGET_Y = 4096;
+// z pass: threads, lines x length per block (16 lines of 384 with 1024
+// threads measured 10 % slower than 8 lines with 512)
+constexpr int FFT_Z_THREADS = 512, FFT_Z_MAXE = 4096;
 constexpr int MAX_STAGES = 12;
 
 // Division by a small positive d through one multiply-high: with
@@ -138,17 +144,17 @@ template <class C> struct DFT<8, C> {
 // radices of the earlier stages.  Butterfly i of a line reads
 // x_q = buf[i + q n/R], twiddles x_q by exp(-+2 pi i q (i mod p) / (p R)),
 // and writes output r to (i - i mod p) R + i mod p + r p.
-template <int R, class C, int MAXE>
+template <int R, class C, int MAXE, int NT>
 __device__ void stage(C *buf, int n, int p, unsigned pm, int tstride, int lb, int es, int ls,
                       const C *__restrict__ tw, bool inv) {
-    constexpr int K = (MAXE / R + FFT_THREADS - 1) / FFT_THREADS;
+    constexpr int K = (MAXE / R + NT - 1) / NT;
     const int T = n / R;
     const int items = T << lb;
     const int bmask = (1 << lb) - 1;
     C x[K][R];
 #pragma unroll
     for (int m = 0; m < K; ++m) {
-        const int w = threadIdx.x + m * FFT_THREADS;
+        const int w = threadIdx.x + m * NT;
         if (w < items) {
             const int l = w & bmask, i = w >> lb;
 #pragma unroll
@@ -158,7 +164,7 @@ __device__ void stage(C *buf, int n, int p, unsigned pm, int tstride, int lb, in
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < K; ++m) {
-        const int w = threadIdx.x + m * FFT_THREADS;
+        const int w = threadIdx.x + m * NT;
         if (w < items) {
             const int l = w & bmask, i = w >> lb;
             const int k = p > 1 ? i - p * (int)__umulhi((unsigned)i, pm) : 0;
@@ -180,16 +186,43 @@ __device__ void stage(C *buf, int n, int p, unsigned pm, int tstride, int lb, in
     __syncthreads();
 }
 
-template <class C, int MAXE = FFT_MAXE>
+template <class C, int MAXE = FFT_MAXE, int NT = FFT_THREADS>
 __device__ void fft_lines(C *buf, const Radices &rd, int lb, int es, int ls, const C *__restrict__ tw, bool inv) {
     for (int s = 0; s < rd.nst; ++s) {
         const int R = rd.r[s];
-        if (R == 8) stage<8, C, MAXE>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
-        else if (R == 4) stage<4, C, MAXE>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
-        else if (R == 3) stage<3, C, MAXE>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
-        else stage<2, C, MAXE>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
+        if (R == 8) stage<8, C, MAXE, NT>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
+        else if (R == 4) stage<4, C, MAXE, NT>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
+        else if (R == 3) stage<3, C, MAXE, NT>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
+        else stage<2, C, MAXE, NT>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
     }
 }
+
+// A block's loads of n_el values from global memory: KL per thread issued
+// together, then stored (ld(e) gives value e, st(e, v) puts it in LDS), so a
+// thread waits once per KL values instead of once per value.  With ntw > 0
+// the ntw twiddles tw_g[] come along into tw_l[] (LDS), so that the stages
+// read them from LDS.
+template <int KL, int NT, class V, class Ld, class St>
+__device__ __forceinline__ void load_batched(int n_el, Ld ld, St st, const V *__restrict__ tw_g = nullptr,
+                                             V *tw_l = nullptr, int ntw = 0) {
+    const int tot = n_el + ntw;
+    for (int e0 = 0; e0 < tot; e0 += KL * NT) {
+        V v[KL];
+#pragma unroll
+        for (int m = 0; m < KL; ++m) {
+            const int e = e0 + threadIdx.x + m * NT;
+            if (e < n_el) v[m] = ld(e);
+            else if (e < tot) v[m] = tw_g[e - n_el];
+        }
+#pragma unroll
+        for (int m = 0; m < KL; ++m) {
+            const int e = e0 + threadIdx.x + m * NT;
+            if (e < n_el) st(e, v[m]);
+            else if (e < tot) tw_l[e - n_el] = v[m];
+        }
+    }
+}
+constexpr int FFT_KL = FFT_MAXE / FFT_THREADS;  // one batch covers a block of the separate passes
 
 // ---------------------------------------------------------------- x passes
 // Rows are the nx-long x lines of the [nz][ny][nx] grid; B = 2^lb complex
@@ -203,20 +236,28 @@ k_fft_x_fwd(const TI *__restrict__ in, const double *__restrict__ sinv, cplx<S> 
     C *lds = reinterpret_cast<C *>(lds_raw);
     const int n = rd.n, ls = n + 1, B = 1 << lb;
     const int r0 = blockIdx.x * 2 * B;
-    for (int e = threadIdx.x; e < B * n; e += FFT_THREADS) {
-        const int l = udiv(e, dn), t = e - l * n;
-        const int ra = r0 + 2 * l, rb = ra + 1;
-        double a = 0.0, b = 0.0;
-        if (rb < nrows) {
-            const size_t ia = (size_t)ra * n + t, ib = ia + n;
-            a = (double)in[ia];
-            b = (double)in[ib];
-            if (sinv) { a *= sinv[ia]; b *= sinv[ib]; }
-        }
-        lds[l * ls + t] = mk<C>((S)a, (S)b);
-    }
+    C *twl = lds + B * ls;
+    load_batched<FFT_KL, FFT_THREADS, C>(
+        B * n,
+        [&](int e) {
+            const int l = udiv(e, dn), t = e - l * n;
+            const int ra = r0 + 2 * l, rb = ra + 1;
+            double a = 0.0, b = 0.0;
+            if (rb < nrows) {
+                const size_t ia = (size_t)ra * n + t, ib = ia + n;
+                a = (double)in[ia];
+                b = (double)in[ib];
+                if (sinv) { a *= sinv[ia]; b *= sinv[ib]; }
+            }
+            return mk<C>((S)a, (S)b);
+        },
+        [&](int e, C v) {
+            const int l = udiv(e, dn), t = e - l * n;
+            lds[l * ls + t] = v;
+        },
+        tw, twl, n);
     __syncthreads();
-    fft_lines(lds, rd, lb, 1, ls, tw, false);
+    fft_lines(lds, rd, lb, 1, ls, twl, false);
     for (int e = threadIdx.x; e < B * nkx; e += FFT_THREADS) {
         const int l = udiv(e, dk), k = e - l * nkx;
         const int ra = r0 + 2 * l, rb = ra + 1;
@@ -239,21 +280,29 @@ k_fft_x_inv(const cplx<S> *__restrict__ in, const double *__restrict__ sinv, TO 
     C *lds = reinterpret_cast<C *>(lds_raw);
     const int n = rd.n, ls = n + 1, B = 1 << lb;
     const int r0 = blockIdx.x * 2 * B;
-    for (int e = threadIdx.x; e < B * n; e += FFT_THREADS) {
-        const int l = udiv(e, dn), k = e - l * n;
-        const int ra = r0 + 2 * l, rb = ra + 1;
-        C z = mk<C>(0, 0);
-        if (rb < nrows) {
-            const int kk = (k < nkx) ? k : n - k;
-            C A = in[(size_t)ra * ldc + kk], Bv = in[(size_t)rb * ldc + kk];
-            if (kk == 0 || 2 * kk == n) { A.y = 0; Bv.y = 0; }
-            if (k >= nkx) { A.y = -A.y; Bv.y = -Bv.y; }  // Hermitian extension
-            z = mk<C>(A.x - Bv.y, A.y + Bv.x);           // A + i B
-        }
-        lds[l * ls + k] = z;
-    }
+    C *twl = lds + B * ls;
+    load_batched<FFT_KL, FFT_THREADS, C>(
+        B * n,
+        [&](int e) {
+            const int l = udiv(e, dn), k = e - l * n;
+            const int ra = r0 + 2 * l, rb = ra + 1;
+            C z = mk<C>(0, 0);
+            if (rb < nrows) {
+                const int kk = (k < nkx) ? k : n - k;
+                C A = in[(size_t)ra * ldc + kk], Bv = in[(size_t)rb * ldc + kk];
+                if (kk == 0 || 2 * kk == n) { A.y = 0; Bv.y = 0; }
+                if (k >= nkx) { A.y = -A.y; Bv.y = -Bv.y; }  // Hermitian extension
+                z = mk<C>(A.x - Bv.y, A.y + Bv.x);           // A + i B
+            }
+            return z;
+        },
+        [&](int e, C v) {
+            const int l = udiv(e, dn), k = e - l * n;
+            lds[l * ls + k] = v;
+        },
+        tw, twl, n);
     __syncthreads();
-    fft_lines(lds, rd, lb, 1, ls, tw, true);
+    fft_lines(lds, rd, lb, 1, ls, twl, true);
     for (int e = threadIdx.x; e < B * n; e += FFT_THREADS) {
         const int l = udiv(e, dn), t = e - l * n;
         const int ra = r0 + 2 * l, rb = ra + 1;
@@ -275,7 +324,9 @@ k_fft_x_inv(const cplx<S> *__restrict__ in, const double *__restrict__ sinv, TO 
 // b mod 8, which gets the contiguous run of tiles [xcd * per, (xcd + 1) * per),
 // so the line tiles of one row (which share the 128-byte cache lines at their
 // edges) run side by side on one XCD and its L2 serves the shared lines once.
-// Returns false for the padding blocks.
+// Returns false for the padding blocks.  (Tiles that leave out the columns
+// beyond the last full group of B, with those columns' lines grouped along
+// the rows instead, measured slower: their scattered accesses form a tail.)
 __device__ __forceinline__ bool xcd_tile2(int ntx, int nty, int &tx, int &ty) {
     const int per = gridDim.x / 8;
     const int t = (blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -302,12 +353,16 @@ k_fft_y(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ tw, int
     const int kx0 = bt * B;
     const int bw = min(B, nkx - kx0);
     const size_t base = (size_t)z * ny * ldc + kx0;
-    for (int e = threadIdx.x; e < B * ny; e += FFT_THREADS) {
-        const int y = e >> lb, l = e & bmask;
-        lds[e] = (l < bw) ? c[base + (size_t)y * ldc + l] : mk<C>(0, 0);
-    }
+    C *twl = lds + B * ny;
+    load_batched<FFT_KL, FFT_THREADS, C>(
+        B * ny,
+        [&](int e) {
+            const int y = e >> lb, l = e & bmask;
+            return (l < bw) ? c[base + (size_t)y * ldc + l] : mk<C>(0, 0);
+        },
+        [&](int e, C v) { lds[e] = v; }, tw, twl, ny);
     __syncthreads();
-    fft_lines(lds, rd, lb, B, 1, tw, inv != 0);
+    fft_lines(lds, rd, lb, B, 1, twl, inv != 0);
     for (int e = threadIdx.x; e < B * ny; e += FFT_THREADS) {
         const int y = e >> lb, l = e & bmask;
         if (l < bw) c[base + (size_t)y * ldc + l] = lds[e];
@@ -326,8 +381,10 @@ __device__ __forceinline__ double neg_recip(double d) {
 }
 __device__ __forceinline__ float neg_recip(float d) { return -__builtin_amdgcn_rcpf(d); }
 
-template <class S, int MAXE = FFT_MAXE>
-__global__ void __launch_bounds__(FFT_THREADS)
+// Block (tile of B = 2^lb consecutive kx, row y): lines along z, LDS element
+// (z, l) at z * B + l.
+template <class S, int MAXE = FFT_MAXE, int NT = FFT_THREADS>
+__global__ void __launch_bounds__(NT)
 k_fft_z_green(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ tw, int lb, int nkx, int ldc, int ny,
               const S *__restrict__ lamx, const S *__restrict__ lamy, const S *__restrict__ lamz, S inv_n) {
     using C = cplx<S>;
@@ -340,14 +397,18 @@ k_fft_z_green(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ t
     const int bw = min(B, nkx - kx0);
     const size_t zstride = (size_t)ny * ldc;
     const size_t base = (size_t)y * ldc + kx0;
-    for (int e = threadIdx.x; e < B * nz; e += FFT_THREADS) {
-        const int z = e >> lb, l = e & bmask;
-        lds[e] = (l < bw) ? c[base + (size_t)z * zstride + l] : mk<C>(0, 0);
-    }
+    C *twl = lds + B * nz;
+    load_batched<(MAXE + NT - 1) / NT, NT, C>(
+        B * nz,
+        [&](int e) {
+            const int z = e >> lb, l = e & bmask;
+            return (l < bw) ? c[base + (size_t)z * zstride + l] : mk<C>(0, 0);
+        },
+        [&](int e, C v) { lds[e] = v; }, tw, twl, nz);
     __syncthreads();
-    fft_lines<C, MAXE>(lds, rd, lb, B, 1, tw, false);
+    fft_lines<C, MAXE, NT>(lds, rd, lb, B, 1, twl, false);
     const S ly = lamy[y];
-    for (int e = threadIdx.x; e < B * nz; e += FFT_THREADS) {
+    for (int e = threadIdx.x; e < B * nz; e += NT) {
         const int z = e >> lb, l = e & bmask;
         const int kx = kx0 + l;
         S g = 0;
@@ -356,12 +417,25 @@ k_fft_z_green(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ t
         lds[e] = mk<C>(v.x * g, v.y * g);
     }
     __syncthreads();
-    fft_lines<C, MAXE>(lds, rd, lb, B, 1, tw, true);
-    for (int e = threadIdx.x; e < B * nz; e += FFT_THREADS) {
+    fft_lines<C, MAXE, NT>(lds, rd, lb, B, 1, twl, true);
+    for (int e = threadIdx.x; e < B * nz; e += NT) {
         const int z = e >> lb, l = e & bmask;
         if (l < bw) c[base + (size_t)z * zstride + l] = lds[e];
     }
 }
+
+// Raise a kernel's dynamic LDS limit to 160 KB, once per device (bit d of
+// `done`), when a launch asks for more than the default 64 KB.
+void lds_attr(const void *fn, std::atomic<unsigned> &done, size_t bytes) {
+    if (bytes <= 64 * 1024) return;
+    int dev = 0;
+    DWP_HIP(hipGetDevice(&dev));
+    const unsigned bit = 1u << (dev & 31);
+    if (done.load() & bit) return;
+    DWP_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    done.fetch_or(bit);
+}
+template <class F> const void *fptr(F *f) { return reinterpret_cast<const void *>(f); }
 
 Radices radices_of(const FFTAxis &ax) {
     Radices r{};
@@ -449,10 +523,25 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
     auto pb = [&](int g) { return prof ? prof->begin(st, g) : -1; };
     auto pe = [&](int ev, int g, double b) { if (prof) prof->end(st, ev, g, b); };
     int ev;
+    // z pass with the Green's function (lines of 8 kx; the twiddles follow
+    // the lines in LDS)
+    auto z_pass = [&]() {
+        const int lbz = tile_log2(p.nz, FFT_Z_MAXE), Bz = 1 << lbz;
+        const int gz = xcd_grid((p.nkx + Bz - 1) / Bz * p.ny);
+        const size_t bytes = sizeof(C) * ((size_t)Bz * p.nz + p.nz);
+        static std::atomic<unsigned> attr{0};
+        lds_attr(fptr(&k_fft_z_green<S, FFT_Z_MAXE, FFT_Z_THREADS>), attr, bytes);
+        k_fft_z_green<S, FFT_Z_MAXE, FFT_Z_THREADS><<<gz, FFT_Z_THREADS, bytes, st>>>(
+            cbuf, radices_of(az), TW(az), lbz, p.nkx, p.ldc, p.ny, LAM(ax), LAM(ay), LAM(az), (S)(1.0 / (double)p.N));
+        DWP_LAUNCH_CHECK();
+    };
     const int nrows = p.ny * p.nz;
     const int lbx = tile_log2(p.nx, sizeof(S) == 4 ? FFT_BUDGET_X32 : FFT_BUDGET_X), Bx = 1 << lbx;
     const int gx = (nrows + 2 * Bx - 1) / (2 * Bx);
-    const size_t ldsx = sizeof(C) * Bx * (p.nx + 1);
+    const size_t ldsx = sizeof(C) * ((size_t)Bx * (p.nx + 1) + p.nx);
+    static std::atomic<unsigned> xf_attr{0}, xi_attr{0}, y_attr{0};
+    lds_attr(fptr(&k_fft_x_fwd<S, TI>), xf_attr, ldsx);
+    lds_attr(fptr(&k_fft_x_inv<S, TO>), xi_attr, ldsx);
     const Div dn = make_div(p.nx), dk = make_div(p.nkx);
     ev = pb(PG_FFT_X);
     k_fft_x_fwd<S, TI><<<gx, FFT_THREADS, ldsx, st>>>(r, sinv, cbuf, radices_of(ax), TW(ax), lbx, nrows, p.nkx, p.ldc, dn,
@@ -461,22 +550,17 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
     pe(ev, PG_FFT_X, bx);
     const int lby = tile_log2(p.ny, FFT_BUDGET_Y), By = 1 << lby;
     const int gy = xcd_grid((p.nkx + By - 1) / By * p.nz);
+    const size_t ldsy = sizeof(C) * ((size_t)By * p.ny + p.ny);
+    lds_attr(fptr(&k_fft_y<S>), y_attr, ldsy);
     ev = pb(PG_FFT_Y);
-    k_fft_y<S><<<gy, FFT_THREADS, sizeof(C) * By * p.ny, st>>>(cbuf, radices_of(ay), TW(ay), lby, p.nkx, p.ldc, p.nz,
-                                                              0);
+    k_fft_y<S><<<gy, FFT_THREADS, ldsy, st>>>(cbuf, radices_of(ay), TW(ay), lby, p.nkx, p.ldc, p.nz, 0);
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_Y, 2.0 * cb * Cn);
-    const int lbz = tile_log2(p.nz, FFT_BUDGET_Z), Bz = 1 << lbz;
-    const int gz = xcd_grid((p.nkx + Bz - 1) / Bz * p.ny);
     ev = pb(PG_FFT_Z);
-    k_fft_z_green<S><<<gz, FFT_THREADS, sizeof(C) * Bz * p.nz, st>>>(cbuf, radices_of(az), TW(az), lbz, p.nkx, p.ldc,
-                                                                      p.ny, LAM(ax), LAM(ay), LAM(az),
-                                                                      (S)(1.0 / (double)p.N));
-    DWP_LAUNCH_CHECK();
+    z_pass();
     pe(ev, PG_FFT_Z, 2.0 * cb * Cn);
     ev = pb(PG_FFT_Y);
-    k_fft_y<S><<<gy, FFT_THREADS, sizeof(C) * By * p.ny, st>>>(cbuf, radices_of(ay), TW(ay), lby, p.nkx, p.ldc, p.nz,
-                                                              1);
+    k_fft_y<S><<<gy, FFT_THREADS, ldsy, st>>>(cbuf, radices_of(ay), TW(ay), lby, p.nkx, p.ldc, p.nz, 1);
     DWP_LAUNCH_CHECK();
     pe(ev, PG_FFT_Y, 2.0 * cb * Cn);
     ev = pb(PG_FFT_X);
