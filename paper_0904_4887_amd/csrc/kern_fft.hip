@@ -12,15 +12,17 @@
 //   z  : forward along z, multiply by -1/(N lambda), inverse along z
 //   y  : inverse
 //   x  : inverse of two rows at once (C2R)
-// Each 1-D transform is a Stockham autosort FFT with radix-8, -4, -3 and -2
+// Each 1-D transform is a Stockham autosort FFT with radix-8, -6, -4, -3 and -2
 // stages; a stage reads its inputs into registers, synchronises, and writes
 // its outputs back in place.  The spectrum and the transforms run in float64,
 // or in float32 (S = float) for the mixed-precision variant; the real input
 // and output grids are float64 either way.
 #include "dwp_internal.h"
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <type_traits>
 
 namespace dwp {
 
@@ -39,6 +41,7 @@ constexpr int FFT_BUDGET_X = 2048, FFT_BUDGET_X32 = 4096, FFT_BUDGET_Y = 4096;
 // z pass: threads, lines x length per block (16 lines of 384 with 1024
 // threads measured 10 % slower than 8 lines with 512)
 constexpr int FFT_Z_THREADS = 512, FFT_Z_MAXE = 4096;
+static_assert(FFT_Z_THREADS >= FFT_THREADS, "a radix-6 line fits every pass");
 constexpr int MAX_STAGES = 12;
 
 // Division by a small positive d through one multiply-high: with
@@ -114,6 +117,26 @@ template <class C> struct DFT<3, C> {
         x[2] = csub(t2, rd);
     }
 };
+template <class C> struct DFT<6, C> {
+    static __device__ __forceinline__ void run(C *x, bool inv) {
+        using S = decltype(C::x);
+        // two radix-3 transforms of the even and odd inputs, then one radix-2
+        // layer with the sixth roots of unity w6^k = exp(-+i pi k / 3):
+        // X[k] = E[k] + w6^k O[k], X[k + 3] = E[k] - w6^k O[k]
+        C ev[3] = {x[0], x[2], x[4]}, od[3] = {x[1], x[3], x[5]};
+        DFT<3, C>::run(ev, inv);
+        DFT<3, C>::run(od, inv);
+        const S h = (S)0.5, sg = inv ? (S)0.86602540378443864676 : (S)-0.86602540378443864676;
+        const C t1 = mk<C>(h * od[1].x - sg * od[1].y, h * od[1].y + sg * od[1].x);    // w6 = 1/2 + i sg
+        const C t2 = mk<C>(-h * od[2].x - sg * od[2].y, sg * od[2].x - h * od[2].y);   // w6^2 = -1/2 + i sg
+        x[0] = cadd(ev[0], od[0]);
+        x[3] = csub(ev[0], od[0]);
+        x[1] = cadd(ev[1], t1);
+        x[4] = csub(ev[1], t1);
+        x[2] = cadd(ev[2], t2);
+        x[5] = csub(ev[2], t2);
+    }
+};
 template <class C> struct DFT<8, C> {
     static __device__ __forceinline__ void run(C *x, bool inv) {
         using S = decltype(C::x);
@@ -147,7 +170,10 @@ template <class C> struct DFT<8, C> {
 template <int R, class C, int MAXE, int NT>
 __device__ void stage(C *buf, int n, int p, unsigned pm, int tstride, int lb, int es, int ls,
                       const C *__restrict__ tw, bool inv) {
-    constexpr int K = (MAXE / R + NT - 1) / NT;
+    // a block whose plan holds a radix-6 stage has at most 6 NT values
+    // (r6_budget), so that the radix-6 stage is one butterfly per thread
+    constexpr int E = R == 6 && MAXE > 6 * NT ? 6 * NT : MAXE;
+    constexpr int K = (E / R + NT - 1) / NT;
     const int T = n / R;
     const int items = T << lb;
     const int bmask = (1 << lb) - 1;
@@ -186,11 +212,14 @@ __device__ void stage(C *buf, int n, int p, unsigned pm, int tstride, int lb, in
     __syncthreads();
 }
 
-template <class C, int MAXE = FFT_MAXE, int NT = FFT_THREADS>
+// R6: the plan may hold a radix-6 stage (a kernel built without it keeps the
+// registers the radix-6 stage would need)
+template <bool R6, class C, int MAXE = FFT_MAXE, int NT = FFT_THREADS>
 __device__ void fft_lines(C *buf, const Radices &rd, int lb, int es, int ls, const C *__restrict__ tw, bool inv) {
     for (int s = 0; s < rd.nst; ++s) {
         const int R = rd.r[s];
         if (R == 8) stage<8, C, MAXE, NT>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
+        else if (R6 && R == 6) stage<6, C, MAXE, NT>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
         else if (R == 4) stage<4, C, MAXE, NT>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
         else if (R == 3) stage<3, C, MAXE, NT>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
         else stage<2, C, MAXE, NT>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
@@ -227,7 +256,7 @@ constexpr int FFT_KL = FFT_MAXE / FFT_THREADS;  // one batch covers a block of t
 // ---------------------------------------------------------------- x passes
 // Rows are the nx-long x lines of the [nz][ny][nx] grid; B = 2^lb complex
 // lines per block carry 2B real rows.  LDS lines are padded to n + 1 elements.
-template <class S, class TI>
+template <class S, class TI, bool R6>
 __global__ void __launch_bounds__(FFT_THREADS)
 k_fft_x_fwd(const TI *__restrict__ in, const double *__restrict__ sinv, cplx<S> *__restrict__ out,
             Radices rd, const cplx<S> *__restrict__ tw, int lb, int nrows, int nkx, int ldc, Div dn, Div dk) {
@@ -257,7 +286,7 @@ k_fft_x_fwd(const TI *__restrict__ in, const double *__restrict__ sinv, cplx<S> 
         },
         tw, twl, n);
     __syncthreads();
-    fft_lines(lds, rd, lb, 1, ls, twl, false);
+    fft_lines<R6>(lds, rd, lb, 1, ls, twl, false);
     for (int e = threadIdx.x; e < B * nkx; e += FFT_THREADS) {
         const int l = udiv(e, dk), k = e - l * nkx;
         const int ra = r0 + 2 * l, rb = ra + 1;
@@ -271,7 +300,7 @@ k_fft_x_fwd(const TI *__restrict__ in, const double *__restrict__ sinv, cplx<S> 
     }
 }
 
-template <class S, class TO>
+template <class S, class TO, bool R6>
 __global__ void __launch_bounds__(FFT_THREADS)
 k_fft_x_inv(const cplx<S> *__restrict__ in, const double *__restrict__ sinv, TO *__restrict__ out,
             Radices rd, const cplx<S> *__restrict__ tw, int lb, int nrows, int nkx, int ldc, Div dn) {
@@ -302,7 +331,7 @@ k_fft_x_inv(const cplx<S> *__restrict__ in, const double *__restrict__ sinv, TO 
         },
         tw, twl, n);
     __syncthreads();
-    fft_lines(lds, rd, lb, 1, ls, twl, true);
+    fft_lines<R6>(lds, rd, lb, 1, ls, twl, true);
     for (int e = threadIdx.x; e < B * n; e += FFT_THREADS) {
         const int l = udiv(e, dn), t = e - l * n;
         const int ra = r0 + 2 * l, rb = ra + 1;
@@ -340,7 +369,7 @@ inline int xcd_grid(int n) { return (n + 7) / 8 * 8; }
 // ---------------------------------------------------------------- y pass
 // Block (tile of B = 2^lb consecutive kx, plane z): lines along y, LDS
 // element (y, l) at y * B + l.
-template <class S>
+template <class S, bool R6>
 __global__ void __launch_bounds__(FFT_THREADS)
 k_fft_y(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ tw, int lb, int nkx, int ldc, int nz,
         int inv) {
@@ -362,7 +391,7 @@ k_fft_y(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ tw, int
         },
         [&](int e, C v) { lds[e] = v; }, tw, twl, ny);
     __syncthreads();
-    fft_lines(lds, rd, lb, B, 1, twl, inv != 0);
+    fft_lines<R6>(lds, rd, lb, B, 1, twl, inv != 0);
     for (int e = threadIdx.x; e < B * ny; e += FFT_THREADS) {
         const int y = e >> lb, l = e & bmask;
         if (l < bw) c[base + (size_t)y * ldc + l] = lds[e];
@@ -383,7 +412,7 @@ __device__ __forceinline__ float neg_recip(float d) { return -__builtin_amdgcn_r
 
 // Block (tile of B = 2^lb consecutive kx, row y): lines along z, LDS element
 // (z, l) at z * B + l.
-template <class S, int MAXE = FFT_MAXE, int NT = FFT_THREADS>
+template <class S, bool R6, int MAXE = FFT_MAXE, int NT = FFT_THREADS>
 __global__ void __launch_bounds__(NT)
 k_fft_z_green(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ tw, int lb, int nkx, int ldc, int ny,
               const S *__restrict__ lamx, const S *__restrict__ lamy, const S *__restrict__ lamz, S inv_n) {
@@ -406,7 +435,7 @@ k_fft_z_green(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ t
         },
         [&](int e, C v) { lds[e] = v; }, tw, twl, nz);
     __syncthreads();
-    fft_lines<C, MAXE, NT>(lds, rd, lb, B, 1, twl, false);
+    fft_lines<R6, C, MAXE, NT>(lds, rd, lb, B, 1, twl, false);
     const S ly = lamy[y];
     for (int e = threadIdx.x; e < B * nz; e += NT) {
         const int z = e >> lb, l = e & bmask;
@@ -417,7 +446,7 @@ k_fft_z_green(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ t
         lds[e] = mk<C>(v.x * g, v.y * g);
     }
     __syncthreads();
-    fft_lines<C, MAXE, NT>(lds, rd, lb, B, 1, twl, true);
+    fft_lines<R6, C, MAXE, NT>(lds, rd, lb, B, 1, twl, true);
     for (int e = threadIdx.x; e < B * nz; e += NT) {
         const int z = e >> lb, l = e & bmask;
         if (l < bw) c[base + (size_t)z * zstride + l] = lds[e];
@@ -437,17 +466,31 @@ void lds_attr(const void *fn, std::atomic<unsigned> &done, size_t bytes) {
 }
 template <class F> const void *fptr(F *f) { return reinterpret_cast<const void *>(f); }
 
-Radices radices_of(const FFTAxis &ax) {
+// The axis' stages; with no6 a radix-6 stage runs as a radix-3 stage in its
+// place and a radix-2 stage at the end (the plan of n without the pairing).
+Radices radices_of(const FFTAxis &ax, bool no6) {
+    std::vector<int> rs;
+    bool two = false;
+    for (int q : ax.radices) {
+        if (no6 && q == 6) {
+            rs.push_back(3);
+            two = true;
+        } else {
+            rs.push_back(q);
+        }
+    }
+    if (two) rs.push_back(2);
+    if ((int)rs.size() > MAX_STAGES) fail(DWP_EINVAL, "too many FFT stages");
     Radices r{};
     r.n = ax.n;
-    r.nst = (int)ax.radices.size();
+    r.nst = (int)rs.size();
     int p = 1;
     for (int s = 0; s < r.nst; ++s) {
-        r.r[s] = ax.radices[s];
+        r.r[s] = rs[s];
         r.p[s] = p;
         r.pm[s] = make_div(p).m;
-        r.tstride[s] = ax.n / (p * ax.radices[s]);
-        p *= ax.radices[s];
+        r.tstride[s] = ax.n / (p * rs[s]);
+        p *= rs[s];
     }
     return r;
 }
@@ -468,11 +511,19 @@ int tile_log2(int n, int budget) {
 void fft_plan_axis(FFTAxis &ax, int n, double h, bool half, int order) {
     ax.n = n;
     ax.radices.clear();
-    int m = n;
-    while (m % 3 == 0) { ax.radices.push_back(3); m /= 3; }
-    while (m % 8 == 0) { ax.radices.push_back(8); m /= 8; }
-    while (m % 4 == 0) { ax.radices.push_back(4); m /= 4; }
-    while (m % 2 == 0) { ax.radices.push_back(2); m /= 2; }
+    int m = n, a = 0, b = 0;
+    while (m % 3 == 0) { ++a; m /= 3; }
+    while (m % 2 == 0) { ++b; m /= 2; }
+    // radix 8 for the power of two as far as it goes; a lone factor 2 left
+    // over pairs with a factor 3 into one radix-6 stage (384 = 6 8 8: three
+    // stages instead of four) on lines short enough for one radix-6
+    // butterfly per thread of a block
+    const bool six = a > 0 && b % 3 == 1 && n <= 6 * FFT_THREADS;
+    for (int i = 0; i < a - (six ? 1 : 0); ++i) ax.radices.push_back(3);
+    if (six) ax.radices.push_back(6);
+    for (int i = 0; i < b / 3; ++i) ax.radices.push_back(8);
+    if (b % 3 == 2) ax.radices.push_back(4);
+    if (b % 3 == 1 && !six) ax.radices.push_back(2);
     if (m != 1 || (int)ax.radices.size() > MAX_STAGES) fail(DWP_EINVAL, "grid size must be 2^a 3^b");
     const long double pi = 3.141592653589793238462643383279502884L;
     std::vector<double2> tw(n);
@@ -523,50 +574,80 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
     auto pb = [&](int g) { return prof ? prof->begin(st, g) : -1; };
     auto pe = [&](int ev, int g, double b) { if (prof) prof->end(st, ev, g, b); };
     int ev;
+    // each pass in the variant with or without a radix-6 stage, as its axis'
+    // plan needs.  Float32 passes run a radix-6 stage as radix 3 and 2: the
+    // radix-6 variant's registers cost the float32 z pass a block per CU
+    // (measured 56 against 53 us a pass at 192 x 192 x 384), while the
+    // float64 z pass gains (86 against 93 us).
+    constexpr bool no6 = sizeof(S) == 4;
+    auto has6 = [](const FFTAxis &a) {
+        return !no6 && std::find(a.radices.begin(), a.radices.end(), 6) != a.radices.end();
+    };
+    auto RD = [&](const FFTAxis &a) { return radices_of(a, no6); };
+    // a pass with a radix-6 stage takes at most 6 values per thread in a block
+    auto budget = [&](const FFTAxis &a, int b, int nt) { return has6(a) ? std::min(b, 6 * nt) : b; };
+    auto with6 = [](bool six, auto &&f) {
+        if (six) f(std::true_type{});
+        else f(std::false_type{});
+    };
+    const int nrows = p.ny * p.nz;
+    const int lbx = tile_log2(p.nx, budget(ax, sizeof(S) == 4 ? FFT_BUDGET_X32 : FFT_BUDGET_X, FFT_THREADS));
+    const int Bx = 1 << lbx;
+    const int gx = (nrows + 2 * Bx - 1) / (2 * Bx);
+    const size_t ldsx = sizeof(C) * ((size_t)Bx * (p.nx + 1) + p.nx);
+    const Div dn = make_div(p.nx), dk = make_div(p.nkx);
+    const int lby = tile_log2(p.ny, budget(ay, FFT_BUDGET_Y, FFT_THREADS)), By = 1 << lby;
+    const int gy = xcd_grid((p.nkx + By - 1) / By * p.nz);
+    const size_t ldsy = sizeof(C) * ((size_t)By * p.ny + p.ny);
+    auto y_pass = [&](int inv) {
+        with6(has6(ay), [&](auto r6) {
+            constexpr bool R6 = decltype(r6)::value;
+            static std::atomic<unsigned> attr{0};
+            lds_attr(fptr(&k_fft_y<S, R6>), attr, ldsy);
+            k_fft_y<S, R6><<<gy, FFT_THREADS, ldsy, st>>>(cbuf, RD(ay), TW(ay), lby, p.nkx, p.ldc, p.nz, inv);
+            DWP_LAUNCH_CHECK();
+        });
+    };
+    ev = pb(PG_FFT_X);
+    with6(has6(ax), [&](auto r6) {
+        constexpr bool R6 = decltype(r6)::value;
+        static std::atomic<unsigned> attr{0};
+        lds_attr(fptr(&k_fft_x_fwd<S, TI, R6>), attr, ldsx);
+        k_fft_x_fwd<S, TI, R6><<<gx, FFT_THREADS, ldsx, st>>>(r, sinv, cbuf, RD(ax), TW(ax), lbx, nrows, p.nkx,
+                                                             p.ldc, dn, dk);
+        DWP_LAUNCH_CHECK();
+    });
+    pe(ev, PG_FFT_X, bx);
+    ev = pb(PG_FFT_Y);
+    y_pass(0);
+    pe(ev, PG_FFT_Y, 2.0 * cb * Cn);
     // z pass with the Green's function (lines of 8 kx; the twiddles follow
     // the lines in LDS)
-    auto z_pass = [&]() {
-        const int lbz = tile_log2(p.nz, FFT_Z_MAXE), Bz = 1 << lbz;
+    ev = pb(PG_FFT_Z);
+    with6(has6(az), [&](auto r6) {
+        constexpr bool R6 = decltype(r6)::value;
+        const int lbz = tile_log2(p.nz, budget(az, FFT_Z_MAXE, FFT_Z_THREADS)), Bz = 1 << lbz;
         const int gz = xcd_grid((p.nkx + Bz - 1) / Bz * p.ny);
         const size_t bytes = sizeof(C) * ((size_t)Bz * p.nz + p.nz);
         static std::atomic<unsigned> attr{0};
-        lds_attr(fptr(&k_fft_z_green<S, FFT_Z_MAXE, FFT_Z_THREADS>), attr, bytes);
-        k_fft_z_green<S, FFT_Z_MAXE, FFT_Z_THREADS><<<gz, FFT_Z_THREADS, bytes, st>>>(
-            cbuf, radices_of(az), TW(az), lbz, p.nkx, p.ldc, p.ny, LAM(ax), LAM(ay), LAM(az), (S)(1.0 / (double)p.N));
+        lds_attr(fptr(&k_fft_z_green<S, R6, FFT_Z_MAXE, FFT_Z_THREADS>), attr, bytes);
+        k_fft_z_green<S, R6, FFT_Z_MAXE, FFT_Z_THREADS><<<gz, FFT_Z_THREADS, bytes, st>>>(
+            cbuf, RD(az), TW(az), lbz, p.nkx, p.ldc, p.ny, LAM(ax), LAM(ay), LAM(az), (S)(1.0 / (double)p.N));
         DWP_LAUNCH_CHECK();
-    };
-    const int nrows = p.ny * p.nz;
-    const int lbx = tile_log2(p.nx, sizeof(S) == 4 ? FFT_BUDGET_X32 : FFT_BUDGET_X), Bx = 1 << lbx;
-    const int gx = (nrows + 2 * Bx - 1) / (2 * Bx);
-    const size_t ldsx = sizeof(C) * ((size_t)Bx * (p.nx + 1) + p.nx);
-    static std::atomic<unsigned> xf_attr{0}, xi_attr{0}, y_attr{0};
-    lds_attr(fptr(&k_fft_x_fwd<S, TI>), xf_attr, ldsx);
-    lds_attr(fptr(&k_fft_x_inv<S, TO>), xi_attr, ldsx);
-    const Div dn = make_div(p.nx), dk = make_div(p.nkx);
-    ev = pb(PG_FFT_X);
-    k_fft_x_fwd<S, TI><<<gx, FFT_THREADS, ldsx, st>>>(r, sinv, cbuf, radices_of(ax), TW(ax), lbx, nrows, p.nkx, p.ldc, dn,
-                                                  dk);
-    DWP_LAUNCH_CHECK();
-    pe(ev, PG_FFT_X, bx);
-    const int lby = tile_log2(p.ny, FFT_BUDGET_Y), By = 1 << lby;
-    const int gy = xcd_grid((p.nkx + By - 1) / By * p.nz);
-    const size_t ldsy = sizeof(C) * ((size_t)By * p.ny + p.ny);
-    lds_attr(fptr(&k_fft_y<S>), y_attr, ldsy);
-    ev = pb(PG_FFT_Y);
-    k_fft_y<S><<<gy, FFT_THREADS, ldsy, st>>>(cbuf, radices_of(ay), TW(ay), lby, p.nkx, p.ldc, p.nz, 0);
-    DWP_LAUNCH_CHECK();
-    pe(ev, PG_FFT_Y, 2.0 * cb * Cn);
-    ev = pb(PG_FFT_Z);
-    z_pass();
+    });
     pe(ev, PG_FFT_Z, 2.0 * cb * Cn);
     ev = pb(PG_FFT_Y);
-    k_fft_y<S><<<gy, FFT_THREADS, ldsy, st>>>(cbuf, radices_of(ay), TW(ay), lby, p.nkx, p.ldc, p.nz, 1);
-    DWP_LAUNCH_CHECK();
+    y_pass(1);
     pe(ev, PG_FFT_Y, 2.0 * cb * Cn);
     ev = pb(PG_FFT_X);
-    k_fft_x_inv<S, TO><<<gx, FFT_THREADS, ldsx, st>>>(cbuf, sinv, out, radices_of(ax), TW(ax), lbx, nrows, p.nkx,
-                                                      p.ldc, dn);
-    DWP_LAUNCH_CHECK();
+    with6(has6(ax), [&](auto r6) {
+        constexpr bool R6 = decltype(r6)::value;
+        static std::atomic<unsigned> attr{0};
+        lds_attr(fptr(&k_fft_x_inv<S, TO, R6>), attr, ldsx);
+        k_fft_x_inv<S, TO, R6><<<gx, FFT_THREADS, ldsx, st>>>(cbuf, sinv, out, RD(ax), TW(ax), lbx, nrows,
+                                                             p.nkx, p.ldc, dn);
+        DWP_LAUNCH_CHECK();
+    });
     pe(ev, PG_FFT_X, bxi);
 }
 

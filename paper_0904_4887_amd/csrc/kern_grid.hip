@@ -481,15 +481,17 @@ __global__ void __launch_bounds__(1024) k_resid_restrict_band(RestrictArgs<T> a,
 // w_m = 1/2 (eps_n + eps_m) / h_d^2.
 template <class T>
 __device__ __forceinline__ void level_sums(const T *__restrict__ u, const T *__restrict__ e,
-                                           const LevelArgs &a, int i, int j, size_t g, T &off,
+                                           const LevelArgs &a, int i, int j, int g, T &off,
                                            T &diag) {
-    const size_t plane = (size_t)a.nx * a.ny;
-    const size_t rowbase = g - (size_t)i;
-    const size_t xp = rowbase + wrap_p(i, a.nx), xm = rowbase + wrap_m(i, a.nx);
-    const size_t pbase = g - (size_t)j * a.nx;  // start of (plane, row 0) + i
-    const size_t yp = pbase + (size_t)wrap_p(j, a.ny) * a.nx;
-    const size_t ym = pbase + (size_t)wrap_m(j, a.ny) * a.nx;
-    const size_t zp = g + plane, zm = g - plane;
+    // 32-bit offsets: the levels that use this (the bottom of the V-cycle)
+    // hold a few thousand points
+    const int plane = a.nx * a.ny;
+    const int rowbase = g - i;
+    const int xp = rowbase + wrap_p(i, a.nx), xm = rowbase + wrap_m(i, a.nx);
+    const int pbase = g - j * a.nx;  // start of (plane, row 0) + i
+    const int yp = pbase + wrap_p(j, a.ny) * a.nx;
+    const int ym = pbase + wrap_m(j, a.ny) * a.nx;
+    const int zp = g + plane, zm = g - plane;
     const T e0 = e[g];
     const T cx = cxv<T>(a, 0), cy = cxv<T>(a, 1), cz = cxv<T>(a, 2);
     const T wxp = cx * (e0 + e[xp]), wxm = cx * (e0 + e[xm]);
@@ -1141,7 +1143,12 @@ struct LevelDesc {
     const T *e;
     LevelArgs a;
     int zc;
+    unsigned mh, mx, my;  // bt_div multipliers for nx / 2, nx, ny
 };
+// q / d through one multiply-high with m = floor((2^32 - 1) / d) + 1 (m = 0
+// for d = 1): exact whenever q d < 2^32, which holds on these levels.
+__device__ __forceinline__ int bt_div(int q, unsigned m) { return m ? (int)__umulhi((unsigned)q, m) : q; }
+inline unsigned bt_magic(int d) { return d > 1 ? 0xFFFFFFFFu / (unsigned)d + 1u : 0u; }
 constexpr int MAX_BOTTOM = 10;
 template <class T>
 struct Bottom {
@@ -1153,11 +1160,12 @@ template <class T>
 __device__ void bt_smooth(const LevelDesc<T> &d, int color) {
     const int half = d.a.nx / 2;
     const int per = half * d.a.ny * d.a.nw;
-    const size_t plane = (size_t)d.a.nx * d.a.ny;
+    const int plane = d.a.nx * d.a.ny;
     for (int q = threadIdx.x; q < per; q += blockDim.x) {
-        const int t = q % half, j = (q / half) % d.a.ny, kk = q / (half * d.a.ny);
+        const int qh = bt_div(q, d.mh), t = q - qh * half;
+        const int kk = bt_div(qh, d.my), j = qh - kk * d.a.ny;
         const int i = 2 * t + ((j + kk + color) & 1);
-        const size_t li = (size_t)kk * plane + (size_t)j * d.a.nx + i;
+        const int li = kk * plane + j * d.a.nx + i;
         T off, diag;
         level_sums(d.u, d.e, d.a, i, j, li + plane, off, diag);
         d.u[li + plane] = gs_value(off, d.f[li], diag);
@@ -1167,12 +1175,13 @@ __device__ void bt_smooth(const LevelDesc<T> &d, int color) {
 
 template <class T>
 __device__ void bt_residual(const LevelDesc<T> &d) {
-    const size_t plane = (size_t)d.a.nx * d.a.ny;
-    const int n = (int)(plane * d.a.nw);
+    const int plane = d.a.nx * d.a.ny;
+    const int n = plane * d.a.nw;
     for (int q = threadIdx.x; q < n; q += blockDim.x) {
-        const int i = q % d.a.nx, j = (q / d.a.nx) % d.a.ny;
+        const int qx = bt_div(q, d.mx), i = q - qx * d.a.nx;
+        const int j = qx - bt_div(qx, d.my) * d.a.ny;
         T off, diag;
-        level_sums(d.u, d.e, d.a, i, j, (size_t)q + plane, off, diag);
+        level_sums(d.u, d.e, d.a, i, j, q + plane, off, diag);
         d.r[q] = d.f[q] - (off - diag * d.u[q + plane]);
     }
     __syncthreads();
@@ -1182,18 +1191,20 @@ template <class T>
 __device__ void bt_restrict_zero(const LevelDesc<T> &F, const LevelDesc<T> &C) {
     const T w3[3] = {T(0.25), T(0.5), T(0.25)};
     const int nxf = F.a.nx, nyf = F.a.ny, nxc = C.a.nx, nyc = C.a.ny;
-    const size_t planef = (size_t)nxf * nyf, planec = (size_t)nxc * nyc;
-    const int n = (int)(planec * C.a.nw);
+    const int planef = nxf * nyf, planec = nxc * nyc;
+    const int n = planec * C.a.nw;
     for (int q = threadIdx.x; q < n; q += blockDim.x) {
-        const int ic = q % nxc, jc = (q / nxc) % nyc, kc = q / (int)planec;
+        const int qx = bt_div(q, C.mx), ic = q - qx * nxc;
+        const int kc = bt_div(qx, C.my), jc = qx - kc * nyc;
         T acc = T(0);
         const int nzt = C.zc ? 3 : 1;
         for (int dz = 0; dz < nzt; ++dz) {
             const int kf = C.zc ? 2 * kc + dz : kc;
             const T wz = C.zc ? w3[dz] : T(1);
             for (int dy = -1; dy <= 1; ++dy) {
-                const int jf = (2 * jc + dy + nyf) % nyf;
-                const size_t rb = (size_t)kf * planef + (size_t)jf * nxf;
+                const int jy = 2 * jc + dy;
+                const int jf = jy < 0 ? jy + nyf : (jy >= nyf ? jy - nyf : jy);
+                const int rb = kf * planef + jf * nxf;
                 const int i0 = 2 * ic;
                 const T sx = T(0.25) * F.r[rb + (i0 == 0 ? nxf - 1 : i0 - 1)] + T(0.5) * F.r[rb + i0] +
                              T(0.25) * F.r[rb + (i0 + 1 == nxf ? 0 : i0 + 1)];
@@ -1202,7 +1213,7 @@ __device__ void bt_restrict_zero(const LevelDesc<T> &F, const LevelDesc<T> &C) {
         }
         C.f[q] = acc;
     }
-    const int ng = (int)(planec * (C.a.nw + 2));
+    const int ng = planec * (C.a.nw + 2);
     for (int q = threadIdx.x; q < ng; q += blockDim.x) C.u[q] = T(0);
     __syncthreads();
 }
@@ -1210,10 +1221,11 @@ __device__ void bt_restrict_zero(const LevelDesc<T> &F, const LevelDesc<T> &C) {
 template <class T>
 __device__ void bt_prolong(const LevelDesc<T> &F, const LevelDesc<T> &C) {
     const int nxf = F.a.nx, nyf = F.a.ny, nxc = C.a.nx, nyc = C.a.ny;
-    const size_t planef = (size_t)nxf * nyf, planec = (size_t)nxc * nyc;
-    const int n = (int)(planef * F.a.nw);
+    const int planef = nxf * nyf, planec = nxc * nyc;
+    const int n = planef * F.a.nw;
     for (int q = threadIdx.x; q < n; q += blockDim.x) {
-        const int i = q % nxf, j = (q / nxf) % nyf, kf = q / (int)planef;
+        const int qx = bt_div(q, F.mx), i = q - qx * nxf;
+        const int kf = bt_div(qx, F.my), j = qx - kf * nyf;
         int ix[2], jy[2], pz[2];
         T wx[2], wyv[2], wz[2];
         int nxs, nys, nzs;
@@ -1229,7 +1241,7 @@ __device__ void bt_prolong(const LevelDesc<T> &F, const LevelDesc<T> &C) {
         for (int a = 0; a < nzs; ++a)
             for (int b = 0; b < nys; ++b)
                 for (int c = 0; c < nxs; ++c)
-                    acc += wz[a] * wyv[b] * wx[c] * C.u[(size_t)pz[a] * planec + (size_t)jy[b] * nxc + ix[c]];
+                    acc += wz[a] * wyv[b] * wx[c] * C.u[pz[a] * planec + jy[b] * nxc + ix[c]];
         F.u[q + planef] += acc;
     }
     __syncthreads();
@@ -1851,6 +1863,9 @@ void launch_vcycle_bottom(hipStream_t s, const std::vector<Level *> &levels, siz
         B.L[l].e = L.eps.as<T>();
         B.L[l].a = level_args(L);
         B.L[l].zc = L.zc ? 1 : 0;
+        B.L[l].mh = bt_magic(L.nx / 2);
+        B.L[l].mx = bt_magic(L.nx);
+        B.L[l].my = bt_magic(L.ny);
     }
     B.pre = pre;
     B.post = post;
