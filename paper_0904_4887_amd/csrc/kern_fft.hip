@@ -167,11 +167,14 @@ template <class C> struct DFT<8, C> {
 // radices of the earlier stages.  Butterfly i of a line reads
 // x_q = buf[i + q n/R], twiddles x_q by exp(-+2 pi i q (i mod p) / (p R)),
 // and writes output r to (i - i mod p) R + i mod p + r p.
-template <int R, class C, int MAXE, int NT>
+// IL: the lines are interleaved (es = B, ls = 1: element t of line l at
+// t B + l), so that work item w = i B + l reads x_q at w + q T B and writes
+// output r at ((i - k) R + k) B + l + r p B without per-element multiplies.
+template <int R, class C, int MAXE, int NT, bool IL>
 __device__ void stage(C *buf, int n, int p, unsigned pm, int tstride, int lb, int es, int ls,
                       const C *__restrict__ tw, bool inv) {
-    // a block whose plan holds a radix-6 stage has at most 6 NT values
-    // (r6_budget), so that the radix-6 stage is one butterfly per thread
+    // a block whose plan holds a radix-6 stage has at most 6 NT values (the
+    // host's tile budget), so that the radix-6 stage is one butterfly per thread
     constexpr int E = R == 6 && MAXE > 6 * NT ? 6 * NT : MAXE;
     constexpr int K = (E / R + NT - 1) / NT;
     const int T = n / R;
@@ -184,7 +187,7 @@ __device__ void stage(C *buf, int n, int p, unsigned pm, int tstride, int lb, in
         if (w < items) {
             const int l = w & bmask, i = w >> lb;
 #pragma unroll
-            for (int q = 0; q < R; ++q) x[m][q] = buf[l * ls + (i + q * T) * es];
+            for (int q = 0; q < R; ++q) x[m][q] = IL ? buf[w + q * items] : buf[l * ls + (i + q * T) * es];
         }
     }
     __syncthreads();
@@ -205,8 +208,12 @@ __device__ void stage(C *buf, int n, int p, unsigned pm, int tstride, int lb, in
             }
             DFT<R, C>::run(x[m], inv);
             const int j = (i - k) * R + k;
+            const int jb = (j << lb) + l, pb = p << lb;
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[l * ls + (j + r * p) * es] = x[m][r];
+            for (int r = 0; r < R; ++r) {
+                if (IL) buf[jb + r * pb] = x[m][r];
+                else buf[l * ls + (j + r * p) * es] = x[m][r];
+            }
         }
     }
     __syncthreads();
@@ -214,15 +221,15 @@ __device__ void stage(C *buf, int n, int p, unsigned pm, int tstride, int lb, in
 
 // R6: the plan may hold a radix-6 stage (a kernel built without it keeps the
 // registers the radix-6 stage would need)
-template <bool R6, class C, int MAXE = FFT_MAXE, int NT = FFT_THREADS>
+template <bool R6, bool IL, class C, int MAXE = FFT_MAXE, int NT = FFT_THREADS>
 __device__ void fft_lines(C *buf, const Radices &rd, int lb, int es, int ls, const C *__restrict__ tw, bool inv) {
     for (int s = 0; s < rd.nst; ++s) {
         const int R = rd.r[s];
-        if (R == 8) stage<8, C, MAXE, NT>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
-        else if (R6 && R == 6) stage<6, C, MAXE, NT>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
-        else if (R == 4) stage<4, C, MAXE, NT>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
-        else if (R == 3) stage<3, C, MAXE, NT>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
-        else stage<2, C, MAXE, NT>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
+        if (R == 8) stage<8, C, MAXE, NT, IL>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
+        else if (R6 && R == 6) stage<6, C, MAXE, NT, IL>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
+        else if (R == 4) stage<4, C, MAXE, NT, IL>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
+        else if (R == 3) stage<3, C, MAXE, NT, IL>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
+        else stage<2, C, MAXE, NT, IL>(buf, rd.n, rd.p[s], rd.pm[s], rd.tstride[s], lb, es, ls, tw, inv);
     }
 }
 
@@ -286,7 +293,7 @@ k_fft_x_fwd(const TI *__restrict__ in, const double *__restrict__ sinv, cplx<S> 
         },
         tw, twl, n);
     __syncthreads();
-    fft_lines<R6>(lds, rd, lb, 1, ls, twl, false);
+    fft_lines<R6, false>(lds, rd, lb, 1, ls, twl, false);
     for (int e = threadIdx.x; e < B * nkx; e += FFT_THREADS) {
         const int l = udiv(e, dk), k = e - l * nkx;
         const int ra = r0 + 2 * l, rb = ra + 1;
@@ -331,7 +338,7 @@ k_fft_x_inv(const cplx<S> *__restrict__ in, const double *__restrict__ sinv, TO 
         },
         tw, twl, n);
     __syncthreads();
-    fft_lines<R6>(lds, rd, lb, 1, ls, twl, true);
+    fft_lines<R6, false>(lds, rd, lb, 1, ls, twl, true);
     for (int e = threadIdx.x; e < B * n; e += FFT_THREADS) {
         const int l = udiv(e, dn), t = e - l * n;
         const int ra = r0 + 2 * l, rb = ra + 1;
@@ -369,10 +376,11 @@ inline int xcd_grid(int n) { return (n + 7) / 8 * 8; }
 // ---------------------------------------------------------------- y pass
 // Block (tile of B = 2^lb consecutive kx, plane z): lines along y, LDS
 // element (y, l) at y * B + l.
-template <class S, bool R6>
+// INV: the inverse transform (a template argument, so that the butterflies'
+// direction is fixed at compile time).
+template <class S, bool R6, bool INV>
 __global__ void __launch_bounds__(FFT_THREADS)
-k_fft_y(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ tw, int lb, int nkx, int ldc, int nz,
-        int inv) {
+k_fft_y(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ tw, int lb, int nkx, int ldc, int nz) {
     using C = cplx<S>;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     C *lds = reinterpret_cast<C *>(lds_raw);
@@ -391,7 +399,7 @@ k_fft_y(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ tw, int
         },
         [&](int e, C v) { lds[e] = v; }, tw, twl, ny);
     __syncthreads();
-    fft_lines<R6>(lds, rd, lb, B, 1, twl, inv != 0);
+    fft_lines<R6, true>(lds, rd, lb, B, 1, twl, INV);
     for (int e = threadIdx.x; e < B * ny; e += FFT_THREADS) {
         const int y = e >> lb, l = e & bmask;
         if (l < bw) c[base + (size_t)y * ldc + l] = lds[e];
@@ -435,7 +443,7 @@ k_fft_z_green(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ t
         },
         [&](int e, C v) { lds[e] = v; }, tw, twl, nz);
     __syncthreads();
-    fft_lines<R6, C, MAXE, NT>(lds, rd, lb, B, 1, twl, false);
+    fft_lines<R6, true, C, MAXE, NT>(lds, rd, lb, B, 1, twl, false);
     const S ly = lamy[y];
     for (int e = threadIdx.x; e < B * nz; e += NT) {
         const int z = e >> lb, l = e & bmask;
@@ -446,7 +454,7 @@ k_fft_z_green(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ t
         lds[e] = mk<C>(v.x * g, v.y * g);
     }
     __syncthreads();
-    fft_lines<R6, C, MAXE, NT>(lds, rd, lb, B, 1, twl, true);
+    fft_lines<R6, true, C, MAXE, NT>(lds, rd, lb, B, 1, twl, true);
     for (int e = threadIdx.x; e < B * nz; e += NT) {
         const int z = e >> lb, l = e & bmask;
         if (l < bw) c[base + (size_t)z * zstride + l] = lds[e];
@@ -466,31 +474,17 @@ void lds_attr(const void *fn, std::atomic<unsigned> &done, size_t bytes) {
 }
 template <class F> const void *fptr(F *f) { return reinterpret_cast<const void *>(f); }
 
-// The axis' stages; with no6 a radix-6 stage runs as a radix-3 stage in its
-// place and a radix-2 stage at the end (the plan of n without the pairing).
-Radices radices_of(const FFTAxis &ax, bool no6) {
-    std::vector<int> rs;
-    bool two = false;
-    for (int q : ax.radices) {
-        if (no6 && q == 6) {
-            rs.push_back(3);
-            two = true;
-        } else {
-            rs.push_back(q);
-        }
-    }
-    if (two) rs.push_back(2);
-    if ((int)rs.size() > MAX_STAGES) fail(DWP_EINVAL, "too many FFT stages");
+Radices radices_of(const FFTAxis &ax) {
     Radices r{};
     r.n = ax.n;
-    r.nst = (int)rs.size();
+    r.nst = (int)ax.radices.size();
     int p = 1;
     for (int s = 0; s < r.nst; ++s) {
-        r.r[s] = rs[s];
+        r.r[s] = ax.radices[s];
         r.p[s] = p;
         r.pm[s] = make_div(p).m;
-        r.tstride[s] = ax.n / (p * rs[s]);
-        p *= rs[s];
+        r.tstride[s] = ax.n / (p * ax.radices[s]);
+        p *= ax.radices[s];
     }
     return r;
 }
@@ -575,15 +569,9 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
     auto pe = [&](int ev, int g, double b) { if (prof) prof->end(st, ev, g, b); };
     int ev;
     // each pass in the variant with or without a radix-6 stage, as its axis'
-    // plan needs.  Float32 passes run a radix-6 stage as radix 3 and 2: the
-    // radix-6 variant's registers cost the float32 z pass a block per CU
-    // (measured 56 against 53 us a pass at 192 x 192 x 384), while the
-    // float64 z pass gains (86 against 93 us).
-    constexpr bool no6 = sizeof(S) == 4;
-    auto has6 = [](const FFTAxis &a) {
-        return !no6 && std::find(a.radices.begin(), a.radices.end(), 6) != a.radices.end();
-    };
-    auto RD = [&](const FFTAxis &a) { return radices_of(a, no6); };
+    // plan needs (the radix-6 code costs registers where it is not used)
+    auto has6 = [](const FFTAxis &a) { return std::find(a.radices.begin(), a.radices.end(), 6) != a.radices.end(); };
+    auto RD = [](const FFTAxis &a) { return radices_of(a); };
     // a pass with a radix-6 stage takes at most 6 values per thread in a block
     auto budget = [&](const FFTAxis &a, int b, int nt) { return has6(a) ? std::min(b, 6 * nt) : b; };
     auto with6 = [](bool six, auto &&f) {
@@ -599,12 +587,13 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
     const int lby = tile_log2(p.ny, budget(ay, FFT_BUDGET_Y, FFT_THREADS)), By = 1 << lby;
     const int gy = xcd_grid((p.nkx + By - 1) / By * p.nz);
     const size_t ldsy = sizeof(C) * ((size_t)By * p.ny + p.ny);
-    auto y_pass = [&](int inv) {
+    auto y_pass = [&](auto inv) {
+        constexpr bool INV = decltype(inv)::value;
         with6(has6(ay), [&](auto r6) {
             constexpr bool R6 = decltype(r6)::value;
             static std::atomic<unsigned> attr{0};
-            lds_attr(fptr(&k_fft_y<S, R6>), attr, ldsy);
-            k_fft_y<S, R6><<<gy, FFT_THREADS, ldsy, st>>>(cbuf, RD(ay), TW(ay), lby, p.nkx, p.ldc, p.nz, inv);
+            lds_attr(fptr(&k_fft_y<S, R6, INV>), attr, ldsy);
+            k_fft_y<S, R6, INV><<<gy, FFT_THREADS, ldsy, st>>>(cbuf, RD(ay), TW(ay), lby, p.nkx, p.ldc, p.nz);
             DWP_LAUNCH_CHECK();
         });
     };
@@ -619,7 +608,7 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
     });
     pe(ev, PG_FFT_X, bx);
     ev = pb(PG_FFT_Y);
-    y_pass(0);
+    y_pass(std::false_type{});
     pe(ev, PG_FFT_Y, 2.0 * cb * Cn);
     // z pass with the Green's function (lines of 8 kx; the twiddles follow
     // the lines in LDS)
@@ -637,7 +626,7 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
     });
     pe(ev, PG_FFT_Z, 2.0 * cb * Cn);
     ev = pb(PG_FFT_Y);
-    y_pass(1);
+    y_pass(std::true_type{});
     pe(ev, PG_FFT_Y, 2.0 * cb * Cn);
     ev = pb(PG_FFT_X);
     with6(has6(ax), [&](auto r6) {
