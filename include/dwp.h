@@ -142,6 +142,12 @@ typedef struct {
                            /* the residual more than 100-fold: there a float16 */
                            /* basis would limit the cycle, which runs on the   */
                            /* float32 basis.  0 = as krylov_fp32 says          */
+    double semi_ratio;     /* multigrid coarsening: a level halves z too only  */
+                           /* once hz <= semi_ratio * max(hx, hy) (before,     */
+                           /* only x and y: semi-coarsening for anisotropic    */
+                           /* spacing); 1..64, default sqrt(2).  A larger      */
+                           /* value coarsens z sooner: cheaper cycles, weaker  */
+                           /* where the wet solve limits the iteration count   */
 } dwp_opts;
 
 /* Per-solve report. */

@@ -35,7 +35,8 @@ class Opts(C.Structure):
                 ("cycles", C.c_int), ("scaled_dry", C.c_int), ("tol", C.c_double), ("max_outer", C.c_int),
                 ("restart", C.c_int), ("warm_start", C.c_int), ("profile", C.c_int),
                 ("smoother", C.c_int), ("fft_fp32", C.c_int), ("order", C.c_int), ("smooth6", C.c_int),
-                ("krylov_fp32", C.c_int), ("krylov_fp16", C.c_int)]
+                ("krylov_fp32", C.c_int), ("krylov_fp16", C.c_int),
+                ("semi_ratio", C.c_double)]
 
 
 class Info(C.Structure):

@@ -153,15 +153,15 @@ struct LevelDims {
 
 // Coarsening rule: x, y periodic, halved only while the child stays even (so
 // red-black colouring survives the wrap); z (Dirichlet) halved when the
-// interval count nw + 1 is even.  While hz > sqrt(2) max(hx, hy) only x, y are
-// coarsened (semi-coarsening for the anisotropic spacing).
-std::vector<LevelDims> plan_levels(int nx, int ny, int nw, const double h[3], int max_levels) {
+// interval count nw + 1 is even.  While hz > semi_ratio max(hx, hy) only x, y
+// are coarsened (semi-coarsening for the anisotropic spacing).
+std::vector<LevelDims> plan_levels(int nx, int ny, int nw, const double h[3], int max_levels, double semi_ratio) {
     std::vector<LevelDims> v;
     LevelDims L{nx, ny, nw, {h[0], h[1], h[2]}, false};
     v.push_back(L);
     while ((int)v.size() < max_levels && (long)L.nx * L.ny * L.nw > COARSE_TARGET) {
         const double hxy = std::max(L.h[0], L.h[1]);
-        const bool semi = L.h[2] > std::sqrt(2.0) * hxy;
+        const bool semi = L.h[2] > semi_ratio * hxy;
         const bool can_xy = L.nx % 4 == 0 && L.ny % 4 == 0;
         const bool can_z = (L.nw + 1) % 2 == 0 && (L.nw + 1) / 2 - 1 >= 1;
         if (!can_xy) break;
@@ -219,10 +219,10 @@ void choose_wet(int nx, int ny, int nz, const double h[3], const double L[3], co
     if (nw0 < 3) fail(DWP_EINVAL, "wet region must hold at least 3 planes");
     if (nw0 > nz - 1) fail(DWP_EINVAL, "wet region must leave at least one dry plane");
     int best_nw = nw0;
-    long best = coarsest_size(plan_levels(nx, ny, nw0, h, o.max_levels));
+    long best = coarsest_size(plan_levels(nx, ny, nw0, h, o.max_levels, o.semi_ratio));
     const int limit = std::min(nz - 1, nw0 + std::max(1, nz / 8));
     for (int nw = nw0; nw <= limit; ++nw) {
-        const long cs = coarsest_size(plan_levels(nx, ny, nw, h, o.max_levels));
+        const long cs = coarsest_size(plan_levels(nx, ny, nw, h, o.max_levels, o.semi_ratio));
         if (cs < best) { best = cs; best_nw = nw; }
         if (cs <= COARSE_TARGET) { best_nw = nw; break; }
     }
@@ -238,7 +238,7 @@ void plan_wet(dwp_ctx *c) {
     Plan &p = c->plan;
     choose_wet(p.nx, p.ny, p.nz, p.h, p.L, c->opts, &p.k_w0, &p.k_w1, &p.nw);
     free_levels(c);
-    for (const LevelDims &d : plan_levels(p.nx, p.ny, p.nw, p.h, c->opts.max_levels)) {
+    for (const LevelDims &d : plan_levels(p.nx, p.ny, p.nw, p.h, c->opts.max_levels, c->opts.semi_ratio)) {
         Level *L = new Level();
         L->nx = d.nx; L->ny = d.ny; L->nw = d.nw;
         L->h[0] = d.h[0]; L->h[1] = d.h[1]; L->h[2] = d.h[2];
@@ -733,6 +733,7 @@ void validate_opts(const dwp_opts &o) {
         fail(DWP_EINVAL, "krylov_fp32 with the sixth-order operator needs cycles = 0 (the FFT dry update alone)");
     if (o.krylov_fp32 && o.restart > 16) fail(DWP_EINVAL, "krylov_fp32 takes restart lengths up to 16");
     if (o.krylov_fp16 != 0 && o.krylov_fp16 != 1) fail(DWP_EINVAL, "krylov_fp16 must be 0 or 1");
+    if (!(o.semi_ratio >= 1.0 && o.semi_ratio <= 64.0)) fail(DWP_EINVAL, "semi_ratio must lie in [1, 64]");
     if (o.krylov_fp16 && (o.krylov_fp32 != 1 || o.order != 2))
         fail(DWP_EINVAL, "krylov_fp16 needs krylov_fp32 = 1 and the second-order operator");
 }
@@ -884,7 +885,7 @@ void set_opts_impl(dwp_ctx *c, const dwp_opts *o) {
         }
         if (o->krylov_fp32) c->V32.alloc(sizeof(float) * c->plan.N * (o->restart + 1));
         const bool replan = o->z_wet_lo != old.z_wet_lo || o->z_wet_hi != old.z_wet_hi ||
-                            o->max_levels != old.max_levels ||
+                            o->max_levels != old.max_levels || o->semi_ratio != old.semi_ratio ||
                             (std::isnan(o->z_wet_lo) != std::isnan(old.z_wet_lo)) ||
                             (std::isnan(o->z_wet_hi) != std::isnan(old.z_wet_hi));
         if (replan) plan_wet(c);
@@ -1332,6 +1333,7 @@ void dwp_default_opts(dwp_opts *o) {
     o->smooth6 = 0;
     o->krylov_fp32 = 0;
     o->krylov_fp16 = 0;
+    o->semi_ratio = std::sqrt(2.0);
 }
 
 int dwp_create(dwp_ctx **out, int device, void *stream) {
@@ -1579,7 +1581,7 @@ int dwp_plan(int nx, int ny, int nz, double Lx, double Ly, double Lz, const dwp_
         const double h[3] = {Lx / nx, Ly / ny, Lz / nz};
         int k0, k1, nw;
         dwp::choose_wet(nx, ny, nz, h, L, opts, &k0, &k1, &nw);
-        const auto lv = dwp::plan_levels(nx, ny, nw, h, opts.max_levels);
+        const auto lv = dwp::plan_levels(nx, ny, nw, h, opts.max_levels, opts.semi_ratio);
         if (!out || out_len < 3 + 3 * (int)lv.size()) dwp::fail(DWP_EINVAL, "output array too short");
         out[0] = k0;
         out[1] = k1;

@@ -22,7 +22,7 @@ def test_default_opts():
     assert math.isnan(o.z_wet_lo) and math.isnan(o.z_wet_hi)
     assert o.tol == 1e-10 and o.restart == 10 and o.warm_start == 0 and o.profile == 0
     assert o.smoother == 1 and o.fft_fp32 == 0 and o.order == 2 and o.smooth6 == 0 and o.krylov_fp32 == 0
-    assert o.krylov_fp16 == 0
+    assert o.krylov_fp16 == 0 and o.semi_ratio == math.sqrt(2.0)
 
 
 @pytest.mark.parametrize("n", [(30, 32, 64), (32, 32, 6), (32, 32, 70), (32, 32, 8192), (33, 32, 64)])
@@ -42,7 +42,8 @@ def test_plan_rejects_bad_grid_sizes(n):
                                 dict(krylov_fp32=1, precision=1, order=6),
                                 dict(krylov_fp32=1, precision=1, restart=17),
                                 dict(krylov_fp16=2), dict(krylov_fp16=1, precision=1),
-                                dict(krylov_fp16=1, krylov_fp32=1, precision=1, order=6, cycles=0)])
+                                dict(krylov_fp16=1, krylov_fp32=1, precision=1, order=6, cycles=0),
+                                dict(semi_ratio=0.5), dict(semi_ratio=65.0), dict(semi_ratio=float("nan"))])
 def test_plan_rejects_bad_options(kw):
     with pytest.raises(B.DWPError) as e:
         B.plan((32, 32, 64), (10.0, 10.0, 20.0), **kw)
@@ -69,6 +70,12 @@ def test_plan_wet_slab_and_hierarchy():
     assert all(l[0] % 2 == 0 and l[1] % 2 == 0 for l in p["levels"])
     last = p["levels"][-1]
     assert last[0] * last[1] * last[2] <= 1024
+    # semi_ratio 2 > 1.69: every coarsening halves z too (the levels' z
+    # interval counts halve: nw + 1 -> (nw + 1) / 2)
+    q = B.plan(w.n, w.L, z_wet_lo=w.z_wet[0], z_wet_hi=w.z_wet[1], semi_ratio=2.0)
+    assert q["levels"][0] == p["levels"][0]
+    assert all(c[2] + 1 == (f[2] + 1) // 2 for f, c in zip(q["levels"], q["levels"][1:]))
+    assert q["levels"][1][2] < p["levels"][1][2]
     # a wet slab that wraps through z = 0
     p = B.plan((32, 32, 64), (10.0, 10.0, 20.0), z_wet_lo=8.0, z_wet_hi=20.0 + 2 * 20.0 / 64)
     assert p["k_w1"] == 66 and p["k_w1"] - p["k_w0"] == p["levels"][0][2]
