@@ -36,9 +36,13 @@ template <> struct ApplyVec<double> {
     typedef double V __attribute__((ext_vector_type(2)));
 };
 
+template <class T, int W> struct ApplyVecOf {
+    typedef T V __attribute__((ext_vector_type(W)));
+};
+
 template <class TS, class TB> struct ApplyArgs {
     const TS *phi, *eps;  // box arrays, nz planes of nx * ny
-    const TB *b;          // MODE 1, 2: box array
+    const TB *b;          // MODE 1, 2: box array (float16 under a float32 phi)
     TS *out;              // MODE 0, 1: box array; MODE 2: nplanes planes
     int nx, ny, nz, k_w0, nplanes;
     int ty, bands, kc;
@@ -52,6 +56,7 @@ template <int MODE, class TS, class TB>
 struct BandApply {
     typedef typename ApplyVec<TS>::V V;
     static constexpr int W = ApplyVec<TS>::W;
+    typedef typename ApplyVecOf<TB, W>::V VB;  // W values of b
 
     ApplyArgs<TS, TB> a;
     int j0, kk0, kk1, base;
@@ -61,7 +66,8 @@ struct BandApply {
     bool out_row;
     unsigned ou;  // element offset of the thread's vector in a plane
     // planes kk - 1, kk, kk + 1 of phi and eps; b of plane kk; set kk + 2 in flight
-    V P0, P1, P2, E0, E1, E2, NB, QP, QE, QB;
+    V P0, P1, P2, E0, E1, E2, QP, QE;
+    VB NB, QB;
 
     __host__ __device__ __forceinline__ void init(const ApplyArgs<TS, TB> &args, TS *lds, int band, int chunk,
                                                   int tid) {
@@ -101,8 +107,8 @@ struct BandApply {
             const int qb = q - 1 > kk1 - 1 ? kk1 - 1 : q - 1;
             const size_t o = boxp(qb) + ou;
             BAND_CHECK(o + W - 1, (size_t)a.nz * plane);
-            static_assert(std::is_same<TB, TS>::value, "b is stored like phi");
-            QB = *(const V *)(a.b + o);
+            static_assert(std::is_same<TB, TS>::value || sizeof(TB) < sizeof(TS), "b is stored like phi or narrower");
+            QB = *(const VB *)(a.b + o);
         }
     }
     __host__ __device__ __forceinline__ void stash(int q, const V &p, const V &e) {

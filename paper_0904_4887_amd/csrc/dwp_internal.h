@@ -234,6 +234,10 @@ void launch_wet_residual(hipStream_t s, const Plan &p, const double *v, const do
 template <class T>
 void launch_wet_residual_v32(hipStream_t s, const Plan &p, const float *v, const float *dD, const float *eps,
                              T *fW);
+// the same for a float16 Krylov basis vector v
+template <class T>
+void launch_wet_residual_v16(hipStream_t s, const Plan &p, const _Float16 *v, const float *dD, const float *eps,
+                             T *fW);
 // out = A phi rounded to float32 for float32 phi and eps (a float32 Krylov
 // basis vector; float64 arithmetic)
 void launch_apply_full_f32(hipStream_t s, const Plan &p, const float *phi, const float *eps, float *out);
@@ -314,6 +318,10 @@ void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const
 void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay,
                          const FFTAxis &az, const float *r, const double *sinv, void *cbuf,
                          float *out, Profiler *prof, bool fp32);
+// and from a float16 one
+void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay,
+                         const FFTAxis &az, const _Float16 *r, const double *sinv, void *cbuf,
+                         float *out, Profiler *prof, bool fp32);
 
 // kern_blas.hip: deterministic reductions
 void launch_dot(hipStream_t s, const double *x, const double *y, size_t n, double *partial,
@@ -357,9 +365,10 @@ void launch_scale_to32(hipStream_t s, float *x32, const double *r, const double 
 bool krylov16_supported(const void *V, size_t ldv, size_t n);
 void launch_multidot16(hipStream_t s, const _Float16 *V, size_t ldv, int nv, const float *w, size_t n,
                        double *partial, double *out, double *norm_out);
-// w <- (w - sum_q h_q V_q) / beta in float32, and into vn (float16)
-void launch_orth_update16(hipStream_t s, float *w, _Float16 *vn, const _Float16 *V, size_t ldv, int nv, double *hc,
-                          size_t n, double *partial);
+// vn <- (w - sum_q h_q V_q) / beta in float16 (w read in float32, not written)
+void launch_orth_update16(hipStream_t s, const float *w, _Float16 *vn, const _Float16 *V, size_t ldv, int nv,
+                          double *hc, size_t n, double *partial);
+// xh = r / sqrt(*den_sq) in float16 (and in float32 into x32 unless null)
 void launch_scale_to16(hipStream_t s, float *x32, _Float16 *xh, const double *r, const double *den_sq, size_t n);
 // x += sum_q c[q] Z_q with float32 Z_q (nv <= 16), float64 x and sums
 void launch_axpy_multi32(hipStream_t s, double *x, const float *Z, size_t ldz, int nv, const double *c, size_t n);

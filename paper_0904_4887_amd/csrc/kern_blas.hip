@@ -284,12 +284,11 @@ k_orth_update4f(float *__restrict__ w, const float *__restrict__ V, size_t ldv, 
 }
 
 // The projection and update for a float16 Krylov basis: V in float16 (eight
-// per 16-byte load), the new vector w in float32 (the one the preconditioner
-// reads).  The products and the sums over a thread's eight points are float32
-// (a float16 value times a float32 one rounds at 2^-24 relative, far below the
-// basis' own 2^-11), everything summed over points is float64.  The update
-// writes the normalised vector twice: into the basis (float16) and back into
-// w (float32).
+// per 16-byte load), the new vector w = A z in float32.  The products and the
+// sums over a thread's eight points are float32 (a float16 value times a
+// float32 one rounds at 2^-24 relative, far below the basis' own 2^-11),
+// everything summed over points is float64.  The update writes the normalised
+// vector into the basis only: the preconditioner reads it from there.
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f8 __attribute__((ext_vector_type(8)));
 
@@ -329,7 +328,7 @@ k_multidot8h(const _Float16 *__restrict__ V, size_t ldv, int v0, const float *__
 
 template <int NV>
 __global__ void __launch_bounds__(RED_THREADS)
-k_orth_update8h(float *__restrict__ w, _Float16 *__restrict__ vn, const _Float16 *__restrict__ V, size_t ldv,
+k_orth_update8h(const float *__restrict__ w, _Float16 *__restrict__ vn, const _Float16 *__restrict__ V, size_t ldv,
                 const double *__restrict__ hc, size_t n8, double *__restrict__ partial, double *__restrict__ beta_out) {
     __shared__ double sh[1][RED_THREADS / 64];
     __shared__ double cs[NV + 1];
@@ -348,7 +347,7 @@ k_orth_update8h(float *__restrict__ w, _Float16 *__restrict__ vn, const _Float16
     float csf[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) csf[q] = (float)cs[q];
-    f8 *w8 = reinterpret_cast<f8 *>(w);
+    const f8 *w8 = reinterpret_cast<const f8 *>(w);
     h8 *vn8 = reinterpret_cast<h8 *>(vn);
     double nrm[1] = {0.0};
     for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n8; t += (size_t)gridDim.x * RED_THREADS) {
@@ -374,18 +373,17 @@ k_orth_update8h(float *__restrict__ w, _Float16 *__restrict__ vn, const _Float16
             nr = __builtin_fmaf(o[e], o[e], nr);
         }
         nrm[0] += (double)nr;
-        w8[t] = o;
         vn8[t] = oh;
     }
     block_sums<1>(nrm, sh, res);
     if (threadIdx.x == 0) partial[blockIdx.x] = res[0];
 }
 
-// As k_rescale_if_f for the float32 copy x, rewriting the float16 basis
-// vector xh from it when it is rescaled.
+// As k_rescale_if_f for the float16 basis vector xh (rescaled from its own
+// float16 values: the rare cancellation case pays one more rounding).
 __global__ void __launch_bounds__(RED_THREADS)
-k_rescale_if_fh(float *__restrict__ x, _Float16 *__restrict__ xh, const double *__restrict__ partial, int nparts,
-                double *__restrict__ nu2, size_t n) {
+k_rescale_if_fh(_Float16 *__restrict__ xh, const double *__restrict__ partial, int nparts, double *__restrict__ nu2,
+                size_t n) {
     __shared__ double sh[RED_THREADS / 64];
     __shared__ double tot;
     double v = 0.0;
@@ -399,21 +397,18 @@ k_rescale_if_fh(float *__restrict__ x, _Float16 *__restrict__ xh, const double *
     const double nu = sqrt(tot);
     if (nu == 0.0 || fabs(nu - 1.0) <= RESCALE_TOL_F32) return;
     const double s = 1.0 / nu;
-    for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n; t += (size_t)gridDim.x * RED_THREADS) {
-        const float y = (float)((double)x[t] * s);
-        x[t] = y;
-        xh[t] = (_Float16)y;
-    }
+    for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n; t += (size_t)gridDim.x * RED_THREADS)
+        xh[t] = (_Float16)((double)xh[t] * s);
 }
 
-// x32 = r / sqrt(*den_sq) rounded to float32, and xh the same rounded on to
-// float16 (0 when *den_sq is 0)
+// xh = r / sqrt(*den_sq) rounded to float32 and on to float16 (0 when
+// *den_sq is 0), and the float32 value into x32 unless it is null
 __global__ void k_scale_to_fh(float *__restrict__ x32, _Float16 *__restrict__ xh, const double *__restrict__ r,
                               const double *__restrict__ den_sq, size_t n) {
     const double s = *den_sq > 0.0 ? 1.0 / sqrt(*den_sq) : 0.0;
     for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n; t += (size_t)gridDim.x * RED_THREADS) {
         const float y = (float)(r[t] * s);
-        x32[t] = y;
+        if (x32) x32[t] = y;
         xh[t] = (_Float16)y;
     }
 }
@@ -858,8 +853,8 @@ void launch_multidot16(hipStream_t s, const _Float16 *V, size_t ldv, int nv, con
     DWP_LAUNCH_CHECK();
 }
 
-void launch_orth_update16(hipStream_t s, float *w, _Float16 *vn, const _Float16 *V, size_t ldv, int nv, double *hc,
-                          size_t n, double *partial) {
+void launch_orth_update16(hipStream_t s, const float *w, _Float16 *vn, const _Float16 *V, size_t ldv, int nv,
+                          double *hc, size_t n, double *partial) {
     if (nv < 1 || nv > 16 || !oct_ok(V, ldv, n) || !oct_ok(vn, 0, n) || !oct_ok(w, 0, n))
         fail(DWP_EINVAL, "internal: float16 orth update layout");
     switch (nv) {
@@ -870,7 +865,7 @@ void launch_orth_update16(hipStream_t s, float *w, _Float16 *vn, const _Float16 
 #undef DWP_OU8_CASE
     }
     DWP_LAUNCH_CHECK();
-    k_rescale_if_fh<<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, vn, partial, RED_BLOCKS, hc + 65, n);
+    k_rescale_if_fh<<<RED_BLOCKS, RED_THREADS, 0, s>>>(vn, partial, RED_BLOCKS, hc + 65, n);
     DWP_LAUNCH_CHECK();
 }
 

@@ -650,5 +650,10 @@ void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const
     if (fp32) vacuum_solve_t<float, float, float>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
     else vacuum_solve_t<double, float, float>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
 }
+void launch_vacuum_solve(hipStream_t st, const Plan &p, const FFTAxis &ax, const FFTAxis &ay, const FFTAxis &az,
+                         const _Float16 *r, const double *sinv, void *cbuf, float *out, Profiler *prof, bool fp32) {
+    if (fp32) vacuum_solve_t<float, _Float16, float>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
+    else vacuum_solve_t<double, _Float16, float>(st, p, ax, ay, az, r, sinv, cbuf, out, prof);
+}
 
 }  // namespace dwp

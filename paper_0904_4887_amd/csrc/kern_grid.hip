@@ -126,6 +126,11 @@ __device__ __forceinline__ double2 ld2(const float *base, unsigned o) {
     const float2 v = ld_at((const float2 *)base, o * 4u);
     return make_double2(v.x, v.y);
 }
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld2(const _Float16 *base, unsigned o) {
+    const half2v v = ld_at((const half2v *)base, o * 2u);
+    return make_double2((double)v[0], (double)v[1]);
+}
 
 template <class T, int MODE, class TB, class TP, class TE>
 __global__ void __launch_bounds__(256)
@@ -1449,7 +1454,7 @@ void launch_zmarch(hipStream_t s, const Plan &p, const TP *phi, const TE *eps, c
                    int nplanes) {
     // row bands where phi, eps and out share one storage type (and b too)
     if constexpr (std::is_same<TP, TE>::value && std::is_same<T, TP>::value &&
-                  (MODE == 0 || std::is_same<TB, TP>::value)) {
+                  (MODE == 0 || std::is_same<TB, TP>::value || sizeof(TB) < sizeof(TP))) {
         if (apply_band<MODE, T, TB>(s, p, phi, eps, b, out, nplanes)) return;
     }
     const bool tile_ok = p.nx % 2 == 0 && al16(phi) && al16(eps) && (MODE == 0 || al16(b)) && al16(out);
@@ -1557,6 +1562,11 @@ template <class T>
 void launch_wet_residual_v32(hipStream_t s, const Plan &p, const float *v, const float *dD, const float *eps,
                              T *fW) {
     launch_zmarch<T, 2, float, float, float>(s, p, dD, eps, v, fW, p.nw);
+}
+template <class T>
+void launch_wet_residual_v16(hipStream_t s, const Plan &p, const _Float16 *v, const float *dD, const float *eps,
+                             T *fW) {
+    launch_zmarch<T, 2, _Float16, float, float>(s, p, dD, eps, v, fW, p.nw);
 }
 void launch_apply_full_f32(hipStream_t s, const Plan &p, const float *phi, const float *eps, float *out) {
     launch_zmarch<float, 0, double, float, float>(s, p, phi, eps, (const double *)nullptr, out, p.nz);
@@ -1912,6 +1922,8 @@ void launch_zero(hipStream_t s, T *x, size_t n) {
     template void launch_wet_residual<T>(hipStream_t, const Plan &, const double *, const double *,  \
                                          const double *, T *);                                      \
     template void launch_wet_residual_v32<T>(hipStream_t, const Plan &, const float *, const float *,   \
+                                             const float *, T *);                                        \
+    template void launch_wet_residual_v16<T>(hipStream_t, const Plan &, const _Float16 *, const float *, \
                                              const float *, T *);                                        \
     template void launch_wet_add<T>(hipStream_t, const Plan &, const T *, double *);                  \
     template void launch_wet_add<T>(hipStream_t, const Plan &, const T *, float *);                   \

@@ -423,7 +423,10 @@ void split_impl(dwp_ctx *c, const TV *v, TZ *z) {
     }
     Level &F = *p.levels[0];
     const double nW = (double)F.n_interior();
-    if constexpr (sizeof(TV) == 4) {
+    if constexpr (std::is_same<TV, _Float16>::value) {
+        PROF(c, PG_WET, (6.0 + sizeof(TZ) + sizeof(T)) * nW,
+             launch_wet_residual_v16<T>(s, p, v, z, c->eps32.as<float>(), F.f.as<T>()));
+    } else if constexpr (sizeof(TV) == 4) {
         PROF(c, PG_WET, (8.0 + sizeof(TZ) + sizeof(T)) * nW,
              launch_wet_residual_v32<T>(s, p, v, z, c->eps32.as<float>(), F.f.as<T>()));
     } else if (c->opts.order == 6) {
@@ -443,10 +446,11 @@ void apply_split(dwp_ctx *c, const double *v, double *z) {
     if (c->opts.precision == DWP_MIXED) split_impl<float, double, double>(c, v, z);
     else split_impl<double, double, double>(c, v, z);
 }
-// the split of a float32 Krylov vector into a float32 one (mixed precision,
-// second order): z is rounded to float32 where it is stored, and the Krylov
-// method uses the stored z as it is
+// the split of a float32 (float16) Krylov vector into a float32 one (mixed
+// precision, second order): z is rounded to float32 where it is stored, and
+// the Krylov method uses the stored z as it is
 void apply_split(dwp_ctx *c, const float *v, float *z) { split_impl<float, float, float>(c, v, z); }
+void apply_split(dwp_ctx *c, const _Float16 *v, float *z) { split_impl<float, _Float16, float>(c, v, z); }
 
 void check_finite_dev(dwp_ctx *c, const double *x, const char *what) {
     int *flags = reinterpret_cast<int *>(c->partial.as<double>());
@@ -515,8 +519,8 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
     float *V32 = c->V32.as<float>();
     float *Z32 = c->Z.as<float>();  // with v32 the Z buffer holds float32 vectors
     // krylov_fp16 (second order): the V32 buffer holds the basis in float16
-    // and, after it, the current vector in float32 (the preconditioner's input
-    // and the new vector w of each step)
+    // and, after it, the new vector w = A z of each step in float32; the
+    // preconditioner reads the float16 basis vector
     const size_t v16_bytes = (sizeof(_Float16) * N * (m + 1) + 255) / 256 * 256;
     _Float16 *V16 = reinterpret_cast<_Float16 *>(V32);
     float *vcur = reinterpret_cast<float *>(reinterpret_cast<char *>(V32) + v16_bytes);
@@ -556,7 +560,7 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
         ++*restarts;
         v16 = v16_ok && beta_prev > 0.0 && beta * V16_MAX_REDUCTION >= beta_prev;
         beta_prev = beta;
-        if (v16) PROF(c, PG_VEC, 14.0 * N, launch_scale_to16(s, vcur, V16, r0, beta2, N));
+        if (v16) PROF(c, PG_VEC, 10.0 * N, launch_scale_to16(s, nullptr, V16, r0, beta2, N));
         else if (v32) PROF(c, PG_VEC, 12.0 * N, launch_scale_to32(s, V32, r0, beta2, N));
         else PROF(c, PG_VEC, 16.0 * N, launch_scale_dev(s, V, nullptr, beta2, N, 0));
         const int mm = std::min(m, o.max_outer - iters);
@@ -607,16 +611,16 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
             double *Vj = V + (size_t)j * N, *Vn = V + (size_t)(j + 1) * N, *Zj = Z + (size_t)j * N;
             double *hc = Hd + (size_t)j * HESS_STRIDE;
             if (v16) {
-                // v_j in float32 (vcur) -> z_j; w = A z_j into vcur; project
-                // on the float16 basis; the normalised vector into the basis
-                // and into vcur
+                // v_j (float16) -> z_j; w = A z_j into vcur (float32);
+                // project on the float16 basis; the normalised vector into
+                // the basis
                 float *Zj32 = Z32 + (size_t)j * N;
-                apply_split(c, (const float *)vcur, Zj32);
+                apply_split(c, (const _Float16 *)(V16 + (size_t)j * N), Zj32);
                 fused[j] = 1;
                 PROF(c, PG_APPLY, 12.0 * N, launch_apply_full_f32(s, p, (const float *)Zj32, c->eps32.as<float>(), vcur));
                 PROF(c, PG_MULTIDOT, (2.0 * (j + 1) + 4.0) * N,
                      launch_multidot16(s, V16, N, j + 1, vcur, N, part, hc, hc + 64));
-                PROF(c, PG_AXPY, (2.0 * (j + 1) + 10.0) * N,
+                PROF(c, PG_AXPY, (2.0 * (j + 1) + 6.0) * N,
                      launch_orth_update16(s, vcur, V16 + (size_t)(j + 1) * N, V16, N, j + 1, hc, N, part));
             } else if (v32) {
                 float *Vj32 = V32 + (size_t)j * N, *Vn32 = V32 + (size_t)(j + 1) * N, *Zj32 = Z32 + (size_t)j * N;
