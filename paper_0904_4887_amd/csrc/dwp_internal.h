@@ -348,6 +348,8 @@ bool krylov32_supported(const float *V, size_t ldv, size_t n);
 // the float32 orth update rescales its result to unit norm only when that norm
 // is off 1 by more than this (float64 vectors: 1e-8)
 constexpr double RESCALE_TOL_F32 = 1e-6;
+// Hessenberg column slot of the float16 basis' Gram row (see launch_multidot16)
+constexpr int GRAM_SLOT = 20;
 void launch_multidot32(hipStream_t s, const float *V, size_t ldv, int nv, const float *w, size_t n, double *partial,
                        double *out, double *norm_out);
 void launch_orth_update32(hipStream_t s, float *w, const float *V, size_t ldv, int nv, double *hc, size_t n,
@@ -363,11 +365,16 @@ void launch_scale_to32(hipStream_t s, float *x32, const double *r, const double 
 // input); projections and update in float64 arithmetic (n and ldv multiples
 // of 8, 16-byte aligned)
 bool krylov16_supported(const void *V, size_t ldv, size_t n);
+// (nv <= 16; with gram_out, also the last vector's products with V_0..V_{nv-1}
+// into gram_out[0..nv), the row of the basis' Gram matrix that the update of
+// a float16 basis divides by)
 void launch_multidot16(hipStream_t s, const _Float16 *V, size_t ldv, int nv, const float *w, size_t n,
-                       double *partial, double *out, double *norm_out);
-// vn <- (w - sum_q h_q V_q) / beta in float16 (w read in float32, not written)
+                       double *partial, double *out, double *norm_out, double *gram_out);
+// vn <- (w - sum_q h_q V_q) / beta in float16 (w read in float32, not written),
+// beta the exact norm of w - V h through the basis' Gram matrix, whose row q
+// the projection pass of step q left in Hessenberg column q (hd0 + q hstride)
 void launch_orth_update16(hipStream_t s, const float *w, _Float16 *vn, const _Float16 *V, size_t ldv, int nv,
-                          double *hc, size_t n, double *partial);
+                          double *hc, const double *hd0, int hstride, size_t n);
 // xh = r / sqrt(*den_sq) in float16 (and in float32 into x32 unless null)
 void launch_scale_to16(hipStream_t s, float *x32, _Float16 *xh, const double *r, const double *den_sq, size_t n);
 // x += sum_q c[q] Z_q with float32 Z_q (nv <= 16), float64 x and sums

@@ -284,25 +284,41 @@ k_orth_update4f(float *__restrict__ w, const float *__restrict__ V, size_t ldv, 
 }
 
 // The projection and update for a float16 Krylov basis: V in float16 (eight
-// per 16-byte load), the new vector w = A z in float32.  The products and the
-// sums over a thread's eight points are float32 (a float16 value times a
-// float32 one rounds at 2^-24 relative, far below the basis' own 2^-11),
-// everything summed over points is float64.  The update writes the normalised
-// vector into the basis only: the preconditioner reads it from there.
+// per 16-byte load), the new vector w = A z in float32.  The products and a
+// thread's sums are float32 (a float16 value times a float32 one rounds at
+// 2^-24 relative, far below the basis' own 2^-11; ||w||^2 is float64), the
+// block and grid sums float64.  The update writes the normalised vector into
+// the basis only: the preconditioner reads it from there.
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 typedef float f8 __attribute__((ext_vector_type(8)));
 
+// The float16 basis is orthonormal only to float16 rounding, so the update
+// divides by the exact norm of w - V h through the basis' Gram matrix,
+// ||w||^2 - 2 h.h + h^T G h (h = V^T w), and its vector comes out unit to
+// float32 rounding: no rescaling pass.  G_qr = V_q . V_r of the stored values;
+// row q (r <= q) is summed by the projection pass of step q, which reads
+// V_0..V_q anyway, into Hessenberg column q (hd0 + q hstride) at GRAM_SLOT + r.
+__device__ __forceinline__ double gram(const double *__restrict__ hd0, int hstride, int q, int r) {
+    return q >= r ? hd0[(size_t)q * hstride + GRAM_SLOT + r] : hd0[(size_t)r * hstride + GRAM_SLOT + q];
+}
+
+// With gram_row, also the products of the last vector V_{v0+NV-1} with each
+// V_{v0+q} (its Gram row; products of float16 values, exact in float32 and
+// summed in float32 per thread) into partial[b stride + GRAM_SLOT + q].
 template <int NV>
 __global__ void __launch_bounds__(RED_THREADS)
 k_multidot8h(const _Float16 *__restrict__ V, size_t ldv, int v0, const float *__restrict__ w, size_t n8,
-             double *__restrict__ partial, int stride, int with_norm) {
-    constexpr int NA = NV + 1;  // dots, ||w||^2
+             double *__restrict__ partial, int stride, int with_norm, int gram_row) {
+    constexpr int NA = NV + 1;  // dots, ||w||^2 (then the Gram row)
     __shared__ double sh[NA][RED_THREADS / 64];
     __shared__ double res[NA];
     const f8 *w8 = reinterpret_cast<const f8 *>(w);
-    double acc[NA];
+    // per thread: the dots and the Gram row in float32, ||w||^2 in float64
+    double wn = 0.0;
+    float acc[NV], gacc[NV];
 #pragma unroll
-    for (int q = 0; q < NA; ++q) acc[q] = 0.0;
+    for (int q = 0; q < NV; ++q) acc[q] = gacc[q] = 0.0f;
     for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n8; t += (size_t)gridDim.x * RED_THREADS) {
         const f8 wt = w8[t];
         h8 vq[NV];
@@ -311,35 +327,63 @@ k_multidot8h(const _Float16 *__restrict__ V, size_t ldv, int v0, const float *__
         double wd[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) wd[e] = wt[e];
-        acc[NV] += ((wd[0] * wd[0] + wd[1] * wd[1]) + (wd[2] * wd[2] + wd[3] * wd[3])) +
-                   ((wd[4] * wd[4] + wd[5] * wd[5]) + (wd[6] * wd[6] + wd[7] * wd[7]));
+        wn += ((wd[0] * wd[0] + wd[1] * wd[1]) + (wd[2] * wd[2] + wd[3] * wd[3])) +
+              ((wd[4] * wd[4] + wd[5] * wd[5]) + (wd[6] * wd[6] + wd[7] * wd[7]));
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
-            float d = 0.0f;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) d = __builtin_fmaf((float)vq[q][e], wt[e], d);
-            acc[q] += (double)d;
+            for (int e = 0; e < 8; ++e) acc[q] = __builtin_fmaf((float)vq[q][e], wt[e], acc[q]);
+        }
+        if (gram_row) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q)
+#pragma unroll
+                for (int e = 0; e < 8; e += 2)
+                    gacc[q] = __builtin_amdgcn_fdot2(h2{vq[q][e], vq[q][e + 1]}, h2{vq[NV - 1][e], vq[NV - 1][e + 1]},
+                                                     gacc[q], false);
         }
     }
-    block_sums<NA>(acc, sh, res);
+    double a[NV + 1];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) a[q] = (double)acc[q];
+    a[NV] = wn;
+    block_sums<NV + 1>(a, sh, res);
     if ((int)threadIdx.x < NV) partial[(size_t)blockIdx.x * stride + v0 + threadIdx.x] = res[threadIdx.x];
     if (with_norm && threadIdx.x == NV) partial[(size_t)blockIdx.x * stride + NORM_SLOT] = res[NV];
+    if (gram_row) {
+        double g[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) g[q] = (double)gacc[q];
+        __syncthreads();  // sh is reused
+        block_sums<NV>(g, sh, res);
+        if ((int)threadIdx.x < NV) partial[(size_t)blockIdx.x * stride + GRAM_SLOT + threadIdx.x] = res[threadIdx.x];
+    }
 }
 
+
+// The update on a float16 basis with the exact divisor (see gram); block 0
+// also sets the column's squared-norm slot to 1, the vector being unit.
 template <int NV>
 __global__ void __launch_bounds__(RED_THREADS)
 k_orth_update8h(const float *__restrict__ w, _Float16 *__restrict__ vn, const _Float16 *__restrict__ V, size_t ldv,
-                const double *__restrict__ hc, size_t n8, double *__restrict__ partial, double *__restrict__ beta_out) {
-    __shared__ double sh[1][RED_THREADS / 64];
+                double *__restrict__ hc, const double *__restrict__ hd0, int hstride, size_t n8,
+                double *__restrict__ beta_out) {
     __shared__ double cs[NV + 1];
-    __shared__ double res[1];
     if (threadIdx.x == 0) {
-        double h2 = 0.0;
-        for (int q = 0; q < NV; ++q) h2 += hc[q] * hc[q];
-        const double w2n = hc[NORM_SLOT], b2 = w2n - h2;
+        double h2 = 0.0, hgh = 0.0;
+        for (int q = 0; q < NV; ++q) {
+            h2 += hc[q] * hc[q];
+            double row = 0.0;
+            for (int r = 0; r < NV; ++r) row += gram(hd0, hstride, q, r) * hc[r];
+            hgh += hc[q] * row;
+        }
+        const double w2n = hc[NORM_SLOT], b2 = w2n - 2.0 * h2 + hgh;
         const double beta = (b2 > 1e-20 * w2n) ? sqrt(b2) : 1.0;
         cs[NV] = 1.0 / beta;
-        if (blockIdx.x == 0) *beta_out = beta;
+        if (blockIdx.x == 0) {
+            *beta_out = beta;
+            hc[65] = 1.0;
+        }
     }
     if ((int)threadIdx.x < NV) cs[threadIdx.x] = -hc[threadIdx.x];
     __syncthreads();
@@ -349,7 +393,6 @@ k_orth_update8h(const float *__restrict__ w, _Float16 *__restrict__ vn, const _F
     for (int q = 0; q < NV; ++q) csf[q] = (float)cs[q];
     const f8 *w8 = reinterpret_cast<const f8 *>(w);
     h8 *vn8 = reinterpret_cast<h8 *>(vn);
-    double nrm[1] = {0.0};
     for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n8; t += (size_t)gridDim.x * RED_THREADS) {
         const f8 wv = w8[t];
         h8 vq[NV];
@@ -363,42 +406,11 @@ k_orth_update8h(const float *__restrict__ w, _Float16 *__restrict__ vn, const _F
         for (int q = 0; q < NV; ++q)
 #pragma unroll
             for (int e = 0; e < 8; ++e) pr[e] = __builtin_fmaf(csf[q], (float)vq[q][e], pr[e]);
-        f8 o;
         h8 oh;
-        float nr = 0.0f;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            o[e] = (float)(((double)wv[e] + (double)pr[e]) * sc);
-            oh[e] = (_Float16)o[e];
-            nr = __builtin_fmaf(o[e], o[e], nr);
-        }
-        nrm[0] += (double)nr;
+        for (int e = 0; e < 8; ++e) oh[e] = (_Float16)(float)(((double)wv[e] + (double)pr[e]) * sc);
         vn8[t] = oh;
     }
-    block_sums<1>(nrm, sh, res);
-    if (threadIdx.x == 0) partial[blockIdx.x] = res[0];
-}
-
-// As k_rescale_if_f for the float16 basis vector xh (rescaled from its own
-// float16 values: the rare cancellation case pays one more rounding).
-__global__ void __launch_bounds__(RED_THREADS)
-k_rescale_if_fh(_Float16 *__restrict__ xh, const double *__restrict__ partial, int nparts, double *__restrict__ nu2,
-                size_t n) {
-    __shared__ double sh[RED_THREADS / 64];
-    __shared__ double tot;
-    double v = 0.0;
-    for (int b = threadIdx.x; b < nparts; b += RED_THREADS) v += partial[b];
-    const double r = block_sum(v, sh);
-    if (threadIdx.x == 0) {
-        tot = r;
-        if (blockIdx.x == 0) *nu2 = r;
-    }
-    __syncthreads();
-    const double nu = sqrt(tot);
-    if (nu == 0.0 || fabs(nu - 1.0) <= RESCALE_TOL_F32) return;
-    const double s = 1.0 / nu;
-    for (size_t t = blockIdx.x * (size_t)RED_THREADS + threadIdx.x; t < n; t += (size_t)gridDim.x * RED_THREADS)
-        xh[t] = (_Float16)((double)xh[t] * s);
 }
 
 // xh = r / sqrt(*den_sq) rounded to float32 and on to float16 (0 when
@@ -833,39 +845,41 @@ static bool oct_ok(const void *a, size_t ldv, size_t n) {
 bool krylov16_supported(const void *V, size_t ldv, size_t n) { return oct_ok(V, ldv, n); }
 
 void launch_multidot16(hipStream_t s, const _Float16 *V, size_t ldv, int nv, const float *w, size_t n,
-                       double *partial, double *out, double *norm_out) {
-    if (nv > 64 || !oct_ok(V, ldv, n) || !oct_ok(w, 0, n)) fail(DWP_EINVAL, "internal: float16 multidot layout");
-    for (int v0 = 0; v0 < nv; v0 += MD2_GROUP) {
-        const int g = nv - v0 < MD2_GROUP ? nv - v0 : MD2_GROUP;
-        const int wn = (v0 == 0 && norm_out) ? 1 : 0;
-        switch (g) {
-#define DWP_MD8_CASE(K)                                                                                      \
-    case K:                                                                                                  \
-        k_multidot8h<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, v0, w, n / 8, partial, MD_STRIDE, wn);    \
+                       double *partial, double *out, double *norm_out, double *gram_out) {
+    if (nv < 1 || nv > MD2_GROUP || !oct_ok(V, ldv, n) || !oct_ok(w, 0, n) || GRAM_SLOT + nv > NORM_SLOT)
+        fail(DWP_EINVAL, "internal: float16 multidot layout");
+    const int wn = norm_out ? 1 : 0, gr = gram_out ? 1 : 0;
+    switch (nv) {
+#define DWP_MD8_CASE(K)                                                                                         \
+    case K:                                                                                                     \
+        k_multidot8h<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, 0, w, n / 8, partial, MD_STRIDE, wn, gr);    \
         break;
-            DWP_NV_CASES(DWP_MD8_CASE)
+        DWP_NV_CASES(DWP_MD8_CASE)
 #undef DWP_MD8_CASE
-        }
-        DWP_LAUNCH_CHECK();
     }
+    DWP_LAUNCH_CHECK();
     k_reduce_partials<<<nv + (norm_out ? 1 : 0), RED_THREADS, 0, s>>>(partial, RED_BLOCKS, MD_STRIDE, out, nv,
                                                                      norm_out);
     DWP_LAUNCH_CHECK();
+    if (gram_out) {
+        k_reduce_partials<<<nv, RED_THREADS, 0, s>>>(partial + GRAM_SLOT, RED_BLOCKS, MD_STRIDE, gram_out, nv, nullptr);
+        DWP_LAUNCH_CHECK();
+    }
 }
 
 void launch_orth_update16(hipStream_t s, const float *w, _Float16 *vn, const _Float16 *V, size_t ldv, int nv,
-                          double *hc, size_t n, double *partial) {
-    if (nv < 1 || nv > 16 || !oct_ok(V, ldv, n) || !oct_ok(vn, 0, n) || !oct_ok(w, 0, n))
+                          double *hc, const double *hd0, int hstride, size_t n) {
+    if (nv < 1 || nv > 16 || !oct_ok(V, ldv, n) || !oct_ok(vn, 0, n) || !oct_ok(w, 0, n) ||
+        GRAM_SLOT + nv > NORM_SLOT || hstride < NORM_SLOT + 3)
         fail(DWP_EINVAL, "internal: float16 orth update layout");
     switch (nv) {
-#define DWP_OU8_CASE(K)                                                                                          \
-    case K: k_orth_update8h<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, vn, V, ldv, hc, n / 8, partial, hc + 66); \
+#define DWP_OU8_CASE(K)                                                                                         \
+    case K:                                                                                                     \
+        k_orth_update8h<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, vn, V, ldv, hc, hd0, hstride, n / 8, hc + 66); \
         break;
         DWP_NV_CASES(DWP_OU8_CASE)
 #undef DWP_OU8_CASE
     }
-    DWP_LAUNCH_CHECK();
-    k_rescale_if_fh<<<RED_BLOCKS, RED_THREADS, 0, s>>>(vn, partial, RED_BLOCKS, hc + 65, n);
     DWP_LAUNCH_CHECK();
 }
 

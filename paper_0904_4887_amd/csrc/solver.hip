@@ -535,7 +535,9 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
     bool v16 = false;
     double *coef = c->coef.as<double>();
     // column j at Hd + j * 72: [0..j] dots, 64 ||w||^2, 65 squared norm of the
-    // new vector before any rescaling, 66 the divisor of the fused update
+    // new vector before any rescaling, 66 the divisor of the fused update;
+    // with a float16 basis [20..20+j] the products of V_j with V_0..V_j (its
+    // row of the basis' Gram matrix; the update divides by the exact norm)
     double *Hd = coef + HESS_OFFSET;
     double *beta2 = coef + 8;
     double *part = c->partial.as<double>();
@@ -583,7 +585,8 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
             for (int i = 0; i <= j; ++i) Hij(i, j) = hc[i];
             // Fused update: the stored vector is (w - V h) / beta, rescaled by
             // its norm nu only when nu is off 1 by more than 1e-8 (1e-6 for a
-            // float32 basis; the same test the device made).  Otherwise:
+            // float32 basis; the same test the device made; a float16 basis
+            // divides by the exact norm and reports nu = 1).  Otherwise:
             // explicit norm.
             double hn = std::sqrt(std::max(hc[65], 0.0));
             const double rtol = v32 ? RESCALE_TOL_F32 : 1e-8;
@@ -619,9 +622,10 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
                 fused[j] = 1;
                 PROF(c, PG_APPLY, 12.0 * N, launch_apply_full_f32(s, p, (const float *)Zj32, c->eps32.as<float>(), vcur));
                 PROF(c, PG_MULTIDOT, (2.0 * (j + 1) + 4.0) * N,
-                     launch_multidot16(s, V16, N, j + 1, vcur, N, part, hc, hc + 64));
+                     launch_multidot16(s, V16, N, j + 1, vcur, N, part, hc, hc + 64, hc + GRAM_SLOT));
                 PROF(c, PG_AXPY, (2.0 * (j + 1) + 6.0) * N,
-                     launch_orth_update16(s, vcur, V16 + (size_t)(j + 1) * N, V16, N, j + 1, hc, N, part));
+                     launch_orth_update16(s, vcur, V16 + (size_t)(j + 1) * N, V16, N, j + 1, hc, Hd, HESS_STRIDE,
+                                          N));
             } else if (v32) {
                 float *Vj32 = V32 + (size_t)j * N, *Vn32 = V32 + (size_t)(j + 1) * N, *Zj32 = Z32 + (size_t)j * N;
                 apply_split(c, (const float *)Vj32, Zj32);
