@@ -102,7 +102,8 @@ k_build(const double *__restrict__ atoms, int natoms, Box b, double eps_inf, dou
             px = r[0]; py = r[1]; pz = r[2];
             const double cut = MODE == 0 ? r[3] + 6.0 * delta : 9.0 * r[5];
             pr = MODE == 0 ? r[3] : r[5];
-            pq = r[4];
+            // a Gaussian's amplitude q (2 pi sigma^2)^(-3/2), once per atom
+            pq = MODE == 0 ? r[4] : r[4] * pow(2.0 * PI * r[5] * r[5], -1.5);
             keep = dist2_to_tile(b, px, py, pz, x0, x1, y0, y1, z0, z1) < cut * cut;
         }
         int total;
@@ -124,7 +125,7 @@ k_build(const double *__restrict__ atoms, int natoms, Box b, double eps_inf, dou
                     if (t < 6.0) acc *= 0.5 * (1.0 + erf(t));
                 } else {
                     const double s2 = ar[q] * ar[q];
-                    if (d2 < 81.0 * s2) acc += aq[q] * pow(2.0 * PI * s2, -1.5) * exp(-d2 / (2.0 * s2));
+                    if (d2 < 81.0 * s2) acc += aq[q] * exp(-d2 / (2.0 * s2));
                 }
             }
         }

@@ -528,18 +528,21 @@ k_axpy4f(double *__restrict__ x, const float *__restrict__ Z, size_t ldz, const 
 }
 
 // out[idx] = sum_b partial[b * stride + idx], one block per idx, fixed order;
-// with norm_out, one more block adds column NORM_SLOT into *norm_out
+// with norm_out, one more block adds column NORM_SLOT into *norm_out; the
+// last ngram blocks add columns GRAM_SLOT + q into gram_out[q]
 __global__ void __launch_bounds__(RED_THREADS)
 k_reduce_partials(const double *__restrict__ partial, int nblocks, int stride, double *__restrict__ out,
-                  int nout, double *__restrict__ norm_out, double *__restrict__ sum_out = nullptr) {
+                  int nout, double *__restrict__ norm_out, double *__restrict__ sum_out = nullptr,
+                  double *__restrict__ gram_out = nullptr, int ngram = 0) {
     __shared__ double sh[RED_THREADS / 64];
-    const int b0 = (int)blockIdx.x;
-    const int idx = b0 < nout ? b0 : (b0 == nout ? NORM_SLOT : SUM_SLOT);
+    const int b0 = (int)blockIdx.x, g0 = (int)gridDim.x - ngram;
+    const int idx = b0 >= g0 ? GRAM_SLOT + b0 - g0 : (b0 < nout ? b0 : (b0 == nout ? NORM_SLOT : SUM_SLOT));
     double v = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += RED_THREADS) v += partial[(size_t)b * stride + idx];
     const double r = block_sum(v, sh);
     if (threadIdx.x == 0) {
-        if (b0 < nout) out[idx] = r;
+        if (b0 >= g0) gram_out[b0 - g0] = r;
+        else if (b0 < nout) out[idx] = r;
         else if (b0 == nout) *norm_out = r;
         else *sum_out = r;
     }
@@ -858,13 +861,10 @@ void launch_multidot16(hipStream_t s, const _Float16 *V, size_t ldv, int nv, con
 #undef DWP_MD8_CASE
     }
     DWP_LAUNCH_CHECK();
-    k_reduce_partials<<<nv + (norm_out ? 1 : 0), RED_THREADS, 0, s>>>(partial, RED_BLOCKS, MD_STRIDE, out, nv,
-                                                                     norm_out);
+    const int ng = gram_out ? nv : 0;
+    k_reduce_partials<<<nv + (norm_out ? 1 : 0) + ng, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, MD_STRIDE, out, nv,
+                                                                          norm_out, nullptr, gram_out, ng);
     DWP_LAUNCH_CHECK();
-    if (gram_out) {
-        k_reduce_partials<<<nv, RED_THREADS, 0, s>>>(partial + GRAM_SLOT, RED_BLOCKS, MD_STRIDE, gram_out, nv, nullptr);
-        DWP_LAUNCH_CHECK();
-    }
 }
 
 void launch_orth_update16(hipStream_t s, const float *w, _Float16 *vn, const _Float16 *V, size_t ldv, int nv,
