@@ -24,6 +24,7 @@ namespace dwp {
 namespace {
 
 constexpr int AT_THREADS = 256;
+constexpr int FU = 4;  // nodes of a z column whose loads k_forces issues together
 constexpr int AREC = 8;
 constexpr double PI = 3.14159265358979323846;
 constexpr double SQRT_PI = 1.77245385090551602730;
@@ -358,30 +359,56 @@ k_forces(const double *__restrict__ atoms, Box b, int eps_mode, double eps_inf, 
         const int kl = max(klo, (int)ceil((Z - dzm) / b.hz)), kh = min(khi, (int)floor((Z + dzm) / b.hz));
         const size_t colbase = (size_t)j * b.nx + i;
         int k = ((kl % b.nz) + b.nz) % b.nz;
-        for (int ku = kl; ku <= kh; ++ku) {
-            const double dz = min_image(k * b.hz - Z, b.Lz, b.iLz);
-            const double d2 = dx * dx + dy * dy + dz * dz;
-            const size_t c = (size_t)k * plane + colbase;
-            // charge term: d rho_n / dR_a = q G(d) (r_n - R_a) / sigma^2
-            if (d2 < crho * crho) {
-                const double w = gnorm * phi[c] * exp(-d2 * inv2s2);
-                fx += w * dx; fy += w * dy; fz += w * dz;
-            }
-            if (eps_mode) {
-                const double d = sqrt(d2);
-                const double t = (d - Ra) / delta;
-                if (t > -6.0 && t < 6.0 && d > 0.0) {
-                    const double Sv = S[c];
-                    if (Sv != 0.0) {
-                        const double H = Hz ? Hz[k] : 1.0;
-                        const double sa = 0.5 * (1.0 + erf(t));
-                        // d eps / dR_a = (eps_inf - 1) H (S / s_a) s_a'(t) (-(r - R_a) / (d delta))
-                        const double w = wz_eps * g[c] * H * (Sv / sa) * exp(-t * t) / d;
-                        fx += w * dx; fy += w * dy; fz += w * dz;
+        // FU nodes of the column at a time: their loads are issued together,
+        // then used in order (the sums' order is that of the nodes)
+        for (int ku0 = kl; ku0 <= kh; ku0 += FU) {
+            int kk[FU];
+            double ph[FU], sv[FU], gv[FU], hv[FU];
+#pragma unroll
+            for (int u = 0; u < FU; ++u) {
+                kk[u] = k;
+                k = (k + 1 == b.nz) ? 0 : k + 1;
+                ph[u] = sv[u] = gv[u] = 0.0;
+                hv[u] = 1.0;
+                if (ku0 + u > kh) continue;
+                const double dz = min_image(kk[u] * b.hz - Z, b.Lz, b.iLz);
+                const double d2 = dxy2 + dz * dz;
+                const size_t c = (size_t)kk[u] * plane + colbase;
+                if (d2 < crho * crho) ph[u] = phi[c];
+                if (eps_mode) {
+                    const double t = (sqrt(d2) - Ra) / delta;
+                    if (t > -6.0 && t < 6.0) {
+                        sv[u] = S[c];
+                        gv[u] = g[c];
+                        if (Hz) hv[u] = Hz[kk[u]];
                     }
                 }
             }
-            k = (k + 1 == b.nz) ? 0 : k + 1;
+#pragma unroll
+            for (int u = 0; u < FU; ++u) {
+                if (ku0 + u > kh) break;
+                const double dz = min_image(kk[u] * b.hz - Z, b.Lz, b.iLz);
+                const double d2 = dx * dx + dy * dy + dz * dz;
+                // charge term: d rho_n / dR_a = q G(d) (r_n - R_a) / sigma^2
+                if (d2 < crho * crho) {
+                    const double w = gnorm * ph[u] * exp(-d2 * inv2s2);
+                    fx += w * dx; fy += w * dy; fz += w * dz;
+                }
+                if (eps_mode) {
+                    const double d = sqrt(d2);
+                    const double t = (d - Ra) / delta;
+                    if (t > -6.0 && t < 6.0 && d > 0.0) {
+                        const double Sv = sv[u];
+                        if (Sv != 0.0) {
+                            const double H = hv[u];
+                            const double sa = 0.5 * (1.0 + erf(t));
+                            // d eps / dR_a = (eps_inf - 1) H (S / s_a) s_a'(t) (-(r - R_a) / (d delta))
+                            const double w = wz_eps * gv[u] * H * (Sv / sa) * exp(-t * t) / d;
+                            fx += w * dx; fy += w * dy; fz += w * dz;
+                        }
+                    }
+                }
+            }
         }
     }
     // block reduction of (fx, fy, fz)
