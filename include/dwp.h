@@ -137,11 +137,13 @@ typedef struct {
                            /* preconditioner; the arithmetic is as above, the  */
                            /* true residual is still recomputed in float64 at  */
                            /* every restart, so the tolerance still holds for  */
-                           /* the float64 residual), except the first cycle    */
-                           /* of a solve and any cycle after one that reduced  */
-                           /* the residual more than 100-fold: there a float16 */
-                           /* basis would limit the cycle, which runs on the   */
-                           /* float32 basis.  0 = as krylov_fp32 says          */
+                           /* the float64 residual), except any cycle after    */
+                           /* one that reduced the residual more than 100-fold */
+                           /* and the first cycle of a solve unless the first  */
+                           /* cycle of the context's previous solve reduced it */
+                           /* less: there a float16 basis would limit the      */
+                           /* cycle, which runs on the float32 basis.          */
+                           /* 0 = as krylov_fp32 says                          */
     double semi_ratio;     /* multigrid coarsening: a level halves z too only  */
                            /* once hz <= semi_ratio * max(hx, hy) (before,     */
                            /* only x and y: semi-coarsening for anisotropic    */

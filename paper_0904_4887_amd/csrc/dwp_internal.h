@@ -191,6 +191,7 @@ struct dwp_ctx {
     bool transposed = false;      // the Krylov solve in progress is the adjoint one
     int fft_order = 0;            // order the FFT symbol tables were built for
     double background = 0.0;      // uniform background of the last order-6 solve
+    double first_cycle_red = -1.0;  // residual reduction of the last solve's first cycle (< 0: none yet)
     dwp::PhaseTimer phases;       // phase timers of the solve in progress
     dwp::DevBuf bw_rhs, bw_lam;   // adjoint right-hand side and solution of dwp_backward
 };

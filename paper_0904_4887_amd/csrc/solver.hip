@@ -528,10 +528,12 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
                         krylov16_supported(V16, N, N) && krylov16_supported(vcur, N, N);
     // A cycle on a float16 basis cannot reduce the residual much below the
     // basis' rounding (2^-11), which costs iterations where cycles reduce it a
-    // lot: the first cycle of a solve, and every cycle after one that reduced
-    // it more than V16_MAX_REDUCTION-fold, runs on the float32 basis.
+    // lot: a cycle after one that reduced it more than V16_MAX_REDUCTION-fold
+    // runs on the float32 basis, and so does the first cycle of a solve unless
+    // the first cycle of the context's previous solve reduced it less.
     constexpr double V16_MAX_REDUCTION = 100.0;
     double beta_prev = -1.0;
+    int cycle = 0;
     bool v16 = false;
     double *coef = c->coef.as<double>();
     // column j at Hd + j * 72: [0..j] dots, 64 ||w||^2, 65 squared norm of the
@@ -557,10 +559,13 @@ int fgmres(dwp_ctx *c, const double *b, double bnorm, double *x, int *restarts, 
         to_host(c, beta2, 1);
         const double beta = std::sqrt(c->host[0]);
         if (!std::isfinite(beta)) fail(DWP_ENONFINITE, "residual is not finite");
+        if (cycle == 1) c->first_cycle_red = beta > 0.0 ? beta_prev / beta : 1e300;
+        ++cycle;
         *rel = beta / bnorm;
         if (*rel <= o.tol || iters >= o.max_outer) return iters;
         ++*restarts;
-        v16 = v16_ok && beta_prev > 0.0 && beta * V16_MAX_REDUCTION >= beta_prev;
+        v16 = v16_ok && (beta_prev > 0.0 ? beta * V16_MAX_REDUCTION >= beta_prev
+                                         : c->first_cycle_red > 0.0 && c->first_cycle_red <= V16_MAX_REDUCTION);
         beta_prev = beta;
         if (v16) PROF(c, PG_VEC, 10.0 * N, launch_scale_to16(s, nullptr, V16, r0, beta2, N));
         else if (v32) PROF(c, PG_VEC, 12.0 * N, launch_scale_to32(s, V32, r0, beta2, N));
