@@ -855,6 +855,7 @@ void set_grid_impl(dwp_ctx *c, int nx, int ny, int nz, double Lx, double Ly, dou
     else dwp_default_opts(&opts);
     validate_opts(opts);
     c->have_grid = c->have_eps = c->have_solution = false;
+    c->first_cycle_red = -1.0;
     free_levels(c);
     Plan &p = c->plan;
     p.nx = nx; p.ny = ny; p.nz = nz;
