@@ -266,14 +266,49 @@ constexpr int FFT_KL = FFT_MAXE / FFT_THREADS;  // one batch covers a block of t
 template <class S, class TI, bool R6>
 __global__ void __launch_bounds__(FFT_THREADS)
 k_fft_x_fwd(const TI *__restrict__ in, const double *__restrict__ sinv, cplx<S> *__restrict__ out,
-            Radices rd, const cplx<S> *__restrict__ tw, int lb, int nrows, int nkx, int ldc, Div dn, Div dk) {
+            Radices rd, const cplx<S> *__restrict__ tw, int lb, int nrows, int nkx, int ldc, Div dn, Div dk, Div dn4) {
     using C = cplx<S>;
+    typedef TI TI4 __attribute__((ext_vector_type(4)));
     extern __shared__ __align__(16) unsigned char lds_raw[];
     C *lds = reinterpret_cast<C *>(lds_raw);
     const int n = rd.n, ls = n + 1, B = 1 << lb;
     const int r0 = blockIdx.x * 2 * B;
     C *twl = lds + B * ls;
-    load_batched<FFT_KL, FFT_THREADS, C>(
+    if (!sinv && (n & 3) == 0) {
+        // unscaled rows of a multiple of 4: four values of each row per load
+        // (dn4 divides by n / 4)
+        const int n4 = n >> 2;
+        for (int e = threadIdx.x; e < n; e += FFT_THREADS) twl[e] = tw[e];
+        constexpr int KV = (FFT_MAXE / 4 + FFT_THREADS - 1) / FFT_THREADS;
+        for (int e0 = 0; e0 < B * n4; e0 += KV * FFT_THREADS) {
+            TI4 va[KV], vb[KV];
+#pragma unroll
+            for (int m = 0; m < KV; ++m) {
+                const int e = e0 + threadIdx.x + m * FFT_THREADS;
+                if (e < B * n4) {
+                    const int l = udiv(e, dn4), t4 = e - l * n4;
+                    const int ra = r0 + 2 * l;
+                    if (ra + 1 < nrows) {
+                        const size_t ia = (size_t)ra * n + 4 * t4;
+                        va[m] = *reinterpret_cast<const TI4 *>(in + ia);
+                        vb[m] = *reinterpret_cast<const TI4 *>(in + ia + n);
+                    } else {
+                        va[m] = vb[m] = TI4(0);
+                    }
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < KV; ++m) {
+                const int e = e0 + threadIdx.x + m * FFT_THREADS;
+                if (e < B * n4) {
+                    const int l = udiv(e, dn4), t4 = e - l * n4;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        lds[l * ls + 4 * t4 + q] = mk<C>((S)(double)va[m][q], (S)(double)vb[m][q]);
+                }
+            }
+        }
+    } else load_batched<FFT_KL, FFT_THREADS, C>(
         B * n,
         [&](int e) {
             const int l = udiv(e, dn), t = e - l * n;
@@ -310,7 +345,7 @@ k_fft_x_fwd(const TI *__restrict__ in, const double *__restrict__ sinv, cplx<S> 
 template <class S, class TO, bool R6>
 __global__ void __launch_bounds__(FFT_THREADS)
 k_fft_x_inv(const cplx<S> *__restrict__ in, const double *__restrict__ sinv, TO *__restrict__ out,
-            Radices rd, const cplx<S> *__restrict__ tw, int lb, int nrows, int nkx, int ldc, Div dn) {
+            Radices rd, const cplx<S> *__restrict__ tw, int lb, int nrows, int nkx, int ldc, Div dn, Div dn4) {
     using C = cplx<S>;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     C *lds = reinterpret_cast<C *>(lds_raw);
@@ -339,6 +374,27 @@ k_fft_x_inv(const cplx<S> *__restrict__ in, const double *__restrict__ sinv, TO 
         tw, twl, n);
     __syncthreads();
     fft_lines<R6, false>(lds, rd, lb, 1, ls, twl, true);
+    if (!sinv && (n & 3) == 0) {
+        // unscaled rows of a multiple of 4: four values of each row per store
+        typedef TO TO4 __attribute__((ext_vector_type(4)));
+        const int n4 = n >> 2;
+        for (int e = threadIdx.x; e < B * n4; e += FFT_THREADS) {
+            const int l = udiv(e, dn4), t4 = e - l * n4;
+            const int ra = r0 + 2 * l;
+            if (ra + 1 >= nrows) continue;
+            TO4 a, b;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const C z = lds[l * ls + 4 * t4 + q];
+                a[q] = (TO)z.x;
+                b[q] = (TO)z.y;
+            }
+            const size_t ia = (size_t)ra * n + 4 * t4;
+            *reinterpret_cast<TO4 *>(out + ia) = a;
+            *reinterpret_cast<TO4 *>(out + ia + n) = b;
+        }
+        return;
+    }
     for (int e = threadIdx.x; e < B * n; e += FFT_THREADS) {
         const int l = udiv(e, dn), t = e - l * n;
         const int ra = r0 + 2 * l, rb = ra + 1;
@@ -583,7 +639,7 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
     const int Bx = 1 << lbx;
     const int gx = (nrows + 2 * Bx - 1) / (2 * Bx);
     const size_t ldsx = sizeof(C) * ((size_t)Bx * (p.nx + 1) + p.nx);
-    const Div dn = make_div(p.nx), dk = make_div(p.nkx);
+    const Div dn = make_div(p.nx), dk = make_div(p.nkx), dn4 = make_div(p.nx / 4 > 0 ? p.nx / 4 : 1);
     const int lby = tile_log2(p.ny, budget(ay, FFT_BUDGET_Y, FFT_THREADS)), By = 1 << lby;
     const int gy = xcd_grid((p.nkx + By - 1) / By * p.nz);
     const size_t ldsy = sizeof(C) * ((size_t)By * p.ny + p.ny);
@@ -603,7 +659,7 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
         static std::atomic<unsigned> attr{0};
         lds_attr(fptr(&k_fft_x_fwd<S, TI, R6>), attr, ldsx);
         k_fft_x_fwd<S, TI, R6><<<gx, FFT_THREADS, ldsx, st>>>(r, sinv, cbuf, RD(ax), TW(ax), lbx, nrows, p.nkx,
-                                                             p.ldc, dn, dk);
+                                                             p.ldc, dn, dk, dn4);
         DWP_LAUNCH_CHECK();
     });
     pe(ev, PG_FFT_X, bx);
@@ -634,7 +690,7 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
         static std::atomic<unsigned> attr{0};
         lds_attr(fptr(&k_fft_x_inv<S, TO, R6>), attr, ldsx);
         k_fft_x_inv<S, TO, R6><<<gx, FFT_THREADS, ldsx, st>>>(cbuf, sinv, out, RD(ax), TW(ax), lbx, nrows,
-                                                             p.nkx, p.ldc, dn);
+                                                             p.nkx, p.ldc, dn, dn4);
         DWP_LAUNCH_CHECK();
     });
     pe(ev, PG_FFT_X, bxi);
