@@ -429,6 +429,48 @@ __device__ __forceinline__ bool xcd_tile2(int ntx, int nty, int &tx, int &ty) {
 }
 inline int xcd_grid(int n) { return (n + 7) / 8 * 8; }
 
+// Float32 spectrum, lines interleaved in LDS (element t of line l at t B + l,
+// B = 2^lb >= 2): the block's B n values move between the spectrum (element
+// t of line l at base + t stride + l) and LDS two neighbouring lines per
+// 16-byte access; lines from bw on are zero in LDS and are not written back.
+// pair_load also brings the n twiddles into twl.
+__device__ __forceinline__ void pair_load(float2 *lds, const float2 *__restrict__ c, size_t base, size_t stride,
+                                          int lb, int n, int bw, const float2 *__restrict__ tw, float2 *twl) {
+    for (int e = threadIdx.x; e < n; e += FFT_THREADS) twl[e] = tw[e];
+    constexpr int KP = FFT_MAXE / 2 / FFT_THREADS;
+    const int np = (n << lb) >> 1, hmask = (1 << (lb - 1)) - 1;
+    for (int e0 = 0; e0 < np; e0 += KP * FFT_THREADS) {
+        float4 v[KP];
+#pragma unroll
+        for (int m = 0; m < KP; ++m) {
+            const int e = e0 + threadIdx.x + m * FFT_THREADS;
+            if (e < np) {
+                const int t = e >> (lb - 1), l = (e & hmask) << 1;
+                const float2 *src = c + base + (size_t)t * stride + l;
+                if (l + 1 < bw) v[m] = *reinterpret_cast<const float4 *>(src);
+                else if (l < bw) v[m] = make_float4(src->x, src->y, 0.0f, 0.0f);
+                else v[m] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < KP; ++m) {
+            const int e = e0 + threadIdx.x + m * FFT_THREADS;
+            if (e < np) reinterpret_cast<float4 *>(lds)[e] = v[m];
+        }
+    }
+}
+__device__ __forceinline__ void pair_store(const float2 *lds, float2 *__restrict__ c, size_t base, size_t stride,
+                                           int lb, int n, int bw) {
+    const int np = (n << lb) >> 1, hmask = (1 << (lb - 1)) - 1;
+    for (int e = threadIdx.x; e < np; e += FFT_THREADS) {
+        const int t = e >> (lb - 1), l = (e & hmask) << 1;
+        float2 *dst = c + base + (size_t)t * stride + l;
+        const float4 v = reinterpret_cast<const float4 *>(lds)[e];
+        if (l + 1 < bw) *reinterpret_cast<float4 *>(dst) = v;
+        else if (l < bw) *dst = make_float2(v.x, v.y);
+    }
+}
+
 // ---------------------------------------------------------------- y pass
 // Block (tile of B = 2^lb consecutive kx, plane z): lines along y, LDS
 // element (y, l) at y * B + l.
@@ -447,15 +489,25 @@ k_fft_y(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ tw, int
     const int bw = min(B, nkx - kx0);
     const size_t base = (size_t)z * ny * ldc + kx0;
     C *twl = lds + B * ny;
-    load_batched<FFT_KL, FFT_THREADS, C>(
-        B * ny,
-        [&](int e) {
-            const int y = e >> lb, l = e & bmask;
-            return (l < bw) ? c[base + (size_t)y * ldc + l] : mk<C>(0, 0);
-        },
-        [&](int e, C v) { lds[e] = v; }, tw, twl, ny);
+    constexpr bool PAIRS = sizeof(S) == 4;
+    if (PAIRS && lb >= 1) {
+        pair_load(reinterpret_cast<float2 *>(lds), reinterpret_cast<const float2 *>(c), base, ldc, lb, ny, bw,
+                  reinterpret_cast<const float2 *>(tw), reinterpret_cast<float2 *>(twl));
+    } else {
+        load_batched<FFT_KL, FFT_THREADS, C>(
+            B * ny,
+            [&](int e) {
+                const int y = e >> lb, l = e & bmask;
+                return (l < bw) ? c[base + (size_t)y * ldc + l] : mk<C>(0, 0);
+            },
+            [&](int e, C v) { lds[e] = v; }, tw, twl, ny);
+    }
     __syncthreads();
     fft_lines<R6, true>(lds, rd, lb, B, 1, twl, INV);
+    if (PAIRS && lb >= 1) {
+        pair_store(reinterpret_cast<const float2 *>(lds), reinterpret_cast<float2 *>(c), base, ldc, lb, ny, bw);
+        return;
+    }
     for (int e = threadIdx.x; e < B * ny; e += FFT_THREADS) {
         const int y = e >> lb, l = e & bmask;
         if (l < bw) c[base + (size_t)y * ldc + l] = lds[e];
@@ -491,13 +543,19 @@ k_fft_z_green(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ t
     const size_t zstride = (size_t)ny * ldc;
     const size_t base = (size_t)y * ldc + kx0;
     C *twl = lds + B * nz;
-    load_batched<(MAXE + NT - 1) / NT, NT, C>(
-        B * nz,
-        [&](int e) {
-            const int z = e >> lb, l = e & bmask;
-            return (l < bw) ? c[base + (size_t)z * zstride + l] : mk<C>(0, 0);
-        },
-        [&](int e, C v) { lds[e] = v; }, tw, twl, nz);
+    constexpr bool PAIRS = sizeof(S) == 4 && NT == FFT_THREADS && MAXE == FFT_MAXE;
+    if (PAIRS && lb >= 1) {
+        pair_load(reinterpret_cast<float2 *>(lds), reinterpret_cast<const float2 *>(c), base, zstride, lb, nz, bw,
+                  reinterpret_cast<const float2 *>(tw), reinterpret_cast<float2 *>(twl));
+    } else {
+        load_batched<(MAXE + NT - 1) / NT, NT, C>(
+            B * nz,
+            [&](int e) {
+                const int z = e >> lb, l = e & bmask;
+                return (l < bw) ? c[base + (size_t)z * zstride + l] : mk<C>(0, 0);
+            },
+            [&](int e, C v) { lds[e] = v; }, tw, twl, nz);
+    }
     __syncthreads();
     fft_lines<R6, true, C, MAXE, NT>(lds, rd, lb, B, 1, twl, false);
     const S ly = lamy[y];
@@ -511,6 +569,10 @@ k_fft_z_green(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ t
     }
     __syncthreads();
     fft_lines<R6, true, C, MAXE, NT>(lds, rd, lb, B, 1, twl, true);
+    if (PAIRS && lb >= 1) {
+        pair_store(reinterpret_cast<const float2 *>(lds), reinterpret_cast<float2 *>(c), base, zstride, lb, nz, bw);
+        return;
+    }
     for (int e = threadIdx.x; e < B * nz; e += NT) {
         const int z = e >> lb, l = e & bmask;
         if (l < bw) c[base + (size_t)z * zstride + l] = lds[e];
