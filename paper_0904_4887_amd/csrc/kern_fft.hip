@@ -266,7 +266,8 @@ constexpr int FFT_KL = FFT_MAXE / FFT_THREADS;  // one batch covers a block of t
 template <class S, class TI, bool R6>
 __global__ void __launch_bounds__(FFT_THREADS)
 k_fft_x_fwd(const TI *__restrict__ in, const double *__restrict__ sinv, cplx<S> *__restrict__ out,
-            Radices rd, const cplx<S> *__restrict__ tw, int lb, int nrows, int nkx, int ldc, Div dn, Div dk, Div dn4) {
+            Radices rd, const cplx<S> *__restrict__ tw, int lb, int nrows, int nkx, int ldc, Div dn, Div dk, Div dn4,
+            Div dk2) {
     using C = cplx<S>;
     typedef TI TI4 __attribute__((ext_vector_type(4)));
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -329,6 +330,33 @@ k_fft_x_fwd(const TI *__restrict__ in, const double *__restrict__ sinv, cplx<S> 
         tw, twl, n);
     __syncthreads();
     fft_lines<R6, false>(lds, rd, lb, 1, ls, twl, false);
+    if constexpr (sizeof(S) == 4) {
+        // two neighbouring kx per thread, stored as 16-byte pairs (ldc even)
+        const int nk2 = (nkx + 1) >> 1;
+        const S h = (S)0.5;
+        for (int e = threadIdx.x; e < B * nk2; e += FFT_THREADS) {
+            const int l = udiv(e, dk2), k = 2 * (e - l * nk2);
+            const int ra = r0 + 2 * l, rb = ra + 1;
+            if (rb >= nrows) continue;
+            float4 A, Bq;
+            {
+                const C z = lds[l * ls + k], zc = lds[l * ls + (k == 0 ? 0 : n - k)];  // Z[k], Z[-k]
+                A.x = h * (z.x + zc.x); A.y = h * (z.y - zc.y);
+                Bq.x = h * (z.y + zc.y); Bq.y = -h * (z.x - zc.x);
+            }
+            if (k + 1 < nkx) {
+                const C z = lds[l * ls + k + 1], zc = lds[l * ls + n - k - 1];
+                A.z = h * (z.x + zc.x); A.w = h * (z.y - zc.y);
+                Bq.z = h * (z.y + zc.y); Bq.w = -h * (z.x - zc.x);
+                *reinterpret_cast<float4 *>(out + (size_t)ra * ldc + k) = A;
+                *reinterpret_cast<float4 *>(out + (size_t)rb * ldc + k) = Bq;
+            } else {
+                out[(size_t)ra * ldc + k] = mk<C>(A.x, A.y);
+                out[(size_t)rb * ldc + k] = mk<C>(Bq.x, Bq.y);
+            }
+        }
+        return;
+    }
     for (int e = threadIdx.x; e < B * nkx; e += FFT_THREADS) {
         const int l = udiv(e, dk), k = e - l * nkx;
         const int ra = r0 + 2 * l, rb = ra + 1;
@@ -701,7 +729,8 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
     const int Bx = 1 << lbx;
     const int gx = (nrows + 2 * Bx - 1) / (2 * Bx);
     const size_t ldsx = sizeof(C) * ((size_t)Bx * (p.nx + 1) + p.nx);
-    const Div dn = make_div(p.nx), dk = make_div(p.nkx), dn4 = make_div(p.nx / 4 > 0 ? p.nx / 4 : 1);
+    const Div dn = make_div(p.nx), dk = make_div(p.nkx), dn4 = make_div(p.nx / 4 > 0 ? p.nx / 4 : 1),
+              dk2 = make_div((p.nkx + 1) / 2);
     const int lby = tile_log2(p.ny, budget(ay, FFT_BUDGET_Y, FFT_THREADS)), By = 1 << lby;
     const int gy = xcd_grid((p.nkx + By - 1) / By * p.nz);
     const size_t ldsy = sizeof(C) * ((size_t)By * p.ny + p.ny);
@@ -721,7 +750,7 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
         static std::atomic<unsigned> attr{0};
         lds_attr(fptr(&k_fft_x_fwd<S, TI, R6>), attr, ldsx);
         k_fft_x_fwd<S, TI, R6><<<gx, FFT_THREADS, ldsx, st>>>(r, sinv, cbuf, RD(ax), TW(ax), lbx, nrows, p.nkx,
-                                                             p.ldc, dn, dk, dn4);
+                                                             p.ldc, dn, dk, dn4, dk2);
         DWP_LAUNCH_CHECK();
     });
     pe(ev, PG_FFT_X, bx);

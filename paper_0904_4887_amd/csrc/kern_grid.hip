@@ -363,16 +363,26 @@ __global__ void k_check(const double *x, size_t n, int *flags, int check_ge1) {
 
 // z at box plane (k_w0 + kk) mod nz += uW (ghosted plane kk + 1).  Grid:
 // (plane chunks, kk); PAIRS: two consecutive points per thread (plane even,
-// z 16-byte aligned).
-template <class T, bool PAIRS, class TZ>
+// z 16-byte aligned); QUADS (float32 both): four, 16-byte accesses (plane a
+// multiple of 4).
+template <class T, bool PAIRS, class TZ, bool QUADS = false>
 __global__ void k_wet_add(const T *__restrict__ uW, TZ *__restrict__ z, int plane, int nz, int k_w0) {
     const int kk = blockIdx.y;
     const int k = (k_w0 + kk) % nz;
     const T *src = uW + (size_t)(kk + 1) * plane;
     TZ *dst = z + (size_t)k * plane;
-    const int q = (PAIRS ? 2 : 1) * (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int q = (QUADS ? 4 : PAIRS ? 2 : 1) * (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (q >= plane) return;
-    if constexpr (PAIRS && sizeof(TZ) == 8) {
+    if constexpr (QUADS) {
+        static_assert(sizeof(T) == 4 && sizeof(TZ) == 4, "float32 quads");
+        float4 v = *reinterpret_cast<float4 *>(dst + q);
+        const float4 u = *reinterpret_cast<const float4 *>(src + q);
+        v.x = (float)((double)v.x + (double)u.x);
+        v.y = (float)((double)v.y + (double)u.y);
+        v.z = (float)((double)v.z + (double)u.z);
+        v.w = (float)((double)v.w + (double)u.w);
+        *reinterpret_cast<float4 *>(dst + q) = v;
+    } else if constexpr (PAIRS && sizeof(TZ) == 8) {
         double2 v = *reinterpret_cast<double2 *>(dst + q);
         v.x += (double)src[q];
         v.y += (double)src[q + 1];
@@ -1583,6 +1593,16 @@ template <class T, class TZ>
 static void wet_add_t(hipStream_t s, const Plan &p, const T *uW, TZ *z) {
     const int plane = p.nx * p.ny;
     const bool pairs = plane % 2 == 0 && (reinterpret_cast<uintptr_t>(z) & 15) == 0;
+    const bool quads = sizeof(T) == 4 && sizeof(TZ) == 4 && plane % 4 == 0 &&
+                       (reinterpret_cast<uintptr_t>(z) & 15) == 0 && (reinterpret_cast<uintptr_t>(uW) & 15) == 0;
+    if constexpr (sizeof(T) == 4 && sizeof(TZ) == 4) {
+        if (quads) {
+            dim3 g((plane / 4 + 255) / 256, p.nw);
+            k_wet_add<T, false, TZ, true><<<g, 256, 0, s>>>(uW, z, plane, p.nz, p.k_w0);
+            DWP_LAUNCH_CHECK();
+            return;
+        }
+    }
     const int per = pairs ? plane / 2 : plane;
     dim3 g((per + 255) / 256, p.nw);
     if (pairs) k_wet_add<T, true, TZ><<<g, 256, 0, s>>>(uW, z, plane, p.nz, p.k_w0);
