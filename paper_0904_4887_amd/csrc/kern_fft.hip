@@ -559,7 +559,8 @@ __device__ __forceinline__ float neg_recip(float d) { return -__builtin_amdgcn_r
 template <class S, bool R6, int MAXE = FFT_MAXE, int NT = FFT_THREADS>
 __global__ void __launch_bounds__(NT)
 k_fft_z_green(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ tw, int lb, int nkx, int ldc, int ny,
-              const S *__restrict__ lamx, const S *__restrict__ lamy, const S *__restrict__ lamz, S inv_n) {
+              const S *__restrict__ lamx, const S *__restrict__ lamy, const S *__restrict__ lamz, S inv_n,
+              int lam_lds) {
     using C = cplx<S>;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     C *lds = reinterpret_cast<C *>(lds_raw);
@@ -571,6 +572,15 @@ k_fft_z_green(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ t
     const size_t zstride = (size_t)ny * ldc;
     const size_t base = (size_t)y * ldc + kx0;
     C *twl = lds + B * nz;
+    // with lam_lds the symbol's z values and the block's kx values follow
+    // the twiddles, loaded with the lines (the Green step then reads LDS only)
+    S *lz = reinterpret_cast<S *>(twl + nz), *lx = lz + nz;
+    if (lam_lds) {
+        for (int e = threadIdx.x; e < nz + B; e += NT) {
+            if (e < nz) lz[e] = lamz[e];
+            else if (kx0 + e - nz < nkx) lx[e - nz] = lamx[kx0 + e - nz];
+        }
+    }
     constexpr bool PAIRS = sizeof(S) == 4 && NT == FFT_THREADS && MAXE == FFT_MAXE;
     if (PAIRS && lb >= 1) {
         pair_load(reinterpret_cast<float2 *>(lds), reinterpret_cast<const float2 *>(c), base, zstride, lb, nz, bw,
@@ -591,7 +601,8 @@ k_fft_z_green(cplx<S> *__restrict__ c, Radices rd, const cplx<S> *__restrict__ t
         const int z = e >> lb, l = e & bmask;
         const int kx = kx0 + l;
         S g = 0;
-        if (l < bw && (kx | y | z) != 0) g = inv_n * neg_recip(lamx[kx] + ly + lamz[z]);
+        if (l < bw && (kx | y | z) != 0)
+            g = inv_n * neg_recip((lam_lds ? lx[l] : lamx[kx]) + ly + (lam_lds ? lz[z] : lamz[z]));
         const C v = lds[e];
         lds[e] = mk<C>(v.x * g, v.y * g);
     }
@@ -764,11 +775,15 @@ static void vacuum_solve_t(hipStream_t st, const Plan &p, const FFTAxis &ax, con
         constexpr bool R6 = decltype(r6)::value;
         const int lbz = tile_log2(p.nz, budget(az, FFT_Z_MAXE, FFT_Z_THREADS)), Bz = 1 << lbz;
         const int gz = xcd_grid((p.nkx + Bz - 1) / Bz * p.ny);
-        const size_t bytes = sizeof(C) * ((size_t)Bz * p.nz + p.nz);
+        // the symbol staged in LDS too where it fits
+        const size_t base_bytes = sizeof(C) * ((size_t)Bz * p.nz + p.nz);
+        const size_t lam_bytes = sizeof(S) * ((size_t)p.nz + Bz);
+        const int lam_lds = base_bytes + lam_bytes <= 160 * 1024 ? 1 : 0;
+        const size_t bytes = base_bytes + (lam_lds ? lam_bytes : 0);
         static std::atomic<unsigned> attr{0};
         lds_attr(fptr(&k_fft_z_green<S, R6, FFT_Z_MAXE, FFT_Z_THREADS>), attr, bytes);
         k_fft_z_green<S, R6, FFT_Z_MAXE, FFT_Z_THREADS><<<gz, FFT_Z_THREADS, bytes, st>>>(
-            cbuf, RD(az), TW(az), lbz, p.nkx, p.ldc, p.ny, LAM(ax), LAM(ay), LAM(az), (S)(1.0 / (double)p.N));
+            cbuf, RD(az), TW(az), lbz, p.nkx, p.ldc, p.ny, LAM(ax), LAM(ay), LAM(az), (S)(1.0 / (double)p.N), lam_lds);
         DWP_LAUNCH_CHECK();
     });
     pe(ev, PG_FFT_Z, 2.0 * cb * Cn);
