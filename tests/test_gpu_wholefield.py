@@ -70,3 +70,30 @@ def test_switching_the_krylov_precision_on_one_context(case):
     for E, phi in zip(Es, phis):
         assert abs(E - E_o) <= 1e-10 * abs(E_o)
         assert np.abs(phi - phi_o).max() <= 1e-8 * np.abs(phi_o).max()
+
+
+def test_second_solve_on_a_float16_basis_from_its_first_cycle(case):
+    # Three solves of the same problem on one context with the float16
+    # Arnoldi basis: the first runs its first cycle on float32; the later
+    # ones, whose predecessor's first cycle cut the residual less than
+    # 100-fold on this slab, run every cycle on float16.  All meet the same
+    # bars against the oracle, take the same iteration count to within one
+    # cycle's worth, and the last two agree bit for bit (same path, same
+    # inputs).
+    from paper_0904_4887_amd.binding import Solver
+    w, rho, phi_o, E_o, g_o = case
+    s = Solver(0)
+    s.set_grid(w.n, w.L, **w.solver_opts(precision=1, fft_fp32=1, krylov_fp32=1, krylov_fp16=1))
+    s.build_epsilon(w.xyz, w.radius, w.eps_params)
+    rho_d = s.build_rho(w.xyz, w.q, w.sigma)
+    out = []
+    for _ in range(3):
+        phi_d, E, info = s.solve(rho_d)
+        assert info["rel_res"] <= 1e-10
+        out.append((E, phi_d.cpu().numpy(), info["outer_iters"]))
+    s.close()
+    for E, phi, _ in out:
+        assert abs(E - E_o) <= 1e-10 * abs(E_o), (E, E_o)
+        assert np.abs(phi - phi_o).max() <= 1e-8 * np.abs(phi_o).max()
+    assert abs(out[1][2] - out[0][2]) <= 16
+    assert out[2][0] == out[1][0] and np.array_equal(out[2][1], out[1][1])
