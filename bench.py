@@ -119,7 +119,7 @@ def sweep_source_digest():
         a = text.index("// Row-band variant of the fused sweep")
         b = text.index("residual + restriction", a)
         c = text.index("// Row-band sweep: returns false")
-        d = text.index("void launch_sweep_fused<double>", c)
+        d = text.index("launch_sweep_fused<double>(", c)
         d = text.index("\n}\n", d) + 3
     except ValueError:
         return None

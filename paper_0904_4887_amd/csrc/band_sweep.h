@@ -57,6 +57,11 @@ template <class T> struct BandArgs {
     int ty, bands, kc;
     int c0;
     T cx, cy, cz;
+    // when set, the output planes are added into this box array (nzb planes
+    // of nx * ny; output plane k at box plane (kw0 + k) mod nzb) instead of
+    // being stored in uout
+    T *zadd;
+    int nzb, kw0;
 };
 
 // Elements of one block's LDS: u (2 slots), eps (3), first colour (2).
@@ -302,9 +307,15 @@ struct BandSweep {
             // one store per thread and step; steps outside the chunk write
             // zeros into the zero plane -1 of the output
             const bool valid = k >= k0 && k < k1;
-            T *dst = a.uout + (valid ? (size_t)(k + 1) * plane : 0) + ou;
-            BAND_CHECK((size_t)(dst - a.uout) + W - 1, (size_t)(a.nw + 2) * plane);
-            *(V *)dst = valid ? o : V(0);
+            if (a.zadd && valid) {
+                T *zd = a.zadd + (size_t)((a.kw0 + k) % a.nzb) * plane + ou;
+                BAND_CHECK((size_t)(zd - a.zadd) + W - 1, (size_t)a.nzb * plane);
+                *(V *)zd = *(const V *)zd + o;
+            } else {
+                T *dst = a.uout + (valid ? (size_t)(k + 1) * plane : 0) + ou;
+                BAND_CHECK((size_t)(dst - a.uout) + W - 1, (size_t)(a.nw + 2) * plane);
+                *(V *)dst = valid ? o : V(0);
+            }
         }
     }
 };

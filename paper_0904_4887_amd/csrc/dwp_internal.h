@@ -270,11 +270,15 @@ template <class T>
 void launch_zero(hipStream_t s, T *x, size_t n);
 // One red-black sweep (first_color, then the other) from uin to uout in a
 // single pass; uin, uout: ghosted arrays of level L (ghost planes zero).
+// With zadd (a box array of nzb planes), the row-band kernel adds the result
+// into zadd at box planes (kw0 + k) mod nzb instead of writing uout, and the
+// call returns true; the tiled kernel ignores zadd and returns false.
 template <class T>
 bool sweep_band_fits(const Level &L);  // the row-band fused sweep takes this level
 template <class T>
-void launch_sweep_fused(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color, bool zero_in,
-                        bool tiles_only, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+bool launch_sweep_fused(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color, bool zero_in,
+                        bool tiles_only, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr,
+                        T *zadd = nullptr, int nzb = 0, int kw0 = 0);
 // The rest of a V-cycle from level l0 down, in one single-workgroup kernel.
 template <class T>
 void launch_vcycle_bottom(hipStream_t s, const std::vector<Level *> &levels, size_t l0, int pre, int post,

@@ -1817,7 +1817,8 @@ static int band_rows(const Level &L) {
 }
 template <class T, int W, bool ZIN>
 static bool sweep_band_w(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color, int ty,
-                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, T *zadd = nullptr, int nzb = 0,
+                         int kw0 = 0) {
     if (ty == 0) ty = band_rows<T, W>(L);
     if (ty == 0 || !band_rows_fit<T, W>(L, ty)) return false;
     const int nt = (ty + 4) * (L.nx / W);
@@ -1838,7 +1839,8 @@ static bool sweep_band_w(hipStream_t s, const Level &L, const T *uin, T *uout, i
     const LevelArgs la = level_args(L);
     const bool f32 = sizeof(T) == 4;
     BandArgs<T> a{uin, uout, L.eps.as<T>(), L.f.as<T>(), L.nx, L.ny, L.nw, ty, bands, kc, first_color,
-                  (T)(f32 ? la.cxf : la.cx), (T)(f32 ? la.cyf : la.cy), (T)(f32 ? la.czf : la.cz)};
+                  (T)(f32 ? la.cxf : la.cx), (T)(f32 ? la.cyf : la.cy), (T)(f32 ? la.czf : la.cz),
+                  zadd, nzb, kw0};
     hipExtLaunchKernelGGL(k_sweep_band<T, W, ZIN>, dim3(padded), dim3(nt), (uint32_t)bytes, s, e0, e1, 0, a, nb, gb);
     DWP_LAUNCH_CHECK();
     return true;
@@ -1858,25 +1860,32 @@ bool sweep_band_fits<double>(const Level &L) {
 // tiled one.
 template <class T, int W>
 static bool sweep_band_z(hipStream_t s, const Level &L, const T *uin, T *uout, int first_color, bool zero_in,
-                         hipEvent_t e0, hipEvent_t e1) {
-    return zero_in ? sweep_band_w<T, W, true>(s, L, uin, uout, first_color, 0, e0, e1)
-                   : sweep_band_w<T, W, false>(s, L, uin, uout, first_color, 0, e0, e1);
+                         hipEvent_t e0, hipEvent_t e1, T *zadd, int nzb, int kw0) {
+    return zero_in ? sweep_band_w<T, W, true>(s, L, uin, uout, first_color, 0, e0, e1, zadd, nzb, kw0)
+                   : sweep_band_w<T, W, false>(s, L, uin, uout, first_color, 0, e0, e1, zadd, nzb, kw0);
+}
+// Returns whether the sweep added its output into zadd (the row-band kernel
+// did); otherwise it is in uout.
+template <>
+bool launch_sweep_fused<float>(hipStream_t s, const Level &L, const float *uin, float *uout, int first_color,
+                               bool zero_in, bool tiles_only, hipEvent_t e0, hipEvent_t e1, float *zadd, int nzb,
+                               int kw0) {
+    const bool w4 = L.nx % 4 == 0;
+    if (!tiles_only && (w4 ? sweep_band_z<float, 4>(s, L, uin, uout, first_color, zero_in, e0, e1, zadd, nzb, kw0)
+                           : sweep_band_z<float, 2>(s, L, uin, uout, first_color, zero_in, e0, e1, zadd, nzb, kw0)))
+        return zadd != nullptr;
+    if (w4) sweep_fused_z<float, 4>(s, L, uin, uout, first_color, zero_in, e0, e1);
+    else sweep_fused_z<float, 2>(s, L, uin, uout, first_color, zero_in, e0, e1);
+    return false;
 }
 template <>
-void launch_sweep_fused<float>(hipStream_t s, const Level &L, const float *uin, float *uout, int first_color,
-                               bool zero_in, bool tiles_only, hipEvent_t e0, hipEvent_t e1) {
-    if (L.nx % 4 == 0) {
-        if (tiles_only || !sweep_band_z<float, 4>(s, L, uin, uout, first_color, zero_in, e0, e1))
-            sweep_fused_z<float, 4>(s, L, uin, uout, first_color, zero_in, e0, e1);
-    } else if (tiles_only || !sweep_band_z<float, 2>(s, L, uin, uout, first_color, zero_in, e0, e1)) {
-        sweep_fused_z<float, 2>(s, L, uin, uout, first_color, zero_in, e0, e1);
-    }
-}
-template <>
-void launch_sweep_fused<double>(hipStream_t s, const Level &L, const double *uin, double *uout, int first_color,
-                                bool zero_in, bool tiles_only, hipEvent_t e0, hipEvent_t e1) {
-    if (tiles_only || !sweep_band_z<double, 2>(s, L, uin, uout, first_color, zero_in, e0, e1))
-        sweep_fused_z<double, 2>(s, L, uin, uout, first_color, zero_in, e0, e1);
+bool launch_sweep_fused<double>(hipStream_t s, const Level &L, const double *uin, double *uout, int first_color,
+                                bool zero_in, bool tiles_only, hipEvent_t e0, hipEvent_t e1, double *zadd, int nzb,
+                                int kw0) {
+    if (!tiles_only && sweep_band_z<double, 2>(s, L, uin, uout, first_color, zero_in, e0, e1, zadd, nzb, kw0))
+        return zadd != nullptr;
+    sweep_fused_z<double, 2>(s, L, uin, uout, first_color, zero_in, e0, e1);
+    return false;
 }
 
 template <class T>

@@ -331,7 +331,7 @@ void to_host(dwp_ctx *c, const double *dev, size_t n) {
 // correction array holds stale values that must act as zero (first cycle),
 // otherwise it holds the previous cycle's correction.
 template <class T>
-void vcycle(dwp_ctx *c, size_t l, bool u_unset) {
+bool vcycle(dwp_ctx *c, size_t l, bool u_unset, T *zadd) {
     Plan &p = c->plan;
     Level &L = *p.levels[l];
     hipStream_t s = c->stream;
@@ -361,9 +361,10 @@ void vcycle(dwp_ctx *c, size_t l, bool u_unset) {
         for (size_t q = l; q < p.levels.size(); ++q) nb += (double)p.levels[q]->n_interior();
         PROF(c, PG_MG_BOTTOM, 4.0 * ts * nb,
              launch_vcycle_bottom<T>(s, p.levels, l, c->opts.pre, c->opts.post, c->opts.coarse_sweeps));
-        return;
+        return false;
     }
-    auto smooth = [&](int first) {
+    bool added = false;
+    auto smooth = [&](int first, T *za) {
         if (six) {
             // u, eps, f and the three components of D1 eps read per point, u written
             PROF(c, sg, (2.0 * ts + 32.0) * (double)L.n_interior(),
@@ -371,12 +372,14 @@ void vcycle(dwp_ctx *c, size_t l, bool u_unset) {
                                 2.0 / 3.0));
             std::swap(L.u.p, L.u2.p);
         } else if (fused) {
-            const double b = zero_in ? 1.5 * pass_bytes : 2.0 * pass_bytes;
             // timed by events that the launch itself records at the kernel's
             // start and end
             const int ev = c->prof.reserve(sg);
-            launch_sweep_fused<T>(s, L, L.u.as<T>(), L.u2.as<T>(), first, zero_in, c->opts.smoother == 2,
-                                  c->prof.event(ev, 0), c->prof.event(ev, 1));
+            added = launch_sweep_fused<T>(s, L, L.u.as<T>(), L.u2.as<T>(), first, zero_in, c->opts.smoother == 2,
+                                          c->prof.event(ev, 0), c->prof.event(ev, 1), za, p.nz, p.k_w0);
+            // u and f read (not u when starting from zero), eps read, u
+            // written -- or z read and written when the result is added into z
+            const double b = (zero_in ? 1.5 : 2.0) * pass_bytes + (added ? 0.5 * pass_bytes : 0.0);
             c->prof.done(ev, sg, b);
             std::swap(L.u.p, L.u2.p);
         } else {
@@ -386,10 +389,10 @@ void vcycle(dwp_ctx *c, size_t l, bool u_unset) {
         zero_in = false;
     };
     if (coarsest) {  // too large for the bottom kernel: coarse_sweeps sweeps here
-        for (int k = 0; k < c->opts.coarse_sweeps; ++k) smooth(0);
-        return;
+        for (int k = 0; k < c->opts.coarse_sweeps; ++k) smooth(0, nullptr);
+        return false;
     }
-    for (int k = 0; k < c->opts.pre; ++k) smooth(0);
+    for (int k = 0; k < c->opts.pre; ++k) smooth(0, nullptr);
     Level &C = *p.levels[l + 1];
     if (six) {
         // the sixth-order residual, then full weighting (which zeroes the coarse unknowns)
@@ -403,9 +406,11 @@ void vcycle(dwp_ctx *c, size_t l, bool u_unset) {
         PROF(c, PG_MG_OTHER, ts * (3.0 * L.n_interior() + C.n_interior() + C.n_ghosted()),
              launch_resid_restrict<T>(s, L, C));
     }
-    vcycle<T>(c, l + 1, false);
+    vcycle<T>(c, l + 1, false, nullptr);
     PROF(c, PG_MG_OTHER, ts * (C.n_interior() + 2.0 * L.n_interior()), launch_prolong_add<T>(s, L, C));
-    for (int k = 0; k < c->opts.post; ++k) smooth(1);
+    // the last sweep may add its result straight into zadd
+    for (int k = 0; k < c->opts.post; ++k) smooth(1, k + 1 == c->opts.post ? zadd : nullptr);
+    return added;
 }
 
 template <class T, class TV, class TZ>
@@ -437,8 +442,14 @@ void split_impl(dwp_ctx *c, const TV *v, TZ *z) {
         PROF(c, PG_WET, (24.0 + sizeof(T)) * nW,
              launch_wet_residual<T>(s, p, v, z, c->eps.as<double>(), F.f.as<T>()));
     }
-    for (int k = 0; k < c->opts.cycles; ++k) vcycle<T>(c, 0, k == 0);
-    PROF(c, PG_WET, (2.0 * sizeof(TZ) + sizeof(T)) * nW, launch_wet_add<T>(s, p, F.u.as<T>(), z));
+    // the wet correction is added into z by the last fine-level sweep where
+    // the row-band kernel runs it and z has the level's type, else afterwards
+    T *za = nullptr;
+    if constexpr (std::is_same<TZ, T>::value) za = z;
+    bool added = false;
+    for (int k = 0; k < c->opts.cycles; ++k) added = vcycle<T>(c, 0, k == 0, k + 1 == c->opts.cycles ? za : nullptr);
+    if (!added)
+        PROF(c, PG_WET, (2.0 * sizeof(TZ) + sizeof(T)) * nW, launch_wet_add<T>(s, p, F.u.as<T>(), z));
     c->phases.mark(s, PH_KRYLOV);
 }
 

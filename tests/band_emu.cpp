@@ -40,8 +40,13 @@ void march(const BandArgs<T> &a, T *lds, int band, int chunk, int nt, bool rever
 }
 
 template <class T, int W, bool ZIN>
-int run(int nx, int ny, int nw, int ty, int kc, int c0, bool reverse, unsigned seed) {
+int run(int nx, int ny, int nw, int ty, int kc, int c0, bool reverse, unsigned seed, int nzb = 0, int kw0 = 0) {
     const size_t plane = (size_t)nx * ny;
+    // nzb > 0: the sweep adds its output into a box array z of nzb planes at
+    // box planes (kw0 + k) mod nzb instead of writing out
+    std::vector<T> z((size_t)nzb * plane), z0;
+    for (size_t i = 0; i < z.size(); ++i) z[i] = (T)(0.25 * (double)(i % 7) - 0.5);
+    z0 = z;
     std::vector<T> u((nw + 2) * plane, T(0)), e((nw + 2) * plane), f(nw * plane), out((nw + 2) * plane, T(0));
     std::mt19937 g(seed);
     std::uniform_real_distribution<double> U(0, 1);
@@ -68,7 +73,8 @@ int run(int nx, int ny, int nw, int ty, int kc, int c0, bool reverse, unsigned s
     }
     const int bands = ny / ty, nchunks = (nw + kc - 1) / kc, nb = bands * nchunks, nt = (ty + 4) * (nx / W);
     const int gb = bands % 4 == 0 ? 4 : (bands % 2 == 0 ? 2 : 1);
-    BandArgs<T> a{u.data(), out.data(), e.data(), f.data(), nx, ny, nw, ty, bands, kc, c0, cx, cy, cz};
+    BandArgs<T> a{u.data(), out.data(), e.data(), f.data(), nx, ny, nw, ty, bands, kc, c0, cx, cy, cz,
+                  nzb ? z.data() : nullptr, nzb, kw0};
     std::vector<int> seen(nb, 0);
     for (int t = 0; t < nb; ++t) {
         // the kernel's tile -> (band, chunk) decoding; odd chunks march down
@@ -91,6 +97,23 @@ int run(int nx, int ny, int nw, int ty, int kc, int c0, bool reverse, unsigned s
         if (v != 1) { printf("tile mapping is not a bijection\n"); return 1; }
     double md = 0, mref = 0;
     size_t bad = 0;
+    if (nzb) {
+        // z at the wet planes gained exactly the sweep's result, other box
+        // planes and out's interior are untouched, out's zero plane stays zero
+        size_t zbad = 0;
+        for (int kb = 0; kb < nzb; ++kb)
+            for (size_t q = 0; q < plane; ++q) {
+                const int k = ((kb - kw0) % nzb + nzb) % nzb;
+                const size_t i = (size_t)kb * plane + q;
+                const T want = k < nw ? (T)(z0[i] + ref[(size_t)(k + 1) * plane + q]) : z0[i];
+                if (!(z[i] == want)) ++zbad;
+            }
+        for (size_t i = 0; i < out.size(); ++i)
+            if (out[i] != T(0)) ++zbad;
+        printf("%s W=%d ZIN=%d %dx%dx%d ty=%d kc=%d c0=%d rev=%d added into %d box planes from %d: mismatches %zu\n",
+               sizeof(T) == 4 ? "f32" : "f64", W, (int)ZIN, nx, ny, nw, ty, kc, c0, (int)reverse, nzb, kw0, zbad);
+        return zbad != 0;
+    }
     for (size_t i = 0; i < out.size(); ++i) {
         const bool ghost = i < plane || i >= (nw + 1) * plane;
         const double want = ghost ? 0.0 : (double)ref[i];
@@ -259,6 +282,9 @@ int main() {
             fails += run<float, 4, false>(8, 8, 1, 4, 2, c0, rev, 10);
             fails += run<float, 4, false>(24, 32, 23, 8, 3, c0, rev, 11);
             fails += run<double, 2, true>(12, 16, 17, 4, 5, c0, rev, 12);
+            fails += run<float, 4, false>(24, 24, 13, 4, 4, c0, rev, 21, 20, 15);  // wraps the box
+            fails += run<float, 2, false>(18, 12, 11, 6, 4, c0, rev, 22, 16, 3);
+            fails += run<double, 2, false>(20, 24, 10, 12, 8, c0, rev, 23, 10, 0);  // every box plane wet
             fails += run<float, 2, false>(10, 36, 9, 6, 1, c0, rev, 13);
         }
     for (int rev = 0; rev < 2; ++rev) {
